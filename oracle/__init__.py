@@ -22,8 +22,12 @@ OR_OK, OR_EINVAL, OR_ENOMEM, OR_ENOCONV, OR_EBS = 0, -1, -2, -4, -5
 
 
 def build_lib(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so with gcc (no FMA contraction)."""
-    if force or not os.path.exists(_LIB_PATH):
+    """Compile oracle.c into liboracle.so with gcc (no FMA contraction).  Without
+    force, rebuilds only when the library is missing or older than its sources."""
+    stale = (not os.path.exists(_LIB_PATH) or
+             os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC),
+                                               os.path.getmtime(os.path.join(_HERE, "oracle.h"))))
+    if force or stale:
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)

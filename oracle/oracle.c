@@ -249,12 +249,12 @@ int or_drift(double mu, const double x0[3], const double v0[3], double h, double
     for (it = 0; it < 100; ++it) {
       double F = E - c * sin(E) + s * (1.0 - cos(E)) - dm;
       double Fp = 1.0 - c * cos(E) + s * sin(E);
+      if (F == 0.0) { ok = 1; break; }
       if (F < 0) lo = E; else hi = E;
       double En = E - F / Fp;
+      if (converged(En - E, En)) { E = En; ok = 1; break; }
       if (!(En > lo && En < hi)) En = 0.5 * (lo + hi);
-      double d = En - E;
       E = En;
-      if (converged(d, E)) { ok = 1; break; }
     }
     if (!ok) return OR_ENOCONV;
     double sE = sin(E);
@@ -285,12 +285,12 @@ int or_drift(double mu, const double x0[3], const double v0[3], double h, double
     for (it = 0; it < 100; ++it) {
       double F = HF(H);
       double Fp = c * cosh(H) + s * sinh(H) - 1.0;
+      if (F == 0.0) { ok = 1; break; }
       if (F < 0) lo = H; else hi = H;
       double Hn = H - F / Fp;
+      if (converged(Hn - H, Hn)) { H = Hn; ok = 1; break; }
       if (!(Hn > lo && Hn < hi)) Hn = 0.5 * (lo + hi);
-      double d = Hn - H;
       H = Hn;
-      if (converged(d, H)) { ok = 1; break; }
     }
 #undef HF
     if (!ok) return OR_ENOCONV;
@@ -327,12 +327,12 @@ int or_drift(double mu, const double x0[3], const double v0[3], double h, double
     int ok = 0;
     for (int it = 0; it < 100; ++it) {
       UF(S, F, rr);
+      if (F == 0.0) { ok = 1; break; }
       if (F < 0) lo = S; else hi = S;
       double Sn = S - F / rr;
+      if (converged(Sn - S, Sn)) { S = Sn; ok = 1; break; }
       if (!(Sn > lo && Sn < hi)) Sn = 0.5 * (lo + hi);
-      double d = Sn - S;
       S = Sn;
-      if (converged(d, S)) { ok = 1; break; }
     }
 #undef UF
     if (!ok) return OR_ENOCONV;

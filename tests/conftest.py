@@ -15,5 +15,5 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def orc():
     import oracle
-    oracle.build_lib(force=not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")))
+    oracle.build_lib(force=False)
     return oracle
