@@ -1,0 +1,183 @@
+/*
+ * mx -- MI355X (gfx950) hybrid symplectic step: C ABI.
+ *
+ * One hybrid step of the Mercury+ integrator (Mercury-Arxes, Sect. 2): a
+ * changeover-weighted kick of every body by the massive ("big") bodies, the
+ * gas-drag acceleration of the massless bodies (Sect. 3.1, Eqs. 1-7), a jump by
+ * the massive-body momentum, a Kepler drift of every body in democratic-
+ * heliocentric coordinates, close-encounter flagging of big/any pairs (the
+ * mce_snif region of Sect. 2.1.2) and a Bulirsch-Stoer hand-off of the flagged
+ * subsystems ("BS for conservative forces", Sect. 2.1).
+ *
+ * Conventions (every entry point):
+ *  - Units: AU, day, solar mass; G is given in mx_params.
+ *  - Bodies: n = n_big + n_small non-star bodies, big bodies first.  The star is
+ *    not an array element.  Vectors are structure-of-arrays double[3][n]
+ *    (x coordinates of all bodies, then y, then z).
+ *  - Pointers marked "host or device" follow is_device_ptr: 0 = host memory,
+ *    1 = device memory on the current HIP device.  Inputs are copied; the library
+ *    never keeps a caller pointer after the call returns.
+ *  - Work is queued on the stream given at init (a hipStream_t; NULL = the null
+ *    stream, which disables graph replay).  Calls that return host values
+ *    synchronise that stream.
+ *  - Every call returns an mx_status.  MX_EINVAL and MX_ECAPACITY leave the
+ *    system unchanged.  Device-side failures (MX_ENOCONV, MX_EBS, MX_ENONFINITE,
+ *    MX_ECAPACITY of a step) are latched on the device and reported by the next
+ *    synchronising call.  mx_last_error() gives a thread-local message.
+ */
+#ifndef MX_H
+#define MX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mx_system mx_system; /* opaque; owned by the library */
+
+typedef enum {
+  MX_OK = 0,
+  MX_EINVAL = -1,      /* bad argument (sizes, NULL where required, non-positive mass) */
+  MX_ENOMEM = -2,      /* device or host allocation failed */
+  MX_EHIP = -3,        /* a HIP runtime call failed */
+  MX_ENOCONV = -4,     /* Kepler iteration cap reached */
+  MX_EBS = -5,         /* Bulirsch-Stoer step-halving limit reached */
+  MX_ENONFINITE = -6,  /* non-finite position or velocity after a step */
+  MX_ECAPACITY = -7    /* encounter list or subsystem table overflow */
+} mx_status;
+
+/* Physical and numerical parameters, all double precision unless stated.
+ * Gas-disk fields follow Sect. 3.1: Sigma(R) = sigma1 (R/1AU)^-gamma, tapered by
+ * exp[(1/r_c)^(2-gamma) - (R/r_c)^(2-gamma)] when r_c > 0 (Eq. 1 normalised to
+ * sigma1 at 1 AU), zero inside r_in; scale height h = (H/r) R; sub-Keplerian
+ * gas speed v_k sqrt(1 - 2 eta) (Eq. 5); drag coefficient of Eq. 7 with its
+ * first bracket raised to kdrag_exp (printed as -2). */
+typedef struct {
+  double G;           /* AU^3 Msun^-1 day^-2 */
+  double m0;          /* stellar mass, Msun */
+  double dt;          /* step, day (may be negative) */
+  double rcrit_hill;  /* changeover radius in Hill radii */
+  double bs_tol;      /* Bulirsch-Stoer relative tolerance */
+  int32_t n_big;      /* massive bodies (>= 0) */
+  int32_t n_small;    /* massless bodies (>= 0) */
+  int32_t gas_on;     /* 1: gas drag on the massless bodies */
+  int32_t pad;
+  double sigma1;      /* gas surface density at 1 AU, g cm^-2 */
+  double gamma;       /* surface-density slope */
+  double r_c;         /* taper radius, AU; 0 = none */
+  double r_in;        /* inner edge, AU */
+  double h_over_r;    /* aspect ratio */
+  double eta;         /* sub-Keplerian parameter */
+  double kdrag_exp;   /* exponent of the first bracket of Eq. 7 */
+  double rho_unit;    /* Msun AU^-3 per g cm^-3 */
+  double au_cm;       /* cm per AU */
+  double mfp_coef;    /* mean free path lambda[AU] = mfp_coef / rho_gas[Msun AU^-3] */
+} mx_params;
+
+/* ---------------------------------------------------------------- system */
+
+/* Create a system from heliocentric states (Sect. 2: the DH transform of
+ * mco_h2dh).  x_h, v_h: [3][n] host or device.  m_big: [n_big] masses (Msun, each
+ * > 0) host or device.  r_p, rho_p: [n_small] radius (AU) and density (g cm^-3) of
+ * each massless body, host or device; required when gas_on.  growth: NULL, or
+ * [n_big][3] = (M0, Mc [Msun], tau_c [day]) per big body, the core-growth law of
+ * Eq. 13 applied at each step start (tau_c <= 0: fixed mass), host or device.
+ * hip_stream: hipStream_t used for all work.  The changeover radius of big body k
+ * is rcrit_hill * a_k (m_k / 3 m0)^(1/3), a_k its osculating semi-major axis
+ * (|x_k| if unbound).  On success *out owns all device memory of the system. */
+mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_h,
+                         const double* m_big, const double* r_p, const double* rho_p,
+                         const double* growth, int is_device_ptr, void* hip_stream,
+                         mx_system** out);
+
+/* Queue n_steps hybrid steps (Sect. 2; kick listing of Sect. 2.1.2, direct force
+ * of Sect. 2.1.3).  Asynchronous; device failures surface at the next sync. */
+mx_status mx_step(mx_system* s, int32_t n_steps);
+
+/* Kernels of one step, in launch order (indices into kernel_ms below). */
+enum {
+  MX_K_GROWTH = 0,          /* core-growth mass schedule (no-op without growth) */
+  MX_K_KICK_JUMP_DRIFT = 1, /* half kick + gas drag + jump + Kepler drift */
+  MX_K_FLAG = 2,            /* close-encounter flagging */
+  MX_K_ENCOUNTER = 3,       /* sort, subsystem plan and Bulirsch-Stoer */
+  MX_K_JUMP_PACK = 4,       /* second jump, source packing */
+  MX_K_FORCE_KICK = 5,      /* changeover-weighted gravity + gas drag + half kick */
+  MX_NUM_KERNELS = 6
+};
+
+/* Same as mx_step, launched without the graph and with a HIP event around each
+ * kernel group on the system stream; kernel_ms[MX_NUM_KERNELS] (host) receives the
+ * summed event time of each group over the n_steps.  Synchronises every step. */
+mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms);
+
+/* Wait for queued work and report any latched device failure (clears it). */
+mx_status mx_sync(mx_system* s);
+
+/* Energy with the potential over massive bodies only (the mxx_en change of
+ * Sect. 2.1.3) and total angular momentum.  E: Msun AU^2 day^-2; L: Msun AU^2
+ * day^-1 (host pointers).  Synchronises. */
+mx_status mx_energy(mx_system* s, double* E, double L[3]);
+
+/* Flagged pairs of the last step, sorted by (i, j), i < n_big, i < j < n
+ * (the ice/jce list of Sect. 2.1.2).  pairs: host [cap][2]; *n_out receives the
+ * total count (may exceed cap).  Synchronises. */
+mx_status mx_encounters(mx_system* s, int32_t* pairs, int32_t cap, int32_t* n_out);
+
+/* Heliocentric state (mco_dh2h) / its replacement.  set_state also recomputes
+ * the stored end-of-step gravity and sets the step counter to step_index. */
+mx_status mx_get_state(mx_system* s, double* x_h, double* v_h, int is_device_ptr);
+mx_status mx_set_state(mx_system* s, const double* x_h, const double* v_h, int is_device_ptr,
+                       int64_t step_index);
+
+/* Democratic-heliocentric state (positions, barycentric velocities), exact copy. */
+mx_status mx_get_state_dh(mx_system* s, double* x, double* u, int is_device_ptr);
+mx_status mx_set_state_dh(mx_system* s, const double* x, const double* u, int is_device_ptr,
+                          int64_t step_index);
+
+/* Stored changeover-weighted gravity [3][n] (reused by the next half kick). */
+mx_status mx_get_accel(mx_system* s, double* a, int is_device_ptr);
+
+/* Current mu = G m and rcrit of the big bodies, host [n_big] each.  Synchronises. */
+mx_status mx_get_masses(mx_system* s, double* mu, double* rcrit);
+
+/* Steps taken so far (the step counter). */
+mx_status mx_get_step_index(mx_system* s, int64_t* step_index);
+
+void mx_destroy(mx_system* s);
+const char* mx_last_error(void);
+
+/* -------------------------------------------- single-kernel entry points
+ * Stateless launches of one kernel of the step on device pointers, queued on
+ * hip_stream.  They exist so that each kernel can be checked on its own. */
+
+/* Changeover-weighted gravity (Sect. 2.1.3): a[t] = sum_{s<n_big, s!=t} mu_s K /r^3
+ * (x_s - x_t), rc = max(rcrit_s, rcrit_t) (rcrit_t = 0 for t >= n_big).
+ * x, a: device [3][n]; mu, rcrit: device [n_big]. */
+mx_status mx_gravity(int32_t n, int32_t n_big, const double* x, const double* mu,
+                     const double* rcrit, double* a, void* hip_stream);
+
+/* Gas drag (Sect. 3.1, Eqs. 1-7) on bodies t >= n_big; a[t] = 0 for big bodies.
+ * u: barycentric velocities; mu: device [n_big] (for the heliocentric shift);
+ * r_p: AU; rho_p: Msun AU^-3.  All device pointers. */
+mx_status mx_gas_drag(const mx_params* p, int32_t n, int32_t n_big, const double* x,
+                      const double* u, const double* mu, const double* r_p,
+                      const double* rho_p, double* a, void* hip_stream);
+
+/* Kepler drift of n bodies about mu0 over h (universal variables).
+ * x0, u0, x1, u1: device [3][n]; x1/u1 may alias x0/u0.  Reports MX_ENOCONV. */
+mx_status mx_kepler_drift(int32_t n, double mu0, double h, const double* x0,
+                          const double* u0, double* x1, double* u1, void* hip_stream);
+
+/* Encounter flagging: pairs (i < n_big, i < j < n) whose minimum separation over
+ * [0, h] (cubic Hermite interpolant of the relative motion) is <= max(rcrit).
+ * pairs: device [cap][2], sorted by (i, j) on return; *n_out (host) total count.
+ * Synchronises hip_stream. */
+mx_status mx_flag_pairs(int32_t n, int32_t n_big, const double* rcrit, const double* x0,
+                        const double* u0, const double* x1, const double* u1, double h,
+                        int32_t* pairs, int32_t cap, int32_t* n_out, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,295 @@
+"""ctypes marshalling for libmx.so: argument conversion only, no arithmetic of the method."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmx.so")
+
+MX_OK = 0
+_CODES = {0: "MX_OK", -1: "MX_EINVAL", -2: "MX_ENOMEM", -3: "MX_EHIP", -4: "MX_ENOCONV",
+          -5: "MX_EBS", -6: "MX_ENONFINITE", -7: "MX_ECAPACITY"}
+
+
+class MxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("G", C.c_double), ("m0", C.c_double), ("dt", C.c_double),
+                ("rcrit_hill", C.c_double), ("bs_tol", C.c_double),
+                ("n_big", C.c_int32), ("n_small", C.c_int32), ("gas_on", C.c_int32),
+                ("pad", C.c_int32),
+                ("sigma1", C.c_double), ("gamma", C.c_double), ("r_c", C.c_double),
+                ("r_in", C.c_double), ("h_over_r", C.c_double), ("eta", C.c_double),
+                ("kdrag_exp", C.c_double), ("rho_unit", C.c_double), ("au_cm", C.c_double),
+                ("mfp_coef", C.c_double)]
+
+
+def make_params(p: dict) -> Params:
+    q = Params()
+    for name, _ in Params._fields_:
+        if name != "pad":
+            setattr(q, name, p[name])
+    return q
+
+
+_lib = None
+_P = C.c_void_p
+_D = C.c_void_p
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libmx.so; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {_LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(_LIB_PATH)
+        st = C.c_int
+        L.mx_last_error.restype = C.c_char_p
+        L.mx_init_system.restype = st
+        L.mx_init_system.argtypes = [C.POINTER(Params), _D, _D, _D, _D, _D, _D, C.c_int, _P,
+                                     C.POINTER(C.c_void_p)]
+        L.mx_step.restype = st
+        L.mx_step.argtypes = [_P, C.c_int32]
+        L.mx_step_profiled.restype = st
+        L.mx_step_profiled.argtypes = [_P, C.c_int32, C.POINTER(C.c_double)]
+        L.mx_sync.restype = st
+        L.mx_sync.argtypes = [_P]
+        L.mx_energy.restype = st
+        L.mx_energy.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.mx_encounters.restype = st
+        L.mx_encounters.argtypes = [_P, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]
+        for name in ("mx_get_state", "mx_get_state_dh"):
+            f = getattr(L, name)
+            f.restype = st
+            f.argtypes = [_P, _D, _D, C.c_int]
+        for name in ("mx_set_state", "mx_set_state_dh"):
+            f = getattr(L, name)
+            f.restype = st
+            f.argtypes = [_P, _D, _D, C.c_int, C.c_int64]
+        L.mx_get_accel.restype = st
+        L.mx_get_accel.argtypes = [_P, _D, C.c_int]
+        L.mx_get_masses.restype = st
+        L.mx_get_masses.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.mx_get_step_index.restype = st
+        L.mx_get_step_index.argtypes = [_P, C.POINTER(C.c_int64)]
+        L.mx_destroy.restype = None
+        L.mx_destroy.argtypes = [_P]
+        L.mx_gravity.restype = st
+        L.mx_gravity.argtypes = [C.c_int32, C.c_int32, _D, _D, _D, _D, _P]
+        L.mx_gas_drag.restype = st
+        L.mx_gas_drag.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, _D, _D, _D, _D, _D, _D,
+                                  _P]
+        L.mx_kepler_drift.restype = st
+        L.mx_kepler_drift.argtypes = [C.c_int32, C.c_double, C.c_double, _D, _D, _D, _D, _P]
+        L.mx_flag_pairs.restype = st
+        L.mx_flag_pairs.argtypes = [C.c_int32, C.c_int32, _D, _D, _D, _D, _D, C.c_double, _D,
+                                    C.c_int32, C.POINTER(C.c_int32), _P]
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != MX_OK:
+        raise MxError(code, lib().mx_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(a, device="cuda"):
+    """float64 contiguous device tensor (copy of a numpy array or tensor)."""
+    torch = _torch()
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.detach().to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class System:
+    """One planetary system on the GPU (owns an mx_system and a dedicated stream)."""
+
+    def __init__(self, params: dict, x, v, m_big, r_p=None, rho_p=None, growth=None,
+                 device="cuda"):
+        torch = _torch()
+        self.params = dict(params)
+        self.n = int(params["n_big"]) + int(params["n_small"])
+        self.nb = int(params["n_big"])
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        tx, tv, tm = _dev(x, device), _dev(v, device), _dev(m_big, device)
+        if tm is None or tm.numel() == 0:
+            tm = torch.zeros(1, dtype=torch.float64, device=device)
+        trp, trh, tg = _dev(r_p, device), _dev(rho_p, device), _dev(growth, device)
+        torch.cuda.current_stream(self.device).synchronize()
+        self._pp = make_params(params)
+        h = C.c_void_p()
+        _check(lib().mx_init_system(C.byref(self._pp), _ptr(tx), _ptr(tv), _ptr(tm), _ptr(trp),
+                                    _ptr(trh), _ptr(tg), 1, C.c_void_p(self.stream.cuda_stream),
+                                    C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, w, device="cuda"):
+        return cls(w.params, w.x, w.v, w.m_big, w.r_p, w.rho_p, w.growth, device=device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1, sync=False):
+        _check(lib().mx_step(self._h, int(n)))
+        if sync:
+            self.sync()
+
+    KERNELS = ("growth", "kick_jump_drift", "flag", "encounter_bs", "jump_pack", "force_kick")
+
+    def step_profiled(self, n=1):
+        """Eager steps with HIP events around each kernel group; returns {name: ms total}."""
+        ms = (C.c_double * len(self.KERNELS))()
+        _check(lib().mx_step_profiled(self._h, int(n), ms))
+        return dict(zip(self.KERNELS, ms[:]))
+
+    def sync(self):
+        _check(lib().mx_sync(self._h))
+
+    def energy(self):
+        E = C.c_double(0)
+        L = (C.c_double * 3)()
+        _check(lib().mx_energy(self._h, C.byref(E), L))
+        return E.value, np.array(L[:])
+
+    def encounters(self, cap=1 << 16):
+        buf = (C.c_int32 * (2 * cap))()
+        n = C.c_int32(0)
+        _check(lib().mx_encounters(self._h, buf, cap, C.byref(n)))
+        k = min(n.value, cap)
+        return np.frombuffer(buf, dtype=np.int32, count=2 * k).reshape(-1, 2).copy()
+
+    def _pair_out(self, fn):
+        torch = _torch()
+        a = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
+        b = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
+        _check(fn(self._h, _ptr(a), _ptr(b), 1))
+        return a, b
+
+    def get_state(self, numpy=True):
+        a, b = self._pair_out(lib().mx_get_state)
+        return (a.cpu().numpy(), b.cpu().numpy()) if numpy else (a, b)
+
+    def get_dh(self, numpy=True):
+        a, b = self._pair_out(lib().mx_get_state_dh)
+        return (a.cpu().numpy(), b.cpu().numpy()) if numpy else (a, b)
+
+    def _set(self, fn, x, u, step_index):
+        torch = _torch()
+        tx, tu = _dev(x, self.device), _dev(u, self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(fn(self._h, _ptr(tx), _ptr(tu), 1, int(step_index)))
+
+    def set_state(self, x, v, step_index=0):
+        self._set(lib().mx_set_state, x, v, step_index)
+
+    def set_dh(self, x, u, step_index=0):
+        self._set(lib().mx_set_state_dh, x, u, step_index)
+
+    def accel(self, numpy=True):
+        torch = _torch()
+        a = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
+        _check(lib().mx_get_accel(self._h, _ptr(a), 1))
+        return a.cpu().numpy() if numpy else a
+
+    def masses(self):
+        k = max(self.nb, 1)
+        mu = (C.c_double * k)()
+        rc = (C.c_double * k)()
+        _check(lib().mx_get_masses(self._h, mu, rc))
+        return np.array(mu[: self.nb]), np.array(rc[: self.nb])
+
+    def step_index(self):
+        v = C.c_int64(0)
+        _check(lib().mx_get_step_index(self._h, C.byref(v)))
+        return v.value
+
+
+# ------------------------------------------------------------ single kernels
+def _stream():
+    torch = _torch()
+    return torch.cuda.current_stream().cuda_stream
+
+
+def gravity(x, mu, rcrit, nb):
+    """Changeover-weighted gravity of every body from the nb massive ones."""
+    torch = _torch()
+    tx = _dev(x)
+    n = tx.shape[1]
+    tmu = _dev(mu) if nb > 0 else torch.zeros(1, dtype=torch.float64, device="cuda")
+    trc = _dev(rcrit) if nb > 0 else torch.zeros(1, dtype=torch.float64, device="cuda")
+    a = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    _check(lib().mx_gravity(n, nb, _ptr(tx), _ptr(tmu), _ptr(trc), _ptr(a), C.c_void_p(_stream())))
+    torch.cuda.synchronize()
+    return a
+
+
+def gas_drag(params, x, u, mu, r_p, rho_p_internal, nb):
+    """Gas drag of the massless bodies; rho_p_internal in Msun/AU^3."""
+    torch = _torch()
+    tx, tu = _dev(x), _dev(u)
+    n = tx.shape[1]
+    tmu = _dev(mu) if nb > 0 else torch.zeros(1, dtype=torch.float64, device="cuda")
+    trp, trh = _dev(r_p), _dev(rho_p_internal)
+    a = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    pp = make_params(params)
+    _check(lib().mx_gas_drag(C.byref(pp), n, nb, _ptr(tx), _ptr(tu), _ptr(tmu), _ptr(trp),
+                             _ptr(trh), _ptr(a), C.c_void_p(_stream())))
+    torch.cuda.synchronize()
+    return a
+
+
+def kepler_drift(mu0, x0, u0, h):
+    torch = _torch()
+    tx, tu = _dev(x0), _dev(u0)
+    n = tx.shape[1]
+    x1 = torch.empty_like(tx)
+    u1 = torch.empty_like(tu)
+    _check(lib().mx_kepler_drift(n, float(mu0), float(h), _ptr(tx), _ptr(tu), _ptr(x1), _ptr(u1),
+                                 C.c_void_p(_stream())))
+    return x1, u1
+
+
+def flag_pairs(nb, rcrit, x0, u0, x1, u1, h, cap=1 << 16):
+    torch = _torch()
+    tx0, tu0, tx1, tu1 = _dev(x0), _dev(u0), _dev(x1), _dev(u1)
+    n = tx0.shape[1]
+    trc = _dev(rcrit) if nb > 0 else torch.zeros(1, dtype=torch.float64, device="cuda")
+    pairs = torch.empty(2 * cap, dtype=torch.int32, device="cuda")
+    nout = C.c_int32(0)
+    _check(lib().mx_flag_pairs(n, nb, _ptr(trc), _ptr(tx0), _ptr(tu0), _ptr(tx1), _ptr(tu1),
+                               float(h), _ptr(pairs), cap, C.byref(nout), C.c_void_p(_stream())))
+    k = min(nout.value, cap)
+    return pairs[: 2 * k].view(-1, 2).cpu().numpy()

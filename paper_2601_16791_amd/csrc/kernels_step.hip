@@ -1,0 +1,431 @@
+// Kernels of the hybrid step that stream over bodies (gfx950, FP64 VALU).
+//
+//   growth            : core-growth mass schedule of Eq. 13 at the step start
+//   kick_jump_drift   : half kick (gravity + gas drag), jump by the massive-body
+//                       momentum, Kepler drift; keeps the pre-drift state
+//   jump_pack         : second jump; packs the massive bodies for the force
+//   force_kick        : changeover-weighted gravity (rectangular, Sect. 2.1.3)
+//                       plus gas drag and the closing half kick
+//
+// Layout: SoA [3][n] FP64 in HBM, big bodies first.  Sources of the force sum
+// are read through wave-uniform (scalar) loads of packed 64-byte records, so
+// every lane of a wave holds one target and all lanes walk the same source.
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+#include "mx_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+using mxd::DragConst;
+
+DragConst make_drag_const(const mx_params& p) {
+  DragConst c;
+  c.mu0 = p.G * p.m0;
+  c.sigma1_unit = p.sigma1 * (p.rho_unit / p.au_cm);
+  c.gamma = p.gamma;
+  c.r_c = p.r_c;
+  c.inv_rc = p.r_c > 0.0 ? 1.0 / p.r_c : 0.0;
+  c.r_in = p.r_in;
+  c.h_over_r = p.h_over_r;
+  c.vg_fac = sqrt(1.0 - 2.0 * p.eta);
+  c.kexp = p.kdrag_exp;
+  c.mfp_coef = p.mfp_coef;
+  c.rc_norm = p.r_c > 0.0 ? pow(1.0 / p.r_c, 2.0 - p.gamma) : 0.0;
+  return c;
+}
+
+// ------------------------------------------------------------------ growth
+// M(t) = M0 + e/(e-1) (Mc - M0) (1 - exp(-t/tau_c)) for t < tau_c, Mc after;
+// rcrit scales with the cube root of the mass (Hill radius).
+__global__ void k_growth(int nb, double dt, const double* __restrict__ growth,
+                         const double* __restrict__ mu_init,
+                         const double* __restrict__ rcrit_init, double* __restrict__ mu,
+                         double* __restrict__ rcrit, const DevScalars* __restrict__ dsc) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nb) return;
+  double tau = growth[3 * k + 2];
+  if (!(tau > 0.0)) return;
+  const double E = 2.718281828459045235;
+  double t = (double)dsc->step * dt;
+  double m0 = growth[3 * k], mc = growth[3 * k + 1];
+  double m = t >= tau ? mc : m0 + (E / (E - 1.0)) * (mc - m0) * (1.0 - exp(-t / tau));
+  mu[k] = m;
+  rcrit[k] = rcrit_init[k] * cbrt(m / mu_init[k]);
+}
+
+// ------------------------------------------------- kick + jump + drift
+__global__ __launch_bounds__(kBlock) void k_kick_jump_drift(
+    int n, int nb, double mu0, double h, DragConst dc, int gas_on, double* __restrict__ x,
+    double* __restrict__ u, const double* __restrict__ ag, double* __restrict__ x0s,
+    double* __restrict__ u0s, const double* __restrict__ mu, const double* __restrict__ rcrit,
+    const double* __restrict__ r_p, const double* __restrict__ rho_p,
+    FlagSource* __restrict__ fpack, DevScalars* __restrict__ dsc) {
+  __shared__ double sh[6 * kBlock];
+  const double hh = 0.5 * h;
+  // massive-body momentum before (drag frame) and after the half kick (jump);
+  // big bodies feel no drag, so their kicked velocity is u + hh * ag.
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = threadIdx.x; k < nb; k += kBlock) {
+    double m = mu[k];
+    double ux = u[k], uy = u[n + k], uz = u[2 * n + k];
+    v[0] += m * ux;
+    v[1] += m * uy;
+    v[2] += m * uz;
+    v[3] += m * (ux + hh * (ag[k] + 0.0));
+    v[4] += m * (uy + hh * (ag[n + k] + 0.0));
+    v[5] += m * (uz + hh * (ag[2 * n + k] + 0.0));
+  }
+  mxd::block_sum<kBlock, 6>(v, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    dsc->n_pairs = 0;
+    dsc->n_sub = 0;
+  }
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  double px = x[t], py = x[n + t], pz = x[2 * n + t];
+  double vx = u[t], vy = u[n + t], vz = u[2 * n + t];
+  double adx = 0.0, ady = 0.0, adz = 0.0;
+  if (t >= nb && gas_on) {
+    int j = t - nb;
+    mxd::gas_drag(dc, px, py, vx + v[0] / mu0, vy + v[1] / mu0, vz + v[2] / mu0, r_p[j],
+                  rho_p[j], adx, ady, adz);
+  }
+  vx += hh * (ag[t] + adx);
+  vy += hh * (ag[n + t] + ady);
+  vz += hh * (ag[2 * n + t] + adz);
+  px += hh * v[3] / mu0;
+  py += hh * v[4] / mu0;
+  pz += hh * v[5] / mu0;
+  x0s[t] = px; x0s[n + t] = py; x0s[2 * n + t] = pz;
+  u0s[t] = vx; u0s[n + t] = vy; u0s[2 * n + t] = vz;
+  double qx = px, qy = py, qz = pz, wx = vx, wy = vy, wz = vz;
+  if (!mxd::kepler_drift(mu0, h, qx, qy, qz, wx, wy, wz)) atomicOr(&dsc->err, MXE_NOCONV);
+  x[t] = qx; x[n + t] = qy; x[2 * n + t] = qz;
+  u[t] = wx; u[n + t] = wy; u[2 * n + t] = wz;
+  if (t < nb) {
+    FlagSource f;
+    f.x0 = px; f.y0 = py; f.z0 = pz; f.u0x = vx; f.u0y = vy; f.u0z = vz;
+    f.dx = qx - px; f.dy = qy - py; f.dz = qz - pz;  // displacement over the drift
+    f.u1x = wx; f.u1y = wy; f.u1z = wz;
+    f.rc = rcrit[t];
+    f.pad0 = f.pad1 = f.pad2 = 0.0;
+    fpack[t] = f;
+  }
+}
+
+// ------------------------------------------------------------ jump + pack
+// x += (h/2) P / mu0 with P over the massive bodies (after the encounter
+// integrator); records P for the drag of the closing kick and packs the
+// massive bodies for the force sum.  rc2 is floored at 1e-300 so that a body's
+// own entry falls in the K = 0 branch.
+__global__ __launch_bounds__(kBlock) void k_jump_pack(int n, int nb, double mu0, double hh,
+                                                      double* __restrict__ x,
+                                                      const double* __restrict__ u,
+                                                      const double* __restrict__ mu,
+                                                      const double* __restrict__ rcrit,
+                                                      KickSource* __restrict__ kpack,
+                                                      DevScalars* __restrict__ dsc, int jump) {
+  __shared__ double sh[3 * kBlock];
+  double v[3] = {0, 0, 0};
+  for (int k = threadIdx.x; k < nb; k += kBlock) {
+    double m = mu[k];
+    v[0] += m * u[k];
+    v[1] += m * u[n + k];
+    v[2] += m * u[2 * n + k];
+  }
+  mxd::block_sum<kBlock, 3>(v, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    dsc->P[0] = v[0];
+    dsc->P[1] = v[1];
+    dsc->P[2] = v[2];
+  }
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  double px = x[t], py = x[n + t], pz = x[2 * n + t];
+  if (jump) {
+    px += hh * v[0] / mu0;
+    py += hh * v[1] / mu0;
+    pz += hh * v[2] / mu0;
+    x[t] = px; x[n + t] = py; x[2 * n + t] = pz;
+  }
+  if (t < nb) {
+    KickSource k;
+    double rc = rcrit[t];
+    k.x = px; k.y = py; k.z = pz;
+    k.mu = mu[t];
+    k.rc2 = fmax(rc * rc, 1e-300);
+    k.rc = rc;
+    k.pad0 = k.pad1 = 0.0;
+    kpack[t] = k;
+  }
+}
+
+// ------------------------------------------------------------- force + kick
+// Each lane holds one target t; the wave walks sources [s0, s1) of its split
+// with scalar loads.  Fast branch (s2 >= rc2, K = 1): mu * y^3 with y the
+// corrected hardware rsqrt.  Changeover branch (rare, divergent): the quintic K.
+// With split > 1 the per-split partial sums go to `part`; the last block of a
+// target tile (atomic ticket) adds the partials in split order, so the result
+// does not depend on block scheduling.
+__device__ __forceinline__ void force_sum(const KickSource* __restrict__ src, int s0, int s1,
+                                          double xt, double yt, double zt, double rc2t,
+                                          double rct, double& ax, double& ay, double& az) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
+  for (int s = s0; s < s1; ++s) {
+    const KickSource S = src[s];
+    double dx = S.x - xt, dy = S.y - yt, dz = S.z - zt;
+    double s2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    double rc2 = fmax(S.rc2, rc2t);
+    double y0 = __builtin_amdgcn_rsq(s2);
+    double y2 = y0 * y0;
+    double e = fma(-s2, y2, 1.0);
+    double c = fma(e, fma(e, 1.875, 1.5), 1.0);
+    double w = (S.mu * y0) * y2 * c;
+    if (__builtin_expect(s2 < rc2, 0)) {
+      w = S.mu * mxd::changeover_weight_slow(s2, fmax(S.rc, rct), rc2);
+    }
+    a0 = fma(w, dx, a0);
+    a1 = fma(w, dy, a1);
+    a2 = fma(w, dz, a2);
+  }
+  ax = a0; ay = a1; az = a2;
+}
+
+__device__ __forceinline__ void finish_body(int t, int n, int nb, double mu0, double hh,
+                                            const DragConst& dc, int gas_on, int kick,
+                                            double ax, double ay, double az,
+                                            const double* __restrict__ x,
+                                            double* __restrict__ u, double* __restrict__ ag,
+                                            const double* __restrict__ r_p,
+                                            const double* __restrict__ rho_p,
+                                            const double* P, int32_t* err) {
+  ag[t] = ax; ag[n + t] = ay; ag[2 * n + t] = az;
+  if (!kick) return;
+  double vx = u[t], vy = u[n + t], vz = u[2 * n + t];
+  double adx = 0.0, ady = 0.0, adz = 0.0;
+  if (t >= nb && gas_on) {
+    int j = t - nb;
+    mxd::gas_drag(dc, x[t], x[n + t], vx + P[0] / mu0, vy + P[1] / mu0, vz + P[2] / mu0,
+                  r_p[j], rho_p[j], adx, ady, adz);
+  }
+  vx += hh * (ax + adx);
+  vy += hh * (ay + ady);
+  vz += hh * (az + adz);
+  u[t] = vx; u[n + t] = vy; u[2 * n + t] = vz;
+  double chk = vx + vy + vz + x[t] + x[n + t] + x[2 * n + t];
+  if (!isfinite(chk)) atomicOr(err, MXE_NONFINITE);
+}
+
+__global__ __launch_bounds__(kBlock) void k_force_kick(
+    int n, int nb, int split, double mu0, double hh, DragConst dc, int gas_on, int kick,
+    const double* __restrict__ x, double* __restrict__ u, double* __restrict__ ag,
+    const KickSource* __restrict__ kpack, const double* __restrict__ r_p,
+    const double* __restrict__ rho_p, double* __restrict__ part, int32_t* __restrict__ tile_cnt,
+    DevScalars* __restrict__ dsc) {
+  const int tile = blockIdx.x / split;
+  const int sp = blockIdx.x - tile * split;
+  const int t = tile * kBlock + threadIdx.x;
+  const int tt = t < n ? t : n - 1;
+  if (kick && blockIdx.x == 0 && threadIdx.x == 0) dsc->step += 1;
+  const double xt = x[tt], yt = x[n + tt], zt = x[2 * n + tt];
+  double rct = 0.0, rc2t = 0.0;
+  if (tt < nb) {
+    rct = kpack[tt].rc;
+    rc2t = rct * rct;
+  }
+  const int per = (nb + split - 1) / split;
+  const int s0 = sp * per;
+  const int s1 = min(nb, s0 + per);
+  double ax, ay, az;
+  force_sum(kpack, s0, s1, xt, yt, zt, rc2t, rct, ax, ay, az);
+  double P[3] = {dsc->P[0], dsc->P[1], dsc->P[2]};
+  if (split == 1) {
+    if (t < n) finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, ax, ay, az, x, u, ag, r_p, rho_p, P, &dsc->err);
+  } else {
+    if (t < n) {
+      size_t base = (size_t)sp * 3 * n;
+      part[base + t] = ax;
+      part[base + n + t] = ay;
+      part[base + 2 * n + t] = az;
+    }
+    __threadfence();
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int ticket = atomicAdd(&tile_cnt[tile], 1);
+      last = (ticket == split - 1);
+      if (last) tile_cnt[tile] = 0;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (t < n) {
+      double bx = 0.0, by = 0.0, bz = 0.0;
+      for (int q = 0; q < split; ++q) {
+        size_t base = (size_t)q * 3 * n;
+        bx += __builtin_nontemporal_load(&part[base + t]);
+        by += __builtin_nontemporal_load(&part[base + n + t]);
+        bz += __builtin_nontemporal_load(&part[base + 2 * n + t]);
+      }
+      finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, bx, by, bz, x, u, ag, r_p, rho_p, P, &dsc->err);
+    }
+  }
+}
+
+// stateless gravity (single-kernel entry): packs then sums, no kick
+__global__ void k_pack_plain(int n, int nb, const double* __restrict__ x,
+                             const double* __restrict__ mu, const double* __restrict__ rcrit,
+                             KickSource* __restrict__ kp) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb) return;
+  double rc = rcrit[t];
+  KickSource k;
+  k.x = x[t]; k.y = x[n + t]; k.z = x[2 * n + t];
+  k.mu = mu[t];
+  k.rc2 = fmax(rc * rc, 1e-300);
+  k.rc = rc;
+  k.pad0 = k.pad1 = 0.0;
+  kp[t] = k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gravity_plain(int n, int nb,
+                                                          const double* __restrict__ x,
+                                                          const KickSource* __restrict__ kp,
+                                                          double* __restrict__ a) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int tt = t < n ? t : n - 1;
+  double rct = tt < nb ? kp[tt].rc : 0.0;
+  double ax, ay, az;
+  force_sum(kp, 0, nb, x[tt], x[n + tt], x[2 * n + tt], rct * rct, rct, ax, ay, az);
+  if (t < n) { a[t] = ax; a[n + t] = ay; a[2 * n + t] = az; }
+}
+
+__global__ __launch_bounds__(kBlock) void k_drag_plain(int n, int nb, double mu0, DragConst dc,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ u,
+                                                       const double* __restrict__ mu,
+                                                       const double* __restrict__ r_p,
+                                                       const double* __restrict__ rho_p,
+                                                       double* __restrict__ a) {
+  __shared__ double sh[3 * kBlock];
+  double v[3] = {0, 0, 0};
+  for (int k = threadIdx.x; k < nb; k += kBlock) {
+    v[0] += mu[k] * u[k];
+    v[1] += mu[k] * u[n + k];
+    v[2] += mu[k] * u[2 * n + k];
+  }
+  mxd::block_sum<kBlock, 3>(v, sh);
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  if (t >= nb) {
+    int j = t - nb;
+    mxd::gas_drag(dc, x[t], x[n + t], u[t] + v[0] / mu0, u[n + t] + v[1] / mu0,
+                  u[2 * n + t] + v[2] / mu0, r_p[j], rho_p[j], ax, ay, az);
+  }
+  a[t] = ax; a[n + t] = ay; a[2 * n + t] = az;
+}
+
+__global__ __launch_bounds__(kBlock) void k_kepler_plain(int n, double mu0, double h,
+                                                         const double* __restrict__ x0,
+                                                         const double* __restrict__ u0,
+                                                         double* __restrict__ x1,
+                                                         double* __restrict__ u1,
+                                                         int32_t* __restrict__ err) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  double px = x0[t], py = x0[n + t], pz = x0[2 * n + t];
+  double vx = u0[t], vy = u0[n + t], vz = u0[2 * n + t];
+  if (!mxd::kepler_drift(mu0, h, px, py, pz, vx, vy, vz)) atomicOr(err, MXE_NOCONV);
+  x1[t] = px; x1[n + t] = py; x1[2 * n + t] = pz;
+  u1[t] = vx; u1[n + t] = vy; u1[2 * n + t] = vz;
+}
+
+int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
+
+}  // namespace
+
+namespace mxk {
+
+int force_split(int n, int nb) {
+  int tiles = blocks_for(n);
+  int split = (512 + tiles - 1) / tiles;
+  int maxs = nb / 32;
+  if (split > maxs) split = maxs;
+  if (split > 64) split = 64;
+  if (split < 1) split = 1;
+  return split;
+}
+
+hipError_t launch_growth(mx_system* s) {
+  if (!s->has_growth || s->nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_growth, dim3((s->nb + 255) / 256), dim3(256), 0, s->stream, s->nb, s->p.dt,
+                     s->growth, s->mu_init, s->rcrit_init, s->mu, s->rcrit, s->dsc);
+  return hipGetLastError();
+}
+
+hipError_t launch_kick_jump_drift(mx_system* s) {
+  DragConst dc = make_drag_const(s->p);
+  hipLaunchKernelGGL(k_kick_jump_drift, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n,
+                     s->nb, s->mu0, s->p.dt, dc, s->p.gas_on, s->x, s->u, s->ag, s->x0, s->u0,
+                     s->mu, s->rcrit, s->r_p, s->rho_p, s->fpack, s->dsc);
+  return hipGetLastError();
+}
+
+hipError_t launch_jump_pack(mx_system* s) {
+  hipLaunchKernelGGL(k_jump_pack, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n, s->nb,
+                     s->mu0, 0.5 * s->p.dt, s->x, s->u, s->mu, s->rcrit, s->kpack, s->dsc, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_only(mx_system* s) {
+  hipLaunchKernelGGL(k_jump_pack, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n, s->nb,
+                     s->mu0, 0.0, s->x, s->u, s->mu, s->rcrit, s->kpack, s->dsc, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_kick(mx_system* s, int kick) {
+  DragConst dc = make_drag_const(s->p);
+  int grid = blocks_for(s->n) * s->split;
+  hipLaunchKernelGGL(k_force_kick, dim3(grid), dim3(kBlock), 0, s->stream, s->n, s->nb, s->split,
+                     s->mu0, 0.5 * s->p.dt, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->kpack,
+                     s->r_p, s->rho_p, s->part, s->tile_cnt, s->dsc);
+  return hipGetLastError();
+}
+
+hipError_t gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,
+                   double* a, hipStream_t st) {
+  KickSource* kp = nullptr;
+  hipError_t e = hipMalloc((void**)&kp, sizeof(KickSource) * (nb > 0 ? nb : 1));
+  if (e != hipSuccess) return e;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_pack_plain, dim3((nb + 255) / 256), dim3(256), 0, st, n, nb, x, mu,
+                       rcrit, kp);
+  hipLaunchKernelGGL(k_gravity_plain, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, nb, x, kp, a);
+  e = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(st);
+  (void)hipFree(kp);
+  return e != hipSuccess ? e : e2;
+}
+
+hipError_t gas_drag(const mx_params* p, int n, int nb, const double* x, const double* u,
+                    const double* mu, const double* r_p, const double* rho_p, double* a,
+                    hipStream_t st) {
+  DragConst dc = make_drag_const(*p);
+  hipLaunchKernelGGL(k_drag_plain, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, nb, p->G * p->m0,
+                     dc, x, u, mu, r_p, rho_p, a);
+  return hipGetLastError();
+}
+
+hipError_t kepler(int n, double mu0, double h, const double* x0, const double* u0, double* x1,
+                  double* u1, int32_t* err, hipStream_t st) {
+  hipLaunchKernelGGL(k_kepler_plain, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, mu0, h, x0, u0,
+                     x1, u1, err);
+  return hipGetLastError();
+}
+
+}  // namespace mxk

@@ -1,0 +1,113 @@
+// Internal layout of an mx_system and the host-side launchers of its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mx.h"
+
+// Latched device failure bits (OR-ed by kernels into mx_system::d_err).
+enum : int32_t {
+  MXE_NOCONV = 1,      // Kepler iteration did not converge
+  MXE_BS = 2,          // Bulirsch-Stoer halving limit
+  MXE_PAIRS = 4,       // more flagged pairs than the list holds
+  MXE_SUBSYS = 8,      // a subsystem larger than the encounter integrator holds
+  MXE_NONFINITE = 16,  // non-finite state after a step
+};
+
+// Encounter-integrator capacity (members and pairs of one subsystem).
+constexpr int kBsMaxMembers = 16;
+constexpr int kBsMaxPairs = 48;
+constexpr int kBsColumns = 8;   // substep sequence n = 2, 4, ..., 16
+
+// Packed source records read with scalar (wave-uniform) loads.
+struct __align__(64) KickSource {   // one massive body at kick time
+  double x, y, z, mu, rc2, rc, pad0, pad1;
+};
+struct __align__(128) FlagSource {  // one massive body over a drift
+  double x0, y0, z0, u0x, u0y, u0z;   // pre-drift state
+  double dx, dy, dz;                  // displacement x1 - x0 over the drift
+  double u1x, u1y, u1z;               // post-drift velocity
+  double rc, pad0, pad1, pad2;
+};
+
+struct Subsystem {                  // one Bulirsch-Stoer subsystem
+  int32_t m, keep_from, np, pad;
+  int32_t mem[kBsMaxMembers];
+  int32_t pl[kBsMaxPairs][2];
+};
+
+// Device scalars of a system (one allocation).
+struct DevScalars {
+  int64_t step;          // step counter (t = step * dt)
+  int32_t n_pairs;       // flagged pairs in the last step
+  int32_t n_sub;         // subsystems in the last step
+  int32_t err;           // latched failure bits
+  int32_t pad;
+  double P[3];           // massive-body momentum sum mu*u after the last jump
+};
+
+struct mx_system {
+  mx_params p;
+  int n, nb, ns;
+  double mu0;
+  hipStream_t stream;
+  bool own_stream;
+  // state, [3][n] SoA
+  double *x, *u, *ag, *x0, *u0;
+  // massive bodies
+  double *mu, *rcrit, *mu_init, *rcrit_init, *growth;  // growth: [nb][3] (G*M0, G*Mc, tau)
+  int has_growth;
+  // massless bodies
+  double *r_p, *rho_p;  // rho_p in Msun/AU^3
+  // packed sources
+  KickSource* kpack;
+  FlagSource* fpack;
+  // force split partials and tile counters
+  double* part;
+  int32_t* tile_cnt;
+  int split;
+  // encounters
+  int32_t* pairs;      // [cap][2]
+  int32_t* pairs_tmp;  // [cap][2] scratch of the planner
+  int32_t cap_pairs;
+  Subsystem* subs;
+  int32_t cap_subs;
+  int32_t* uf;         // [nb] union-find scratch
+  DevScalars* dsc;
+  // energy scratch
+  double* red;
+  int red_blocks;
+  // graph of one step
+  hipGraphExec_t graph;
+  bool graph_ok;
+  int64_t host_step;
+};
+
+// ---- launchers (kernels_*.hip)
+namespace mxk {
+hipError_t launch_growth(mx_system* s);
+hipError_t launch_kick_jump_drift(mx_system* s);
+hipError_t launch_flag(mx_system* s);
+hipError_t launch_bs(mx_system* s);
+hipError_t launch_jump_pack(mx_system* s);
+hipError_t launch_force_kick(mx_system* s, int kick);
+hipError_t launch_pack_only(mx_system* s);
+hipError_t launch_energy(mx_system* s, double* out7);  // device [7] out
+hipError_t launch_h2dh(mx_system* s, const double* v_h);
+hipError_t launch_dh2h(mx_system* s, double* v_h);
+hipError_t launch_init_bodies(mx_system* s, const double* x_h, const double* v_h);
+hipError_t launch_reset_scalars(mx_system* s, int64_t step);
+
+// stateless single-kernel launchers
+hipError_t gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,
+                   double* a, hipStream_t st);
+hipError_t gas_drag(const mx_params* p, int n, int nb, const double* x, const double* u,
+                    const double* mu, const double* r_p, const double* rho_p, double* a,
+                    hipStream_t st);
+hipError_t kepler(int n, double mu0, double h, const double* x0, const double* u0, double* x1,
+                  double* u1, int32_t* err, hipStream_t st);
+hipError_t flag_pairs(int n, int nb, const double* rcrit, const double* x0, const double* u0,
+                      const double* x1, const double* u1, double h, int32_t* pairs,
+                      int32_t* pairs_tmp, int32_t cap, int32_t* counter, hipStream_t st);
+}  // namespace mxk

@@ -1,0 +1,279 @@
+"""Parity of the HIP path with the CPU oracle (GPU tests, called through the C ABI).
+
+Tolerances: positions and velocities of one step 1e-12 relative (per body, against
+the body's own |x| and |u|); energy-drift difference 1e-10.  Kernel-level checks
+use the same seeded inputs on both sides.  Floating-point decisions that pick an
+integer result (encounter flags) are compared exactly; a mismatch is accepted only
+where the deciding quantity lies within 1e-10 relative of its threshold.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from synth import ic
+
+pytestmark = pytest.mark.gpu
+
+G = ic.G
+MU0 = G
+
+
+@pytest.fixture(scope="module")
+def mx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_16791_amd as m
+    m.lib()
+    return m
+
+
+def relerr_rows(a, b):
+    """max over bodies of |a_t - b_t| / |b_t| (3-vectors per body)."""
+    num = np.linalg.norm(a - b, axis=0)
+    den = np.linalg.norm(b, axis=0)
+    den = np.where(den > 0, den, 1.0)
+    return float((num / den).max()) if a.size else 0.0
+
+
+# ----------------------------------------------------------- gravity kernel
+@pytest.mark.parametrize("n,nb,spread,rcf", [
+    (1, 1, 1.0, 0.01), (7, 3, 1.0, 0.01), (255, 10, 5.0, 0.02), (257, 10, 5.0, 0.02),
+    (1000, 40, 0.5, 0.3), (3000, 3000, 4.0, 0.002), (600, 0, 1.0, 0.1)])
+def test_gravity_kernel_matches_oracle(mx, orc, n, nb, spread, rcf):
+    rng = np.random.default_rng(n * 7 + nb)
+    x = rng.uniform(-spread, spread, (3, n))
+    mu = rng.uniform(1e-10, 1e-6, nb)
+    rcrit = rng.uniform(0.5, 1.5, nb) * rcf * spread
+    a_o = orc.gravity(x, mu, rcrit, nb)
+    a_g = mx.gravity(x, mu, rcrit, nb).cpu().numpy()
+    scale = np.abs(a_o).max() if nb else 1.0
+    err = np.abs(a_g - a_o)
+    assert np.all(err <= 1e-12 * np.abs(a_o) + 1e-14 * scale), err.max()
+
+
+def test_gravity_changeover_zone_pairs(mx, orc):
+    # every pair inside the changeover zone, including the K = 0 core
+    rng = np.random.default_rng(1)
+    n = 300
+    x = rng.uniform(-0.05, 0.05, (3, n))
+    mu = rng.uniform(1e-9, 1e-7, n)
+    rcrit = np.full(n, 0.08)
+    a_o = orc.gravity(x, mu, rcrit, n)
+    a_g = mx.gravity(x, mu, rcrit, n).cpu().numpy()
+    assert relerr_rows(a_g, a_o) < 1e-11
+
+
+# -------------------------------------------------------------- drag kernel
+def test_drag_kernel_matches_oracle(mx, orc):
+    w = ic.embryo_disk(seed=3, n_small=5000, n_emb=6)
+    o = orc.OracleSystem.from_workload(w)
+    x, u = o.get_dh()
+    mu, _ = o.mu()
+    rho = w.rho_p * ic.RHO_UNIT
+    a_o = orc.drag(w.params, x, u, mu, w.r_p, rho, w.params["n_big"])
+    a_g = mx.gas_drag(w.params, x, u, mu, w.r_p, rho, w.params["n_big"]).cpu().numpy()
+    nb = w.params["n_big"]
+    assert np.all(a_g[:, :nb] == 0)
+    assert relerr_rows(a_g[:, nb:], a_o[:, nb:]) < 1e-12
+
+
+def test_drag_kernel_general_disk(mx, orc):
+    """Tapered disk (gamma != 1), inner edge, other C_D exponent."""
+    w = ic.embryo_disk(seed=4, n_small=3000, n_emb=3)
+    p = dict(w.params, gamma=0.8, r_c=6.0, r_in=1.5, kdrag_exp=-1.0, eta=0.004)
+    o = orc.OracleSystem(p, w.x, w.v, w.m_big, w.r_p, w.rho_p)
+    x, u = o.get_dh()
+    mu, _ = o.mu()
+    rho = w.rho_p * ic.RHO_UNIT
+    a_o = orc.drag(p, x, u, mu, w.r_p, rho, p["n_big"])
+    a_g = mx.gas_drag(p, x, u, mu, w.r_p, rho, p["n_big"]).cpu().numpy()
+    nb = p["n_big"]
+    R = np.hypot(x[0, nb:], x[1, nb:])
+    assert np.all(a_g[:, nb:][:, R < 1.5] == 0)
+    assert relerr_rows(a_g[:, nb:], a_o[:, nb:]) < 1e-11
+
+
+# -------------------------------------------------------------- Kepler drift
+@pytest.mark.parametrize("kind", ["disk", "eccentric", "hyperbolic", "near_parabolic", "backward"])
+def test_kepler_kernel_matches_oracle(mx, orc, kind):
+    rng = np.random.default_rng(["disk", "eccentric", "hyperbolic", "near_parabolic", "backward"].index(kind))
+    k = 513
+    r = rng.uniform(0.5, 12, k)
+    th = rng.uniform(0, 2 * np.pi, k)
+    x0 = np.stack([r * np.cos(th), r * np.sin(th), rng.normal(0, 0.02, k) * r])
+    vc = np.sqrt(MU0 / r)
+    tang = np.stack([-np.sin(th), np.cos(th), np.zeros(k)])
+    h = 18.26
+    if kind == "disk":
+        v0 = tang * vc * rng.uniform(0.97, 1.03, k) + rng.normal(0, 0.01, (3, k)) * vc
+    elif kind == "eccentric":
+        v0 = tang * vc * rng.uniform(0.2, 1.35, k)
+        h = 400.0
+    elif kind == "hyperbolic":
+        v0 = tang * vc * rng.uniform(1.5, 3.0, k) + rng.normal(0, 0.1, (3, k)) * vc
+        h = 300.0
+    elif kind == "near_parabolic":
+        v0 = tang * np.sqrt(2 * MU0 / np.linalg.norm(x0, axis=0)) * (1 + rng.uniform(-1e-8, 1e-8, k))
+        h = 50.0
+    else:
+        v0 = tang * vc * rng.uniform(0.9, 1.1, k)
+        h = -25.0
+    xo = np.zeros_like(x0); vo = np.zeros_like(v0)
+    for t in range(k):
+        xo[:, t], vo[:, t] = orc.drift(MU0, x0[:, t], v0[:, t], h)
+    xg, vg = mx.kepler_drift(MU0, x0, v0, h)
+    assert relerr_rows(xg.cpu().numpy(), xo) < 1e-12
+    assert relerr_rows(vg.cpu().numpy(), vo) < 1e-12
+
+
+# --------------------------------------------------------------- flagging
+def _flag_inputs(orc, seed, nb, ns, h, spread=0.08):
+    rng = np.random.default_rng(seed)
+    n = nb + ns
+    a = np.concatenate([rng.uniform(3.0, 3.5, nb), rng.uniform(2.8, 3.7, ns)])
+    e = rng.uniform(0, 0.05, n)
+    inc = rng.uniform(0, 0.01, n)
+    O = np.full(n, 0.3); w = np.full(n, 1.1)
+    M = np.concatenate([rng.uniform(0, 0.5, nb), rng.normal(0.25, spread, ns)])
+    x0, u0 = ic.el2x(MU0, a, e, inc, O, w, M)
+    x1 = np.zeros_like(x0); u1 = np.zeros_like(u0)
+    for t in range(n):
+        x1[:, t], u1[:, t] = orc.drift(MU0, x0[:, t], u0[:, t], h)
+    return x0, u0, x1, u1
+
+
+@pytest.mark.parametrize("nb,ns", [(3, 700), (40, 300), (300, 0)])
+def test_flag_kernel_matches_oracle(mx, orc, nb, ns):
+    h = 20.0
+    x0, u0, x1, u1 = _flag_inputs(orc, nb + ns, nb, ns, h)
+    rcrit = np.random.default_rng(2).uniform(0.02, 0.08, nb)
+    po = orc.flag(nb, rcrit, x0, u0, x1, u1, h)
+    pg = mx.flag_pairs(nb, rcrit, x0, u0, x1, u1, h)
+    so, sg = {tuple(p) for p in po}, {tuple(p) for p in pg}
+    assert len(so) > 3
+    for (i, j) in so ^ sg:  # only borderline decisions may differ
+        rc = max(rcrit[i], rcrit[j] if j < nb else 0.0)
+        d = orc.pair_dmin2(x0[:, j] - x0[:, i], u0[:, j] - u0[:, i], x1[:, j] - x1[:, i],
+                           u1[:, j] - u1[:, i], h)
+        assert abs(d - rc * rc) <= 1e-10 * rc * rc, (i, j, d, rc * rc)
+    assert np.array_equal(pg, np.array(sorted(sg), dtype=np.int32).reshape(-1, 2))
+
+
+# -------------------------------------------------------- whole-step parity
+def _workloads():
+    c1 = ic.two_giants(seed=0, n_small=400)
+    c2 = ic.embryo_disk(seed=0, n_small=3000, n_emb=10)
+    c3 = ic.self_gravitating(seed=0, n_pl=4, n_pls=600)
+    c3.growth[:4, 2] = 40 * c3.params["dt"]   # the mass schedule moves within the test
+    return {"two_giants": c1, "embryo_disk": c2, "self_gravitating": c3}
+
+
+@pytest.mark.parametrize("name", ["two_giants", "embryo_disk", "self_gravitating"])
+def test_step_parity_per_step(mx, orc, name):
+    w = _workloads()[name]
+    g = mx.System.from_workload(w)
+    o = orc.OracleSystem.from_workload(w)
+    x, u = g.get_dh()
+    o.set_dh(x, u, 0)
+    g.set_dh(x, u, 0)
+    assert relerr_rows(g.accel(), o.accel()) < 1e-12
+    n_enc = 0
+    for k in range(6):
+        g.step(1)
+        g.sync()
+        o.step(1)
+        xg, ug = g.get_dh()
+        xo, uo = o.get_dh()
+        pg, po = g.encounters(), o.encounters()
+        n_enc += len(po)
+        same_pairs = {tuple(p) for p in pg} == {tuple(p) for p in po}
+        ex, eu = relerr_rows(xg, xo), relerr_rows(ug, uo)
+        assert same_pairs, (k, len(pg), len(po))
+        assert ex < 1e-12 and eu < 1e-12, (k, ex, eu)
+        mu_g, rc_g = g.masses()
+        mu_o, rc_o = o.mu()
+        assert np.allclose(mu_g, mu_o, rtol=1e-14, atol=0)
+        o.set_dh(xg, ug, o.step_index())      # same bits into the next step
+    if name != "self_gravitating":
+        assert n_enc > 0
+
+
+def test_energy_matches_oracle(mx, orc):
+    w = ic.self_gravitating(seed=1, n_pl=4, n_pls=900)
+    g = mx.System.from_workload(w)
+    o = orc.OracleSystem.from_workload(w)
+    x, u = g.get_dh()
+    o.set_dh(x, u, 0)
+    E, L = g.energy()
+    Eo, Lo = o.energy()
+    assert abs(E - Eo) <= 1e-13 * abs(Eo)
+    assert np.allclose(L, Lo, rtol=1e-13, atol=1e-13 * np.abs(Lo).max())
+
+
+def test_energy_drift_matches_oracle(mx, orc):
+    """Independent trajectories (no re-seeding) of the two-giant system."""
+    w = ic.two_giants(seed=2, n_small=200)
+    g = mx.System.from_workload(w)
+    o = orc.OracleSystem.from_workload(w)
+    x, u = g.get_dh()
+    o.set_dh(x, u, 0)
+    g.set_dh(x, u, 0)
+    E0g, _ = g.energy()
+    E0o, _ = o.energy()
+    g.step(500)
+    g.sync()
+    o.step(500)
+    Eg, _ = g.energy()
+    Eo, _ = o.energy()
+    dg = (Eg - E0g) / abs(E0g)
+    do = (Eo - E0o) / abs(E0o)
+    assert abs(dg - do) < 1e-10, (dg, do)
+
+
+# ----------------------------------------------------- determinism, resume
+def test_bitwise_deterministic_and_resumable(mx):
+    w = ic.embryo_disk(seed=5, n_small=2000, n_emb=8)
+    a = mx.System.from_workload(w)
+    b = mx.System.from_workload(w)
+    a.step(20)
+    b.step(10)
+    xb, ub = b.get_dh()
+    c = mx.System.from_workload(w)
+    c.set_dh(xb, ub, 10)
+    c.step(10)
+    b.step(10)
+    xa, ua = a.get_dh()
+    xb, ub = b.get_dh()
+    xc, uc = c.get_dh()
+    assert np.array_equal(xa, xb) and np.array_equal(ua, ub)
+    assert np.array_equal(xa, xc) and np.array_equal(ua, uc)
+    assert a.step_index() == 20 and c.step_index() == 20
+
+
+def test_heliocentric_roundtrip(mx, orc):
+    w = ic.two_giants(seed=3, n_small=100)
+    g = mx.System.from_workload(w)
+    x, v = g.get_state()
+    assert np.allclose(x, w.x, rtol=0, atol=0)
+    assert relerr_rows(v, w.v) < 1e-14
+
+
+# ----------------------------------------------------------------- errors
+def test_error_paths(mx):
+    w = ic.two_giants(seed=0, n_small=10)
+    bad = dict(w.params, m0=-1.0)
+    with pytest.raises(mx.MxError) as e:
+        mx.System(bad, w.x, w.v, w.m_big)
+    assert e.value.code == -1
+    m = w.m_big.copy(); m[0] = 0.0
+    with pytest.raises(mx.MxError) as e:
+        mx.System(w.params, w.x, w.v, m)
+    assert e.value.code == -1
+    x = w.x.copy(); x[0, 5] = np.nan
+    g = mx.System(w.params, x, w.v, w.m_big)
+    g.step(1)
+    with pytest.raises(mx.MxError) as e:
+        g.sync()
+    assert e.value.code in (-6, -4)
