@@ -254,7 +254,9 @@ int or_drift(double mu, const double x0[3], const double v0[3], double h, double
       double En = E - F / Fp;
       if (converged(En - E, En)) { E = En; ok = 1; break; }
       if (!(En > lo && En < hi)) En = 0.5 * (lo + hi);
+      double d = En - E;
       E = En;
+      if (converged(d, E)) { ok = 1; break; }
     }
     if (!ok) return OR_ENOCONV;
     double sE = sin(E);
@@ -290,7 +292,9 @@ int or_drift(double mu, const double x0[3], const double v0[3], double h, double
       double Hn = H - F / Fp;
       if (converged(Hn - H, Hn)) { H = Hn; ok = 1; break; }
       if (!(Hn > lo && Hn < hi)) Hn = 0.5 * (lo + hi);
+      double d = Hn - H;
       H = Hn;
+      if (converged(d, H)) { ok = 1; break; }
     }
 #undef HF
     if (!ok) return OR_ENOCONV;
@@ -332,7 +336,9 @@ int or_drift(double mu, const double x0[3], const double v0[3], double h, double
       double Sn = S - F / rr;
       if (converged(Sn - S, Sn)) { S = Sn; ok = 1; break; }
       if (!(Sn > lo && Sn < hi)) Sn = 0.5 * (lo + hi);
+      double d = Sn - S;
       S = Sn;
+      if (converged(d, S)) { ok = 1; break; }
     }
 #undef UF
     if (!ok) return OR_ENOCONV;
