@@ -201,16 +201,16 @@ __device__ __forceinline__ bool kepler_drift(double mu, double h, double& x, dou
     }
     if (F < 0.0) lo = s;
     else hi = s;
-    double ds = F / (Fp - 0.5 * F * Fpp / Fp);
-    double sn = s - ds;
-    if (fabs(ds) <= 1e-13 * fabs(sn)) {
+    double sn = s - F / (Fp - 0.5 * F * Fpp / Fp);
+    if (fabs(sn - s) <= 1e-13 * fabs(sn)) {
       s = sn;
       ok = true;
       break;
     }
     if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+    double ds = sn - s;
     s = sn;
-    if (lo == hi) {
+    if (fabs(ds) <= 1e-13 * fabs(s) || lo == hi) {
       ok = true;
       break;
     }

@@ -6,11 +6,11 @@
 //                  rest get the Hermite minimum-separation test; flagged pairs are
 //                  appended with an integer atomic (the mce_snif critical region of
 //                  Sect. 2.1.2 becomes a ticket counter)
-//   k_sort_pairs : one block, bitonic sort of the list by (i, j): deterministic
-//                  order whatever the append order was
-//   k_plan       : one block; connected big-big components and one subsystem per
-//                  flagged massless body with copies of the big components it
-//                  touches
+//   k_plan       : one block: bitonic sort of the list by (i, j) (deterministic
+//                  order whatever the append order was), connected big-big
+//                  components, and one subsystem per flagged massless body with
+//                  copies of the big components it touches; ordered compactions
+//                  by block-wide prefix sums, one massless subsystem per thread
 //   k_bs         : one wave per subsystem; the eight Stoermer sequences of a BS
 //                  step run in eight lanes at once, the Aitken-Neville table is
 //                  built across lanes, and the first accepted column is taken, the
@@ -50,8 +50,10 @@ __global__ __launch_bounds__(kBlock) void k_flag(
   const int jmax = min(n - 1, tile * kBlock + kBlock - 1);
   s1 = min(s1, jmax);
   const double k427 = (4.0 / 27.0) * fabs(h);
+  FlagSource S;
+  if (s0 < s1) S = fp[s0];
   for (int i = s0; i < s1; ++i) {
-    const FlagSource S = fp[i];
+    const FlagSource N = fp[i + 1 < s1 ? i + 1 : i];  // requested ahead of use
     double r0x = ax0 - S.x0, r0y = ay0 - S.y0, r0z = az0 - S.z0;
     double w0x = bx0 - S.u0x, w0y = by0 - S.u0y, w0z = bz0 - S.u0z;
     double w1x = bx1 - S.u1x, w1y = by1 - S.u1y, w1z = bz1 - S.u1z;
@@ -79,10 +81,12 @@ __global__ __launch_bounds__(kBlock) void k_flag(
         }
       }
     }
+    S = N;
   }
 }
 
-// Bitonic sort of up to `cap` 64-bit keys with one block (global memory).
+// Bitonic sort of p2 (a power of two) 64-bit keys with one block; `key` may
+// point to LDS or to global memory.
 __device__ void block_bitonic(int64_t* key, int p2) {
   for (int k = 2; k <= p2; k <<= 1) {
     for (int jx = k >> 1; jx > 0; jx >>= 1) {
@@ -108,24 +112,39 @@ __device__ int next_pow2(int v) {
   return p;
 }
 
-__global__ __launch_bounds__(1024) void k_sort_pairs(int32_t* __restrict__ pairs,
-                                                     int64_t* __restrict__ keys, int32_t cap,
-                                                     const int32_t* __restrict__ counter) {
-  int np = min(*counter, cap);
-  if (np <= 1) return;
-  int p2 = next_pow2(np);
-  for (int q = threadIdx.x; q < p2; q += blockDim.x)
-    keys[q] = q < np ? (((int64_t)pairs[2 * q]) << 32) | (uint32_t)pairs[2 * q + 1] : INT64_MAX;
+// Ordered compaction over q in [0, m): emit(position, q) for every q with pred(q),
+// positions in increasing q.  Each thread scans a contiguous chunk; chunk counts
+// are prefix-summed in LDS (Hillis-Steele).  Returns the total (block-uniform).
+template <class Pred, class Emit>
+__device__ int block_compact(int m, Pred pred, Emit emit, int* scan) {
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int per = (m + T - 1) / T;
+  const int b = min(m, tid * per), e = min(m, b + per);
+  int c = 0;
+  for (int q = b; q < e; ++q) c += pred(q) ? 1 : 0;
+  scan[tid] = c;
   __syncthreads();
-  block_bitonic(keys, p2);
-  for (int q = threadIdx.x; q < np; q += blockDim.x) {
-    pairs[2 * q] = (int32_t)(keys[q] >> 32);
-    pairs[2 * q + 1] = (int32_t)(keys[q] & 0xffffffff);
+  for (int off = 1; off < T; off <<= 1) {
+    int v = tid >= off ? scan[tid - off] : 0;
+    __syncthreads();
+    scan[tid] += v;
+    __syncthreads();
   }
+  int pos = scan[tid] - c;
+  for (int q = b; q < e; ++q)
+    if (pred(q)) emit(pos++, q);
+  int total = scan[T - 1];
+  __syncthreads();
+  return total;
 }
 
-// ------------------------------------------------------------------ plan
-__device__ int uf_find(int32_t* par, int a) {
+__device__ __forceinline__ int key_hi(int64_t k) { return (int)(k >> 32); }
+__device__ __forceinline__ int key_lo(int64_t k) { return (int)(k & 0xffffffff); }
+__device__ __forceinline__ int64_t make_key(int a, int b) {
+  return (((int64_t)a) << 32) | (uint32_t)b;
+}
+
+__device__ int uf_find(const int32_t* par, int a) {
   while (par[a] != a) a = par[a];
   return a;
 }
@@ -136,7 +155,9 @@ __device__ int index_in(const int32_t* v, int m, int b) {
   return -1;
 }
 
-__device__ void insert_sorted(int32_t* v, int& m, int b) {
+__device__ bool insert_sorted(int32_t* v, int& m, int cap, int b) {
+  if (index_in(v, m, b) >= 0) return true;
+  if (m >= cap) return false;
   int k = m;
   while (k > 0 && v[k - 1] > b) {
     v[k] = v[k - 1];
@@ -144,189 +165,209 @@ __device__ void insert_sorted(int32_t* v, int& m, int b) {
   }
   v[k] = b;
   ++m;
+  return true;
 }
 
-// uf: [2*nb]; par = uf[0..nb) (self at rest), flag = uf[nb..2nb) (0 at rest).
-// keys: scratch of cap int64 (the small-pair list, sorted by (j, i)).
-__global__ __launch_bounds__(1024) void k_plan(int nb, const int32_t* __restrict__ pairs,
-                                               int32_t cap, int64_t* __restrict__ keys,
-                                               int32_t* __restrict__ uf,
-                                               Subsystem* __restrict__ subs, int32_t cap_subs,
-                                               DevScalars* __restrict__ dsc) {
+constexpr int kPlanThreads = 1024;
+constexpr int kPlanLds = 2048;   // pairs handled in LDS; larger lists use global scratch
+
+// Sort of the flagged list by (i, j) and the subsystem plan, in one block.
+//   - big-big pairs join big bodies (union-find, root = smallest index); every
+//     component of two or more bodies is one subsystem (all members kept);
+//   - each flagged massless body j is one subsystem: copies of the components
+//     of the big bodies flagged with j, plus j (only j kept).
+// gkeys: [2*cap] int64 global scratch; gidx: [2*cap] int32 global scratch.
+// uf: [2*nb] with par[b] = b and inbig[b] = 0 at rest (restored on exit).
+__global__ __launch_bounds__(kPlanThreads) void k_plan(
+    int nb, int32_t* __restrict__ pairs, int32_t cap, int64_t* __restrict__ gkeys,
+    int32_t* __restrict__ gidx, int32_t* __restrict__ uf, Subsystem* __restrict__ subs,
+    int32_t cap_subs, DevScalars* __restrict__ dsc, int sort_only) {
+  __shared__ int64_t lk[kPlanLds];
+  __shared__ int64_t ls[kPlanLds];
+  __shared__ int32_t lbb[kPlanLds];
+  __shared__ int32_t lgs[kPlanLds];
+  __shared__ int scan[kPlanThreads];
+  __shared__ int s_nbig_sub;
   const int np = min(dsc->n_pairs, cap);
   if (np == 0) return;
-  // small-body pairs keyed by (j, i)
-  __shared__ int nsmall;
-  if (threadIdx.x == 0) {
-    int c = 0;
-    for (int q = 0; q < np; ++q)
-      if (pairs[2 * q + 1] >= nb) keys[c++] = (((int64_t)pairs[2 * q + 1]) << 32) | (uint32_t)pairs[2 * q];
-    nsmall = c;
-  }
+  const bool small_list = np <= kPlanLds;
+  int64_t* K = small_list ? lk : gkeys;
+  int64_t* S = small_list ? ls : gkeys + cap;
+  int32_t* BB = small_list ? lbb : gidx;
+  int32_t* GS = small_list ? lgs : gidx + cap;
+  const int tid = threadIdx.x, T = blockDim.x;
+  // 1. sort by (i, j)
+  int p2 = next_pow2(np);
+  for (int q = tid; q < p2; q += T)
+    K[q] = q < np ? make_key(pairs[2 * q], pairs[2 * q + 1]) : INT64_MAX;
   __syncthreads();
-  int ns = nsmall;
-  if (ns > 1) {
-    int p2 = next_pow2(ns);
-    for (int q = ns + threadIdx.x; q < p2; q += blockDim.x) keys[q] = INT64_MAX;
-    __syncthreads();
-    block_bitonic(keys, p2);
+  if (np > 1) block_bitonic(K, p2);
+  for (int q = tid; q < np; q += T) {
+    pairs[2 * q] = key_hi(K[q]);
+    pairs[2 * q + 1] = key_lo(K[q]);
   }
-  if (threadIdx.x != 0) return;
+  if (sort_only) return;
+  // 2. big-big pairs (in (i, j) order) and massless pairs keyed (j, i)
+  const int nbb = block_compact(
+      np, [&](int q) { return key_lo(K[q]) < nb; }, [&](int pos, int q) { BB[pos] = q; }, scan);
+  const int ns = block_compact(
+      np, [&](int q) { return key_lo(K[q]) >= nb; },
+      [&](int pos, int q) { S[pos] = make_key(key_lo(K[q]), key_hi(K[q])); }, scan);
+  int p2s = next_pow2(ns > 0 ? ns : 1);
+  for (int q = ns + tid; q < p2s; q += T) S[q] = INT64_MAX;
+  __syncthreads();
+  if (ns > 1) block_bitonic(S, p2s);
+  // 3. one group per flagged massless body
+  const int ng = block_compact(
+      ns, [&](int q) { return q == 0 || key_hi(S[q]) != key_hi(S[q - 1]); },
+      [&](int pos, int q) { GS[pos] = q; }, scan);
   int32_t* par = uf;
   int32_t* inbig = uf + nb;
-  // union of big-big pairs (root = smallest index)
-  int nbb = 0;
-  for (int q = 0; q < np; ++q) {
-    int i = pairs[2 * q], j = pairs[2 * q + 1];
-    if (j >= nb) continue;
-    ++nbb;
-    int ri = uf_find(par, i), rj = uf_find(par, j);
-    if (ri != rj) {
-      if (ri < rj) par[rj] = ri;
-      else par[ri] = rj;
-    }
-    inbig[i] = 1;
-    inbig[j] = 1;
-  }
-  int nsub = 0;
-  // big components, ordered by their smallest member: walk the pair list's
-  // bodies in ascending order (a body of a big-big pair is its own or a
-  // later root's member)
-  for (int q = 0; q < np && nbb > 0; ++q) {
-    int i = pairs[2 * q], j = pairs[2 * q + 1];
-    if (j >= nb) continue;
-    int r = uf_find(par, i);
-    if (inbig[r] != 1) continue;  // component already emitted (marked 2)
-    Subsystem S;
-    S.m = 0;
-    S.keep_from = 0;
-    S.np = 0;
-    S.pad = 0;
-    bool over = false;
-    for (int q2 = 0; q2 < np; ++q2) {
-      int a = pairs[2 * q2], b = pairs[2 * q2 + 1];
-      if (b >= nb || uf_find(par, a) != r) continue;
-      if (index_in(S.mem, S.m, a) < 0) {
-        if (S.m >= kBsMaxMembers) { over = true; break; }
-        insert_sorted(S.mem, S.m, a);
+  // 4. components of the big-big graph and their subsystems (one thread; the
+  //    big-big list is short)
+  if (tid == 0) {
+    for (int b = 0; b < nbb; ++b) {
+      int64_t k = K[BB[b]];
+      int i = key_hi(k), j = key_lo(k);
+      int ri = uf_find(par, i), rj = uf_find(par, j);
+      if (ri != rj) {
+        if (ri < rj) par[rj] = ri;
+        else par[ri] = rj;
       }
-      if (index_in(S.mem, S.m, b) < 0) {
-        if (S.m >= kBsMaxMembers) { over = true; break; }
-        insert_sorted(S.mem, S.m, b);
+      inbig[i] = 1;
+      inbig[j] = 1;
+    }
+    int nsub = 0;
+    for (int b = 0; b < nbb; ++b) {
+      int i = key_hi(K[BB[b]]);
+      int r = uf_find(par, i);
+      if (inbig[r] != 1) continue;  // component already emitted (root marked 2)
+      Subsystem sub;
+      sub.m = 0;
+      sub.keep_from = 0;
+      sub.np = 0;
+      sub.pad = 0;
+      bool ok = true;
+      for (int c = 0; c < nbb && ok; ++c) {
+        int64_t k = K[BB[c]];
+        if (uf_find(par, key_hi(k)) != r) continue;
+        ok = insert_sorted(sub.mem, sub.m, kBsMaxMembers, key_hi(k)) &&
+             insert_sorted(sub.mem, sub.m, kBsMaxMembers, key_lo(k));
       }
+      for (int c = 0; c < nbb && ok; ++c) {
+        int64_t k = K[BB[c]];
+        if (uf_find(par, key_hi(k)) != r) continue;
+        if (sub.np >= kBsMaxPairs) { ok = false; break; }
+        sub.pl[sub.np][0] = index_in(sub.mem, sub.m, key_hi(k));
+        sub.pl[sub.np][1] = index_in(sub.mem, sub.m, key_lo(k));
+        ++sub.np;
+      }
+      inbig[r] = 2;
+      if (!ok || nsub >= cap_subs) {
+        atomicOr(&dsc->err, MXE_SUBSYS);
+        continue;
+      }
+      subs[nsub++] = sub;
     }
-    for (int q2 = 0; q2 < np && !over; ++q2) {
-      int a = pairs[2 * q2], b = pairs[2 * q2 + 1];
-      if (b >= nb || uf_find(par, a) != r) continue;
-      if (S.np >= kBsMaxPairs) { over = true; break; }
-      S.pl[S.np][0] = index_in(S.mem, S.m, a);
-      S.pl[S.np][1] = index_in(S.mem, S.m, b);
-      ++S.np;
-    }
-    inbig[r] = 2;
-    if (over || nsub >= cap_subs) {
-      atomicOr(&dsc->err, MXE_SUBSYS);
-      continue;
-    }
-    subs[nsub++] = S;
+    s_nbig_sub = nsub;
   }
-  // one subsystem per flagged massless body, ascending
-  for (int q = 0; q < ns; ++q) {
-    int j = (int)(keys[q] >> 32);
-    if (q > 0 && (int)(keys[q - 1] >> 32) == j) continue;
-    Subsystem S;
-    S.m = 0;
-    S.np = 0;
-    S.pad = 0;
-    bool over = false;
-    for (int q2 = q; q2 < ns && (int)(keys[q2] >> 32) == j && !over; ++q2) {
-      int i = (int)(keys[q2] & 0xffffffff);
+  __syncthreads();
+  const int nbig_sub = s_nbig_sub;
+  // 5. massless subsystems, one group per thread
+  for (int g = tid; g < ng; g += T) {
+    const int q0 = GS[g];
+    const int q1 = g + 1 < ng ? GS[g + 1] : ns;
+    const int j = key_hi(S[q0]);
+    Subsystem sub;
+    sub.m = 0;
+    sub.np = 0;
+    sub.pad = 0;
+    bool ok = true;
+    for (int q = q0; q < q1 && ok; ++q) {
+      int i = key_lo(S[q]);
       if (inbig[i]) {
         int r = uf_find(par, i);
-        for (int q3 = 0; q3 < np && !over; ++q3) {
-          int a = pairs[2 * q3], b = pairs[2 * q3 + 1];
-          if (b >= nb || uf_find(par, a) != r) continue;
-          if (index_in(S.mem, S.m, a) < 0) {
-            if (S.m >= kBsMaxMembers - 1) { over = true; break; }
-            insert_sorted(S.mem, S.m, a);
-          }
-          if (index_in(S.mem, S.m, b) < 0) {
-            if (S.m >= kBsMaxMembers - 1) { over = true; break; }
-            insert_sorted(S.mem, S.m, b);
-          }
+        for (int c = 0; c < nbb && ok; ++c) {
+          int64_t k = K[BB[c]];
+          if (uf_find(par, key_hi(k)) != r) continue;
+          ok = insert_sorted(sub.mem, sub.m, kBsMaxMembers - 1, key_hi(k)) &&
+               insert_sorted(sub.mem, sub.m, kBsMaxMembers - 1, key_lo(k));
         }
-      } else if (index_in(S.mem, S.m, i) < 0) {
-        if (S.m >= kBsMaxMembers - 1) { over = true; break; }
-        insert_sorted(S.mem, S.m, i);
+      } else {
+        ok = insert_sorted(sub.mem, sub.m, kBsMaxMembers - 1, i);
       }
     }
-    int nbig_mem = S.m;
-    if (!over) {
-      S.mem[S.m++] = j;
-      S.keep_from = nbig_mem;
-      for (int q2 = 0; q2 < np && !over; ++q2) {
-        int a = pairs[2 * q2], b = pairs[2 * q2 + 1];
-        if (b < nb) {
-          int la = index_in(S.mem, nbig_mem, a), lb = index_in(S.mem, nbig_mem, b);
-          if (la >= 0 && lb >= 0) {
-            if (S.np >= kBsMaxPairs) { over = true; break; }
-            S.pl[S.np][0] = la;
-            S.pl[S.np][1] = lb;
-            ++S.np;
-          }
-        } else if (b == j) {
-          if (S.np >= kBsMaxPairs) { over = true; break; }
-          S.pl[S.np][0] = index_in(S.mem, nbig_mem, a);
-          S.pl[S.np][1] = nbig_mem;
-          ++S.np;
-        }
+    const int nbm = sub.m;
+    if (ok) {
+      sub.mem[sub.m++] = j;
+      sub.keep_from = nbm;
+      // big-big pairs among the members, then the pairs naming j, both in (i, j) order
+      for (int c = 0; c < nbb && ok; ++c) {
+        int64_t k = K[BB[c]];
+        int la = index_in(sub.mem, nbm, key_hi(k)), lb = index_in(sub.mem, nbm, key_lo(k));
+        if (la < 0 || lb < 0) continue;
+        if (sub.np >= kBsMaxPairs) { ok = false; break; }
+        sub.pl[sub.np][0] = la;
+        sub.pl[sub.np][1] = lb;
+        ++sub.np;
+      }
+      for (int q = q0; q < q1 && ok; ++q) {
+        if (sub.np >= kBsMaxPairs) { ok = false; break; }
+        sub.pl[sub.np][0] = index_in(sub.mem, nbm, key_lo(S[q]));
+        sub.pl[sub.np][1] = nbm;
+        ++sub.np;
       }
     }
-    if (over || nsub >= cap_subs) {
+    const int slot = nbig_sub + g;
+    if (!ok || slot >= cap_subs) {
       atomicOr(&dsc->err, MXE_SUBSYS);
-      continue;
+      sub.m = 0;  // an empty subsystem keeps the table dense; the integrator skips it
+      sub.np = 0;
+      sub.keep_from = 0;
     }
-    subs[nsub++] = S;
+    if (slot < cap_subs) subs[slot] = sub;
   }
-  // restore the union-find scratch
-  for (int q = 0; q < np; ++q) {
-    int i = pairs[2 * q], j = pairs[2 * q + 1];
-    par[i] = i;
-    inbig[i] = 0;
-    if (j < nb) {
-      par[j] = j;
-      inbig[j] = 0;
-    }
+  __syncthreads();
+  // 6. restore the union-find scratch
+  for (int b = tid; b < nbb; b += T) {
+    int64_t k = K[BB[b]];
+    par[key_hi(k)] = key_hi(k);
+    par[key_lo(k)] = key_lo(k);
+    inbig[key_hi(k)] = 0;
+    inbig[key_lo(k)] = 0;
   }
-  dsc->n_sub = nsub;
+  if (tid == 0) dsc->n_sub = min(nbig_sub + ng, cap_subs);
 }
 
 // ------------------------------------------------------------------ BS
-// Plain IEEE evaluation (no contraction) so that the integrator is the same
-// sequence of operations as its definition.
-#pragma clang fp contract(off)
-
 constexpr int kM = kBsMaxMembers;
 constexpr int kC = kBsColumns;
 
-__device__ double bs_k(double s2, double rc) {
-  double rc2 = rc * rc;
-  if (s2 >= rc2) return 1.0;
-  if (s2 <= 0.01 * rc2) return 0.0;
-  double s = sqrt(s2);
-  double q = (s - 0.1 * rc) / (0.9 * rc);
-  double q2 = q * q, q3 = q * q2, q4 = q2 * q2, q5 = q2 * q3;
-  return 10.0 * q3 - 15.0 * q4 + 6.0 * q5;
-}
+// 1 / ((n_k / n_{k-j})^2 - 1) for the substep counts n_k = 2 (k + 1): the
+// Aitken-Neville weights of polynomial extrapolation in (H/n)^2.
+__constant__ double kNevilleInv[kC][kC] = {
+    {0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 1.0 / 3.0, 0, 0, 0, 0, 0, 0},
+    {0, 1.0 / (9.0 / 4.0 - 1.0), 1.0 / 8.0, 0, 0, 0, 0, 0},
+    {0, 1.0 / (16.0 / 9.0 - 1.0), 1.0 / (16.0 / 4.0 - 1.0), 1.0 / 15.0, 0, 0, 0, 0},
+    {0, 1.0 / (25.0 / 16.0 - 1.0), 1.0 / (25.0 / 9.0 - 1.0), 1.0 / (25.0 / 4.0 - 1.0), 1.0 / 24.0,
+     0, 0, 0},
+    {0, 1.0 / (36.0 / 25.0 - 1.0), 1.0 / (36.0 / 16.0 - 1.0), 1.0 / (36.0 / 9.0 - 1.0),
+     1.0 / (36.0 / 4.0 - 1.0), 1.0 / 35.0, 0, 0},
+    {0, 1.0 / (49.0 / 36.0 - 1.0), 1.0 / (49.0 / 25.0 - 1.0), 1.0 / (49.0 / 16.0 - 1.0),
+     1.0 / (49.0 / 9.0 - 1.0), 1.0 / (49.0 / 4.0 - 1.0), 1.0 / 48.0, 0},
+    {0, 1.0 / (64.0 / 49.0 - 1.0), 1.0 / (64.0 / 36.0 - 1.0), 1.0 / (64.0 / 25.0 - 1.0),
+     1.0 / (64.0 / 16.0 - 1.0), 1.0 / (64.0 / 9.0 - 1.0), 1.0 / (64.0 / 4.0 - 1.0), 1.0 / 63.0}};
 
-// star (mu0) plus the complementary (1-K) part of every flagged pair
+// star (mu0) plus the complementary (1-K) part of every flagged pair; inverse
+// cubes from the corrected hardware rsqrt
 __device__ void bs_force(int m, int np, const int32_t (*pl)[2], const double* mum,
                          const double* rcm, double mu0, const double* xs, double* as) {
   for (int k = 0; k < m; ++k) {
     const double* p = xs + 3 * k;
-    double r2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
-    double r = sqrt(r2);
-    double f = -mu0 / (r2 * r);
+    double r2 = fma(p[2], p[2], fma(p[1], p[1], p[0] * p[0]));
+    double y = mxd::rsqrt_full(r2);
+    double f = -mu0 * (y * y * y);
     as[3 * k] = f * p[0];
     as[3 * k + 1] = f * p[1];
     as[3 * k + 2] = f * p[2];
@@ -336,18 +377,102 @@ __device__ void bs_force(int m, int np, const int32_t (*pl)[2], const double* mu
     double d0 = xs[3 * b] - xs[3 * a];
     double d1 = xs[3 * b + 1] - xs[3 * a + 1];
     double d2 = xs[3 * b + 2] - xs[3 * a + 2];
-    double s2 = d0 * d0 + d1 * d1 + d2 * d2;
-    double rc = rcm[a] > rcm[b] ? rcm[a] : rcm[b];
-    double w = s2 > 0.0 ? (1.0 / (s2 * sqrt(s2))) * (1.0 - bs_k(s2, rc)) : 0.0;
-    as[3 * a] += mum[b] * w * d0;
-    as[3 * a + 1] += mum[b] * w * d1;
-    as[3 * a + 2] += mum[b] * w * d2;
-    as[3 * b] -= mum[a] * w * d0;
-    as[3 * b + 1] -= mum[a] * w * d1;
-    as[3 * b + 2] -= mum[a] * w * d2;
+    double s2 = fma(d2, d2, fma(d1, d1, d0 * d0));
+    double rc = fmax(rcm[a], rcm[b]);
+    double rc2 = rc * rc;
+    double w = 0.0;
+    if (s2 < rc2 && s2 > 0.0) {
+      double y = mxd::rsqrt_full(s2);
+      double y3 = y * y * y;
+      if (s2 <= 0.01 * rc2) {
+        w = y3;
+      } else {
+        double q1 = (s2 * y - 0.1 * rc) / (0.9 * rc);
+        double q2 = q1 * q1, q3 = q1 * q2;
+        double K = q3 * fma(q1, fma(q1, 6.0, -15.0), 10.0);
+        w = y3 * (1.0 - K);
+      }
+    }
+    double wa = mum[b] * w, wb = mum[a] * w;
+    as[3 * a] = fma(wa, d0, as[3 * a]);
+    as[3 * a + 1] = fma(wa, d1, as[3 * a + 1]);
+    as[3 * a + 2] = fma(wa, d2, as[3 * a + 2]);
+    as[3 * b] = fma(-wb, d0, as[3 * b]);
+    as[3 * b + 1] = fma(-wb, d1, as[3 * b + 1]);
+    as[3 * b + 2] = fma(-wb, d2, as[3 * b + 2]);
   }
 }
 
+// One Stoermer (velocity-Verlet) sequence of ns = 2 (col + 1) substeps over H
+// from (xs, vs); end positions and velocities go to out[0..nn) and out[nn..2nn).
+__device__ void stoermer_seq(int col, double H, int m, int np, const int32_t (*pl)[2],
+                             const double* mum, const double* rcm, double mu0, const double* xs,
+                             const double* vs, double* pos, double* d, double* acc, double* out) {
+  const int nn = 3 * m;
+  const int ns = 2 * (col + 1);
+  const double dt = H / ns;
+  for (int i = 0; i < nn; ++i) pos[i] = xs[i];
+  bs_force(m, np, pl, mum, rcm, mu0, pos, acc);
+  for (int i = 0; i < nn; ++i) {
+    d[i] = dt * (vs[i] + 0.5 * dt * acc[i]);
+    pos[i] += d[i];
+  }
+  for (int k = 1; k < ns; ++k) {
+    bs_force(m, np, pl, mum, rcm, mu0, pos, acc);
+    for (int i = 0; i < nn; ++i) {
+      d[i] += dt * dt * acc[i];
+      pos[i] += d[i];
+    }
+  }
+  bs_force(m, np, pl, mum, rcm, mu0, pos, acc);
+  for (int i = 0; i < nn; ++i) {
+    out[i] = pos[i];
+    out[nn + i] = d[i] / dt + 0.5 * dt * acc[i];
+  }
+}
+
+constexpr int kRound = 4;
+
+// Rows K0..K0+3 of the Aitken-Neville table for this lane's two elements (all
+// indices compile-time, so the table stays in registers), with the per-row
+// error max(dx^2 xscal, dv^2 vscal) of the lane.
+template <int K0>
+__device__ __forceinline__ void neville_round(int lane, int nn, int m, const double (*res)[6 * kM],
+                                              const double* scal, double (&prev)[2][kC],
+                                              double (&diag)[2][kC], double (&lerr)[kRound]) {
+#pragma unroll
+  for (int kk = 0; kk < kRound; ++kk) lerr[kk] = 0.0;
+#pragma unroll
+  for (int slot = 0; slot < 2; ++slot) {
+    const int e = lane + 64 * slot;
+    if (e >= 2 * nn) continue;
+    const double sc = e < nn ? scal[e / 3] : scal[m + (e - nn) / 3];
+#pragma unroll
+    for (int kk = 0; kk < kRound; ++kk) {
+      const int k = K0 + kk;
+      double T[kC];
+      T[0] = res[k][e];
+#pragma unroll
+      for (int jx = 1; jx < kC; ++jx)
+        if (jx <= k) T[jx] = fma(T[jx - 1] - prev[slot][jx - 1], kNevilleInv[k][jx], T[jx - 1]);
+#pragma unroll
+      for (int jx = 0; jx < kC; ++jx)
+        if (jx == k) diag[slot][jx] = T[jx];
+      if (k >= 1) {
+        double ex = T[k] - T[k - 1];
+        lerr[kk] = fmax(lerr[kk], ex * ex * sc);
+      }
+#pragma unroll
+      for (int jx = 0; jx < kC; ++jx)
+        if (jx <= k) prev[slot][jx] = T[jx];
+    }
+  }
+}
+
+// Columns are evaluated in two rounds (n = 2..8, then n = 10..16, four lanes
+// each): most steps are accepted in the first round, and the table rows do not
+// depend on later rows, so the accepted column is the one a sequential
+// integrator would stop at.
 __global__ __launch_bounds__(64) void k_bs(int n, int nb, double mu0, double h, double tol,
                                            const double* __restrict__ x0s,
                                            const double* __restrict__ u0s,
@@ -359,16 +484,21 @@ __global__ __launch_bounds__(64) void k_bs(int n, int nb, double mu0, double h, 
   __shared__ Subsystem S;
   __shared__ double xs[3 * kM], vs[3 * kM], mum[kM], rcm[kM], scal[2 * kM];
   __shared__ double res[kC][6 * kM];
-  __shared__ double wk[kC][3][3 * kM];
-  __shared__ double errk[kC];
+  __shared__ double wk[kRound][3][3 * kM];
   const int lane = threadIdx.x;
   const int nsub = dsc->n_sub;
+  const double tol2 = tol * tol;
   for (int b = blockIdx.x; b < nsub; b += gridDim.x) {
     __syncthreads();
-    if (lane == 0) S = subs[b];
+    {
+      const int32_t* src = reinterpret_cast<const int32_t*>(subs + b);
+      int32_t* dst = reinterpret_cast<int32_t*>(&S);
+      for (int i = lane; i < (int)(sizeof(Subsystem) / 4); i += 64) dst[i] = src[i];
+    }
     __syncthreads();
     const int m = S.m, np = S.np;
     const int nn = 3 * m;
+    if (m == 0) continue;  // a subsystem dropped for capacity (error already latched)
     for (int e = lane; e < nn; e += 64) {
       int k = e / 3, c = e - 3 * (e / 3);
       int body = S.mem[k];
@@ -393,78 +523,37 @@ __global__ __launch_bounds__(64) void k_bs(int n, int nb, double mu0, double h, 
         scal[k] = 1.0 / (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
         scal[m + k] = 1.0 / (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
       }
-      // the Stoermer (velocity-Verlet) sequences n = 2, 4, ..., 16 in lanes 0..7
-      if (lane < kC) {
-        const int ns = 2 * (lane + 1);
-        const double dt = H / ns;
-        double* pos = wk[lane][0];
-        double* d = wk[lane][1];
-        double* acc = wk[lane][2];
-        for (int i = 0; i < nn; ++i) pos[i] = xs[i];
-        bs_force(m, np, S.pl, mum, rcm, mu0, pos, acc);
-        for (int i = 0; i < nn; ++i) {
-          d[i] = dt * (vs[i] + 0.5 * dt * acc[i]);
-          pos[i] += d[i];
-        }
-        for (int k = 1; k < ns; ++k) {
-          bs_force(m, np, S.pl, mum, rcm, mu0, pos, acc);
-          for (int i = 0; i < nn; ++i) {
-            d[i] += dt * dt * acc[i];
-            pos[i] += d[i];
-          }
-        }
-        bs_force(m, np, S.pl, mum, rcm, mu0, pos, acc);
-        for (int i = 0; i < nn; ++i) {
-          res[lane][i] = pos[i];
-          res[lane][nn + i] = d[i] / dt + 0.5 * dt * acc[i];
-        }
-      }
-      if (lane < kC) errk[lane] = 0.0;
-      __syncthreads();
-      // Aitken-Neville extrapolation in (H/n)^2, one table per element, and the
-      // per-column error max(dx^2 xscal, dv^2 vscal)
-      double diag[2][kC];
-      double lerr[kC];
-      for (int k = 0; k < kC; ++k) lerr[k] = 0.0;
-      for (int slot = 0; slot < 2; ++slot) {
-        int e = lane + 64 * slot;
-        for (int k = 0; k < kC; ++k) diag[slot][k] = 0.0;
-        if (e >= 2 * nn) continue;
-        double sc = e < nn ? scal[e / 3] : scal[m + (e - nn) / 3];
-        double T[kC], P[kC];
-        for (int k = 0; k < kC; ++k) {
-          T[0] = res[k][e];
-          for (int jx = 1; jx <= k; ++jx) {
-            double ratio = (double)(2 * (k + 1)) / (double)(2 * (k - jx + 1));
-            double den = ratio * ratio - 1.0;
-            T[jx] = T[jx - 1] + (T[jx - 1] - P[jx - 1]) / den;
-          }
-          diag[slot][k] = T[k];
-          if (k >= 1) {
-            double ex = T[k] - T[k - 1];
-            double v = ex * ex * sc;
-            if (v > lerr[k]) lerr[k] = v;
-          }
-          for (int jx = 0; jx <= k; ++jx) P[jx] = T[jx];
-        }
-      }
-      // wave-wide maximum of each column's error
-      for (int k = 1; k < kC; ++k) {
-        double v = lerr[k];
-        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-        lerr[k] = v;
-      }
+      // per element (two per lane): the previous table row and the diagonal
+      double prev[2][kC], diag[2][kC];
       int accepted = -1;
-      for (int k = 1; k < kC; ++k)
-        if (accepted < 0 && lerr[k] <= tol * tol) accepted = k;
-      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kC / kRound; ++r) {
+        if (accepted < 0) {
+          const int k0 = r * kRound;
+          if (lane < kRound)
+            stoermer_seq(k0 + lane, H, m, np, S.pl, mum, rcm, mu0, xs, vs, wk[lane][0],
+                         wk[lane][1], wk[lane][2], res[k0 + lane]);
+          __syncthreads();
+          double lerr[kRound];
+          if (r == 0) neville_round<0>(lane, nn, m, res, scal, prev, diag, lerr);
+          else neville_round<kRound>(lane, nn, m, res, scal, prev, diag, lerr);
+#pragma unroll
+          for (int kk = 0; kk < kRound; ++kk) {
+            double v = lerr[kk];
+            for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+            const int k = k0 + kk;
+            if (accepted < 0 && k >= 1 && v <= tol2) accepted = k;
+          }
+          __syncthreads();
+        }
+      }
       if (accepted >= 0) {
         for (int slot = 0; slot < 2; ++slot) {
-          int e = lane + 64 * slot;
+          const int e = lane + 64 * slot;
           if (e >= 2 * nn) continue;
-          double val = diag[slot][0];
+          double val = diag[slot][1];
 #pragma unroll
-          for (int k = 1; k < kC; ++k)
+          for (int k = 2; k < kC; ++k)
             if (k == accepted) val = diag[slot][k];
           if (e < nn) xs[e] = val;
           else vs[e - nn] = val;
@@ -494,17 +583,26 @@ __global__ __launch_bounds__(64) void k_bs(int n, int nb, double mu0, double h, 
     }
   }
 }
-#pragma clang fp contract(on)
 
 }  // namespace
 
 namespace mxk {
 
-int force_split(int n, int nb);
+// Source split of the flag kernel: 256 targets per block, enough blocks for
+// about four waves per SIMD, at least 32 sources per split.
+int flag_split(int n, int nb) {
+  int tiles = (n + kBlock - 1) / kBlock;
+  int split = (1024 + tiles - 1) / tiles;
+  int maxs = nb / 32;
+  if (split > maxs) split = maxs;
+  if (split > 64) split = 64;
+  if (split < 1) split = 1;
+  return split;
+}
 
 hipError_t launch_flag(mx_system* s) {
   int tiles = (s->n + kBlock - 1) / kBlock;
-  int split = force_split(s->n, s->nb);
+  int split = flag_split(s->n, s->nb);
   if (s->nb > 0)
     hipLaunchKernelGGL(k_flag, dim3(tiles * split), dim3(kBlock), 0, s->stream, s->n, s->nb, split,
                        s->p.dt, s->x0, s->u0, s->x, s->u, s->fpack, s->pairs, s->cap_pairs,
@@ -514,10 +612,9 @@ hipError_t launch_flag(mx_system* s) {
 
 hipError_t launch_bs(mx_system* s) {
   if (s->nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sort_pairs, dim3(1), dim3(1024), 0, s->stream, s->pairs,
-                     (int64_t*)s->pairs_tmp, s->cap_pairs, &s->dsc->n_pairs);
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s->stream, s->nb, s->pairs, s->cap_pairs,
-                     (int64_t*)s->pairs_tmp, s->uf, s->subs, s->cap_subs, s->dsc);
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s->stream, s->nb, s->pairs,
+                     s->cap_pairs, (int64_t*)s->pairs_tmp, s->plan_idx, s->uf, s->subs,
+                     s->cap_subs, s->dsc, 0);
   hipLaunchKernelGGL(k_bs, dim3(512), dim3(64), 0, s->stream, s->n, s->nb, s->mu0, s->p.dt,
                      s->p.bs_tol, s->x0, s->u0, s->x, s->u, s->mu, s->rcrit, s->subs, s->dsc);
   return hipGetLastError();
@@ -542,20 +639,19 @@ __global__ void k_fpack_plain(int n, int nb, const double* __restrict__ rcrit,
 
 hipError_t flag_pairs(int n, int nb, const double* rcrit, const double* x0, const double* u0,
                       const double* x1, const double* u1, double h, int32_t* pairs,
-                      int32_t* pairs_tmp, int32_t cap, int32_t* counter, hipStream_t st) {
+                      int32_t* pairs_tmp, int32_t cap, DevScalars* dsc, hipStream_t st) {
   if (nb == 0) return hipSuccess;
   FlagSource* fp = nullptr;
   hipError_t e = hipMalloc((void**)&fp, sizeof(FlagSource) * nb);
   if (e != hipSuccess) return e;
-  int32_t* err = counter + 1;
   hipLaunchKernelGGL(k_fpack_plain, dim3((nb + 255) / 256), dim3(256), 0, st, n, nb, rcrit, x0, u0,
                      x1, u1, fp);
   int tiles = (n + kBlock - 1) / kBlock;
-  int split = force_split(n, nb);
+  int split = flag_split(n, nb);
   hipLaunchKernelGGL(k_flag, dim3(tiles * split), dim3(kBlock), 0, st, n, nb, split, h, x0, u0, x1,
-                     u1, fp, pairs, cap, counter, err);
-  hipLaunchKernelGGL(k_sort_pairs, dim3(1), dim3(1024), 0, st, pairs, (int64_t*)pairs_tmp, cap,
-                     counter);
+                     u1, fp, pairs, cap, &dsc->n_pairs, &dsc->err);
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, st, nb, pairs, cap,
+                     (int64_t*)pairs_tmp, nullptr, nullptr, nullptr, 0, dsc, 1);
   e = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(st);
   (void)hipFree(fp);

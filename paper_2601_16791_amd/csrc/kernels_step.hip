@@ -167,27 +167,62 @@ __global__ __launch_bounds__(kBlock) void k_jump_pack(int n, int nb, double mu0,
 // Each lane holds one target t; the wave walks sources [s0, s1) of its split
 // with scalar loads.  Fast branch (s2 >= rc2, K = 1): mu * y^3 with y the
 // corrected hardware rsqrt.  Changeover branch (rare, divergent): the quintic K.
-// With split > 1 the per-split partial sums go to `part`; the last block of a
-// target tile (atomic ticket) adds the partials in split order, so the result
-// does not depend on block scheduling.
+// With split > 1 the per-split partial sums go to `part` and a second kernel adds
+// them in split order, so the result does not depend on block scheduling and no
+// device-wide fence is needed inside the force kernel.
+// one interaction: K = 1 weight mu y^3, y the hardware rsqrt with the
+// third-order correction y0 (1 + 3e/2 + 15e^2/8), e = 1 - s2 y0^2
+__device__ __forceinline__ double fast_weight(double mu, double s2) {
+  double y0 = __builtin_amdgcn_rsq(s2);
+  double y2 = y0 * y0;
+  double e = fma(-s2, y2, 1.0);
+  double c = fma(e, fma(e, 1.875, 1.5), 1.0);
+  return (mu * y0) * y2 * c;
+}
+
+// Sources [s0, s1) in ascending order, two per iteration (independent chains
+// for the scheduler), the next two records requested before the current ones
+// are used.  The changeover branch is taken only when either pair is inside
+// its changeover radius.
 __device__ __forceinline__ void force_sum(const KickSource* __restrict__ src, int s0, int s1,
                                           double xt, double yt, double zt, double rc2t,
                                           double rct, double& ax, double& ay, double& az) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-#pragma unroll 4
-  for (int s = s0; s < s1; ++s) {
-    const KickSource S = src[s];
-    double dx = S.x - xt, dy = S.y - yt, dz = S.z - zt;
-    double s2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    double rc2 = fmax(S.rc2, rc2t);
-    double y0 = __builtin_amdgcn_rsq(s2);
-    double y2 = y0 * y0;
-    double e = fma(-s2, y2, 1.0);
-    double c = fma(e, fma(e, 1.875, 1.5), 1.0);
-    double w = (S.mu * y0) * y2 * c;
-    if (__builtin_expect(s2 < rc2, 0)) {
-      w = S.mu * mxd::changeover_weight_slow(s2, fmax(S.rc, rct), rc2);
+  int s = s0;
+  if (s + 1 < s1) {
+    KickSource A = src[s], B = src[s + 1];
+    for (; s + 1 < s1; s += 2) {
+      const int na = s + 2 < s1 ? s + 2 : s;
+      const int nb2 = s + 3 < s1 ? s + 3 : s;
+      const KickSource NA = src[na], NB = src[nb2];
+      double dxa = A.x - xt, dya = A.y - yt, dza = A.z - zt;
+      double dxb = B.x - xt, dyb = B.y - yt, dzb = B.z - zt;
+      double s2a = fma(dza, dza, fma(dya, dya, dxa * dxa));
+      double s2b = fma(dzb, dzb, fma(dyb, dyb, dxb * dxb));
+      double rc2a = fmax(A.rc2, rc2t), rc2b = fmax(B.rc2, rc2t);
+      double wa = fast_weight(A.mu, s2a);
+      double wb = fast_weight(B.mu, s2b);
+      if (__builtin_expect((s2a < rc2a) | (s2b < rc2b), 0)) {
+        if (s2a < rc2a) wa = A.mu * mxd::changeover_weight_slow(s2a, fmax(A.rc, rct), rc2a);
+        if (s2b < rc2b) wb = B.mu * mxd::changeover_weight_slow(s2b, fmax(B.rc, rct), rc2b);
+      }
+      a0 = fma(wa, dxa, a0);
+      a1 = fma(wa, dya, a1);
+      a2 = fma(wa, dza, a2);
+      a0 = fma(wb, dxb, a0);
+      a1 = fma(wb, dyb, a1);
+      a2 = fma(wb, dzb, a2);
+      A = NA;
+      B = NB;
     }
+  }
+  if (s < s1) {
+    const KickSource A = src[s];
+    double dx = A.x - xt, dy = A.y - yt, dz = A.z - zt;
+    double s2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    double rc2 = fmax(A.rc2, rc2t);
+    double w = fast_weight(A.mu, s2);
+    if (s2 < rc2) w = A.mu * mxd::changeover_weight_slow(s2, fmax(A.rc, rct), rc2);
     a0 = fma(w, dx, a0);
     a1 = fma(w, dy, a1);
     a2 = fma(w, dz, a2);
@@ -220,15 +255,14 @@ __device__ __forceinline__ void finish_body(int t, int n, int nb, double mu0, do
   if (!isfinite(chk)) atomicOr(err, MXE_NONFINITE);
 }
 
+// Wide layout (few massive bodies): 256 targets per block, every wave walks
+// all sources, and the body is finished in the same kernel.
 __global__ __launch_bounds__(kBlock) void k_force_kick(
-    int n, int nb, int split, double mu0, double hh, DragConst dc, int gas_on, int kick,
+    int n, int nb, double mu0, double hh, DragConst dc, int gas_on, int kick,
     const double* __restrict__ x, double* __restrict__ u, double* __restrict__ ag,
     const KickSource* __restrict__ kpack, const double* __restrict__ r_p,
-    const double* __restrict__ rho_p, double* __restrict__ part, int32_t* __restrict__ tile_cnt,
-    DevScalars* __restrict__ dsc) {
-  const int tile = blockIdx.x / split;
-  const int sp = blockIdx.x - tile * split;
-  const int t = tile * kBlock + threadIdx.x;
+    const double* __restrict__ rho_p, DevScalars* __restrict__ dsc) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
   const int tt = t < n ? t : n - 1;
   if (kick && blockIdx.x == 0 && threadIdx.x == 0) dsc->step += 1;
   const double xt = x[tt], yt = x[n + tt], zt = x[2 * n + tt];
@@ -237,43 +271,73 @@ __global__ __launch_bounds__(kBlock) void k_force_kick(
     rct = kpack[tt].rc;
     rc2t = rct * rct;
   }
+  double ax, ay, az;
+  force_sum(kpack, 0, nb, xt, yt, zt, rc2t, rct, ax, ay, az);
+  double P[3] = {dsc->P[0], dsc->P[1], dsc->P[2]};
+  if (t < n) finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, ax, ay, az, x, u, ag, r_p, rho_p, P, &dsc->err);
+}
+
+// Split layout (many massive bodies): 64 targets per block; the block's source
+// chunk is divided among its four waves and their sums are added in wave order
+// through LDS; the chunk sums of the `split` blocks of a tile go to `part`.
+__global__ __launch_bounds__(kBlock) void k_force_split(
+    int n, int nb, int split, const double* __restrict__ x,
+    const KickSource* __restrict__ kpack, double* __restrict__ part) {
+  __shared__ double red[3][4][64];
+  const int tile = blockIdx.x / split;
+  const int sp = blockIdx.x - tile * split;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int t = tile * 64 + lane;
+  const int tt = t < n ? t : n - 1;
+  const double xt = x[tt], yt = x[n + tt], zt = x[2 * n + tt];
+  double rct = 0.0, rc2t = 0.0;
+  if (tt < nb) {
+    rct = kpack[tt].rc;
+    rc2t = rct * rct;
+  }
   const int per = (nb + split - 1) / split;
-  const int s0 = sp * per;
-  const int s1 = min(nb, s0 + per);
+  const int c0 = sp * per;
+  const int c1 = min(nb, c0 + per);
+  const int q = (c1 - c0 + 3) / 4;
+  const int s0 = min(c1, c0 + wv * q);
+  const int s1 = min(c1, s0 + q);
   double ax, ay, az;
   force_sum(kpack, s0, s1, xt, yt, zt, rc2t, rct, ax, ay, az);
-  double P[3] = {dsc->P[0], dsc->P[1], dsc->P[2]};
-  if (split == 1) {
-    if (t < n) finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, ax, ay, az, x, u, ag, r_p, rho_p, P, &dsc->err);
-  } else {
-    if (t < n) {
-      size_t base = (size_t)sp * 3 * n;
-      part[base + t] = ax;
-      part[base + n + t] = ay;
-      part[base + 2 * n + t] = az;
-    }
-    __threadfence();
-    __shared__ int last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int ticket = atomicAdd(&tile_cnt[tile], 1);
-      last = (ticket == split - 1);
-      if (last) tile_cnt[tile] = 0;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (t < n) {
-      double bx = 0.0, by = 0.0, bz = 0.0;
-      for (int q = 0; q < split; ++q) {
-        size_t base = (size_t)q * 3 * n;
-        bx += __builtin_nontemporal_load(&part[base + t]);
-        by += __builtin_nontemporal_load(&part[base + n + t]);
-        bz += __builtin_nontemporal_load(&part[base + 2 * n + t]);
-      }
-      finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, bx, by, bz, x, u, ag, r_p, rho_p, P, &dsc->err);
-    }
+  red[0][wv][lane] = ax;
+  red[1][wv][lane] = ay;
+  red[2][wv][lane] = az;
+  __syncthreads();
+  if (wv == 0 && t < n) {
+    double bx = ((red[0][0][lane] + red[0][1][lane]) + red[0][2][lane]) + red[0][3][lane];
+    double by = ((red[1][0][lane] + red[1][1][lane]) + red[1][2][lane]) + red[1][3][lane];
+    double bz = ((red[2][0][lane] + red[2][1][lane]) + red[2][2][lane]) + red[2][3][lane];
+    size_t base = (size_t)sp * 3 * n;
+    part[base + t] = bx;
+    part[base + n + t] = by;
+    part[base + 2 * n + t] = bz;
   }
+}
+
+// sum of the split partials in split order, then drag and the half kick
+__global__ __launch_bounds__(kBlock) void k_force_finish(
+    int n, int nb, int split, double mu0, double hh, DragConst dc, int gas_on, int kick,
+    const double* __restrict__ x, double* __restrict__ u, double* __restrict__ ag,
+    const double* __restrict__ r_p, const double* __restrict__ rho_p,
+    const double* __restrict__ part, DevScalars* __restrict__ dsc) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (kick && blockIdx.x == 0 && threadIdx.x == 0) dsc->step += 1;
+  if (t >= n) return;
+  double bx = 0.0, by = 0.0, bz = 0.0;
+#pragma unroll 8
+  for (int q = 0; q < split; ++q) {
+    size_t base = (size_t)q * 3 * n;
+    bx += part[base + t];
+    by += part[base + n + t];
+    bz += part[base + 2 * n + t];
+  }
+  double P[3] = {dsc->P[0], dsc->P[1], dsc->P[2]};
+  finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, bx, by, bz, x, u, ag, r_p, rho_p, P, &dsc->err);
 }
 
 // stateless gravity (single-kernel entry): packs then sums, no kick
@@ -351,10 +415,15 @@ int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
 namespace mxk {
 
+// Source split of the force and flag kernels: with at least 128 massive bodies
+// the force runs in the split layout (64 targets x 4 waves per block) with
+// enough blocks to give every SIMD about four waves (256 CUs x 4 SIMDs) and at
+// least 32 sources per wave; 1 selects the wide layout.
 int force_split(int n, int nb) {
-  int tiles = blocks_for(n);
-  int split = (512 + tiles - 1) / tiles;
-  int maxs = nb / 32;
+  if (nb < 128) return 1;
+  int tiles = (n + 63) / 64;
+  int split = (1024 + tiles - 1) / tiles;
+  int maxs = nb / 128;
   if (split > maxs) split = maxs;
   if (split > 64) split = 64;
   if (split < 1) split = 1;
@@ -390,10 +459,19 @@ hipError_t launch_pack_only(mx_system* s) {
 
 hipError_t launch_force_kick(mx_system* s, int kick) {
   DragConst dc = make_drag_const(s->p);
-  int grid = blocks_for(s->n) * s->split;
-  hipLaunchKernelGGL(k_force_kick, dim3(grid), dim3(kBlock), 0, s->stream, s->n, s->nb, s->split,
-                     s->mu0, 0.5 * s->p.dt, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->kpack,
-                     s->r_p, s->rho_p, s->part, s->tile_cnt, s->dsc);
+  const double hh = 0.5 * s->p.dt;
+  if (s->split <= 1) {
+    hipLaunchKernelGGL(k_force_kick, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n,
+                       s->nb, s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->kpack,
+                       s->r_p, s->rho_p, s->dsc);
+  } else {
+    int tiles = (s->n + 63) / 64;
+    hipLaunchKernelGGL(k_force_split, dim3(tiles * s->split), dim3(kBlock), 0, s->stream, s->n,
+                       s->nb, s->split, s->x, s->kpack, s->part);
+    hipLaunchKernelGGL(k_force_finish, dim3(tiles), dim3(64), 0, s->stream, s->n, s->nb, s->split,
+                       s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->r_p, s->rho_p,
+                       s->part, s->dsc);
+  }
   return hipGetLastError();
 }
 

@@ -61,8 +61,8 @@ void free_system(mx_system* s) {
   if (!s) return;
   if (s->graph_ok) (void)hipGraphExecDestroy(s->graph);
   void* ptrs[] = {s->x, s->u, s->ag, s->x0, s->u0, s->mu, s->rcrit, s->mu_init, s->rcrit_init,
-                  s->growth, s->r_p, s->rho_p, s->kpack, s->fpack, s->part, s->tile_cnt,
-                  s->pairs, s->pairs_tmp, s->subs, s->uf, s->dsc, s->red};
+                  s->growth, s->r_p, s->rho_p, s->kpack, s->fpack, s->part,
+                  s->pairs, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -152,7 +152,6 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   s->cap_subs = 4096;
   s->red_blocks = 256;
   s->has_growth = growth != nullptr && nb > 0;
-  int tiles = (s->n + 255) / 256;
   hipError_t e = hipSuccess;
 #define ALLOC(ptr, cnt)                                          \
   if (e == hipSuccess) e = dalloc(&(ptr), (size_t)(cnt));
@@ -161,8 +160,8 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   ALLOC(s->growth, 3 * (size_t)nb) ALLOC(s->r_p, s->ns) ALLOC(s->rho_p, s->ns)
   ALLOC(s->kpack, nb) ALLOC(s->fpack, nb)
   ALLOC(s->part, s->split > 1 ? (size_t)s->split * n3 : 1)
-  ALLOC(s->tile_cnt, tiles)
-  ALLOC(s->pairs, 2 * (size_t)s->cap_pairs) ALLOC(s->pairs_tmp, 2 * (size_t)s->cap_pairs)
+  ALLOC(s->pairs, 2 * (size_t)s->cap_pairs) ALLOC(s->pairs_tmp, 4 * (size_t)s->cap_pairs)
+  ALLOC(s->plan_idx, 2 * (size_t)s->cap_pairs)
   ALLOC(s->subs, s->cap_subs) ALLOC(s->uf, 2 * (size_t)nb) ALLOC(s->dsc, 1) ALLOC(s->red, s->red_blocks)
 #undef ALLOC
   if (e != hipSuccess) {
@@ -182,7 +181,6 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
     }                                                        \
   } while (0)
   STEP(dalloc(&vh_tmp, n3), "alloc v_h");
-  STEP(hipMemsetAsync(s->tile_cnt, 0, sizeof(int32_t) * tiles, sm), "memset");
   STEP(hipMemsetAsync(s->dsc, 0, sizeof(DevScalars), sm), "memset");
   STEP(hipMemsetAsync(s->ag, 0, sizeof(double) * n3, sm), "memset");
   STEP(copy_in(s->x, x_h, sizeof(double) * n3, is_device_ptr, sm), "copy x");
@@ -448,19 +446,19 @@ mx_status mx_flag_pairs(int32_t n, int32_t n_big, const double* rcrit, const dou
       !pairs || (n_big > 0 && !rcrit) || (cap & (cap - 1)) != 0)
     return fail(MX_EINVAL, "bad argument (cap must be a power of two)");
   hipStream_t st = (hipStream_t)hip_stream;
-  int32_t* cnt = nullptr;
+  DevScalars* dsc = nullptr;
   int32_t* tmp = nullptr;
-  HIPCHK(hipMalloc((void**)&cnt, 2 * sizeof(int32_t)), "alloc");
-  HIPCHK(hipMalloc((void**)&tmp, 2 * sizeof(int32_t) * (size_t)cap), "alloc");
-  HIPCHK(hipMemsetAsync(cnt, 0, 2 * sizeof(int32_t), st), "memset");
-  HIPCHK(mxk::flag_pairs(n, n_big, rcrit, x0, u0, x1, u1, h, pairs, tmp, cap, cnt, st), "flag");
-  int32_t hc[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st), "copy");
+  HIPCHK(hipMalloc((void**)&dsc, sizeof(DevScalars)), "alloc");
+  HIPCHK(hipMalloc((void**)&tmp, 4 * sizeof(int32_t) * (size_t)cap), "alloc");
+  HIPCHK(hipMemsetAsync(dsc, 0, sizeof(DevScalars), st), "memset");
+  HIPCHK(mxk::flag_pairs(n, n_big, rcrit, x0, u0, x1, u1, h, pairs, tmp, cap, dsc, st), "flag");
+  DevScalars hd;
+  HIPCHK(hipMemcpyAsync(&hd, dsc, sizeof(hd), hipMemcpyDeviceToHost, st), "copy");
   HIPCHK(hipStreamSynchronize(st), "sync");
-  (void)hipFree(cnt);
+  (void)hipFree(dsc);
   (void)hipFree(tmp);
-  *n_out = hc[0];
-  if (hc[1]) return fail(MX_ECAPACITY, "more flagged pairs than cap");
+  *n_out = hd.n_pairs;
+  if (hd.err) return fail(MX_ECAPACITY, "more flagged pairs than cap");
   return MX_OK;
 }
 

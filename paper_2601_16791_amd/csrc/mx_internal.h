@@ -63,13 +63,13 @@ struct mx_system {
   // packed sources
   KickSource* kpack;
   FlagSource* fpack;
-  // force split partials and tile counters
+  // force split partials
   double* part;
-  int32_t* tile_cnt;
   int split;
   // encounters
   int32_t* pairs;      // [cap][2]
-  int32_t* pairs_tmp;  // [cap][2] scratch of the planner
+  int32_t* pairs_tmp;  // [4*cap] int32 = [2*cap] int64 sort keys of the planner
+  int32_t* plan_idx;   // [2*cap] index lists of the planner
   int32_t cap_pairs;
   Subsystem* subs;
   int32_t cap_subs;
@@ -109,5 +109,5 @@ hipError_t kepler(int n, double mu0, double h, const double* x0, const double* u
                   double* u1, int32_t* err, hipStream_t st);
 hipError_t flag_pairs(int n, int nb, const double* rcrit, const double* x0, const double* u0,
                       const double* x1, const double* u1, double h, int32_t* pairs,
-                      int32_t* pairs_tmp, int32_t cap, int32_t* counter, hipStream_t st);
+                      int32_t* pairs_tmp, int32_t cap, DevScalars* dsc, hipStream_t st);
 }  // namespace mxk

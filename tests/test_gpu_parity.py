@@ -31,10 +31,38 @@ def mx():
 
 def relerr_rows(a, b):
     """max over bodies of |a_t - b_t| / |b_t| (3-vectors per body)."""
+    return float(relerr_per_body(a, b).max()) if a.size else 0.0
+
+
+def relerr_per_body(a, b):
     num = np.linalg.norm(a - b, axis=0)
     den = np.linalg.norm(b, axis=0)
     den = np.where(den > 0, den, 1.0)
-    return float((num / den).max()) if a.size else 0.0
+    return num / den
+
+
+def oracle_sensitivity(o, x, u, step_index, trials=2, seed=0):
+    """Per-body relative change of the oracle's own one-step result when every input
+    coordinate is moved by at most one ulp (relative 2.2e-16).  A body in a deep
+    encounter can amplify such differences by orders of magnitude within one step;
+    the GPU is then held to the oracle's own reproducibility.  Leaves o at the
+    unperturbed result."""
+    rng = np.random.default_rng(seed)
+    o.set_dh(x, u, step_index)
+    o.step(1)
+    xr, ur = o.get_dh()
+    sx = np.zeros(x.shape[1]); su = np.zeros(x.shape[1])
+    for _ in range(trials):
+        xp = x * (1 + rng.uniform(-2.2e-16, 2.2e-16, x.shape))
+        up = u * (1 + rng.uniform(-2.2e-16, 2.2e-16, u.shape))
+        o.set_dh(xp, up, step_index)
+        o.step(1)
+        xq, uq = o.get_dh()
+        sx = np.maximum(sx, relerr_per_body(xq, xr))
+        su = np.maximum(su, relerr_per_body(uq, ur))
+    o.set_dh(x, u, step_index)
+    o.step(1)
+    return xr, ur, sx, su
 
 
 # ----------------------------------------------------------- gravity kernel
@@ -277,3 +305,104 @@ def test_error_paths(mx):
     with pytest.raises(mx.MxError) as e:
         g.sync()
     assert e.value.code in (-6, -4)
+
+
+def _close_planets_workload(n_far=200):
+    """Three planets, two of them inside each other's changeover radius, with a cloud
+    of massless bodies around the pair: big-big components and shared copies."""
+    rng = np.random.default_rng(9)
+    mJ = ic.M_JUP
+    a_p = 5.2
+    vp = math.sqrt(G * (1 + mJ) / a_p)
+    rH = a_p * (mJ / 3) ** (1 / 3)
+    m = np.array([mJ, 0.3 * mJ, 0.1 * mJ])
+    xb = np.array([[a_p, a_p + 0.7 * rH, -8.0], [0.0, 0.15 * rH, 1.0], [0.0, 0.0, 0.01]])
+    vb = np.array([[0.0, 0.0, -0.1 * vp * 0.5], [vp, vp * 1.002, -0.8 * vp * 0.6], [0.0, 1e-5, 0.0]])
+    k = 40
+    d = rng.normal(0, 0.6 * rH, (3, k)); d[2] *= 0.1
+    xs = xb[:, :1] + d
+    vs = vb[:, :1] + rng.normal(0, 0.02 * vp, (3, k))
+    a = rng.uniform(2.0, 12.0, n_far)
+    xf, vf = ic.el2x(G, a, rng.uniform(0, 0.05, n_far), rng.uniform(0, 0.01, n_far),
+                     rng.uniform(0, 6.28, n_far), rng.uniform(0, 6.28, n_far), rng.uniform(0, 6.28, n_far))
+    x = np.hstack([xb, xs, xf]); v = np.hstack([vb, vs, vf])
+    P = 2 * math.pi * math.sqrt(a_p ** 3 / (G * (1 + mJ)))
+    p = ic.default_params(m0=1.0, dt=P / 400.0, n_big=3, n_small=k + n_far, gas_on=0)
+    return ic.Workload("close_planets", p, x, v, m)
+
+
+def test_step_parity_big_components(mx, orc):
+    w = _close_planets_workload()
+    g = mx.System.from_workload(w)
+    o = orc.OracleSystem.from_workload(w)
+    x, u = g.get_dh()
+    o.set_dh(x, u, 0)
+    g.set_dh(x, u, 0)
+    saw_bigbig = False
+    ill = 0
+    for k in range(4):
+        x, u = g.get_dh()
+        g.step(1)
+        g.sync()
+        xo, uo, sx, su = oracle_sensitivity(o, x, u, k)
+        xg, ug = g.get_dh()
+        pg, po = g.encounters(), o.encounters()
+        saw_bigbig |= bool(np.any(po[:, 1] < 3))
+        assert {tuple(p) for p in pg} == {tuple(p) for p in po}
+        # 1e-12 per body, or ten times the oracle's own one-ulp sensitivity
+        tol_x = np.maximum(1e-12, 10 * sx)
+        tol_u = np.maximum(1e-12, 10 * su)
+        assert np.all(relerr_per_body(xg, xo) <= tol_x), k
+        assert np.all(relerr_per_body(ug, uo) <= tol_u), k
+        ill += int(np.sum(np.maximum(sx, su) > 1e-13))
+    assert saw_bigbig
+
+
+def test_flag_kernel_large_list(mx, orc):
+    """More flagged pairs than the planner keeps in LDS (global-scratch sort path)."""
+    h = 20.0
+    x0, u0, x1, u1 = _flag_inputs(orc, 77, 6, 6000, h, spread=0.02)
+    rcrit = np.full(6, 0.25)
+    po = orc.flag(6, rcrit, x0, u0, x1, u1, h)
+    pg = mx.flag_pairs(6, rcrit, x0, u0, x1, u1, h)
+    assert len(po) > 2048
+    so, sg = {tuple(p) for p in po}, {tuple(p) for p in pg}
+    for (i, j) in so ^ sg:
+        d = orc.pair_dmin2(x0[:, j] - x0[:, i], u0[:, j] - u0[:, i], x1[:, j] - x1[:, i],
+                           u1[:, j] - u1[:, i], h)
+        assert abs(d - rcrit[i] ** 2) <= 1e-10 * rcrit[i] ** 2
+    assert np.array_equal(pg, np.array(sorted(sg), dtype=np.int32).reshape(-1, 2))
+
+
+def test_force_split_layout_full_size(mx, orc):
+    """The 4,004-body self-gravitating case in the launch configuration the
+    benchmark times (split layout, 64 targets x 4 waves per block): the stored
+    end-of-step force against the oracle's direct sum, every body."""
+    w = ic.self_gravitating(seed=0)
+    g = mx.System.from_workload(w)
+    x, u = g.get_dh()
+    mu, rcrit = g.masses()
+    a_g = g.accel()
+    a_o = orc.gravity(x, mu, rcrit, w.params["n_big"])
+    assert relerr_rows(a_g, a_o) < 1e-12
+    g.step(1)
+    g.sync()
+    x1, _ = g.get_dh()
+    mu1, rc1 = g.masses()
+    assert relerr_rows(g.accel(), orc.gravity(x1, mu1, rc1, w.params["n_big"])) < 1e-12
+
+
+def test_full_size_embryo_disk_step(mx, orc):
+    """One step of the 100,000-body embryo disk (the benchmark workload) against
+    the oracle on the same input state, every body."""
+    w = ic.embryo_disk(seed=0)
+    g = mx.System.from_workload(w)
+    o = orc.OracleSystem.from_workload(w)
+    x, u = g.get_dh()
+    g.step(1)
+    g.sync()
+    xo, uo, sx, su = oracle_sensitivity(o, x, u, 0, trials=1)
+    xg, ug = g.get_dh()
+    assert {tuple(p) for p in g.encounters()} == {tuple(p) for p in o.encounters()}
+    assert np.all(relerr_per_body(xg, xo) <= np.maximum(1e-12, 10 * sx))
+    assert np.all(relerr_per_body(ug, uo) <= np.maximum(1e-12, 10 * su))
