@@ -469,6 +469,115 @@ __device__ __forceinline__ void neville_round(int lane, int nn, int m, const dou
   }
 }
 
+// Register-resident variant for subsystems of M <= 4 members: positions,
+// increments and accelerations stay in VGPRs; the flagged pairs are a bit mask
+// over the M (M-1) / 2 possible pairs, walked at compile time.
+template <int M>
+__device__ __forceinline__ void force_reg(uint32_t pmask, const double (&mu)[M],
+                                          const double (&rc)[M], double mu0,
+                                          const double (&pos)[3 * M], double (&acc)[3 * M]) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    double r2 = fma(pos[3 * k + 2], pos[3 * k + 2],
+                    fma(pos[3 * k + 1], pos[3 * k + 1], pos[3 * k] * pos[3 * k]));
+    double y = mxd::rsqrt_full(r2);
+    double f = -mu0 * (y * y * y);
+    acc[3 * k] = f * pos[3 * k];
+    acc[3 * k + 1] = f * pos[3 * k + 1];
+    acc[3 * k + 2] = f * pos[3 * k + 2];
+  }
+  int bit = 0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+#pragma unroll
+    for (int b = a + 1; b < M; ++b, ++bit) {
+      if (!((pmask >> bit) & 1u)) continue;
+      double d0 = pos[3 * b] - pos[3 * a];
+      double d1 = pos[3 * b + 1] - pos[3 * a + 1];
+      double d2 = pos[3 * b + 2] - pos[3 * a + 2];
+      double s2 = fma(d2, d2, fma(d1, d1, d0 * d0));
+      double rcp = fmax(rc[a], rc[b]);
+      double rc2 = rcp * rcp;
+      double w = 0.0;
+      if (s2 < rc2 && s2 > 0.0) {
+        double y = mxd::rsqrt_full(s2);
+        double y3 = y * y * y;
+        if (s2 <= 0.01 * rc2) {
+          w = y3;
+        } else {
+          double q1 = (s2 * y - 0.1 * rcp) / (0.9 * rcp);
+          double q2 = q1 * q1, q3 = q1 * q2;
+          double K = q3 * fma(q1, fma(q1, 6.0, -15.0), 10.0);
+          w = y3 * (1.0 - K);
+        }
+      }
+      double wa = mu[b] * w, wb = mu[a] * w;
+      acc[3 * a] = fma(wa, d0, acc[3 * a]);
+      acc[3 * a + 1] = fma(wa, d1, acc[3 * a + 1]);
+      acc[3 * a + 2] = fma(wa, d2, acc[3 * a + 2]);
+      acc[3 * b] = fma(-wb, d0, acc[3 * b]);
+      acc[3 * b + 1] = fma(-wb, d1, acc[3 * b + 1]);
+      acc[3 * b + 2] = fma(-wb, d2, acc[3 * b + 2]);
+    }
+  }
+}
+
+template <int M>
+__device__ void stoermer_reg(int col, double H, uint32_t pmask, const double* mum,
+                             const double* rcm, double mu0, const double* xs, const double* vs,
+                             double* out) {
+  constexpr int NN = 3 * M;
+  double mu[M], rc[M], pos[NN], d[NN], acc[NN];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    mu[k] = mum[k];
+    rc[k] = rcm[k];
+  }
+#pragma unroll
+  for (int i = 0; i < NN; ++i) pos[i] = xs[i];
+  const int ns = 2 * (col + 1);
+  const double dt = H / ns;
+  force_reg<M>(pmask, mu, rc, mu0, pos, acc);
+#pragma unroll
+  for (int i = 0; i < NN; ++i) {
+    d[i] = dt * (vs[i] + 0.5 * dt * acc[i]);
+    pos[i] += d[i];
+  }
+  const double dt2 = dt * dt;
+  for (int k = 1; k < ns; ++k) {
+    force_reg<M>(pmask, mu, rc, mu0, pos, acc);
+#pragma unroll
+    for (int i = 0; i < NN; ++i) {
+      d[i] = fma(dt2, acc[i], d[i]);
+      pos[i] += d[i];
+    }
+  }
+  force_reg<M>(pmask, mu, rc, mu0, pos, acc);
+#pragma unroll
+  for (int i = 0; i < NN; ++i) {
+    out[i] = pos[i];
+    out[NN + i] = d[i] / dt + 0.5 * dt * acc[i];
+  }
+}
+
+// pair (a, b), a < b, of an M-member subsystem -> bit of the pair mask
+__device__ __forceinline__ int pair_bit(int a, int b, int m) {
+  return a * (2 * m - a - 1) / 2 + (b - a - 1);
+}
+
+__device__ __forceinline__ void run_column(int col, double H, int m, int np,
+                                           const int32_t (*pl)[2], uint32_t pmask,
+                                           const double* mum, const double* rcm, double mu0,
+                                           const double* xs, const double* vs, double* wk0,
+                                           double* wk1, double* wk2, double* out) {
+  switch (m) {
+    case 2: stoermer_reg<2>(col, H, pmask, mum, rcm, mu0, xs, vs, out); break;
+    case 3: stoermer_reg<3>(col, H, pmask, mum, rcm, mu0, xs, vs, out); break;
+    case 4: stoermer_reg<4>(col, H, pmask, mum, rcm, mu0, xs, vs, out); break;
+    default: stoermer_seq(col, H, m, np, pl, mum, rcm, mu0, xs, vs, wk0, wk1, wk2, out);
+  }
+}
+
 // Columns are evaluated in two rounds (n = 2..8, then n = 10..16, four lanes
 // each): most steps are accepted in the first round, and the table rows do not
 // depend on later rows, so the accepted column is the one a sequential
@@ -484,7 +593,7 @@ __global__ __launch_bounds__(64) void k_bs(int n, int nb, double mu0, double h, 
   __shared__ Subsystem S;
   __shared__ double xs[3 * kM], vs[3 * kM], mum[kM], rcm[kM], scal[2 * kM];
   __shared__ double res[kC][6 * kM];
-  __shared__ double wk[kRound][3][3 * kM];
+  __shared__ double wk[kC][3][3 * kM];
   const int lane = threadIdx.x;
   const int nsub = dsc->n_sub;
   const double tol2 = tol * tol;
@@ -510,6 +619,9 @@ __global__ __launch_bounds__(64) void k_bs(int n, int nb, double mu0, double h, 
       mum[k] = body < nb ? mu[body] : 0.0;
       rcm[k] = body < nb ? rcrit[body] : 0.0;
     }
+    uint32_t pmask = 0;
+    if (m <= 4)
+      for (int q = 0; q < np; ++q) pmask |= 1u << pair_bit(S.pl[q][0], S.pl[q][1], m);
     __syncthreads();
     double done = 0.0, H = h;
     int fails = 0;
@@ -526,13 +638,22 @@ __global__ __launch_bounds__(64) void k_bs(int n, int nb, double mu0, double h, 
       // per element (two per lane): the previous table row and the diagonal
       double prev[2][kC], diag[2][kC];
       int accepted = -1;
+      // after a rejection all eight columns run at once (a short first round
+      // rarely succeeds there); otherwise n = 2..8 first, n = 10..16 if needed
+      const bool wide = fails > 0;
 #pragma unroll
       for (int r = 0; r < kC / kRound; ++r) {
         if (accepted < 0) {
           const int k0 = r * kRound;
-          if (lane < kRound)
-            stoermer_seq(k0 + lane, H, m, np, S.pl, mum, rcm, mu0, xs, vs, wk[lane][0],
+          if (r == 0 && wide) {
+            if (lane < kC)
+              run_column(lane, H, m, np, S.pl, pmask, mum, rcm, mu0, xs, vs, wk[lane][0],
+                         wk[lane][1], wk[lane][2], res[lane]);
+          } else if (!(r == 1 && wide)) {
+            if (lane < kRound)
+              run_column(k0 + lane, H, m, np, S.pl, pmask, mum, rcm, mu0, xs, vs, wk[lane][0],
                          wk[lane][1], wk[lane][2], res[k0 + lane]);
+          }
           __syncthreads();
           double lerr[kRound];
           if (r == 0) neville_round<0>(lane, nn, m, res, scal, prev, diag, lerr);

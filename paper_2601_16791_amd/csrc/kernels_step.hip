@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_math.h"
+#include "force_sum.h"
 #include "mx_internal.h"
 
 namespace {
@@ -170,66 +171,6 @@ __global__ __launch_bounds__(kBlock) void k_jump_pack(int n, int nb, double mu0,
 // With split > 1 the per-split partial sums go to `part` and a second kernel adds
 // them in split order, so the result does not depend on block scheduling and no
 // device-wide fence is needed inside the force kernel.
-// one interaction: K = 1 weight mu y^3, y the hardware rsqrt with the
-// third-order correction y0 (1 + 3e/2 + 15e^2/8), e = 1 - s2 y0^2
-__device__ __forceinline__ double fast_weight(double mu, double s2) {
-  double y0 = __builtin_amdgcn_rsq(s2);
-  double y2 = y0 * y0;
-  double e = fma(-s2, y2, 1.0);
-  double c = fma(e, fma(e, 1.875, 1.5), 1.0);
-  return (mu * y0) * y2 * c;
-}
-
-// Sources [s0, s1) in ascending order, two per iteration (independent chains
-// for the scheduler), the next two records requested before the current ones
-// are used.  The changeover branch is taken only when either pair is inside
-// its changeover radius.
-__device__ __forceinline__ void force_sum(const KickSource* __restrict__ src, int s0, int s1,
-                                          double xt, double yt, double zt, double rc2t,
-                                          double rct, double& ax, double& ay, double& az) {
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  int s = s0;
-  if (s + 1 < s1) {
-    KickSource A = src[s], B = src[s + 1];
-    for (; s + 1 < s1; s += 2) {
-      const int na = s + 2 < s1 ? s + 2 : s;
-      const int nb2 = s + 3 < s1 ? s + 3 : s;
-      const KickSource NA = src[na], NB = src[nb2];
-      double dxa = A.x - xt, dya = A.y - yt, dza = A.z - zt;
-      double dxb = B.x - xt, dyb = B.y - yt, dzb = B.z - zt;
-      double s2a = fma(dza, dza, fma(dya, dya, dxa * dxa));
-      double s2b = fma(dzb, dzb, fma(dyb, dyb, dxb * dxb));
-      double rc2a = fmax(A.rc2, rc2t), rc2b = fmax(B.rc2, rc2t);
-      double wa = fast_weight(A.mu, s2a);
-      double wb = fast_weight(B.mu, s2b);
-      if (__builtin_expect((s2a < rc2a) | (s2b < rc2b), 0)) {
-        if (s2a < rc2a) wa = A.mu * mxd::changeover_weight_slow(s2a, fmax(A.rc, rct), rc2a);
-        if (s2b < rc2b) wb = B.mu * mxd::changeover_weight_slow(s2b, fmax(B.rc, rct), rc2b);
-      }
-      a0 = fma(wa, dxa, a0);
-      a1 = fma(wa, dya, a1);
-      a2 = fma(wa, dza, a2);
-      a0 = fma(wb, dxb, a0);
-      a1 = fma(wb, dyb, a1);
-      a2 = fma(wb, dzb, a2);
-      A = NA;
-      B = NB;
-    }
-  }
-  if (s < s1) {
-    const KickSource A = src[s];
-    double dx = A.x - xt, dy = A.y - yt, dz = A.z - zt;
-    double s2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    double rc2 = fmax(A.rc2, rc2t);
-    double w = fast_weight(A.mu, s2);
-    if (s2 < rc2) w = A.mu * mxd::changeover_weight_slow(s2, fmax(A.rc, rct), rc2);
-    a0 = fma(w, dx, a0);
-    a1 = fma(w, dy, a1);
-    a2 = fma(w, dz, a2);
-  }
-  ax = a0; ay = a1; az = a2;
-}
-
 __device__ __forceinline__ void finish_body(int t, int n, int nb, double mu0, double hh,
                                             const DragConst& dc, int gas_on, int kick,
                                             double ax, double ay, double az,
@@ -272,23 +213,20 @@ __global__ __launch_bounds__(kBlock) void k_force_kick(
     rc2t = rct * rct;
   }
   double ax, ay, az;
-  force_sum(kpack, 0, nb, xt, yt, zt, rc2t, rct, ax, ay, az);
+  mxd::force_sum(kpack, 0, nb, xt, yt, zt, rc2t, rct, ax, ay, az);
   double P[3] = {dsc->P[0], dsc->P[1], dsc->P[2]};
   if (t < n) finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, ax, ay, az, x, u, ag, r_p, rho_p, P, &dsc->err);
 }
 
-// Split layout (many massive bodies): 64 targets per block; the block's source
-// chunk is divided among its four waves and their sums are added in wave order
-// through LDS; the chunk sums of the `split` blocks of a tile go to `part`.
+// Split layout (many massive bodies): 256 targets per block, the four waves walk
+// the same source chunk (its records stay in the scalar cache), and the chunk
+// sums of the `split` blocks of a tile go to `part`.
 __global__ __launch_bounds__(kBlock) void k_force_split(
     int n, int nb, int split, const double* __restrict__ x,
     const KickSource* __restrict__ kpack, double* __restrict__ part) {
-  __shared__ double red[3][4][64];
   const int tile = blockIdx.x / split;
   const int sp = blockIdx.x - tile * split;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int t = tile * 64 + lane;
+  const int t = tile * kBlock + threadIdx.x;
   const int tt = t < n ? t : n - 1;
   const double xt = x[tt], yt = x[n + tt], zt = x[2 * n + tt];
   double rct = 0.0, rc2t = 0.0;
@@ -297,25 +235,15 @@ __global__ __launch_bounds__(kBlock) void k_force_split(
     rc2t = rct * rct;
   }
   const int per = (nb + split - 1) / split;
-  const int c0 = sp * per;
-  const int c1 = min(nb, c0 + per);
-  const int q = (c1 - c0 + 3) / 4;
-  const int s0 = min(c1, c0 + wv * q);
-  const int s1 = min(c1, s0 + q);
+  const int s0 = sp * per;
+  const int s1 = min(nb, s0 + per);
   double ax, ay, az;
-  force_sum(kpack, s0, s1, xt, yt, zt, rc2t, rct, ax, ay, az);
-  red[0][wv][lane] = ax;
-  red[1][wv][lane] = ay;
-  red[2][wv][lane] = az;
-  __syncthreads();
-  if (wv == 0 && t < n) {
-    double bx = ((red[0][0][lane] + red[0][1][lane]) + red[0][2][lane]) + red[0][3][lane];
-    double by = ((red[1][0][lane] + red[1][1][lane]) + red[1][2][lane]) + red[1][3][lane];
-    double bz = ((red[2][0][lane] + red[2][1][lane]) + red[2][2][lane]) + red[2][3][lane];
+  mxd::force_sum(kpack, s0, s1, xt, yt, zt, rc2t, rct, ax, ay, az);
+  if (t < n) {
     size_t base = (size_t)sp * 3 * n;
-    part[base + t] = bx;
-    part[base + n + t] = by;
-    part[base + 2 * n + t] = bz;
+    part[base + t] = ax;
+    part[base + n + t] = ay;
+    part[base + 2 * n + t] = az;
   }
 }
 
@@ -364,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity_plain(int n, int nb,
   const int tt = t < n ? t : n - 1;
   double rct = tt < nb ? kp[tt].rc : 0.0;
   double ax, ay, az;
-  force_sum(kp, 0, nb, x[tt], x[n + tt], x[2 * n + tt], rct * rct, rct, ax, ay, az);
+  mxd::force_sum(kp, 0, nb, x[tt], x[n + tt], x[2 * n + tt], rct * rct, rct, ax, ay, az);
   if (t < n) { a[t] = ax; a[n + t] = ay; a[2 * n + t] = az; }
 }
 
@@ -415,15 +343,15 @@ int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
 namespace mxk {
 
-// Source split of the force and flag kernels: with at least 128 massive bodies
-// the force runs in the split layout (64 targets x 4 waves per block) with
-// enough blocks to give every SIMD about four waves (256 CUs x 4 SIMDs) and at
-// least 32 sources per wave; 1 selects the wide layout.
+// Source split of the force kernel: with at least 128 massive bodies the force
+// runs in the split layout, with enough blocks to give every SIMD about four
+// waves (256 CUs x 4 SIMDs) and at least 32 sources per split; 1 selects the
+// wide layout.
 int force_split(int n, int nb) {
   if (nb < 128) return 1;
-  int tiles = (n + 63) / 64;
+  int tiles = blocks_for(n);
   int split = (1024 + tiles - 1) / tiles;
-  int maxs = nb / 128;
+  int maxs = nb / 32;
   if (split > maxs) split = maxs;
   if (split > 64) split = 64;
   if (split < 1) split = 1;
@@ -465,10 +393,10 @@ hipError_t launch_force_kick(mx_system* s, int kick) {
                        s->nb, s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->kpack,
                        s->r_p, s->rho_p, s->dsc);
   } else {
-    int tiles = (s->n + 63) / 64;
-    hipLaunchKernelGGL(k_force_split, dim3(tiles * s->split), dim3(kBlock), 0, s->stream, s->n,
-                       s->nb, s->split, s->x, s->kpack, s->part);
-    hipLaunchKernelGGL(k_force_finish, dim3(tiles), dim3(64), 0, s->stream, s->n, s->nb, s->split,
+    hipLaunchKernelGGL(k_force_split, dim3(blocks_for(s->n) * s->split), dim3(kBlock), 0,
+                       s->stream, s->n, s->nb, s->split, s->x, s->kpack, s->part);
+    hipLaunchKernelGGL(k_force_finish, dim3((s->n + 63) / 64), dim3(64), 0, s->stream, s->n, s->nb,
+                       s->split,
                        s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->r_p, s->rho_p,
                        s->part, s->dsc);
   }
