@@ -98,10 +98,12 @@ mx_status mx_step(mx_system* s, int32_t n_steps);
 /* Kernels of one step, in launch order (indices into kernel_ms below). */
 enum {
   MX_K_GROWTH = 0,          /* core-growth mass schedule (no-op without growth) */
-  MX_K_KICK_JUMP_DRIFT = 1, /* half kick + gas drag + jump + Kepler drift */
-  MX_K_FLAG = 2,            /* close-encounter flagging */
+  MX_K_KICK_JUMP_DRIFT = 1, /* half kick + gas drag + jump + Kepler drift (with n_big <= 64
+                               also the close-encounter flagging) */
+  MX_K_FLAG = 2,            /* close-encounter flagging (empty with n_big <= 64) */
   MX_K_ENCOUNTER = 3,       /* sort, subsystem plan and Bulirsch-Stoer */
-  MX_K_JUMP_PACK = 4,       /* second jump, source packing */
+  MX_K_JUMP_PACK = 4,       /* second jump, source packing (empty with n_big <= 64: the jump
+                               is done by the force kernel) */
   MX_K_FORCE_KICK = 5,      /* changeover-weighted gravity + gas drag + half kick */
   MX_NUM_KERNELS = 6
 };

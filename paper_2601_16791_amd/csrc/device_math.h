@@ -60,6 +60,23 @@ struct DragConst {
   double rc_norm;  // (1/r_c)^(2-gamma), the normalisation of the taper at 1 AU
 };
 
+// Drag constants of a parameter set (host side).
+inline DragConst make_drag_const(const mx_params& p) {
+  DragConst c;
+  c.mu0 = p.G * p.m0;
+  c.sigma1_unit = p.sigma1 * (p.rho_unit / p.au_cm);
+  c.gamma = p.gamma;
+  c.r_c = p.r_c;
+  c.inv_rc = p.r_c > 0.0 ? 1.0 / p.r_c : 0.0;
+  c.r_in = p.r_in;
+  c.h_over_r = p.h_over_r;
+  c.vg_fac = sqrt(1.0 - 2.0 * p.eta);
+  c.kexp = p.kdrag_exp;
+  c.mfp_coef = p.mfp_coef;
+  c.rc_norm = p.r_c > 0.0 ? pow(1.0 / p.r_c, 2.0 - p.gamma) : 0.0;
+  return c;
+}
+
 __device__ __forceinline__ double pow_kexp(double b, double kexp) {
   if (kexp == -2.0) return 1.0 / (b * b);
   if (kexp == -1.0) return 1.0 / b;

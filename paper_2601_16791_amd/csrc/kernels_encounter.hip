@@ -168,7 +168,7 @@ __device__ bool insert_sorted(int32_t* v, int& m, int cap, int b) {
   return true;
 }
 
-constexpr int kPlanThreads = 1024;
+constexpr int kPlanThreads = 256;
 constexpr int kPlanLds = 2048;   // pairs handled in LDS; larger lists use global scratch
 
 // Sort of the flagged list by (i, j) and the subsystem plan, in one block.
@@ -189,7 +189,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(
   __shared__ int scan[kPlanThreads];
   __shared__ int s_nbig_sub;
   const int np = min(dsc->n_pairs, cap);
-  if (np == 0) return;
+  if (threadIdx.x == 0) dsc->n_pairs_last = dsc->n_pairs;
+  if (np == 0) {
+    if (threadIdx.x == 0 && !sort_only) dsc->n_sub = 0;
+    return;
+  }
   const bool small_list = np <= kPlanLds;
   int64_t* K = small_list ? lk : gkeys;
   int64_t* S = small_list ? ls : gkeys + cap;
@@ -589,7 +593,8 @@ __global__ __launch_bounds__(64) void k_bs(int n, int nb, double mu0, double h, 
                                            const double* __restrict__ mu,
                                            const double* __restrict__ rcrit,
                                            const Subsystem* __restrict__ subs,
-                                           DevScalars* __restrict__ dsc) {
+                                           DevScalars* __restrict__ dsc,
+                                           double* __restrict__ bigmid) {
   __shared__ Subsystem S;
   __shared__ double xs[3 * kM], vs[3 * kM], mum[kM], rcm[kM], scal[2 * kM];
   __shared__ double res[kC][6 * kM];
@@ -701,6 +706,10 @@ __global__ __launch_bounds__(64) void k_bs(int n, int nb, double mu0, double h, 
       int body = S.mem[k];
       x[(size_t)c * n + body] = xs[e];
       u[(size_t)c * n + body] = vs[e];
+      if (body < nb) {
+        bigmid[(size_t)c * nb + body] = xs[e];
+        bigmid[(size_t)(3 + c) * nb + body] = vs[e];
+      }
     }
   }
 }
@@ -737,7 +746,8 @@ hipError_t launch_bs(mx_system* s) {
                      s->cap_pairs, (int64_t*)s->pairs_tmp, s->plan_idx, s->uf, s->subs,
                      s->cap_subs, s->dsc, 0);
   hipLaunchKernelGGL(k_bs, dim3(512), dim3(64), 0, s->stream, s->n, s->nb, s->mu0, s->p.dt,
-                     s->p.bs_tol, s->x0, s->u0, s->x, s->u, s->mu, s->rcrit, s->subs, s->dsc);
+                     s->p.bs_tol, s->x0, s->u0, s->x, s->u, s->mu, s->rcrit, s->subs, s->dsc,
+                     s->bigmid);
   return hipGetLastError();
 }
 

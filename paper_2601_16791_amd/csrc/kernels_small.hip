@@ -1,0 +1,280 @@
+// Fused step kernels for systems with few massive bodies (n_big <= 64), the
+// embryo-disk regime: massless planetesimals that feel a handful of embryos.
+//
+//   k_step_a_small : every block first advances the massive bodies itself (half
+//                    kick, jump, Kepler drift: the same few bodies in every block,
+//                    with identical arithmetic) and keeps them in LDS; then each
+//                    thread takes one body through drag, half kick, jump and drift
+//                    and tests it against the massive bodies for close encounters
+//                    (Hermite minimum separation) with the sources read from LDS.
+//   k_step_b_small : jump by the massive-body momentum after the encounter
+//                    integrator, changeover-weighted gravity from the massive
+//                    bodies held in LDS, gas drag and the closing half kick.
+//
+// Between the two run the encounter planner and the Bulirsch-Stoer kernel.  Four
+// launches per step instead of six, and no packed-source round trip through HBM.
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+#include "force_sum.h"
+#include "mx_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+using mxd::DragConst;
+
+// half kick (with drag for massless bodies, in the frame shifted by Ppre/mu0),
+// jump by Ppost/mu0, Kepler drift.  On entry (p, v, a) is the step-start state;
+// on exit (p, v) is the pre-drift state and (q, w) the post-drift state.
+__device__ __forceinline__ bool advance_body(int t, int nb, double mu0, double h,
+                                             const DragConst& dc, int gas_on,
+                                             const double* __restrict__ r_p,
+                                             const double* __restrict__ rho_p, const double* Ppre,
+                                             const double* Ppost, double (&p)[3], double (&v)[3],
+                                             const double (&a)[3], double (&q)[3],
+                                             double (&w)[3]) {
+  const double hh = 0.5 * h;
+  double ad[3] = {0.0, 0.0, 0.0};
+  if (t >= nb && gas_on) {
+    int j = t - nb;
+    mxd::gas_drag(dc, p[0], p[1], v[0] + Ppre[0] / mu0, v[1] + Ppre[1] / mu0,
+                  v[2] + Ppre[2] / mu0, r_p[j], rho_p[j], ad[0], ad[1], ad[2]);
+  }
+  for (int c = 0; c < 3; ++c) {
+    v[c] += hh * (a[c] + ad[c]);
+    p[c] += hh * Ppost[c] / mu0;
+    q[c] = p[c];
+    w[c] = v[c];
+  }
+  return mxd::kepler_drift(mu0, h, q[0], q[1], q[2], w[0], w[1], w[2]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_step_a_small(
+    int n, int nb, double mu0, double h, DragConst dc, int gas_on, double* __restrict__ x,
+    double* __restrict__ u, const double* __restrict__ ag, double* __restrict__ x0s,
+    double* __restrict__ u0s, const double* __restrict__ mu, const double* __restrict__ rcrit,
+    const double* __restrict__ r_p, const double* __restrict__ rho_p,
+    int32_t* __restrict__ pairs, int32_t cap, DevScalars* __restrict__ dsc,
+    const double* __restrict__ bigsnap, double* __restrict__ bigmid) {
+  __shared__ double sh[6 * kBlock];
+  __shared__ double bst[12][kSmallBig];  // x0 (3) u0 (3) x1 (3) u1 (3) of the big bodies
+  __shared__ double brc[kSmallBig];
+  const int tid = threadIdx.x;
+  const double hh = 0.5 * h;
+  // massive bodies from the step-start snapshot (block 0 overwrites x, u of the
+  // massive bodies while other blocks may still be reading)
+  double vsum[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = tid; k < nb; k += kBlock) {
+    double m = mu[k];
+    double ux = bigsnap[3 * nb + k], uy = bigsnap[4 * nb + k], uz = bigsnap[5 * nb + k];
+    vsum[0] += m * ux;
+    vsum[1] += m * uy;
+    vsum[2] += m * uz;
+    vsum[3] += m * (ux + hh * (bigsnap[6 * nb + k] + 0.0));
+    vsum[4] += m * (uy + hh * (bigsnap[7 * nb + k] + 0.0));
+    vsum[5] += m * (uz + hh * (bigsnap[8 * nb + k] + 0.0));
+  }
+  mxd::block_sum<kBlock, 6>(vsum, sh);
+  const double Ppre[3] = {vsum[0], vsum[1], vsum[2]};
+  const double Ppost[3] = {vsum[3], vsum[4], vsum[5]};
+  if (tid < nb) {
+    double p[3], v[3], a[3], q[3], w[3];
+    for (int c = 0; c < 3; ++c) {
+      p[c] = bigsnap[c * nb + tid];
+      v[c] = bigsnap[(3 + c) * nb + tid];
+      a[c] = bigsnap[(6 + c) * nb + tid];
+    }
+    bool ok = advance_body(tid, nb, mu0, h, dc, gas_on, r_p, rho_p, Ppre, Ppost, p, v, a, q, w);
+    if (!ok && blockIdx.x == 0) atomicOr(&dsc->err, MXE_NOCONV);
+    for (int c = 0; c < 3; ++c) {
+      bst[c][tid] = p[c];
+      bst[3 + c][tid] = v[c];
+      bst[6 + c][tid] = q[c];
+      bst[9 + c][tid] = w[c];
+    }
+    brc[tid] = rcrit[tid];
+  }
+  __syncthreads();
+  const int t = blockIdx.x * kBlock + tid;
+  if (t >= n) return;
+  double p[3], v[3], q[3], w[3];
+  if (t < nb) {
+    for (int c = 0; c < 3; ++c) {
+      p[c] = bst[c][t];
+      v[c] = bst[3 + c][t];
+      q[c] = bst[6 + c][t];
+      w[c] = bst[9 + c][t];
+    }
+    for (int c = 0; c < 3; ++c) {
+      bigmid[c * nb + t] = q[c];
+      bigmid[(3 + c) * nb + t] = w[c];
+    }
+  } else {
+    double a[3];
+    for (int c = 0; c < 3; ++c) {
+      p[c] = x[c * n + t];
+      v[c] = u[c * n + t];
+      a[c] = ag[c * n + t];
+    }
+    if (!advance_body(t, nb, mu0, h, dc, gas_on, r_p, rho_p, Ppre, Ppost, p, v, a, q, w))
+      atomicOr(&dsc->err, MXE_NOCONV);
+  }
+  for (int c = 0; c < 3; ++c) {
+    x0s[c * n + t] = p[c];
+    u0s[c * n + t] = v[c];
+    x[c * n + t] = q[c];
+    u[c * n + t] = w[c];
+  }
+  // encounter test against every massive body i < t (same bound and exact
+  // Hermite test as the general flag kernel)
+  const double rct = t < nb ? brc[t] : 0.0;
+  const int imax = t < nb ? t : nb;
+  const double k427 = (4.0 / 27.0) * fabs(h);
+  for (int i = 0; i < imax; ++i) {
+    double r0[3], w0[3], w1[3], dd[3];
+    for (int c = 0; c < 3; ++c) {
+      r0[c] = p[c] - bst[c][i];
+      w0[c] = v[c] - bst[3 + c][i];
+      w1[c] = w[c] - bst[9 + c][i];
+      dd[c] = (q[c] - p[c]) - (bst[6 + c][i] - bst[c][i]);
+    }
+    double m0 = fma(r0[2], r0[2], fma(r0[1], r0[1], r0[0] * r0[0]));
+    double nd = fmax(fmax(fabs(dd[0]), fabs(dd[1])), fabs(dd[2]));
+    double nw = fmax(fmax(fabs(w0[0]), fabs(w0[1])), fabs(w0[2])) +
+                fmax(fmax(fabs(w1[0]), fabs(w1[1])), fabs(w1[2]));
+    double rc = fmax(brc[i], rct);
+    double bound = rc + 1.7320508075688773 * fma(k427, nw, nd) * (1.0 + 1e-12);
+    if (__builtin_expect(m0 <= bound * bound * (1.0 + 1e-12), 0)) {
+      double r1[3];
+      for (int c = 0; c < 3; ++c) r1[c] = q[c] - bst[6 + c][i];
+      double dmin = mxd::hermite_dmin2(r0[0], r0[1], r0[2], w0[0], w0[1], w0[2], r1[0], r1[1],
+                                       r1[2], w1[0], w1[1], w1[2], h);
+      if (dmin <= rc * rc) {
+        int idx = atomicAdd(&dsc->n_pairs, 1);
+        if (idx < cap) {
+          pairs[2 * idx] = i;
+          pairs[2 * idx + 1] = t;
+        } else {
+          atomicOr(&dsc->err, MXE_PAIRS);
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_step_b_small(
+    int n, int nb, double mu0, double hh, DragConst dc, int gas_on, int kick,
+    double* __restrict__ x, double* __restrict__ u, double* __restrict__ ag,
+    const double* __restrict__ mu, const double* __restrict__ rcrit,
+    const double* __restrict__ r_p, const double* __restrict__ rho_p,
+    DevScalars* __restrict__ dsc, const double* __restrict__ bigmid,
+    double* __restrict__ bigsnap) {
+  __shared__ double sh[3 * kBlock];
+  __shared__ KickSource src[kSmallBig];
+  const int tid = threadIdx.x;
+  // massive bodies after drift and encounters from their snapshot (block 0
+  // overwrites x, u of the massive bodies while other blocks may still read)
+  double P[3] = {0, 0, 0};
+  for (int k = tid; k < nb; k += kBlock) {
+    double m = mu[k];
+    P[0] += m * bigmid[3 * nb + k];
+    P[1] += m * bigmid[4 * nb + k];
+    P[2] += m * bigmid[5 * nb + k];
+  }
+  mxd::block_sum<kBlock, 3>(P, sh);
+  const double J[3] = {hh * P[0] / mu0, hh * P[1] / mu0, hh * P[2] / mu0};
+  if (tid < nb) {
+    KickSource k;
+    double rc = rcrit[tid];
+    k.x = bigmid[tid] + J[0];
+    k.y = bigmid[nb + tid] + J[1];
+    k.z = bigmid[2 * nb + tid] + J[2];
+    k.mu = mu[tid];
+    k.rc2 = fmax(rc * rc, 1e-300);
+    k.rc = rc;
+    k.pad0 = k.pad1 = 0.0;
+    src[tid] = k;
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    dsc->P[0] = P[0];
+    dsc->P[1] = P[1];
+    dsc->P[2] = P[2];
+    if (kick) {
+      dsc->step += 1;
+      dsc->n_pairs = 0;  // the encounter list of this step has been planned
+    }
+  }
+  __syncthreads();
+  const int t = blockIdx.x * kBlock + tid;
+  if (t >= n) return;
+  const double px = x[t] + J[0], py = x[n + t] + J[1], pz = x[2 * n + t] + J[2];
+  x[t] = px;
+  x[n + t] = py;
+  x[2 * n + t] = pz;
+  const double rct = t < nb ? src[t].rc : 0.0;
+  const double rc2t = rct * rct;
+  double k15, k1875;
+  mxd::vgpr_constants(k15, k1875);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int s = 0; s < nb; ++s) {
+    const KickSource S = src[s];
+    double dx = S.x - px, dy = S.y - py, dz = S.z - pz;
+    double s2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    double rc2 = fmax(S.rc2, rc2t);
+    double wgt = mxd::fast_weight(S.mu, s2, k15, k1875);
+    if (s2 < rc2) wgt = S.mu * mxd::changeover_weight_slow(s2, fmax(S.rc, rct), rc2);
+    a0 = fma(wgt, dx, a0);
+    a1 = fma(wgt, dy, a1);
+    a2 = fma(wgt, dz, a2);
+  }
+  ag[t] = a0;
+  ag[n + t] = a1;
+  ag[2 * n + t] = a2;
+  if (!kick) return;
+  double vx = u[t], vy = u[n + t], vz = u[2 * n + t];
+  double adx = 0.0, ady = 0.0, adz = 0.0;
+  if (t >= nb && gas_on) {
+    int j = t - nb;
+    mxd::gas_drag(dc, px, py, vx + P[0] / mu0, vy + P[1] / mu0, vz + P[2] / mu0, r_p[j], rho_p[j],
+                  adx, ady, adz);
+  }
+  vx += hh * (a0 + adx);
+  vy += hh * (a1 + ady);
+  vz += hh * (a2 + adz);
+  u[t] = vx;
+  u[n + t] = vy;
+  u[2 * n + t] = vz;
+  if (!isfinite(vx + vy + vz + px + py + pz)) atomicOr(&dsc->err, MXE_NONFINITE);
+  if (t < nb) {
+    bigsnap[t] = px; bigsnap[nb + t] = py; bigsnap[2 * nb + t] = pz;
+    bigsnap[3 * nb + t] = vx; bigsnap[4 * nb + t] = vy; bigsnap[5 * nb + t] = vz;
+    bigsnap[6 * nb + t] = a0; bigsnap[7 * nb + t] = a1; bigsnap[8 * nb + t] = a2;
+  }
+}
+
+int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
+
+}  // namespace
+
+namespace mxk {
+
+hipError_t launch_step_a_small(mx_system* s) {
+  mxd::DragConst dc = mxd::make_drag_const(s->p);
+  hipLaunchKernelGGL(k_step_a_small, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n,
+                     s->nb, s->mu0, s->p.dt, dc, s->p.gas_on, s->x, s->u, s->ag, s->x0, s->u0,
+                     s->mu, s->rcrit, s->r_p, s->rho_p, s->pairs, s->cap_pairs, s->dsc,
+                     s->bigsnap, s->bigmid);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_b_small(mx_system* s, int kick) {
+  mxd::DragConst dc = mxd::make_drag_const(s->p);
+  hipLaunchKernelGGL(k_step_b_small, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n,
+                     s->nb, s->mu0, 0.5 * s->p.dt, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->mu,
+                     s->rcrit, s->r_p, s->rho_p, s->dsc, s->bigmid, s->bigsnap);
+  return hipGetLastError();
+}
+
+}  // namespace mxk

@@ -21,22 +21,8 @@ namespace {
 constexpr int kBlock = 256;
 
 using mxd::DragConst;
+using mxd::make_drag_const;
 
-DragConst make_drag_const(const mx_params& p) {
-  DragConst c;
-  c.mu0 = p.G * p.m0;
-  c.sigma1_unit = p.sigma1 * (p.rho_unit / p.au_cm);
-  c.gamma = p.gamma;
-  c.r_c = p.r_c;
-  c.inv_rc = p.r_c > 0.0 ? 1.0 / p.r_c : 0.0;
-  c.r_in = p.r_in;
-  c.h_over_r = p.h_over_r;
-  c.vg_fac = sqrt(1.0 - 2.0 * p.eta);
-  c.kexp = p.kdrag_exp;
-  c.mfp_coef = p.mfp_coef;
-  c.rc_norm = p.r_c > 0.0 ? pow(1.0 / p.r_c, 2.0 - p.gamma) : 0.0;
-  return c;
-}
 
 // ------------------------------------------------------------------ growth
 // M(t) = M0 + e/(e-1) (Mc - M0) (1 - exp(-t/tau_c)) for t < tau_c, Mc after;
@@ -63,27 +49,26 @@ __global__ __launch_bounds__(kBlock) void k_kick_jump_drift(
     double* __restrict__ u, const double* __restrict__ ag, double* __restrict__ x0s,
     double* __restrict__ u0s, const double* __restrict__ mu, const double* __restrict__ rcrit,
     const double* __restrict__ r_p, const double* __restrict__ rho_p,
-    FlagSource* __restrict__ fpack, DevScalars* __restrict__ dsc) {
+    FlagSource* __restrict__ fpack, DevScalars* __restrict__ dsc,
+    const double* __restrict__ bigsnap) {
   __shared__ double sh[6 * kBlock];
   const double hh = 0.5 * h;
   // massive-body momentum before (drag frame) and after the half kick (jump);
   // big bodies feel no drag, so their kicked velocity is u + hh * ag.
+  // (from the step-start snapshot: the blocks that own massive bodies overwrite
+  // u while other blocks are still reading)
   double v[6] = {0, 0, 0, 0, 0, 0};
   for (int k = threadIdx.x; k < nb; k += kBlock) {
     double m = mu[k];
-    double ux = u[k], uy = u[n + k], uz = u[2 * n + k];
+    double ux = bigsnap[3 * nb + k], uy = bigsnap[4 * nb + k], uz = bigsnap[5 * nb + k];
     v[0] += m * ux;
     v[1] += m * uy;
     v[2] += m * uz;
-    v[3] += m * (ux + hh * (ag[k] + 0.0));
-    v[4] += m * (uy + hh * (ag[n + k] + 0.0));
-    v[5] += m * (uz + hh * (ag[2 * n + k] + 0.0));
+    v[3] += m * (ux + hh * (bigsnap[6 * nb + k] + 0.0));
+    v[4] += m * (uy + hh * (bigsnap[7 * nb + k] + 0.0));
+    v[5] += m * (uz + hh * (bigsnap[8 * nb + k] + 0.0));
   }
   mxd::block_sum<kBlock, 6>(v, sh);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    dsc->n_pairs = 0;
-    dsc->n_sub = 0;
-  }
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= n) return;
   double px = x[t], py = x[n + t], pz = x[2 * n + t];
@@ -178,10 +163,18 @@ __device__ __forceinline__ void finish_body(int t, int n, int nb, double mu0, do
                                             double* __restrict__ u, double* __restrict__ ag,
                                             const double* __restrict__ r_p,
                                             const double* __restrict__ rho_p,
-                                            const double* P, int32_t* err) {
+                                            const double* P, int32_t* err,
+                                            double* __restrict__ bigsnap) {
   ag[t] = ax; ag[n + t] = ay; ag[2 * n + t] = az;
-  if (!kick) return;
   double vx = u[t], vy = u[n + t], vz = u[2 * n + t];
+  if (!kick) {
+    if (t < nb) {
+      bigsnap[t] = x[t]; bigsnap[nb + t] = x[n + t]; bigsnap[2 * nb + t] = x[2 * n + t];
+      bigsnap[3 * nb + t] = vx; bigsnap[4 * nb + t] = vy; bigsnap[5 * nb + t] = vz;
+      bigsnap[6 * nb + t] = ax; bigsnap[7 * nb + t] = ay; bigsnap[8 * nb + t] = az;
+    }
+    return;
+  }
   double adx = 0.0, ady = 0.0, adz = 0.0;
   if (t >= nb && gas_on) {
     int j = t - nb;
@@ -194,6 +187,11 @@ __device__ __forceinline__ void finish_body(int t, int n, int nb, double mu0, do
   u[t] = vx; u[n + t] = vy; u[2 * n + t] = vz;
   double chk = vx + vy + vz + x[t] + x[n + t] + x[2 * n + t];
   if (!isfinite(chk)) atomicOr(err, MXE_NONFINITE);
+  if (t < nb) {
+    bigsnap[t] = x[t]; bigsnap[nb + t] = x[n + t]; bigsnap[2 * nb + t] = x[2 * n + t];
+    bigsnap[3 * nb + t] = vx; bigsnap[4 * nb + t] = vy; bigsnap[5 * nb + t] = vz;
+    bigsnap[6 * nb + t] = ax; bigsnap[7 * nb + t] = ay; bigsnap[8 * nb + t] = az;
+  }
 }
 
 // Wide layout (few massive bodies): 256 targets per block, every wave walks
@@ -202,10 +200,14 @@ __global__ __launch_bounds__(kBlock) void k_force_kick(
     int n, int nb, double mu0, double hh, DragConst dc, int gas_on, int kick,
     const double* __restrict__ x, double* __restrict__ u, double* __restrict__ ag,
     const KickSource* __restrict__ kpack, const double* __restrict__ r_p,
-    const double* __restrict__ rho_p, DevScalars* __restrict__ dsc) {
+    const double* __restrict__ rho_p, DevScalars* __restrict__ dsc,
+    double* __restrict__ bigsnap) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int tt = t < n ? t : n - 1;
-  if (kick && blockIdx.x == 0 && threadIdx.x == 0) dsc->step += 1;
+  if (kick && blockIdx.x == 0 && threadIdx.x == 0) {
+    dsc->step += 1;
+    dsc->n_pairs = 0;  // the encounter list of this step has been planned
+  }
   const double xt = x[tt], yt = x[n + tt], zt = x[2 * n + tt];
   double rct = 0.0, rc2t = 0.0;
   if (tt < nb) {
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_force_kick(
   double ax, ay, az;
   mxd::force_sum(kpack, 0, nb, xt, yt, zt, rc2t, rct, ax, ay, az);
   double P[3] = {dsc->P[0], dsc->P[1], dsc->P[2]};
-  if (t < n) finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, ax, ay, az, x, u, ag, r_p, rho_p, P, &dsc->err);
+  if (t < n) finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, ax, ay, az, x, u, ag, r_p, rho_p, P, &dsc->err, bigsnap);
 }
 
 // Split layout (many massive bodies): 256 targets per block, the four waves walk
@@ -252,9 +254,13 @@ __global__ __launch_bounds__(kBlock) void k_force_finish(
     int n, int nb, int split, double mu0, double hh, DragConst dc, int gas_on, int kick,
     const double* __restrict__ x, double* __restrict__ u, double* __restrict__ ag,
     const double* __restrict__ r_p, const double* __restrict__ rho_p,
-    const double* __restrict__ part, DevScalars* __restrict__ dsc) {
+    const double* __restrict__ part, DevScalars* __restrict__ dsc,
+    double* __restrict__ bigsnap) {
   const int t = blockIdx.x * 64 + threadIdx.x;
-  if (kick && blockIdx.x == 0 && threadIdx.x == 0) dsc->step += 1;
+  if (kick && blockIdx.x == 0 && threadIdx.x == 0) {
+    dsc->step += 1;
+    dsc->n_pairs = 0;  // the encounter list of this step has been planned
+  }
   if (t >= n) return;
   double bx = 0.0, by = 0.0, bz = 0.0;
 #pragma unroll 8
@@ -265,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_force_finish(
     bz += part[base + 2 * n + t];
   }
   double P[3] = {dsc->P[0], dsc->P[1], dsc->P[2]};
-  finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, bx, by, bz, x, u, ag, r_p, rho_p, P, &dsc->err);
+  finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, bx, by, bz, x, u, ag, r_p, rho_p, P, &dsc->err, bigsnap);
 }
 
 // stateless gravity (single-kernel entry): packs then sums, no kick
@@ -369,7 +375,7 @@ hipError_t launch_kick_jump_drift(mx_system* s) {
   DragConst dc = make_drag_const(s->p);
   hipLaunchKernelGGL(k_kick_jump_drift, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n,
                      s->nb, s->mu0, s->p.dt, dc, s->p.gas_on, s->x, s->u, s->ag, s->x0, s->u0,
-                     s->mu, s->rcrit, s->r_p, s->rho_p, s->fpack, s->dsc);
+                     s->mu, s->rcrit, s->r_p, s->rho_p, s->fpack, s->dsc, s->bigsnap);
   return hipGetLastError();
 }
 
@@ -391,14 +397,13 @@ hipError_t launch_force_kick(mx_system* s, int kick) {
   if (s->split <= 1) {
     hipLaunchKernelGGL(k_force_kick, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n,
                        s->nb, s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->kpack,
-                       s->r_p, s->rho_p, s->dsc);
+                       s->r_p, s->rho_p, s->dsc, s->bigsnap);
   } else {
     hipLaunchKernelGGL(k_force_split, dim3(blocks_for(s->n) * s->split), dim3(kBlock), 0,
                        s->stream, s->n, s->nb, s->split, s->x, s->kpack, s->part);
     hipLaunchKernelGGL(k_force_finish, dim3((s->n + 63) / 64), dim3(64), 0, s->stream, s->n, s->nb,
-                       s->split,
-                       s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->r_p, s->rho_p,
-                       s->part, s->dsc);
+                       s->split, s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->r_p,
+                       s->rho_p, s->part, s->dsc, s->bigsnap);
   }
   return hipGetLastError();
 }

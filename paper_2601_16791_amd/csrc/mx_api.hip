@@ -61,21 +61,34 @@ void free_system(mx_system* s) {
   if (!s) return;
   if (s->graph_ok) (void)hipGraphExecDestroy(s->graph);
   void* ptrs[] = {s->x, s->u, s->ag, s->x0, s->u0, s->mu, s->rcrit, s->mu_init, s->rcrit_init,
-                  s->growth, s->r_p, s->rho_p, s->kpack, s->fpack, s->part,
+                  s->growth, s->r_p, s->rho_p, s->bigsnap, s->bigmid, s->kpack, s->fpack, s->part,
                   s->pairs, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
 }
 
+// kernel group k of one step (MX_K_* order); the fused small-B path runs its
+// flagging inside the first kernel and its jump inside the last
+hipError_t launch_group(mx_system* s, int k) {
+  const bool small = s->nb <= kSmallBig;
+  switch (k) {
+    case MX_K_GROWTH: return mxk::launch_growth(s);
+    case MX_K_KICK_JUMP_DRIFT:
+      return small ? mxk::launch_step_a_small(s) : mxk::launch_kick_jump_drift(s);
+    case MX_K_FLAG: return small ? hipSuccess : mxk::launch_flag(s);
+    case MX_K_ENCOUNTER: return mxk::launch_bs(s);
+    case MX_K_JUMP_PACK: return small ? hipSuccess : mxk::launch_jump_pack(s);
+    default: return small ? mxk::launch_step_b_small(s, 1) : mxk::launch_force_kick(s, 1);
+  }
+}
+
 hipError_t enqueue_step(mx_system* s) {
-  hipError_t e;
-  if ((e = mxk::launch_growth(s)) != hipSuccess) return e;
-  if ((e = mxk::launch_kick_jump_drift(s)) != hipSuccess) return e;
-  if ((e = mxk::launch_flag(s)) != hipSuccess) return e;
-  if ((e = mxk::launch_bs(s)) != hipSuccess) return e;
-  if ((e = mxk::launch_jump_pack(s)) != hipSuccess) return e;
-  return mxk::launch_force_kick(s, 1);
+  for (int k = 0; k < MX_NUM_KERNELS; ++k) {
+    hipError_t e = launch_group(s, k);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // FSAL gravity at the current positions (no kick)
@@ -158,6 +171,7 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   ALLOC(s->x, n3) ALLOC(s->u, n3) ALLOC(s->ag, n3) ALLOC(s->x0, n3) ALLOC(s->u0, n3)
   ALLOC(s->mu, nb) ALLOC(s->rcrit, nb) ALLOC(s->mu_init, nb) ALLOC(s->rcrit_init, nb)
   ALLOC(s->growth, 3 * (size_t)nb) ALLOC(s->r_p, s->ns) ALLOC(s->rho_p, s->ns)
+  ALLOC(s->bigsnap, 9 * (size_t)nb) ALLOC(s->bigmid, 6 * (size_t)nb)
   ALLOC(s->kpack, nb) ALLOC(s->fpack, nb)
   ALLOC(s->part, s->split > 1 ? (size_t)s->split * n3 : 1)
   ALLOC(s->pairs, 2 * (size_t)s->cap_pairs) ALLOC(s->pairs_tmp, 4 * (size_t)s->cap_pairs)
@@ -250,14 +264,7 @@ mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms) {
   for (int32_t q = 0; q < n_steps && e == hipSuccess; ++q) {
     e = hipEventRecord(ev[0], s->stream);
     for (int k = 0; k < K && e == hipSuccess; ++k) {
-      switch (k) {
-        case MX_K_GROWTH: e = mxk::launch_growth(s); break;
-        case MX_K_KICK_JUMP_DRIFT: e = mxk::launch_kick_jump_drift(s); break;
-        case MX_K_FLAG: e = mxk::launch_flag(s); break;
-        case MX_K_ENCOUNTER: e = mxk::launch_bs(s); break;
-        case MX_K_JUMP_PACK: e = mxk::launch_jump_pack(s); break;
-        default: e = mxk::launch_force_kick(s, 1); break;
-      }
+      e = launch_group(s, k);
       if (e == hipSuccess) e = hipEventRecord(ev[k + 1], s->stream);
     }
     if (e == hipSuccess) e = hipEventSynchronize(ev[K]);
@@ -300,8 +307,8 @@ mx_status mx_encounters(mx_system* s, int32_t* pairs, int32_t cap, int32_t* n_ou
   HIPCHK(hipStreamSynchronize(s->stream), "sync");
   DevScalars d;
   HIPCHK(hipMemcpy(&d, s->dsc, sizeof(DevScalars), hipMemcpyDeviceToHost), "read scalars");
-  *n_out = d.n_pairs;
-  int m = d.n_pairs < cap ? d.n_pairs : cap;
+  *n_out = d.n_pairs_last;
+  int m = d.n_pairs_last < cap ? d.n_pairs_last : cap;
   if (m > s->cap_pairs) m = s->cap_pairs;
   if (m > 0) HIPCHK(hipMemcpy(pairs, s->pairs, sizeof(int32_t) * 2 * m, hipMemcpyDeviceToHost), "copy pairs");
   return MX_OK;
@@ -457,7 +464,7 @@ mx_status mx_flag_pairs(int32_t n, int32_t n_big, const double* rcrit, const dou
   HIPCHK(hipStreamSynchronize(st), "sync");
   (void)hipFree(dsc);
   (void)hipFree(tmp);
-  *n_out = hd.n_pairs;
+  *n_out = hd.n_pairs_last;
   if (hd.err) return fail(MX_ECAPACITY, "more flagged pairs than cap");
   return MX_OK;
 }

@@ -15,6 +15,9 @@ enum : int32_t {
   MXE_NONFINITE = 16,  // non-finite state after a step
 };
 
+// Systems with at most this many massive bodies use the fused small-B kernels.
+constexpr int kSmallBig = 64;
+
 // Encounter-integrator capacity (members and pairs of one subsystem).
 constexpr int kBsMaxMembers = 16;
 constexpr int kBsMaxPairs = 48;
@@ -40,10 +43,10 @@ struct Subsystem {                  // one Bulirsch-Stoer subsystem
 // Device scalars of a system (one allocation).
 struct DevScalars {
   int64_t step;          // step counter (t = step * dt)
-  int32_t n_pairs;       // flagged pairs in the last step
-  int32_t n_sub;         // subsystems in the last step
+  int32_t n_pairs;       // pairs flagged so far in the current step (append counter)
+  int32_t n_sub;         // subsystems of the current step
   int32_t err;           // latched failure bits
-  int32_t pad;
+  int32_t n_pairs_last;  // flagged pairs of the last completed step
   double P[3];           // massive-body momentum sum mu*u after the last jump
 };
 
@@ -58,6 +61,11 @@ struct mx_system {
   // massive bodies
   double *mu, *rcrit, *mu_init, *rcrit_init, *growth;  // growth: [nb][3] (G*M0, G*Mc, tau)
   int has_growth;
+  // snapshots of the massive bodies, so that a kernel whose every block reads
+  // them never sees them half-updated by the block that owns them:
+  //   bigsnap [9][nb]: x, u, a at the step start (written at the end of a step)
+  //   bigmid  [6][nb]: x, u after drift and encounter integration (fused path)
+  double *bigsnap, *bigmid;
   // massless bodies
   double *r_p, *rho_p;  // rho_p in Msun/AU^3
   // packed sources
@@ -98,6 +106,8 @@ hipError_t launch_h2dh(mx_system* s, const double* v_h);
 hipError_t launch_dh2h(mx_system* s, double* v_h);
 hipError_t launch_init_bodies(mx_system* s, const double* x_h, const double* v_h);
 hipError_t launch_reset_scalars(mx_system* s, int64_t step);
+hipError_t launch_step_a_small(mx_system* s);
+hipError_t launch_step_b_small(mx_system* s, int kick);
 
 // stateless single-kernel launchers
 hipError_t gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,
