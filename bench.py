@@ -50,7 +50,7 @@ def workload(name: str, seed: int = 0):
     raise SystemExit(f"unknown workload {name}")
 
 
-def roofline_for(name: str, avg_s: float, w, n_pairs_avg: float):
+def roofline_for(name: str, avg_s: float, w, n_pairs_avg: float, bs_flop_per_launch: float = 0.0):
     nb, ns = w.params["n_big"], w.params["n_small"]
     n = nb + ns
     if name == "force_kick":
@@ -71,13 +71,19 @@ def roofline_for(name: str, avg_s: float, w, n_pairs_avg: float):
         return {"kernel": name, "bound": "hbm", "achieved": a / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s", "frac": a / PEAK_HBM, "traffic": None,
                 "model": "96 B per body (x0,u0,x1,u1) + 128 B per massive source record"}
-    # encounter integration and the small kernels: report against HBM for the state
-    # they touch (a latency-bound sparse phase)
-    b = 48 * 2 * max(n_pairs_avg, 1.0)
+    if name == "bs":
+        # model FP64 operations counted by the library while the kernel ran
+        a = bs_flop_per_launch / avg_s
+        return {"kernel": name, "bound": "alu", "achieved": a / 1e12, "peak": PEAK_FP64 / 1e12,
+                "unit": "TFLOP/s", "frac": a / PEAK_FP64, "traffic": None,
+                "model": "per force evaluation 24 FP64 ops per member + 25 per flagged pair, "
+                         "3 per extrapolation-table entry (FMA = 2), summed over the steps taken"}
+    # planner and the small kernels: HBM bytes of the pair list they sort and rewrite
+    b = 8 * 3 * max(n_pairs_avg, 1.0)
     a = b / avg_s
     return {"kernel": name, "bound": "hbm", "achieved": a / 1e9, "peak": PEAK_HBM / 1e9,
             "unit": "GB/s", "frac": a / PEAK_HBM, "traffic": None,
-            "model": "96 B per flagged pair (start state in, end state out)"}
+            "model": "24 B per flagged pair (list read, sorted list and plan written)"}
 
 
 def cpu_baseline(w, target_s: float):
@@ -159,10 +165,13 @@ def main():
     T = time.perf_counter() - t0
     print(f"[bench] timed {args.steps} steps in {T:.3f} s", file=sys.stderr, flush=True)
     pairs_last = len(s.encounters())
+    f0, p0 = s.counters()
     prof = s.step_profiled(args.profile_steps)
+    f1, p1 = s.counters()
     avg = {k: v / args.profile_steps / 1e3 for k, v in prof.items()}  # seconds per launch
     dominant = max(avg, key=avg.get)
-    roof = roofline_for(dominant, avg[dominant], w, pairs_last)
+    pairs_avg = (p1 - p0) / args.profile_steps
+    roof = roofline_for(dominant, avg[dominant], w, pairs_avg, (f1 - f0) / args.profile_steps)
     E, L = s.energy()
     s.close()
     out = {
@@ -184,6 +193,7 @@ def main():
         "steps_per_s": args.steps / T,
         "kernel_us_per_step": {k: v * 1e6 for k, v in avg.items()},
         "encounter_pairs_last_step": pairs_last,
+        "encounter_pairs_per_step": pairs_avg,
         "roofline": roof,
     }
     if not args.no_kick:

@@ -101,17 +101,23 @@ enum {
   MX_K_KICK_JUMP_DRIFT = 1, /* half kick + gas drag + jump + Kepler drift (with n_big <= 64
                                also the close-encounter flagging) */
   MX_K_FLAG = 2,            /* close-encounter flagging (empty with n_big <= 64) */
-  MX_K_ENCOUNTER = 3,       /* sort, subsystem plan and Bulirsch-Stoer */
-  MX_K_JUMP_PACK = 4,       /* second jump, source packing (empty with n_big <= 64: the jump
+  MX_K_PLAN = 3,            /* sort of the encounter list and subsystem plan */
+  MX_K_BS = 4,              /* Bulirsch-Stoer integration of the subsystems */
+  MX_K_JUMP_PACK = 5,       /* second jump, source packing (empty with n_big <= 64: the jump
                                is done by the force kernel) */
-  MX_K_FORCE_KICK = 5,      /* changeover-weighted gravity + gas drag + half kick */
-  MX_NUM_KERNELS = 6
+  MX_K_FORCE_KICK = 6,      /* changeover-weighted gravity + gas drag + half kick */
+  MX_NUM_KERNELS = 7
 };
 
 /* Same as mx_step, launched without the graph and with a HIP event around each
  * kernel group on the system stream; kernel_ms[MX_NUM_KERNELS] (host) receives the
  * summed event time of each group over the n_steps.  Synchronises every step. */
 mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms);
+
+/* Cumulative work counters of the system since init: FP64 operations of the
+ * encounter integrator (a model count per force evaluation and extrapolation
+ * entry, FMA = 2) and encounter pairs flagged.  Host pointers.  Synchronises. */
+mx_status mx_get_counters(mx_system* s, uint64_t* bs_flop, uint64_t* pairs_flagged);
 
 /* Wait for queued work and report any latched device failure (clears it). */
 mx_status mx_sync(mx_system* s);

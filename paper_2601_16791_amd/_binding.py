@@ -64,6 +64,8 @@ def lib():
         L.mx_step.argtypes = [_P, C.c_int32]
         L.mx_step_profiled.restype = st
         L.mx_step_profiled.argtypes = [_P, C.c_int32, C.POINTER(C.c_double)]
+        L.mx_get_counters.restype = st
+        L.mx_get_counters.argtypes = [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.mx_sync.restype = st
         L.mx_sync.argtypes = [_P]
         L.mx_energy.restype = st
@@ -167,13 +169,20 @@ class System:
         if sync:
             self.sync()
 
-    KERNELS = ("growth", "kick_jump_drift", "flag", "encounter_bs", "jump_pack", "force_kick")
+    KERNELS = ("growth", "kick_jump_drift", "flag", "plan", "bs", "jump_pack", "force_kick")
 
     def step_profiled(self, n=1):
         """Eager steps with HIP events around each kernel group; returns {name: ms total}."""
         ms = (C.c_double * len(self.KERNELS))()
         _check(lib().mx_step_profiled(self._h, int(n), ms))
         return dict(zip(self.KERNELS, ms[:]))
+
+    def counters(self):
+        """(model FP64 ops of the encounter integrator, flagged pairs), cumulative."""
+        a = C.c_uint64(0)
+        b = C.c_uint64(0)
+        _check(lib().mx_get_counters(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def sync(self):
         _check(lib().mx_sync(self._h))

@@ -189,7 +189,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(
   __shared__ int scan[kPlanThreads];
   __shared__ int s_nbig_sub;
   const int np = min(dsc->n_pairs, cap);
-  if (threadIdx.x == 0) dsc->n_pairs_last = dsc->n_pairs;
+  if (threadIdx.x == 0) {
+    dsc->n_pairs_last = dsc->n_pairs;
+    if (!sort_only) dsc->pairs_flagged += (unsigned long long)dsc->n_pairs;
+  }
   if (np == 0) {
     if (threadIdx.x == 0 && !sort_only) dsc->n_sub = 0;
     return;
@@ -650,14 +653,28 @@ __global__ __launch_bounds__(64) void k_bs(int n, int nb, double mu0, double h, 
       for (int r = 0; r < kC / kRound; ++r) {
         if (accepted < 0) {
           const int k0 = r * kRound;
+          int c_lo = 0, c_hi = 0;  // columns evaluated in this round
           if (r == 0 && wide) {
+            c_lo = 0;
+            c_hi = kC;
             if (lane < kC)
               run_column(lane, H, m, np, S.pl, pmask, mum, rcm, mu0, xs, vs, wk[lane][0],
                          wk[lane][1], wk[lane][2], res[lane]);
           } else if (!(r == 1 && wide)) {
+            c_lo = k0;
+            c_hi = k0 + kRound;
             if (lane < kRound)
               run_column(k0 + lane, H, m, np, S.pl, pmask, mum, rcm, mu0, xs, vs, wk[lane][0],
                          wk[lane][1], wk[lane][2], res[k0 + lane]);
+          }
+          if (lane == 0) {
+            // model count: per force evaluation 24 ops per member (star term and
+            // position update) and 25 per flagged pair; 3 per extrapolation entry
+            unsigned long long f = 0;
+            for (int c = c_lo; c < c_hi; ++c)
+              f += (unsigned long long)(2 * (c + 1) + 1) * (24 * m + 25 * np);
+            for (int k = k0; k < k0 + kRound; ++k) f += (unsigned long long)3 * k * 6 * m;
+            atomicAdd(&dsc->bs_flop, f);
           }
           __syncthreads();
           double lerr[kRound];
@@ -740,11 +757,16 @@ hipError_t launch_flag(mx_system* s) {
   return hipGetLastError();
 }
 
-hipError_t launch_bs(mx_system* s) {
+hipError_t launch_plan(mx_system* s) {
   if (s->nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s->stream, s->nb, s->pairs,
                      s->cap_pairs, (int64_t*)s->pairs_tmp, s->plan_idx, s->uf, s->subs,
                      s->cap_subs, s->dsc, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_bs(mx_system* s) {
+  if (s->nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_bs, dim3(512), dim3(64), 0, s->stream, s->n, s->nb, s->mu0, s->p.dt,
                      s->p.bs_tol, s->x0, s->u0, s->x, s->u, s->mu, s->rcrit, s->subs, s->dsc,
                      s->bigmid);

@@ -77,7 +77,8 @@ hipError_t launch_group(mx_system* s, int k) {
     case MX_K_KICK_JUMP_DRIFT:
       return small ? mxk::launch_step_a_small(s) : mxk::launch_kick_jump_drift(s);
     case MX_K_FLAG: return small ? hipSuccess : mxk::launch_flag(s);
-    case MX_K_ENCOUNTER: return mxk::launch_bs(s);
+    case MX_K_PLAN: return mxk::launch_plan(s);
+    case MX_K_BS: return mxk::launch_bs(s);
     case MX_K_JUMP_PACK: return small ? hipSuccess : mxk::launch_jump_pack(s);
     default: return small ? mxk::launch_step_b_small(s, 1) : mxk::launch_force_kick(s, 1);
   }
@@ -278,6 +279,16 @@ mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms) {
   if (e != hipSuccess) return hip_fail(e, "profiled step");
   s->host_step += n_steps;
   return read_err(s);
+}
+
+mx_status mx_get_counters(mx_system* s, uint64_t* bs_flop, uint64_t* pairs_flagged) {
+  if (!s || !bs_flop || !pairs_flagged) return fail(MX_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(s->stream), "sync");
+  DevScalars d;
+  HIPCHK(hipMemcpy(&d, s->dsc, sizeof(DevScalars), hipMemcpyDeviceToHost), "read scalars");
+  *bs_flop = d.bs_flop;
+  *pairs_flagged = d.pairs_flagged;
+  return MX_OK;
 }
 
 mx_status mx_sync(mx_system* s) {

@@ -48,6 +48,8 @@ struct DevScalars {
   int32_t err;           // latched failure bits
   int32_t n_pairs_last;  // flagged pairs of the last completed step
   double P[3];           // massive-body momentum sum mu*u after the last jump
+  unsigned long long bs_flop;        // cumulative model FP64 ops of the encounter integrator
+  unsigned long long pairs_flagged;  // cumulative flagged pairs
 };
 
 struct mx_system {
@@ -97,6 +99,7 @@ namespace mxk {
 hipError_t launch_growth(mx_system* s);
 hipError_t launch_kick_jump_drift(mx_system* s);
 hipError_t launch_flag(mx_system* s);
+hipError_t launch_plan(mx_system* s);
 hipError_t launch_bs(mx_system* s);
 hipError_t launch_jump_pack(mx_system* s);
 hipError_t launch_force_kick(mx_system* s, int kick);
