@@ -8,9 +8,12 @@ one JSON line.  `value` is changeover-weighted kick interactions per second over
 whole steps (I = n_big * (n - 1) per step, ordered pairs, n = non-star bodies).
 
 Extra objects:
-  roofline      -- the dominant kernel of the step against its bound (measured with
-                   HIP events around each kernel over a profiled run of the same
-                   system, right after the timed region)
+  roofline      -- the dominant kernel group of the step against its bound: groups
+                   are ranked with HIP events around each group, then the dominant
+                   one is timed over K further steps of the same run with HIP events
+                   bound to its kernels' own start and end (eager launches); its
+                   HBM traffic comes from the committed counter summary while the
+                   kernel source is unchanged
   kick_fp64     -- the force kernel of the fully self-gravitating 4,004-body case
                    (16.0 M interactions per kick) against FP64 peak
   cpu_baseline  -- the CPU oracle (single thread) on a bounded sample of steps
@@ -29,6 +32,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64 = 78.6e12        # MI355X FP64 vector, FLOP/s (FMA = 2)
 PEAK_HBM = 8.0e12          # bytes/s
 FLOP_PER_INTERACTION = 20  # conventional pairwise-force count
+COPY_BYTES = 256 << 20     # calibration copy: bytes read (and bytes written)
 # algorithmic HBM bytes per body of the kick+drag+jump+drift kernel:
 # read x,u,a (72) + r_p,rho_p (16, massless only); write x0,u0,x,u (96)
 BYTES_KJD_SMALL = 184
@@ -86,6 +90,31 @@ def roofline_for(name: str, avg_s: float, w, n_pairs_avg: float, bs_flop_per_lau
             "model": "24 B per flagged pair (list read, sorted list and plan written)"}
 
 
+def recorded_traffic(kernel_group: str, workload_name: str):
+    """HBM bytes per launch of a kernel group from the committed counter summary
+    (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or
+    None when there is none or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_group}_{workload_name}.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            rec[k.strip()] = v.strip().strip("`")
+    try:
+        h = hashlib.sha256()
+        for f in rec["source"].split(","):
+            h.update(open(os.path.join(ROOT, f.strip()), "rb").read())
+        digest = h.hexdigest()[:16]
+        if digest != rec["source_sha256_16"]:
+            return None
+        return float(rec["bytes_per_launch"]), os.path.relpath(path, ROOT)
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def cpu_baseline(w, target_s: float):
     import oracle
     oracle.build_lib(force=False)
@@ -115,16 +144,22 @@ def kick_fp64(args):
     s.step(3)
     s.sync()
     reps = args.kick_reps
-    prof = s.step_profiled(reps)
-    avg = prof["force_kick"] / reps / 1e3
+    t0 = time.perf_counter()
+    s.step(reps)
+    s.sync()
+    T = time.perf_counter() - t0
+    per_step_ms, n_launch = s.step_timed(reps, "force_kick")
+    avg = sum(per_step_ms) / max(n_launch, 1) / 1e3
     nb, n = w.params["n_big"], w.params["n_big"] + w.params["n_small"]
     I = interactions_per_step(nb, n)
     a = FLOP_PER_INTERACTION * I / avg
     s.close()
     return {"workload": "self_gravitating", "n_big": nb, "interactions_per_kick": I,
-            "avg_kernel_us": avg * 1e6, "achieved": a / 1e12, "peak": PEAK_FP64 / 1e12,
-            "unit": "TFLOP/s", "frac": a / PEAK_FP64, "interactions_per_s": I / avg,
-            "kernel_ms_per_step": {k: v / reps for k, v in prof.items()}}
+            "kernels": "k_force_split + k_force_finish (start of the first to end of the second)",
+            "avg_kick_us": avg * 1e6, "launches": n_launch, "achieved": a / 1e12,
+            "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": a / PEAK_FP64,
+            "interactions_per_s": I / avg, "steps_per_s": reps / T,
+            "model": f"{FLOP_PER_INTERACTION} FP64 flop per ordered interaction"}
 
 
 def main():
@@ -139,6 +174,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kick", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 256 MiB device-to-device once (reference reading for "
+                         "HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -149,6 +187,13 @@ def main():
     import paper_2601_16791_amd as mx
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = workload(args.workload, args.seed)
     nb, ns = w.params["n_big"], w.params["n_small"]
     n = nb + ns
@@ -156,22 +201,42 @@ def main():
     s = mx.System.from_workload(w)
     print(f"[bench] {w.name}: n_big={nb} n_small={ns} warmup={args.warmup}", file=sys.stderr, flush=True)
     s.step(args.warmup)
+    # rank the kernel groups (HIP events around each group; includes event overhead)
+    prof = s.step_profiled(args.profile_steps)
+    avg = {k: v / args.profile_steps / 1e3 for k, v in prof.items()}  # seconds per step
+    dominant = max(avg, key=avg.get)
+    s.step_timed(args.steps, dominant)  # also creates the timing events outside the timed region
     s.sync()
     torch.cuda.synchronize()
+    # timed region: K steps, eager launches (the default launch mode), with HIP events
+    # bound to the dominant group's kernels' own start and end
+    f0, p0 = s.counters()
     t0 = time.perf_counter()
-    s.step(args.steps)
+    per_step_ms, n_launch = s.step_timed(args.steps, dominant)
     s.sync()
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
+    f1, p1 = s.counters()
     print(f"[bench] timed {args.steps} steps in {T:.3f} s", file=sys.stderr, flush=True)
     pairs_last = len(s.encounters())
-    f0, p0 = s.counters()
-    prof = s.step_profiled(args.profile_steps)
-    f1, p1 = s.counters()
-    avg = {k: v / args.profile_steps / 1e3 for k, v in prof.items()}  # seconds per launch
-    dominant = max(avg, key=avg.get)
-    pairs_avg = (p1 - p0) / args.profile_steps
-    roof = roofline_for(dominant, avg[dominant], w, pairs_avg, (f1 - f0) / args.profile_steps)
+    pairs_avg = (p1 - p0) / args.steps
+    dom_avg_s = sum(per_step_ms) / max(n_launch, 1) / 1e3
+    roof = roofline_for(dominant, dom_avg_s, w, pairs_avg, (f1 - f0) / max(n_launch, 1))
+    roof["avg_launch_us"] = dom_avg_s * 1e6
+    roof["launches"] = n_launch
+    roof["traffic_unit"] = "bytes per launch"
+    roof["traffic_source"] = None
+    tr = recorded_traffic(dominant, w.name)
+    if tr is not None:
+        roof["traffic"], roof["traffic_source"] = tr
+    # the same number of steps launched as one captured HIP graph per step (context)
+    s.set_launch_mode("graph")
+    s.step(1)
+    s.sync()
+    t1 = time.perf_counter()
+    s.step(args.steps)
+    s.sync()
+    T_graph = time.perf_counter() - t1
     E, L = s.energy()
     s.close()
     out = {
@@ -191,7 +256,8 @@ def main():
                    "dt_days": w.params["dt"], "gas": bool(w.params["gas_on"]),
                    "interactions_per_step": I},
         "steps_per_s": args.steps / T,
-        "kernel_us_per_step": {k: v * 1e6 for k, v in avg.items()},
+        "kernel_us_per_step_events": {k: v * 1e6 for k, v in avg.items()},
+        "steps_per_s_graph_launch": args.steps / T_graph,
         "encounter_pairs_last_step": pairs_last,
         "encounter_pairs_per_step": pairs_avg,
         "roofline": roof,

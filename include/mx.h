@@ -92,8 +92,17 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
                          mx_system** out);
 
 /* Queue n_steps hybrid steps (Sect. 2; kick listing of Sect. 2.1.2, direct force
- * of Sect. 2.1.3).  Asynchronous; device failures surface at the next sync. */
+ * of Sect. 2.1.3).  Asynchronous; device failures surface at the next sync.
+ * Kernels are launched one by one (MX_LAUNCH_EAGER, the default) or as one
+ * captured HIP graph per step (MX_LAUNCH_GRAPH); both run the same kernels on
+ * the same data and give bitwise identical states. */
 mx_status mx_step(mx_system* s, int32_t n_steps);
+
+enum { MX_LAUNCH_EAGER = 0, MX_LAUNCH_GRAPH = 1 };
+
+/* Select how mx_step launches a step (see above).  The graph is captured on the
+ * first graph-mode step and kept until destroy. */
+mx_status mx_set_launch_mode(mx_system* s, int32_t mode);
 
 /* Kernels of one step, in launch order (indices into kernel_ms below). */
 enum {
@@ -113,6 +122,14 @@ enum {
  * kernel group on the system stream; kernel_ms[MX_NUM_KERNELS] (host) receives the
  * summed event time of each group over the n_steps.  Synchronises every step. */
 mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms);
+
+/* Runs n_steps steps with eager launches (no graph) and times one kernel group
+ * (an MX_K_* value) with HIP events bound to its kernels' own start and end:
+ * kernel_ms[q] (host, [n_steps]) is the time from the start of the group's
+ * first kernel to the end of its last in step q, 0 where the group launched
+ * nothing; *n_launched counts the steps where it launched.  Synchronises. */
+mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, float* kernel_ms,
+                        int32_t* n_launched);
 
 /* Cumulative work counters of the system since init: FP64 operations of the
  * encounter integrator (a model count per force evaluation and extrapolation

@@ -64,6 +64,11 @@ def lib():
         L.mx_step.argtypes = [_P, C.c_int32]
         L.mx_step_profiled.restype = st
         L.mx_step_profiled.argtypes = [_P, C.c_int32, C.POINTER(C.c_double)]
+        L.mx_set_launch_mode.restype = st
+        L.mx_set_launch_mode.argtypes = [_P, C.c_int32]
+        L.mx_step_timed.restype = st
+        L.mx_step_timed.argtypes = [_P, C.c_int32, C.c_int32, C.POINTER(C.c_float),
+                                    C.POINTER(C.c_int32)]
         L.mx_get_counters.restype = st
         L.mx_get_counters.argtypes = [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.mx_sync.restype = st
@@ -176,6 +181,20 @@ class System:
         ms = (C.c_double * len(self.KERNELS))()
         _check(lib().mx_step_profiled(self._h, int(n), ms))
         return dict(zip(self.KERNELS, ms[:]))
+
+    def set_launch_mode(self, mode):
+        """'eager' (default) or 'graph' (one captured HIP graph per step)."""
+        _check(lib().mx_set_launch_mode(self._h, {"eager": 0, "graph": 1}[mode]))
+
+    def step_timed(self, n, group):
+        """n eager steps; HIP events bound to the kernels of `group` (a name of
+        KERNELS).  Returns (per-step group milliseconds as a list, steps where the
+        group launched)."""
+        g = self.KERNELS.index(group)
+        ms = (C.c_float * max(int(n), 1))()
+        nl = C.c_int32(0)
+        _check(lib().mx_step_timed(self._h, int(n), g, ms, C.byref(nl)))
+        return list(ms[: int(n)]), nl.value
 
     def counters(self):
         """(model FP64 ops of the encounter integrator, flagged pairs), cumulative."""

@@ -750,27 +750,22 @@ int flag_split(int n, int nb) {
 hipError_t launch_flag(mx_system* s) {
   int tiles = (s->n + kBlock - 1) / kBlock;
   int split = flag_split(s->n, s->nb);
-  if (s->nb > 0)
-    hipLaunchKernelGGL(k_flag, dim3(tiles * split), dim3(kBlock), 0, s->stream, s->n, s->nb, split,
-                       s->p.dt, s->x0, s->u0, s->x, s->u, s->fpack, s->pairs, s->cap_pairs,
-                       &s->dsc->n_pairs, &s->dsc->err);
-  return hipGetLastError();
+  if (s->nb == 0) return hipSuccess;
+  return mxlaunch(s, k_flag, dim3(tiles * split), dim3(kBlock), s->n, s->nb, split, s->p.dt,
+                  s->x0, s->u0, s->x, s->u, s->fpack, s->pairs, s->cap_pairs, &s->dsc->n_pairs,
+                  &s->dsc->err);
 }
 
 hipError_t launch_plan(mx_system* s) {
   if (s->nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s->stream, s->nb, s->pairs,
-                     s->cap_pairs, (int64_t*)s->pairs_tmp, s->plan_idx, s->uf, s->subs,
-                     s->cap_subs, s->dsc, 0);
-  return hipGetLastError();
+  return mxlaunch(s, k_plan, dim3(1), dim3(kPlanThreads), s->nb, s->pairs, s->cap_pairs,
+                  (int64_t*)s->pairs_tmp, s->plan_idx, s->uf, s->subs, s->cap_subs, s->dsc, 0);
 }
 
 hipError_t launch_bs(mx_system* s) {
   if (s->nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bs, dim3(512), dim3(64), 0, s->stream, s->n, s->nb, s->mu0, s->p.dt,
-                     s->p.bs_tol, s->x0, s->u0, s->x, s->u, s->mu, s->rcrit, s->subs, s->dsc,
-                     s->bigmid);
-  return hipGetLastError();
+  return mxlaunch(s, k_bs, dim3(512), dim3(64), s->n, s->nb, s->mu0, s->p.dt, s->p.bs_tol,
+                  s->x0, s->u0, s->x, s->u, s->mu, s->rcrit, s->subs, s->dsc, s->bigmid);
 }
 
 // flag + sort for the stateless entry; fpack built from the given states

@@ -262,19 +262,17 @@ namespace mxk {
 
 hipError_t launch_step_a_small(mx_system* s) {
   mxd::DragConst dc = mxd::make_drag_const(s->p);
-  hipLaunchKernelGGL(k_step_a_small, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n,
-                     s->nb, s->mu0, s->p.dt, dc, s->p.gas_on, s->x, s->u, s->ag, s->x0, s->u0,
-                     s->mu, s->rcrit, s->r_p, s->rho_p, s->pairs, s->cap_pairs, s->dsc,
-                     s->bigsnap, s->bigmid);
-  return hipGetLastError();
+  return mxlaunch(s, k_step_a_small, dim3(blocks_for(s->n)), dim3(kBlock), s->n,
+                  s->nb, s->mu0, s->p.dt, dc, s->p.gas_on, s->x, s->u, s->ag, s->x0, s->u0,
+                  s->mu, s->rcrit, s->r_p, s->rho_p, s->pairs, s->cap_pairs, s->dsc,
+                  s->bigsnap, s->bigmid);
 }
 
 hipError_t launch_step_b_small(mx_system* s, int kick) {
   mxd::DragConst dc = mxd::make_drag_const(s->p);
-  hipLaunchKernelGGL(k_step_b_small, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n,
-                     s->nb, s->mu0, 0.5 * s->p.dt, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->mu,
-                     s->rcrit, s->r_p, s->rho_p, s->dsc, s->bigmid, s->bigsnap);
-  return hipGetLastError();
+  return mxlaunch(s, k_step_b_small, dim3(blocks_for(s->n)), dim3(kBlock), s->n,
+                  s->nb, s->mu0, 0.5 * s->p.dt, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->mu,
+                  s->rcrit, s->r_p, s->rho_p, s->dsc, s->bigmid, s->bigsnap);
 }
 
 }  // namespace mxk

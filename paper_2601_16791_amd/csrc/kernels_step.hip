@@ -366,46 +366,40 @@ int force_split(int n, int nb) {
 
 hipError_t launch_growth(mx_system* s) {
   if (!s->has_growth || s->nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_growth, dim3((s->nb + 255) / 256), dim3(256), 0, s->stream, s->nb, s->p.dt,
-                     s->growth, s->mu_init, s->rcrit_init, s->mu, s->rcrit, s->dsc);
-  return hipGetLastError();
+  return mxlaunch(s, k_growth, dim3((s->nb + 255) / 256), dim3(256), s->nb, s->p.dt,
+                  s->growth, s->mu_init, s->rcrit_init, s->mu, s->rcrit, s->dsc);
 }
 
 hipError_t launch_kick_jump_drift(mx_system* s) {
   DragConst dc = make_drag_const(s->p);
-  hipLaunchKernelGGL(k_kick_jump_drift, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n,
-                     s->nb, s->mu0, s->p.dt, dc, s->p.gas_on, s->x, s->u, s->ag, s->x0, s->u0,
-                     s->mu, s->rcrit, s->r_p, s->rho_p, s->fpack, s->dsc, s->bigsnap);
-  return hipGetLastError();
+  return mxlaunch(s, k_kick_jump_drift, dim3(blocks_for(s->n)), dim3(kBlock), s->n,
+                  s->nb, s->mu0, s->p.dt, dc, s->p.gas_on, s->x, s->u, s->ag, s->x0, s->u0,
+                  s->mu, s->rcrit, s->r_p, s->rho_p, s->fpack, s->dsc, s->bigsnap);
 }
 
 hipError_t launch_jump_pack(mx_system* s) {
-  hipLaunchKernelGGL(k_jump_pack, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n, s->nb,
-                     s->mu0, 0.5 * s->p.dt, s->x, s->u, s->mu, s->rcrit, s->kpack, s->dsc, 1);
-  return hipGetLastError();
+  return mxlaunch(s, k_jump_pack, dim3(blocks_for(s->n)), dim3(kBlock), s->n, s->nb,
+                  s->mu0, 0.5 * s->p.dt, s->x, s->u, s->mu, s->rcrit, s->kpack, s->dsc, 1);
 }
 
 hipError_t launch_pack_only(mx_system* s) {
-  hipLaunchKernelGGL(k_jump_pack, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n, s->nb,
-                     s->mu0, 0.0, s->x, s->u, s->mu, s->rcrit, s->kpack, s->dsc, 0);
-  return hipGetLastError();
+  return mxlaunch(s, k_jump_pack, dim3(blocks_for(s->n)), dim3(kBlock), s->n, s->nb,
+                  s->mu0, 0.0, s->x, s->u, s->mu, s->rcrit, s->kpack, s->dsc, 0);
 }
 
 hipError_t launch_force_kick(mx_system* s, int kick) {
   DragConst dc = make_drag_const(s->p);
   const double hh = 0.5 * s->p.dt;
-  if (s->split <= 1) {
-    hipLaunchKernelGGL(k_force_kick, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n,
-                       s->nb, s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->kpack,
-                       s->r_p, s->rho_p, s->dsc, s->bigsnap);
-  } else {
-    hipLaunchKernelGGL(k_force_split, dim3(blocks_for(s->n) * s->split), dim3(kBlock), 0,
-                       s->stream, s->n, s->nb, s->split, s->x, s->kpack, s->part);
-    hipLaunchKernelGGL(k_force_finish, dim3((s->n + 63) / 64), dim3(64), 0, s->stream, s->n, s->nb,
-                       s->split, s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->r_p,
-                       s->rho_p, s->part, s->dsc, s->bigsnap);
-  }
-  return hipGetLastError();
+  if (s->split <= 1)
+    return mxlaunch(s, k_force_kick, dim3(blocks_for(s->n)), dim3(kBlock), s->n, s->nb, s->mu0,
+                    hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->kpack, s->r_p, s->rho_p,
+                    s->dsc, s->bigsnap);
+  hipError_t e = mxlaunch(s, k_force_split, dim3(blocks_for(s->n) * s->split), dim3(kBlock),
+                          s->n, s->nb, s->split, s->x, s->kpack, s->part);
+  if (e != hipSuccess) return e;
+  return mxlaunch(s, k_force_finish, dim3((s->n + 63) / 64), dim3(64), s->n, s->nb, s->split,
+                  s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->r_p, s->rho_p,
+                  s->part, s->dsc, s->bigsnap);
 }
 
 hipError_t gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,

@@ -12,6 +12,8 @@
 #include <cstring>
 #include <string>
 
+#include <vector>
+
 #include "mx_internal.h"
 
 namespace mxk {
@@ -60,6 +62,8 @@ hipError_t copy_out(void* dst, const void* src, size_t bytes, int is_dev, hipStr
 void free_system(mx_system* s) {
   if (!s) return;
   if (s->graph_ok) (void)hipGraphExecDestroy(s->graph);
+  for (int32_t k = 0; k < s->tev_pool_n; ++k) (void)hipEventDestroy(s->tev_pool[k]);
+  delete[] s->tev_pool;
   void* ptrs[] = {s->x, s->u, s->ag, s->x0, s->u0, s->mu, s->rcrit, s->mu_init, s->rcrit_init,
                   s->growth, s->r_p, s->rho_p, s->bigsnap, s->bigmid, s->kpack, s->fpack, s->part,
                   s->pairs, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red};
@@ -235,7 +239,8 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
 mx_status mx_step(mx_system* s, int32_t n_steps) {
   if (!s || n_steps < 0) return fail(MX_EINVAL, "bad system or step count");
   if (n_steps == 0) return MX_OK;
-  if (s->stream != nullptr && !s->graph_ok) {
+  const bool use_graph = s->launch_mode == MX_LAUNCH_GRAPH && s->stream != nullptr;
+  if (use_graph && !s->graph_ok) {
     hipGraph_t g;
     HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal), "begin capture");
     hipError_t e = enqueue_step(s);
@@ -248,10 +253,19 @@ mx_status mx_step(mx_system* s, int32_t n_steps) {
     s->graph_ok = true;
   }
   for (int32_t k = 0; k < n_steps; ++k) {
-    if (s->graph_ok) HIPCHK(hipGraphLaunch(s->graph, s->stream), "graph launch");
+    if (use_graph) HIPCHK(hipGraphLaunch(s->graph, s->stream), "graph launch");
     else HIPCHK(enqueue_step(s), "step launch");
   }
   s->host_step += n_steps;
+  return MX_OK;
+}
+
+mx_status mx_set_launch_mode(mx_system* s, int32_t mode) {
+  if (!s || (mode != MX_LAUNCH_EAGER && mode != MX_LAUNCH_GRAPH))
+    return fail(MX_EINVAL, "bad system or launch mode");
+  if (mode == MX_LAUNCH_GRAPH && s->stream == nullptr)
+    return fail(MX_EINVAL, "graph launches need a non-default stream");
+  s->launch_mode = mode;
   return MX_OK;
 }
 
@@ -277,6 +291,58 @@ mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms) {
   }
   for (int k = 0; k <= K; ++k) (void)hipEventDestroy(ev[k]);
   if (e != hipSuccess) return hip_fail(e, "profiled step");
+  s->host_step += n_steps;
+  return read_err(s);
+}
+
+mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, float* kernel_ms,
+                        int32_t* n_launched) {
+  if (!s || n_steps < 0 || group < 0 || group >= MX_NUM_KERNELS || !kernel_ms || !n_launched)
+    return fail(MX_EINVAL, "bad argument");
+  *n_launched = 0;
+  if (n_steps == 0) return MX_OK;
+  if (n_steps > (1 << 24)) return fail(MX_EINVAL, "too many timed steps in one call");
+  hipError_t e = hipSuccess;
+  if (s->tev_pool_n < 2 * n_steps) {  // grow the event pool (kept for later calls)
+    hipEvent_t* pool = new hipEvent_t[2 * (size_t)n_steps];
+    int32_t k = 0;
+    for (; k < s->tev_pool_n; ++k) pool[k] = s->tev_pool[k];
+    for (; k < 2 * n_steps && e == hipSuccess; ++k) e = hipEventCreate(&pool[k]);
+    if (e != hipSuccess) --k;  // pool[k] was not created
+    delete[] s->tev_pool;
+    s->tev_pool = pool;
+    s->tev_pool_n = k;
+    if (e != hipSuccess) return hip_fail(e, "event create");
+  }
+  hipEvent_t* ev = s->tev_pool;
+  std::vector<char> used(n_steps, 0);
+  for (int32_t q = 0; q < n_steps && e == hipSuccess; ++q) {
+    for (int k = 0; k < MX_NUM_KERNELS && e == hipSuccess; ++k) {
+      if (k == group) {
+        s->tev_armed = true;
+        s->tev_start = ev[2 * q];
+        s->tev_stop = ev[2 * q + 1];
+      }
+      e = launch_group(s, k);
+      if (k == group) {
+        used[q] = s->tev_start == nullptr;  // the start event went to a kernel
+        s->tev_armed = false;
+        s->tev_start = s->tev_stop = nullptr;
+      }
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  int32_t nl = 0;
+  for (int32_t q = 0; q < n_steps; ++q) {
+    float ms = 0.f;
+    if (e == hipSuccess && used[q]) {
+      e = hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]);
+      ++nl;
+    }
+    kernel_ms[q] = ms;
+  }
+  if (e != hipSuccess) return hip_fail(e, "timed step");
+  *n_launched = nl;
   s->host_step += n_steps;
   return read_err(s);
 }

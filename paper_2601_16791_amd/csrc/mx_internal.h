@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include "../../include/mx.h"
@@ -91,8 +92,30 @@ struct mx_system {
   // graph of one step
   hipGraphExec_t graph;
   bool graph_ok;
+  int launch_mode;  // MX_LAUNCH_EAGER or MX_LAUNCH_GRAPH
+  // kernel timing of one group (eager launches only, never under capture): the
+  // next kernel launched records tev_start at its start, which is then cleared;
+  // every kernel launched while armed records tev_stop at its end
+  bool tev_armed;
+  hipEvent_t tev_start, tev_stop;
+  hipEvent_t* tev_pool;  // events of mx_step_timed, kept between calls
+  int32_t tev_pool_n;
   int64_t host_step;
 };
+
+// Launch on the system's stream (kernel timing as described at tev_armed).
+template <typename... KArgs, typename... Args>
+inline hipError_t mxlaunch(mx_system* s, void (*k)(KArgs...), dim3 grid, dim3 block,
+                           Args... args) {
+  if (s->tev_armed) {
+    hipExtLaunchKernelGGL(k, grid, block, 0, s->stream, s->tev_start, s->tev_stop, 0,
+                          static_cast<KArgs>(args)...);
+    s->tev_start = nullptr;
+  } else {
+    k<<<grid, block, 0, s->stream>>>(static_cast<KArgs>(args)...);
+  }
+  return hipGetLastError();
+}
 
 // ---- launchers (kernels_*.hip)
 namespace mxk {

@@ -280,6 +280,34 @@ def test_bitwise_deterministic_and_resumable(mx):
     assert a.step_index() == 20 and c.step_index() == 20
 
 
+@pytest.mark.parametrize("name,kw,group", [
+    ("embryo_disk", dict(seed=2, n_small=3000, n_emb=8), "bs"),
+    ("self_gravitating", dict(seed=1, n_pl=4, n_pls=600), "force_kick"),
+])
+def test_launch_modes_give_identical_states(mx, name, kw, group):
+    """Eager, graph, timed and profiled launches run the same kernels on the same
+    data: identical states, and a positive time for every timed launch."""
+    w = getattr(ic, name)(**kw)
+    a = mx.System.from_workload(w)
+    b = mx.System.from_workload(w)
+    c = mx.System.from_workload(w)
+    a.set_launch_mode("graph")
+    a.step(12)
+    c.step(12)
+    ms, nl = b.step_timed(8, group)
+    prof = b.step_profiled(4)
+    assert nl == 8 and len(ms) == 8 and min(ms) > 0.0
+    assert set(prof) == set(mx.System.KERNELS)
+    xa, ua = a.get_dh()
+    xb, ub = b.get_dh()
+    xc, uc = c.get_dh()
+    assert np.array_equal(xa, xb) and np.array_equal(ua, ub)
+    assert np.array_equal(xa, xc) and np.array_equal(ua, uc)
+    assert a.step_index() == b.step_index() == c.step_index() == 12
+    f, npairs = b.counters()
+    assert f >= 0 and npairs >= 0
+
+
 def test_heliocentric_roundtrip(mx, orc):
     w = ic.two_giants(seed=3, n_small=100)
     g = mx.System.from_workload(w)
