@@ -3,9 +3,11 @@
 // A system owns all of its device memory (allocated once at init, freed at
 // destroy; nothing is allocated per step).  One hybrid step is the kernel
 // sequence
-//   [growth] -> kick_jump_drift -> flag -> sort/plan/BS -> jump_pack -> force_kick
-// on the system's stream; with a non-null stream the sequence is captured once
-// into a HIP graph and replayed for every step.
+//   [growth] -> kick_jump_drift -> flag -> plan -> BS -> jump_pack -> force_kick
+// on the system's stream (with n_big <= 64 the fused small-B kernels replace
+// kick_jump_drift + flag and jump_pack + force_kick).  Steps are launched kernel
+// by kernel, or, in graph mode, captured once into a HIP graph that is replayed
+// for every step.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
