@@ -35,6 +35,7 @@ extern "C" {
 #endif
 
 typedef struct mx_system mx_system; /* opaque; owned by the library */
+typedef struct mx_batch mx_batch;   /* opaque; many independent systems stepped together */
 
 typedef enum {
   MX_OK = 0,
@@ -171,6 +172,59 @@ mx_status mx_get_step_index(mx_system* s, int64_t* step_index);
 
 void mx_destroy(mx_system* s);
 const char* mx_last_error(void);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent systems stepped together: every launch of a step covers all
+ * systems (the fused small-B kernels walk one table of body tiles of all the
+ * systems, the planner runs one block per system, the encounter integrator a
+ * grid of bs_blocks x n_sys).  Each system computes exactly what mx_step computes
+ * for it alone, with bitwise identical results whatever the configuration.
+ * Every system needs n_big <= 64; growth schedules are not supported here. */
+
+/* params: host [n_sys] (n_big, n_small of each); offsets: host [n_sys + 1] body
+ * offsets, offsets[0] = 0, offsets[k+1] - offsets[k] = n_big + n_small of system
+ * k.  x_h, v_h: concatenated SoA [3][N], N = offsets[n_sys], system k in columns
+ * offsets[k] .. offsets[k+1] (big bodies first), heliocentric.  m_big: the
+ * systems' n_big masses one after the other; r_p, rho_p: the systems' massless
+ * bodies one after the other (NULL allowed when no system has gas).  Host or
+ * device pointers per is_device_ptr, read during the call only.  Systems share
+ * hip_stream.  Each system is initialised as mx_init_system would. */
+mx_status mx_init_batch(int32_t n_sys, const mx_params* params, const int64_t* offsets,
+                        const double* x_h, const double* v_h, const double* m_big,
+                        const double* r_p, const double* rho_p, int is_device_ptr,
+                        void* hip_stream, mx_batch** out);
+
+/* Queue n_steps steps of every system.  Eager launches, or in graph mode one
+ * captured HIP graph of steps_per_graph whole steps replayed as often as it fits
+ * (the rest eagerly).  Asynchronous. */
+mx_status mx_step_batch(mx_batch* b, int32_t n_steps);
+mx_status mx_batch_set_launch_mode(mx_batch* b, int32_t mode, int32_t steps_per_graph);
+
+/* Launch shape: blk bodies per tile (64, 128, 256 or 512), tiles_per_block
+ * consecutive tiles per workgroup (1..64; the massive bodies of a system are
+ * advanced once per workgroup and system), bs_blocks encounter-integrator
+ * workgroups per system (1..1024).  cfg (host [3]) receives the same triple. */
+mx_status mx_batch_set_config(mx_batch* b, int32_t blk, int32_t tiles_per_block,
+                              int32_t bs_blocks);
+mx_status mx_batch_get_config(mx_batch* b, int32_t* cfg);
+
+/* Autotuner: times real steps of the batch (steps_per_candidate per candidate;
+ * every candidate gives the same results) over the tile shapes and then the
+ * encounter-integrator width, and keeps the fastest.  *steps_taken (host) is the
+ * number of steps it advanced; cfg_out (host [3]) the chosen triple; *best_ms the
+ * best time per step.  Synchronises and reports device failures. */
+mx_status mx_batch_autotune(mx_batch* b, int32_t steps_per_candidate, int32_t* steps_taken,
+                            int32_t* cfg_out, float* best_ms);
+
+/* Wait for queued work; reports the first system with a latched failure. */
+mx_status mx_batch_sync(mx_batch* b);
+
+/* Borrowed view of system k for the per-system calls (energy, encounters, state,
+ * step index, and mx_step to advance that system alone).  Owned by the batch:
+ * mx_destroy on it does nothing. */
+mx_status mx_batch_system(mx_batch* b, int32_t k, mx_system** view);
+
+void mx_destroy_batch(mx_batch* b);
 
 /* -------------------------------------------- single-kernel entry points
  * Stateless launches of one kernel of the step on device pointers, queued on

@@ -6,6 +6,7 @@ kernels of the library.  There is no CPU fallback: if the library is missing the
 import of any entry point raises.
 """
 from ._binding import (  # noqa: F401
+    Batch,
     MxError,
     Params,
     System,

@@ -100,6 +100,25 @@ def lib():
                                   _P]
         L.mx_kepler_drift.restype = st
         L.mx_kepler_drift.argtypes = [C.c_int32, C.c_double, C.c_double, _D, _D, _D, _D, _P]
+        L.mx_init_batch.restype = st
+        L.mx_init_batch.argtypes = [C.c_int32, C.POINTER(Params), C.POINTER(C.c_int64), _D, _D,
+                                    _D, _D, _D, C.c_int, _P, C.POINTER(C.c_void_p)]
+        L.mx_step_batch.restype = st
+        L.mx_step_batch.argtypes = [_P, C.c_int32]
+        L.mx_batch_set_launch_mode.restype = st
+        L.mx_batch_set_launch_mode.argtypes = [_P, C.c_int32, C.c_int32]
+        L.mx_batch_set_config.restype = st
+        L.mx_batch_set_config.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32]
+        L.mx_batch_get_config.restype = st
+        L.mx_batch_get_config.argtypes = [_P, C.POINTER(C.c_int32)]
+        L.mx_batch_autotune.restype = st
+        L.mx_batch_autotune.argtypes = [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_float)]
+        L.mx_batch_sync.restype = st
+        L.mx_batch_sync.argtypes = [_P]
+        L.mx_batch_system.restype = st
+        L.mx_batch_system.argtypes = [_P, C.c_int32, C.POINTER(C.c_void_p)]
+        L.mx_destroy_batch.argtypes = [_P]
         L.mx_flag_pairs.restype = st
         L.mx_flag_pairs.argtypes = [C.c_int32, C.c_int32, _D, _D, _D, _D, _D, C.c_double, _D,
                                     C.c_int32, C.POINTER(C.c_int32), _P]
@@ -158,9 +177,23 @@ class System:
     def from_workload(cls, w, device="cuda"):
         return cls(w.params, w.x, w.v, w.m_big, w.r_p, w.rho_p, w.growth, device=device)
 
+    @classmethod
+    def _view(cls, handle, params, device, stream, owner):
+        """A system owned by a batch (closing the view does not free it)."""
+        torch = _torch()
+        obj = cls.__new__(cls)
+        obj.params = dict(params)
+        obj.n = int(params["n_big"]) + int(params["n_small"])
+        obj.nb = int(params["n_big"])
+        obj.device = torch.device(device)
+        obj.stream = stream
+        obj._h = handle
+        obj._owner = owner  # keeps the batch alive while the view exists
+        return obj
+
     def close(self):
         if getattr(self, "_h", None):
-            lib().mx_destroy(self._h)
+            lib().mx_destroy(self._h)  # no-op for a system owned by a batch
             self._h = None
 
     def __del__(self):
@@ -263,6 +296,90 @@ class System:
         v = C.c_int64(0)
         _check(lib().mx_get_step_index(self._h, C.byref(v)))
         return v.value
+
+
+class Batch:
+    """Independent systems stepped together (every system needs n_big <= 64)."""
+
+    def __init__(self, params_list, xs, vs, m_bigs, r_ps=None, rho_ps=None, device="cuda"):
+        torch = _torch()
+        k = len(params_list)
+        self.params = [dict(p) for p in params_list]
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        sizes = [int(p["n_big"]) + int(p["n_small"]) for p in self.params]
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        tx = _dev(np.hstack([np.asarray(x, dtype=np.float64) for x in xs]), device)
+        tv = _dev(np.hstack([np.asarray(v, dtype=np.float64) for v in vs]), device)
+        mb = [np.asarray(m, dtype=np.float64).reshape(-1) for m in m_bigs]
+        tm = _dev(np.concatenate(mb) if sum(len(m) for m in mb) else np.zeros(1), device)
+        trp = trh = None
+        if r_ps is not None and any(r is not None for r in r_ps):
+            rp = [np.asarray(r if r is not None else np.zeros(int(p["n_small"])), dtype=np.float64)
+                  for r, p in zip(r_ps, self.params)]
+            rh = [np.asarray(r if r is not None else np.ones(int(p["n_small"])), dtype=np.float64)
+                  for r, p in zip(rho_ps, self.params)]
+            trp, trh = _dev(np.concatenate(rp), device), _dev(np.concatenate(rh), device)
+        torch.cuda.current_stream(self.device).synchronize()
+        self._pp = (Params * k)(*[make_params(p) for p in self.params])
+        offs = (C.c_int64 * (k + 1))(*[int(o) for o in self.offsets])
+        h = C.c_void_p()
+        _check(lib().mx_init_batch(k, self._pp, offs, _ptr(tx), _ptr(tv), _ptr(tm), _ptr(trp),
+                                   _ptr(trh), 1, C.c_void_p(self.stream.cuda_stream),
+                                   C.byref(h)))
+        self._h = h
+        self.n_sys = k
+
+    @classmethod
+    def from_workloads(cls, ws, device="cuda"):
+        return cls([w.params for w in ws], [w.x for w in ws], [w.v for w in ws],
+                   [w.m_big for w in ws], [w.r_p for w in ws], [w.rho_p for w in ws],
+                   device=device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mx_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1, sync=False):
+        _check(lib().mx_step_batch(self._h, int(n)))
+        if sync:
+            self.sync()
+
+    def sync(self):
+        _check(lib().mx_batch_sync(self._h))
+
+    def set_launch_mode(self, mode, steps_per_graph=1):
+        _check(lib().mx_batch_set_launch_mode(self._h, {"eager": 0, "graph": 1}[mode],
+                                              int(steps_per_graph)))
+
+    def set_config(self, blk, tiles_per_block, bs_blocks):
+        _check(lib().mx_batch_set_config(self._h, int(blk), int(tiles_per_block), int(bs_blocks)))
+
+    def config(self):
+        cfg = (C.c_int32 * 3)()
+        _check(lib().mx_batch_get_config(self._h, cfg))
+        return tuple(cfg[:])
+
+    def autotune(self, steps_per_candidate=3):
+        """Returns (steps taken, (blk, tiles_per_block, bs_blocks), best ms per step)."""
+        taken = C.c_int32(0)
+        cfg = (C.c_int32 * 3)()
+        ms = C.c_float(0)
+        _check(lib().mx_batch_autotune(self._h, int(steps_per_candidate), C.byref(taken), cfg,
+                                       C.byref(ms)))
+        return taken.value, tuple(cfg[:]), ms.value
+
+    def system(self, k):
+        h = C.c_void_p()
+        _check(lib().mx_batch_system(self._h, int(k), C.byref(h)))
+        return System._view(h, self.params[k], self.device, self.stream, self)
 
 
 # ------------------------------------------------------------ single kernels

@@ -55,27 +55,7 @@ __device__ __forceinline__ double changeover_k(double s2, double rc) {
 // nu = sqrt(8/pi) c_s lambda / 3, and F_D of Eq. 3 directed against dv.
 // (vx, vy, vz) is the heliocentric velocity.  Returns a zero vector where the
 // gas density vanishes or dv = 0.
-struct DragConst {
-  double mu0, sigma1_unit, gamma, r_c, inv_rc, r_in, h_over_r, vg_fac, kexp, mfp_coef;
-  double rc_norm;  // (1/r_c)^(2-gamma), the normalisation of the taper at 1 AU
-};
-
-// Drag constants of a parameter set (host side).
-inline DragConst make_drag_const(const mx_params& p) {
-  DragConst c;
-  c.mu0 = p.G * p.m0;
-  c.sigma1_unit = p.sigma1 * (p.rho_unit / p.au_cm);
-  c.gamma = p.gamma;
-  c.r_c = p.r_c;
-  c.inv_rc = p.r_c > 0.0 ? 1.0 / p.r_c : 0.0;
-  c.r_in = p.r_in;
-  c.h_over_r = p.h_over_r;
-  c.vg_fac = sqrt(1.0 - 2.0 * p.eta);
-  c.kexp = p.kdrag_exp;
-  c.mfp_coef = p.mfp_coef;
-  c.rc_norm = p.r_c > 0.0 ? pow(1.0 / p.r_c, 2.0 - p.gamma) : 0.0;
-  return c;
-}
+// DragConst and make_drag_const live in mx_internal.h (host and device).
 
 __device__ __forceinline__ double pow_kexp(double b, double kexp) {
   if (kexp == -2.0) return 1.0 / (b * b);

@@ -178,10 +178,11 @@ constexpr int kPlanLds = 2048;   // pairs handled in LDS; larger lists use globa
 //     of the big bodies flagged with j, plus j (only j kept).
 // gkeys: [2*cap] int64 global scratch; gidx: [2*cap] int32 global scratch.
 // uf: [2*nb] with par[b] = b and inbig[b] = 0 at rest (restored on exit).
-__global__ __launch_bounds__(kPlanThreads) void k_plan(
-    int nb, int32_t* __restrict__ pairs, int32_t cap, int64_t* __restrict__ gkeys,
-    int32_t* __restrict__ gidx, int32_t* __restrict__ uf, Subsystem* __restrict__ subs,
-    int32_t cap_subs, DevScalars* __restrict__ dsc, int sort_only) {
+__device__ __forceinline__ void plan_block(int nb, int32_t* __restrict__ pairs, int32_t cap,
+                                           int64_t* __restrict__ gkeys,
+                                           int32_t* __restrict__ gidx, int32_t* __restrict__ uf,
+                                           Subsystem* __restrict__ subs, int32_t cap_subs,
+                                           DevScalars* __restrict__ dsc, int sort_only) {
   __shared__ int64_t lk[kPlanLds];
   __shared__ int64_t ls[kPlanLds];
   __shared__ int32_t lbb[kPlanLds];
@@ -344,6 +345,20 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(
     inbig[key_lo(k)] = 0;
   }
   if (tid == 0) dsc->n_sub = min(nbig_sub + ng, cap_subs);
+}
+
+__global__ __launch_bounds__(kPlanThreads) void k_plan(
+    int nb, int32_t* __restrict__ pairs, int32_t cap, int64_t* __restrict__ gkeys,
+    int32_t* __restrict__ gidx, int32_t* __restrict__ uf, Subsystem* __restrict__ subs,
+    int32_t cap_subs, DevScalars* __restrict__ dsc, int sort_only) {
+  plan_block(nb, pairs, cap, gkeys, gidx, uf, subs, cap_subs, dsc, sort_only);
+}
+
+// one block per system of the descriptor table
+__global__ __launch_bounds__(kPlanThreads) void k_plan_sys(const SysDesc* __restrict__ desc) {
+  const SysDesc& D = desc[blockIdx.x];
+  if (D.nb == 0) return;
+  plan_block(D.nb, D.pairs, D.cap_pairs, D.keys, D.plan_idx, D.uf, D.subs, D.cap_subs, D.dsc, 0);
 }
 
 // ------------------------------------------------------------------ BS
@@ -589,15 +604,20 @@ __device__ __forceinline__ void run_column(int col, double H, int m, int np,
 // each): most steps are accepted in the first round, and the table rows do not
 // depend on later rows, so the accepted column is the one a sequential
 // integrator would stop at.
-__global__ __launch_bounds__(64) void k_bs(int n, int nb, double mu0, double h, double tol,
-                                           const double* __restrict__ x0s,
-                                           const double* __restrict__ u0s,
-                                           double* __restrict__ x, double* __restrict__ u,
-                                           const double* __restrict__ mu,
-                                           const double* __restrict__ rcrit,
-                                           const Subsystem* __restrict__ subs,
-                                           DevScalars* __restrict__ dsc,
-                                           double* __restrict__ bigmid) {
+__global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc) {
+  const SysDesc& D = desc[blockIdx.y];
+  const int n = D.n, nb = D.nb;
+  const double mu0 = D.mu0, h = D.h, tol = D.bs_tol;
+  const double* __restrict__ x0s = D.x0;
+  const double* __restrict__ u0s = D.u0;
+  double* __restrict__ x = D.x;
+  double* __restrict__ u = D.u;
+  const double* __restrict__ mu = D.mu;
+  const double* __restrict__ rcrit = D.rcrit;
+  const Subsystem* __restrict__ subs = D.subs;
+  DevScalars* __restrict__ dsc = D.dsc;
+  double* __restrict__ bigmid = D.bigmid;
+  if (nb == 0) return;
   __shared__ Subsystem S;
   __shared__ double xs[3 * kM], vs[3 * kM], mum[kM], rcm[kM], scal[2 * kM];
   __shared__ double res[kC][6 * kM];
@@ -756,16 +776,15 @@ hipError_t launch_flag(mx_system* s) {
                   &s->dsc->err);
 }
 
-hipError_t launch_plan(mx_system* s) {
-  if (s->nb == 0) return hipSuccess;
-  return mxlaunch(s, k_plan, dim3(1), dim3(kPlanThreads), s->nb, s->pairs, s->cap_pairs,
-                  (int64_t*)s->pairs_tmp, s->plan_idx, s->uf, s->subs, s->cap_subs, s->dsc, 0);
+hipError_t launch_plan_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys) {
+  if (n_sys <= 0) return hipSuccess;
+  return mxlaunch_on(st, tm, k_plan_sys, dim3(n_sys), dim3(kPlanThreads), desc);
 }
 
-hipError_t launch_bs(mx_system* s) {
-  if (s->nb == 0) return hipSuccess;
-  return mxlaunch(s, k_bs, dim3(512), dim3(64), s->n, s->nb, s->mu0, s->p.dt, s->p.bs_tol,
-                  s->x0, s->u0, s->x, s->u, s->mu, s->rcrit, s->subs, s->dsc, s->bigmid);
+hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys,
+                         int bps) {
+  if (n_sys <= 0 || bps <= 0) return hipSuccess;
+  return mxlaunch_on(st, tm, k_bs, dim3(bps, n_sys), dim3(64), desc);
 }
 
 // flag + sort for the stateless entry; fpack built from the given states

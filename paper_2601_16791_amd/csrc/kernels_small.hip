@@ -1,18 +1,24 @@
 // Fused step kernels for systems with few massive bodies (n_big <= 64), the
 // embryo-disk regime: massless planetesimals that feel a handful of embryos.
+// Both kernels walk a table of tiles (system, first body), so one launch steps
+// one system or a whole batch of independent systems with the same code.
 //
-//   k_step_a_small : every block first advances the massive bodies itself (half
-//                    kick, jump, Kepler drift: the same few bodies in every block,
-//                    with identical arithmetic) and keeps them in LDS; then each
-//                    thread takes one body through drag, half kick, jump and drift
-//                    and tests it against the massive bodies for close encounters
-//                    (Hermite minimum separation) with the sources read from LDS.
-//   k_step_b_small : jump by the massive-body momentum after the encounter
-//                    integrator, changeover-weighted gravity from the massive
-//                    bodies held in LDS, gas drag and the closing half kick.
+//   k_step_a : the block first advances the massive bodies of the tile's system
+//              itself (half kick, jump, Kepler drift: the same few bodies in every
+//              block, with identical arithmetic) and keeps them in LDS; then each
+//              thread takes one body through drag, half kick, jump and drift and
+//              tests it against the massive bodies for close encounters (Hermite
+//              minimum separation) with the sources read from LDS.
+//   k_step_b : jump by the massive-body momentum after the encounter integrator,
+//              changeover-weighted gravity from the massive bodies held in LDS,
+//              gas drag and the closing half kick.
 //
 // Between the two run the encounter planner and the Bulirsch-Stoer kernel.  Four
 // launches per step instead of six, and no packed-source round trip through HBM.
+// A block takes tpb consecutive tiles (persistent over them) and redoes the
+// massive-body phase only when the system changes.  Per body the arithmetic does
+// not depend on the tile shape: the block sums run over at most 64 massive bodies,
+// one per thread, with the same pairing for every block size >= 64.
 #include <hip/hip_runtime.h>
 
 #include "device_math.h"
@@ -20,8 +26,6 @@
 #include "mx_internal.h"
 
 namespace {
-
-constexpr int kBlock = 256;
 
 using mxd::DragConst;
 
@@ -51,23 +55,22 @@ __device__ __forceinline__ bool advance_body(int t, int nb, double mu0, double h
   return mxd::kepler_drift(mu0, h, q[0], q[1], q[2], w[0], w[1], w[2]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_step_a_small(
-    int n, int nb, double mu0, double h, DragConst dc, int gas_on, double* __restrict__ x,
-    double* __restrict__ u, const double* __restrict__ ag, double* __restrict__ x0s,
-    double* __restrict__ u0s, const double* __restrict__ mu, const double* __restrict__ rcrit,
-    const double* __restrict__ r_p, const double* __restrict__ rho_p,
-    int32_t* __restrict__ pairs, int32_t cap, DevScalars* __restrict__ dsc,
-    const double* __restrict__ bigsnap, double* __restrict__ bigmid) {
-  __shared__ double sh[6 * kBlock];
-  __shared__ double bst[12][kSmallBig];  // x0 (3) u0 (3) x1 (3) u1 (3) of the big bodies
-  __shared__ double brc[kSmallBig];
+// Massive bodies of system D for a block: half kick, jump and drift of every
+// massive body (identical arithmetic in every block), kept in LDS.  Returns the
+// momentum sums through Ppre / Ppost.  `first` latches a failure once per system.
+template <int BLK>
+__device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double* sh,
+                                            double (*bst)[kSmallBig], double* brc,
+                                            double (&Ppre)[3], double (&Ppost)[3]) {
   const int tid = threadIdx.x;
-  const double hh = 0.5 * h;
-  // massive bodies from the step-start snapshot (block 0 overwrites x, u of the
-  // massive bodies while other blocks may still be reading)
+  const int nb = D.nb;
+  const double hh = 0.5 * D.h;
+  const double* bigsnap = D.bigsnap;
+  // massive bodies from the step-start snapshot (the owner tile overwrites x, u
+  // of the massive bodies while other blocks may still be reading)
   double vsum[6] = {0, 0, 0, 0, 0, 0};
-  for (int k = tid; k < nb; k += kBlock) {
-    double m = mu[k];
+  for (int k = tid; k < nb; k += BLK) {
+    double m = D.mu[k];
     double ux = bigsnap[3 * nb + k], uy = bigsnap[4 * nb + k], uz = bigsnap[5 * nb + k];
     vsum[0] += m * ux;
     vsum[1] += m * uy;
@@ -76,9 +79,11 @@ __global__ __launch_bounds__(kBlock) void k_step_a_small(
     vsum[4] += m * (uy + hh * (bigsnap[7 * nb + k] + 0.0));
     vsum[5] += m * (uz + hh * (bigsnap[8 * nb + k] + 0.0));
   }
-  mxd::block_sum<kBlock, 6>(vsum, sh);
-  const double Ppre[3] = {vsum[0], vsum[1], vsum[2]};
-  const double Ppost[3] = {vsum[3], vsum[4], vsum[5]};
+  mxd::block_sum<BLK, 6>(vsum, sh);
+  for (int c = 0; c < 3; ++c) {
+    Ppre[c] = vsum[c];
+    Ppost[c] = vsum[3 + c];
+  }
   if (tid < nb) {
     double p[3], v[3], a[3], q[3], w[3];
     for (int c = 0; c < 3; ++c) {
@@ -86,193 +91,255 @@ __global__ __launch_bounds__(kBlock) void k_step_a_small(
       v[c] = bigsnap[(3 + c) * nb + tid];
       a[c] = bigsnap[(6 + c) * nb + tid];
     }
-    bool ok = advance_body(tid, nb, mu0, h, dc, gas_on, r_p, rho_p, Ppre, Ppost, p, v, a, q, w);
-    if (!ok && blockIdx.x == 0) atomicOr(&dsc->err, MXE_NOCONV);
+    bool ok = advance_body(tid, nb, D.mu0, D.h, D.dc, D.gas_on, D.r_p, D.rho_p, Ppre, Ppost, p,
+                           v, a, q, w);
+    if (!ok && first) atomicOr(&D.dsc->err, MXE_NOCONV);
     for (int c = 0; c < 3; ++c) {
       bst[c][tid] = p[c];
       bst[3 + c][tid] = v[c];
       bst[6 + c][tid] = q[c];
       bst[9 + c][tid] = w[c];
     }
-    brc[tid] = rcrit[tid];
+    brc[tid] = D.rcrit[tid];
   }
-  __syncthreads();
-  const int t = blockIdx.x * kBlock + tid;
-  if (t >= n) return;
-  double p[3], v[3], q[3], w[3];
-  if (t < nb) {
-    for (int c = 0; c < 3; ++c) {
-      p[c] = bst[c][t];
-      v[c] = bst[3 + c][t];
-      q[c] = bst[6 + c][t];
-      w[c] = bst[9 + c][t];
+}
+
+// First half of the fused step over a tile table: per tile, drag + half kick +
+// jump + Kepler drift of its bodies and the encounter test against the massive
+// bodies.  A block takes `tpb` consecutive tiles and redoes the massive-body
+// phase only when the system changes.
+template <int BLK>
+__global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc,
+                                                const Tile* __restrict__ tiles, int n_tiles,
+                                                int tpb) {
+  __shared__ double sh[6 * BLK];
+  __shared__ double bst[12][kSmallBig];  // x0 (3) u0 (3) x1 (3) u1 (3) of the big bodies
+  __shared__ double brc[kSmallBig];
+  const int tid = threadIdx.x;
+  const int t_lo = blockIdx.x * tpb;
+  const int t_hi = min(n_tiles, t_lo + tpb);
+  int cur = -1;
+  double Ppre[3], Ppost[3];
+  for (int ti = t_lo; ti < t_hi; ++ti) {
+    const Tile tl = tiles[ti];
+    const SysDesc& D = desc[tl.sys];
+    if (tl.sys != cur) {
+      __syncthreads();  // the previous tile is done with the LDS copies
+      big_phase_a<BLK>(D, tl.first == 0, sh, bst, brc, Ppre, Ppost);
+      __syncthreads();
+      cur = tl.sys;
+    }
+    const int n = D.n, nb = D.nb;
+    const double h = D.h;
+    const int t = tl.first + tid;
+    if (t >= n) continue;
+    double p[3], v[3], q[3], w[3];
+    if (t < nb) {
+      for (int c = 0; c < 3; ++c) {
+        p[c] = bst[c][t];
+        v[c] = bst[3 + c][t];
+        q[c] = bst[6 + c][t];
+        w[c] = bst[9 + c][t];
+      }
+      for (int c = 0; c < 3; ++c) {
+        D.bigmid[c * nb + t] = q[c];
+        D.bigmid[(3 + c) * nb + t] = w[c];
+      }
+    } else {
+      double a[3];
+      for (int c = 0; c < 3; ++c) {
+        p[c] = D.x[c * n + t];
+        v[c] = D.u[c * n + t];
+        a[c] = D.ag[c * n + t];
+      }
+      if (!advance_body(t, nb, D.mu0, h, D.dc, D.gas_on, D.r_p, D.rho_p, Ppre, Ppost, p, v, a, q,
+                        w))
+        atomicOr(&D.dsc->err, MXE_NOCONV);
     }
     for (int c = 0; c < 3; ++c) {
-      bigmid[c * nb + t] = q[c];
-      bigmid[(3 + c) * nb + t] = w[c];
+      D.x0[c * n + t] = p[c];
+      D.u0[c * n + t] = v[c];
+      D.x[c * n + t] = q[c];
+      D.u[c * n + t] = w[c];
     }
-  } else {
-    double a[3];
-    for (int c = 0; c < 3; ++c) {
-      p[c] = x[c * n + t];
-      v[c] = u[c * n + t];
-      a[c] = ag[c * n + t];
-    }
-    if (!advance_body(t, nb, mu0, h, dc, gas_on, r_p, rho_p, Ppre, Ppost, p, v, a, q, w))
-      atomicOr(&dsc->err, MXE_NOCONV);
-  }
-  for (int c = 0; c < 3; ++c) {
-    x0s[c * n + t] = p[c];
-    u0s[c * n + t] = v[c];
-    x[c * n + t] = q[c];
-    u[c * n + t] = w[c];
-  }
-  // encounter test against every massive body i < t (same bound and exact
-  // Hermite test as the general flag kernel)
-  const double rct = t < nb ? brc[t] : 0.0;
-  const int imax = t < nb ? t : nb;
-  const double k427 = (4.0 / 27.0) * fabs(h);
-  for (int i = 0; i < imax; ++i) {
-    double r0[3], w0[3], w1[3], dd[3];
-    for (int c = 0; c < 3; ++c) {
-      r0[c] = p[c] - bst[c][i];
-      w0[c] = v[c] - bst[3 + c][i];
-      w1[c] = w[c] - bst[9 + c][i];
-      dd[c] = (q[c] - p[c]) - (bst[6 + c][i] - bst[c][i]);
-    }
-    double m0 = fma(r0[2], r0[2], fma(r0[1], r0[1], r0[0] * r0[0]));
-    double nd = fmax(fmax(fabs(dd[0]), fabs(dd[1])), fabs(dd[2]));
-    double nw = fmax(fmax(fabs(w0[0]), fabs(w0[1])), fabs(w0[2])) +
-                fmax(fmax(fabs(w1[0]), fabs(w1[1])), fabs(w1[2]));
-    double rc = fmax(brc[i], rct);
-    double bound = rc + 1.7320508075688773 * fma(k427, nw, nd) * (1.0 + 1e-12);
-    if (__builtin_expect(m0 <= bound * bound * (1.0 + 1e-12), 0)) {
-      double r1[3];
-      for (int c = 0; c < 3; ++c) r1[c] = q[c] - bst[6 + c][i];
-      double dmin = mxd::hermite_dmin2(r0[0], r0[1], r0[2], w0[0], w0[1], w0[2], r1[0], r1[1],
-                                       r1[2], w1[0], w1[1], w1[2], h);
-      if (dmin <= rc * rc) {
-        int idx = atomicAdd(&dsc->n_pairs, 1);
-        if (idx < cap) {
-          pairs[2 * idx] = i;
-          pairs[2 * idx + 1] = t;
-        } else {
-          atomicOr(&dsc->err, MXE_PAIRS);
+    // encounter test against every massive body i < t (same bound and exact
+    // Hermite test as the general flag kernel)
+    const double rct = t < nb ? brc[t] : 0.0;
+    const int imax = t < nb ? t : nb;
+    const double k427 = (4.0 / 27.0) * fabs(h);
+    for (int i = 0; i < imax; ++i) {
+      double r0[3], w0[3], w1[3], dd[3];
+      for (int c = 0; c < 3; ++c) {
+        r0[c] = p[c] - bst[c][i];
+        w0[c] = v[c] - bst[3 + c][i];
+        w1[c] = w[c] - bst[9 + c][i];
+        dd[c] = (q[c] - p[c]) - (bst[6 + c][i] - bst[c][i]);
+      }
+      double m0 = fma(r0[2], r0[2], fma(r0[1], r0[1], r0[0] * r0[0]));
+      double nd = fmax(fmax(fabs(dd[0]), fabs(dd[1])), fabs(dd[2]));
+      double nw = fmax(fmax(fabs(w0[0]), fabs(w0[1])), fabs(w0[2])) +
+                  fmax(fmax(fabs(w1[0]), fabs(w1[1])), fabs(w1[2]));
+      double rc = fmax(brc[i], rct);
+      double bound = rc + 1.7320508075688773 * fma(k427, nw, nd) * (1.0 + 1e-12);
+      if (__builtin_expect(m0 <= bound * bound * (1.0 + 1e-12), 0)) {
+        double r1[3];
+        for (int c = 0; c < 3; ++c) r1[c] = q[c] - bst[6 + c][i];
+        double dmin = mxd::hermite_dmin2(r0[0], r0[1], r0[2], w0[0], w0[1], w0[2], r1[0], r1[1],
+                                         r1[2], w1[0], w1[1], w1[2], h);
+        if (dmin <= rc * rc) {
+          int idx = atomicAdd(&D.dsc->n_pairs, 1);
+          if (idx < D.cap_pairs) {
+            D.pairs[2 * idx] = i;
+            D.pairs[2 * idx + 1] = t;
+          } else {
+            atomicOr(&D.dsc->err, MXE_PAIRS);
+          }
         }
       }
     }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_step_b_small(
-    int n, int nb, double mu0, double hh, DragConst dc, int gas_on, int kick,
-    double* __restrict__ x, double* __restrict__ u, double* __restrict__ ag,
-    const double* __restrict__ mu, const double* __restrict__ rcrit,
-    const double* __restrict__ r_p, const double* __restrict__ rho_p,
-    DevScalars* __restrict__ dsc, const double* __restrict__ bigmid,
-    double* __restrict__ bigsnap) {
-  __shared__ double sh[3 * kBlock];
+// Second half of the fused step over a tile table: jump by the massive-body
+// momentum after the encounter integrator, changeover-weighted gravity from the
+// massive bodies held in LDS, gas drag and (kick != 0) the closing half kick.
+template <int BLK>
+__global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc,
+                                                const Tile* __restrict__ tiles, int n_tiles,
+                                                int tpb, int kick) {
+  __shared__ double sh[3 * BLK];
   __shared__ KickSource src[kSmallBig];
   const int tid = threadIdx.x;
-  // massive bodies after drift and encounters from their snapshot (block 0
-  // overwrites x, u of the massive bodies while other blocks may still read)
-  double P[3] = {0, 0, 0};
-  for (int k = tid; k < nb; k += kBlock) {
-    double m = mu[k];
-    P[0] += m * bigmid[3 * nb + k];
-    P[1] += m * bigmid[4 * nb + k];
-    P[2] += m * bigmid[5 * nb + k];
-  }
-  mxd::block_sum<kBlock, 3>(P, sh);
-  const double J[3] = {hh * P[0] / mu0, hh * P[1] / mu0, hh * P[2] / mu0};
-  if (tid < nb) {
-    KickSource k;
-    double rc = rcrit[tid];
-    k.x = bigmid[tid] + J[0];
-    k.y = bigmid[nb + tid] + J[1];
-    k.z = bigmid[2 * nb + tid] + J[2];
-    k.mu = mu[tid];
-    k.rc2 = fmax(rc * rc, 1e-300);
-    k.rc = rc;
-    k.pad0 = k.pad1 = 0.0;
-    src[tid] = k;
-  }
-  if (blockIdx.x == 0 && tid == 0) {
-    dsc->P[0] = P[0];
-    dsc->P[1] = P[1];
-    dsc->P[2] = P[2];
-    if (kick) {
-      dsc->step += 1;
-      dsc->n_pairs = 0;  // the encounter list of this step has been planned
+  const int t_lo = blockIdx.x * tpb;
+  const int t_hi = min(n_tiles, t_lo + tpb);
+  int cur = -1;
+  double P[3], J[3];
+  for (int ti = t_lo; ti < t_hi; ++ti) {
+    const Tile tl = tiles[ti];
+    const SysDesc& D = desc[tl.sys];
+    const int n = D.n, nb = D.nb;
+    const double hh = 0.5 * D.h, mu0 = D.mu0;
+    if (tl.sys != cur) {
+      __syncthreads();  // the previous tile is done with the LDS sources
+      // massive bodies after drift and encounters from their snapshot (the owner
+      // tile overwrites x, u of the massive bodies while other blocks may read)
+      for (int c = 0; c < 3; ++c) P[c] = 0.0;
+      for (int k = tid; k < nb; k += BLK) {
+        double m = D.mu[k];
+        P[0] += m * D.bigmid[3 * nb + k];
+        P[1] += m * D.bigmid[4 * nb + k];
+        P[2] += m * D.bigmid[5 * nb + k];
+      }
+      mxd::block_sum<BLK, 3>(P, sh);
+      for (int c = 0; c < 3; ++c) J[c] = hh * P[c] / mu0;
+      if (tid < nb) {
+        KickSource k;
+        double rc = D.rcrit[tid];
+        k.x = D.bigmid[tid] + J[0];
+        k.y = D.bigmid[nb + tid] + J[1];
+        k.z = D.bigmid[2 * nb + tid] + J[2];
+        k.mu = D.mu[tid];
+        k.rc2 = fmax(rc * rc, 1e-300);
+        k.rc = rc;
+        k.pad0 = k.pad1 = 0.0;
+        src[tid] = k;
+      }
+      __syncthreads();
+      cur = tl.sys;
+    }
+    if (tl.first == 0 && tid == 0) {
+      D.dsc->P[0] = P[0];
+      D.dsc->P[1] = P[1];
+      D.dsc->P[2] = P[2];
+      if (kick) {
+        D.dsc->step += 1;
+        D.dsc->n_pairs = 0;  // the encounter list of this step has been planned
+      }
+    }
+    const int t = tl.first + tid;
+    if (t >= n) continue;
+    double* __restrict__ x = D.x;
+    double* __restrict__ u = D.u;
+    double* __restrict__ ag = D.ag;
+    const double px = x[t] + J[0], py = x[n + t] + J[1], pz = x[2 * n + t] + J[2];
+    x[t] = px;
+    x[n + t] = py;
+    x[2 * n + t] = pz;
+    const double rct = t < nb ? src[t].rc : 0.0;
+    const double rc2t = rct * rct;
+    double k15, k1875;
+    mxd::vgpr_constants(k15, k1875);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int s = 0; s < nb; ++s) {
+      const KickSource S = src[s];
+      double dx = S.x - px, dy = S.y - py, dz = S.z - pz;
+      double s2 = fma(dz, dz, fma(dy, dy, dx * dx));
+      double rc2 = fmax(S.rc2, rc2t);
+      double wgt = mxd::fast_weight(S.mu, s2, k15, k1875);
+      if (s2 < rc2) wgt = S.mu * mxd::changeover_weight_slow(s2, fmax(S.rc, rct), rc2);
+      a0 = fma(wgt, dx, a0);
+      a1 = fma(wgt, dy, a1);
+      a2 = fma(wgt, dz, a2);
+    }
+    ag[t] = a0;
+    ag[n + t] = a1;
+    ag[2 * n + t] = a2;
+    if (!kick) continue;
+    double vx = u[t], vy = u[n + t], vz = u[2 * n + t];
+    double adx = 0.0, ady = 0.0, adz = 0.0;
+    if (t >= nb && D.gas_on) {
+      int j = t - nb;
+      mxd::gas_drag(D.dc, px, py, vx + P[0] / mu0, vy + P[1] / mu0, vz + P[2] / mu0, D.r_p[j],
+                    D.rho_p[j], adx, ady, adz);
+    }
+    vx += hh * (a0 + adx);
+    vy += hh * (a1 + ady);
+    vz += hh * (a2 + adz);
+    u[t] = vx;
+    u[n + t] = vy;
+    u[2 * n + t] = vz;
+    if (!isfinite(vx + vy + vz + px + py + pz)) atomicOr(&D.dsc->err, MXE_NONFINITE);
+    if (t < nb) {
+      double* bigsnap = D.bigsnap;
+      bigsnap[t] = px; bigsnap[nb + t] = py; bigsnap[2 * nb + t] = pz;
+      bigsnap[3 * nb + t] = vx; bigsnap[4 * nb + t] = vy; bigsnap[5 * nb + t] = vz;
+      bigsnap[6 * nb + t] = a0; bigsnap[7 * nb + t] = a1; bigsnap[8 * nb + t] = a2;
     }
   }
-  __syncthreads();
-  const int t = blockIdx.x * kBlock + tid;
-  if (t >= n) return;
-  const double px = x[t] + J[0], py = x[n + t] + J[1], pz = x[2 * n + t] + J[2];
-  x[t] = px;
-  x[n + t] = py;
-  x[2 * n + t] = pz;
-  const double rct = t < nb ? src[t].rc : 0.0;
-  const double rc2t = rct * rct;
-  double k15, k1875;
-  mxd::vgpr_constants(k15, k1875);
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int s = 0; s < nb; ++s) {
-    const KickSource S = src[s];
-    double dx = S.x - px, dy = S.y - py, dz = S.z - pz;
-    double s2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    double rc2 = fmax(S.rc2, rc2t);
-    double wgt = mxd::fast_weight(S.mu, s2, k15, k1875);
-    if (s2 < rc2) wgt = S.mu * mxd::changeover_weight_slow(s2, fmax(S.rc, rct), rc2);
-    a0 = fma(wgt, dx, a0);
-    a1 = fma(wgt, dy, a1);
-    a2 = fma(wgt, dz, a2);
-  }
-  ag[t] = a0;
-  ag[n + t] = a1;
-  ag[2 * n + t] = a2;
-  if (!kick) return;
-  double vx = u[t], vy = u[n + t], vz = u[2 * n + t];
-  double adx = 0.0, ady = 0.0, adz = 0.0;
-  if (t >= nb && gas_on) {
-    int j = t - nb;
-    mxd::gas_drag(dc, px, py, vx + P[0] / mu0, vy + P[1] / mu0, vz + P[2] / mu0, r_p[j], rho_p[j],
-                  adx, ady, adz);
-  }
-  vx += hh * (a0 + adx);
-  vy += hh * (a1 + ady);
-  vz += hh * (a2 + adz);
-  u[t] = vx;
-  u[n + t] = vy;
-  u[2 * n + t] = vz;
-  if (!isfinite(vx + vy + vz + px + py + pz)) atomicOr(&dsc->err, MXE_NONFINITE);
-  if (t < nb) {
-    bigsnap[t] = px; bigsnap[nb + t] = py; bigsnap[2 * nb + t] = pz;
-    bigsnap[3 * nb + t] = vx; bigsnap[4 * nb + t] = vy; bigsnap[5 * nb + t] = vz;
-    bigsnap[6 * nb + t] = a0; bigsnap[7 * nb + t] = a1; bigsnap[8 * nb + t] = a2;
-  }
 }
-
-int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
 }  // namespace
 
 namespace mxk {
 
-hipError_t launch_step_a_small(mx_system* s) {
-  mxd::DragConst dc = mxd::make_drag_const(s->p);
-  return mxlaunch(s, k_step_a_small, dim3(blocks_for(s->n)), dim3(kBlock), s->n,
-                  s->nb, s->mu0, s->p.dt, dc, s->p.gas_on, s->x, s->u, s->ag, s->x0, s->u0,
-                  s->mu, s->rcrit, s->r_p, s->rho_p, s->pairs, s->cap_pairs, s->dsc,
-                  s->bigsnap, s->bigmid);
+hipError_t launch_step_a_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
+                               const Tile* tiles, int n_tiles, int blk, int tpb) {
+  if (n_tiles <= 0) return hipSuccess;
+  const dim3 grid((n_tiles + tpb - 1) / tpb);
+  switch (blk) {
+    case 64: return mxlaunch_on(st, tm, k_step_a<64>, grid, dim3(64), desc, tiles, n_tiles, tpb);
+    case 128: return mxlaunch_on(st, tm, k_step_a<128>, grid, dim3(128), desc, tiles, n_tiles, tpb);
+    case 256: return mxlaunch_on(st, tm, k_step_a<256>, grid, dim3(256), desc, tiles, n_tiles, tpb);
+    case 512: return mxlaunch_on(st, tm, k_step_a<512>, grid, dim3(512), desc, tiles, n_tiles, tpb);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-hipError_t launch_step_b_small(mx_system* s, int kick) {
-  mxd::DragConst dc = mxd::make_drag_const(s->p);
-  return mxlaunch(s, k_step_b_small, dim3(blocks_for(s->n)), dim3(kBlock), s->n,
-                  s->nb, s->mu0, 0.5 * s->p.dt, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->mu,
-                  s->rcrit, s->r_p, s->rho_p, s->dsc, s->bigmid, s->bigsnap);
+hipError_t launch_step_b_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
+                               const Tile* tiles, int n_tiles, int blk, int tpb, int kick) {
+  if (n_tiles <= 0) return hipSuccess;
+  const dim3 grid((n_tiles + tpb - 1) / tpb);
+  switch (blk) {
+    case 64:
+      return mxlaunch_on(st, tm, k_step_b<64>, grid, dim3(64), desc, tiles, n_tiles, tpb, kick);
+    case 128:
+      return mxlaunch_on(st, tm, k_step_b<128>, grid, dim3(128), desc, tiles, n_tiles, tpb, kick);
+    case 256:
+      return mxlaunch_on(st, tm, k_step_b<256>, grid, dim3(256), desc, tiles, n_tiles, tpb, kick);
+    case 512:
+      return mxlaunch_on(st, tm, k_step_b<512>, grid, dim3(512), desc, tiles, n_tiles, tpb, kick);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace mxk

@@ -61,6 +61,46 @@ hipError_t copy_out(void* dst, const void* src, size_t bytes, int is_dev, hipStr
                         st);
 }
 
+constexpr int kTileBlk = 256;   // bodies per tile of a single system's fused kernels
+constexpr int kBsBlocks = 512;  // encounter-integrator blocks of a single system
+
+SysDesc make_desc(const mx_system* s) {
+  SysDesc d;
+  std::memset((void*)&d, 0, sizeof(d));
+  d.x = s->x;
+  d.u = s->u;
+  d.ag = s->ag;
+  d.x0 = s->x0;
+  d.u0 = s->u0;
+  d.mu = s->mu;
+  d.rcrit = s->rcrit;
+  d.r_p = s->r_p;
+  d.rho_p = s->rho_p;
+  d.bigsnap = s->bigsnap;
+  d.bigmid = s->bigmid;
+  d.pairs = s->pairs;
+  d.keys = reinterpret_cast<int64_t*>(s->pairs_tmp);
+  d.plan_idx = s->plan_idx;
+  d.uf = s->uf;
+  d.subs = s->subs;
+  d.dsc = s->dsc;
+  d.dc = mxd::make_drag_const(s->p);
+  d.mu0 = s->mu0;
+  d.h = s->p.dt;
+  d.bs_tol = s->p.bs_tol;
+  d.n = s->n;
+  d.nb = s->nb;
+  d.cap_pairs = s->cap_pairs;
+  d.cap_subs = s->cap_subs;
+  d.gas_on = s->p.gas_on;
+  return d;
+}
+
+// tiles of blk consecutive bodies of system `sys` (n bodies), appended to out
+void append_tiles(std::vector<Tile>& out, int sys, int n, int blk) {
+  for (int f = 0; f < n; f += blk) out.push_back(Tile{sys, f});
+}
+
 void free_system(mx_system* s) {
   if (!s) return;
   if (s->graph_ok) (void)hipGraphExecDestroy(s->graph);
@@ -68,7 +108,8 @@ void free_system(mx_system* s) {
   delete[] s->tev_pool;
   void* ptrs[] = {s->x, s->u, s->ag, s->x0, s->u0, s->mu, s->rcrit, s->mu_init, s->rcrit_init,
                   s->growth, s->r_p, s->rho_p, s->bigsnap, s->bigmid, s->kpack, s->fpack, s->part,
-                  s->pairs, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red};
+                  s->pairs, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red,
+                  s->desc, s->tiles};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -81,12 +122,20 @@ hipError_t launch_group(mx_system* s, int k) {
   switch (k) {
     case MX_K_GROWTH: return mxk::launch_growth(s);
     case MX_K_KICK_JUMP_DRIFT:
-      return small ? mxk::launch_step_a_small(s) : mxk::launch_kick_jump_drift(s);
+      return small ? mxk::launch_step_a_tiles(s->stream, &s->tev, s->desc, s->tiles, s->n_tiles,
+                                              kTileBlk, 1)
+                   : mxk::launch_kick_jump_drift(s);
     case MX_K_FLAG: return small ? hipSuccess : mxk::launch_flag(s);
-    case MX_K_PLAN: return mxk::launch_plan(s);
-    case MX_K_BS: return mxk::launch_bs(s);
+    case MX_K_PLAN:
+      return s->nb > 0 ? mxk::launch_plan_sys(s->stream, &s->tev, s->desc, 1) : hipSuccess;
+    case MX_K_BS:
+      return s->nb > 0 ? mxk::launch_bs_sys(s->stream, &s->tev, s->desc, 1, kBsBlocks)
+                       : hipSuccess;
     case MX_K_JUMP_PACK: return small ? hipSuccess : mxk::launch_jump_pack(s);
-    default: return small ? mxk::launch_step_b_small(s, 1) : mxk::launch_force_kick(s, 1);
+    default:
+      return small ? mxk::launch_step_b_tiles(s->stream, &s->tev, s->desc, s->tiles, s->n_tiles,
+                                              kTileBlk, 1, 1)
+                   : mxk::launch_force_kick(s, 1);
   }
 }
 
@@ -184,6 +233,8 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   ALLOC(s->pairs, 2 * (size_t)s->cap_pairs) ALLOC(s->pairs_tmp, 4 * (size_t)s->cap_pairs)
   ALLOC(s->plan_idx, 2 * (size_t)s->cap_pairs)
   ALLOC(s->subs, s->cap_subs) ALLOC(s->uf, 2 * (size_t)nb) ALLOC(s->dsc, 1) ALLOC(s->red, s->red_blocks)
+  s->n_tiles = (s->n + kTileBlk - 1) / kTileBlk;
+  ALLOC(s->desc, 1) ALLOC(s->tiles, s->n_tiles)
 #undef ALLOC
   if (e != hipSuccess) {
     free_system(s);
@@ -201,6 +252,14 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
       return _r;                                             \
     }                                                        \
   } while (0)
+  {
+    SysDesc d = make_desc(s);
+    std::vector<Tile> tl;
+    append_tiles(tl, 0, s->n, kTileBlk);
+    STEP(hipMemcpy(s->desc, &d, sizeof(SysDesc), hipMemcpyHostToDevice), "copy descriptor");
+    STEP(hipMemcpy(s->tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice),
+         "copy tiles");
+  }
   STEP(dalloc(&vh_tmp, n3), "alloc v_h");
   STEP(hipMemsetAsync(s->dsc, 0, sizeof(DevScalars), sm), "memset");
   STEP(hipMemsetAsync(s->ag, 0, sizeof(double) * n3, sm), "memset");
@@ -321,15 +380,15 @@ mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, float* ker
   for (int32_t q = 0; q < n_steps && e == hipSuccess; ++q) {
     for (int k = 0; k < MX_NUM_KERNELS && e == hipSuccess; ++k) {
       if (k == group) {
-        s->tev_armed = true;
-        s->tev_start = ev[2 * q];
-        s->tev_stop = ev[2 * q + 1];
+        s->tev.armed = true;
+        s->tev.start = ev[2 * q];
+        s->tev.stop = ev[2 * q + 1];
       }
       e = launch_group(s, k);
       if (k == group) {
-        used[q] = s->tev_start == nullptr;  // the start event went to a kernel
-        s->tev_armed = false;
-        s->tev_start = s->tev_stop = nullptr;
+        used[q] = s->tev.start == nullptr;  // the start event went to a kernel
+        s->tev.armed = false;
+        s->tev.start = s->tev.stop = nullptr;
       }
     }
   }
@@ -485,7 +544,7 @@ mx_status mx_get_step_index(mx_system* s, int64_t* step_index) {
 }
 
 void mx_destroy(mx_system* s) {
-  if (!s) return;
+  if (!s || s->in_batch) return;
   (void)hipStreamSynchronize(s->stream);
   free_system(s);
 }
@@ -546,6 +605,343 @@ mx_status mx_flag_pairs(int32_t n, int32_t n_big, const double* rcrit, const dou
   *n_out = hd.n_pairs_last;
   if (hd.err) return fail(MX_ECAPACITY, "more flagged pairs than cap");
   return MX_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+struct mx_batch {
+  int32_t n_sys;
+  mx_system** sys;
+  hipStream_t stream;
+  SysDesc* desc;    // device [n_sys]
+  Tile* tiles;      // device, room for the finest tiling (64 bodies per tile)
+  int32_t tiles_cap;
+  int32_t n_tiles;
+  int32_t blk, tpb, bps;
+  int32_t launch_mode, graph_steps;
+  hipGraphExec_t graph;
+  bool graph_ok;
+  LaunchTiming tev;
+};
+
+namespace {
+
+bool valid_config(int blk, int tpb, int bps) {
+  return (blk == 64 || blk == 128 || blk == 256 || blk == 512) && tpb >= 1 && tpb <= 64 &&
+         bps >= 1 && bps <= 1024;
+}
+
+// tile table of the current blk: systems in order, tiles of each system in order
+hipError_t upload_tiles(mx_batch* b) {
+  std::vector<Tile> tl;
+  for (int k = 0; k < b->n_sys; ++k) append_tiles(tl, k, b->sys[k]->n, b->blk);
+  if ((int64_t)tl.size() > b->tiles_cap) return hipErrorInvalidValue;
+  b->n_tiles = (int32_t)tl.size();
+  return hipMemcpy(b->tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice);
+}
+
+hipError_t enqueue_batch_step(mx_batch* b) {
+  hipError_t e;
+  if ((e = mxk::launch_step_a_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles, b->blk,
+                                    b->tpb)) != hipSuccess)
+    return e;
+  if ((e = mxk::launch_plan_sys(b->stream, &b->tev, b->desc, b->n_sys)) != hipSuccess) return e;
+  if ((e = mxk::launch_bs_sys(b->stream, &b->tev, b->desc, b->n_sys, b->bps)) != hipSuccess)
+    return e;
+  return mxk::launch_step_b_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles, b->blk,
+                                  b->tpb, 1);
+}
+
+void drop_graph(mx_batch* b) {
+  if (b->graph_ok) (void)hipGraphExecDestroy(b->graph);
+  b->graph_ok = false;
+}
+
+void free_batch(mx_batch* b) {
+  if (!b) return;
+  drop_graph(b);
+  if (b->sys) {
+    for (int k = 0; k < b->n_sys; ++k)
+      if (b->sys[k]) {
+        b->sys[k]->in_batch = false;
+        mx_destroy(b->sys[k]);
+      }
+    delete[] b->sys;
+  }
+  if (b->desc) (void)hipFree(b->desc);
+  if (b->tiles) (void)hipFree(b->tiles);
+  delete b;
+}
+
+void advance_host_steps(mx_batch* b, int32_t n) {
+  for (int k = 0; k < b->n_sys; ++k) b->sys[k]->host_step += n;
+}
+
+}  // namespace
+
+extern "C" {
+
+mx_status mx_init_batch(int32_t n_sys, const mx_params* params, const int64_t* offsets,
+                        const double* x_h, const double* v_h, const double* m_big,
+                        const double* r_p, const double* rho_p, int is_device_ptr,
+                        void* hip_stream, mx_batch** out) {
+  if (!out) return fail(MX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_sys <= 0 || !params || !offsets || !x_h || !v_h)
+    return fail(MX_EINVAL, "need n_sys > 0, params, offsets, x_h and v_h");
+  if (offsets[0] != 0) return fail(MX_EINVAL, "offsets[0] must be 0");
+  int64_t nbig_total = 0, nsmall_total = 0;
+  bool any_gas = false;
+  for (int k = 0; k < n_sys; ++k) {
+    mx_status st = check_params(&params[k]);
+    if (st != MX_OK) return st;
+    if (params[k].n_big > kSmallBig)
+      return fail(MX_EINVAL, "batched systems need n_big <= 64");
+    if (offsets[k + 1] - offsets[k] != (int64_t)params[k].n_big + params[k].n_small)
+      return fail(MX_EINVAL, "offsets[k+1] - offsets[k] must equal n_big + n_small of system k");
+    nbig_total += params[k].n_big;
+    nsmall_total += params[k].n_small;
+    any_gas |= params[k].gas_on && params[k].n_small > 0;
+  }
+  if (nbig_total > 0 && !m_big) return fail(MX_EINVAL, "m_big is required");
+  if (any_gas && (!r_p || !rho_p)) return fail(MX_EINVAL, "r_p and rho_p are required with gas");
+  const int64_t N = offsets[n_sys];
+  mx_batch* b = new mx_batch();
+  std::memset((void*)b, 0, sizeof(mx_batch));
+  b->n_sys = n_sys;
+  b->stream = (hipStream_t)hip_stream;
+  b->blk = kTileBlk;
+  b->tpb = 1;
+  b->bps = 4;
+  b->graph_steps = 1;
+  b->sys = new mx_system*[n_sys]();
+  // each system from its columns of the concatenated SoA arrays
+  int64_t boff = 0, soff = 0;
+  std::vector<double> hx, hv;
+  double *dx = nullptr, *dv = nullptr;
+  for (int k = 0; k < n_sys; ++k) {
+    const int64_t off = offsets[k], nk = offsets[k + 1] - offsets[k];
+    const double *xs, *vs;
+    hipError_t e = hipSuccess;
+    if (is_device_ptr) {
+      if (dx) (void)hipFree(dx);
+      if (dv) (void)hipFree(dv);
+      dx = dv = nullptr;
+      if ((e = dalloc(&dx, 3 * nk)) == hipSuccess && (e = dalloc(&dv, 3 * nk)) == hipSuccess &&
+          (e = hipMemcpy2DAsync(dx, nk * 8, x_h + off, N * 8, nk * 8, 3,
+                                hipMemcpyDeviceToDevice, b->stream)) == hipSuccess)
+        e = hipMemcpy2DAsync(dv, nk * 8, v_h + off, N * 8, nk * 8, 3, hipMemcpyDeviceToDevice,
+                             b->stream);
+      xs = dx;
+      vs = dv;
+    } else {
+      hx.resize(3 * nk);
+      hv.resize(3 * nk);
+      for (int c = 0; c < 3; ++c)
+        for (int64_t i = 0; i < nk; ++i) {
+          hx[c * nk + i] = x_h[c * N + off + i];
+          hv[c * nk + i] = v_h[c * N + off + i];
+        }
+      xs = hx.data();
+      vs = hv.data();
+    }
+    mx_status st = MX_OK;
+    if (e != hipSuccess) {
+      st = hip_fail(e, "gather system state");
+    } else {
+      const bool gas = params[k].gas_on && params[k].n_small > 0;
+      st = mx_init_system(&params[k], xs, vs, nbig_total ? m_big + boff : nullptr,
+                          gas ? r_p + soff : nullptr, gas ? rho_p + soff : nullptr, nullptr,
+                          is_device_ptr, hip_stream, &b->sys[k]);
+    }
+    if (st != MX_OK) {
+      std::string msg = "system " + std::to_string(k) + ": " + g_err;
+      if (dx) (void)hipFree(dx);
+      if (dv) (void)hipFree(dv);
+      free_batch(b);
+      g_err = msg;
+      return st;
+    }
+    b->sys[k]->in_batch = true;
+    boff += params[k].n_big;
+    soff += params[k].n_small;
+  }
+  if (dx) (void)hipFree(dx);
+  if (dv) (void)hipFree(dv);
+  // descriptor and tile tables
+  std::vector<SysDesc> d(n_sys);
+  int64_t max_tiles = 0;
+  for (int k = 0; k < n_sys; ++k) {
+    d[k] = make_desc(b->sys[k]);
+    max_tiles += (b->sys[k]->n + 63) / 64;
+  }
+  hipError_t e = dalloc(&b->desc, n_sys);
+  if (e == hipSuccess) e = dalloc(&b->tiles, max_tiles);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->desc, d.data(), sizeof(SysDesc) * n_sys, hipMemcpyHostToDevice);
+  b->tiles_cap = (int32_t)max_tiles;
+  if (e == hipSuccess) e = upload_tiles(b);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return hip_fail(e, "batch tables");
+  }
+  *out = b;
+  return MX_OK;
+}
+
+mx_status mx_batch_set_config(mx_batch* b, int32_t blk, int32_t tiles_per_block,
+                              int32_t bs_blocks) {
+  if (!b || !valid_config(blk, tiles_per_block, bs_blocks))
+    return fail(MX_EINVAL, "bad batch or config (blk in {64,128,256,512}, 1 <= tpb <= 64, "
+                           "1 <= bs_blocks <= 1024)");
+  HIPCHK(hipStreamSynchronize(b->stream), "sync");
+  const bool retile = blk != b->blk;
+  b->blk = blk;
+  b->tpb = tiles_per_block;
+  b->bps = bs_blocks;
+  if (retile) HIPCHK(upload_tiles(b), "tile table");
+  drop_graph(b);
+  return MX_OK;
+}
+
+mx_status mx_batch_get_config(mx_batch* b, int32_t* cfg) {
+  if (!b || !cfg) return fail(MX_EINVAL, "NULL argument");
+  cfg[0] = b->blk;
+  cfg[1] = b->tpb;
+  cfg[2] = b->bps;
+  return MX_OK;
+}
+
+mx_status mx_batch_set_launch_mode(mx_batch* b, int32_t mode, int32_t steps_per_graph) {
+  if (!b || (mode != MX_LAUNCH_EAGER && mode != MX_LAUNCH_GRAPH) || steps_per_graph < 1 ||
+      steps_per_graph > 1000)
+    return fail(MX_EINVAL, "bad batch, launch mode or steps per graph (1..1000)");
+  if (mode == MX_LAUNCH_GRAPH && b->stream == nullptr)
+    return fail(MX_EINVAL, "graph launches need a non-default stream");
+  if (steps_per_graph != b->graph_steps) drop_graph(b);
+  b->launch_mode = mode;
+  b->graph_steps = steps_per_graph;
+  return MX_OK;
+}
+
+mx_status mx_step_batch(mx_batch* b, int32_t n_steps) {
+  if (!b || n_steps < 0) return fail(MX_EINVAL, "bad batch or step count");
+  int32_t done = 0;
+  if (b->launch_mode == MX_LAUNCH_GRAPH && n_steps >= b->graph_steps) {
+    if (!b->graph_ok) {
+      hipGraph_t g;
+      HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+      hipError_t e = hipSuccess;
+      for (int q = 0; q < b->graph_steps && e == hipSuccess; ++q) e = enqueue_batch_step(b);
+      hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+      if (e != hipSuccess) return hip_fail(e, "capture batch step");
+      if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+      e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+      b->graph_ok = true;
+    }
+    for (; done + b->graph_steps <= n_steps; done += b->graph_steps)
+      HIPCHK(hipGraphLaunch(b->graph, b->stream), "graph launch");
+  }
+  for (; done < n_steps; ++done) HIPCHK(enqueue_batch_step(b), "batch step launch");
+  advance_host_steps(b, n_steps);
+  return MX_OK;
+}
+
+mx_status mx_batch_autotune(mx_batch* b, int32_t steps_per_candidate, int32_t* steps_taken,
+                            int32_t* cfg_out, float* best_ms) {
+  if (!b || steps_per_candidate < 1 || !steps_taken || !cfg_out || !best_ms)
+    return fail(MX_EINVAL, "bad argument");
+  *steps_taken = 0;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0), "event");
+  HIPCHK(hipEventCreate(&e1), "event");
+  const int saved_mode = b->launch_mode;
+  b->launch_mode = MX_LAUNCH_EAGER;
+  int32_t taken = 0;
+  // time `steps_per_candidate` real steps of the batch under one configuration
+  auto trial = [&](int blk, int tpb, int bps, float* ms) -> mx_status {
+    mx_status st = mx_batch_set_config(b, blk, tpb, bps);
+    if (st != MX_OK) return st;
+    HIPCHK(hipEventRecord(e0, b->stream), "record");
+    for (int q = 0; q < steps_per_candidate; ++q) HIPCHK(enqueue_batch_step(b), "trial step");
+    HIPCHK(hipEventRecord(e1, b->stream), "record");
+    HIPCHK(hipEventSynchronize(e1), "sync");
+    HIPCHK(hipEventElapsedTime(ms, e0, e1), "elapsed");
+    advance_host_steps(b, steps_per_candidate);
+    taken += steps_per_candidate;
+    return MX_OK;
+  };
+  mx_status st = MX_OK;
+  float best = 3.0e38f;
+  int bb = b->blk, bt = b->tpb, bs = b->bps;
+  // tile shape of the body kernels first, then the encounter-integrator width
+  const int blks[] = {64, 128, 256, 512};
+  const int tpbs[] = {1, 2, 4, 8};
+  const int bpss[] = {1, 2, 4, 8, 16};
+  float ms = 0.f;
+  if (st == MX_OK) st = trial(bb, bt, bs, &ms);  // warm-up of the current configuration
+  for (int blk : blks)
+    for (int tpb : tpbs) {
+      if (st != MX_OK) break;
+      st = trial(blk, tpb, bs, &ms);
+      if (st == MX_OK && ms < best) {
+        best = ms;
+        bb = blk;
+        bt = tpb;
+      }
+    }
+  for (int bps : bpss) {
+    if (st != MX_OK) break;
+    st = trial(bb, bt, bps, &ms);
+    if (st == MX_OK && ms <= best) {
+      best = ms;
+      bs = bps;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->launch_mode = saved_mode;
+  *steps_taken = taken;
+  if (st != MX_OK) return st;
+  st = mx_batch_set_config(b, bb, bt, bs);
+  if (st != MX_OK) return st;
+  cfg_out[0] = bb;
+  cfg_out[1] = bt;
+  cfg_out[2] = bs;
+  *best_ms = best / steps_per_candidate;
+  for (int k = 0; k < b->n_sys; ++k) {
+    st = read_err(b->sys[k]);
+    if (st != MX_OK) return st;
+  }
+  return MX_OK;
+}
+
+mx_status mx_batch_sync(mx_batch* b) {
+  if (!b) return fail(MX_EINVAL, "batch is NULL");
+  HIPCHK(hipStreamSynchronize(b->stream), "sync");
+  for (int k = 0; k < b->n_sys; ++k) {
+    mx_status st = read_err(b->sys[k]);
+    if (st != MX_OK) {
+      g_err = "system " + std::to_string(k) + ": " + g_err;
+      return st;
+    }
+  }
+  return MX_OK;
+}
+
+mx_status mx_batch_system(mx_batch* b, int32_t k, mx_system** view) {
+  if (!b || !view || k < 0 || k >= b->n_sys) return fail(MX_EINVAL, "bad batch or index");
+  *view = b->sys[k];
+  return MX_OK;
+}
+
+void mx_destroy_batch(mx_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  free_batch(b);
 }
 
 }  // extern "C"

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
+#include <math.h>
 #include <stdint.h>
 
 #include "../../include/mx.h"
@@ -53,6 +54,64 @@ struct DevScalars {
   unsigned long long pairs_flagged;  // cumulative flagged pairs
 };
 
+namespace mxd {
+// Gas-disk constants of a parameter set in the units of the drag formula.
+struct DragConst {
+  double mu0, sigma1_unit, gamma, r_c, inv_rc, r_in, h_over_r, vg_fac, kexp, mfp_coef;
+  double rc_norm;  // (1/r_c)^(2-gamma), the normalisation of the taper at 1 AU
+};
+
+// Drag constants of a parameter set (host side).
+inline DragConst make_drag_const(const mx_params& p) {
+  DragConst c;
+  c.mu0 = p.G * p.m0;
+  c.sigma1_unit = p.sigma1 * (p.rho_unit / p.au_cm);
+  c.gamma = p.gamma;
+  c.r_c = p.r_c;
+  c.inv_rc = p.r_c > 0.0 ? 1.0 / p.r_c : 0.0;
+  c.r_in = p.r_in;
+  c.h_over_r = p.h_over_r;
+  c.vg_fac = sqrt(1.0 - 2.0 * p.eta);
+  c.kexp = p.kdrag_exp;
+  c.mfp_coef = p.mfp_coef;
+  c.rc_norm = p.r_c > 0.0 ? pow(1.0 / p.r_c, 2.0 - p.gamma) : 0.0;
+  return c;
+}
+}  // namespace mxd
+
+// Device view of one system for the kernels that step one or many systems per
+// launch (fused small-B step, planner, encounter integrator).  All pointers are
+// device pointers into the system's own allocations; the state is SoA [3][n].
+struct SysDesc {
+  double *x, *u, *ag, *x0, *u0;
+  const double *mu, *rcrit;         // [nb]
+  const double *r_p, *rho_p;        // [n - nb]
+  double *bigsnap, *bigmid;         // [9][nb], [6][nb]
+  int32_t* pairs;                   // [cap_pairs][2]
+  int64_t* keys;                    // planner scratch [2 * cap_pairs]
+  int32_t* plan_idx;                // planner scratch [2 * cap_pairs]
+  int32_t* uf;                      // [2 * nb] union-find scratch
+  Subsystem* subs;                  // [cap_subs]
+  DevScalars* dsc;
+  mxd::DragConst dc;
+  double mu0, h, bs_tol;
+  int32_t n, nb, cap_pairs, cap_subs, gas_on, pad;
+};
+
+// A tile of consecutive bodies of one system for the fused small-B kernels.
+struct Tile {
+  int32_t sys, first;
+};
+
+// Kernel timing of one kernel group (eager launches only, never under
+// capture): the next kernel launched while armed records `start` at its start,
+// which is then cleared; every kernel launched while armed records `stop` at
+// its end.
+struct LaunchTiming {
+  bool armed;
+  hipEvent_t start, stop;
+};
+
 struct mx_system {
   mx_params p;
   int n, nb, ns;
@@ -93,28 +152,36 @@ struct mx_system {
   hipGraphExec_t graph;
   bool graph_ok;
   int launch_mode;  // MX_LAUNCH_EAGER or MX_LAUNCH_GRAPH
-  // kernel timing of one group (eager launches only, never under capture): the
-  // next kernel launched records tev_start at its start, which is then cleared;
-  // every kernel launched while armed records tev_stop at its end
-  bool tev_armed;
-  hipEvent_t tev_start, tev_stop;
+  LaunchTiming tev;
   hipEvent_t* tev_pool;  // events of mx_step_timed, kept between calls
   int32_t tev_pool_n;
+  // one-entry device view and the tile table of the fused small-B kernels
+  SysDesc* desc;
+  Tile* tiles;
+  int32_t n_tiles;
+  bool in_batch;  // owned by an mx_batch: mx_destroy leaves it alone
   int64_t host_step;
 };
 
-// Launch on the system's stream (kernel timing as described at tev_armed).
+// Launch on a stream with optional kernel timing (see LaunchTiming).
+template <typename... KArgs, typename... Args>
+inline hipError_t mxlaunch_on(hipStream_t st, LaunchTiming* tm, void (*k)(KArgs...), dim3 grid,
+                              dim3 block, Args... args) {
+  if (tm && tm->armed) {
+    hipExtLaunchKernelGGL(k, grid, block, 0, st, tm->start, tm->stop, 0,
+                          static_cast<KArgs>(args)...);
+    tm->start = nullptr;
+  } else {
+    k<<<grid, block, 0, st>>>(static_cast<KArgs>(args)...);
+  }
+  return hipGetLastError();
+}
+
+// Launch on the system's stream with the system's kernel timing.
 template <typename... KArgs, typename... Args>
 inline hipError_t mxlaunch(mx_system* s, void (*k)(KArgs...), dim3 grid, dim3 block,
                            Args... args) {
-  if (s->tev_armed) {
-    hipExtLaunchKernelGGL(k, grid, block, 0, s->stream, s->tev_start, s->tev_stop, 0,
-                          static_cast<KArgs>(args)...);
-    s->tev_start = nullptr;
-  } else {
-    k<<<grid, block, 0, s->stream>>>(static_cast<KArgs>(args)...);
-  }
-  return hipGetLastError();
+  return mxlaunch_on(s->stream, &s->tev, k, grid, block, args...);
 }
 
 // ---- launchers (kernels_*.hip)
@@ -122,8 +189,6 @@ namespace mxk {
 hipError_t launch_growth(mx_system* s);
 hipError_t launch_kick_jump_drift(mx_system* s);
 hipError_t launch_flag(mx_system* s);
-hipError_t launch_plan(mx_system* s);
-hipError_t launch_bs(mx_system* s);
 hipError_t launch_jump_pack(mx_system* s);
 hipError_t launch_force_kick(mx_system* s, int kick);
 hipError_t launch_pack_only(mx_system* s);
@@ -132,8 +197,16 @@ hipError_t launch_h2dh(mx_system* s, const double* v_h);
 hipError_t launch_dh2h(mx_system* s, double* v_h);
 hipError_t launch_init_bodies(mx_system* s, const double* x_h, const double* v_h);
 hipError_t launch_reset_scalars(mx_system* s, int64_t step);
-hipError_t launch_step_a_small(mx_system* s);
-hipError_t launch_step_b_small(mx_system* s, int kick);
+// fused small-B kernels over a tile table (n_big <= kSmallBig in every system);
+// blk bodies per tile (64, 128, 256 or 512), tpb consecutive tiles per block
+hipError_t launch_step_a_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
+                               const Tile* tiles, int n_tiles, int blk, int tpb);
+hipError_t launch_step_b_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
+                               const Tile* tiles, int n_tiles, int blk, int tpb, int kick);
+// planner (one block per system) and encounter integrator (bps blocks per system)
+hipError_t launch_plan_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys);
+hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys,
+                         int bps);
 
 // stateless single-kernel launchers
 hipError_t gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,
