@@ -16,6 +16,9 @@ Extra objects:
                    kernel source is unchanged
   kick_fp64     -- the force kernel of the fully self-gravitating 4,004-body case
                    (16.0 M interactions per kick) against FP64 peak
+  batch         -- 256 independent embryo disks of uneven size stepped together
+                   (autotuned launch shape; eager and graph launches), against the
+                   sum of the same systems stepped one at a time
   cpu_baseline  -- the CPU oracle (single thread) on a bounded sample of steps
 """
 from __future__ import annotations
@@ -162,6 +165,54 @@ def kick_fp64(args):
             "model": f"{FLOP_PER_INTERACTION} FP64 flop per ordered interaction"}
 
 
+def batch_leg(args):
+    """256 independent embryo disks of uneven size stepped together, against the
+    same systems stepped one at a time (each batch member alone)."""
+    import paper_2601_16791_amd as mx
+    from synth import ic
+    ws = ic.batch(seed=args.seed, n_sys=args.batch_systems)
+    I = sum(interactions_per_step(w.params["n_big"], w.n) for w in ws)
+    bodies = sum(w.n for w in ws)
+    b = mx.Batch.from_workloads(ws)
+    del ws
+    taken, cfg, best_ms = b.autotune(steps_per_candidate=3)
+    b.step(args.warmup)
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(args.batch_steps)
+    b.sync()
+    T = time.perf_counter() - t0
+    b.set_launch_mode("graph", steps_per_graph=args.graph_steps)
+    b.step(args.graph_steps)  # capture
+    b.sync()
+    t1 = time.perf_counter()
+    b.step(args.batch_steps)
+    b.sync()
+    T_graph = time.perf_counter() - t1
+    # every member alone (its own single-system launches), a few steps each
+    single_s = 0.0
+    for k in range(b.n_sys):
+        v = b.system(k)
+        v.step(2)
+        v.sync()
+        t2 = time.perf_counter()
+        v.step(args.single_steps)
+        v.sync()
+        single_s += (time.perf_counter() - t2) / args.single_steps
+    b.close()
+    return {"workload": f"{args.batch_systems} embryo disks, 2-8 embryos and 1e3-5e4 massless "
+                        "bodies each (log-uniform), gas drag",
+            "systems": args.batch_systems, "bodies": bodies, "interactions_per_step": I,
+            "config_autotuned": {"bodies_per_tile": cfg[0], "tiles_per_block": cfg[1],
+                                 "bs_blocks_per_system": cfg[2]},
+            "autotune_steps": taken, "steps": args.batch_steps,
+            "steps_per_s": args.batch_steps / T, "interactions_per_s": I * args.batch_steps / T,
+            "steps_per_s_graph": args.batch_steps / T_graph,
+            "graph_steps_per_launch": args.graph_steps,
+            "single_system_sum_ms_per_step": 1e3 * single_s,
+            "speedup_vs_single_systems": single_s / (T / args.batch_steps)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +225,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kick", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-systems", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--graph-steps", type=int, default=10)
+    ap.add_argument("--single-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device-to-device once (reference reading for "
                          "HBM byte counters)")
@@ -264,6 +320,8 @@ def main():
     }
     if not args.no_kick:
         out["kick_fp64"] = kick_fp64(args)
+    if not args.no_batch:
+        out["batch"] = batch_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out))

@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -193,8 +194,9 @@ class System:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().mx_destroy(self._h)  # no-op for a system owned by a batch
-            self._h = None
+            if getattr(self, "_owner", None) is None:
+                lib().mx_destroy(self._h)
+            self._h = None  # a view only lets go of the batch member
 
     def __del__(self):
         try:
@@ -329,6 +331,7 @@ class Batch:
                                    C.byref(h)))
         self._h = h
         self.n_sys = k
+        self._views = weakref.WeakSet()
 
     @classmethod
     def from_workloads(cls, ws, device="cuda"):
@@ -338,6 +341,8 @@ class Batch:
 
     def close(self):
         if getattr(self, "_h", None):
+            for v in list(self._views):
+                v._h = None  # views of destroyed members become unusable
             lib().mx_destroy_batch(self._h)
             self._h = None
 
@@ -379,7 +384,9 @@ class Batch:
     def system(self, k):
         h = C.c_void_p()
         _check(lib().mx_batch_system(self._h, int(k), C.byref(h)))
-        return System._view(h, self.params[k], self.device, self.stream, self)
+        v = System._view(h, self.params[k], self.device, self.stream, self)
+        self._views.add(v)
+        return v
 
 
 # ------------------------------------------------------------ single kernels

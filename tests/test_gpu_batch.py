@@ -113,6 +113,11 @@ def test_batch_member_steps_alone_and_errors(mx):
         b.set_config(100, 1, 1)
     with pytest.raises(mx.MxError):
         b.system(3)
+    keep = b.system(2)
+    b.close()             # views of a closed batch refuse to run
+    with pytest.raises(mx.MxError):
+        keep.step(1)
+    del keep
     big = ic.self_gravitating(seed=0, n_pl=4, n_pls=100)  # 104 massive bodies
     with pytest.raises(mx.MxError) as e:
         mx.Batch.from_workloads([ws[0], big])
