@@ -76,6 +76,7 @@ def lib():
         L.or_set_dh.argtypes = [C.c_void_p, _D, _D, C.c_long]
         L.or_get_accel.argtypes = [C.c_void_p, _D]
         L.or_get_mu.argtypes = [C.c_void_p, _D, _D]
+        L.or_set_rcrit.argtypes = [C.c_void_p, _D]
         L.or_step_index.restype = C.c_long
         L.or_step_index.argtypes = [C.c_void_p]
         L.or_changeover.restype = C.c_double
@@ -177,6 +178,12 @@ class OracleSystem:
 
     def step_index(self):
         return lib().or_step_index(self._h)
+
+    def set_rcrit(self, rcrit):
+        """Hold the changeover radii at the given values (FSAL force refreshed)."""
+        rc = _d(rcrit)
+        assert rc.shape == (self.nb,)
+        lib().or_set_rcrit(self._h, _p(rc))
 
 
 # ------------------------------------------------------------ components

@@ -966,6 +966,17 @@ void or_set_dh(or_sys* s, const double* x, const double* u, long step_index) {
 
 void or_get_accel(const or_sys* s, double* a) { memcpy(a, s->ag, sizeof(double) * 3 * s->n); }
 
+/* Replace the changeover radii (massive bodies; the value at the current mass,
+ * also kept as the reference radius of the growth law) and refresh the FSAL
+ * force.  Used to hold the radii fixed while masses or orbits are perturbed. */
+void or_set_rcrit(or_sys* s, const double* rcrit) {
+  for (int k = 0; k < s->nb; ++k) {
+    s->rcrit[k] = rcrit[k];
+    s->rcrit_init[k] = rcrit[k] * cbrt(s->mu_init[k] / s->mu[k]);
+  }
+  refresh_fsal(s);
+}
+
 void or_get_mu(const or_sys* s, double* mu, double* rcrit) {
   for (int k = 0; k < s->nb; ++k) { mu[k] = s->mu[k]; rcrit[k] = s->rcrit[k]; }
 }

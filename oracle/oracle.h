@@ -44,6 +44,7 @@ void or_get_dh(const or_sys* s, double* x, double* u);
 void or_set_dh(or_sys* s, const double* x, const double* u, long step_index);
 void or_get_accel(const or_sys* s, double* a);  /* FSAL gravity (changeover-weighted) */
 void or_get_mu(const or_sys* s, double* mu, double* rcrit);
+void or_set_rcrit(or_sys* s, const double* rcrit);
 long or_step_index(const or_sys* s);
 
 /* --- component functions (pins and kernel-level parity) --------------- */
