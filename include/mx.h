@@ -36,6 +36,7 @@ extern "C" {
 
 typedef struct mx_system mx_system; /* opaque; owned by the library */
 typedef struct mx_batch mx_batch;   /* opaque; many independent systems stepped together */
+typedef struct mx_adjoint mx_adjoint; /* opaque; a differentiable run of one system */
 
 typedef enum {
   MX_OK = 0,
@@ -225,6 +226,46 @@ mx_status mx_batch_sync(mx_batch* b);
 mx_status mx_batch_system(mx_batch* b, int32_t k, mx_system** view);
 
 void mx_destroy_batch(mx_batch* b);
+
+/* ---------------------------------------------------------------- adjoint
+ * Reverse-mode derivative of a run of n_steps hybrid steps of one system
+ * (n_big <= 64, no growth schedule) with respect to the massive-body masses and
+ * the initial heliocentric state of every body.  The run is the map of mx_step;
+ * its adjoint takes every sub-step back in reverse order: the half kicks (the
+ * changeover-weighted gravity of Sect. 2.1.3 and its mass dependence, the gas
+ * drag of Sect. 3.1 with its regime held at the value), the jumps by the
+ * massive-body momentum, the Kepler drift (derivative through the solved time
+ * equation) and the Bulirsch-Stoer integration of encounter subsystems of up to
+ * four members (derivative of the map along the accepted step sizes and
+ * columns of the forward run).  The changeover radii are constants of the map.
+ * The forward run keeps its state every checkpoint_every steps; the reverse pass
+ * recomputes each segment forward from its checkpoint.  Storage: about
+ * (n_steps / checkpoint_every + checkpoint_every) x 72 n bytes on the device. */
+
+/* As mx_init_system (no growth); rcrit: changeover radii [n_big] to use instead
+ * of the Hill-radius rule (host or device per is_device_ptr), or NULL.  hip_stream
+ * must not be the default stream. */
+mx_status mx_adjoint_create(const mx_params* p, const double* x_h, const double* v_h,
+                            const double* m_big, const double* r_p, const double* rho_p,
+                            const double* rcrit, int32_t n_steps, int32_t checkpoint_every,
+                            int is_device_ptr, void* hip_stream, mx_adjoint** out);
+
+/* Runs the n_steps from the initial state (again at every call); x_h, v_h
+ * ([3][n], host or device) receive the final heliocentric state.  Synchronises. */
+mx_status mx_adjoint_forward(mx_adjoint* a, double* x_h, double* v_h, int is_device_ptr);
+
+/* Given gx, gv = dL/d(final x_h, v_h) ([3][n]), writes g_m = dL/dm ([n_big],
+ * masses in Msun) and g_x, g_v = dL/d(initial x_h, v_h) ([3][n]).  Needs a
+ * completed mx_adjoint_forward; leaves the system at the final state.  Reports
+ * MX_ECAPACITY when an encounter subsystem had more than four members or more
+ * than 64 accepted Bulirsch-Stoer steps.  Synchronises. */
+mx_status mx_adjoint_backward(mx_adjoint* a, const double* gx, const double* gv, double* g_m,
+                              double* g_x, double* g_v, int is_device_ptr);
+
+/* Borrowed view of the system being differentiated (masses, radii, energy). */
+mx_status mx_adjoint_system(mx_adjoint* a, mx_system** view);
+
+void mx_destroy_adjoint(mx_adjoint* a);
 
 /* -------------------------------------------- single-kernel entry points
  * Stateless launches of one kernel of the step on device pointers, queued on

@@ -6,6 +6,7 @@ kernels of the library.  There is no CPU fallback: if the library is missing the
 import of any entry point raises.
 """
 from ._binding import (  # noqa: F401
+    Adjoint,
     Batch,
     MxError,
     Params,
@@ -13,6 +14,7 @@ from ._binding import (  # noqa: F401
     flag_pairs,
     gas_drag,
     gravity,
+    hybrid_run,
     kepler_drift,
     lib,
     lib_path,

@@ -120,6 +120,16 @@ def lib():
         L.mx_batch_system.restype = st
         L.mx_batch_system.argtypes = [_P, C.c_int32, C.POINTER(C.c_void_p)]
         L.mx_destroy_batch.argtypes = [_P]
+        L.mx_adjoint_create.restype = st
+        L.mx_adjoint_create.argtypes = [C.POINTER(Params), _D, _D, _D, _D, _D, _D, C.c_int32,
+                                        C.c_int32, C.c_int, _P, C.POINTER(C.c_void_p)]
+        L.mx_adjoint_forward.restype = st
+        L.mx_adjoint_forward.argtypes = [_P, _D, _D, C.c_int]
+        L.mx_adjoint_backward.restype = st
+        L.mx_adjoint_backward.argtypes = [_P, _D, _D, _D, _D, _D, C.c_int]
+        L.mx_adjoint_system.restype = st
+        L.mx_adjoint_system.argtypes = [_P, C.POINTER(C.c_void_p)]
+        L.mx_destroy_adjoint.argtypes = [_P]
         L.mx_flag_pairs.restype = st
         L.mx_flag_pairs.argtypes = [C.c_int32, C.c_int32, _D, _D, _D, _D, _D, C.c_double, _D,
                                     C.c_int32, C.POINTER(C.c_int32), _P]
@@ -387,6 +397,121 @@ class Batch:
         v = System._view(h, self.params[k], self.device, self.stream, self)
         self._views.add(v)
         return v
+
+
+class Adjoint:
+    """n_steps hybrid steps of one system (n_big <= 64) with checkpoints every
+    `checkpoint_every` steps, and the reverse-mode adjoint of the run: gradients
+    of a function of the final heliocentric state with respect to the masses and
+    the initial heliocentric state.  The changeover radii are held fixed (given,
+    or from the Hill rule at the initial state)."""
+
+    def __init__(self, params, x, v, m_big, r_p=None, rho_p=None, n_steps=1,
+                 checkpoint_every=50, rcrit=None, device="cuda"):
+        torch = _torch()
+        self.params = dict(params)
+        self.nb = int(params["n_big"])
+        self.n = self.nb + int(params["n_small"])
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        tx, tv, tm = _dev(x, device), _dev(v, device), _dev(m_big, device)
+        if tm is None or tm.numel() == 0:
+            tm = torch.zeros(1, dtype=torch.float64, device=device)
+        trp, trh, trc = _dev(r_p, device), _dev(rho_p, device), _dev(rcrit, device)
+        torch.cuda.current_stream(self.device).synchronize()
+        self._pp = make_params(params)
+        h = C.c_void_p()
+        _check(lib().mx_adjoint_create(C.byref(self._pp), _ptr(tx), _ptr(tv), _ptr(tm), _ptr(trp),
+                                       _ptr(trh), _ptr(trc), int(n_steps), int(checkpoint_every),
+                                       1, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mx_destroy_adjoint(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self):
+        """Final heliocentric (x, v), device tensors [3, n]."""
+        torch = _torch()
+        x = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
+        v = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(lib().mx_adjoint_forward(self._h, _ptr(x), _ptr(v), 1))
+        return x, v
+
+    def backward(self, gx, gv):
+        """(dL/dm [n_big], dL/dx0 [3, n], dL/dv0 [3, n]) from dL/dx, dL/dv of the
+        final heliocentric state."""
+        torch = _torch()
+        tgx, tgv = _dev(gx, self.device), _dev(gv, self.device)
+        gm = torch.zeros(max(self.nb, 1), dtype=torch.float64, device=self.device)
+        g_x = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
+        g_v = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(lib().mx_adjoint_backward(self._h, _ptr(tgx), _ptr(tgv), _ptr(gm), _ptr(g_x),
+                                         _ptr(g_v), 1))
+        return gm[: self.nb], g_x, g_v
+
+    def rcrit(self):
+        h = C.c_void_p()
+        _check(lib().mx_adjoint_system(self._h, C.byref(h)))
+        k = max(self.nb, 1)
+        mu = (C.c_double * k)()
+        rc = (C.c_double * k)()
+        _check(lib().mx_get_masses(h, mu, rc))
+        return np.array(rc[: self.nb])
+
+
+def _hybrid_function():
+    torch = _torch()
+
+    class HybridRun(torch.autograd.Function):
+        """(m_big, x_big, v_big) -> final heliocentric (x, v) of every body after the
+        spec's n_steps hybrid steps; backward runs the adjoint of the library."""
+
+        @staticmethod
+        def forward(ctx, m_big, x_big, v_big, spec):
+            nb = int(spec["params"]["n_big"])
+            x = torch.as_tensor(np.asarray(spec["x"], dtype=np.float64)).clone()
+            v = torch.as_tensor(np.asarray(spec["v"], dtype=np.float64)).clone()
+            x[:, :nb] = x_big.detach().cpu()
+            v[:, :nb] = v_big.detach().cpu()
+            adj = Adjoint(spec["params"], x, v, m_big.detach(), spec.get("r_p"),
+                          spec.get("rho_p"), spec["n_steps"], spec.get("checkpoint_every", 50),
+                          spec.get("rcrit"), device=m_big.device)
+            xf, vf = adj.forward()
+            ctx.adj = adj
+            ctx.nb = nb
+            return xf, vf
+
+        @staticmethod
+        def backward(ctx, gx, gv):
+            gm, g_x, g_v = ctx.adj.backward(gx.contiguous(), gv.contiguous())
+            ctx.adj.close()
+            nb = ctx.nb
+            return gm, g_x[:, :nb].contiguous(), g_v[:, :nb].contiguous(), None
+
+    return HybridRun
+
+
+_HYBRID = None
+
+
+def hybrid_run(m_big, x_big, v_big, spec):
+    """Differentiable run: m_big [n_big], x_big, v_big [3, n_big] torch tensors (float64,
+    device); spec: dict(params, x, v (all bodies, heliocentric), r_p, rho_p, n_steps,
+    checkpoint_every, rcrit).  Returns the final heliocentric (x, v) [3, n]."""
+    global _HYBRID
+    if _HYBRID is None:
+        _HYBRID = _hybrid_function()
+    return _HYBRID.apply(m_big, x_big, v_big, spec)
 
 
 # ------------------------------------------------------------ single kernels

@@ -652,7 +652,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc) {
       for (int q = 0; q < np; ++q) pmask |= 1u << pair_bit(S.pl[q][0], S.pl[q][1], m);
     __syncthreads();
     double done = 0.0, H = h;
-    int fails = 0;
+    int fails = 0, nsched = 0;
     bool failed = false;
     while (fabs(h - done) > 1e-14 * fabs(h)) {
       double rem = h - done;
@@ -721,6 +721,15 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc) {
           if (e < nn) xs[e] = val;
           else vs[e - nn] = val;
         }
+        if (D.bs_sched && lane == 0) {
+          if (nsched < kBsMaxSched) {
+            D.bs_sched[((size_t)b * kBsMaxSched + nsched) * 2] = H;
+            D.bs_sched[((size_t)b * kBsMaxSched + nsched) * 2 + 1] = (double)accepted;
+          } else {
+            atomicOr(&dsc->err, MXE_ADJOINT);
+          }
+        }
+        ++nsched;
         done += H;
         fails = 0;
         if (accepted <= 4) H = 2.0 * H;
@@ -733,6 +742,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc) {
       }
       __syncthreads();
     }
+    if (D.bs_sched && lane == 0) D.bs_nsched[b] = failed ? 0 : nsched;
     if (failed) {
       if (lane == 0) atomicOr(&dsc->err, MXE_BS);
       continue;

@@ -165,6 +165,9 @@ mx_status read_err(mx_system* s) {
     if (err & MXE_NOCONV) return fail(MX_ENOCONV, "Kepler iteration did not converge");
     if (err & MXE_BS) return fail(MX_EBS, "Bulirsch-Stoer step-halving limit reached");
     if (err & (MXE_PAIRS | MXE_SUBSYS)) return fail(MX_ECAPACITY, "encounter capacity exceeded");
+    if (err & MXE_ADJOINT)
+      return fail(MX_ECAPACITY, "an encounter subsystem exceeds what the adjoint handles "
+                                "(more than 4 members or 64 accepted steps)");
   }
   return MX_OK;
 }
@@ -544,7 +547,7 @@ mx_status mx_get_step_index(mx_system* s, int64_t* step_index) {
 }
 
 void mx_destroy(mx_system* s) {
-  if (!s || s->in_batch) return;
+  if (!s || s->owned) return;
   (void)hipStreamSynchronize(s->stream);
   free_system(s);
 }
@@ -664,7 +667,7 @@ void free_batch(mx_batch* b) {
   if (b->sys) {
     for (int k = 0; k < b->n_sys; ++k)
       if (b->sys[k]) {
-        b->sys[k]->in_batch = false;
+        b->sys[k]->owned = false;
         mx_destroy(b->sys[k]);
       }
     delete[] b->sys;
@@ -763,7 +766,7 @@ mx_status mx_init_batch(int32_t n_sys, const mx_params* params, const int64_t* o
       g_err = msg;
       return st;
     }
-    b->sys[k]->in_batch = true;
+    b->sys[k]->owned = true;
     boff += params[k].n_big;
     soff += params[k].n_small;
   }
@@ -942,6 +945,274 @@ void mx_destroy_batch(mx_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
   free_batch(b);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ adjoint
+namespace mxk {
+hipError_t adj_kick(hipStream_t st, int n, int nb, double mu0, double hh,
+                    const mxd::DragConst& dc, int gas_on, const double* x, const double* up,
+                    const double* mu, const double* rcrit, const double* r_p,
+                    const double* rho_p, double* lx, double* lu, double* lmu, double* part,
+                    double jump_coef);
+hipError_t adj_momentum(hipStream_t st, int n, int nb, const double* a, double coef,
+                        const double* mu, const double* uref, double* lu, double* lmu,
+                        double* part);
+hipError_t adj_drift(hipStream_t st, int n, int nb, double mu0, double h, const double* x0,
+                     const double* u0, const double* mu, const double* rcrit,
+                     const Subsystem* subs, const DevScalars* dsc, const double* sched,
+                     const int32_t* nsched, int32_t* kept, double* contrib, double* lx,
+                     double* lu, double* lmu, int32_t* err);
+hipError_t adj_h2dh(hipStream_t st, int n, int nb, double G, double m0, const double* m_big,
+                    const double* v_h, const double* lu, const double* lmu, double* gm,
+                    double* gv, double* part);
+}  // namespace mxk
+
+struct mx_adjoint {
+  mx_system* s;
+  int32_t n_steps, every, n_ckpt;
+  size_t blk;        // doubles of one saved state: x, u, ag [3][n], bigsnap [9][nb]
+  double* ckpt;      // [n_ckpt][blk]: states at steps 0, every, 2 every, ...
+  double* seg;       // [every][blk]: step-start states of the segment being reversed
+  double* fin;       // [blk]: state after the last step
+  double *mid_x, *mid_u;  // [3][n]: positions and velocities after drift and encounters
+  double *lx, *lu, *lmu;  // adjoints of x, u [3][n] and of mu [n_big]
+  double* part;      // wave partials
+  double* sched;     // [cap_subs][kBsMaxSched][2]
+  int32_t* nsched;   // [cap_subs]
+  double* contrib;   // [cap_subs][28]
+  int32_t* kept;     // [n]
+  double *m_big, *v_h0;   // start masses [n_big] and heliocentric velocities [3][n]
+  double *gm, *gv;        // gradient scratch [n_big], [3][n]
+  bool forward_done;
+};
+
+namespace {
+
+void free_adjoint(mx_adjoint* a) {
+  if (!a) return;
+  if (a->s) {
+    a->s->owned = false;
+    mx_destroy(a->s);
+  }
+  void* ptrs[] = {a->ckpt, a->seg, a->fin, a->mid_x, a->mid_u, a->lx, a->lu, a->lmu, a->part,
+                  a->sched, a->nsched, a->contrib, a->kept, a->m_big, a->v_h0, a->gm, a->gv};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete a;
+}
+
+hipError_t save_state(mx_adjoint* a, double* dst) {
+  mx_system* s = a->s;
+  const size_t n3 = 3 * (size_t)s->n;
+  hipError_t e = hipMemcpyAsync(dst, s->x, n3 * 8, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst + n3, s->u, n3 * 8, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst + 2 * n3, s->ag, n3 * 8, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess && s->nb > 0)
+    e = hipMemcpyAsync(dst + 3 * n3, s->bigsnap, 9 * (size_t)s->nb * 8, hipMemcpyDeviceToDevice,
+                       s->stream);
+  return e;
+}
+
+hipError_t restore_state(mx_adjoint* a, const double* src, int64_t step) {
+  mx_system* s = a->s;
+  const size_t n3 = 3 * (size_t)s->n;
+  hipError_t e = hipMemcpyAsync(s->x, src, n3 * 8, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->u, src + n3, n3 * 8, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->ag, src + 2 * n3, n3 * 8, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess && s->nb > 0)
+    e = hipMemcpyAsync(s->bigsnap, src + 3 * n3, 9 * (size_t)s->nb * 8, hipMemcpyDeviceToDevice,
+                       s->stream);
+  if (e == hipSuccess) e = mxk::launch_reset_scalars(s, step);
+  return e;
+}
+
+// one step with the state after drift and encounters kept in mid_x, mid_u
+hipError_t instrumented_step(mx_adjoint* a) {
+  mx_system* s = a->s;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < MX_NUM_KERNELS && e == hipSuccess; ++k) {
+    if (k == MX_K_JUMP_PACK) {
+      const size_t b3 = 3 * (size_t)s->n * 8;
+      e = hipMemcpyAsync(a->mid_x, s->x, b3, hipMemcpyDeviceToDevice, s->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(a->mid_u, s->u, b3, hipMemcpyDeviceToDevice, s->stream);
+    }
+    if (e == hipSuccess) e = launch_group(s, k);
+  }
+  return e;
+}
+
+// adjoint of one step whose forward was just run by instrumented_step from the
+// step-start state `start` (x_a, u_a)
+hipError_t reverse_step(mx_adjoint* a, const double* start) {
+  mx_system* s = a->s;
+  const int n = s->n, nb = s->nb;
+  const double h = s->p.dt, hh = 0.5 * h, mu0 = s->mu0;
+  const mxd::DragConst dc = mxd::make_drag_const(s->p);
+  const size_t n3 = 3 * (size_t)n;
+  hipError_t e;
+  // closing half kick at the final positions, with the jump before it
+  e = mxk::adj_kick(s->stream, n, nb, mu0, hh, dc, s->p.gas_on, s->x, a->mid_u, s->mu, s->rcrit,
+                    s->r_p, s->rho_p, a->lx, a->lu, a->lmu, a->part, hh / mu0);
+  if (e != hipSuccess) return e;
+  // Kepler drift / encounter integration from the pre-drift state (x0, u0)
+  e = mxk::adj_drift(s->stream, n, nb, mu0, h, s->x0, s->u0, s->mu, s->rcrit, s->subs, s->dsc,
+                     a->sched, a->nsched, a->kept, a->contrib, a->lx, a->lu, a->lmu,
+                     &s->dsc->err);
+  if (e != hipSuccess) return e;
+  // first jump: x0 = x_a + hh P(u0) / mu0
+  e = mxk::adj_momentum(s->stream, n, nb, a->lx, hh / mu0, s->mu, s->u0, a->lu, a->lmu, a->part);
+  if (e != hipSuccess) return e;
+  // opening half kick at the step-start state
+  return mxk::adj_kick(s->stream, n, nb, mu0, hh, dc, s->p.gas_on, start, start + n3, s->mu,
+                       s->rcrit, s->r_p, s->rho_p, a->lx, a->lu, a->lmu, a->part, 0.0);
+}
+
+}  // namespace
+
+extern "C" {
+
+mx_status mx_adjoint_create(const mx_params* p, const double* x_h, const double* v_h,
+                            const double* m_big, const double* r_p, const double* rho_p,
+                            const double* rcrit, int32_t n_steps, int32_t checkpoint_every,
+                            int is_device_ptr, void* hip_stream, mx_adjoint** out) {
+  if (!out) return fail(MX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p || n_steps < 1 || checkpoint_every < 1)
+    return fail(MX_EINVAL, "need params, n_steps >= 1 and checkpoint_every >= 1");
+  if (p->n_big > kSmallBig) return fail(MX_EINVAL, "the adjoint needs n_big <= 64");
+  if (hip_stream == nullptr) return fail(MX_EINVAL, "the adjoint needs a non-default stream");
+  mx_adjoint* a = new mx_adjoint();
+  std::memset((void*)a, 0, sizeof(mx_adjoint));
+  mx_status st = mx_init_system(p, x_h, v_h, m_big, r_p, rho_p, nullptr, is_device_ptr,
+                                hip_stream, &a->s);
+  if (st != MX_OK) {
+    delete a;
+    return st;
+  }
+  mx_system* s = a->s;
+  s->owned = true;
+  const int n = s->n, nb = s->nb;
+  const size_t n3 = 3 * (size_t)n;
+  a->n_steps = n_steps;
+  a->every = checkpoint_every < n_steps ? checkpoint_every : n_steps;
+  a->n_ckpt = (n_steps + a->every - 1) / a->every;
+  a->blk = 3 * n3 + 9 * (size_t)nb;
+  const size_t nwaves = 4 * (size_t)((n + 255) / 256);
+  hipError_t e = hipSuccess;
+#define ALLOC(ptr, cnt) \
+  if (e == hipSuccess) e = dalloc(&(ptr), (size_t)(cnt));
+  ALLOC(a->ckpt, a->n_ckpt * a->blk) ALLOC(a->seg, a->every * a->blk) ALLOC(a->fin, a->blk)
+  ALLOC(a->mid_x, n3) ALLOC(a->mid_u, n3) ALLOC(a->lx, n3) ALLOC(a->lu, n3) ALLOC(a->lmu, nb)
+  ALLOC(a->part, nwaves * (4 * (size_t)kSmallBig + 6))
+  ALLOC(a->sched, (size_t)s->cap_subs * kBsMaxSched * 2) ALLOC(a->nsched, s->cap_subs)
+  ALLOC(a->contrib, (size_t)s->cap_subs * 28) ALLOC(a->kept, n) ALLOC(a->m_big, nb)
+  ALLOC(a->v_h0, n3) ALLOC(a->gm, nb) ALLOC(a->gv, n3)
+#undef ALLOC
+  if (e == hipSuccess) e = hipMemsetAsync(a->kept, 0, sizeof(int32_t) * n, s->stream);
+  if (e == hipSuccess && nb > 0)
+    e = copy_in(a->m_big, m_big, sizeof(double) * nb, is_device_ptr, s->stream);
+  if (e == hipSuccess) e = copy_in(a->v_h0, v_h, sizeof(double) * n3, is_device_ptr, s->stream);
+  if (e == hipSuccess && rcrit && nb > 0) {
+    // changeover radii given by the caller (held fixed, as under differentiation)
+    e = copy_in(s->rcrit, rcrit, sizeof(double) * nb, is_device_ptr, s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->rcrit_init, s->rcrit, sizeof(double) * nb, hipMemcpyDeviceToDevice,
+                         s->stream);
+    if (e == hipSuccess) e = refresh_accel(s);
+  }
+  if (e == hipSuccess) {
+    SysDesc d = make_desc(s);
+    d.bs_sched = a->sched;
+    d.bs_nsched = a->nsched;
+    e = hipMemcpy(s->desc, &d, sizeof(SysDesc), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = save_state(a, a->ckpt);  // the start state
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) {
+    free_adjoint(a);
+    return hip_fail(e, "adjoint set-up");
+  }
+  st = read_err(s);
+  if (st != MX_OK) {
+    free_adjoint(a);
+    return st;
+  }
+  *out = a;
+  return MX_OK;
+}
+
+mx_status mx_adjoint_forward(mx_adjoint* a, double* x_h, double* v_h, int is_device_ptr) {
+  if (!a || !x_h || !v_h) return fail(MX_EINVAL, "NULL argument");
+  mx_system* s = a->s;
+  HIPCHK(restore_state(a, a->ckpt, 0), "restore start");
+  for (int32_t j = 0; j < a->n_steps; ++j) {
+    if (j % a->every == 0) HIPCHK(save_state(a, a->ckpt + (size_t)(j / a->every) * a->blk), "checkpoint");
+    HIPCHK(enqueue_step(s), "step");
+  }
+  HIPCHK(save_state(a, a->fin), "final state");
+  s->host_step = a->n_steps;
+  mx_status st = read_err(s);
+  if (st != MX_OK) return st;
+  st = mx_get_state(s, x_h, v_h, is_device_ptr);
+  if (st == MX_OK) a->forward_done = true;
+  return st;
+}
+
+mx_status mx_adjoint_backward(mx_adjoint* a, const double* gx, const double* gv, double* g_m,
+                              double* g_x, double* g_v, int is_device_ptr) {
+  if (!a || !gx || !gv || !g_x || !g_v || (a->s->nb > 0 && !g_m))
+    return fail(MX_EINVAL, "NULL argument");
+  if (!a->forward_done) return fail(MX_EINVAL, "call mx_adjoint_forward first");
+  mx_system* s = a->s;
+  const int n = s->n, nb = s->nb;
+  const size_t n3 = 3 * (size_t)n;
+  hipStream_t st = s->stream;
+  HIPCHK(copy_in(a->lx, gx, n3 * 8, is_device_ptr, st), "copy gx");
+  HIPCHK(copy_in(a->lu, gv, n3 * 8, is_device_ptr, st), "copy gv");
+  if (nb > 0) HIPCHK(hipMemsetAsync(a->lmu, 0, sizeof(double) * nb, st), "zero lmu");
+  // final heliocentric velocities v = u + P / mu0
+  HIPCHK(mxk::adj_momentum(st, n, nb, a->lu, 1.0 / s->mu0, s->mu, a->fin + n3, a->lu, a->lmu,
+                           a->part),
+         "final velocities");
+  for (int c = a->n_ckpt - 1; c >= 0; --c) {
+    const int32_t j0 = c * a->every;
+    const int32_t j1 = j0 + a->every < a->n_steps ? j0 + a->every : a->n_steps;
+    HIPCHK(restore_state(a, a->ckpt + (size_t)c * a->blk, j0), "restore checkpoint");
+    for (int32_t j = j0; j < j1; ++j) {
+      HIPCHK(save_state(a, a->seg + (size_t)(j - j0) * a->blk), "segment state");
+      if (j + 1 < j1) HIPCHK(enqueue_step(s), "segment step");
+    }
+    for (int32_t j = j1 - 1; j >= j0; --j) {
+      const double* start = a->seg + (size_t)(j - j0) * a->blk;
+      HIPCHK(restore_state(a, start, j), "restore step");
+      HIPCHK(instrumented_step(a), "recompute step");
+      HIPCHK(reverse_step(a, start), "adjoint step");
+    }
+  }
+  hipError_t e = mxk::adj_h2dh(st, n, nb, s->p.G, s->p.m0, a->m_big, a->v_h0, a->lu, a->lmu,
+                               a->gm, a->gv, a->part);
+  if (e == hipSuccess) e = copy_out(g_x, a->lx, n3 * 8, is_device_ptr, st);
+  if (e == hipSuccess) e = copy_out(g_v, a->gv, n3 * 8, is_device_ptr, st);
+  if (e == hipSuccess && nb > 0) e = copy_out(g_m, a->gm, sizeof(double) * nb, is_device_ptr, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "adjoint output");
+  // leave the system at its final state
+  HIPCHK(restore_state(a, a->fin, a->n_steps), "restore final");
+  return read_err(s);
+}
+
+mx_status mx_adjoint_system(mx_adjoint* a, mx_system** view) {
+  if (!a || !view) return fail(MX_EINVAL, "NULL argument");
+  *view = a->s;
+  return MX_OK;
+}
+
+void mx_destroy_adjoint(mx_adjoint* a) {
+  if (!a) return;
+  (void)hipStreamSynchronize(a->s->stream);
+  free_adjoint(a);
 }
 
 }  // extern "C"

@@ -15,6 +15,7 @@ enum : int32_t {
   MXE_PAIRS = 4,       // more flagged pairs than the list holds
   MXE_SUBSYS = 8,      // a subsystem larger than the encounter integrator holds
   MXE_NONFINITE = 16,  // non-finite state after a step
+  MXE_ADJOINT = 32,    // a subsystem beyond what the adjoint handles
 };
 
 // Systems with at most this many massive bodies use the fused small-B kernels.
@@ -24,6 +25,7 @@ constexpr int kSmallBig = 64;
 constexpr int kBsMaxMembers = 16;
 constexpr int kBsMaxPairs = 48;
 constexpr int kBsColumns = 8;   // substep sequence n = 2, 4, ..., 16
+constexpr int kBsMaxSched = 64; // accepted steps of one subsystem kept for the adjoint
 
 // Packed source records read with scalar (wave-uniform) loads.
 struct __align__(64) KickSource {   // one massive body at kick time
@@ -93,6 +95,11 @@ struct SysDesc {
   int32_t* uf;                      // [2 * nb] union-find scratch
   Subsystem* subs;                  // [cap_subs]
   DevScalars* dsc;
+  // accepted Bulirsch-Stoer steps of each subsystem of the step, for the adjoint
+  // (null when not recorded): bs_sched[(b * kBsMaxSched + q) * 2 + {0,1}] = (H,
+  // accepted column) of the q-th accepted step of subsystem b; bs_nsched[b] count
+  double* bs_sched;
+  int32_t* bs_nsched;
   mxd::DragConst dc;
   double mu0, h, bs_tol;
   int32_t n, nb, cap_pairs, cap_subs, gas_on, pad;
@@ -159,7 +166,7 @@ struct mx_system {
   SysDesc* desc;
   Tile* tiles;
   int32_t n_tiles;
-  bool in_batch;  // owned by an mx_batch: mx_destroy leaves it alone
+  bool owned;  // owned by a batch or an adjoint: mx_destroy leaves it alone
   int64_t host_step;
 };
 
