@@ -19,6 +19,8 @@ Extra objects:
   batch         -- 256 independent embryo disks of uneven size stepped together
                    (autotuned launch shape; eager and graph launches), against the
                    sum of the same systems stepped one at a time
+  adjoint       -- 1,000 differentiable steps of a 20,000-body embryo disk (checkpoints
+                   every 50 steps) and the reverse pass, against plain steps
   cpu_baseline  -- the CPU oracle (single thread) on a bounded sample of steps
 """
 from __future__ import annotations
@@ -213,6 +215,59 @@ def batch_leg(args):
             "speedup_vs_single_systems": single_s / (T / args.batch_steps)}
 
 
+def adjoint_leg(args):
+    """Differentiable run of the 20,000-body embryo disk: forward with checkpoints,
+    loss = mean + variance of the final massless eccentricities, reverse pass,
+    against the plain single-system steps of the same system."""
+    import torch
+    import paper_2601_16791_amd as mx
+    from synth import ic
+    w = ic.adjoint_shape(seed=args.seed)
+    nb = w.params["n_big"]
+    steps, every = args.adjoint_steps, 50
+    spec = dict(params=w.params, x=w.x, v=w.v, r_p=w.r_p, rho_p=w.rho_p, n_steps=steps,
+                checkpoint_every=every)
+    dev = "cuda"
+
+    def run(spec_run):
+        m = torch.tensor(w.m_big, dtype=torch.float64, device=dev, requires_grad=True)
+        xb = torch.tensor(w.x[:, :nb], dtype=torch.float64, device=dev, requires_grad=True)
+        vb = torch.tensor(w.v[:, :nb], dtype=torch.float64, device=dev, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xf, vf = mx.hybrid_run(m, xb, vb, spec_run)
+        torch.cuda.synchronize()
+        T_f = time.perf_counter() - t0
+        h = torch.linalg.cross(xf.T, vf.T)
+        r = torch.linalg.norm(xf, dim=0)
+        e = torch.linalg.norm(torch.linalg.cross(vf.T, h) / w.params["G"] - (xf / r).T,
+                              dim=1)[nb:]
+        loss = e.mean() + e.var(unbiased=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        return T_f, time.perf_counter() - t1, loss, m, xb, vb
+
+    run(dict(spec, n_steps=2, checkpoint_every=1))  # loads the torch kernels of the loss
+    T_fwd, T_bwd, loss, m, xb, vb = run(spec)
+    s = mx.System.from_workload(w)
+    s.step(5)
+    s.sync()
+    t2 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    T_plain = time.perf_counter() - t2
+    s.close()
+    return {"workload": f"embryo disk, {nb} embryos + {w.params['n_small']} massless bodies, gas "
+                        "drag; loss = mean + variance of final massless eccentricity",
+            "steps": steps, "checkpoint_every": every, "forward_s": T_fwd, "backward_s": T_bwd,
+            "backward_over_forward": T_bwd / T_fwd, "plain_steps_s": T_plain,
+            "backward_steps_per_s": steps / T_bwd,
+            "loss": loss.item(), "grad_norm_mass": float(m.grad.norm()),
+            "grad_norm_x": float(xb.grad.norm()), "grad_norm_v": float(vb.grad.norm())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +281,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kick", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--batch-systems", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--graph-steps", type=int, default=10)
@@ -322,6 +379,8 @@ def main():
         out["kick_fp64"] = kick_fp64(args)
     if not args.no_batch:
         out["batch"] = batch_leg(args)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out))

@@ -13,8 +13,8 @@
 //                     f = K(r)/r^3, Jacobian f I + f'(r)/r d d^T), its mass term,
 //                     and the drag Jacobian (forward-mode over the drag formula,
 //                     drag regime fixed); source-side sums reduced per wave
-//   k_adj_kick_sum  : fixed-order sums of the per-wave partials, applied to the
-//                     massive bodies, with the momentum terms of the jump and of
+//   k_adj_reduce /  : fixed-order sums of the per-wave partials, applied to the
+//   k_adj_kick_apply  massive bodies, with the momentum terms of the jump and of
 //                     the heliocentric velocity that the drag sees
 //   k_adj_drift     : transposed Jacobian of the Kepler map per body, by
 //                     forward-mode evaluation at the solved universal variable,
@@ -26,6 +26,8 @@
 //   k_adj_bs_apply  : those contributions added in subsystem order
 //   k_adj_sum3 / k_adj_momentum : sum of an adjoint over all bodies and the
 //                     resulting momentum term (jumps, DH <-> heliocentric)
+//   k_adj_copy, k_adj_copy_tape : the per-step record (state, subsystem table,
+//                     accepted Bulirsch-Stoer steps) kept for the reverse pass
 #include <hip/hip_runtime.h>
 
 #include "device_math.h"
@@ -409,7 +411,7 @@ __device__ __forceinline__ void pair_f(double s2, double rc, double& f, double& 
 // ------------------------------------------------------------------ kick
 // Partials per wave: [4 nb] source terms (3 position, 1 mass), [3] sum of the
 // updated lx over the wave's bodies, [3] momentum term of the drag.
-__device__ __forceinline__ int part_stride(int nb) { return 4 * nb + 6; }
+__host__ __device__ __forceinline__ int part_stride(int nb) { return 4 * nb + 6; }
 
 // One half kick u' = u + hh (a(x) + ad(x, u + P/mu0)) taken back: g = lu (the
 // adjoint of u'); x: positions of the kick; up: velocities before it.
@@ -502,53 +504,43 @@ __global__ __launch_bounds__(kBlock) void k_adj_kick(
   }
 }
 
-// Fixed-order sums of the kick partials over the nw waves.  Source terms go to
-// the massive bodies (lx, lmu).  The momentum adjoint lP = jump_coef * (sum of
-// the updated lx over all bodies) + (drag term) then feeds lu and lmu of the
-// massive bodies through P = sum mu_k u_k, u_k = up_k.
-__global__ __launch_bounds__(64) void k_adj_kick_sum(int n, int nb, int nw,
-                                                     const double* __restrict__ part,
-                                                     double jump_coef,
-                                                     const double* __restrict__ mu,
-                                                     const double* __restrict__ up,
-                                                     double* __restrict__ lx,
-                                                     double* __restrict__ lu,
-                                                     double* __restrict__ lmu) {
-  __shared__ double src[kSmallBig][3];
-  __shared__ double tot[6];
+// Fixed-order sum over the nw waves of value v of the wave partials (stride S):
+// lane l adds waves l, l + 64, ... in order, then a fixed butterfly.
+__global__ __launch_bounds__(64) void k_adj_reduce(const double* __restrict__ part, int nw, int S,
+                                                   double* __restrict__ tot) {
+  const int v = blockIdx.x;
+  double a = 0.0;
+  for (int w = threadIdx.x; w < nw; w += 64) a += part[(size_t)w * S + v];
+  a = wave_sum(a);
+  if (threadIdx.x == 0) tot[v] = a;
+}
+
+// Kick totals applied: source terms to the massive bodies (lx, lmu); the
+// momentum adjoint lP = jump_coef * (sum of the updated lx over all bodies) +
+// (drag term) feeds lu and lmu of the massive bodies through P = sum mu_k up_k.
+__global__ __launch_bounds__(64) void k_adj_kick_apply(int n, int nb,
+                                                       const double* __restrict__ tot,
+                                                       double jump_coef,
+                                                       const double* __restrict__ mu,
+                                                       const double* __restrict__ up,
+                                                       double* __restrict__ lx,
+                                                       double* __restrict__ lu,
+                                                       double* __restrict__ lmu) {
   const int tid = threadIdx.x;
-  const int S = part_stride(nb);
-  if (tid < nb) {
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int w = 0; w < nw; ++w)
-      for (int c = 0; c < 4; ++c) a[c] += part[(size_t)w * S + 4 * tid + c];
-    for (int c = 0; c < 3; ++c) {
-      lx[c * n + tid] += a[c];
-      src[tid][c] = a[c];
-    }
-    lmu[tid] += a[3];
+  if (tid >= nb) return;
+  double lP[3];
+  for (int c = 0; c < 3; ++c) {
+    double sx = tot[4 * nb + c];
+    for (int s = 0; s < nb; ++s) sx += tot[4 * s + c];
+    lP[c] = jump_coef * sx + tot[4 * nb + 3 + c];
   }
-  if (tid >= 32 && tid < 38) {
-    const int c = tid - 32;
-    double a = 0.0;
-    for (int w = 0; w < nw; ++w) a += part[(size_t)w * S + 4 * nb + c];
-    tot[c] = a;
+  double dm = tot[4 * tid + 3];
+  for (int c = 0; c < 3; ++c) {
+    lx[c * n + tid] += tot[4 * tid + c];
+    lu[c * n + tid] += mu[tid] * lP[c];
+    dm += up[c * n + tid] * lP[c];
   }
-  __syncthreads();
-  if (tid < nb) {
-    double lP[3];
-    for (int c = 0; c < 3; ++c) {
-      double sx = tot[c];
-      for (int s = 0; s < nb; ++s) sx += src[s][c];
-      lP[c] = jump_coef * sx + tot[3 + c];
-    }
-    double dm = 0.0;
-    for (int c = 0; c < 3; ++c) {
-      lu[c * n + tid] += mu[tid] * lP[c];
-      dm += up[c * n + tid] * lP[c];
-    }
-    lmu[tid] += dm;
-  }
+  lmu[tid] += dm;
 }
 
 // ------------------------------------------------------------------ sums
@@ -565,35 +557,27 @@ __global__ __launch_bounds__(kBlock) void k_adj_sum3(int n, const double* __rest
   }
 }
 
-// lP = coef * (sum of the wave partials); lu_k += mu_k lP, lmu_k += uref_k . lP
-__global__ __launch_bounds__(64) void k_adj_momentum(int n, int nb, int nw,
-                                                     const double* __restrict__ part, double coef,
-                                                     const double* __restrict__ mu,
+// lP = coef * tot[0..2]; lu_k += mu_k lP, lmu_k += uref_k . lP
+__global__ __launch_bounds__(64) void k_adj_momentum(int n, int nb, const double* __restrict__ tot,
+                                                     double coef, const double* __restrict__ mu,
                                                      const double* __restrict__ uref,
                                                      double* __restrict__ lu,
                                                      double* __restrict__ lmu) {
-  __shared__ double tot[3];
   const int tid = threadIdx.x;
-  if (tid < 3) {
-    double a = 0.0;
-    for (int w = 0; w < nw; ++w) a += part[(size_t)w * 3 + tid];
-    tot[tid] = coef * a;
+  if (tid >= nb) return;
+  double dm = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double lP = coef * tot[c];
+    lu[c * n + tid] += mu[tid] * lP;
+    dm += uref[c * n + tid] * lP;
   }
-  __syncthreads();
-  if (tid < nb) {
-    double dm = 0.0;
-    for (int c = 0; c < 3; ++c) {
-      lu[c * n + tid] += mu[tid] * tot[c];
-      dm += uref[c * n + tid] * tot[c];
-    }
-    lmu[tid] += dm;
-  }
+  lmu[tid] += dm;
 }
 
 // ------------------------------------------------------------------ drift
-__global__ void k_adj_mark(const Subsystem* __restrict__ subs, const DevScalars* __restrict__ dsc,
+__global__ void k_adj_mark(const Subsystem* __restrict__ subs, const int32_t* __restrict__ n_sub,
                            int32_t* __restrict__ kept, int32_t val) {
-  const int nsub = dsc->n_sub;
+  const int nsub = *n_sub;
   for (int b = blockIdx.x; b < nsub; b += gridDim.x) {
     const Subsystem& S = subs[b];
     for (int k = S.keep_from + threadIdx.x; k < S.m; k += blockDim.x) kept[S.mem[k]] = val;
@@ -786,7 +770,7 @@ __global__ __launch_bounds__(64) void k_adj_bs(int n, int nb, double mu0,
                                                const double* __restrict__ mu,
                                                const double* __restrict__ rcrit,
                                                const Subsystem* __restrict__ subs,
-                                               const DevScalars* __restrict__ dsc,
+                                               const int32_t* __restrict__ n_sub,
                                                const double* __restrict__ sched,
                                                const int32_t* __restrict__ nsched,
                                                const double* __restrict__ lx,
@@ -795,7 +779,7 @@ __global__ __launch_bounds__(64) void k_adj_bs(int n, int nb, double mu0,
                                                int32_t* __restrict__ err) {
   __shared__ double xs[12], vs[12], mum[4], rcm[4], lxo[12], luo[12];
   const int lane = threadIdx.x;
-  const int nsub = dsc->n_sub;
+  const int nsub = *n_sub;
   for (int b = blockIdx.x; b < nsub; b += gridDim.x) {
     const Subsystem& S = subs[b];
     const int m = S.m;
@@ -836,10 +820,10 @@ __global__ __launch_bounds__(64) void k_adj_bs(int n, int nb, double mu0,
 // Adds the subsystem contributions in subsystem order: thread k < nb walks all
 // subsystems for massive body k; massless members belong to one subsystem only.
 __global__ void k_adj_bs_apply(int n, int nb, const Subsystem* __restrict__ subs,
-                               const DevScalars* __restrict__ dsc,
+                               const int32_t* __restrict__ n_sub,
                                const double* __restrict__ contrib, double* __restrict__ lx,
                                double* __restrict__ lu, double* __restrict__ lmu) {
-  const int nsub = dsc->n_sub;
+  const int nsub = *n_sub;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   if (tid < nb) {
     double ax[3] = {0.0, 0.0, 0.0}, av[3] = {0.0, 0.0, 0.0}, am = 0.0;
@@ -885,7 +869,7 @@ __global__ void k_adj_bs_apply(int n, int nb, const Subsystem* __restrict__ subs
 // over the massive bodies.  lu_sum (device [3]) is the sum of lu over all
 // bodies; gm[k] = dL/dm_k = G lmu_k + the mass term of V; gv = lu + the V term.
 __global__ __launch_bounds__(64) void k_adj_h2dh(int n, int nb, double G, double m0,
-                                                 const double* __restrict__ part, int nw,
+                                                 const double* __restrict__ tot,
                                                  const double* __restrict__ m_big,
                                                  const double* __restrict__ v_h,
                                                  const double* __restrict__ lmu,
@@ -898,10 +882,9 @@ __global__ __launch_bounds__(64) void k_adj_h2dh(int n, int nb, double G, double
     for (int k = 0; k < nb; ++k) M += m_big[k];
     Mt = M;
     for (int c = 0; c < 3; ++c) {
-      double a = 0.0, pv = 0.0;
-      for (int w = 0; w < nw; ++w) a += part[(size_t)w * 3 + c];
+      double pv = 0.0;
       for (int k = 0; k < nb; ++k) pv += m_big[k] * v_h[c * n + k];
-      lV[c] = -a;
+      lV[c] = -tot[c];
       Vc[c] = pv / M;
     }
   }
@@ -916,52 +899,102 @@ __global__ __launch_bounds__(64) void k_adj_h2dh(int n, int nb, double G, double
   }
 }
 
+// Copies of the step state in one launch: up to four arrays of given lengths
+// packed one after another in dst (or unpacked from src when unpack != 0).
+struct CopyList {
+  double* ptr[4];
+  int64_t len[4];
+};
+
+__global__ __launch_bounds__(kBlock) void k_adj_copy(CopyList l, double* __restrict__ packed,
+                                                     int unpack) {
+  int64_t off = 0;
+  for (int a = 0; a < 4; ++a) {
+    const int64_t m = l.len[a];
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * kBlock) {
+      if (unpack) l.ptr[a][i] = packed[off + i];
+      else packed[off + i] = l.ptr[a][i];
+    }
+    off += m;
+  }
+}
+
+// the subsystem table of a step (its n_sub entries), n_sub, and the accepted
+// Bulirsch-Stoer steps of those subsystems
+__global__ void k_adj_copy_tape(const Subsystem* __restrict__ subs,
+                                const DevScalars* __restrict__ dsc,
+                                const double* __restrict__ sched,
+                                const int32_t* __restrict__ nsched, Subsystem* __restrict__ dsubs,
+                                int32_t* __restrict__ n_sub_out, double* __restrict__ dsched,
+                                int32_t* __restrict__ dnsched) {
+  const int nsub = dsc->n_sub;
+  const int words = (int)(sizeof(Subsystem) / 4);
+  const int32_t* src = reinterpret_cast<const int32_t*>(subs);
+  int32_t* out = reinterpret_cast<int32_t*>(dsubs);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < (int64_t)nsub * words; i += stride) out[i] = src[i];
+  for (int64_t i = i0; i < (int64_t)nsub * kBsMaxSched * 2; i += stride) dsched[i] = sched[i];
+  for (int64_t i = i0; i < nsub; i += stride) dnsched[i] = nsched[i];
+  if (i0 == 0) *n_sub_out = nsub;
+}
+
 int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
 }  // namespace
 
 namespace mxk {
 
-// adjoint of the closing (phase 2) or opening (phase 1) half kick of a step,
-// with the jump that follows (phase 2: jump_coef = hh / mu0) or none (0)
+hipError_t adj_reduce(hipStream_t st, const double* part, int nw, int S, double* tot) {
+  hipLaunchKernelGGL(k_adj_reduce, dim3(S), dim3(64), 0, st, part, nw, S, tot);
+  return hipGetLastError();
+}
+
+// adjoint of the closing (jump_coef = hh / mu0: with the jump before it) or
+// opening (0) half kick of a step
 hipError_t adj_kick(hipStream_t st, int n, int nb, double mu0, double hh,
                     const mxd::DragConst& dc, int gas_on, const double* x, const double* up,
                     const double* mu, const double* rcrit, const double* r_p,
                     const double* rho_p, double* lx, double* lu, double* lmu, double* part,
-                    double jump_coef) {
+                    double* tot, double jump_coef) {
   if (nb > kSmallBig) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_adj_kick, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, nb, mu0, hh, dc,
                      gas_on, x, up, mu, rcrit, r_p, rho_p, lx, lu, part);
-  const int nw = (n + 63) / 64;
-  hipLaunchKernelGGL(k_adj_kick_sum, dim3(1), dim3(64), 0, st, n, nb, nw, part, jump_coef, mu,
-                     up, lx, lu, lmu);
+  hipError_t e = adj_reduce(st, part, (n + 63) / 64, part_stride(nb), tot);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_kick_apply, dim3(1), dim3(64), 0, st, n, nb, tot, jump_coef, mu, up,
+                     lx, lu, lmu);
   return hipGetLastError();
 }
 
 // lP = coef * sum_t a_t; lu_k += mu_k lP; lmu_k += uref_k . lP
 hipError_t adj_momentum(hipStream_t st, int n, int nb, const double* a, double coef,
                         const double* mu, const double* uref, double* lu, double* lmu,
-                        double* part) {
+                        double* part, double* tot) {
   hipLaunchKernelGGL(k_adj_sum3, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, a, part);
-  hipLaunchKernelGGL(k_adj_momentum, dim3(1), dim3(64), 0, st, n, nb, (n + 63) / 64, part, coef,
-                     mu, uref, lu, lmu);
+  hipError_t e = adj_reduce(st, part, (n + 63) / 64, 3, tot);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_momentum, dim3(1), dim3(64), 0, st, n, nb, tot, coef, mu, uref, lu,
+                     lmu);
   return hipGetLastError();
 }
 
-// adjoint of the drift and encounter integration of a step
+// adjoint of the drift and encounter integration of a step (tape: pre-drift
+// state x0, u0, the step's subsystem table and count, the accepted BS steps)
 hipError_t adj_drift(hipStream_t st, int n, int nb, double mu0, double h, const double* x0,
                      const double* u0, const double* mu, const double* rcrit,
-                     const Subsystem* subs, const DevScalars* dsc, const double* sched,
+                     const Subsystem* subs, const int32_t* n_sub, const double* sched,
                      const int32_t* nsched, int32_t* kept, double* contrib, double* lx,
                      double* lu, double* lmu, int32_t* err) {
-  hipLaunchKernelGGL(k_adj_mark, dim3(256), dim3(64), 0, st, subs, dsc, kept, 1);
+  hipLaunchKernelGGL(k_adj_mark, dim3(256), dim3(64), 0, st, subs, n_sub, kept, 1);
   hipLaunchKernelGGL(k_adj_bs, dim3(256), dim3(64), 0, st, n, nb, mu0, x0, u0, mu, rcrit, subs,
-                     dsc, sched, nsched, lx, lu, contrib, err);
+                     n_sub, sched, nsched, lx, lu, contrib, err);
   hipLaunchKernelGGL(k_adj_drift, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, mu0, h, x0, u0,
                      kept, lx, lu, err);
-  hipLaunchKernelGGL(k_adj_bs_apply, dim3(4), dim3(256), 0, st, n, nb, subs, dsc, contrib, lx,
+  hipLaunchKernelGGL(k_adj_bs_apply, dim3(4), dim3(256), 0, st, n, nb, subs, n_sub, contrib, lx,
                      lu, lmu);
-  hipLaunchKernelGGL(k_adj_mark, dim3(256), dim3(64), 0, st, subs, dsc, kept, 0);
+  hipLaunchKernelGGL(k_adj_mark, dim3(256), dim3(64), 0, st, subs, n_sub, kept, 0);
   return hipGetLastError();
 }
 
@@ -969,13 +1002,39 @@ hipError_t adj_drift(hipStream_t st, int n, int nb, double mu0, double h, const 
 // adjoint of the DH start state: gx = lx, gv = lu + V term, gm
 hipError_t adj_h2dh(hipStream_t st, int n, int nb, double G, double m0, const double* m_big,
                     const double* v_h, const double* lu, const double* lmu, double* gm,
-                    double* gv, double* part) {
+                    double* gv, double* part, double* tot) {
   hipLaunchKernelGGL(k_adj_sum3, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, lu, part);
-  hipError_t e = hipMemcpyAsync(gv, lu, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToDevice,
-                                st);
+  hipError_t e = adj_reduce(st, part, (n + 63) / 64, 3, tot);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_h2dh, dim3(1), dim3(64), 0, st, n, nb, G, m0, part, (n + 63) / 64,
-                     m_big, v_h, lmu, gm, gv);
+  e = hipMemcpyAsync(gv, lu, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_h2dh, dim3(1), dim3(64), 0, st, n, nb, G, m0, tot, m_big, v_h, lmu,
+                     gm, gv);
+  return hipGetLastError();
+}
+
+// pack (unpack != 0: unpack) up to four arrays into / from one buffer
+hipError_t adj_copy(hipStream_t st, double* const* ptr, const int64_t* len, int count,
+                    double* packed, int unpack) {
+  CopyList l;
+  int64_t tot = 0;
+  for (int a = 0; a < 4; ++a) {
+    l.ptr[a] = a < count ? ptr[a] : nullptr;
+    l.len[a] = a < count ? len[a] : 0;
+    tot += l.len[a];
+  }
+  int64_t blocks = (tot / 4 + kBlock - 1) / kBlock;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_adj_copy, dim3((unsigned)blocks), dim3(kBlock), 0, st, l, packed, unpack);
+  return hipGetLastError();
+}
+
+hipError_t adj_copy_tape(hipStream_t st, const Subsystem* subs, const DevScalars* dsc,
+                         const double* sched, const int32_t* nsched, Subsystem* dsubs,
+                         int32_t* n_sub_out, double* dsched, int32_t* dnsched) {
+  hipLaunchKernelGGL(k_adj_copy_tape, dim3(64), dim3(256), 0, st, subs, dsc, sched, nsched, dsubs,
+                     n_sub_out, dsched, dnsched);
   return hipGetLastError();
 }
 

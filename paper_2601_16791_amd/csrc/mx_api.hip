@@ -955,20 +955,29 @@ hipError_t adj_kick(hipStream_t st, int n, int nb, double mu0, double hh,
                     const mxd::DragConst& dc, int gas_on, const double* x, const double* up,
                     const double* mu, const double* rcrit, const double* r_p,
                     const double* rho_p, double* lx, double* lu, double* lmu, double* part,
-                    double jump_coef);
+                    double* tot, double jump_coef);
 hipError_t adj_momentum(hipStream_t st, int n, int nb, const double* a, double coef,
                         const double* mu, const double* uref, double* lu, double* lmu,
-                        double* part);
+                        double* part, double* tot);
 hipError_t adj_drift(hipStream_t st, int n, int nb, double mu0, double h, const double* x0,
                      const double* u0, const double* mu, const double* rcrit,
-                     const Subsystem* subs, const DevScalars* dsc, const double* sched,
+                     const Subsystem* subs, const int32_t* n_sub, const double* sched,
                      const int32_t* nsched, int32_t* kept, double* contrib, double* lx,
                      double* lu, double* lmu, int32_t* err);
 hipError_t adj_h2dh(hipStream_t st, int n, int nb, double G, double m0, const double* m_big,
                     const double* v_h, const double* lu, const double* lmu, double* gm,
-                    double* gv, double* part);
+                    double* gv, double* part, double* tot);
+hipError_t adj_copy(hipStream_t st, double* const* ptr, const int64_t* len, int count,
+                    double* packed, int unpack);
+hipError_t adj_copy_tape(hipStream_t st, const Subsystem* subs, const DevScalars* dsc,
+                         const double* sched, const int32_t* nsched, Subsystem* dsubs,
+                         int32_t* n_sub_out, double* dsched, int32_t* dnsched);
 }  // namespace mxk
 
+// A differentiable run.  Per step of the segment being reversed, the record
+// ("tape") keeps the pre-drift state x0, u0, the velocities after drift and
+// encounters, the positions after the step, the subsystem table, its size and
+// the accepted Bulirsch-Stoer steps.
 struct mx_adjoint {
   mx_system* s;
   int32_t n_steps, every, n_ckpt;
@@ -976,10 +985,15 @@ struct mx_adjoint {
   double* ckpt;      // [n_ckpt][blk]: states at steps 0, every, 2 every, ...
   double* seg;       // [every][blk]: step-start states of the segment being reversed
   double* fin;       // [blk]: state after the last step
-  double *mid_x, *mid_u;  // [3][n]: positions and velocities after drift and encounters
+  double* tape;      // [every][12 n]: x0, u0, u after drift/encounters, x after the step
+  Subsystem* tsubs;  // [every][cap_subs]
+  int32_t* tnsub;    // [every]
+  double* tsched;    // [every][cap_subs][kBsMaxSched][2]
+  int32_t* tnsched;  // [every][cap_subs]
   double *lx, *lu, *lmu;  // adjoints of x, u [3][n] and of mu [n_big]
   double* part;      // wave partials
-  double* sched;     // [cap_subs][kBsMaxSched][2]
+  double* tot;       // reduced partials
+  double* sched;     // [cap_subs][kBsMaxSched][2] written by the forward integrator
   int32_t* nsched;   // [cap_subs]
   double* contrib;   // [cap_subs][28]
   int32_t* kept;     // [n]
@@ -996,77 +1010,85 @@ void free_adjoint(mx_adjoint* a) {
     a->s->owned = false;
     mx_destroy(a->s);
   }
-  void* ptrs[] = {a->ckpt, a->seg, a->fin, a->mid_x, a->mid_u, a->lx, a->lu, a->lmu, a->part,
-                  a->sched, a->nsched, a->contrib, a->kept, a->m_big, a->v_h0, a->gm, a->gv};
+  void* ptrs[] = {a->ckpt, a->seg, a->fin, a->tape, a->tsubs, a->tnsub, a->tsched, a->tnsched,
+                  a->lx, a->lu, a->lmu, a->part, a->tot, a->sched, a->nsched, a->contrib,
+                  a->kept, a->m_big, a->v_h0, a->gm, a->gv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete a;
 }
 
-hipError_t save_state(mx_adjoint* a, double* dst) {
+// pack (x, u, ag, bigsnap) of the system into dst, or unpack src into it
+hipError_t state_copy(mx_adjoint* a, double* buf, int unpack) {
   mx_system* s = a->s;
-  const size_t n3 = 3 * (size_t)s->n;
-  hipError_t e = hipMemcpyAsync(dst, s->x, n3 * 8, hipMemcpyDeviceToDevice, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(dst + n3, s->u, n3 * 8, hipMemcpyDeviceToDevice, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(dst + 2 * n3, s->ag, n3 * 8, hipMemcpyDeviceToDevice, s->stream);
-  if (e == hipSuccess && s->nb > 0)
-    e = hipMemcpyAsync(dst + 3 * n3, s->bigsnap, 9 * (size_t)s->nb * 8, hipMemcpyDeviceToDevice,
-                       s->stream);
-  return e;
+  const int64_t n3 = 3 * (int64_t)s->n;
+  double* ptr[4] = {s->x, s->u, s->ag, s->bigsnap};
+  int64_t len[4] = {n3, n3, n3, 9 * (int64_t)s->nb};
+  return mxk::adj_copy(s->stream, ptr, len, 4, buf, unpack);
 }
 
 hipError_t restore_state(mx_adjoint* a, const double* src, int64_t step) {
-  mx_system* s = a->s;
-  const size_t n3 = 3 * (size_t)s->n;
-  hipError_t e = hipMemcpyAsync(s->x, src, n3 * 8, hipMemcpyDeviceToDevice, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(s->u, src + n3, n3 * 8, hipMemcpyDeviceToDevice, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(s->ag, src + 2 * n3, n3 * 8, hipMemcpyDeviceToDevice, s->stream);
-  if (e == hipSuccess && s->nb > 0)
-    e = hipMemcpyAsync(s->bigsnap, src + 3 * n3, 9 * (size_t)s->nb * 8, hipMemcpyDeviceToDevice,
-                       s->stream);
-  if (e == hipSuccess) e = mxk::launch_reset_scalars(s, step);
+  hipError_t e = state_copy(a, const_cast<double*>(src), 1);
+  if (e == hipSuccess) e = mxk::launch_reset_scalars(a->s, step);
   return e;
 }
 
-// one step with the state after drift and encounters kept in mid_x, mid_u
-hipError_t instrumented_step(mx_adjoint* a) {
+// one step from the current state, recording slot q of the tape
+hipError_t recorded_step(mx_adjoint* a, int q) {
   mx_system* s = a->s;
+  const int64_t n3 = 3 * (int64_t)s->n;
+  double* tp = a->tape + (size_t)q * 4 * n3;
   hipError_t e = hipSuccess;
   for (int k = 0; k < MX_NUM_KERNELS && e == hipSuccess; ++k) {
     if (k == MX_K_JUMP_PACK) {
-      const size_t b3 = 3 * (size_t)s->n * 8;
-      e = hipMemcpyAsync(a->mid_x, s->x, b3, hipMemcpyDeviceToDevice, s->stream);
-      if (e == hipSuccess) e = hipMemcpyAsync(a->mid_u, s->u, b3, hipMemcpyDeviceToDevice, s->stream);
+      // after drift and encounters: x0, u0 (pre-drift) and u
+      double* ptr[3] = {s->x0, s->u0, s->u};
+      int64_t len[3] = {n3, n3, n3};
+      e = mxk::adj_copy(s->stream, ptr, len, 3, tp, 0);
+      if (e == hipSuccess)
+        e = mxk::adj_copy_tape(s->stream, s->subs, s->dsc, a->sched, a->nsched,
+                               a->tsubs + (size_t)q * s->cap_subs, a->tnsub + q,
+                               a->tsched + (size_t)q * s->cap_subs * kBsMaxSched * 2,
+                               a->tnsched + (size_t)q * s->cap_subs);
     }
     if (e == hipSuccess) e = launch_group(s, k);
+  }
+  if (e == hipSuccess) {
+    double* ptr[1] = {s->x};
+    int64_t len[1] = {n3};
+    e = mxk::adj_copy(s->stream, ptr, len, 1, tp + 3 * n3, 0);
   }
   return e;
 }
 
-// adjoint of one step whose forward was just run by instrumented_step from the
-// step-start state `start` (x_a, u_a)
-hipError_t reverse_step(mx_adjoint* a, const double* start) {
+// adjoint of the step recorded in slot q, whose start state is `start`
+hipError_t reverse_step(mx_adjoint* a, int q, const double* start) {
   mx_system* s = a->s;
   const int n = s->n, nb = s->nb;
   const double h = s->p.dt, hh = 0.5 * h, mu0 = s->mu0;
   const mxd::DragConst dc = mxd::make_drag_const(s->p);
   const size_t n3 = 3 * (size_t)n;
+  const double* tp = a->tape + (size_t)q * 4 * n3;
+  const double *x0 = tp, *u0 = tp + n3, *ud = tp + 2 * n3, *xe = tp + 3 * n3;
   hipError_t e;
   // closing half kick at the final positions, with the jump before it
-  e = mxk::adj_kick(s->stream, n, nb, mu0, hh, dc, s->p.gas_on, s->x, a->mid_u, s->mu, s->rcrit,
-                    s->r_p, s->rho_p, a->lx, a->lu, a->lmu, a->part, hh / mu0);
+  e = mxk::adj_kick(s->stream, n, nb, mu0, hh, dc, s->p.gas_on, xe, ud, s->mu, s->rcrit, s->r_p,
+                    s->rho_p, a->lx, a->lu, a->lmu, a->part, a->tot, hh / mu0);
   if (e != hipSuccess) return e;
   // Kepler drift / encounter integration from the pre-drift state (x0, u0)
-  e = mxk::adj_drift(s->stream, n, nb, mu0, h, s->x0, s->u0, s->mu, s->rcrit, s->subs, s->dsc,
-                     a->sched, a->nsched, a->kept, a->contrib, a->lx, a->lu, a->lmu,
-                     &s->dsc->err);
+  e = mxk::adj_drift(s->stream, n, nb, mu0, h, x0, u0, s->mu, s->rcrit,
+                     a->tsubs + (size_t)q * s->cap_subs, a->tnsub + q,
+                     a->tsched + (size_t)q * s->cap_subs * kBsMaxSched * 2,
+                     a->tnsched + (size_t)q * s->cap_subs, a->kept, a->contrib, a->lx, a->lu,
+                     a->lmu, &s->dsc->err);
   if (e != hipSuccess) return e;
   // first jump: x0 = x_a + hh P(u0) / mu0
-  e = mxk::adj_momentum(s->stream, n, nb, a->lx, hh / mu0, s->mu, s->u0, a->lu, a->lmu, a->part);
+  e = mxk::adj_momentum(s->stream, n, nb, a->lx, hh / mu0, s->mu, u0, a->lu, a->lmu, a->part,
+                        a->tot);
   if (e != hipSuccess) return e;
   // opening half kick at the step-start state
   return mxk::adj_kick(s->stream, n, nb, mu0, hh, dc, s->p.gas_on, start, start + n3, s->mu,
-                       s->rcrit, s->r_p, s->rho_p, a->lx, a->lu, a->lmu, a->part, 0.0);
+                       s->rcrit, s->r_p, s->rho_p, a->lx, a->lu, a->lmu, a->part, a->tot, 0.0);
 }
 
 }  // namespace
@@ -1103,9 +1125,12 @@ mx_status mx_adjoint_create(const mx_params* p, const double* x_h, const double*
   hipError_t e = hipSuccess;
 #define ALLOC(ptr, cnt) \
   if (e == hipSuccess) e = dalloc(&(ptr), (size_t)(cnt));
+  const size_t cs = (size_t)s->cap_subs;
   ALLOC(a->ckpt, a->n_ckpt * a->blk) ALLOC(a->seg, a->every * a->blk) ALLOC(a->fin, a->blk)
-  ALLOC(a->mid_x, n3) ALLOC(a->mid_u, n3) ALLOC(a->lx, n3) ALLOC(a->lu, n3) ALLOC(a->lmu, nb)
-  ALLOC(a->part, nwaves * (4 * (size_t)kSmallBig + 6))
+  ALLOC(a->tape, a->every * 4 * n3) ALLOC(a->tsubs, a->every * cs) ALLOC(a->tnsub, a->every)
+  ALLOC(a->tsched, a->every * cs * kBsMaxSched * 2) ALLOC(a->tnsched, a->every * cs)
+  ALLOC(a->lx, n3) ALLOC(a->lu, n3) ALLOC(a->lmu, nb)
+  ALLOC(a->part, nwaves * (4 * (size_t)kSmallBig + 6)) ALLOC(a->tot, 4 * (size_t)kSmallBig + 6)
   ALLOC(a->sched, (size_t)s->cap_subs * kBsMaxSched * 2) ALLOC(a->nsched, s->cap_subs)
   ALLOC(a->contrib, (size_t)s->cap_subs * 28) ALLOC(a->kept, n) ALLOC(a->m_big, nb)
   ALLOC(a->v_h0, n3) ALLOC(a->gm, nb) ALLOC(a->gv, n3)
@@ -1128,7 +1153,7 @@ mx_status mx_adjoint_create(const mx_params* p, const double* x_h, const double*
     d.bs_nsched = a->nsched;
     e = hipMemcpy(s->desc, &d, sizeof(SysDesc), hipMemcpyHostToDevice);
   }
-  if (e == hipSuccess) e = save_state(a, a->ckpt);  // the start state
+  if (e == hipSuccess) e = state_copy(a, a->ckpt, 0);  // the start state
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) {
     free_adjoint(a);
@@ -1148,10 +1173,11 @@ mx_status mx_adjoint_forward(mx_adjoint* a, double* x_h, double* v_h, int is_dev
   mx_system* s = a->s;
   HIPCHK(restore_state(a, a->ckpt, 0), "restore start");
   for (int32_t j = 0; j < a->n_steps; ++j) {
-    if (j % a->every == 0) HIPCHK(save_state(a, a->ckpt + (size_t)(j / a->every) * a->blk), "checkpoint");
+    if (j % a->every == 0 && j > 0)
+      HIPCHK(state_copy(a, a->ckpt + (size_t)(j / a->every) * a->blk, 0), "checkpoint");
     HIPCHK(enqueue_step(s), "step");
   }
-  HIPCHK(save_state(a, a->fin), "final state");
+  HIPCHK(state_copy(a, a->fin, 0), "final state");
   s->host_step = a->n_steps;
   mx_status st = read_err(s);
   if (st != MX_OK) return st;
@@ -1174,25 +1200,23 @@ mx_status mx_adjoint_backward(mx_adjoint* a, const double* gx, const double* gv,
   if (nb > 0) HIPCHK(hipMemsetAsync(a->lmu, 0, sizeof(double) * nb, st), "zero lmu");
   // final heliocentric velocities v = u + P / mu0
   HIPCHK(mxk::adj_momentum(st, n, nb, a->lu, 1.0 / s->mu0, s->mu, a->fin + n3, a->lu, a->lmu,
-                           a->part),
+                           a->part, a->tot),
          "final velocities");
   for (int c = a->n_ckpt - 1; c >= 0; --c) {
     const int32_t j0 = c * a->every;
     const int32_t j1 = j0 + a->every < a->n_steps ? j0 + a->every : a->n_steps;
+    // forward over the segment, recording every step
     HIPCHK(restore_state(a, a->ckpt + (size_t)c * a->blk, j0), "restore checkpoint");
     for (int32_t j = j0; j < j1; ++j) {
-      HIPCHK(save_state(a, a->seg + (size_t)(j - j0) * a->blk), "segment state");
-      if (j + 1 < j1) HIPCHK(enqueue_step(s), "segment step");
+      HIPCHK(state_copy(a, a->seg + (size_t)(j - j0) * a->blk, 0), "segment state");
+      HIPCHK(recorded_step(a, j - j0), "recorded step");
     }
-    for (int32_t j = j1 - 1; j >= j0; --j) {
-      const double* start = a->seg + (size_t)(j - j0) * a->blk;
-      HIPCHK(restore_state(a, start, j), "restore step");
-      HIPCHK(instrumented_step(a), "recompute step");
-      HIPCHK(reverse_step(a, start), "adjoint step");
-    }
+    // and back
+    for (int32_t j = j1 - 1; j >= j0; --j)
+      HIPCHK(reverse_step(a, j - j0, a->seg + (size_t)(j - j0) * a->blk), "adjoint step");
   }
   hipError_t e = mxk::adj_h2dh(st, n, nb, s->p.G, s->p.m0, a->m_big, a->v_h0, a->lu, a->lmu,
-                               a->gm, a->gv, a->part);
+                               a->gm, a->gv, a->part, a->tot);
   if (e == hipSuccess) e = copy_out(g_x, a->lx, n3 * 8, is_device_ptr, st);
   if (e == hipSuccess) e = copy_out(g_v, a->gv, n3 * 8, is_device_ptr, st);
   if (e == hipSuccess && nb > 0) e = copy_out(g_m, a->gm, sizeof(double) * nb, is_device_ptr, st);
