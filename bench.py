@@ -160,7 +160,8 @@ def kick_fp64(args):
     a = FLOP_PER_INTERACTION * I / avg
     s.close()
     return {"workload": "self_gravitating", "n_big": nb, "interactions_per_kick": I,
-            "kernels": "k_force_split + k_force_finish (start of the first to end of the second)",
+            "kernels": "k_force_sym + k_force_finish_sym (start of the first to end of the "
+                       "second): massive pairs once each by tiles, Newton's third law",
             "avg_kick_us": avg * 1e6, "launches": n_launch, "achieved": a / 1e12,
             "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": a / PEAK_FP64,
             "interactions_per_s": I / avg, "steps_per_s": reps / T,

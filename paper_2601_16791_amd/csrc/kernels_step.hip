@@ -220,47 +220,210 @@ __global__ __launch_bounds__(kBlock) void k_force_kick(
   if (t < n) finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, ax, ay, az, x, u, ag, r_p, rho_p, P, &dsc->err, bigsnap);
 }
 
-// Split layout (many massive bodies): 256 targets per block, the four waves walk
-// the same source chunk (its records stay in the scalar cache), and the chunk
-// sums of the `split` blocks of a tile go to `part`.
-__global__ __launch_bounds__(kBlock) void k_force_split(
-    int n, int nb, int split, const double* __restrict__ x,
-    const KickSource* __restrict__ kpack, double* __restrict__ part) {
-  const int tile = blockIdx.x / split;
-  const int sp = blockIdx.x - tile * split;
-  const int t = tile * kBlock + threadIdx.x;
-  const int tt = t < n ? t : n - 1;
-  const double xt = x[tt], yt = x[n + tt], zt = x[2 * n + tt];
-  double rct = 0.0, rc2t = 0.0;
-  if (tt < nb) {
-    rct = kpack[tt].rc;
-    rc2t = rct * rct;
+// Symmetric layout of the massive-massive forces (Newton's third law, the
+// triangular form of the direct-force routine): every pair of 64-body tiles
+// I < J is one block.  Pass 1: lanes hold the bodies i of I, the four waves walk
+// the sources j of J (16 each, scalar loads), accumulate mu_j K/r^3 (x_j - x_i)
+// and store mu_i K/r^3 in LDS.  Pass 2: lanes hold the bodies j of J, the waves
+// walk i of I and read the stored weights transposed, so the reaction
+// -mu_i K/r^3 (x_j - x_i) costs no second inverse square root.  Diagonal tiles
+// I = J take pass 1 only, self pairs excluded.  Rows of 3 x 64 partial sums go
+// to `out` at [I][J] (forces on the bodies of I from J) and [J][I]; the finish
+// kernel adds the row of each source tile J in ascending order.
+constexpr int kSymT = 64;
+constexpr int kSymS = 65;  // LDS row stride in doubles (odd: transposed reads hit all banks)
+
+// pair weight K(r)/r^3 without the mass: fast branch, exact branch below the bound
+__device__ __forceinline__ double sym_weight(double s2, double rc2s, double rcs, double rc2t,
+                                             double rct, uint32_t wave_hi, double k15,
+                                             double k1875) {
+  double w = mxd::fast_weight(1.0, s2, k15, k1875);
+  if (__builtin_expect(s2 < mxd::upper_rc2(rc2s, wave_hi), 0)) {
+    const double rc2 = fmax(rc2s, rc2t);
+    if (s2 < rc2) w = mxd::changeover_weight_slow(s2, fmax(rcs, rct), rc2);
   }
-  const int per = (nb + split - 1) / split;
-  const int s0 = sp * per;
-  const int s1 = min(nb, s0 + per);
-  double ax, ay, az;
-  mxd::force_sum(kpack, s0, s1, xt, yt, zt, rc2t, rct, ax, ay, az);
-  if (t < n) {
-    size_t base = (size_t)sp * 3 * n;
-    part[base + t] = ax;
-    part[base + n + t] = ay;
-    part[base + 2 * n + t] = az;
+  return w;
+}
+
+// a packed record of a tile body in LDS: x, y, z, mu, rc2, rc
+struct SymRec {
+  double x, y, z, mu, rc2, rc;
+};
+
+template <bool DIAG>
+__device__ __forceinline__ void sym_block(int I, int J, int nb, int nT,
+                                          const KickSource* __restrict__ kp,
+                                          double* __restrict__ out, double* W,
+                                          double (*red)[3][kSymT], SymRec (*rec)[kSymT]) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  const int nI = min(kSymT, nb - I * kSymT), nJ = min(kSymT, nb - J * kSymT);
+  // stage the records of I (waves 0) and J (wave 1); absent bodies get mu 0
+  if (wv < (DIAG ? 1 : 2)) {
+    const int T = wv ? J : I;
+    const int nT_ = wv ? nJ : nI;
+    SymRec r;
+    if (lane < nT_) {
+      const KickSource k = kp[T * kSymT + lane];
+      r = SymRec{k.x, k.y, k.z, k.mu, k.rc2, k.rc};
+    } else {
+      r = SymRec{0.0, 0.0, 0.0, 0.0, 1e-300, 0.0};
+    }
+    rec[wv][lane] = r;
+  }
+  __syncthreads();
+  const SymRec* RI = rec[0];
+  const SymRec* RJ = rec[DIAG ? 0 : 1];
+  double k15, k1875;
+  mxd::vgpr_constants(k15, k1875);
+  // ---- pass 1: lanes = bodies of I, sources = this wave's 16 bodies of J, four
+  // per iteration (independent chains, one changeover branch for the four)
+  {
+    const SymRec me = RI[lane];
+    const double xi = me.x, yi = me.y, zi = me.z, mui = me.mu;
+    const double rci = lane < nI ? me.rc : 0.0, rc2i = rci * rci;
+    const uint32_t wave_hi = mxd::wave_max_hi(rc2i);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    const int j0 = 16 * wv;
+    const int jn = min(16, nJ - j0);
+    for (int k = 0; k < jn; k += 4) {
+      SymRec S[4];
+      double dx[4], dy[4], dz[4], s2[4], w[4];
+      bool near = false;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        S[q] = RJ[j0 + min(k + q, jn - 1)];
+        dx[q] = S[q].x - xi;
+        dy[q] = S[q].y - yi;
+        dz[q] = S[q].z - zi;
+        s2[q] = fma(dz[q], dz[q], fma(dy[q], dy[q], dx[q] * dx[q]));
+        w[q] = mxd::fast_weight(1.0, s2[q], k15, k1875);
+        near |= s2[q] < fmax(S[q].rc2, rc2i);
+      }
+      if (__builtin_expect(near, 0)) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double rc2 = fmax(S[q].rc2, rc2i);
+          if (s2[q] < rc2) w[q] = mxd::changeover_weight_slow(s2[q], fmax(S[q].rc, rci), rc2);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int jl = j0 + k + q;
+        if (k + q >= jn) break;  // wave-uniform
+        if (DIAG && jl == lane) w[q] = 0.0;
+        const double t = S[q].mu * w[q];
+        a0 = fma(t, dx[q], a0);
+        a1 = fma(t, dy[q], a1);
+        a2 = fma(t, dz[q], a2);
+        if (!DIAG) W[jl * kSymS + lane] = mui * w[q];
+      }
+    }
+    red[wv][0][lane] = a0;
+    red[wv][1][lane] = a1;
+    red[wv][2][lane] = a2;
+  }
+  __syncthreads();
+  if (wv == 0 && lane < nI) {
+    double* row = out + ((size_t)I * nT + J) * 3 * kSymT;  // forces on I from J
+    for (int c = 0; c < 3; ++c)
+      row[c * kSymT + lane] = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) +
+                              red[3][c][lane];
+  }
+  if (DIAG) return;
+  __syncthreads();
+  // ---- pass 2: lanes = bodies of J, reactions from this wave's 16 bodies of I
+  {
+    const SymRec me = RJ[lane];
+    const double xj = me.x, yj = me.y, zj = me.z;
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+    const int i0 = 16 * wv;
+    const int in = min(16, nI - i0);
+    for (int k = 0; k < in; k += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (k + q >= in) break;  // wave-uniform
+        const SymRec& S = RI[i0 + k + q];
+        const double w = W[lane * kSymS + i0 + k + q];
+        r0 = fma(w, S.x - xj, r0);
+        r1 = fma(w, S.y - yj, r1);
+        r2 = fma(w, S.z - zj, r2);
+      }
+    }
+    red[wv][0][lane] = r0;
+    red[wv][1][lane] = r1;
+    red[wv][2][lane] = r2;
+  }
+  __syncthreads();
+  if (wv == 0 && lane < nJ) {
+    double* rowJ = out + ((size_t)J * nT + I) * 3 * kSymT;  // forces on J from I
+    for (int c = 0; c < 3; ++c)
+      rowJ[c * kSymT + lane] = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) +
+                               red[3][c][lane];
   }
 }
 
-// sum of the split partials in split order, then drag and the half kick
-__global__ __launch_bounds__(kBlock) void k_force_finish(
-    int n, int nb, int split, double mu0, double hh, DragConst dc, int gas_on, int kick,
-    const double* __restrict__ x, double* __restrict__ u, double* __restrict__ ag,
+__global__ __launch_bounds__(256) void k_force_sym(int nb, int nT, int npairs,
+                                                   const KickSource* __restrict__ kp,
+                                                   double* __restrict__ out) {
+  __shared__ double W[kSymT * kSymS];
+  __shared__ double red[4][3][kSymT];
+  __shared__ SymRec rec[2][kSymT];
+  if ((int)blockIdx.x >= npairs) {
+    const int I = (int)blockIdx.x - npairs;
+    sym_block<true>(I, I, nb, nT, kp, out, W, red, rec);
+    return;
+  }
+  int p = blockIdx.x, I = 0;
+  while (p >= nT - 1 - I) {
+    p -= nT - 1 - I;
+    ++I;
+  }
+  sym_block<false>(I, I + 1 + p, nb, nT, kp, out, W, red, rec);
+}
+
+// massive bodies: the symmetric rows in source-tile order (four quarter sums of
+// consecutive source tiles, added in quarter order); massless bodies: the split
+// partials in split order; then drag and the half kick.  Blocks of 256 threads:
+// for massive bodies thread q * 64 + l adds quarter q for body l of the block's
+// tile; for massless bodies each thread finishes one body.
+__global__ __launch_bounds__(256) void k_force_finish_sym(
+    int n, int nb, int nT, int split, double mu0, double hh, DragConst dc, int gas_on,
+    int kick, const double* __restrict__ x, double* __restrict__ u, double* __restrict__ ag,
     const double* __restrict__ r_p, const double* __restrict__ rho_p,
-    const double* __restrict__ part, DevScalars* __restrict__ dsc,
-    double* __restrict__ bigsnap) {
-  const int t = blockIdx.x * 64 + threadIdx.x;
+    const double* __restrict__ sym, const double* __restrict__ part,
+    DevScalars* __restrict__ dsc, double* __restrict__ bigsnap) {
+  __shared__ double q3[4][3][kSymT];
   if (kick && blockIdx.x == 0 && threadIdx.x == 0) {
     dsc->step += 1;
     dsc->n_pairs = 0;  // the encounter list of this step has been planned
   }
+  double P[3] = {dsc->P[0], dsc->P[1], dsc->P[2]};
+  if ((int)blockIdx.x < nT) {
+    const int I = blockIdx.x;
+    const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int Ja = (q * nT) / 4, Jb = ((q + 1) * nT) / 4;
+    const double* row = sym + (size_t)I * nT * 3 * kSymT + l;
+    double bx = 0.0, by = 0.0, bz = 0.0;
+#pragma unroll 4
+    for (int J = Ja; J < Jb; ++J) {
+      bx += row[(size_t)J * 3 * kSymT];
+      by += row[(size_t)J * 3 * kSymT + kSymT];
+      bz += row[(size_t)J * 3 * kSymT + 2 * kSymT];
+    }
+    q3[q][0][l] = bx;
+    q3[q][1][l] = by;
+    q3[q][2][l] = bz;
+    __syncthreads();
+    const int t = I * kSymT + l;
+    if (q != 0 || t >= nb) return;
+    double a[3];
+    for (int c = 0; c < 3; ++c) a[c] = ((q3[0][c][l] + q3[1][c][l]) + q3[2][c][l]) + q3[3][c][l];
+    finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, a[0], a[1], a[2], x, u, ag, r_p, rho_p, P,
+                &dsc->err, bigsnap);
+    return;
+  }
+  const int t = nb + ((int)blockIdx.x - nT) * 256 + threadIdx.x;
   if (t >= n) return;
   double bx = 0.0, by = 0.0, bz = 0.0;
 #pragma unroll 8
@@ -270,8 +433,29 @@ __global__ __launch_bounds__(kBlock) void k_force_finish(
     by += part[base + n + t];
     bz += part[base + 2 * n + t];
   }
-  double P[3] = {dsc->P[0], dsc->P[1], dsc->P[2]};
   finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, bx, by, bz, x, u, ag, r_p, rho_p, P, &dsc->err, bigsnap);
+}
+
+// split layout for massless targets only (bodies first .. n - 1)
+__global__ __launch_bounds__(kBlock) void k_force_split_small(
+    int n, int nb, int first, int split, const double* __restrict__ x,
+    const KickSource* __restrict__ kpack, double* __restrict__ part) {
+  const int tile = blockIdx.x / split;
+  const int sp = blockIdx.x - tile * split;
+  const int t = first + tile * kBlock + threadIdx.x;
+  const int tt = t < n ? t : n - 1;
+  const double xt = x[tt], yt = x[n + tt], zt = x[2 * n + tt];
+  const int per = (nb + split - 1) / split;
+  const int s0 = sp * per;
+  const int s1 = min(nb, s0 + per);
+  double ax, ay, az;
+  mxd::force_sum(kpack, s0, s1, xt, yt, zt, 0.0, 0.0, ax, ay, az);
+  if (t < n) {
+    size_t base = (size_t)sp * 3 * n;
+    part[base + t] = ax;
+    part[base + n + t] = ay;
+    part[base + 2 * n + t] = az;
+  }
 }
 
 // stateless gravity (single-kernel entry): packs then sums, no kick
@@ -390,16 +574,24 @@ hipError_t launch_pack_only(mx_system* s) {
 hipError_t launch_force_kick(mx_system* s, int kick) {
   DragConst dc = make_drag_const(s->p);
   const double hh = 0.5 * s->p.dt;
-  if (s->split <= 1)
+  if (!s->use_sym)
     return mxlaunch(s, k_force_kick, dim3(blocks_for(s->n)), dim3(kBlock), s->n, s->nb, s->mu0,
                     hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->kpack, s->r_p, s->rho_p,
                     s->dsc, s->bigsnap);
-  hipError_t e = mxlaunch(s, k_force_split, dim3(blocks_for(s->n) * s->split), dim3(kBlock),
-                          s->n, s->nb, s->split, s->x, s->kpack, s->part);
+  // massive-massive block by symmetric tile pairs, massless targets by the split
+  const int nT = (s->nb + kSymT - 1) / kSymT;
+  const int npairs = nT * (nT - 1) / 2;
+  hipError_t e = mxlaunch(s, k_force_sym, dim3(npairs + nT), dim3(256), s->nb, nT, npairs,
+                          s->kpack, s->sympart);
   if (e != hipSuccess) return e;
-  return mxlaunch(s, k_force_finish, dim3((s->n + 63) / 64), dim3(64), s->n, s->nb, s->split,
-                  s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag, s->r_p, s->rho_p,
-                  s->part, s->dsc, s->bigsnap);
+  if (s->ns > 0) {
+    e = mxlaunch(s, k_force_split_small, dim3(blocks_for(s->ns) * s->split), dim3(kBlock), s->n,
+                 s->nb, s->nb, s->split, s->x, s->kpack, s->part);
+    if (e != hipSuccess) return e;
+  }
+  return mxlaunch(s, k_force_finish_sym, dim3(nT + (s->ns + 255) / 256), dim3(256), s->n,
+                  s->nb, nT, s->split, s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag,
+                  s->r_p, s->rho_p, s->sympart, s->part, s->dsc, s->bigsnap);
 }
 
 hipError_t gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,

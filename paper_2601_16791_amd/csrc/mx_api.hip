@@ -108,6 +108,7 @@ void free_system(mx_system* s) {
   delete[] s->tev_pool;
   void* ptrs[] = {s->x, s->u, s->ag, s->x0, s->u0, s->mu, s->rcrit, s->mu_init, s->rcrit_init,
                   s->growth, s->r_p, s->rho_p, s->bigsnap, s->bigmid, s->kpack, s->fpack, s->part,
+                  s->sympart,
                   s->pairs, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red,
                   s->desc, s->tiles};
   for (void* p : ptrs)
@@ -219,7 +220,8 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   s->stream = (hipStream_t)hip_stream;
   const size_t n3 = 3 * (size_t)s->n;
   const int nb = s->nb;
-  s->split = mxk::force_split(s->n, nb);
+  s->use_sym = mxk::force_split(s->n, nb) > 1;  // many massive bodies: symmetric tile pairs
+  s->split = s->ns > 0 ? mxk::force_split(s->ns, nb) : 1;
   s->cap_pairs = 1 << 16;
   s->cap_subs = 4096;
   s->red_blocks = 256;
@@ -232,7 +234,11 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   ALLOC(s->growth, 3 * (size_t)nb) ALLOC(s->r_p, s->ns) ALLOC(s->rho_p, s->ns)
   ALLOC(s->bigsnap, 9 * (size_t)nb) ALLOC(s->bigmid, 6 * (size_t)nb)
   ALLOC(s->kpack, nb) ALLOC(s->fpack, nb)
-  ALLOC(s->part, s->split > 1 ? (size_t)s->split * n3 : 1)
+  ALLOC(s->part, s->use_sym && s->ns > 0 ? (size_t)s->split * n3 : 1)
+  {
+    const size_t nT = (size_t)(nb + 63) / 64;
+    ALLOC(s->sympart, s->use_sym ? nT * nT * 3 * 64 : 1)
+  }
   ALLOC(s->pairs, 2 * (size_t)s->cap_pairs) ALLOC(s->pairs_tmp, 4 * (size_t)s->cap_pairs)
   ALLOC(s->plan_idx, 2 * (size_t)s->cap_pairs)
   ALLOC(s->subs, s->cap_subs) ALLOC(s->uf, 2 * (size_t)nb) ALLOC(s->dsc, 1) ALLOC(s->red, s->red_blocks)

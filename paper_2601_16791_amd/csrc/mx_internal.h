@@ -140,9 +140,12 @@ struct mx_system {
   // packed sources
   KickSource* kpack;
   FlagSource* fpack;
-  // force split partials
+  // force partials: split sums of the massless targets, symmetric tile-pair rows
+  // of the massive-massive block (n_big >= 128)
   double* part;
+  double* sympart;
   int split;
+  int use_sym;
   // encounters
   int32_t* pairs;      // [cap][2]
   int32_t* pairs_tmp;  // [4*cap] int32 = [2*cap] int64 sort keys of the planner
