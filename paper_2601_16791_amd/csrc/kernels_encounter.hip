@@ -168,6 +168,39 @@ __device__ bool insert_sorted(int32_t* v, int& m, int cap, int b) {
   return true;
 }
 
+// ---- single-wave planner for short lists of massless encounters
+// Sort of np distinct keys in[0, np) into out by rank: the rank of a key is the
+// number of smaller keys, counted against every key read as a wave-uniform LDS
+// broadcast.  One wave; its LDS accesses complete in order.
+__device__ void wave_rank_sort(const int64_t* in, int64_t* out, int np) {
+  const int lane = threadIdx.x & 63;
+  int64_t key[4];
+  int rank[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = 64 * r + lane;
+    key[r] = e < np ? in[e] : INT64_MAX;
+    rank[r] = 0;
+  }
+  int f = 0;
+  for (; f + 4 <= np; f += 4) {
+    const int64_t k0 = in[f], k1 = in[f + 1], k2 = in[f + 2], k3 = in[f + 3];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      rank[r] += (k0 < key[r]) + (k1 < key[r]) + (k2 < key[r]) + (k3 < key[r]);
+  }
+  for (; f < np; ++f) {
+    const int64_t k0 = in[f];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rank[r] += k0 < key[r];
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (64 * r + lane < np) out[rank[r]] = key[r];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 constexpr int kPlanThreads = 256;
 constexpr int kPlanLds = 2048;   // pairs handled in LDS; larger lists use global scratch
 
@@ -197,6 +230,79 @@ __device__ __forceinline__ void plan_block(int nb, int32_t* __restrict__ pairs, 
   if (np == 0) {
     if (threadIdx.x == 0 && !sort_only) dsc->n_sub = 0;
     return;
+  }
+  // Short lists without big-big pairs (the common case): one wave sorts in
+  // registers and writes each flagged massless body's subsystem directly; the
+  // result is the same table as the general path below.
+  {
+    bool bb = false;
+    if (np <= 256)
+      for (int q = threadIdx.x; q < np; q += blockDim.x) bb |= pairs[2 * q + 1] < nb;
+    const bool any_bb = __syncthreads_or(bb);
+    if (np <= 256 && !any_bb) {
+      if (threadIdx.x >= 64) return;
+      const int lane = threadIdx.x;
+      for (int e = lane; e < np; e += 64) ls[e] = make_key(pairs[2 * e], pairs[2 * e + 1]);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      wave_rank_sort(ls, lk, np);  // (i, j) order
+      for (int e = lane; e < np; e += 64) {
+        pairs[2 * e] = key_hi(lk[e]);
+        pairs[2 * e + 1] = key_lo(lk[e]);
+      }
+      if (sort_only) return;
+      // regroup by massless body j: keys (j, i)
+      for (int e = lane; e < np; e += 64) lk[256 + e] = make_key(key_lo(lk[e]), key_hi(lk[e]));
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      wave_rank_sort(lk + 256, ls, np);
+      int32_t* lj = reinterpret_cast<int32_t*>(lk);  // [256] j of the sorted list
+      int32_t* li = lj + 256;                          // [256] i
+      for (int e = lane; e < np; e += 64) {
+        lj[e] = key_hi(ls[e]);
+        li[e] = key_lo(ls[e]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // group starts, numbered in list order
+      int base = 0;
+      for (int r = 0; r < (np + 63) / 64; ++r) {
+        const int e = 64 * r + lane;
+        const bool start = e < np && (e == 0 || lj[e] != lj[e - 1]);
+        const uint64_t bal = __ballot(start);
+        const int g = base + __popcll(bal & ((1ull << lane) - 1ull));
+        base += __popcll(bal);
+        if (!start) continue;
+        int k = 1;
+        while (e + k < np && lj[e + k] == lj[e]) ++k;
+        const int j = lj[e];
+        Subsystem* S = subs + g;
+        if (g >= cap_subs) {
+          atomicOr(&dsc->err, MXE_SUBSYS);
+          continue;
+        }
+        if (k + 1 > kBsMaxMembers || k > kBsMaxPairs) {
+          atomicOr(&dsc->err, MXE_SUBSYS);
+          S->m = 0;  // an empty subsystem keeps the table dense; the integrator skips it
+          S->np = 0;
+          S->keep_from = 0;
+          S->pad = 0;
+          continue;
+        }
+        S->m = k + 1;
+        S->keep_from = k;
+        S->np = k;
+        S->pad = 0;
+        for (int q = 0; q < k; ++q) {
+          S->mem[q] = li[e + q];
+          S->pl[q][0] = q;
+          S->pl[q][1] = k;
+        }
+        S->mem[k] = j;
+      }
+      if (lane == 0) dsc->n_sub = min(base, cap_subs);
+      return;
+    }
   }
   const bool small_list = np <= kPlanLds;
   int64_t* K = small_list ? lk : gkeys;
@@ -250,7 +356,12 @@ __device__ __forceinline__ void plan_block(int nb, int32_t* __restrict__ pairs, 
       int i = key_hi(K[BB[b]]);
       int r = uf_find(par, i);
       if (inbig[r] != 1) continue;  // component already emitted (root marked 2)
-      Subsystem sub;
+      if (nsub >= cap_subs) {
+        inbig[r] = 2;
+        atomicOr(&dsc->err, MXE_SUBSYS);
+        continue;
+      }
+      Subsystem& sub = subs[nsub];  // built in place (no private copy)
       sub.m = 0;
       sub.keep_from = 0;
       sub.np = 0;
@@ -271,11 +382,11 @@ __device__ __forceinline__ void plan_block(int nb, int32_t* __restrict__ pairs, 
         ++sub.np;
       }
       inbig[r] = 2;
-      if (!ok || nsub >= cap_subs) {
+      if (!ok) {
         atomicOr(&dsc->err, MXE_SUBSYS);
         continue;
       }
-      subs[nsub++] = sub;
+      ++nsub;
     }
     s_nbig_sub = nsub;
   }
@@ -286,7 +397,12 @@ __device__ __forceinline__ void plan_block(int nb, int32_t* __restrict__ pairs, 
     const int q0 = GS[g];
     const int q1 = g + 1 < ng ? GS[g + 1] : ns;
     const int j = key_hi(S[q0]);
-    Subsystem sub;
+    const int slot = nbig_sub + g;
+    if (slot >= cap_subs) {
+      atomicOr(&dsc->err, MXE_SUBSYS);
+      continue;
+    }
+    Subsystem& sub = subs[slot];  // built in place (no private copy)
     sub.m = 0;
     sub.np = 0;
     sub.pad = 0;
@@ -326,14 +442,12 @@ __device__ __forceinline__ void plan_block(int nb, int32_t* __restrict__ pairs, 
         ++sub.np;
       }
     }
-    const int slot = nbig_sub + g;
-    if (!ok || slot >= cap_subs) {
+    if (!ok) {
       atomicOr(&dsc->err, MXE_SUBSYS);
       sub.m = 0;  // an empty subsystem keeps the table dense; the integrator skips it
       sub.np = 0;
       sub.keep_from = 0;
     }
-    if (slot < cap_subs) subs[slot] = sub;
   }
   __syncthreads();
   // 6. restore the union-find scratch
@@ -666,9 +780,11 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc) {
       // per element (two per lane): the previous table row and the diagonal
       double prev[2][kC], diag[2][kC];
       int accepted = -1;
-      // after a rejection all eight columns run at once (a short first round
-      // rarely succeeds there); otherwise n = 2..8 first, n = 10..16 if needed
-      const bool wide = fails > 0;
+      // all eight columns run at once in lanes 0..7: a step costs the longest
+      // sequence (n = 16) instead of n = 8 followed by n = 16, which is what the
+      // slowest subsystem of a launch pays; the accepted column is still the
+      // first one within tolerance
+      const bool wide = true;
 #pragma unroll
       for (int r = 0; r < kC / kRound; ++r) {
         if (accepted < 0) {
