@@ -221,179 +221,195 @@ __global__ __launch_bounds__(kBlock) void k_force_kick(
 }
 
 // Symmetric layout of the massive-massive forces (Newton's third law, the
-// triangular form of the direct-force routine): every pair of 64-body tiles
-// I < J is one block.  Pass 1: lanes hold the bodies i of I, the four waves walk
-// the sources j of J (16 each, scalar loads), accumulate mu_j K/r^3 (x_j - x_i)
-// and store mu_i K/r^3 in LDS.  Pass 2: lanes hold the bodies j of J, the waves
-// walk i of I and read the stored weights transposed, so the reaction
-// -mu_i K/r^3 (x_j - x_i) costs no second inverse square root.  Diagonal tiles
-// I = J take pass 1 only, self pairs excluded.  Rows of 3 x 64 partial sums go
-// to `out` at [I][J] (forces on the bodies of I from J) and [J][I]; the finish
-// kernel adds the row of each source tile J in ascending order.
-constexpr int kSymT = 64;
-constexpr int kSymS = 65;  // LDS row stride in doubles (odd: transposed reads hit all banks)
+// triangular form of the direct-force routine).  The massive bodies are cut into
+// 64-body tiles; one wave takes one tile pair (I, J) with J = (I + d) mod nT,
+// d = 0 .. nT/2 (every unordered pair once; d = 0 is the diagonal tile).
+// Pass 1: lanes hold the bodies i of I and walk the 64 sources j of J, read with
+// wave-uniform (scalar) loads one group of four ahead; they accumulate
+// mu_j K/r^3 (x_j - x_i) and store w_ij = mu_i K/r^3 in LDS, 16 sources at a
+// time.  Pass 2 after each 16 sources: lane (g, l) sums w_ij (x_i - x_j) for
+// source j = l of the chunk over the 16 targets i of group g, and the four
+// groups are added across lanes ((g0 + g1) + (g2 + g3)), so the reaction costs
+// no second inverse square root.  Diagonal tiles take pass 1 only, self pairs
+// excluded.  Rows of 3 x 64 partial sums go to `out` at [I][J] (forces on the
+// bodies of I from J) and [J][I]; the finish kernel adds the rows of each tile
+// in ascending source tile.  The record array is padded to whole tiles with
+// massless bodies far away from everything (see pad_kick_sources), so the loops
+// have no bounds.  Waves are independent (no block barrier): four per block,
+// about two per SIMD for the 4,004-body kick.
+constexpr int kSymT = 64;     // bodies per tile
+constexpr int kSymC = 16;     // sources per pass-2 chunk
+constexpr int kSymS = 65;     // LDS row stride of the weights (odd: no bank conflicts)
+constexpr int kSymWaves = 4;  // independent waves per block
 
-// pair weight K(r)/r^3 without the mass: fast branch, exact branch below the bound
-__device__ __forceinline__ double sym_weight(double s2, double rc2s, double rcs, double rc2t,
-                                             double rct, uint32_t wave_hi, double k15,
-                                             double k1875) {
-  double w = mxd::fast_weight(1.0, s2, k15, k1875);
-  if (__builtin_expect(s2 < mxd::upper_rc2(rc2s, wave_hi), 0)) {
-    const double rc2 = fmax(rc2s, rc2t);
-    if (s2 < rc2) w = mxd::changeover_weight_slow(s2, fmax(rcs, rct), rc2);
-  }
-  return w;
-}
-
-// a packed record of a tile body in LDS: x, y, z, mu, rc2, rc
-struct SymRec {
-  double x, y, z, mu, rc2, rc;
+struct SymSrc {
+  double x, y, z, mu;
 };
 
-template <bool DIAG>
-__device__ __forceinline__ void sym_block(int I, int J, int nb, int nT,
-                                          const KickSource* __restrict__ kp,
-                                          double* __restrict__ out, double* W,
-                                          double (*red)[3][kSymT], SymRec (*rec)[kSymT]) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+struct SymLds {                 // one wave's LDS
+  double tx[kSymT], ty[kSymT], tz[kSymT];   // positions of the tile I bodies
+  double W[kSymC * kSymS];                  // w_ij of one chunk, [j][i]
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ SymSrc sym_src(const KickSource* __restrict__ S, int j) {
+  return SymSrc{S[j].x, S[j].y, S[j].z, S[j].mu};
+}
+
+// tile pair of work unit u (units nT x (nT/2 + 1)); skip marks the duplicate
+// pairs of d = nT/2 for even nT
+__device__ __forceinline__ void sym_unit(int u, int nT, int& I, int& J, bool& skip) {
+  const int d = u / nT;
+  I = u - d * nT;
+  J = I + d;
+  if (J >= nT) J -= nT;
+  skip = 2 * d == nT && 2 * I >= nT;
+}
+
+__global__ __launch_bounds__(64 * kSymWaves) void k_force_sym(int nb, int nT, int nunits,
+                                                               const KickSource* __restrict__ kp,
+                                                               double* __restrict__ out) {
+  __shared__ SymLds lds[kSymWaves];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int u = blockIdx.x * kSymWaves + wv;
+  if (u >= nunits) return;
+  int I, J;
+  bool skip;
+  sym_unit(u, nT, I, J, skip);
+  if (skip) return;
+  I = __builtin_amdgcn_readfirstlane(I);
+  J = __builtin_amdgcn_readfirstlane(J);
+  SymLds& L = lds[wv];
   const int nI = min(kSymT, nb - I * kSymT), nJ = min(kSymT, nb - J * kSymT);
-  // stage the records of I (waves 0) and J (wave 1); absent bodies get mu 0
-  if (wv < (DIAG ? 1 : 2)) {
-    const int T = wv ? J : I;
-    const int nT_ = wv ? nJ : nI;
-    SymRec r;
-    if (lane < nT_) {
-      const KickSource k = kp[T * kSymT + lane];
-      r = SymRec{k.x, k.y, k.z, k.mu, k.rc2, k.rc};
-    } else {
-      r = SymRec{0.0, 0.0, 0.0, 0.0, 1e-300, 0.0};
-    }
-    rec[wv][lane] = r;
-  }
-  __syncthreads();
-  const SymRec* RI = rec[0];
-  const SymRec* RJ = rec[DIAG ? 0 : 1];
+  const KickSource& tk = kp[I * kSymT + lane];
+  const double xi = tk.x, yi = tk.y, zi = tk.z, mui = tk.mu, rci = tk.rc, rc2i = rci * rci;
+  // wave-uniform bound >= max(rc2) over both tiles: pairs below it take the
+  // exact changeover test
+  const uint32_t hi = mxd::wave_max_hi(fmax(rc2i, kp[J * kSymT + lane].rc2));
+  const double bound = __longlong_as_double((long long)(((uint64_t)hi << 32) | 0xffffffffull));
+  L.tx[lane] = xi;
+  L.ty[lane] = yi;
+  L.tz[lane] = zi;
   double k15, k1875;
   mxd::vgpr_constants(k15, k1875);
-  // ---- pass 1: lanes = bodies of I, sources = this wave's 16 bodies of J, four
-  // per iteration (independent chains, one changeover branch for the four)
-  {
-    const SymRec me = RI[lane];
-    const double xi = me.x, yi = me.y, zi = me.z, mui = me.mu;
-    const double rci = lane < nI ? me.rc : 0.0, rc2i = rci * rci;
-    const uint32_t wave_hi = mxd::wave_max_hi(rc2i);
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    const int j0 = 16 * wv;
-    const int jn = min(16, nJ - j0);
-    for (int k = 0; k < jn; k += 4) {
-      SymRec S[4];
-      double dx[4], dy[4], dz[4], s2[4], w[4];
-      bool near = false;
+  wave_sync();
+  const bool diag = I == J;
+  const KickSource* __restrict__ S = kp + J * kSymT;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  SymSrc A0 = sym_src(S, 0), A1 = sym_src(S, 1), A2 = sym_src(S, 2), A3 = sym_src(S, 3);
+#pragma unroll 1
+  for (int j = 0; j < kSymT; j += 4) {
+    const int jn = j + 4 < kSymT ? j + 4 : j;
+    const SymSrc N0 = sym_src(S, jn), N1 = sym_src(S, jn + 1), N2 = sym_src(S, jn + 2),
+                 N3 = sym_src(S, jn + 3);
+    const SymSrc Sx[4] = {A0, A1, A2, A3};
+    double dx[4], dy[4], dz[4], s2[4], w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      dx[q] = Sx[q].x - xi;
+      dy[q] = Sx[q].y - yi;
+      dz[q] = Sx[q].z - zi;
+      s2[q] = fma(dz[q], dz[q], fma(dy[q], dy[q], dx[q] * dx[q]));
+      w[q] = mxd::fast_weight(1.0, s2[q], k15, k1875);
+    }
+    const uint64_t near = __builtin_amdgcn_ballot_w64(s2[0] < bound) |
+                          __builtin_amdgcn_ballot_w64(s2[1] < bound) |
+                          __builtin_amdgcn_ballot_w64(s2[2] < bound) |
+                          __builtin_amdgcn_ballot_w64(s2[3] < bound);
+    if (__builtin_expect(near != 0, 0)) {
+      // a self pair (s2 = 0) always lands here
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        S[q] = RJ[j0 + min(k + q, jn - 1)];
-        dx[q] = S[q].x - xi;
-        dy[q] = S[q].y - yi;
-        dz[q] = S[q].z - zi;
-        s2[q] = fma(dz[q], dz[q], fma(dy[q], dy[q], dx[q] * dx[q]));
-        w[q] = mxd::fast_weight(1.0, s2[q], k15, k1875);
-        near |= s2[q] < fmax(S[q].rc2, rc2i);
-      }
-      if (__builtin_expect(near, 0)) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double rc2 = fmax(S[q].rc2, rc2i);
-          if (s2[q] < rc2) w[q] = mxd::changeover_weight_slow(s2[q], fmax(S[q].rc, rci), rc2);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int jl = j0 + k + q;
-        if (k + q >= jn) break;  // wave-uniform
-        if (DIAG && jl == lane) w[q] = 0.0;
-        const double t = S[q].mu * w[q];
-        a0 = fma(t, dx[q], a0);
-        a1 = fma(t, dy[q], a1);
-        a2 = fma(t, dz[q], a2);
-        if (!DIAG) W[jl * kSymS + lane] = mui * w[q];
+        const double rc2 = fmax(S[j + q].rc2, rc2i);
+        if (s2[q] < rc2) w[q] = mxd::changeover_weight_slow(s2[q], fmax(S[j + q].rc, rci), rc2);
+        if (diag && j + q == lane) w[q] = 0.0;
       }
     }
-    red[wv][0][lane] = a0;
-    red[wv][1][lane] = a1;
-    red[wv][2][lane] = a2;
+    const int jw = j & (kSymC - 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double t = Sx[q].mu * w[q];
+      a0 = fma(t, dx[q], a0);
+      a1 = fma(t, dy[q], a1);
+      a2 = fma(t, dz[q], a2);
+      L.W[(jw + q) * kSymS + lane] = mui * w[q];
+    }
+    A0 = N0;
+    A1 = N1;
+    A2 = N2;
+    A3 = N3;
+    if (jw + 4 == kSymC && !diag) {
+      const int j0 = j + 4 - kSymC;
+      wave_sync();
+      const int g = lane / kSymC, jl = lane % kSymC;
+      const double xj = S[j0 + jl].x, yj = S[j0 + jl].y, zj = S[j0 + jl].z;
+      double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < kSymC; ++k) {
+        const int i = g * kSymC + k;
+        const double ww = L.W[jl * kSymS + i];
+        r0 = fma(ww, L.tx[i] - xj, r0);
+        r1 = fma(ww, L.ty[i] - yj, r1);
+        r2 = fma(ww, L.tz[i] - zj, r2);
+      }
+#pragma unroll
+      for (int off = kSymC; off < 64; off <<= 1) {
+        r0 += __shfl_xor(r0, off);
+        r1 += __shfl_xor(r1, off);
+        r2 += __shfl_xor(r2, off);
+      }
+      if (lane < kSymC && j0 + jl < nJ) {
+        double* row = out + ((size_t)J * nT + I) * 3 * kSymT;  // forces on J from I
+        row[j0 + jl] = r0;
+        row[kSymT + j0 + jl] = r1;
+        row[2 * kSymT + j0 + jl] = r2;
+      }
+      wave_sync();
+    }
   }
-  __syncthreads();
-  if (wv == 0 && lane < nI) {
+  if (lane < nI) {
     double* row = out + ((size_t)I * nT + J) * 3 * kSymT;  // forces on I from J
-    for (int c = 0; c < 3; ++c)
-      row[c * kSymT + lane] = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) +
-                              red[3][c][lane];
-  }
-  if (DIAG) return;
-  __syncthreads();
-  // ---- pass 2: lanes = bodies of J, reactions from this wave's 16 bodies of I
-  {
-    const SymRec me = RJ[lane];
-    const double xj = me.x, yj = me.y, zj = me.z;
-    double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-    const int i0 = 16 * wv;
-    const int in = min(16, nI - i0);
-    for (int k = 0; k < in; k += 4) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (k + q >= in) break;  // wave-uniform
-        const SymRec& S = RI[i0 + k + q];
-        const double w = W[lane * kSymS + i0 + k + q];
-        r0 = fma(w, S.x - xj, r0);
-        r1 = fma(w, S.y - yj, r1);
-        r2 = fma(w, S.z - zj, r2);
-      }
-    }
-    red[wv][0][lane] = r0;
-    red[wv][1][lane] = r1;
-    red[wv][2][lane] = r2;
-  }
-  __syncthreads();
-  if (wv == 0 && lane < nJ) {
-    double* rowJ = out + ((size_t)J * nT + I) * 3 * kSymT;  // forces on J from I
-    for (int c = 0; c < 3; ++c)
-      rowJ[c * kSymT + lane] = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) +
-                               red[3][c][lane];
+    row[lane] = a0;
+    row[kSymT + lane] = a1;
+    row[2 * kSymT + lane] = a2;
   }
 }
 
-__global__ __launch_bounds__(256) void k_force_sym(int nb, int nT, int npairs,
-                                                   const KickSource* __restrict__ kp,
-                                                   double* __restrict__ out) {
-  __shared__ double W[kSymT * kSymS];
-  __shared__ double red[4][3][kSymT];
-  __shared__ SymRec rec[2][kSymT];
-  if ((int)blockIdx.x >= npairs) {
-    const int I = (int)blockIdx.x - npairs;
-    sym_block<true>(I, I, nb, nT, kp, out, W, red, rec);
-    return;
-  }
-  int p = blockIdx.x, I = 0;
-  while (p >= nT - 1 - I) {
-    p -= nT - 1 - I;
-    ++I;
-  }
-  sym_block<false>(I, I + 1 + p, nb, nT, kp, out, W, red, rec);
+// Padding records of the last tile: massless, far apart from each other and
+// from every body, so that they add exactly zero to every sum.
+__global__ void k_pad_kick_sources(int nb, int ntot, KickSource* __restrict__ kp) {
+  const int t = nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntot) return;
+  KickSource k;
+  k.x = -1e20 * (double)(1 + (t & (kSymT - 1)));
+  k.y = k.z = 0.0;
+  k.mu = 0.0;
+  k.rc2 = 1e-300;
+  k.rc = 0.0;
+  k.pad0 = k.pad1 = 0.0;
+  kp[t] = k;
 }
 
-// massive bodies: the symmetric rows in source-tile order (four quarter sums of
-// consecutive source tiles, added in quarter order); massless bodies: the split
-// partials in split order; then drag and the half kick.  Blocks of 256 threads:
-// for massive bodies thread q * 64 + l adds quarter q for body l of the block's
-// tile; for massless bodies each thread finishes one body.
-__global__ __launch_bounds__(256) void k_force_finish_sym(
+// Finish.  Massive bodies (blocks < nT, one per tile): 16 slices of the source
+// tiles, thread q * 64 + l sums slice q for body l of the tile, then the slices
+// are added in order (fixed order: the result does not depend on scheduling).
+// Massless bodies (blocks >= nT): the split partials in split order.  Then drag
+// and the half kick.
+constexpr int kFinSlices = 16;
+
+__global__ __launch_bounds__(64 * kFinSlices) void k_force_finish_sym(
     int n, int nb, int nT, int split, double mu0, double hh, DragConst dc, int gas_on,
     int kick, const double* __restrict__ x, double* __restrict__ u, double* __restrict__ ag,
     const double* __restrict__ r_p, const double* __restrict__ rho_p,
     const double* __restrict__ sym, const double* __restrict__ part,
     DevScalars* __restrict__ dsc, double* __restrict__ bigsnap) {
-  __shared__ double q3[4][3][kSymT];
+  __shared__ double sl[kFinSlices][3][kSymT];
   if (kick && blockIdx.x == 0 && threadIdx.x == 0) {
     dsc->step += 1;
     dsc->n_pairs = 0;  // the encounter list of this step has been planned
@@ -402,7 +418,7 @@ __global__ __launch_bounds__(256) void k_force_finish_sym(
   if ((int)blockIdx.x < nT) {
     const int I = blockIdx.x;
     const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int Ja = (q * nT) / 4, Jb = ((q + 1) * nT) / 4;
+    const int Ja = (q * nT) / kFinSlices, Jb = ((q + 1) * nT) / kFinSlices;
     const double* row = sym + (size_t)I * nT * 3 * kSymT + l;
     double bx = 0.0, by = 0.0, bz = 0.0;
 #pragma unroll 4
@@ -411,19 +427,23 @@ __global__ __launch_bounds__(256) void k_force_finish_sym(
       by += row[(size_t)J * 3 * kSymT + kSymT];
       bz += row[(size_t)J * 3 * kSymT + 2 * kSymT];
     }
-    q3[q][0][l] = bx;
-    q3[q][1][l] = by;
-    q3[q][2][l] = bz;
+    sl[q][0][l] = bx;
+    sl[q][1][l] = by;
+    sl[q][2][l] = bz;
     __syncthreads();
     const int t = I * kSymT + l;
     if (q != 0 || t >= nb) return;
     double a[3];
-    for (int c = 0; c < 3; ++c) a[c] = ((q3[0][c][l] + q3[1][c][l]) + q3[2][c][l]) + q3[3][c][l];
+    for (int c = 0; c < 3; ++c) {
+      double s = sl[0][c][l];
+      for (int k = 1; k < kFinSlices; ++k) s += sl[k][c][l];
+      a[c] = s;
+    }
     finish_body(t, n, nb, mu0, hh, dc, gas_on, kick, a[0], a[1], a[2], x, u, ag, r_p, rho_p, P,
                 &dsc->err, bigsnap);
     return;
   }
-  const int t = nb + ((int)blockIdx.x - nT) * 256 + threadIdx.x;
+  const int t = nb + ((int)blockIdx.x - nT) * (64 * kFinSlices) + threadIdx.x;
   if (t >= n) return;
   double bx = 0.0, by = 0.0, bz = 0.0;
 #pragma unroll 8
@@ -580,18 +600,30 @@ hipError_t launch_force_kick(mx_system* s, int kick) {
                     s->dsc, s->bigsnap);
   // massive-massive block by symmetric tile pairs, massless targets by the split
   const int nT = (s->nb + kSymT - 1) / kSymT;
-  const int npairs = nT * (nT - 1) / 2;
-  hipError_t e = mxlaunch(s, k_force_sym, dim3(npairs + nT), dim3(256), s->nb, nT, npairs,
-                          s->kpack, s->sympart);
+  const int nunits = nT * (nT / 2 + 1);
+  hipError_t e = mxlaunch(s, k_force_sym, dim3((nunits + kSymWaves - 1) / kSymWaves),
+                          dim3(64 * kSymWaves), s->nb, nT, nunits, s->kpack, s->sympart);
   if (e != hipSuccess) return e;
   if (s->ns > 0) {
     e = mxlaunch(s, k_force_split_small, dim3(blocks_for(s->ns) * s->split), dim3(kBlock), s->n,
                  s->nb, s->nb, s->split, s->x, s->kpack, s->part);
     if (e != hipSuccess) return e;
   }
-  return mxlaunch(s, k_force_finish_sym, dim3(nT + (s->ns + 255) / 256), dim3(256), s->n,
-                  s->nb, nT, s->split, s->mu0, hh, dc, s->p.gas_on, kick, s->x, s->u, s->ag,
-                  s->r_p, s->rho_p, s->sympart, s->part, s->dsc, s->bigsnap);
+  return mxlaunch(s, k_force_finish_sym,
+                  dim3(nT + (s->ns + 64 * kFinSlices - 1) / (64 * kFinSlices)),
+                  dim3(64 * kFinSlices), s->n, s->nb, nT, s->split, s->mu0, hh, dc, s->p.gas_on,
+                  kick, s->x, s->u, s->ag, s->r_p, s->rho_p, s->sympart, s->part, s->dsc,
+                  s->bigsnap);
+}
+
+// Padding records [nb, kick_source_count(nb)) written once at initialisation.
+int kick_source_count(int nb) { return ((nb + kSymT - 1) / kSymT) * kSymT; }
+
+hipError_t pad_kick_sources(int nb, KickSource* kp, hipStream_t st) {
+  const int ntot = kick_source_count(nb);
+  if (ntot == nb) return hipSuccess;
+  hipLaunchKernelGGL(k_pad_kick_sources, dim3(1), dim3(kSymT), 0, st, nb, ntot, kp);
+  return hipGetLastError();
 }
 
 hipError_t gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,

@@ -20,6 +20,8 @@
 
 namespace mxk {
 int force_split(int n, int nb);
+int kick_source_count(int nb);
+hipError_t pad_kick_sources(int nb, KickSource* kp, hipStream_t st);
 }
 
 namespace {
@@ -233,7 +235,7 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   ALLOC(s->mu, nb) ALLOC(s->rcrit, nb) ALLOC(s->mu_init, nb) ALLOC(s->rcrit_init, nb)
   ALLOC(s->growth, 3 * (size_t)nb) ALLOC(s->r_p, s->ns) ALLOC(s->rho_p, s->ns)
   ALLOC(s->bigsnap, 9 * (size_t)nb) ALLOC(s->bigmid, 6 * (size_t)nb)
-  ALLOC(s->kpack, nb) ALLOC(s->fpack, nb)
+  ALLOC(s->kpack, mxk::kick_source_count(nb)) ALLOC(s->fpack, nb)
   ALLOC(s->part, s->use_sym && s->ns > 0 ? (size_t)s->split * n3 : 1)
   {
     const size_t nT = (size_t)(nb + 63) / 64;
@@ -272,6 +274,7 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   STEP(dalloc(&vh_tmp, n3), "alloc v_h");
   STEP(hipMemsetAsync(s->dsc, 0, sizeof(DevScalars), sm), "memset");
   STEP(hipMemsetAsync(s->ag, 0, sizeof(double) * n3, sm), "memset");
+  STEP(mxk::pad_kick_sources(nb, s->kpack, sm), "pad sources");
   STEP(copy_in(s->x, x_h, sizeof(double) * n3, is_device_ptr, sm), "copy x");
   STEP(copy_in(vh_tmp, v_h, sizeof(double) * n3, is_device_ptr, sm), "copy v");
   STEP(copy_in(s->mu_init, m_big, sizeof(double) * nb, is_device_ptr, sm), "copy m");
