@@ -714,6 +714,134 @@ __device__ __forceinline__ void run_column(int col, double H, int m, int np,
   }
 }
 
+// Subsystems of M <= 4 members: each round evaluates eight step sizes at once,
+// H, H/2, ..., H/128 (lanes 8c .. 8c + 7 run the eight substep sequences of
+// step size H / 2^c), and takes the largest one the sequential control would
+// accept: candidate c is the step the sequential integrator tries after c
+// consecutive failures of the larger ones, from the same state with the same
+// scales, so the accepted steps, their columns and the results are those of
+// the sequential loop, bit for bit, while a run of failures costs one round.
+// Returns the number of accepted steps, or -1 when more than 30 consecutive
+// failures occurred.
+template <int M>
+__device__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, int np,
+                        const double* mum, const double* rcm, double mu0, double* xs,
+                        double* vs, double* scal, double (*resS)[kC][6 * 4],
+                        const SysDesc& D, DevScalars* __restrict__ dsc) {
+  constexpr int NN = 3 * M, E = 2 * NN;
+  constexpr int EPL = (E + 7) / 8;  // table elements per lane of a candidate group
+  const int cand = lane >> 3, j = lane & 7;
+  double done = 0.0, H = h;
+  int fails = 0, nsched = 0;
+  while (fabs(h - done) > 1e-14 * fabs(h)) {
+    const double rem = h - done;
+    if (fabs(H) > fabs(rem)) H = rem;
+    if (lane < M) {
+      const double* p = xs + 3 * lane;
+      const double* q = vs + 3 * lane;
+      scal[lane] = 1.0 / (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+      scal[M + lane] = 1.0 / (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    }
+    // H / 2^cand: repeated halving is exact, so is the scaling by 2^-cand
+    const double Hc = H * __longlong_as_double((long long)(1023 - cand) << 52);
+    stoermer_reg<M>(j, Hc, pmask, mum, rcm, mu0, xs, vs, resS[cand][j]);
+    __syncthreads();
+    // Aitken-Neville table of candidate `cand` for elements j, j + 8, ...
+    double lerr[kC], dg[EPL][kC];
+#pragma unroll
+    for (int k = 0; k < kC; ++k) lerr[k] = 0.0;
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) {
+      const int e = j + 8 * s;
+#pragma unroll
+      for (int k = 0; k < kC; ++k) dg[s][k] = 0.0;
+      if (e >= E) continue;
+      const double sc = e < NN ? scal[e / 3] : scal[M + (e - NN) / 3];
+      double prev[kC];
+#pragma unroll
+      for (int k = 0; k < kC; ++k) {
+        double T[kC];
+        T[0] = resS[cand][k][e];
+#pragma unroll
+        for (int jx = 1; jx < kC; ++jx)
+          if (jx <= k) T[jx] = fma(T[jx - 1] - prev[jx - 1], kNevilleInv[k][jx], T[jx - 1]);
+        dg[s][k] = T[k];
+        if (k >= 1) {
+          const double ex = T[k] - T[k - 1];
+          lerr[k] = fmax(lerr[k], ex * ex * sc);
+        }
+#pragma unroll
+        for (int jx = 0; jx < kC; ++jx)
+          if (jx <= k) prev[jx] = T[jx];
+      }
+    }
+    int acc = -1;  // first column within tolerance for this lane's candidate
+#pragma unroll
+    for (int k = 1; k < kC; ++k) {
+      double v = lerr[k];
+      for (int off = 1; off < 8; off <<= 1) v = fmax(v, __shfl_xor(v, off));
+      if (acc < 0 && v <= tol2) acc = k;
+    }
+    // the sequential control: candidates in order, failures counted
+    const uint64_t okm = __builtin_amdgcn_ballot_w64(j == 0 && acc >= 0);
+    int chosen = -1;
+    bool failed = false;
+    for (int c = 0; c < 8; ++c) {
+      if ((okm >> (8 * c)) & 1ull) {
+        chosen = c;
+        break;
+      }
+      if (++fails > 30) {
+        failed = true;
+        break;
+      }
+    }
+    if (lane == 0) {
+      // model count as for the sequential loop: eight columns per attempt made
+      const int att = chosen >= 0 ? chosen + 1 : 8;
+      unsigned long long f = 0;
+      for (int c = 0; c < kC; ++c) f += (unsigned long long)(2 * (c + 1) + 1) * (24 * M + 25 * np);
+      for (int k = 0; k < kC; ++k) f += (unsigned long long)3 * k * 6 * M;
+      atomicAdd(&dsc->bs_flop, f * (unsigned long long)att);
+    }
+    __syncthreads();
+    if (failed) return -1;
+    if (chosen < 0) {
+      H = H * 0.00390625;  // eight halvings
+      continue;
+    }
+    const int accepted = __shfl(acc, 8 * chosen);
+    if (cand == chosen) {
+#pragma unroll
+      for (int s = 0; s < EPL; ++s) {
+        const int e = j + 8 * s;
+        if (e >= E) continue;
+        double val = dg[s][1];
+#pragma unroll
+        for (int k = 2; k < kC; ++k)
+          if (k == accepted) val = dg[s][k];
+        if (e < NN) xs[e] = val;
+        else vs[e - NN] = val;
+      }
+    }
+    const double Hs = H * __longlong_as_double((long long)(1023 - chosen) << 52);
+    if (D.bs_sched && lane == 0) {
+      if (nsched < kBsMaxSched) {
+        D.bs_sched[((size_t)b * kBsMaxSched + nsched) * 2] = Hs;
+        D.bs_sched[((size_t)b * kBsMaxSched + nsched) * 2 + 1] = (double)accepted;
+      } else {
+        atomicOr(&dsc->err, MXE_ADJOINT);
+      }
+    }
+    ++nsched;
+    done += Hs;
+    fails = 0;
+    H = accepted <= 4 ? 2.0 * Hs : Hs;
+    __syncthreads();
+  }
+  return nsched;
+}
+
 // Columns are evaluated in two rounds (n = 2..8, then n = 10..16, four lanes
 // each): most steps are accepted in the first round, and the table rows do not
 // depend on later rows, so the accepted column is the one a sequential
@@ -736,6 +864,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc) {
   __shared__ double xs[3 * kM], vs[3 * kM], mum[kM], rcm[kM], scal[2 * kM];
   __shared__ double res[kC][6 * kM];
   __shared__ double wk[kC][3][3 * kM];
+  __shared__ double resS[8][kC][6 * 4];  // speculative rounds of subsystems of <= 4 members
   const int lane = threadIdx.x;
   const int nsub = dsc->n_sub;
   const double tol2 = tol * tol;
@@ -768,6 +897,13 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc) {
     double done = 0.0, H = h;
     int fails = 0, nsched = 0;
     bool failed = false;
+    if (m <= 4) {
+      if (m == 2) nsched = bs_small<2>(lane, b, h, tol2, pmask, np, mum, rcm, mu0, xs, vs, scal, resS, D, dsc);
+      else if (m == 3) nsched = bs_small<3>(lane, b, h, tol2, pmask, np, mum, rcm, mu0, xs, vs, scal, resS, D, dsc);
+      else nsched = bs_small<4>(lane, b, h, tol2, pmask, np, mum, rcm, mu0, xs, vs, scal, resS, D, dsc);
+      failed = nsched < 0;
+      done = h;  // the loop below is for larger subsystems
+    }
     while (fabs(h - done) > 1e-14 * fabs(h)) {
       double rem = h - done;
       if (fabs(H) > fabs(rem)) H = rem;

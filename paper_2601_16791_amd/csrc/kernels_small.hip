@@ -157,8 +157,6 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
         atomicOr(&D.dsc->err, MXE_NOCONV);
     }
     for (int c = 0; c < 3; ++c) {
-      D.x0[c * n + t] = p[c];
-      D.u0[c * n + t] = v[c];
       D.x[c * n + t] = q[c];
       D.u[c * n + t] = w[c];
     }
@@ -167,6 +165,7 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
     const double rct = t < nb ? brc[t] : 0.0;
     const int imax = t < nb ? t : nb;
     const double k427 = (4.0 / 27.0) * fabs(h);
+    bool hit = false;
     for (int i = 0; i < imax; ++i) {
       double r0[3], w0[3], w1[3], dd[3];
       for (int c = 0; c < 3; ++c) {
@@ -187,6 +186,7 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
         double dmin = mxd::hermite_dmin2(r0[0], r0[1], r0[2], w0[0], w0[1], w0[2], r1[0], r1[1],
                                          r1[2], w1[0], w1[1], w1[2], h);
         if (dmin <= rc * rc) {
+          hit = true;
           int idx = atomicAdd(&D.dsc->n_pairs, 1);
           if (idx < D.cap_pairs) {
             D.pairs[2 * idx] = i;
@@ -195,6 +195,13 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
             atomicOr(&D.dsc->err, MXE_PAIRS);
           }
         }
+      }
+    }
+    // pre-drift state: the encounter integrator starts its subsystems from it
+    if (hit || t < nb || D.keep_x0) {
+      for (int c = 0; c < 3; ++c) {
+        D.x0[c * n + t] = p[c];
+        D.u0[c * n + t] = v[c];
       }
     }
   }

@@ -1159,6 +1159,7 @@ mx_status mx_adjoint_create(const mx_params* p, const double* x_h, const double*
   if (e == hipSuccess) {
     SysDesc d = make_desc(s);
     d.bs_sched = a->sched;
+    d.keep_x0 = 1;
     d.bs_nsched = a->nsched;
     e = hipMemcpy(s->desc, &d, sizeof(SysDesc), hipMemcpyHostToDevice);
   }

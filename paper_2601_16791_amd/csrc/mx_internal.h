@@ -102,7 +102,11 @@ struct SysDesc {
   int32_t* bs_nsched;
   mxd::DragConst dc;
   double mu0, h, bs_tol;
-  int32_t n, nb, cap_pairs, cap_subs, gas_on, pad;
+  int32_t n, nb, cap_pairs, cap_subs, gas_on;
+  // 1: the fused step keeps the pre-drift state of every body in x0, u0 (the
+  // adjoint records it); 0: only of the massive and the flagged bodies, the
+  // ones the encounter integrator starts from
+  int32_t keep_x0;
 };
 
 // A tile of consecutive bodies of one system for the fused small-B kernels.
