@@ -66,35 +66,36 @@ __device__ __forceinline__ double pow_kexp(double b, double kexp) {
 __device__ __forceinline__ void gas_drag(const DragConst& c, double X, double Y, double vx,
                                          double vy, double vz, double r_p, double rho_p,
                                          double& ax, double& ay, double& az) {
+  // Written with few divisions (each is a long dependent chain in FP64):
+  // c_s = (H/r) v_k; rho_g = Sigma / (sqrt(2 pi) (H/r) R); Re = 2 r_p dv / nu with
+  // nu = sqrt(8/pi) c_s (mfp / rho_g) / 3, i.e. Re = re_fac r_p dv rho_g / c_s;
+  // 1 / (24/Re + 40/(10 + Re)) = Re (10 + Re) / (240 + 64 Re).
   ax = ay = az = 0.0;
   double R2 = X * X + Y * Y;
   double R = sqrt(R2);
   if (!(R > 0.0) || R < c.r_in) return;
   double inv_R = 1.0 / R;
   double vk = sqrt(c.mu0 * inv_R);
-  double om = vk * inv_R;
-  double hg = c.h_over_r * R;
-  double cs = hg * om;
+  double cs = c.h_over_r * vk;
   double sig;
   if (c.gamma == 1.0) sig = c.sigma1_unit * inv_R;
   else sig = c.sigma1_unit * pow(R, -c.gamma);
   if (c.r_c > 0.0) sig *= exp(c.rc_norm - pow(R * c.inv_rc, 2.0 - c.gamma));
   if (!(sig > 0.0)) return;
-  double rhog = sig / (kSqrt2Pi * hg);
+  double rhog = sig * inv_R * c.rho_fac;
   double vg = vk * c.vg_fac;
   double dvx = vx + vg * Y * inv_R;
   double dvy = vy - vg * X * inv_R;
   double dvz = vz;
   double dv = sqrt(dvx * dvx + dvy * dvy + dvz * dvz);
   if (!(dv > 0.0)) return;
-  double ma = dv / cs;
-  double lam = c.mfp_coef / rhog;
-  double nu = (1.0 / 3.0) * kSqrt8OverPi * cs * lam;
-  double re = 2.0 * r_p * dv / nu;
+  double inv_cs = 1.0 / cs;
+  double ma = dv * inv_cs;
+  double re = c.re_fac * r_p * dv * rhog * inv_cs;
   double k = re < 1.0e5 ? 0.4 : 0.2;
-  double inner = 1.0 / (24.0 / re + 40.0 / (10.0 + re)) + 0.23 * ma;
+  double inner = re * (10.0 + re) / fma(64.0, re, 240.0) + 0.23 * ma;
   double cd = pow_kexp(inner, c.kexp) + 2.0 * (0.8 * k + ma) / (1.6 + ma);
-  double f = -0.375 * (cd / r_p) * (rhog / rho_p) * dv;
+  double f = -0.375 * cd * rhog * dv / (r_p * rho_p);
   ax = f * dvx;
   ay = f * dvy;
   az = f * dvz;
@@ -162,9 +163,9 @@ __device__ __forceinline__ bool kepler_drift(double mu, double h, double& x, dou
   double c0, G1, G2, G3;
   double lo, hi;
   if (beta > 0.0) {
-    double sb = sqrt(beta);
-    double S = 2.0 * kPi / sb;
-    double P = S * mu / beta;          // 2 pi mu / beta^(3/2)
+    double isb = 1.0 / sqrt(beta);
+    double S = 2.0 * kPi * isb;
+    double P = S * mu * (isb * isb);   // 2 pi mu / beta^(3/2)
     if (fabs(h) > 0.5 * P) h -= rint(h / P) * P;
     lo = -S;
     hi = S;
@@ -198,7 +199,7 @@ __device__ __forceinline__ bool kepler_drift(double mu, double h, double& x, dou
     }
     if (F < 0.0) lo = s;
     else hi = s;
-    double sn = s - F / (Fp - 0.5 * F * Fpp / Fp);
+    double sn = s - F * Fp / fma(Fp, Fp, -0.5 * F * Fpp);  // Halley step
     if (fabs(sn - s) <= 1e-13 * fabs(sn)) {
       s = sn;
       ok = true;
@@ -217,8 +218,9 @@ __device__ __forceinline__ bool kepler_drift(double mu, double h, double& x, dou
   double r = fma(eta, G1, fma(zeta, G2, r0));
   double f = 1.0 - mu * G2 * inv_r0;
   double g = h - mu * G3;
-  double fd = -mu * G1 / (r * r0);
-  double gd = 1.0 - mu * G2 / r;
+  double inv_r = 1.0 / r;
+  double fd = -mu * G1 * inv_r * inv_r0;
+  double gd = 1.0 - mu * G2 * inv_r;
   double nx = f * x + g * vx, ny = f * y + g * vy, nz = f * z + g * vz;
   double nvx = fd * x + gd * vx, nvy = fd * y + gd * vy, nvz = fd * z + gd * vz;
   x = nx; y = ny; z = nz;
@@ -260,17 +262,30 @@ __device__ __noinline__ double hermite_dmin2(double r0x, double r0y, double r0z,
     s = 2.0 * (acc[0] * dr[0] + acc[1] * dr[1] + acc[2] * dr[2]);
     return s;
   };
-  const int NG = 16;
-  double dprev = dd(0.0);
+  // the 17 grid values are independent: evaluate them all first
+  constexpr int NG = 16;
+  double g[NG + 1];
+#pragma unroll
+  for (int k = 0; k <= NG; ++k) g[k] = dd((double)k / NG);
   for (int k = 0; k < NG; ++k) {
-    double t1 = (double)(k + 1) / NG;
-    double dnext = dd(t1);
-    if (dprev < 0.0 && dnext >= 0.0) {
-      double lo = (double)k / NG, hi = t1;
-      for (int it = 0; it < 40; ++it) {
-        double mid = 0.5 * (lo + hi);
-        if (dd(mid) < 0.0) lo = mid;
-        else hi = mid;
+    if (g[k] < 0.0 && g[k + 1] >= 0.0) {
+      double lo = (double)k / NG, hi = (double)(k + 1) / NG;
+      // 40 bisection steps taken two at a time: the midpoint and both possible
+      // next midpoints are evaluated together, then the two decisions are
+      // made in order (the same points and decisions as one step at a time)
+      for (int it = 0; it < 20; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        const double qa = 0.5 * (lo + mid), qb = 0.5 * (mid + hi);
+        const double fm = dd(mid), fa = dd(qa), fb = dd(qb);
+        if (fm < 0.0) {
+          lo = mid;
+          if (fb < 0.0) lo = qb;
+          else hi = qb;
+        } else {
+          hi = mid;
+          if (fa < 0.0) lo = qa;
+          else hi = qa;
+        }
       }
       double t = 0.5 * (lo + hi);
       double r[3];
@@ -278,7 +293,6 @@ __device__ __noinline__ double hermite_dmin2(double r0x, double r0y, double r0z,
       double d = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
       if (d < best) best = d;
     }
-    dprev = dnext;
   }
   return best;
 }

@@ -607,10 +607,36 @@ __device__ __forceinline__ void neville_round(int lane, int nn, int m, const dou
 
 // Register-resident variant for subsystems of M <= 4 members: positions,
 // increments and accelerations stay in VGPRs; the flagged pairs are a bit mask
-// over the M (M-1) / 2 possible pairs, walked at compile time.
+// over the M (M-1) / 2 possible pairs, walked at compile time.  The pair weight
+// is formed without branches (the lanes of a wave sit at different step sizes
+// and would otherwise run every branch in turn): inside 0.1 rc the full y^3,
+// in the changeover zone y^3 (1 - K) with q = (s - 0.1 rc) / (0.9 rc) taken as
+// a product with the reciprocal of 0.9 rc, zero outside rc.
+template <int M>
+struct PairConst {
+  double rc2[M * (M - 1) / 2 > 0 ? M * (M - 1) / 2 : 1];
+  double rc01[M * (M - 1) / 2 > 0 ? M * (M - 1) / 2 : 1];   // 0.1 rc
+  double inv09[M * (M - 1) / 2 > 0 ? M * (M - 1) / 2 : 1];  // 1 / (0.9 rc)
+};
+
+template <int M>
+__device__ __forceinline__ void pair_consts(const double (&rc)[M], PairConst<M>& pc) {
+  int bit = 0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+#pragma unroll
+    for (int b = a + 1; b < M; ++b, ++bit) {
+      const double rcp = fmax(rc[a], rc[b]);
+      pc.rc2[bit] = rcp * rcp;
+      pc.rc01[bit] = 0.1 * rcp;
+      pc.inv09[bit] = 1.0 / (0.9 * rcp);
+    }
+  }
+}
+
 template <int M>
 __device__ __forceinline__ void force_reg(uint32_t pmask, const double (&mu)[M],
-                                          const double (&rc)[M], double mu0,
+                                          const PairConst<M>& pc, double mu0,
                                           const double (&pos)[3 * M], double (&acc)[3 * M]) {
 #pragma unroll
   for (int k = 0; k < M; ++k) {
@@ -622,31 +648,26 @@ __device__ __forceinline__ void force_reg(uint32_t pmask, const double (&mu)[M],
     acc[3 * k + 1] = f * pos[3 * k + 1];
     acc[3 * k + 2] = f * pos[3 * k + 2];
   }
+  // every possible pair, unflagged ones with weight zero: one basic block, so
+  // the independent chains of the members and pairs interleave
   int bit = 0;
 #pragma unroll
   for (int a = 0; a < M; ++a) {
 #pragma unroll
     for (int b = a + 1; b < M; ++b, ++bit) {
-      if (!((pmask >> bit) & 1u)) continue;
       double d0 = pos[3 * b] - pos[3 * a];
       double d1 = pos[3 * b + 1] - pos[3 * a + 1];
       double d2 = pos[3 * b + 2] - pos[3 * a + 2];
       double s2 = fma(d2, d2, fma(d1, d1, d0 * d0));
-      double rcp = fmax(rc[a], rc[b]);
-      double rc2 = rcp * rcp;
-      double w = 0.0;
-      if (s2 < rc2 && s2 > 0.0) {
-        double y = mxd::rsqrt_full(s2);
-        double y3 = y * y * y;
-        if (s2 <= 0.01 * rc2) {
-          w = y3;
-        } else {
-          double q1 = (s2 * y - 0.1 * rcp) / (0.9 * rcp);
-          double q2 = q1 * q1, q3 = q1 * q2;
-          double K = q3 * fma(q1, fma(q1, 6.0, -15.0), 10.0);
-          w = y3 * (1.0 - K);
-        }
-      }
+      const double rc2 = pc.rc2[bit];
+      double y = mxd::rsqrt_full(s2);
+      double y3 = y * y * y;
+      double q1 = (s2 * y - pc.rc01[bit]) * pc.inv09[bit];
+      double q2 = q1 * q1, q3 = q1 * q2;
+      double K = q3 * fma(q1, fma(q1, 6.0, -15.0), 10.0);
+      double wz = s2 <= 0.01 * rc2 ? y3 : y3 * (1.0 - K);
+      const bool on = ((pmask >> bit) & 1u) && s2 < rc2 && s2 > 0.0;
+      double w = on ? wz : 0.0;
       double wa = mu[b] * w, wb = mu[a] * w;
       acc[3 * a] = fma(wa, d0, acc[3 * a]);
       acc[3 * a + 1] = fma(wa, d1, acc[3 * a + 1]);
@@ -669,11 +690,13 @@ __device__ void stoermer_reg(int col, double H, uint32_t pmask, const double* mu
     mu[k] = mum[k];
     rc[k] = rcm[k];
   }
+  PairConst<M> pc;
+  pair_consts<M>(rc, pc);
 #pragma unroll
   for (int i = 0; i < NN; ++i) pos[i] = xs[i];
   const int ns = 2 * (col + 1);
   const double dt = H / ns;
-  force_reg<M>(pmask, mu, rc, mu0, pos, acc);
+  force_reg<M>(pmask, mu, pc, mu0, pos, acc);
 #pragma unroll
   for (int i = 0; i < NN; ++i) {
     d[i] = dt * (vs[i] + 0.5 * dt * acc[i]);
@@ -681,14 +704,14 @@ __device__ void stoermer_reg(int col, double H, uint32_t pmask, const double* mu
   }
   const double dt2 = dt * dt;
   for (int k = 1; k < ns; ++k) {
-    force_reg<M>(pmask, mu, rc, mu0, pos, acc);
+    force_reg<M>(pmask, mu, pc, mu0, pos, acc);
 #pragma unroll
     for (int i = 0; i < NN; ++i) {
       d[i] = fma(dt2, acc[i], d[i]);
       pos[i] += d[i];
     }
   }
-  force_reg<M>(pmask, mu, rc, mu0, pos, acc);
+  force_reg<M>(pmask, mu, pc, mu0, pos, acc);
 #pragma unroll
   for (int i = 0; i < NN; ++i) {
     out[i] = pos[i];
@@ -714,6 +737,53 @@ __device__ __forceinline__ void run_column(int col, double H, int m, int np,
   }
 }
 
+// Rows K0 .. K1-1 of the Aitken-Neville tables of one candidate group: lane j
+// of the group holds elements j, j + 8, ...; prev/dg carry the previous row and
+// the diagonal across calls, lerr[k] the lane's error of row k.
+template <int M, int K0, int K1>
+__device__ __forceinline__ void neville_rows(int cand, int j, const double* scal,
+                                             const double (*resS)[kC][6 * 4],
+                                             double (&prev)[(6 * M + 7) / 8][kC],
+                                             double (&dg)[(6 * M + 7) / 8][kC], double (&lerr)[kC]) {
+  constexpr int NN = 3 * M, E = 2 * NN, EPL = (E + 7) / 8;
+#pragma unroll
+  for (int s = 0; s < EPL; ++s) {
+    const int e = j + 8 * s;
+    if (e >= E) continue;
+    const double sc = e < NN ? scal[e / 3] : scal[M + (e - NN) / 3];
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+      double T[kC];
+      T[0] = resS[cand][k][e];
+#pragma unroll
+      for (int jx = 1; jx < kC; ++jx)
+        if (jx <= k) T[jx] = fma(T[jx - 1] - prev[s][jx - 1], kNevilleInv[k][jx], T[jx - 1]);
+      dg[s][k] = T[k];
+      if (k >= 1) {
+        const double ex = T[k] - T[k - 1];
+        lerr[k] = fmax(lerr[k], ex * ex * sc);
+      }
+#pragma unroll
+      for (int jx = 0; jx < kC; ++jx)
+        if (jx <= k) prev[s][jx] = T[jx];
+    }
+  }
+}
+
+// first row k in [K0, K1) whose error, reduced over the 8 lanes of the group,
+// is within tolerance (-1 if none)
+template <int K0, int K1>
+__device__ __forceinline__ int first_ok(const double (&lerr)[kC], double tol2) {
+  int acc = -1;
+#pragma unroll
+  for (int k = K0; k < K1; ++k) {
+    double v = lerr[k];
+    for (int off = 1; off < 8; off <<= 1) v = fmax(v, __shfl_xor(v, off));
+    if (acc < 0 && k >= 1 && v <= tol2) acc = k;
+  }
+  return acc;
+}
+
 // Subsystems of M <= 4 members: each round evaluates eight step sizes at once,
 // H, H/2, ..., H/128 (lanes 8c .. 8c + 7 run the eight substep sequences of
 // step size H / 2^c), and takes the largest one the sequential control would
@@ -721,8 +791,10 @@ __device__ __forceinline__ void run_column(int col, double H, int m, int np,
 // consecutive failures of the larger ones, from the same state with the same
 // scales, so the accepted steps, their columns and the results are those of
 // the sequential loop, bit for bit, while a run of failures costs one round.
-// Returns the number of accepted steps, or -1 when more than 30 consecutive
-// failures occurred.
+// The sequences stop after 8 substeps for a first look at columns 0..3: when
+// step size H is accepted there (the usual case) the longer sequences are not
+// finished.  Returns the number of accepted steps, or -1 when more than 30
+// consecutive failures occurred.
 template <int M>
 __device__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, int np,
                         const double* mum, const double* rcm, double mu0, double* xs,
@@ -731,6 +803,23 @@ __device__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, 
   constexpr int NN = 3 * M, E = 2 * NN;
   constexpr int EPL = (E + 7) / 8;  // table elements per lane of a candidate group
   const int cand = lane >> 3, j = lane & 7;
+  double mu[M], rc[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    mu[k] = mum[k];
+    rc[k] = rcm[k];
+  }
+  PairConst<M> pc;
+  pair_consts<M>(rc, pc);
+  // model count per sequential attempt: sequences of columns 0..3 (first look)
+  // or 0..7, 3 per extrapolation-table entry (FMA = 2)
+  unsigned long long f_half = 0, f_full = 0;
+  for (int c = 0; c < kC; ++c) {
+    const unsigned long long fc = (unsigned long long)(2 * (c + 1) + 1) * (24 * M + 25 * np) +
+                                  (unsigned long long)3 * c * 6 * M;
+    f_full += fc;
+    if (c < 4) f_half += fc;
+  }
   double done = 0.0, H = h;
   int fails = 0, nsched = 0;
   while (fabs(h - done) > 1e-14 * fabs(h)) {
@@ -744,65 +833,92 @@ __device__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, 
     }
     // H / 2^cand: repeated halving is exact, so is the scaling by 2^-cand
     const double Hc = H * __longlong_as_double((long long)(1023 - cand) << 52);
-    stoermer_reg<M>(j, Hc, pmask, mum, rcm, mu0, xs, vs, resS[cand][j]);
+    // Stoermer sequence of n = 2 (j + 1) substeps (the same operations as
+    // stoermer_reg), split after substep 8
+    const int ns = 2 * (j + 1);
+    const double dt = Hc / ns, dt2 = dt * dt;
+    double pos[NN], d[NN], acc[NN];
+#pragma unroll
+    for (int i = 0; i < NN; ++i) pos[i] = xs[i];
+    force_reg<M>(pmask, mu, pc, mu0, pos, acc);
+#pragma unroll
+    for (int i = 0; i < NN; ++i) {
+      d[i] = dt * (vs[i] + 0.5 * dt * acc[i]);
+      pos[i] += d[i];
+    }
+    const int na = ns < 8 ? ns : 8;
+    for (int k = 1; k < na; ++k) {
+      force_reg<M>(pmask, mu, pc, mu0, pos, acc);
+#pragma unroll
+      for (int i = 0; i < NN; ++i) {
+        d[i] = fma(dt2, acc[i], d[i]);
+        pos[i] += d[i];
+      }
+    }
+    if (ns <= 8) {
+      double ac2[NN];
+      force_reg<M>(pmask, mu, pc, mu0, pos, ac2);
+#pragma unroll
+      for (int i = 0; i < NN; ++i) {
+        resS[cand][j][i] = pos[i];
+        resS[cand][j][NN + i] = d[i] / dt + 0.5 * dt * ac2[i];
+      }
+    }
     __syncthreads();
-    // Aitken-Neville table of candidate `cand` for elements j, j + 8, ...
-    double lerr[kC], dg[EPL][kC];
+    double lerr[kC], prev[EPL][kC], dg[EPL][kC];
 #pragma unroll
     for (int k = 0; k < kC; ++k) lerr[k] = 0.0;
 #pragma unroll
-    for (int s = 0; s < EPL; ++s) {
-      const int e = j + 8 * s;
+    for (int s = 0; s < EPL; ++s)
 #pragma unroll
-      for (int k = 0; k < kC; ++k) dg[s][k] = 0.0;
-      if (e >= E) continue;
-      const double sc = e < NN ? scal[e / 3] : scal[M + (e - NN) / 3];
-      double prev[kC];
-#pragma unroll
-      for (int k = 0; k < kC; ++k) {
-        double T[kC];
-        T[0] = resS[cand][k][e];
-#pragma unroll
-        for (int jx = 1; jx < kC; ++jx)
-          if (jx <= k) T[jx] = fma(T[jx - 1] - prev[jx - 1], kNevilleInv[k][jx], T[jx - 1]);
-        dg[s][k] = T[k];
-        if (k >= 1) {
-          const double ex = T[k] - T[k - 1];
-          lerr[k] = fmax(lerr[k], ex * ex * sc);
-        }
-#pragma unroll
-        for (int jx = 0; jx < kC; ++jx)
-          if (jx <= k) prev[jx] = T[jx];
-      }
-    }
-    int acc = -1;  // first column within tolerance for this lane's candidate
-#pragma unroll
-    for (int k = 1; k < kC; ++k) {
-      double v = lerr[k];
-      for (int off = 1; off < 8; off <<= 1) v = fmax(v, __shfl_xor(v, off));
-      if (acc < 0 && v <= tol2) acc = k;
-    }
-    // the sequential control: candidates in order, failures counted
-    const uint64_t okm = __builtin_amdgcn_ballot_w64(j == 0 && acc >= 0);
-    int chosen = -1;
+      for (int k = 0; k < kC; ++k) prev[s][k] = dg[s][k] = 0.0;
+    neville_rows<M, 0, 4>(cand, j, scal, resS, prev, dg, lerr);
+    int okc = first_ok<0, 4>(lerr, tol2);
+    const bool early = (__builtin_amdgcn_ballot_w64(lane == 0 && okc >= 0) & 1ull) != 0;
+    int chosen = -1, accepted = -1;
     bool failed = false;
-    for (int c = 0; c < 8; ++c) {
-      if ((okm >> (8 * c)) & 1ull) {
-        chosen = c;
-        break;
+    if (early) {
+      chosen = 0;
+      accepted = __shfl(okc, 0);
+    } else {
+      for (int k = 8; k < ns; ++k) {
+        force_reg<M>(pmask, mu, pc, mu0, pos, acc);
+#pragma unroll
+        for (int i = 0; i < NN; ++i) {
+          d[i] = fma(dt2, acc[i], d[i]);
+          pos[i] += d[i];
+        }
       }
-      if (++fails > 30) {
-        failed = true;
-        break;
+      if (ns > 8) {
+        force_reg<M>(pmask, mu, pc, mu0, pos, acc);
+#pragma unroll
+        for (int i = 0; i < NN; ++i) {
+          resS[cand][j][i] = pos[i];
+          resS[cand][j][NN + i] = d[i] / dt + 0.5 * dt * acc[i];
+        }
       }
+      __syncthreads();
+      neville_rows<M, 4, kC>(cand, j, scal, resS, prev, dg, lerr);
+      const int ok2 = first_ok<4, kC>(lerr, tol2);  // all lanes: the reduction crosses lanes
+      if (okc < 0) okc = ok2;
+      // the sequential control: candidates in order, failures counted
+      const uint64_t okm = __builtin_amdgcn_ballot_w64(j == 0 && okc >= 0);
+      for (int c = 0; c < 8; ++c) {
+        if ((okm >> (8 * c)) & 1ull) {
+          chosen = c;
+          break;
+        }
+        if (++fails > 30) {
+          failed = true;
+          break;
+        }
+      }
+      if (chosen >= 0) accepted = __shfl(okc, 8 * chosen);
     }
     if (lane == 0) {
-      // model count as for the sequential loop: eight columns per attempt made
-      const int att = chosen >= 0 ? chosen + 1 : 8;
-      unsigned long long f = 0;
-      for (int c = 0; c < kC; ++c) f += (unsigned long long)(2 * (c + 1) + 1) * (24 * M + 25 * np);
-      for (int k = 0; k < kC; ++k) f += (unsigned long long)3 * k * 6 * M;
-      atomicAdd(&dsc->bs_flop, f * (unsigned long long)att);
+      const unsigned long long f =
+          early ? f_half : f_full * (unsigned long long)(chosen >= 0 ? chosen + 1 : 8);
+      atomicAdd(&dsc->bs_flop, f);
     }
     __syncthreads();
     if (failed) return -1;
@@ -810,7 +926,6 @@ __device__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, 
       H = H * 0.00390625;  // eight halvings
       continue;
     }
-    const int accepted = __shfl(acc, 8 * chosen);
     if (cand == chosen) {
 #pragma unroll
       for (int s = 0; s < EPL; ++s) {

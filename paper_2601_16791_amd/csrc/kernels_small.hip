@@ -33,22 +33,21 @@ using mxd::DragConst;
 // jump by Ppost/mu0, Kepler drift.  On entry (p, v, a) is the step-start state;
 // on exit (p, v) is the pre-drift state and (q, w) the post-drift state.
 __device__ __forceinline__ bool advance_body(int t, int nb, double mu0, double h,
-                                             const DragConst& dc, int gas_on,
-                                             const double* __restrict__ r_p,
-                                             const double* __restrict__ rho_p, const double* Ppre,
-                                             const double* Ppost, double (&p)[3], double (&v)[3],
+                                             const DragConst& dc, int gas_on, double rp,
+                                             double rhop, const double* vpre,
+                                             const double* jpost, double (&p)[3], double (&v)[3],
                                              const double (&a)[3], double (&q)[3],
                                              double (&w)[3]) {
+  // vpre = Ppre / mu0 (frame velocity of the drag), jpost = (h/2) Ppost / mu0 (jump);
+  // rp, rhop: radius and density of a massless body (unused for massive ones)
   const double hh = 0.5 * h;
   double ad[3] = {0.0, 0.0, 0.0};
-  if (t >= nb && gas_on) {
-    int j = t - nb;
-    mxd::gas_drag(dc, p[0], p[1], v[0] + Ppre[0] / mu0, v[1] + Ppre[1] / mu0,
-                  v[2] + Ppre[2] / mu0, r_p[j], rho_p[j], ad[0], ad[1], ad[2]);
-  }
+  if (t >= nb && gas_on)
+    mxd::gas_drag(dc, p[0], p[1], v[0] + vpre[0], v[1] + vpre[1], v[2] + vpre[2], rp, rhop,
+                  ad[0], ad[1], ad[2]);
   for (int c = 0; c < 3; ++c) {
     v[c] += hh * (a[c] + ad[c]);
-    p[c] += hh * Ppost[c] / mu0;
+    p[c] += jpost[c];
     q[c] = p[c];
     w[c] = v[c];
   }
@@ -57,7 +56,8 @@ __device__ __forceinline__ bool advance_body(int t, int nb, double mu0, double h
 
 // Massive bodies of system D for a block: half kick, jump and drift of every
 // massive body (identical arithmetic in every block), kept in LDS.  Returns the
-// momentum sums through Ppre / Ppost.  `first` latches a failure once per system.
+// momentum terms through Ppre = P_pre / mu0 and Ppost = (h/2) P_post / mu0.
+// `first` latches a failure once per system.
 template <int BLK>
 __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double* sh,
                                             double (*bst)[kSmallBig], double* brc,
@@ -68,31 +68,39 @@ __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double
   const double* bigsnap = D.bigsnap;
   // massive bodies from the step-start snapshot (the owner tile overwrites x, u
   // of the massive bodies while other blocks may still be reading)
-  double vsum[6] = {0, 0, 0, 0, 0, 0};
-  for (int k = tid; k < nb; k += BLK) {
-    double m = D.mu[k];
-    double ux = bigsnap[3 * nb + k], uy = bigsnap[4 * nb + k], uz = bigsnap[5 * nb + k];
-    vsum[0] += m * ux;
-    vsum[1] += m * uy;
-    vsum[2] += m * uz;
-    vsum[3] += m * (ux + hh * (bigsnap[6 * nb + k] + 0.0));
-    vsum[4] += m * (uy + hh * (bigsnap[7 * nb + k] + 0.0));
-    vsum[5] += m * (uz + hh * (bigsnap[8 * nb + k] + 0.0));
-  }
-  mxd::block_sum<BLK, 6>(vsum, sh);
-  for (int c = 0; c < 3; ++c) {
-    Ppre[c] = vsum[c];
-    Ppost[c] = vsum[3 + c];
-  }
+  double p[3], v[3], a[3];
   if (tid < nb) {
-    double p[3], v[3], a[3], q[3], w[3];
     for (int c = 0; c < 3; ++c) {
       p[c] = bigsnap[c * nb + tid];
       v[c] = bigsnap[(3 + c) * nb + tid];
       a[c] = bigsnap[(6 + c) * nb + tid];
     }
-    bool ok = advance_body(tid, nb, D.mu0, D.h, D.dc, D.gas_on, D.r_p, D.rho_p, Ppre, Ppost, p,
-                           v, a, q, w);
+  }
+  // momentum sums: thread 0 adds the massive bodies in index order (the same
+  // order in every block)
+  if (tid == 0) {
+    double vsum[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < nb; ++k) {
+      double m = D.mu[k];
+      double ux = bigsnap[3 * nb + k], uy = bigsnap[4 * nb + k], uz = bigsnap[5 * nb + k];
+      vsum[0] += m * ux;
+      vsum[1] += m * uy;
+      vsum[2] += m * uz;
+      vsum[3] += m * (ux + hh * bigsnap[6 * nb + k]);
+      vsum[4] += m * (uy + hh * bigsnap[7 * nb + k]);
+      vsum[5] += m * (uz + hh * bigsnap[8 * nb + k]);
+    }
+    for (int c = 0; c < 6; ++c) sh[c] = vsum[c];
+  }
+  __syncthreads();
+  for (int c = 0; c < 3; ++c) {
+    Ppre[c] = sh[c] / D.mu0;
+    Ppost[c] = hh * sh[3 + c] / D.mu0;
+  }
+  if (tid < nb) {
+    double q[3], w[3];
+    bool ok = advance_body(tid, nb, D.mu0, D.h, D.dc, D.gas_on, 0.0, 0.0, Ppre, Ppost, p, v, a,
+                           q, w);
     if (!ok && first) atomicOr(&D.dsc->err, MXE_NOCONV);
     for (int c = 0; c < 3; ++c) {
       bst[c][tid] = p[c];
@@ -112,7 +120,7 @@ template <int BLK>
 __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc,
                                                 const Tile* __restrict__ tiles, int n_tiles,
                                                 int tpb) {
-  __shared__ double sh[6 * BLK];
+  __shared__ double sh[8];
   __shared__ double bst[12][kSmallBig];  // x0 (3) u0 (3) x1 (3) u1 (3) of the big bodies
   __shared__ double brc[kSmallBig];
   const int tid = threadIdx.x;
@@ -123,17 +131,30 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
   for (int ti = t_lo; ti < t_hi; ++ti) {
     const Tile tl = tiles[ti];
     const SysDesc& D = desc[tl.sys];
+    const int n = D.n, nb = D.nb;
+    const double h = D.h;
+    const int t = tl.first + tid;
+    // the body's state is requested before the massive-body phase, whose loads
+    // and arithmetic then overlap its latency
+    double p[3], v[3], q[3], w[3], a[3], rp = 0.0, rhop = 0.0;
+    if (t < n && t >= nb) {
+      for (int c = 0; c < 3; ++c) {
+        p[c] = D.x[c * n + t];
+        v[c] = D.u[c * n + t];
+        a[c] = D.ag[c * n + t];
+      }
+      if (D.gas_on) {
+        rp = D.r_p[t - nb];
+        rhop = D.rho_p[t - nb];
+      }
+    }
     if (tl.sys != cur) {
       __syncthreads();  // the previous tile is done with the LDS copies
       big_phase_a<BLK>(D, tl.first == 0, sh, bst, brc, Ppre, Ppost);
       __syncthreads();
       cur = tl.sys;
     }
-    const int n = D.n, nb = D.nb;
-    const double h = D.h;
-    const int t = tl.first + tid;
     if (t >= n) continue;
-    double p[3], v[3], q[3], w[3];
     if (t < nb) {
       for (int c = 0; c < 3; ++c) {
         p[c] = bst[c][t];
@@ -146,14 +167,7 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
         D.bigmid[(3 + c) * nb + t] = w[c];
       }
     } else {
-      double a[3];
-      for (int c = 0; c < 3; ++c) {
-        p[c] = D.x[c * n + t];
-        v[c] = D.u[c * n + t];
-        a[c] = D.ag[c * n + t];
-      }
-      if (!advance_body(t, nb, D.mu0, h, D.dc, D.gas_on, D.r_p, D.rho_p, Ppre, Ppost, p, v, a, q,
-                        w))
+      if (!advance_body(t, nb, D.mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v, a, q, w))
         atomicOr(&D.dsc->err, MXE_NOCONV);
     }
     for (int c = 0; c < 3; ++c) {
@@ -166,6 +180,7 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
     const int imax = t < nb ? t : nb;
     const double k427 = (4.0 / 27.0) * fabs(h);
     bool hit = false;
+#pragma unroll 4
     for (int i = 0; i < imax; ++i) {
       double r0[3], w0[3], w1[3], dd[3];
       for (int c = 0; c < 3; ++c) {
@@ -214,40 +229,75 @@ template <int BLK>
 __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc,
                                                 const Tile* __restrict__ tiles, int n_tiles,
                                                 int tpb, int kick) {
-  __shared__ double sh[3 * BLK];
+  __shared__ double sh[4];
   __shared__ KickSource src[kSmallBig];
   const int tid = threadIdx.x;
   const int t_lo = blockIdx.x * tpb;
   const int t_hi = min(n_tiles, t_lo + tpb);
   int cur = -1;
-  double P[3], J[3];
+  double P[3], J[3], vpre[3];
   for (int ti = t_lo; ti < t_hi; ++ti) {
     const Tile tl = tiles[ti];
     const SysDesc& D = desc[tl.sys];
     const int n = D.n, nb = D.nb;
     const double hh = 0.5 * D.h, mu0 = D.mu0;
+    const int t = tl.first + tid;
+    double* __restrict__ x = D.x;
+    double* __restrict__ u = D.u;
+    double* __restrict__ ag = D.ag;
+    // the body's state is requested before the massive-body phase
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0, vx = 0.0, vy = 0.0, vz = 0.0, rp = 0.0, rhop = 0.0;
+    if (t < n) {
+      x0 = x[t];
+      x1 = x[n + t];
+      x2 = x[2 * n + t];
+      if (kick) {
+        vx = u[t];
+        vy = u[n + t];
+        vz = u[2 * n + t];
+        if (t >= nb && D.gas_on) {
+          rp = D.r_p[t - nb];
+          rhop = D.rho_p[t - nb];
+        }
+      }
+    }
     if (tl.sys != cur) {
       __syncthreads();  // the previous tile is done with the LDS sources
       // massive bodies after drift and encounters from their snapshot (the owner
-      // tile overwrites x, u of the massive bodies while other blocks may read)
-      for (int c = 0; c < 3; ++c) P[c] = 0.0;
-      for (int k = tid; k < nb; k += BLK) {
-        double m = D.mu[k];
-        P[0] += m * D.bigmid[3 * nb + k];
-        P[1] += m * D.bigmid[4 * nb + k];
-        P[2] += m * D.bigmid[5 * nb + k];
+      // tile overwrites x, u of the massive bodies while other blocks may read);
+      // thread 0 adds the momentum in index order (the same in every block)
+      if (tid == 0) {
+        double Q[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < nb; ++k) {
+          double m = D.mu[k];
+          Q[0] += m * D.bigmid[3 * nb + k];
+          Q[1] += m * D.bigmid[4 * nb + k];
+          Q[2] += m * D.bigmid[5 * nb + k];
+        }
+        for (int c = 0; c < 3; ++c) sh[c] = Q[c];
       }
-      mxd::block_sum<BLK, 3>(P, sh);
-      for (int c = 0; c < 3; ++c) J[c] = hh * P[c] / mu0;
+      double bx = 0.0, by = 0.0, bz = 0.0, bm = 0.0, brc = 0.0;
+      if (tid < nb) {
+        bx = D.bigmid[tid];
+        by = D.bigmid[nb + tid];
+        bz = D.bigmid[2 * nb + tid];
+        bm = D.mu[tid];
+        brc = D.rcrit[tid];
+      }
+      __syncthreads();
+      for (int c = 0; c < 3; ++c) {
+        P[c] = sh[c];
+        J[c] = hh * P[c] / mu0;
+        vpre[c] = P[c] / mu0;
+      }
       if (tid < nb) {
         KickSource k;
-        double rc = D.rcrit[tid];
-        k.x = D.bigmid[tid] + J[0];
-        k.y = D.bigmid[nb + tid] + J[1];
-        k.z = D.bigmid[2 * nb + tid] + J[2];
-        k.mu = D.mu[tid];
-        k.rc2 = fmax(rc * rc, 1e-300);
-        k.rc = rc;
+        k.x = bx + J[0];
+        k.y = by + J[1];
+        k.z = bz + J[2];
+        k.mu = bm;
+        k.rc2 = fmax(brc * brc, 1e-300);
+        k.rc = brc;
         k.pad0 = k.pad1 = 0.0;
         src[tid] = k;
       }
@@ -263,12 +313,8 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
         D.dsc->n_pairs = 0;  // the encounter list of this step has been planned
       }
     }
-    const int t = tl.first + tid;
     if (t >= n) continue;
-    double* __restrict__ x = D.x;
-    double* __restrict__ u = D.u;
-    double* __restrict__ ag = D.ag;
-    const double px = x[t] + J[0], py = x[n + t] + J[1], pz = x[2 * n + t] + J[2];
+    const double px = x0 + J[0], py = x1 + J[1], pz = x2 + J[2];
     x[t] = px;
     x[n + t] = py;
     x[2 * n + t] = pz;
@@ -277,6 +323,7 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
     double k15, k1875;
     mxd::vgpr_constants(k15, k1875);
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
     for (int s = 0; s < nb; ++s) {
       const KickSource S = src[s];
       double dx = S.x - px, dy = S.y - py, dz = S.z - pz;
@@ -292,13 +339,10 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
     ag[n + t] = a1;
     ag[2 * n + t] = a2;
     if (!kick) continue;
-    double vx = u[t], vy = u[n + t], vz = u[2 * n + t];
     double adx = 0.0, ady = 0.0, adz = 0.0;
-    if (t >= nb && D.gas_on) {
-      int j = t - nb;
-      mxd::gas_drag(D.dc, px, py, vx + P[0] / mu0, vy + P[1] / mu0, vz + P[2] / mu0, D.r_p[j],
-                    D.rho_p[j], adx, ady, adz);
-    }
+    if (t >= nb && D.gas_on)
+      mxd::gas_drag(D.dc, px, py, vx + vpre[0], vy + vpre[1], vz + vpre[2], rp, rhop, adx, ady,
+                    adz);
     vx += hh * (a0 + adx);
     vy += hh * (a1 + ady);
     vz += hh * (a2 + adz);

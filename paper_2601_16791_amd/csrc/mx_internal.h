@@ -61,6 +61,8 @@ namespace mxd {
 struct DragConst {
   double mu0, sigma1_unit, gamma, r_c, inv_rc, r_in, h_over_r, vg_fac, kexp, mfp_coef;
   double rc_norm;  // (1/r_c)^(2-gamma), the normalisation of the taper at 1 AU
+  double rho_fac;  // 1 / (sqrt(2 pi) H/r): midplane density = Sigma / R * rho_fac
+  double re_fac;   // 6 / (sqrt(8/pi) mfp_coef): Re = re_fac r_p dv rho_g / c_s
 };
 
 // Drag constants of a parameter set (host side).
@@ -77,6 +79,8 @@ inline DragConst make_drag_const(const mx_params& p) {
   c.kexp = p.kdrag_exp;
   c.mfp_coef = p.mfp_coef;
   c.rc_norm = p.r_c > 0.0 ? pow(1.0 / p.r_c, 2.0 - p.gamma) : 0.0;
+  c.rho_fac = 1.0 / (2.5066282746310002 * p.h_over_r);
+  c.re_fac = 6.0 / (1.5957691216057308 * p.mfp_coef);
   return c;
 }
 }  // namespace mxd
