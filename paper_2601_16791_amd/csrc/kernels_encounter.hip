@@ -172,25 +172,39 @@ __device__ bool insert_sorted(int32_t* v, int& m, int cap, int b) {
 // Sort of np distinct keys in[0, np) into out by rank: the rank of a key is the
 // number of smaller keys, counted against every key read as a wave-uniform LDS
 // broadcast.  One wave; its LDS accesses complete in order.
-__device__ void wave_rank_sort(const int64_t* in, int64_t* out, int np) {
+__device__ __forceinline__ int64_t key_max(int64_t) { return INT64_MAX; }
+__device__ __forceinline__ uint32_t key_max(uint32_t) { return 0xffffffffu; }
+
+template <class K>
+__device__ __forceinline__ void wave_rank_sort(const K* in, K* out, int np) {
   const int lane = threadIdx.x & 63;
-  int64_t key[4];
+  const int nr = (np + 63) >> 6;  // key slots in use per lane (np <= 256)
+  K key[4];
   int rank[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int e = 64 * r + lane;
-    key[r] = e < np ? in[e] : INT64_MAX;
+    key[r] = e < np ? in[e] : key_max(K());
     rank[r] = 0;
   }
+  // sixteen broadcast reads in flight per round
   int f = 0;
-  for (; f + 4 <= np; f += 4) {
-    const int64_t k0 = in[f], k1 = in[f + 1], k2 = in[f + 2], k3 = in[f + 3];
+  for (; f + 16 <= np; f += 16) {
+    K kk[16];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      rank[r] += (k0 < key[r]) + (k1 < key[r]) + (k2 < key[r]) + (k3 < key[r]);
+    for (int q = 0; q < 16; ++q) kk[q] = in[f + q];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (r < nr) {
+        int c = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) c += kk[q] < key[r];
+        rank[r] += c;
+      }
+    }
   }
   for (; f < np; ++f) {
-    const int64_t k0 = in[f];
+    const K k0 = in[f];
 #pragma unroll
     for (int r = 0; r < 4; ++r) rank[r] += k0 < key[r];
   }
@@ -211,11 +225,13 @@ constexpr int kPlanLds = 2048;   // pairs handled in LDS; larger lists use globa
 //     of the big bodies flagged with j, plus j (only j kept).
 // gkeys: [2*cap] int64 global scratch; gidx: [2*cap] int32 global scratch.
 // uf: [2*nb] with par[b] = b and inbig[b] = 0 at rest (restored on exit).
-__device__ __forceinline__ void plan_block(int nb, int32_t* __restrict__ pairs, int32_t cap,
+__device__ __forceinline__ void plan_block(int n, int nb, int32_t* __restrict__ pairs, int32_t cap,
                                            int64_t* __restrict__ gkeys,
                                            int32_t* __restrict__ gidx, int32_t* __restrict__ uf,
                                            Subsystem* __restrict__ subs, int32_t cap_subs,
                                            DevScalars* __restrict__ dsc, int sort_only) {
+  const auto gpairs = gbl(pairs);
+  const auto gsubs = gbl(subs);
   __shared__ int64_t lk[kPlanLds];
   __shared__ int64_t ls[kPlanLds];
   __shared__ int32_t lbb[kPlanLds];
@@ -237,30 +253,47 @@ __device__ __forceinline__ void plan_block(int nb, int32_t* __restrict__ pairs, 
   {
     bool bb = false;
     if (np <= 256)
-      for (int q = threadIdx.x; q < np; q += blockDim.x) bb |= pairs[2 * q + 1] < nb;
+      for (int q = threadIdx.x; q < np; q += blockDim.x) bb |= gpairs[2 * q + 1] < nb;
     const bool any_bb = __syncthreads_or(bb);
     if (np <= 256 && !any_bb) {
       if (threadIdx.x >= 64) return;
       const int lane = threadIdx.x;
-      for (int e = lane; e < np; e += 64) ls[e] = make_key(pairs[2 * e], pairs[2 * e + 1]);
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      wave_rank_sort(ls, lk, np);  // (i, j) order
-      for (int e = lane; e < np; e += 64) {
-        pairs[2 * e] = key_hi(lk[e]);
-        pairs[2 * e + 1] = key_lo(lk[e]);
-      }
-      if (sort_only) return;
-      // regroup by massless body j: keys (j, i)
-      for (int e = lane; e < np; e += 64) lk[256 + e] = make_key(key_lo(lk[e]), key_hi(lk[e]));
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      wave_rank_sort(lk + 256, ls, np);
-      int32_t* lj = reinterpret_cast<int32_t*>(lk);  // [256] j of the sorted list
+      int32_t* lj = reinterpret_cast<int32_t*>(lk);  // [256] j of the (j, i)-sorted list
       int32_t* li = lj + 256;                          // [256] i
-      for (int e = lane; e < np; e += 64) {
-        lj[e] = key_hi(ls[e]);
-        li[e] = key_lo(ls[e]);
+      if (!sort_only && nb <= 64 && n > 0 && n < (1 << 26)) {
+        // Only the grouping by massless body is needed here: one sort of 32-bit
+        // keys (j, i).  The list in memory stays in append order; the host puts
+        // it in (i, j) order when it is read.
+        uint32_t* ka = reinterpret_cast<uint32_t*>(ls);
+        uint32_t* kb = ka + 256;
+        for (int e = lane; e < np; e += 64)
+          ka[e] = ((uint32_t)gpairs[2 * e + 1] << 6) | (uint32_t)gpairs[2 * e];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        wave_rank_sort(ka, kb, np);
+        for (int e = lane; e < np; e += 64) {
+          lj[e] = (int32_t)(kb[e] >> 6);
+          li[e] = (int32_t)(kb[e] & 63u);
+        }
+      } else {
+        for (int e = lane; e < np; e += 64) ls[e] = make_key(gpairs[2 * e], gpairs[2 * e + 1]);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        wave_rank_sort(ls, lk, np);  // (i, j) order
+        for (int e = lane; e < np; e += 64) {
+          gpairs[2 * e] = key_hi(lk[e]);
+          gpairs[2 * e + 1] = key_lo(lk[e]);
+        }
+        if (sort_only) return;
+        // regroup by massless body j: keys (j, i)
+        for (int e = lane; e < np; e += 64) lk[256 + e] = make_key(key_lo(lk[e]), key_hi(lk[e]));
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        wave_rank_sort(lk + 256, ls, np);
+        for (int e = lane; e < np; e += 64) {
+          lj[e] = key_hi(ls[e]);
+          li[e] = key_lo(ls[e]);
+        }
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -276,7 +309,7 @@ __device__ __forceinline__ void plan_block(int nb, int32_t* __restrict__ pairs, 
         int k = 1;
         while (e + k < np && lj[e + k] == lj[e]) ++k;
         const int j = lj[e];
-        Subsystem* S = subs + g;
+        const auto S = gsubs + g;
         if (g >= cap_subs) {
           atomicOr(&dsc->err, MXE_SUBSYS);
           continue;
@@ -313,12 +346,12 @@ __device__ __forceinline__ void plan_block(int nb, int32_t* __restrict__ pairs, 
   // 1. sort by (i, j)
   int p2 = next_pow2(np);
   for (int q = tid; q < p2; q += T)
-    K[q] = q < np ? make_key(pairs[2 * q], pairs[2 * q + 1]) : INT64_MAX;
+    K[q] = q < np ? make_key(gpairs[2 * q], gpairs[2 * q + 1]) : INT64_MAX;
   __syncthreads();
   if (np > 1) block_bitonic(K, p2);
   for (int q = tid; q < np; q += T) {
-    pairs[2 * q] = key_hi(K[q]);
-    pairs[2 * q + 1] = key_lo(K[q]);
+    gpairs[2 * q] = key_hi(K[q]);
+    gpairs[2 * q + 1] = key_lo(K[q]);
   }
   if (sort_only) return;
   // 2. big-big pairs (in (i, j) order) and massless pairs keyed (j, i)
@@ -465,14 +498,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(
     int nb, int32_t* __restrict__ pairs, int32_t cap, int64_t* __restrict__ gkeys,
     int32_t* __restrict__ gidx, int32_t* __restrict__ uf, Subsystem* __restrict__ subs,
     int32_t cap_subs, DevScalars* __restrict__ dsc, int sort_only) {
-  plan_block(nb, pairs, cap, gkeys, gidx, uf, subs, cap_subs, dsc, sort_only);
+  plan_block(0, nb, pairs, cap, gkeys, gidx, uf, subs, cap_subs, dsc, sort_only);
 }
 
 // one block per system of the descriptor table
 __global__ __launch_bounds__(kPlanThreads) void k_plan_sys(const SysDesc* __restrict__ desc) {
   const SysDesc& D = desc[blockIdx.x];
   if (D.nb == 0) return;
-  plan_block(D.nb, D.pairs, D.cap_pairs, D.keys, D.plan_idx, D.uf, D.subs, D.cap_subs, D.dsc, 0);
+  plan_block(D.n, D.nb, D.pairs, D.cap_pairs, D.keys, D.plan_idx, D.uf, D.subs, D.cap_subs, D.dsc, 0);
 }
 
 // ------------------------------------------------------------------ BS
@@ -965,15 +998,15 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc) {
   const SysDesc& D = desc[blockIdx.y];
   const int n = D.n, nb = D.nb;
   const double mu0 = D.mu0, h = D.h, tol = D.bs_tol;
-  const double* __restrict__ x0s = D.x0;
-  const double* __restrict__ u0s = D.u0;
-  double* __restrict__ x = D.x;
-  double* __restrict__ u = D.u;
-  const double* __restrict__ mu = D.mu;
-  const double* __restrict__ rcrit = D.rcrit;
-  const Subsystem* __restrict__ subs = D.subs;
+  const auto x0s = gbl(D.x0);
+  const auto u0s = gbl(D.u0);
+  const auto x = gbl(D.x);
+  const auto u = gbl(D.u);
+  const auto mu = gbl(D.mu);
+  const auto rcrit = gbl(D.rcrit);
+  const auto subs = gbl(D.subs);
   DevScalars* __restrict__ dsc = D.dsc;
-  double* __restrict__ bigmid = D.bigmid;
+  const auto bigmid = gbl(D.bigmid);
   if (nb == 0) return;
   __shared__ Subsystem S;
   __shared__ double xs[3 * kM], vs[3 * kM], mum[kM], rcm[kM], scal[2 * kM];
@@ -986,7 +1019,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc) {
   for (int b = blockIdx.x; b < nsub; b += gridDim.x) {
     __syncthreads();
     {
-      const int32_t* src = reinterpret_cast<const int32_t*>(subs + b);
+      const auto src = reinterpret_cast<gmem<const int32_t>>(subs + b);
       int32_t* dst = reinterpret_cast<int32_t*>(&S);
       for (int i = lane; i < (int)(sizeof(Subsystem) / 4); i += 64) dst[i] = src[i];
     }

@@ -65,7 +65,7 @@ __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double
   const int tid = threadIdx.x;
   const int nb = D.nb;
   const double hh = 0.5 * D.h;
-  const double* bigsnap = D.bigsnap;
+  const auto bigsnap = gbl(D.bigsnap);
   // massive bodies from the step-start snapshot (the owner tile overwrites x, u
   // of the massive bodies while other blocks may still be reading)
   double p[3], v[3], a[3];
@@ -81,7 +81,7 @@ __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double
   if (tid == 0) {
     double vsum[6] = {0, 0, 0, 0, 0, 0};
     for (int k = 0; k < nb; ++k) {
-      double m = D.mu[k];
+      double m = gbl(D.mu)[k];
       double ux = bigsnap[3 * nb + k], uy = bigsnap[4 * nb + k], uz = bigsnap[5 * nb + k];
       vsum[0] += m * ux;
       vsum[1] += m * uy;
@@ -108,7 +108,7 @@ __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double
       bst[6 + c][tid] = q[c];
       bst[9 + c][tid] = w[c];
     }
-    brc[tid] = D.rcrit[tid];
+    brc[tid] = gbl(D.rcrit)[tid];
   }
 }
 
@@ -139,13 +139,13 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
     double p[3], v[3], q[3], w[3], a[3], rp = 0.0, rhop = 0.0;
     if (t < n && t >= nb) {
       for (int c = 0; c < 3; ++c) {
-        p[c] = D.x[c * n + t];
-        v[c] = D.u[c * n + t];
-        a[c] = D.ag[c * n + t];
+        p[c] = gbl(D.x)[c * n + t];
+        v[c] = gbl(D.u)[c * n + t];
+        a[c] = gbl(D.ag)[c * n + t];
       }
       if (D.gas_on) {
-        rp = D.r_p[t - nb];
-        rhop = D.rho_p[t - nb];
+        rp = gbl(D.r_p)[t - nb];
+        rhop = gbl(D.rho_p)[t - nb];
       }
     }
     if (tl.sys != cur) {
@@ -163,16 +163,16 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
         w[c] = bst[9 + c][t];
       }
       for (int c = 0; c < 3; ++c) {
-        D.bigmid[c * nb + t] = q[c];
-        D.bigmid[(3 + c) * nb + t] = w[c];
+        gbl(D.bigmid)[c * nb + t] = q[c];
+        gbl(D.bigmid)[(3 + c) * nb + t] = w[c];
       }
     } else {
       if (!advance_body(t, nb, D.mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v, a, q, w))
         atomicOr(&D.dsc->err, MXE_NOCONV);
     }
     for (int c = 0; c < 3; ++c) {
-      D.x[c * n + t] = q[c];
-      D.u[c * n + t] = w[c];
+      gbl(D.x)[c * n + t] = q[c];
+      gbl(D.u)[c * n + t] = w[c];
     }
     // encounter test against every massive body i < t (same bound and exact
     // Hermite test as the general flag kernel)
@@ -204,8 +204,8 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
           hit = true;
           int idx = atomicAdd(&D.dsc->n_pairs, 1);
           if (idx < D.cap_pairs) {
-            D.pairs[2 * idx] = i;
-            D.pairs[2 * idx + 1] = t;
+            gbl(D.pairs)[2 * idx] = i;
+            gbl(D.pairs)[2 * idx + 1] = t;
           } else {
             atomicOr(&D.dsc->err, MXE_PAIRS);
           }
@@ -215,8 +215,8 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
     // pre-drift state: the encounter integrator starts its subsystems from it
     if (hit || t < nb || D.keep_x0) {
       for (int c = 0; c < 3; ++c) {
-        D.x0[c * n + t] = p[c];
-        D.u0[c * n + t] = v[c];
+        gbl(D.x0)[c * n + t] = p[c];
+        gbl(D.u0)[c * n + t] = v[c];
       }
     }
   }
@@ -242,9 +242,9 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
     const int n = D.n, nb = D.nb;
     const double hh = 0.5 * D.h, mu0 = D.mu0;
     const int t = tl.first + tid;
-    double* __restrict__ x = D.x;
-    double* __restrict__ u = D.u;
-    double* __restrict__ ag = D.ag;
+    const auto x = gbl(D.x);
+    const auto u = gbl(D.u);
+    const auto ag = gbl(D.ag);
     // the body's state is requested before the massive-body phase
     double x0 = 0.0, x1 = 0.0, x2 = 0.0, vx = 0.0, vy = 0.0, vz = 0.0, rp = 0.0, rhop = 0.0;
     if (t < n) {
@@ -256,8 +256,8 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
         vy = u[n + t];
         vz = u[2 * n + t];
         if (t >= nb && D.gas_on) {
-          rp = D.r_p[t - nb];
-          rhop = D.rho_p[t - nb];
+          rp = gbl(D.r_p)[t - nb];
+          rhop = gbl(D.rho_p)[t - nb];
         }
       }
     }
@@ -269,20 +269,20 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
       if (tid == 0) {
         double Q[3] = {0.0, 0.0, 0.0};
         for (int k = 0; k < nb; ++k) {
-          double m = D.mu[k];
-          Q[0] += m * D.bigmid[3 * nb + k];
-          Q[1] += m * D.bigmid[4 * nb + k];
-          Q[2] += m * D.bigmid[5 * nb + k];
+          double m = gbl(D.mu)[k];
+          Q[0] += m * gbl(D.bigmid)[3 * nb + k];
+          Q[1] += m * gbl(D.bigmid)[4 * nb + k];
+          Q[2] += m * gbl(D.bigmid)[5 * nb + k];
         }
         for (int c = 0; c < 3; ++c) sh[c] = Q[c];
       }
       double bx = 0.0, by = 0.0, bz = 0.0, bm = 0.0, brc = 0.0;
       if (tid < nb) {
-        bx = D.bigmid[tid];
-        by = D.bigmid[nb + tid];
-        bz = D.bigmid[2 * nb + tid];
-        bm = D.mu[tid];
-        brc = D.rcrit[tid];
+        bx = gbl(D.bigmid)[tid];
+        by = gbl(D.bigmid)[nb + tid];
+        bz = gbl(D.bigmid)[2 * nb + tid];
+        bm = gbl(D.mu)[tid];
+        brc = gbl(D.rcrit)[tid];
       }
       __syncthreads();
       for (int c = 0; c < 3; ++c) {
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
     u[2 * n + t] = vz;
     if (!isfinite(vx + vy + vz + px + py + pz)) atomicOr(&D.dsc->err, MXE_NONFINITE);
     if (t < nb) {
-      double* bigsnap = D.bigsnap;
+      const auto bigsnap = gbl(D.bigsnap);
       bigsnap[t] = px; bigsnap[nb + t] = py; bigsnap[2 * nb + t] = pz;
       bigsnap[3 * nb + t] = vx; bigsnap[4 * nb + t] = vy; bigsnap[5 * nb + t] = vz;
       bigsnap[6 * nb + t] = a0; bigsnap[7 * nb + t] = a1; bigsnap[8 * nb + t] = a2;

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <string>
 
+#include <algorithm>
 #include <vector>
 
 #include "mx_internal.h"
@@ -458,9 +459,22 @@ mx_status mx_encounters(mx_system* s, int32_t* pairs, int32_t cap, int32_t* n_ou
   DevScalars d;
   HIPCHK(hipMemcpy(&d, s->dsc, sizeof(DevScalars), hipMemcpyDeviceToHost), "read scalars");
   *n_out = d.n_pairs_last;
-  int m = d.n_pairs_last < cap ? d.n_pairs_last : cap;
-  if (m > s->cap_pairs) m = s->cap_pairs;
-  if (m > 0) HIPCHK(hipMemcpy(pairs, s->pairs, sizeof(int32_t) * 2 * m, hipMemcpyDeviceToHost), "copy pairs");
+  // the planner may leave the list in append order: order it by (i, j) here
+  const int all = d.n_pairs_last < s->cap_pairs ? d.n_pairs_last : s->cap_pairs;
+  const int m = all < cap ? all : cap;
+  if (m > 0) {
+    std::vector<int32_t> buf(2 * (size_t)all);
+    HIPCHK(hipMemcpy(buf.data(), s->pairs, sizeof(int32_t) * 2 * all, hipMemcpyDeviceToHost),
+           "copy pairs");
+    std::vector<int64_t> key(all);
+    for (int q = 0; q < all; ++q)
+      key[q] = ((int64_t)buf[2 * q] << 32) | (uint32_t)buf[2 * q + 1];
+    std::sort(key.begin(), key.end());
+    for (int q = 0; q < m; ++q) {
+      pairs[2 * q] = (int32_t)(key[q] >> 32);
+      pairs[2 * q + 1] = (int32_t)(key[q] & 0xffffffff);
+    }
+  }
   return MX_OK;
 }
 

@@ -113,6 +113,17 @@ struct SysDesc {
   int32_t keep_x0;
 };
 
+// Global-memory view of a device pointer.  Pointers read from a descriptor
+// table are generic, and accesses through them compile to flat instructions
+// (which also hold the LDS counter); through this view they compile to global
+// loads and stores.
+template <class T>
+using gmem = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gmem<T> gbl(T* p) {
+  return (gmem<T>)p;
+}
+
 // A tile of consecutive bodies of one system for the fused small-B kernels.
 struct Tile {
   int32_t sys, first;
