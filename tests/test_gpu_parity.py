@@ -434,3 +434,46 @@ def test_full_size_embryo_disk_step(mx, orc):
     assert {tuple(p) for p in g.encounters()} == {tuple(p) for p in o.encounters()}
     assert np.all(relerr_per_body(xg, xo) <= np.maximum(1e-12, 10 * sx))
     assert np.all(relerr_per_body(ug, uo) <= np.maximum(1e-12, 10 * su))
+
+
+def test_deep_encounters_with_step_halvings(mx, orc):
+    """Massless bodies aimed at an embryo with impact parameters of 0.3-3% of its
+    changeover radius and slow approach: the encounter integrator has to halve its
+    step repeatedly (the rounds that try eight step sizes at once must pick the
+    step the sequential control would accept).  Several steps, each started from
+    the same state on both sides, every body against the oracle within its own
+    one-ulp sensitivity."""
+    w = ic.embryo_disk(seed=8, n_small=200, n_emb=3)
+    o = orc.OracleSystem.from_workload(w)
+    rc = o.mu()[1].copy()
+    o.close()
+    nb = w.params["n_big"]
+    rng = np.random.default_rng(8)
+    h = w.params["dt"]
+    for q, b in enumerate((0.003, 0.01, 0.03)):
+        j = nb + q
+        # start one step before closest approach, at impact parameter b rc
+        vrel = 0.3 * rc[0] / h
+        dirn = rng.normal(size=3)
+        dirn /= np.linalg.norm(dirn)
+        perp = np.cross(dirn, rng.normal(size=3))
+        perp /= np.linalg.norm(perp)
+        w.x[:, j] = w.x[:, 0] + b * rc[0] * perp - vrel * h * dirn
+        w.v[:, j] = w.v[:, 0] + vrel * dirn
+    g = mx.System.from_workload(w)
+    o = orc.OracleSystem.from_workload(w)
+    x, u = g.get_dh()
+    flagged = 0
+    for k in range(4):
+        g.set_dh(x, u, k)
+        g.step(1)
+        g.sync()
+        xo, uo, sx, su = oracle_sensitivity(o, x, u, k, trials=1)
+        xg, ug = g.get_dh()
+        po = {tuple(p) for p in o.encounters()}
+        assert {tuple(p) for p in g.encounters()} == po, k
+        flagged += sum(1 for (i, jj) in po if i == 0 and nb <= jj < nb + 3)
+        assert np.all(relerr_per_body(xg, xo) <= np.maximum(1e-12, 10 * sx)), k
+        assert np.all(relerr_per_body(ug, uo) <= np.maximum(1e-12, 10 * su)), k
+        x, u = xg, ug
+    assert flagged >= 3
