@@ -803,6 +803,23 @@ __device__ __forceinline__ void neville_rows(int cand, int j, const double* scal
   }
 }
 
+// Lane exchange within rows of the wave by DPP (VALU moves, no LDS round trip):
+// quad_perm [1,0,3,2] (0xB1) and [2,3,0,1] (0x4E) swap within quads, row_half_mirror
+// (0x141) maps lane i of each group of eight to lane 7 - i.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// maximum over the 8 lanes of each group (every lane receives it)
+__device__ __forceinline__ double group8_max(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  return fmax(v, dpp_f64<0x141>(v));
+}
+
 // first row k in [K0, K1) whose error, reduced over the 8 lanes of the group,
 // is within tolerance (-1 if none)
 template <int K0, int K1>
@@ -810,8 +827,7 @@ __device__ __forceinline__ int first_ok(const double (&lerr)[kC], double tol2) {
   int acc = -1;
 #pragma unroll
   for (int k = K0; k < K1; ++k) {
-    double v = lerr[k];
-    for (int off = 1; off < 8; off <<= 1) v = fmax(v, __shfl_xor(v, off));
+    const double v = group8_max(lerr[k]);
     if (acc < 0 && k >= 1 && v <= tol2) acc = k;
   }
   return acc;
