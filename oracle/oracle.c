@@ -363,18 +363,30 @@ int or_drift(double mu, const double x0[3], const double v0[3], double h, double
  * (r0, h*w0) at tau = 0 and (r1, h*w1) at tau = 1.  Its squared length is
  * minimised over the end points and over every interior root of d|r|^2/dtau
  * at which the derivative changes from negative to non-negative on a fixed
- * 16-interval grid; each such root is refined by 40 bisection steps.         */
-static void herm_eval(const double c[4][3], double tau, double r[3], double dr[3]) {
-  for (int k = 0; k < 3; ++k) {
+ * 16-interval grid; each such root is refined by 40 bisection steps.  The
+ * derivative (halved) is r . r', a quintic in tau whose coefficient of tau^m is
+ * the sum of j c_i . c_j over i + j = m + 1 (c_0..c_3 the cubic's
+ * coefficients); it is evaluated by Horner's rule.                            */
+static void herm_pos(const double c[4][3], double tau, double r[3]) {
+  for (int k = 0; k < 3; ++k)
     r[k] = c[0][k] + tau * (c[1][k] + tau * (c[2][k] + tau * c[3][k]));
-    dr[k] = c[1][k] + tau * (2.0 * c[2][k] + tau * 3.0 * c[3][k]);
-  }
 }
 
-static double herm_dd(const double c[4][3], double tau) {
-  double r[3], dr[3];
-  herm_eval(c, tau, r, dr);
-  return 2.0 * (r[0] * dr[0] + r[1] * dr[1] + r[2] * dr[2]);
+static double dot3(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+static void herm_poly(const double c[4][3], double a[6]) {
+  a[0] = dot3(c[0], c[1]);
+  a[1] = dot3(c[1], c[1]) + 2.0 * dot3(c[0], c[2]);
+  a[2] = 3.0 * dot3(c[0], c[3]) + 3.0 * dot3(c[1], c[2]);
+  a[3] = 4.0 * dot3(c[1], c[3]) + 2.0 * dot3(c[2], c[2]);
+  a[4] = 5.0 * dot3(c[2], c[3]);
+  a[5] = 3.0 * dot3(c[3], c[3]);
+}
+
+static double herm_dd(const double a[6], double tau) {
+  return a[0] + tau * (a[1] + tau * (a[2] + tau * (a[3] + tau * (a[4] + tau * a[5]))));
 }
 
 double or_pair_dmin2(const double r0[3], const double w0[3], const double r1[3],
@@ -386,22 +398,24 @@ double or_pair_dmin2(const double r0[3], const double w0[3], const double r1[3],
     c[2][k] = 3.0 * (r1[k] - r0[k]) - h * (2.0 * w0[k] + w1[k]);
     c[3][k] = 2.0 * (r0[k] - r1[k]) + h * (w0[k] + w1[k]);
   }
+  double a[6];
+  herm_poly(c, a);
   double d0 = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
   double d1 = r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2];
   double best = d0 < d1 ? d0 : d1;
   const int NG = 16;
-  double dprev = herm_dd(c, 0.0);
+  double dprev = herm_dd(a, 0.0);
   for (int k = 0; k < NG; ++k) {
     double t1 = (double)(k + 1) / NG;
-    double dnext = herm_dd(c, t1);
+    double dnext = herm_dd(a, t1);
     if (dprev < 0.0 && dnext >= 0.0) {
       double lo = (double)k / NG, hi = t1;
       for (int it = 0; it < 40; ++it) {
         double mid = 0.5 * (lo + hi);
-        if (herm_dd(c, mid) < 0.0) lo = mid; else hi = mid;
+        if (herm_dd(a, mid) < 0.0) lo = mid; else hi = mid;
       }
-      double r[3], dr[3];
-      herm_eval(c, 0.5 * (lo + hi), r, dr);
+      double r[3];
+      herm_pos(c, 0.5 * (lo + hi), r);
       double d = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
       if (d < best) best = d;
     }

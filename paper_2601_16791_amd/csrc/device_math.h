@@ -233,8 +233,11 @@ __device__ __forceinline__ bool kepler_drift(double mu, double h, double& x, dou
 // of the relative position (end values r0, r1 and rates w0, w1 over [0, h]):
 // the end points plus each interior minimum of |r|^2 located by a sign change
 // (negative to non-negative) of d|r|^2/dtau on a 16-interval grid, refined by
-// 40 bisection steps.  Evaluated without contraction so that it is the plain
-// sequence of IEEE operations of its definition.
+// 40 bisection steps.  The derivative (halved) is r . r', a quintic in tau
+// whose coefficient of tau^m is the sum of j c_i . c_j over i + j = m + 1
+// (c_0..c_3 the cubic's coefficients), evaluated by Horner's rule.  Evaluated
+// without contraction so that it is the plain sequence of IEEE operations of
+// its definition.
 #pragma clang fp contract(off)
 __device__ __noinline__ double hermite_dmin2(double r0x, double r0y, double r0z, double w0x,
                                              double w0y, double w0z, double r1x, double r1y,
@@ -249,18 +252,21 @@ __device__ __noinline__ double hermite_dmin2(double r0x, double r0y, double r0z,
     c[2][k] = 3.0 * (r1[k] - r0[k]) - h * (2.0 * w0[k] + w1[k]);
     c[3][k] = 2.0 * (r0[k] - r1[k]) + h * (w0[k] + w1[k]);
   }
+  auto dot3 = [&](int i, int j) {
+    return c[i][0] * c[j][0] + c[i][1] * c[j][1] + c[i][2] * c[j][2];
+  };
+  double a[6];
+  a[0] = dot3(0, 1);
+  a[1] = dot3(1, 1) + 2.0 * dot3(0, 2);
+  a[2] = 3.0 * dot3(0, 3) + 3.0 * dot3(1, 2);
+  a[3] = 4.0 * dot3(1, 3) + 2.0 * dot3(2, 2);
+  a[4] = 5.0 * dot3(2, 3);
+  a[5] = 3.0 * dot3(3, 3);
   double d0 = r0x * r0x + r0y * r0y + r0z * r0z;
   double d1 = r1x * r1x + r1y * r1y + r1z * r1z;
   double best = d0 < d1 ? d0 : d1;
   auto dd = [&](double t) {
-    double s = 0.0;
-    double acc[3], dr[3];
-    for (int k = 0; k < 3; ++k) {
-      acc[k] = c[0][k] + t * (c[1][k] + t * (c[2][k] + t * c[3][k]));
-      dr[k] = c[1][k] + t * (2.0 * c[2][k] + t * 3.0 * c[3][k]);
-    }
-    s = 2.0 * (acc[0] * dr[0] + acc[1] * dr[1] + acc[2] * dr[2]);
-    return s;
+    return a[0] + t * (a[1] + t * (a[2] + t * (a[3] + t * (a[4] + t * a[5]))));
   };
   // the 17 grid values are independent: evaluate them all first
   constexpr int NG = 16;
