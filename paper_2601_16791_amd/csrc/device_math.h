@@ -273,8 +273,15 @@ __device__ __noinline__ double hermite_dmin2(double r0x, double r0y, double r0z,
   double g[NG + 1];
 #pragma unroll
   for (int k = 0; k <= NG; ++k) g[k] = dd((double)k / NG);
-  for (int k = 0; k < NG; ++k) {
-    if (g[k] < 0.0 && g[k + 1] >= 0.0) {
+  // intervals holding a sign change, as a bit mask: the lanes of a wave then
+  // refine their first, second, ... roots together whatever their intervals
+  uint32_t roots = 0;
+#pragma unroll
+  for (int k = 0; k < NG; ++k) roots |= (g[k] < 0.0 && g[k + 1] >= 0.0) ? (1u << k) : 0u;
+  while (roots != 0) {
+    const int k = __builtin_ctz(roots);
+    roots &= roots - 1;
+    {
       double lo = (double)k / NG, hi = (double)(k + 1) / NG;
       // 40 bisection steps taken two at a time: the midpoint and both possible
       // next midpoints are evaluated together, then the two decisions are
@@ -305,6 +312,16 @@ __device__ __noinline__ double hermite_dmin2(double r0x, double r0y, double r0z,
 #pragma clang fp contract(on)
 
 // ---------------------------------------------------------- reductions
+// Sum over the 64 lanes of a wave by an xor butterfly.  Each step adds the same
+// two partial sums on both lanes of a pair (in either order, which IEEE
+// addition does not distinguish), so every lane ends with the same bits and
+// the result depends only on the lane values, not on the caller.
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
 // Fixed-order sum over a block of BS threads (power of two): each thread's value
 // lands in LDS, then a binary tree with a fixed pairing.  Every block that runs
 // the same reduction on the same data gets the same bits.

@@ -667,7 +667,9 @@ __device__ __forceinline__ void pair_consts(const double (&rc)[M], PairConst<M>&
   }
 }
 
-template <int M>
+// LM: the last member is massless, so it exerts no force (its reaction terms
+// are zero and are skipped: the other members' sums are unchanged bit for bit).
+template <int M, bool LM = false>
 __device__ __forceinline__ void force_reg(uint32_t pmask, const double (&mu)[M],
                                           const PairConst<M>& pc, double mu0,
                                           const double (&pos)[3 * M], double (&acc)[3 * M]) {
@@ -701,10 +703,13 @@ __device__ __forceinline__ void force_reg(uint32_t pmask, const double (&mu)[M],
       double wz = s2 <= 0.01 * rc2 ? y3 : y3 * (1.0 - K);
       const bool on = ((pmask >> bit) & 1u) && s2 < rc2 && s2 > 0.0;
       double w = on ? wz : 0.0;
-      double wa = mu[b] * w, wb = mu[a] * w;
-      acc[3 * a] = fma(wa, d0, acc[3 * a]);
-      acc[3 * a + 1] = fma(wa, d1, acc[3 * a + 1]);
-      acc[3 * a + 2] = fma(wa, d2, acc[3 * a + 2]);
+      const double wb = mu[a] * w;
+      if (!(LM && b == M - 1)) {
+        const double wa = mu[b] * w;
+        acc[3 * a] = fma(wa, d0, acc[3 * a]);
+        acc[3 * a + 1] = fma(wa, d1, acc[3 * a + 1]);
+        acc[3 * a + 2] = fma(wa, d2, acc[3 * a + 2]);
+      }
       acc[3 * b] = fma(-wb, d0, acc[3 * b]);
       acc[3 * b + 1] = fma(-wb, d1, acc[3 * b + 1]);
       acc[3 * b + 2] = fma(-wb, d2, acc[3 * b + 2]);
@@ -840,11 +845,11 @@ __device__ __forceinline__ int first_ok(const double (&lerr)[kC], double tol2) {
 // consecutive failures of the larger ones, from the same state with the same
 // scales, so the accepted steps, their columns and the results are those of
 // the sequential loop, bit for bit, while a run of failures costs one round.
-// The sequences stop after 8 substeps for a first look at columns 0..3: when
-// step size H is accepted there (the usual case) the longer sequences are not
-// finished.  Returns the number of accepted steps, or -1 when more than 30
-// consecutive failures occurred.
-template <int M>
+// The sequences stop after 8 and after 12 substeps for a look at columns 0..3
+// and 4..5: when step size H is accepted there (the usual case) the longer
+// sequences are not finished.  Returns the number of accepted steps, or -1
+// when more than 30 consecutive failures occurred.
+template <int M, bool LM>
 __device__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, int np,
                         const double* mum, const double* rcm, double mu0, double* xs,
                         double* vs, double* scal, double (*resS)[kC][6 * 4],
@@ -860,14 +865,15 @@ __device__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, 
   }
   PairConst<M> pc;
   pair_consts<M>(rc, pc);
-  // model count per sequential attempt: sequences of columns 0..3 (first look)
-  // or 0..7, 3 per extrapolation-table entry (FMA = 2)
-  unsigned long long f_half = 0, f_full = 0;
+  // model count per sequential attempt: sequences of columns 0..3, 0..5 (the
+  // two looks) or 0..7, 3 per extrapolation-table entry (FMA = 2)
+  unsigned long long f_look0 = 0, f_look1 = 0, f_look2 = 0;
   for (int c = 0; c < kC; ++c) {
     const unsigned long long fc = (unsigned long long)(2 * (c + 1) + 1) * (24 * M + 25 * np) +
                                   (unsigned long long)3 * c * 6 * M;
-    f_full += fc;
-    if (c < 4) f_half += fc;
+    f_look2 += fc;
+    if (c < 6) f_look1 += fc;
+    if (c < 4) f_look0 += fc;
   }
   double done = 0.0, H = h;
   int fails = 0, nsched = 0;
@@ -883,36 +889,40 @@ __device__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, 
     // H / 2^cand: repeated halving is exact, so is the scaling by 2^-cand
     const double Hc = H * __longlong_as_double((long long)(1023 - cand) << 52);
     // Stoermer sequence of n = 2 (j + 1) substeps (the same operations as
-    // stoermer_reg), split after substep 8
+    // stoermer_reg up to the velocity, formed with the reciprocal of the
+    // substep), split after substeps 8 and 12
     const int ns = 2 * (j + 1);
-    const double dt = Hc / ns, dt2 = dt * dt;
+    const double dt = Hc / ns, dt2 = dt * dt, idt = 1.0 / dt, hdt = 0.5 * dt;
     double pos[NN], d[NN], acc[NN];
 #pragma unroll
     for (int i = 0; i < NN; ++i) pos[i] = xs[i];
-    force_reg<M>(pmask, mu, pc, mu0, pos, acc);
+    force_reg<M, LM>(pmask, mu, pc, mu0, pos, acc);
 #pragma unroll
     for (int i = 0; i < NN; ++i) {
-      d[i] = dt * (vs[i] + 0.5 * dt * acc[i]);
+      d[i] = dt * (vs[i] + hdt * acc[i]);
       pos[i] += d[i];
     }
-    const int na = ns < 8 ? ns : 8;
-    for (int k = 1; k < na; ++k) {
-      force_reg<M>(pmask, mu, pc, mu0, pos, acc);
+    // substeps k0 .. min(ns, k1) - 1, then the column's entry when it ends by k1
+    auto advance = [&](int k0, int k1) {
+      const int ke = ns < k1 ? ns : k1;
+      for (int k = k0; k < ke; ++k) {
+        force_reg<M, LM>(pmask, mu, pc, mu0, pos, acc);
 #pragma unroll
-      for (int i = 0; i < NN; ++i) {
-        d[i] = fma(dt2, acc[i], d[i]);
-        pos[i] += d[i];
+        for (int i = 0; i < NN; ++i) {
+          d[i] = fma(dt2, acc[i], d[i]);
+          pos[i] += d[i];
+        }
       }
-    }
-    if (ns <= 8) {
-      double ac2[NN];
-      force_reg<M>(pmask, mu, pc, mu0, pos, ac2);
+      if (ns > k0 && ns <= k1) {
+        force_reg<M, LM>(pmask, mu, pc, mu0, pos, acc);
 #pragma unroll
-      for (int i = 0; i < NN; ++i) {
-        resS[cand][j][i] = pos[i];
-        resS[cand][j][NN + i] = d[i] / dt + 0.5 * dt * ac2[i];
+        for (int i = 0; i < NN; ++i) {
+          resS[cand][j][i] = pos[i];
+          resS[cand][j][NN + i] = fma(d[i], idt, hdt * acc[i]);
+        }
       }
-    }
+    };
+    advance(1, 8);
     __syncthreads();
     double lerr[kC], prev[EPL][kC], dg[EPL][kC];
 #pragma unroll
@@ -923,50 +933,49 @@ __device__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, 
       for (int k = 0; k < kC; ++k) prev[s][k] = dg[s][k] = 0.0;
     neville_rows<M, 0, 4>(cand, j, scal, resS, prev, dg, lerr);
     int okc = first_ok<0, 4>(lerr, tol2);
-    const bool early = (__builtin_amdgcn_ballot_w64(lane == 0 && okc >= 0) & 1ull) != 0;
+    int look = 0;  // 0, 1: accepted by candidate 0 at the first or second look
     int chosen = -1, accepted = -1;
     bool failed = false;
-    if (early) {
+    if ((__builtin_amdgcn_ballot_w64(lane == 0 && okc >= 0) & 1ull) != 0) {
       chosen = 0;
       accepted = __shfl(okc, 0);
     } else {
-      for (int k = 8; k < ns; ++k) {
-        force_reg<M>(pmask, mu, pc, mu0, pos, acc);
-#pragma unroll
-        for (int i = 0; i < NN; ++i) {
-          d[i] = fma(dt2, acc[i], d[i]);
-          pos[i] += d[i];
-        }
-      }
-      if (ns > 8) {
-        force_reg<M>(pmask, mu, pc, mu0, pos, acc);
-#pragma unroll
-        for (int i = 0; i < NN; ++i) {
-          resS[cand][j][i] = pos[i];
-          resS[cand][j][NN + i] = d[i] / dt + 0.5 * dt * acc[i];
-        }
-      }
+      advance(8, 12);
       __syncthreads();
-      neville_rows<M, 4, kC>(cand, j, scal, resS, prev, dg, lerr);
-      const int ok2 = first_ok<4, kC>(lerr, tol2);  // all lanes: the reduction crosses lanes
+      neville_rows<M, 4, 6>(cand, j, scal, resS, prev, dg, lerr);
+      const int ok2 = first_ok<4, 6>(lerr, tol2);  // all lanes: the reduction crosses lanes
       if (okc < 0) okc = ok2;
-      // the sequential control: candidates in order, failures counted
-      const uint64_t okm = __builtin_amdgcn_ballot_w64(j == 0 && okc >= 0);
-      for (int c = 0; c < 8; ++c) {
-        if ((okm >> (8 * c)) & 1ull) {
-          chosen = c;
-          break;
+      look = 1;
+      if ((__builtin_amdgcn_ballot_w64(lane == 0 && okc >= 0) & 1ull) != 0) {
+        chosen = 0;
+        accepted = __shfl(okc, 0);
+      } else {
+        advance(12, 16);
+        __syncthreads();
+        neville_rows<M, 6, kC>(cand, j, scal, resS, prev, dg, lerr);
+        const int ok3 = first_ok<6, kC>(lerr, tol2);
+        if (okc < 0) okc = ok3;
+        look = 2;
+        // the sequential control: candidates in order, failures counted
+        const uint64_t okm = __builtin_amdgcn_ballot_w64(j == 0 && okc >= 0);
+        for (int c = 0; c < 8; ++c) {
+          if ((okm >> (8 * c)) & 1ull) {
+            chosen = c;
+            break;
+          }
+          if (++fails > 30) {
+            failed = true;
+            break;
+          }
         }
-        if (++fails > 30) {
-          failed = true;
-          break;
-        }
+        if (chosen >= 0) accepted = __shfl(okc, 8 * chosen);
       }
-      if (chosen >= 0) accepted = __shfl(okc, 8 * chosen);
     }
     if (lane == 0) {
       const unsigned long long f =
-          early ? f_half : f_full * (unsigned long long)(chosen >= 0 ? chosen + 1 : 8);
+          look == 0 ? f_look0
+          : look == 1 ? f_look1
+                      : f_look2 * (unsigned long long)(chosen >= 0 ? chosen + 1 : 8);
       atomicAdd(&dsc->bs_flop, f);
     }
     __syncthreads();
@@ -1062,9 +1071,14 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc) {
     int fails = 0, nsched = 0;
     bool failed = false;
     if (m <= 4) {
-      if (m == 2) nsched = bs_small<2>(lane, b, h, tol2, pmask, np, mum, rcm, mu0, xs, vs, scal, resS, D, dsc);
-      else if (m == 3) nsched = bs_small<3>(lane, b, h, tol2, pmask, np, mum, rcm, mu0, xs, vs, scal, resS, D, dsc);
-      else nsched = bs_small<4>(lane, b, h, tol2, pmask, np, mum, rcm, mu0, xs, vs, scal, resS, D, dsc);
+      // a massless last member (the usual subsystem: massive bodies and the
+      // planetesimal they met) takes the variant without its reaction terms
+      const bool lm = mum[m - 1] == 0.0;
+#define MX_BS_SMALL(MM, LMV) bs_small<MM, LMV>(lane, b, h, tol2, pmask, np, mum, rcm, mu0, xs, vs, scal, resS, D, dsc)
+      if (m == 2) nsched = lm ? MX_BS_SMALL(2, true) : MX_BS_SMALL(2, false);
+      else if (m == 3) nsched = lm ? MX_BS_SMALL(3, true) : MX_BS_SMALL(3, false);
+      else nsched = lm ? MX_BS_SMALL(4, true) : MX_BS_SMALL(4, false);
+#undef MX_BS_SMALL
       failed = nsched < 0;
       done = h;  // the loop below is for larger subsystems
     }

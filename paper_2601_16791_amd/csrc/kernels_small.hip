@@ -68,29 +68,26 @@ __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double
   const auto bigsnap = gbl(D.bigsnap);
   // massive bodies from the step-start snapshot (the owner tile overwrites x, u
   // of the massive bodies while other blocks may still be reading)
-  double p[3], v[3], a[3];
+  double p[3], v[3], a[3], m = 0.0;
   if (tid < nb) {
+    m = gbl(D.mu)[tid];
     for (int c = 0; c < 3; ++c) {
       p[c] = bigsnap[c * nb + tid];
       v[c] = bigsnap[(3 + c) * nb + tid];
       a[c] = bigsnap[(6 + c) * nb + tid];
     }
   }
-  // momentum sums: thread 0 adds the massive bodies in index order (the same
-  // order in every block)
-  if (tid == 0) {
-    double vsum[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < nb; ++k) {
-      double m = gbl(D.mu)[k];
-      double ux = bigsnap[3 * nb + k], uy = bigsnap[4 * nb + k], uz = bigsnap[5 * nb + k];
-      vsum[0] += m * ux;
-      vsum[1] += m * uy;
-      vsum[2] += m * uz;
-      vsum[3] += m * (ux + hh * bigsnap[6 * nb + k]);
-      vsum[4] += m * (uy + hh * bigsnap[7 * nb + k]);
-      vsum[5] += m * (uz + hh * bigsnap[8 * nb + k]);
+  // momentum sums over the massive bodies, one per lane of the first wave, by
+  // the fixed butterfly (the same bits in every block)
+  if (tid < 64) {
+    double t[6];
+    for (int c = 0; c < 3; ++c) {
+      t[c] = tid < nb ? m * v[c] : 0.0;
+      t[3 + c] = tid < nb ? m * (v[c] + hh * a[c]) : 0.0;
     }
-    for (int c = 0; c < 6; ++c) sh[c] = vsum[c];
+    for (int c = 0; c < 6; ++c) t[c] = mxd::wave_sum_fixed(t[c]);
+    if (tid == 0)
+      for (int c = 0; c < 6; ++c) sh[c] = t[c];
   }
   __syncthreads();
   for (int c = 0; c < 3; ++c) {
@@ -175,11 +172,14 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
       gbl(D.u)[c * n + t] = w[c];
     }
     // encounter test against every massive body i < t (same bound and exact
-    // Hermite test as the general flag kernel)
+    // Hermite test as the general flag kernel): the bound marks candidates in a
+    // bit mask (nb <= 64), then the lanes of the wave take their candidates one
+    // at a time together, so a wave with candidates against different massive
+    // bodies runs the Hermite test once per round rather than once per body
     const double rct = t < nb ? brc[t] : 0.0;
     const int imax = t < nb ? t : nb;
     const double k427 = (4.0 / 27.0) * fabs(h);
-    bool hit = false;
+    uint64_t cmask = 0;
 #pragma unroll 4
     for (int i = 0; i < imax; ++i) {
       double r0[3], w0[3], w1[3], dd[3];
@@ -195,20 +195,30 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
                   fmax(fmax(fabs(w1[0]), fabs(w1[1])), fabs(w1[2]));
       double rc = fmax(brc[i], rct);
       double bound = rc + 1.7320508075688773 * fma(k427, nw, nd) * (1.0 + 1e-12);
-      if (__builtin_expect(m0 <= bound * bound * (1.0 + 1e-12), 0)) {
-        double r1[3];
-        for (int c = 0; c < 3; ++c) r1[c] = q[c] - bst[6 + c][i];
-        double dmin = mxd::hermite_dmin2(r0[0], r0[1], r0[2], w0[0], w0[1], w0[2], r1[0], r1[1],
-                                         r1[2], w1[0], w1[1], w1[2], h);
-        if (dmin <= rc * rc) {
-          hit = true;
-          int idx = atomicAdd(&D.dsc->n_pairs, 1);
-          if (idx < D.cap_pairs) {
-            gbl(D.pairs)[2 * idx] = i;
-            gbl(D.pairs)[2 * idx + 1] = t;
-          } else {
-            atomicOr(&D.dsc->err, MXE_PAIRS);
-          }
+      if (__builtin_expect(m0 <= bound * bound * (1.0 + 1e-12), 0)) cmask |= 1ull << i;
+    }
+    bool hit = false;
+    while (cmask != 0) {
+      const int i = __builtin_ctzll(cmask);
+      cmask &= cmask - 1;
+      double r0[3], w0[3], w1[3], r1[3];
+      for (int c = 0; c < 3; ++c) {
+        r0[c] = p[c] - bst[c][i];
+        w0[c] = v[c] - bst[3 + c][i];
+        w1[c] = w[c] - bst[9 + c][i];
+        r1[c] = q[c] - bst[6 + c][i];
+      }
+      const double rc = fmax(brc[i], rct);
+      double dmin = mxd::hermite_dmin2(r0[0], r0[1], r0[2], w0[0], w0[1], w0[2], r1[0], r1[1],
+                                       r1[2], w1[0], w1[1], w1[2], h);
+      if (dmin <= rc * rc) {
+        hit = true;
+        int idx = atomicAdd(&D.dsc->n_pairs, 1);
+        if (idx < D.cap_pairs) {
+          gbl(D.pairs)[2 * idx] = i;
+          gbl(D.pairs)[2 * idx + 1] = t;
+        } else {
+          atomicOr(&D.dsc->err, MXE_PAIRS);
         }
       }
     }
@@ -265,24 +275,22 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
       __syncthreads();  // the previous tile is done with the LDS sources
       // massive bodies after drift and encounters from their snapshot (the owner
       // tile overwrites x, u of the massive bodies while other blocks may read);
-      // thread 0 adds the momentum in index order (the same in every block)
-      if (tid == 0) {
-        double Q[3] = {0.0, 0.0, 0.0};
-        for (int k = 0; k < nb; ++k) {
-          double m = gbl(D.mu)[k];
-          Q[0] += m * gbl(D.bigmid)[3 * nb + k];
-          Q[1] += m * gbl(D.bigmid)[4 * nb + k];
-          Q[2] += m * gbl(D.bigmid)[5 * nb + k];
-        }
-        for (int c = 0; c < 3; ++c) sh[c] = Q[c];
-      }
+      // the first wave sums the momentum by the fixed butterfly (the same bits
+      // in every block)
       double bx = 0.0, by = 0.0, bz = 0.0, bm = 0.0, brc = 0.0;
+      double Q[3] = {0.0, 0.0, 0.0};
       if (tid < nb) {
         bx = gbl(D.bigmid)[tid];
         by = gbl(D.bigmid)[nb + tid];
         bz = gbl(D.bigmid)[2 * nb + tid];
         bm = gbl(D.mu)[tid];
         brc = gbl(D.rcrit)[tid];
+        for (int c = 0; c < 3; ++c) Q[c] = bm * gbl(D.bigmid)[(3 + c) * nb + tid];
+      }
+      if (tid < 64) {
+        for (int c = 0; c < 3; ++c) Q[c] = mxd::wave_sum_fixed(Q[c]);
+        if (tid == 0)
+          for (int c = 0; c < 3; ++c) sh[c] = Q[c];
       }
       __syncthreads();
       for (int c = 0; c < 3; ++c) {
