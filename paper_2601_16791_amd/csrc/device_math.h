@@ -312,14 +312,30 @@ __device__ __noinline__ double hermite_dmin2(double r0x, double r0y, double r0z,
 #pragma clang fp contract(on)
 
 // ---------------------------------------------------------- reductions
-// Sum over the 64 lanes of a wave by an xor butterfly.  Each step adds the same
-// two partial sums on both lanes of a pair (in either order, which IEEE
-// addition does not distinguish), so every lane ends with the same bits and
-// the result depends only on the lane values, not on the caller.
+// Sum over the 64 lanes of a wave (all lanes active), the same bits on every
+// lane and for every caller.  Within each row of 16 lanes, DPP moves pair lane i
+// with i ^ 1, i ^ 2, then 7 - i within eight and 15 - i within sixteen: each
+// step adds the same two partial sums on both lanes of a pair (in either
+// order, which IEEE addition does not distinguish), so every lane of a row ends
+// with the row's sum; the four row sums are then added as (r0 + r1) + (r2 + r3).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
 __device__ __forceinline__ double wave_sum_fixed(double v) {
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
-  return v;
+  v += dpp_move_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move_f64<0x141>(v);  // row_half_mirror
+  v += dpp_move_f64<0x140>(v);  // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 // Fixed-order sum over a block of BS threads (power of two): each thread's value

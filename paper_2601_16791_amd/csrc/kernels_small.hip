@@ -55,36 +55,28 @@ __device__ __forceinline__ bool advance_body(int t, int nb, double mu0, double h
 }
 
 // Massive bodies of system D for a block: half kick, jump and drift of every
-// massive body (identical arithmetic in every block), kept in LDS.  Returns the
-// momentum terms through Ppre = P_pre / mu0 and Ppost = (h/2) P_post / mu0.
-// `first` latches a failure once per system.
+// massive body (identical arithmetic in every block), kept in LDS.  Thread
+// tid < nb enters with massive body tid (p, v, a, mass m) already loaded from the
+// step-start snapshot.  Returns the momentum terms through Ppre = P_pre / mu0 and
+// Ppost = (h/2) P_post / mu0.  `first` latches a failure once per system.
 template <int BLK>
 __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double* sh,
                                             double (*bst)[kSmallBig], double* brc,
-                                            double (&Ppre)[3], double (&Ppost)[3]) {
+                                            double (&p)[3], double (&v)[3], const double (&a)[3],
+                                            double m, double rc, double (&Ppre)[3],
+                                            double (&Ppost)[3]) {
   const int tid = threadIdx.x;
   const int nb = D.nb;
   const double hh = 0.5 * D.h;
-  const auto bigsnap = gbl(D.bigsnap);
-  // massive bodies from the step-start snapshot (the owner tile overwrites x, u
-  // of the massive bodies while other blocks may still be reading)
-  double p[3], v[3], a[3], m = 0.0;
-  if (tid < nb) {
-    m = gbl(D.mu)[tid];
-    for (int c = 0; c < 3; ++c) {
-      p[c] = bigsnap[c * nb + tid];
-      v[c] = bigsnap[(3 + c) * nb + tid];
-      a[c] = bigsnap[(6 + c) * nb + tid];
-    }
-  }
   // momentum sums over the massive bodies, one per lane of the first wave, by
-  // the fixed butterfly (the same bits in every block)
+  // the fixed lane reduction (the same bits in every block)
   if (tid < 64) {
     double t[6];
     for (int c = 0; c < 3; ++c) {
       t[c] = tid < nb ? m * v[c] : 0.0;
       t[3 + c] = tid < nb ? m * (v[c] + hh * a[c]) : 0.0;
     }
+#pragma unroll
     for (int c = 0; c < 6; ++c) t[c] = mxd::wave_sum_fixed(t[c]);
     if (tid == 0)
       for (int c = 0; c < 6; ++c) sh[c] = t[c];
@@ -105,7 +97,7 @@ __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double
       bst[6 + c][tid] = q[c];
       bst[9 + c][tid] = w[c];
     }
-    brc[tid] = gbl(D.rcrit)[tid];
+    brc[tid] = rc;
   }
 }
 
@@ -131,8 +123,22 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
     const int n = D.n, nb = D.nb;
     const double h = D.h;
     const int t = tl.first + tid;
-    // the body's state is requested before the massive-body phase, whose loads
-    // and arithmetic then overlap its latency
+    const bool fresh = tl.sys != cur;  // block-uniform
+    // the massive bodies (step-start snapshot: the owner tile overwrites x, u of
+    // the massive bodies while other blocks may still be reading) are requested
+    // first, then the body's own state: the massive-body phase waits only for the
+    // former, and the latter arrives while it runs
+    double bp[3], bv[3], ba[3], bm = 0.0, brc_t = 0.0;
+    if (fresh && tid < nb) {
+      const auto bigsnap = gbl(D.bigsnap);
+      bm = gbl(D.mu)[tid];
+      brc_t = gbl(D.rcrit)[tid];
+      for (int c = 0; c < 3; ++c) {
+        bp[c] = bigsnap[c * nb + tid];
+        bv[c] = bigsnap[(3 + c) * nb + tid];
+        ba[c] = bigsnap[(6 + c) * nb + tid];
+      }
+    }
     double p[3], v[3], q[3], w[3], a[3], rp = 0.0, rhop = 0.0;
     if (t < n && t >= nb) {
       for (int c = 0; c < 3; ++c) {
@@ -145,9 +151,9 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
         rhop = gbl(D.rho_p)[t - nb];
       }
     }
-    if (tl.sys != cur) {
+    if (fresh) {
       __syncthreads();  // the previous tile is done with the LDS copies
-      big_phase_a<BLK>(D, tl.first == 0, sh, bst, brc, Ppre, Ppost);
+      big_phase_a<BLK>(D, tl.first == 0, sh, bst, brc, bp, bv, ba, bm, brc_t, Ppre, Ppost);
       __syncthreads();
       cur = tl.sys;
     }
@@ -255,7 +261,21 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
     const auto x = gbl(D.x);
     const auto u = gbl(D.u);
     const auto ag = gbl(D.ag);
-    // the body's state is requested before the massive-body phase
+    const bool fresh = tl.sys != cur;  // block-uniform
+    // massive bodies after drift and encounters from their snapshot (the owner
+    // tile overwrites x, u of the massive bodies while other blocks may read),
+    // requested before the body's own state
+    double bx = 0.0, by = 0.0, bz = 0.0, bm = 0.0, brc = 0.0;
+    double Q[3] = {0.0, 0.0, 0.0};
+    if (fresh && tid < nb) {
+      const auto bigmid = gbl(D.bigmid);
+      bx = bigmid[tid];
+      by = bigmid[nb + tid];
+      bz = bigmid[2 * nb + tid];
+      bm = gbl(D.mu)[tid];
+      brc = gbl(D.rcrit)[tid];
+      for (int c = 0; c < 3; ++c) Q[c] = bigmid[(3 + c) * nb + tid];
+    }
     double x0 = 0.0, x1 = 0.0, x2 = 0.0, vx = 0.0, vy = 0.0, vz = 0.0, rp = 0.0, rhop = 0.0;
     if (t < n) {
       x0 = x[t];
@@ -271,24 +291,13 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
         }
       }
     }
-    if (tl.sys != cur) {
+    if (fresh) {
       __syncthreads();  // the previous tile is done with the LDS sources
-      // massive bodies after drift and encounters from their snapshot (the owner
-      // tile overwrites x, u of the massive bodies while other blocks may read);
-      // the first wave sums the momentum by the fixed butterfly (the same bits
-      // in every block)
-      double bx = 0.0, by = 0.0, bz = 0.0, bm = 0.0, brc = 0.0;
-      double Q[3] = {0.0, 0.0, 0.0};
-      if (tid < nb) {
-        bx = gbl(D.bigmid)[tid];
-        by = gbl(D.bigmid)[nb + tid];
-        bz = gbl(D.bigmid)[2 * nb + tid];
-        bm = gbl(D.mu)[tid];
-        brc = gbl(D.rcrit)[tid];
-        for (int c = 0; c < 3; ++c) Q[c] = bm * gbl(D.bigmid)[(3 + c) * nb + tid];
-      }
+      // the first wave sums the momentum by the fixed lane reduction (the same
+      // bits in every block)
       if (tid < 64) {
-        for (int c = 0; c < 3; ++c) Q[c] = mxd::wave_sum_fixed(Q[c]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Q[c] = mxd::wave_sum_fixed(bm * Q[c]);
         if (tid == 0)
           for (int c = 0; c < 3; ++c) sh[c] = Q[c];
       }
