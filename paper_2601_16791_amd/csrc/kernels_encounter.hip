@@ -218,6 +218,167 @@ __device__ __forceinline__ void wave_rank_sort(const K* in, K* out, int np) {
 constexpr int kPlanThreads = 256;
 constexpr int kPlanLds = 2048;   // pairs handled in LDS; larger lists use global scratch
 
+// General plan (any list): sort by (i, j), big-big components by union-find,
+// one subsystem per flagged massless body.  K, S: 64-bit key arrays of at least
+// next_pow2(np) entries; BB, GS: index arrays of np entries (LDS or global
+// scratch); scan: blockDim.x ints of LDS.
+__device__ void plan_general(int nb, gmem<int32_t> gpairs, int np, int64_t* K, int64_t* S,
+                             int32_t* BB, int32_t* GS, int32_t* __restrict__ uf,
+                             Subsystem* __restrict__ subs, int32_t cap_subs,
+                             DevScalars* __restrict__ dsc, int sort_only, int* scan,
+                             int* s_nbig_sub) {
+  const int tid = threadIdx.x, T = blockDim.x;
+  // 1. sort by (i, j)
+  int p2 = next_pow2(np);
+  for (int q = tid; q < p2; q += T)
+    K[q] = q < np ? make_key(gpairs[2 * q], gpairs[2 * q + 1]) : INT64_MAX;
+  __syncthreads();
+  if (np > 1) block_bitonic(K, p2);
+  for (int q = tid; q < np; q += T) {
+    gpairs[2 * q] = key_hi(K[q]);
+    gpairs[2 * q + 1] = key_lo(K[q]);
+  }
+  if (sort_only) return;
+  // 2. big-big pairs (in (i, j) order) and massless pairs keyed (j, i)
+  const int nbb = block_compact(
+      np, [&](int q) { return key_lo(K[q]) < nb; }, [&](int pos, int q) { BB[pos] = q; }, scan);
+  const int ns = block_compact(
+      np, [&](int q) { return key_lo(K[q]) >= nb; },
+      [&](int pos, int q) { S[pos] = make_key(key_lo(K[q]), key_hi(K[q])); }, scan);
+  int p2s = next_pow2(ns > 0 ? ns : 1);
+  for (int q = ns + tid; q < p2s; q += T) S[q] = INT64_MAX;
+  __syncthreads();
+  if (ns > 1) block_bitonic(S, p2s);
+  // 3. one group per flagged massless body
+  const int ng = block_compact(
+      ns, [&](int q) { return q == 0 || key_hi(S[q]) != key_hi(S[q - 1]); },
+      [&](int pos, int q) { GS[pos] = q; }, scan);
+  int32_t* par = uf;
+  int32_t* inbig = uf + nb;
+  // 4. components of the big-big graph and their subsystems (one thread; the
+  //    big-big list is short)
+  if (tid == 0) {
+    for (int b = 0; b < nbb; ++b) {
+      int64_t k = K[BB[b]];
+      int i = key_hi(k), j = key_lo(k);
+      int ri = uf_find(par, i), rj = uf_find(par, j);
+      if (ri != rj) {
+        if (ri < rj) par[rj] = ri;
+        else par[ri] = rj;
+      }
+      inbig[i] = 1;
+      inbig[j] = 1;
+    }
+    int nsub = 0;
+    for (int b = 0; b < nbb; ++b) {
+      int i = key_hi(K[BB[b]]);
+      int r = uf_find(par, i);
+      if (inbig[r] != 1) continue;  // component already emitted (root marked 2)
+      if (nsub >= cap_subs) {
+        inbig[r] = 2;
+        atomicOr(&dsc->err, MXE_SUBSYS);
+        continue;
+      }
+      Subsystem& sub = subs[nsub];  // built in place (no private copy)
+      sub.m = 0;
+      sub.keep_from = 0;
+      sub.np = 0;
+      sub.pad = 0;
+      bool ok = true;
+      for (int c = 0; c < nbb && ok; ++c) {
+        int64_t k = K[BB[c]];
+        if (uf_find(par, key_hi(k)) != r) continue;
+        ok = insert_sorted(sub.mem, sub.m, kBsMaxMembers, key_hi(k)) &&
+             insert_sorted(sub.mem, sub.m, kBsMaxMembers, key_lo(k));
+      }
+      for (int c = 0; c < nbb && ok; ++c) {
+        int64_t k = K[BB[c]];
+        if (uf_find(par, key_hi(k)) != r) continue;
+        if (sub.np >= kBsMaxPairs) { ok = false; break; }
+        sub.pl[sub.np][0] = index_in(sub.mem, sub.m, key_hi(k));
+        sub.pl[sub.np][1] = index_in(sub.mem, sub.m, key_lo(k));
+        ++sub.np;
+      }
+      inbig[r] = 2;
+      if (!ok) {
+        atomicOr(&dsc->err, MXE_SUBSYS);
+        continue;
+      }
+      ++nsub;
+    }
+    *s_nbig_sub = nsub;
+  }
+  __syncthreads();
+  const int nbig_sub = *s_nbig_sub;
+  // 5. massless subsystems, one group per thread
+  for (int g = tid; g < ng; g += T) {
+    const int q0 = GS[g];
+    const int q1 = g + 1 < ng ? GS[g + 1] : ns;
+    const int j = key_hi(S[q0]);
+    const int slot = nbig_sub + g;
+    if (slot >= cap_subs) {
+      atomicOr(&dsc->err, MXE_SUBSYS);
+      continue;
+    }
+    Subsystem& sub = subs[slot];  // built in place (no private copy)
+    sub.m = 0;
+    sub.np = 0;
+    sub.pad = 0;
+    bool ok = true;
+    for (int q = q0; q < q1 && ok; ++q) {
+      int i = key_lo(S[q]);
+      if (inbig[i]) {
+        int r = uf_find(par, i);
+        for (int c = 0; c < nbb && ok; ++c) {
+          int64_t k = K[BB[c]];
+          if (uf_find(par, key_hi(k)) != r) continue;
+          ok = insert_sorted(sub.mem, sub.m, kBsMaxMembers - 1, key_hi(k)) &&
+               insert_sorted(sub.mem, sub.m, kBsMaxMembers - 1, key_lo(k));
+        }
+      } else {
+        ok = insert_sorted(sub.mem, sub.m, kBsMaxMembers - 1, i);
+      }
+    }
+    const int nbm = sub.m;
+    if (ok) {
+      sub.mem[sub.m++] = j;
+      sub.keep_from = nbm;
+      // big-big pairs among the members, then the pairs naming j, both in (i, j) order
+      for (int c = 0; c < nbb && ok; ++c) {
+        int64_t k = K[BB[c]];
+        int la = index_in(sub.mem, nbm, key_hi(k)), lb = index_in(sub.mem, nbm, key_lo(k));
+        if (la < 0 || lb < 0) continue;
+        if (sub.np >= kBsMaxPairs) { ok = false; break; }
+        sub.pl[sub.np][0] = la;
+        sub.pl[sub.np][1] = lb;
+        ++sub.np;
+      }
+      for (int q = q0; q < q1 && ok; ++q) {
+        if (sub.np >= kBsMaxPairs) { ok = false; break; }
+        sub.pl[sub.np][0] = index_in(sub.mem, nbm, key_lo(S[q]));
+        sub.pl[sub.np][1] = nbm;
+        ++sub.np;
+      }
+    }
+    if (!ok) {
+      atomicOr(&dsc->err, MXE_SUBSYS);
+      sub.m = 0;  // an empty subsystem keeps the table dense; the integrator skips it
+      sub.np = 0;
+      sub.keep_from = 0;
+    }
+  }
+  __syncthreads();
+  // 6. restore the union-find scratch
+  for (int b = tid; b < nbb; b += T) {
+    int64_t k = K[BB[b]];
+    par[key_hi(k)] = key_hi(k);
+    par[key_lo(k)] = key_lo(k);
+    inbig[key_hi(k)] = 0;
+    inbig[key_lo(k)] = 0;
+  }
+  if (tid == 0) dsc->n_sub = min(nbig_sub + ng, cap_subs);
+}
+
 // Sort of the flagged list by (i, j) and the subsystem plan, in one block.
 //   - big-big pairs join big bodies (union-find, root = smallest index); every
 //     component of two or more bodies is one subsystem (all members kept);
@@ -342,156 +503,7 @@ __device__ __forceinline__ void plan_block(int n, int nb, int32_t* __restrict__ 
   int64_t* S = small_list ? ls : gkeys + cap;
   int32_t* BB = small_list ? lbb : gidx;
   int32_t* GS = small_list ? lgs : gidx + cap;
-  const int tid = threadIdx.x, T = blockDim.x;
-  // 1. sort by (i, j)
-  int p2 = next_pow2(np);
-  for (int q = tid; q < p2; q += T)
-    K[q] = q < np ? make_key(gpairs[2 * q], gpairs[2 * q + 1]) : INT64_MAX;
-  __syncthreads();
-  if (np > 1) block_bitonic(K, p2);
-  for (int q = tid; q < np; q += T) {
-    gpairs[2 * q] = key_hi(K[q]);
-    gpairs[2 * q + 1] = key_lo(K[q]);
-  }
-  if (sort_only) return;
-  // 2. big-big pairs (in (i, j) order) and massless pairs keyed (j, i)
-  const int nbb = block_compact(
-      np, [&](int q) { return key_lo(K[q]) < nb; }, [&](int pos, int q) { BB[pos] = q; }, scan);
-  const int ns = block_compact(
-      np, [&](int q) { return key_lo(K[q]) >= nb; },
-      [&](int pos, int q) { S[pos] = make_key(key_lo(K[q]), key_hi(K[q])); }, scan);
-  int p2s = next_pow2(ns > 0 ? ns : 1);
-  for (int q = ns + tid; q < p2s; q += T) S[q] = INT64_MAX;
-  __syncthreads();
-  if (ns > 1) block_bitonic(S, p2s);
-  // 3. one group per flagged massless body
-  const int ng = block_compact(
-      ns, [&](int q) { return q == 0 || key_hi(S[q]) != key_hi(S[q - 1]); },
-      [&](int pos, int q) { GS[pos] = q; }, scan);
-  int32_t* par = uf;
-  int32_t* inbig = uf + nb;
-  // 4. components of the big-big graph and their subsystems (one thread; the
-  //    big-big list is short)
-  if (tid == 0) {
-    for (int b = 0; b < nbb; ++b) {
-      int64_t k = K[BB[b]];
-      int i = key_hi(k), j = key_lo(k);
-      int ri = uf_find(par, i), rj = uf_find(par, j);
-      if (ri != rj) {
-        if (ri < rj) par[rj] = ri;
-        else par[ri] = rj;
-      }
-      inbig[i] = 1;
-      inbig[j] = 1;
-    }
-    int nsub = 0;
-    for (int b = 0; b < nbb; ++b) {
-      int i = key_hi(K[BB[b]]);
-      int r = uf_find(par, i);
-      if (inbig[r] != 1) continue;  // component already emitted (root marked 2)
-      if (nsub >= cap_subs) {
-        inbig[r] = 2;
-        atomicOr(&dsc->err, MXE_SUBSYS);
-        continue;
-      }
-      Subsystem& sub = subs[nsub];  // built in place (no private copy)
-      sub.m = 0;
-      sub.keep_from = 0;
-      sub.np = 0;
-      sub.pad = 0;
-      bool ok = true;
-      for (int c = 0; c < nbb && ok; ++c) {
-        int64_t k = K[BB[c]];
-        if (uf_find(par, key_hi(k)) != r) continue;
-        ok = insert_sorted(sub.mem, sub.m, kBsMaxMembers, key_hi(k)) &&
-             insert_sorted(sub.mem, sub.m, kBsMaxMembers, key_lo(k));
-      }
-      for (int c = 0; c < nbb && ok; ++c) {
-        int64_t k = K[BB[c]];
-        if (uf_find(par, key_hi(k)) != r) continue;
-        if (sub.np >= kBsMaxPairs) { ok = false; break; }
-        sub.pl[sub.np][0] = index_in(sub.mem, sub.m, key_hi(k));
-        sub.pl[sub.np][1] = index_in(sub.mem, sub.m, key_lo(k));
-        ++sub.np;
-      }
-      inbig[r] = 2;
-      if (!ok) {
-        atomicOr(&dsc->err, MXE_SUBSYS);
-        continue;
-      }
-      ++nsub;
-    }
-    s_nbig_sub = nsub;
-  }
-  __syncthreads();
-  const int nbig_sub = s_nbig_sub;
-  // 5. massless subsystems, one group per thread
-  for (int g = tid; g < ng; g += T) {
-    const int q0 = GS[g];
-    const int q1 = g + 1 < ng ? GS[g + 1] : ns;
-    const int j = key_hi(S[q0]);
-    const int slot = nbig_sub + g;
-    if (slot >= cap_subs) {
-      atomicOr(&dsc->err, MXE_SUBSYS);
-      continue;
-    }
-    Subsystem& sub = subs[slot];  // built in place (no private copy)
-    sub.m = 0;
-    sub.np = 0;
-    sub.pad = 0;
-    bool ok = true;
-    for (int q = q0; q < q1 && ok; ++q) {
-      int i = key_lo(S[q]);
-      if (inbig[i]) {
-        int r = uf_find(par, i);
-        for (int c = 0; c < nbb && ok; ++c) {
-          int64_t k = K[BB[c]];
-          if (uf_find(par, key_hi(k)) != r) continue;
-          ok = insert_sorted(sub.mem, sub.m, kBsMaxMembers - 1, key_hi(k)) &&
-               insert_sorted(sub.mem, sub.m, kBsMaxMembers - 1, key_lo(k));
-        }
-      } else {
-        ok = insert_sorted(sub.mem, sub.m, kBsMaxMembers - 1, i);
-      }
-    }
-    const int nbm = sub.m;
-    if (ok) {
-      sub.mem[sub.m++] = j;
-      sub.keep_from = nbm;
-      // big-big pairs among the members, then the pairs naming j, both in (i, j) order
-      for (int c = 0; c < nbb && ok; ++c) {
-        int64_t k = K[BB[c]];
-        int la = index_in(sub.mem, nbm, key_hi(k)), lb = index_in(sub.mem, nbm, key_lo(k));
-        if (la < 0 || lb < 0) continue;
-        if (sub.np >= kBsMaxPairs) { ok = false; break; }
-        sub.pl[sub.np][0] = la;
-        sub.pl[sub.np][1] = lb;
-        ++sub.np;
-      }
-      for (int q = q0; q < q1 && ok; ++q) {
-        if (sub.np >= kBsMaxPairs) { ok = false; break; }
-        sub.pl[sub.np][0] = index_in(sub.mem, nbm, key_lo(S[q]));
-        sub.pl[sub.np][1] = nbm;
-        ++sub.np;
-      }
-    }
-    if (!ok) {
-      atomicOr(&dsc->err, MXE_SUBSYS);
-      sub.m = 0;  // an empty subsystem keeps the table dense; the integrator skips it
-      sub.np = 0;
-      sub.keep_from = 0;
-    }
-  }
-  __syncthreads();
-  // 6. restore the union-find scratch
-  for (int b = tid; b < nbb; b += T) {
-    int64_t k = K[BB[b]];
-    par[key_hi(k)] = key_hi(k);
-    par[key_lo(k)] = key_lo(k);
-    inbig[key_hi(k)] = 0;
-    inbig[key_lo(k)] = 0;
-  }
-  if (tid == 0) dsc->n_sub = min(nbig_sub + ng, cap_subs);
+  plan_general(nb, gpairs, np, K, S, BB, GS, uf, subs, cap_subs, dsc, sort_only, scan, &s_nbig_sub);
 }
 
 __global__ __launch_bounds__(kPlanThreads) void k_plan(
@@ -1019,7 +1031,23 @@ __device__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, 
 // each): most steps are accepted in the first round, and the table rows do not
 // depend on later rows, so the accepted column is the one a sequential
 // integrator would stop at.
-__global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc) {
+// In-kernel plan (plan != 0, systems of at most 64 massive bodies): the blocks
+// of a system plan their subsystems themselves, so the step needs no planning
+// launch.  A list of at most 256 pairs none of which joins two massive bodies
+// (the common case) is planned by every block at once: one wave rank-sorts the
+// 32-bit keys (j, i) in LDS and numbers the groups of equal j, which is the
+// table the planning kernel builds (one subsystem per flagged massless body in
+// order of j, its partners in order of i).  Block 0 also writes that table and
+// the list counters for the readers after the step.  Any other list takes the
+// general plan in block 0 while the other blocks of the system wait for its
+// flag; the wait is bounded, and an expired wait latches an error.
+struct FastPlan {
+  uint32_t ka[256], kb[256];  // keys (j << 6) | i in append order, then sorted
+  int32_t gs[257];            // first sorted entry of each group, then the list length
+};
+constexpr int kPlanWaitMax = 1 << 22;  // polls of the plan flag (each after a short sleep)
+
+__global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int plan) {
   const SysDesc& D = desc[blockIdx.y];
   const int n = D.n, nb = D.nb;
   const double mu0 = D.mu0, h = D.h, tol = D.bs_tol;
@@ -1038,12 +1066,129 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc) {
   __shared__ double res[kC][6 * kM];
   __shared__ double wk[kC][3][3 * kM];
   __shared__ double resS[8][kC][6 * 4];  // speculative rounds of subsystems of <= 4 members
+  __shared__ FastPlan F;
+  __shared__ int s_scan[64], s_nbig, s_nsub;
   const int lane = threadIdx.x;
-  const int nsub = dsc->n_sub;
   const double tol2 = tol * tol;
+  int nsub = 0;
+  bool fast = false;
+  if (!plan) {
+    nsub = dsc->n_sub;
+  } else {
+    const bool b0 = blockIdx.x == 0;
+    const int n_pairs = dsc->n_pairs;
+    const int np = min(n_pairs, D.cap_pairs);
+    const auto gpairs = gbl(D.pairs);
+    if (b0 && lane == 0) {
+      dsc->n_pairs_last = n_pairs;
+      dsc->pairs_flagged += (unsigned long long)n_pairs;
+      if (np == 0) dsc->n_sub = 0;
+    }
+    if (np > 0) {
+      fast = np <= 256 && nb <= 64 && n < (1 << 26);
+      if (fast) {
+        bool bb = false;
+        for (int e = lane; e < np; e += 64) {
+          const int i = gpairs[2 * e], j = gpairs[2 * e + 1];
+          bb |= j < nb;
+          F.ka[e] = ((uint32_t)j << 6) | (uint32_t)i;
+        }
+        fast = __builtin_amdgcn_ballot_w64(bb) == 0;
+      }
+      if (fast) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        wave_rank_sort(F.ka, F.kb, np);
+        // group starts, numbered in list order
+        int base = 0;
+        for (int r = 0; r < (np + 63) / 64; ++r) {
+          const int e = 64 * r + lane;
+          const bool start = e < np && (e == 0 || (F.kb[e] >> 6) != (F.kb[e - 1] >> 6));
+          const uint64_t bal = __ballot(start);
+          const int g = base + __popcll(bal & ((1ull << lane) - 1ull));
+          base += __popcll(bal);
+          if (start) F.gs[g] = e;
+        }
+        if (lane == 0) F.gs[base] = np;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        nsub = min(base, D.cap_subs);
+        if (b0) {
+          // the table for the readers after the step (same records as the
+          // planning kernel writes)
+          for (int g = lane; g < base; g += 64) {
+            if (g >= D.cap_subs) {
+              atomicOr(&dsc->err, MXE_SUBSYS);
+              continue;
+            }
+            const int e0 = F.gs[g], k = F.gs[g + 1] - e0;
+            const auto R = subs + g;
+            R->pad = 0;
+            if (k + 1 > kBsMaxMembers || k > kBsMaxPairs) {
+              atomicOr(&dsc->err, MXE_SUBSYS);
+              R->m = 0;
+              R->np = 0;
+              R->keep_from = 0;
+              continue;
+            }
+            R->m = k + 1;
+            R->keep_from = k;
+            R->np = k;
+            for (int q = 0; q < k; ++q) {
+              R->mem[q] = (int32_t)(F.kb[e0 + q] & 63u);
+              R->pl[q][0] = q;
+              R->pl[q][1] = k;
+            }
+            R->mem[k] = (int32_t)(F.kb[e0] >> 6);
+          }
+          if (lane == 0) dsc->n_sub = nsub;
+        }
+      } else {
+        if (b0) {
+          plan_general(nb, gpairs, np, D.keys, D.keys + D.cap_pairs, D.plan_idx,
+                       D.plan_idx + D.cap_pairs, D.uf, D.subs, D.cap_subs, dsc, 0, s_scan, &s_nbig);
+          __syncthreads();
+          if (lane == 0) {
+            s_nsub = dsc->n_sub;
+            __hip_atomic_store(&dsc->plan_ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        } else if (lane == 0) {
+          int it = 0;
+          while (__hip_atomic_load(&dsc->plan_ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            __builtin_amdgcn_s_sleep(8);
+            if (++it >= kPlanWaitMax) break;
+          }
+          if (it >= kPlanWaitMax) {
+            atomicOr(&dsc->err, MXE_PLANWAIT);
+            s_nsub = 0;
+          } else {
+            s_nsub = __hip_atomic_load(&dsc->n_sub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+        __syncthreads();
+        nsub = s_nsub;
+      }
+    }
+  }
   for (int b = blockIdx.x; b < nsub; b += gridDim.x) {
     __syncthreads();
-    {
+    if (fast) {
+      // subsystem b from the sorted keys in LDS
+      const int e0 = F.gs[b], k = F.gs[b + 1] - e0;
+      const bool fits = k + 1 <= kBsMaxMembers && k <= kBsMaxPairs;
+      if (lane == 0) {
+        S.m = fits ? k + 1 : 0;
+        S.keep_from = fits ? k : 0;
+        S.np = fits ? k : 0;
+        S.pad = 0;
+        if (fits) S.mem[k] = (int32_t)(F.kb[e0] >> 6);
+      }
+      if (fits && lane < k) {
+        S.mem[lane] = (int32_t)(F.kb[e0 + lane] & 63u);
+        S.pl[lane][0] = lane;
+        S.pl[lane][1] = k;
+      }
+    } else {
       const auto src = reinterpret_cast<gmem<const int32_t>>(subs + b);
       int32_t* dst = reinterpret_cast<int32_t*>(&S);
       for (int i = lane; i < (int)(sizeof(Subsystem) / 4); i += 64) dst[i] = src[i];
@@ -1222,9 +1367,9 @@ hipError_t launch_plan_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc
 }
 
 hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys,
-                         int bps) {
+                         int bps, int plan) {
   if (n_sys <= 0 || bps <= 0) return hipSuccess;
-  return mxlaunch_on(st, tm, k_bs, dim3(bps, n_sys), dim3(64), desc);
+  return mxlaunch_on(st, tm, k_bs, dim3(bps, n_sys), dim3(64), desc, plan);
 }
 
 // flag + sort for the stateless entry; fpack built from the given states

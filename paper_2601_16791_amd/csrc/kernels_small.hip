@@ -328,6 +328,7 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
       if (kick) {
         D.dsc->step += 1;
         D.dsc->n_pairs = 0;  // the encounter list of this step has been planned
+        D.dsc->plan_ready = 0;
       }
     }
     if (t >= n) continue;

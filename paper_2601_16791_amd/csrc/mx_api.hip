@@ -130,10 +130,11 @@ hipError_t launch_group(mx_system* s, int k) {
                                               kTileBlk, 1)
                    : mxk::launch_kick_jump_drift(s);
     case MX_K_FLAG: return small ? hipSuccess : mxk::launch_flag(s);
-    case MX_K_PLAN:
-      return s->nb > 0 ? mxk::launch_plan_sys(s->stream, &s->tev, s->desc, 1) : hipSuccess;
+    case MX_K_PLAN:  // the fused path plans inside the encounter integrator
+      return s->nb > 0 && !small ? mxk::launch_plan_sys(s->stream, &s->tev, s->desc, 1)
+                                 : hipSuccess;
     case MX_K_BS:
-      return s->nb > 0 ? mxk::launch_bs_sys(s->stream, &s->tev, s->desc, 1, kBsBlocks)
+      return s->nb > 0 ? mxk::launch_bs_sys(s->stream, &s->tev, s->desc, 1, kBsBlocks, small)
                        : hipSuccess;
     case MX_K_JUMP_PACK: return small ? hipSuccess : mxk::launch_jump_pack(s);
     default:
@@ -172,6 +173,8 @@ mx_status read_err(mx_system* s) {
     if (err & MXE_ADJOINT)
       return fail(MX_ECAPACITY, "an encounter subsystem exceeds what the adjoint handles "
                                 "(more than 4 members or 64 accepted steps)");
+    if (err & MXE_PLANWAIT)
+      return fail(MX_EHIP, "the encounter integrator's wait for its plan expired");
   }
   return MX_OK;
 }
@@ -672,8 +675,8 @@ hipError_t enqueue_batch_step(mx_batch* b) {
   if ((e = mxk::launch_step_a_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles, b->blk,
                                     b->tpb)) != hipSuccess)
     return e;
-  if ((e = mxk::launch_plan_sys(b->stream, &b->tev, b->desc, b->n_sys)) != hipSuccess) return e;
-  if ((e = mxk::launch_bs_sys(b->stream, &b->tev, b->desc, b->n_sys, b->bps)) != hipSuccess)
+  // (the encounter integrator plans its subsystems itself: every system has n_big <= 64)
+  if ((e = mxk::launch_bs_sys(b->stream, &b->tev, b->desc, b->n_sys, b->bps, 1)) != hipSuccess)
     return e;
   return mxk::launch_step_b_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles, b->blk,
                                   b->tpb, 1);

@@ -16,6 +16,7 @@ enum : int32_t {
   MXE_SUBSYS = 8,      // a subsystem larger than the encounter integrator holds
   MXE_NONFINITE = 16,  // non-finite state after a step
   MXE_ADJOINT = 32,    // a subsystem beyond what the adjoint handles
+  MXE_PLANWAIT = 64,   // a block of the encounter integrator gave up waiting for the plan
 };
 
 // Systems with at most this many massive bodies use the fused small-B kernels.
@@ -54,6 +55,8 @@ struct DevScalars {
   double P[3];           // massive-body momentum sum mu*u after the last jump
   unsigned long long bs_flop;        // cumulative model FP64 ops of the encounter integrator
   unsigned long long pairs_flagged;  // cumulative flagged pairs
+  int32_t plan_ready;    // set when the in-kernel general plan of this step is written
+  int32_t pad0;
 };
 
 namespace mxd {
@@ -232,10 +235,11 @@ hipError_t launch_step_a_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* 
                                const Tile* tiles, int n_tiles, int blk, int tpb);
 hipError_t launch_step_b_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
                                const Tile* tiles, int n_tiles, int blk, int tpb, int kick);
-// planner (one block per system) and encounter integrator (bps blocks per system)
+// planner (one block per system) and encounter integrator (bps blocks per system;
+// plan != 0: the integrator plans its subsystems itself, systems of n_big <= 64)
 hipError_t launch_plan_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys);
 hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys,
-                         int bps);
+                         int bps, int plan);
 
 // stateless single-kernel launchers
 hipError_t gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,

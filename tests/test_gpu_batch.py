@@ -82,6 +82,28 @@ def test_batch_launch_shapes_bitwise_identical(mx, cfg):
     assert_batch_equals(b, ref, steps)
 
 
+def test_batch_with_big_components_and_long_lists(mx):
+    """Systems whose encounter lists take the general plan (big-big pairs; more
+    than 256 pairs) next to systems on the common plan, in one launch: each must
+    still compute exactly what it computes alone."""
+    from test_gpu_parity import _planets_with_cloud
+    ws = [ic.embryo_disk(seed=21, n_small=900, n_emb=3),
+          _planets_with_cloud(n_far=60, k=40, close_pair=True),
+          ic.embryo_disk(seed=22, n_small=300, n_emb=2),
+          _planets_with_cloud(n_far=20, k=320, close_pair=False)]
+    steps = 3
+    ref = single_runs(mx, ws, steps)
+    for cfg in [(128, 1, 4), (256, 2, 1)]:
+        b = mx.Batch.from_workloads(ws)
+        b.set_config(*cfg)
+        b.step(steps)
+        b.sync()
+        assert_batch_equals(b, ref, steps)
+        b.close()
+    assert max(len(r[2]) for r in ref) > 256
+    assert any(np.any(np.asarray(r[2])[:, 1] < 3) for r in ref if len(r[2]))
+
+
 def test_batch_autotune_and_graph_launch(mx):
     ws = uneven_workloads()
     b = mx.Batch.from_workloads(ws)

@@ -338,6 +338,13 @@ def test_error_paths(mx):
 def _close_planets_workload(n_far=200):
     """Three planets, two of them inside each other's changeover radius, with a cloud
     of massless bodies around the pair: big-big components and shared copies."""
+    return _planets_with_cloud(n_far, k=40, close_pair=True)
+
+
+def _planets_with_cloud(n_far, k, close_pair):
+    """Three planets (the second inside the first one's changeover radius when
+    close_pair, else far out) with k massless bodies in a cloud of 0.6 Hill radii
+    around the first and n_far massless bodies on near-circular orbits."""
     rng = np.random.default_rng(9)
     mJ = ic.M_JUP
     a_p = 5.2
@@ -346,7 +353,9 @@ def _close_planets_workload(n_far=200):
     m = np.array([mJ, 0.3 * mJ, 0.1 * mJ])
     xb = np.array([[a_p, a_p + 0.7 * rH, -8.0], [0.0, 0.15 * rH, 1.0], [0.0, 0.0, 0.01]])
     vb = np.array([[0.0, 0.0, -0.1 * vp * 0.5], [vp, vp * 1.002, -0.8 * vp * 0.6], [0.0, 1e-5, 0.0]])
-    k = 40
+    if not close_pair:
+        xb[:, 1] = [-9.0, 2.0, 0.02]
+        vb[:, 1] = [-0.2 * vp * 0.74, -0.97 * vp * 0.74, 0.0]
     d = rng.normal(0, 0.6 * rH, (3, k)); d[2] *= 0.1
     xs = xb[:, :1] + d
     vs = vb[:, :1] + rng.normal(0, 0.02 * vp, (3, k))
@@ -384,6 +393,34 @@ def test_step_parity_big_components(mx, orc):
         assert np.all(relerr_per_body(ug, uo) <= tol_u), k
         ill += int(np.sum(np.maximum(sx, su) > 1e-13))
     assert saw_bigbig
+
+
+def test_step_parity_long_encounter_list(mx, orc):
+    """More than 256 flagged pairs in a step of the fused path (no big-big pair):
+    the encounter integrator's first block takes the general plan while the other
+    blocks wait for it."""
+    w = _planets_with_cloud(n_far=50, k=320, close_pair=False)
+    g = mx.System.from_workload(w)
+    o = orc.OracleSystem.from_workload(w)
+    x, u = g.get_dh()
+    o.set_dh(x, u, 0)
+    g.set_dh(x, u, 0)
+    longest = 0
+    for k in range(2):
+        x, u = g.get_dh()
+        g.step(1)
+        g.sync()
+        xo, uo, sx, su = oracle_sensitivity(o, x, u, k)
+        xg, ug = g.get_dh()
+        pg, po = g.encounters(), o.encounters()
+        assert not np.any(po[:, 1] < 3)
+        longest = max(longest, len(po))
+        assert {tuple(p) for p in pg} == {tuple(p) for p in po}
+        tol_x = np.maximum(1e-12, 10 * sx)
+        tol_u = np.maximum(1e-12, 10 * su)
+        assert np.all(relerr_per_body(xg, xo) <= tol_x), k
+        assert np.all(relerr_per_body(ug, uo) <= tol_u), k
+    assert longest > 256
 
 
 def test_flag_kernel_large_list(mx, orc):
