@@ -16,7 +16,9 @@
 //                  built across lanes, and the first accepted column is taken, the
 //                  same column a sequential integrator would stop at.  Pair forces
 //                  inside a subsystem are owner-computed in one lane (no atomics,
-//                  the fo_hkce critical region of Sect. 2.1.2 disappears).
+//                  the fo_hkce critical region of Sect. 2.1.2 disappears).  For
+//                  systems of at most 64 massive bodies the blocks plan the
+//                  subsystems themselves first (see FastPlan), without k_plan.
 #include <hip/hip_runtime.h>
 
 #include "device_math.h"

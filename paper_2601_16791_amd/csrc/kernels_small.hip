@@ -13,8 +13,9 @@
 //              changeover-weighted gravity from the massive bodies held in LDS,
 //              gas drag and the closing half kick.
 //
-// Between the two run the encounter planner and the Bulirsch-Stoer kernel.  Four
-// launches per step instead of six, and no packed-source round trip through HBM.
+// Between the two runs the Bulirsch-Stoer kernel, which plans its subsystems
+// itself.  Three launches per step instead of six, and no packed-source round
+// trip through HBM.
 // A block takes tpb consecutive tiles (persistent over them) and redoes the
 // massive-body phase only when the system changes.  Per body the arithmetic does
 // not depend on the tile shape: the block sums run over at most 64 massive bodies,
