@@ -1049,7 +1049,7 @@ struct FastPlan {
 };
 constexpr int kPlanWaitMax = 1 << 22;  // polls of the plan flag (each after a short sleep)
 
-__global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int plan) {
+__global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int plan, int par) {
   const SysDesc& D = desc[blockIdx.y];
   const int n = D.n, nb = D.nb;
   const double mu0 = D.mu0, h = D.h, tol = D.bs_tol;
@@ -1061,7 +1061,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
   const auto rcrit = gbl(D.rcrit);
   const auto subs = gbl(D.subs);
   DevScalars* __restrict__ dsc = D.dsc;
-  const auto bigmid = gbl(D.bigmid);
+  const auto bigmid = gbl(D.bigmid) + (size_t)par * 6 * nb;
   if (nb == 0) return;
   __shared__ Subsystem S;
   __shared__ double xs[3 * kM], vs[3 * kM], mum[kM], rcm[kM], scal[2 * kM];
@@ -1078,7 +1078,10 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
     nsub = dsc->n_sub;
   } else {
     const bool b0 = blockIdx.x == 0;
-    const int n_pairs = dsc->n_pairs;
+    const int n_pairs = *pair_counter(dsc, par);
+    // the other counter takes the next step's appends when steps are joined in
+    // one launch; nothing reads or appends to it while this kernel runs
+    if (b0 && lane == 0) *pair_counter(dsc, par ^ 1) = 0;
     const int np = min(n_pairs, D.cap_pairs);
     const auto gpairs = gbl(D.pairs);
     if (b0 && lane == 0) {
@@ -1369,9 +1372,9 @@ hipError_t launch_plan_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc
 }
 
 hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys,
-                         int bps, int plan) {
+                         int bps, int plan, int par) {
   if (n_sys <= 0 || bps <= 0) return hipSuccess;
-  return mxlaunch_on(st, tm, k_bs, dim3(bps, n_sys), dim3(64), desc, plan);
+  return mxlaunch_on(st, tm, k_bs, dim3(bps, n_sys), dim3(64), desc, plan, par);
 }
 
 // flag + sort for the stateless entry; fpack built from the given states

@@ -102,6 +102,74 @@ __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double
   }
 }
 
+// Encounter test of body t (pre-drift p, v; post-drift q, w) against every
+// massive body i < t held in LDS (same bound and exact Hermite test as the
+// general flag kernel): the bound marks candidates in a bit mask (nb <= 64), then
+// the lanes of the wave take their candidates one at a time together, so a wave
+// with candidates against different massive bodies runs the Hermite test once
+// per round rather than once per body.  Flagged pairs are appended to the list
+// (append counter of step parity par);
+// the pre-drift state is stored where the encounter integrator starts from it.
+__device__ __forceinline__ void flag_body(const SysDesc& D, int par, int t, int n, int nb,
+                                          double h, const double (*bst)[kSmallBig],
+                                          const double* brc, const double (&p)[3],
+                                          const double (&v)[3], const double (&q)[3],
+                                          const double (&w)[3]) {
+  const double rct = t < nb ? brc[t] : 0.0;
+  const int imax = t < nb ? t : nb;
+  const double k427 = (4.0 / 27.0) * fabs(h);
+  uint64_t cmask = 0;
+#pragma unroll 4
+  for (int i = 0; i < imax; ++i) {
+    double r0[3], w0[3], w1[3], dd[3];
+    for (int c = 0; c < 3; ++c) {
+      r0[c] = p[c] - bst[c][i];
+      w0[c] = v[c] - bst[3 + c][i];
+      w1[c] = w[c] - bst[9 + c][i];
+      dd[c] = (q[c] - p[c]) - (bst[6 + c][i] - bst[c][i]);
+    }
+    double m0 = fma(r0[2], r0[2], fma(r0[1], r0[1], r0[0] * r0[0]));
+    double nd = fmax(fmax(fabs(dd[0]), fabs(dd[1])), fabs(dd[2]));
+    double nw = fmax(fmax(fabs(w0[0]), fabs(w0[1])), fabs(w0[2])) +
+                fmax(fmax(fabs(w1[0]), fabs(w1[1])), fabs(w1[2]));
+    double rc = fmax(brc[i], rct);
+    double bound = rc + 1.7320508075688773 * fma(k427, nw, nd) * (1.0 + 1e-12);
+    if (__builtin_expect(m0 <= bound * bound * (1.0 + 1e-12), 0)) cmask |= 1ull << i;
+  }
+  bool hit = false;
+  while (cmask != 0) {
+    const int i = __builtin_ctzll(cmask);
+    cmask &= cmask - 1;
+    double r0[3], w0[3], w1[3], r1[3];
+    for (int c = 0; c < 3; ++c) {
+      r0[c] = p[c] - bst[c][i];
+      w0[c] = v[c] - bst[3 + c][i];
+      w1[c] = w[c] - bst[9 + c][i];
+      r1[c] = q[c] - bst[6 + c][i];
+    }
+    const double rc = fmax(brc[i], rct);
+    double dmin = mxd::hermite_dmin2(r0[0], r0[1], r0[2], w0[0], w0[1], w0[2], r1[0], r1[1],
+                                     r1[2], w1[0], w1[1], w1[2], h);
+    if (dmin <= rc * rc) {
+      hit = true;
+      int idx = atomicAdd(pair_counter(D.dsc, par), 1);
+      if (idx < D.cap_pairs) {
+        gbl(D.pairs)[2 * idx] = i;
+        gbl(D.pairs)[2 * idx + 1] = t;
+      } else {
+        atomicOr(&D.dsc->err, MXE_PAIRS);
+      }
+    }
+  }
+  // pre-drift state: the encounter integrator starts its subsystems from it
+  if (hit || t < nb || D.keep_x0) {
+    for (int c = 0; c < 3; ++c) {
+      gbl(D.x0)[c * n + t] = p[c];
+      gbl(D.u0)[c * n + t] = v[c];
+    }
+  }
+}
+
 // First half of the fused step over a tile table: per tile, drag + half kick +
 // jump + Kepler drift of its bodies and the encounter test against the massive
 // bodies.  A block takes `tpb` consecutive tiles and redoes the massive-body
@@ -109,7 +177,7 @@ __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double
 template <int BLK>
 __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc,
                                                 const Tile* __restrict__ tiles, int n_tiles,
-                                                int tpb) {
+                                                int tpb, int par) {
   __shared__ double sh[8];
   __shared__ double bst[12][kSmallBig];  // x0 (3) u0 (3) x1 (3) u1 (3) of the big bodies
   __shared__ double brc[kSmallBig];
@@ -166,9 +234,10 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
         q[c] = bst[6 + c][t];
         w[c] = bst[9 + c][t];
       }
+      const auto bigmid = gbl(D.bigmid) + (size_t)par * 6 * nb;
       for (int c = 0; c < 3; ++c) {
-        gbl(D.bigmid)[c * nb + t] = q[c];
-        gbl(D.bigmid)[(3 + c) * nb + t] = w[c];
+        bigmid[c * nb + t] = q[c];
+        bigmid[(3 + c) * nb + t] = w[c];
       }
     } else {
       if (!advance_body(t, nb, D.mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v, a, q, w))
@@ -178,65 +247,51 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
       gbl(D.x)[c * n + t] = q[c];
       gbl(D.u)[c * n + t] = w[c];
     }
-    // encounter test against every massive body i < t (same bound and exact
-    // Hermite test as the general flag kernel): the bound marks candidates in a
-    // bit mask (nb <= 64), then the lanes of the wave take their candidates one
-    // at a time together, so a wave with candidates against different massive
-    // bodies runs the Hermite test once per round rather than once per body
-    const double rct = t < nb ? brc[t] : 0.0;
-    const int imax = t < nb ? t : nb;
-    const double k427 = (4.0 / 27.0) * fabs(h);
-    uint64_t cmask = 0;
-#pragma unroll 4
-    for (int i = 0; i < imax; ++i) {
-      double r0[3], w0[3], w1[3], dd[3];
-      for (int c = 0; c < 3; ++c) {
-        r0[c] = p[c] - bst[c][i];
-        w0[c] = v[c] - bst[3 + c][i];
-        w1[c] = w[c] - bst[9 + c][i];
-        dd[c] = (q[c] - p[c]) - (bst[6 + c][i] - bst[c][i]);
-      }
-      double m0 = fma(r0[2], r0[2], fma(r0[1], r0[1], r0[0] * r0[0]));
-      double nd = fmax(fmax(fabs(dd[0]), fabs(dd[1])), fabs(dd[2]));
-      double nw = fmax(fmax(fabs(w0[0]), fabs(w0[1])), fabs(w0[2])) +
-                  fmax(fmax(fabs(w1[0]), fabs(w1[1])), fabs(w1[2]));
-      double rc = fmax(brc[i], rct);
-      double bound = rc + 1.7320508075688773 * fma(k427, nw, nd) * (1.0 + 1e-12);
-      if (__builtin_expect(m0 <= bound * bound * (1.0 + 1e-12), 0)) cmask |= 1ull << i;
-    }
-    bool hit = false;
-    while (cmask != 0) {
-      const int i = __builtin_ctzll(cmask);
-      cmask &= cmask - 1;
-      double r0[3], w0[3], w1[3], r1[3];
-      for (int c = 0; c < 3; ++c) {
-        r0[c] = p[c] - bst[c][i];
-        w0[c] = v[c] - bst[3 + c][i];
-        w1[c] = w[c] - bst[9 + c][i];
-        r1[c] = q[c] - bst[6 + c][i];
-      }
-      const double rc = fmax(brc[i], rct);
-      double dmin = mxd::hermite_dmin2(r0[0], r0[1], r0[2], w0[0], w0[1], w0[2], r1[0], r1[1],
-                                       r1[2], w1[0], w1[1], w1[2], h);
-      if (dmin <= rc * rc) {
-        hit = true;
-        int idx = atomicAdd(&D.dsc->n_pairs, 1);
-        if (idx < D.cap_pairs) {
-          gbl(D.pairs)[2 * idx] = i;
-          gbl(D.pairs)[2 * idx + 1] = t;
-        } else {
-          atomicOr(&D.dsc->err, MXE_PAIRS);
-        }
-      }
-    }
-    // pre-drift state: the encounter integrator starts its subsystems from it
-    if (hit || t < nb || D.keep_x0) {
-      for (int c = 0; c < 3; ++c) {
-        gbl(D.x0)[c * n + t] = p[c];
-        gbl(D.u0)[c * n + t] = v[c];
-      }
-    }
+    flag_body(D, par, t, n, nb, h, bst, brc, p, v, q, w);
   }
+}
+
+// Closing part of a step for one body, from its state after the encounter
+// integrator: jump by J, changeover-weighted gravity of the massive bodies in
+// src (rct: the body's own changeover radius, 0 when massless) and, with kick,
+// the gas drag (massless bodies, frame velocity vpre) and the half kick.
+// pos: in before the jump, out after it; acc: out, the gravity.
+__device__ __forceinline__ void close_body(int t, int nb, const KickSource* src, double rct,
+                                           const double (&J)[3], const double (&vpre)[3],
+                                           double hh, const DragConst& dc, int gas_on, double rp,
+                                           double rhop, bool kick, double (&pos)[3],
+                                           double (&vel)[3], double (&acc)[3]) {
+  const double px = pos[0] + J[0], py = pos[1] + J[1], pz = pos[2] + J[2];
+  const double rc2t = rct * rct;
+  double k15, k1875;
+  mxd::vgpr_constants(k15, k1875);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
+  for (int s = 0; s < nb; ++s) {
+    const KickSource S = src[s];
+    double dx = S.x - px, dy = S.y - py, dz = S.z - pz;
+    double s2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    double rc2 = fmax(S.rc2, rc2t);
+    double wgt = mxd::fast_weight(S.mu, s2, k15, k1875);
+    if (s2 < rc2) wgt = S.mu * mxd::changeover_weight_slow(s2, fmax(S.rc, rct), rc2);
+    a0 = fma(wgt, dx, a0);
+    a1 = fma(wgt, dy, a1);
+    a2 = fma(wgt, dz, a2);
+  }
+  pos[0] = px;
+  pos[1] = py;
+  pos[2] = pz;
+  acc[0] = a0;
+  acc[1] = a1;
+  acc[2] = a2;
+  if (!kick) return;
+  double adx = 0.0, ady = 0.0, adz = 0.0;
+  if (t >= nb && gas_on)
+    mxd::gas_drag(dc, px, py, vel[0] + vpre[0], vel[1] + vpre[1], vel[2] + vpre[2], rp, rhop,
+                  adx, ady, adz);
+  vel[0] += hh * (a0 + adx);
+  vel[1] += hh * (a1 + ady);
+  vel[2] += hh * (a2 + adz);
 }
 
 // Second half of the fused step over a tile table: jump by the massive-body
@@ -245,7 +300,7 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
 template <int BLK>
 __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc,
                                                 const Tile* __restrict__ tiles, int n_tiles,
-                                                int tpb, int kick) {
+                                                int tpb, int kick, int par) {
   __shared__ double sh[4];
   __shared__ KickSource src[kSmallBig];
   const int tid = threadIdx.x;
@@ -269,7 +324,7 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
     double bx = 0.0, by = 0.0, bz = 0.0, bm = 0.0, brc = 0.0;
     double Q[3] = {0.0, 0.0, 0.0};
     if (fresh && tid < nb) {
-      const auto bigmid = gbl(D.bigmid);
+      const auto bigmid = gbl(D.bigmid) + (size_t)par * 6 * nb;
       bx = bigmid[tid];
       by = bigmid[nb + tid];
       bz = bigmid[2 * nb + tid];
@@ -329,42 +384,26 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
       if (kick) {
         D.dsc->step += 1;
         D.dsc->n_pairs = 0;  // the encounter list of this step has been planned
+        D.dsc->n_pairs_alt = 0;
         D.dsc->plan_ready = 0;
       }
     }
     if (t >= n) continue;
-    const double px = x0 + J[0], py = x1 + J[1], pz = x2 + J[2];
+    double pos[3] = {x0, x1, x2}, vel[3] = {vx, vy, vz}, acc[3];
+    close_body(t, nb, src, t < nb ? src[t].rc : 0.0, J, vpre, hh, D.dc, D.gas_on, rp, rhop,
+               kick != 0, pos, vel, acc);
+    const double px = pos[0], py = pos[1], pz = pos[2];
+    const double a0 = acc[0], a1 = acc[1], a2 = acc[2];
     x[t] = px;
     x[n + t] = py;
     x[2 * n + t] = pz;
-    const double rct = t < nb ? src[t].rc : 0.0;
-    const double rc2t = rct * rct;
-    double k15, k1875;
-    mxd::vgpr_constants(k15, k1875);
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-#pragma unroll 4
-    for (int s = 0; s < nb; ++s) {
-      const KickSource S = src[s];
-      double dx = S.x - px, dy = S.y - py, dz = S.z - pz;
-      double s2 = fma(dz, dz, fma(dy, dy, dx * dx));
-      double rc2 = fmax(S.rc2, rc2t);
-      double wgt = mxd::fast_weight(S.mu, s2, k15, k1875);
-      if (s2 < rc2) wgt = S.mu * mxd::changeover_weight_slow(s2, fmax(S.rc, rct), rc2);
-      a0 = fma(wgt, dx, a0);
-      a1 = fma(wgt, dy, a1);
-      a2 = fma(wgt, dz, a2);
-    }
     ag[t] = a0;
     ag[n + t] = a1;
     ag[2 * n + t] = a2;
     if (!kick) continue;
-    double adx = 0.0, ady = 0.0, adz = 0.0;
-    if (t >= nb && D.gas_on)
-      mxd::gas_drag(D.dc, px, py, vx + vpre[0], vy + vpre[1], vz + vpre[2], rp, rhop, adx, ady,
-                    adz);
-    vx += hh * (a0 + adx);
-    vy += hh * (a1 + ady);
-    vz += hh * (a2 + adz);
+    vx = vel[0];
+    vy = vel[1];
+    vz = vel[2];
     u[t] = vx;
     u[n + t] = vy;
     u[2 * n + t] = vz;
@@ -378,36 +417,185 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
   }
 }
 
+// Two steps joined at their boundary: the closing part of step n (as k_step_b,
+// with kick) and the opening part of step n + 1 (as k_step_a) in one pass over
+// the tiles, the body's state staying in registers in between.  Each block
+// closes step n for the massive bodies itself, from their state after the
+// encounter integrator (the same arithmetic as the owner tile of k_step_b, in
+// every block), then advances them as k_step_a does; every body sees exactly the
+// operations of k_step_b followed by k_step_a.  What only those kernels store in
+// between (positions after the jump, accelerations, the massive-body snapshot)
+// is not stored.  Step n's massive bodies are read from bigmid buffer par (every
+// block reads them), step n + 1's are written to buffer par ^ 1, and its flagged
+// pairs are counted by the append counter of parity par ^ 1: no block overwrites
+// what another may still read.
+template <int BLK>
+__global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ desc,
+                                                 const Tile* __restrict__ tiles, int n_tiles,
+                                                 int tpb, int par) {
+  __shared__ double sh[8];
+  __shared__ KickSource src[kSmallBig];
+  __shared__ double bst[12][kSmallBig];
+  __shared__ double brc[kSmallBig];
+  const int tid = threadIdx.x;
+  const int t_lo = blockIdx.x * tpb;
+  const int t_hi = min(n_tiles, t_lo + tpb);
+  int cur = -1;
+  double J[3], vpre[3], Ppre[3], Ppost[3];
+  for (int ti = t_lo; ti < t_hi; ++ti) {
+    const Tile tl = tiles[ti];
+    const SysDesc& D = desc[tl.sys];
+    const int n = D.n, nb = D.nb;
+    const double h = D.h, hh = 0.5 * D.h, mu0 = D.mu0;
+    const int t = tl.first + tid;
+    const bool fresh = tl.sys != cur;  // block-uniform
+    // massive bodies after the encounter integrator, then the body's own state
+    double bpos[3], bvel[3], bacc[3], bm = 0.0, brc_t = 0.0;
+    if (fresh && tid < nb) {
+      const auto bigmid = gbl(D.bigmid) + (size_t)par * 6 * nb;
+      for (int c = 0; c < 3; ++c) {
+        bpos[c] = bigmid[c * nb + tid];
+        bvel[c] = bigmid[(3 + c) * nb + tid];
+      }
+      bm = gbl(D.mu)[tid];
+      brc_t = gbl(D.rcrit)[tid];
+    }
+    double p[3], v[3], a[3], q[3], w[3], rp = 0.0, rhop = 0.0;
+    if (t < n && t >= nb) {
+      for (int c = 0; c < 3; ++c) {
+        p[c] = gbl(D.x)[c * n + t];
+        v[c] = gbl(D.u)[c * n + t];
+      }
+      if (D.gas_on) {
+        rp = gbl(D.r_p)[t - nb];
+        rhop = gbl(D.rho_p)[t - nb];
+      }
+    }
+    if (fresh) {
+      __syncthreads();  // the previous tile is done with the LDS copies
+      // step n: momentum after the encounter integrator (as k_step_b)
+      if (tid < 64) {
+        double Q[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Q[c] = mxd::wave_sum_fixed(tid < nb ? bm * bvel[c] : 0.0);
+        if (tid == 0)
+          for (int c = 0; c < 3; ++c) sh[c] = Q[c];
+      }
+      __syncthreads();
+      double P[3];
+      for (int c = 0; c < 3; ++c) {
+        P[c] = sh[c];
+        J[c] = hh * P[c] / mu0;
+        vpre[c] = P[c] / mu0;
+      }
+      if (tid < nb) {
+        KickSource k;
+        k.x = bpos[0] + J[0];
+        k.y = bpos[1] + J[1];
+        k.z = bpos[2] + J[2];
+        k.mu = bm;
+        k.rc2 = fmax(brc_t * brc_t, 1e-300);
+        k.rc = brc_t;
+        k.pad0 = k.pad1 = 0.0;
+        src[tid] = k;
+      }
+      __syncthreads();
+      if (tl.first == 0 && tid == 0) {
+        D.dsc->P[0] = P[0];
+        D.dsc->P[1] = P[1];
+        D.dsc->P[2] = P[2];
+        D.dsc->step += 1;
+        D.dsc->plan_ready = 0;
+      }
+      // step n closed for the massive bodies, then step n + 1 opened for them
+      if (tid < nb) {
+        close_body(tid, nb, src, src[tid].rc, J, vpre, hh, D.dc, D.gas_on, 0.0, 0.0, true, bpos,
+                   bvel, bacc);
+        if (tl.first == 0 &&
+            !isfinite(bvel[0] + bvel[1] + bvel[2] + bpos[0] + bpos[1] + bpos[2]))
+          atomicOr(&D.dsc->err, MXE_NONFINITE);
+      }
+      big_phase_a<BLK>(D, tl.first == 0, sh, bst, brc, bpos, bvel, bacc, bm, brc_t, Ppre, Ppost);
+      __syncthreads();
+      cur = tl.sys;
+    }
+    if (t < n) {
+      if (t < nb) {
+        for (int c = 0; c < 3; ++c) {
+          p[c] = bst[c][t];
+          v[c] = bst[3 + c][t];
+          q[c] = bst[6 + c][t];
+          w[c] = bst[9 + c][t];
+        }
+        // step n + 1's massive bodies go to the other bigmid buffer
+        const auto bigmid = gbl(D.bigmid) + (size_t)(par ^ 1) * 6 * nb;
+        for (int c = 0; c < 3; ++c) {
+          bigmid[c * nb + t] = q[c];
+          bigmid[(3 + c) * nb + t] = w[c];
+        }
+      } else {
+        close_body(t, nb, src, 0.0, J, vpre, hh, D.dc, D.gas_on, rp, rhop, true, p, v, a);
+        if (!isfinite(v[0] + v[1] + v[2] + p[0] + p[1] + p[2]))
+          atomicOr(&D.dsc->err, MXE_NONFINITE);
+        if (!advance_body(t, nb, mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v, a, q, w))
+          atomicOr(&D.dsc->err, MXE_NOCONV);
+      }
+      for (int c = 0; c < 3; ++c) {
+        gbl(D.x)[c * n + t] = q[c];
+        gbl(D.u)[c * n + t] = w[c];
+      }
+      flag_body(D, par ^ 1, t, n, nb, h, bst, brc, p, v, q, w);
+    }
+  }
+}
+
 }  // namespace
 
 namespace mxk {
 
 hipError_t launch_step_a_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
-                               const Tile* tiles, int n_tiles, int blk, int tpb) {
+                               const Tile* tiles, int n_tiles, int blk, int tpb, int par) {
   if (n_tiles <= 0) return hipSuccess;
   const dim3 grid((n_tiles + tpb - 1) / tpb);
   switch (blk) {
-    case 64: return mxlaunch_on(st, tm, k_step_a<64>, grid, dim3(64), desc, tiles, n_tiles, tpb);
-    case 128: return mxlaunch_on(st, tm, k_step_a<128>, grid, dim3(128), desc, tiles, n_tiles, tpb);
-    case 256: return mxlaunch_on(st, tm, k_step_a<256>, grid, dim3(256), desc, tiles, n_tiles, tpb);
-    case 512: return mxlaunch_on(st, tm, k_step_a<512>, grid, dim3(512), desc, tiles, n_tiles, tpb);
+    case 64: return mxlaunch_on(st, tm, k_step_a<64>, grid, dim3(64), desc, tiles, n_tiles, tpb, par);
+    case 128: return mxlaunch_on(st, tm, k_step_a<128>, grid, dim3(128), desc, tiles, n_tiles, tpb, par);
+    case 256: return mxlaunch_on(st, tm, k_step_a<256>, grid, dim3(256), desc, tiles, n_tiles, tpb, par);
+    case 512: return mxlaunch_on(st, tm, k_step_a<512>, grid, dim3(512), desc, tiles, n_tiles, tpb, par);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_step_ba_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
+                                const Tile* tiles, int n_tiles, int blk, int tpb, int par) {
+  if (n_tiles <= 0) return hipSuccess;
+  const dim3 grid((n_tiles + tpb - 1) / tpb);
+  switch (blk) {
+    case 64: return mxlaunch_on(st, tm, k_step_ba<64>, grid, dim3(64), desc, tiles, n_tiles, tpb, par);
+    case 128:
+      return mxlaunch_on(st, tm, k_step_ba<128>, grid, dim3(128), desc, tiles, n_tiles, tpb, par);
+    case 256:
+      return mxlaunch_on(st, tm, k_step_ba<256>, grid, dim3(256), desc, tiles, n_tiles, tpb, par);
+    case 512:
+      return mxlaunch_on(st, tm, k_step_ba<512>, grid, dim3(512), desc, tiles, n_tiles, tpb, par);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_step_b_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
-                               const Tile* tiles, int n_tiles, int blk, int tpb, int kick) {
+                               const Tile* tiles, int n_tiles, int blk, int tpb, int kick,
+                               int par) {
   if (n_tiles <= 0) return hipSuccess;
   const dim3 grid((n_tiles + tpb - 1) / tpb);
   switch (blk) {
     case 64:
-      return mxlaunch_on(st, tm, k_step_b<64>, grid, dim3(64), desc, tiles, n_tiles, tpb, kick);
+      return mxlaunch_on(st, tm, k_step_b<64>, grid, dim3(64), desc, tiles, n_tiles, tpb, kick, par);
     case 128:
-      return mxlaunch_on(st, tm, k_step_b<128>, grid, dim3(128), desc, tiles, n_tiles, tpb, kick);
+      return mxlaunch_on(st, tm, k_step_b<128>, grid, dim3(128), desc, tiles, n_tiles, tpb, kick, par);
     case 256:
-      return mxlaunch_on(st, tm, k_step_b<256>, grid, dim3(256), desc, tiles, n_tiles, tpb, kick);
+      return mxlaunch_on(st, tm, k_step_b<256>, grid, dim3(256), desc, tiles, n_tiles, tpb, kick, par);
     case 512:
-      return mxlaunch_on(st, tm, k_step_b<512>, grid, dim3(512), desc, tiles, n_tiles, tpb, kick);
+      return mxlaunch_on(st, tm, k_step_b<512>, grid, dim3(512), desc, tiles, n_tiles, tpb, kick, par);
     default: return hipErrorInvalidValue;
   }
 }

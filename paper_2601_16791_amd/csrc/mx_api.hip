@@ -120,26 +120,27 @@ void free_system(mx_system* s) {
 }
 
 // kernel group k of one step (MX_K_* order); the fused small-B path runs its
-// flagging inside the first kernel and its jump inside the last
-hipError_t launch_group(mx_system* s, int k) {
+// flagging inside the first kernel and its jump inside the last.  par: the step
+// parity inside a joined sequence (0 otherwise).
+hipError_t launch_group(mx_system* s, int k, int par = 0) {
   const bool small = s->nb <= kSmallBig;
   switch (k) {
     case MX_K_GROWTH: return mxk::launch_growth(s);
     case MX_K_KICK_JUMP_DRIFT:
       return small ? mxk::launch_step_a_tiles(s->stream, &s->tev, s->desc, s->tiles, s->n_tiles,
-                                              kTileBlk, 1)
+                                              kTileBlk, 1, par)
                    : mxk::launch_kick_jump_drift(s);
     case MX_K_FLAG: return small ? hipSuccess : mxk::launch_flag(s);
     case MX_K_PLAN:  // the fused path plans inside the encounter integrator
       return s->nb > 0 && !small ? mxk::launch_plan_sys(s->stream, &s->tev, s->desc, 1)
                                  : hipSuccess;
     case MX_K_BS:
-      return s->nb > 0 ? mxk::launch_bs_sys(s->stream, &s->tev, s->desc, 1, kBsBlocks, small)
+      return s->nb > 0 ? mxk::launch_bs_sys(s->stream, &s->tev, s->desc, 1, kBsBlocks, small, par)
                        : hipSuccess;
     case MX_K_JUMP_PACK: return small ? hipSuccess : mxk::launch_jump_pack(s);
     default:
       return small ? mxk::launch_step_b_tiles(s->stream, &s->tev, s->desc, s->tiles, s->n_tiles,
-                                              kTileBlk, 1, 1)
+                                              kTileBlk, 1, 1, par)
                    : mxk::launch_force_kick(s, 1);
   }
 }
@@ -148,6 +149,32 @@ hipError_t enqueue_step(mx_system* s) {
   for (int k = 0; k < MX_NUM_KERNELS; ++k) {
     hipError_t e = launch_group(s, k);
     if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// n steps launched eagerly.  On the fused path without growth the closing kernel
+// of a step and the opening kernel of the next one run as one launch
+// (k_step_ba), the same operations per body.  visit(k, q) runs before the launch
+// of group k of step q (the joined launch is visited as the closing group of its
+// first step) and after(k, q) right after it.
+template <class Visit, class After>
+hipError_t enqueue_steps(mx_system* s, int32_t n, bool join, Visit visit, After after) {
+  join = join && n >= 2 && s->nb <= kSmallBig && !s->has_growth;
+  for (int32_t q = 0; q < n; ++q) {
+    const int par = join ? (q & 1) : 0;  // step parity (buffers alternate between joined steps)
+    for (int k = 0; k < MX_NUM_KERNELS; ++k) {
+      if (join && q > 0 && (k == MX_K_GROWTH || k == MX_K_KICK_JUMP_DRIFT)) continue;
+      visit(k, q);
+      hipError_t e;
+      if (join && q < n - 1 && k == MX_K_FORCE_KICK)
+        e = mxk::launch_step_ba_tiles(s->stream, &s->tev, s->desc, s->tiles, s->n_tiles,
+                                      kTileBlk, 1, par);
+      else
+        e = launch_group(s, k, par);
+      after(k, q);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
@@ -238,7 +265,7 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   ALLOC(s->x, n3) ALLOC(s->u, n3) ALLOC(s->ag, n3) ALLOC(s->x0, n3) ALLOC(s->u0, n3)
   ALLOC(s->mu, nb) ALLOC(s->rcrit, nb) ALLOC(s->mu_init, nb) ALLOC(s->rcrit_init, nb)
   ALLOC(s->growth, 3 * (size_t)nb) ALLOC(s->r_p, s->ns) ALLOC(s->rho_p, s->ns)
-  ALLOC(s->bigsnap, 9 * (size_t)nb) ALLOC(s->bigmid, 6 * (size_t)nb)
+  ALLOC(s->bigsnap, 9 * (size_t)nb) ALLOC(s->bigmid, 12 * (size_t)nb)
   ALLOC(s->kpack, mxk::kick_source_count(nb)) ALLOC(s->fpack, nb)
   ALLOC(s->part, s->use_sym && s->ns > 0 ? (size_t)s->split * n3 : 1)
   {
@@ -329,9 +356,11 @@ mx_status mx_step(mx_system* s, int32_t n_steps) {
     if (e != hipSuccess) return hip_fail(e, "graph instantiate");
     s->graph_ok = true;
   }
-  for (int32_t k = 0; k < n_steps; ++k) {
-    if (use_graph) HIPCHK(hipGraphLaunch(s->graph, s->stream), "graph launch");
-    else HIPCHK(enqueue_step(s), "step launch");
+  if (use_graph) {
+    for (int32_t k = 0; k < n_steps; ++k)
+      HIPCHK(hipGraphLaunch(s->graph, s->stream), "graph launch");
+  } else {
+    HIPCHK(enqueue_steps(s, n_steps, true, [](int, int) {}, [](int, int) {}), "step launch");
   }
   s->host_step += n_steps;
   return MX_OK;
@@ -393,21 +422,25 @@ mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, float* ker
   }
   hipEvent_t* ev = s->tev_pool;
   std::vector<char> used(n_steps, 0);
-  for (int32_t q = 0; q < n_steps && e == hipSuccess; ++q) {
-    for (int k = 0; k < MX_NUM_KERNELS && e == hipSuccess; ++k) {
-      if (k == group) {
-        s->tev.armed = true;
-        s->tev.start = ev[2 * q];
-        s->tev.stop = ev[2 * q + 1];
-      }
-      e = launch_group(s, k);
-      if (k == group) {
-        used[q] = s->tev.start == nullptr;  // the start event went to a kernel
-        s->tev.armed = false;
-        s->tev.start = s->tev.stop = nullptr;
-      }
-    }
-  }
+  // the joined launch spans two steps: it is used unless the timed group is one
+  // of the two kernels it joins
+  const bool join = group != MX_K_KICK_JUMP_DRIFT && group != MX_K_FORCE_KICK;
+  e = enqueue_steps(
+      s, n_steps, join,
+      [&](int k, int q) {
+        if (k == group) {
+          s->tev.armed = true;
+          s->tev.start = ev[2 * q];
+          s->tev.stop = ev[2 * q + 1];
+        }
+      },
+      [&](int k, int q) {
+        if (k == group) {
+          used[q] = s->tev.start == nullptr;  // the start event went to a kernel
+          s->tev.armed = false;
+          s->tev.start = s->tev.stop = nullptr;
+        }
+      });
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   int32_t nl = 0;
   for (int32_t q = 0; q < n_steps; ++q) {
@@ -670,16 +703,26 @@ hipError_t upload_tiles(mx_batch* b) {
   return hipMemcpy(b->tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice);
 }
 
-hipError_t enqueue_batch_step(mx_batch* b) {
-  hipError_t e;
-  if ((e = mxk::launch_step_a_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles, b->blk,
-                                    b->tpb)) != hipSuccess)
-    return e;
-  // (the encounter integrator plans its subsystems itself: every system has n_big <= 64)
-  if ((e = mxk::launch_bs_sys(b->stream, &b->tev, b->desc, b->n_sys, b->bps, 1)) != hipSuccess)
-    return e;
-  return mxk::launch_step_b_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles, b->blk,
-                                  b->tpb, 1);
+// n batch steps; between two steps the closing and opening kernels are one launch
+// (k_step_ba), the same operations per body
+hipError_t enqueue_batch_steps(mx_batch* b, int32_t n) {
+  hipError_t e = hipSuccess;
+  for (int32_t q = 0; q < n && e == hipSuccess; ++q) {
+    const int par = q & 1;  // step parity (buffers alternate between joined steps)
+    if (q == 0)
+      e = mxk::launch_step_a_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles, b->blk,
+                                   b->tpb, 0);
+    if (e == hipSuccess)
+      e = mxk::launch_bs_sys(b->stream, &b->tev, b->desc, b->n_sys, b->bps, 1, par);
+    if (e != hipSuccess) break;
+    if (q < n - 1)
+      e = mxk::launch_step_ba_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles, b->blk,
+                                    b->tpb, par);
+    else
+      e = mxk::launch_step_b_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles, b->blk,
+                                   b->tpb, 1, par);
+  }
+  return e;
 }
 
 void drop_graph(mx_batch* b) {
@@ -862,7 +905,7 @@ mx_status mx_step_batch(mx_batch* b, int32_t n_steps) {
       hipGraph_t g;
       HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
       hipError_t e = hipSuccess;
-      for (int q = 0; q < b->graph_steps && e == hipSuccess; ++q) e = enqueue_batch_step(b);
+      e = enqueue_batch_steps(b, b->graph_steps);
       hipError_t e2 = hipStreamEndCapture(b->stream, &g);
       if (e != hipSuccess) return hip_fail(e, "capture batch step");
       if (e2 != hipSuccess) return hip_fail(e2, "end capture");
@@ -874,7 +917,7 @@ mx_status mx_step_batch(mx_batch* b, int32_t n_steps) {
     for (; done + b->graph_steps <= n_steps; done += b->graph_steps)
       HIPCHK(hipGraphLaunch(b->graph, b->stream), "graph launch");
   }
-  for (; done < n_steps; ++done) HIPCHK(enqueue_batch_step(b), "batch step launch");
+  if (done < n_steps) HIPCHK(enqueue_batch_steps(b, n_steps - done), "batch step launch");
   advance_host_steps(b, n_steps);
   return MX_OK;
 }
@@ -895,7 +938,7 @@ mx_status mx_batch_autotune(mx_batch* b, int32_t steps_per_candidate, int32_t* s
     mx_status st = mx_batch_set_config(b, blk, tpb, bps);
     if (st != MX_OK) return st;
     HIPCHK(hipEventRecord(e0, b->stream), "record");
-    for (int q = 0; q < steps_per_candidate; ++q) HIPCHK(enqueue_batch_step(b), "trial step");
+    HIPCHK(enqueue_batch_steps(b, steps_per_candidate), "trial step");
     HIPCHK(hipEventRecord(e1, b->stream), "record");
     HIPCHK(hipEventSynchronize(e1), "sync");
     HIPCHK(hipEventElapsedTime(ms, e0, e1), "elapsed");

@@ -56,8 +56,14 @@ struct DevScalars {
   unsigned long long bs_flop;        // cumulative model FP64 ops of the encounter integrator
   unsigned long long pairs_flagged;  // cumulative flagged pairs
   int32_t plan_ready;    // set when the in-kernel general plan of this step is written
-  int32_t pad0;
+  int32_t n_pairs_alt;   // second append counter: steps joined in one launch alternate
+  int32_t pad0[2];
 };
+
+// Append counter of the flagged list for step parity w (0 outside joined launches).
+__host__ __device__ inline int32_t* pair_counter(DevScalars* d, int w) {
+  return w ? &d->n_pairs_alt : &d->n_pairs;
+}
 
 namespace mxd {
 // Gas-disk constants of a parameter set in the units of the drag formula.
@@ -95,7 +101,7 @@ struct SysDesc {
   double *x, *u, *ag, *x0, *u0;
   const double *mu, *rcrit;         // [nb]
   const double *r_p, *rho_p;        // [n - nb]
-  double *bigsnap, *bigmid;         // [9][nb], [6][nb]
+  double *bigsnap, *bigmid;         // [9][nb], [2][6][nb] (by step parity)
   int32_t* pairs;                   // [cap_pairs][2]
   int64_t* keys;                    // planner scratch [2 * cap_pairs]
   int32_t* plan_idx;                // planner scratch [2 * cap_pairs]
@@ -232,14 +238,21 @@ hipError_t launch_reset_scalars(mx_system* s, int64_t step);
 // fused small-B kernels over a tile table (n_big <= kSmallBig in every system);
 // blk bodies per tile (64, 128, 256 or 512), tpb consecutive tiles per block
 hipError_t launch_step_a_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
-                               const Tile* tiles, int n_tiles, int blk, int tpb);
+                               const Tile* tiles, int n_tiles, int blk, int tpb, int par);
 hipError_t launch_step_b_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
-                               const Tile* tiles, int n_tiles, int blk, int tpb, int kick);
+                               const Tile* tiles, int n_tiles, int blk, int tpb, int kick,
+                               int par);
+// k_step_b (with kick) of one step joined with k_step_a of the next.  par: the
+// step parity (0 outside joined sequences): selects the bigmid buffer and the
+// append counter of the flagged list; the joined kernel reads parity par and
+// writes par ^ 1.
+hipError_t launch_step_ba_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
+                                const Tile* tiles, int n_tiles, int blk, int tpb, int par);
 // planner (one block per system) and encounter integrator (bps blocks per system;
 // plan != 0: the integrator plans its subsystems itself, systems of n_big <= 64)
 hipError_t launch_plan_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys);
 hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys,
-                         int bps, int plan);
+                         int bps, int plan, int par);
 
 // stateless single-kernel launchers
 hipError_t gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,

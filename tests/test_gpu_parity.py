@@ -280,6 +280,26 @@ def test_bitwise_deterministic_and_resumable(mx):
     assert a.step_index() == 20 and c.step_index() == 20
 
 
+def test_joined_steps_equal_single_steps(mx):
+    """A multi-step call joins the closing kernel of each step with the opening
+    kernel of the next (one launch) and alternates the massive-body and list
+    buffers between steps: the states, the last step's encounter list and the
+    step count must equal those of one-step calls, bit for bit."""
+    w = ic.embryo_disk(seed=7, n_small=3000, n_emb=6)
+    a = mx.System.from_workload(w)
+    b = mx.System.from_workload(w)
+    a.step(9)
+    for _ in range(9):
+        b.step(1)
+    xa, ua = a.get_dh()
+    xb, ub = b.get_dh()
+    assert np.array_equal(xa, xb) and np.array_equal(ua, ub)
+    assert np.array_equal(a.encounters(), b.encounters())
+    assert a.step_index() == b.step_index() == 9
+    assert a.energy()[0] == b.energy()[0]
+    assert a.counters() == b.counters()
+
+
 @pytest.mark.parametrize("name,kw,group", [
     ("embryo_disk", dict(seed=2, n_small=3000, n_emb=8), "bs"),
     ("self_gravitating", dict(seed=1, n_pl=4, n_pls=600), "force_kick"),
