@@ -60,6 +60,61 @@ __device__ __forceinline__ bool advance_body(int t, int nb, double mu0, double h
 // tid < nb enters with massive body tid (p, v, a, mass m) already loaded from the
 // step-start snapshot.  Returns the momentum terms through Ppre = P_pre / mu0 and
 // Ppost = (h/2) P_post / mu0.  `first` latches a failure once per system.
+// Momentum terms of the massive bodies for the opening half of a step: lane
+// k < nb of the first wave holds massive body k (velocity v, acceleration a,
+// mass m); the sums of m v and m (v + h/2 a) go to sh[0..5] by the fixed lane
+// reduction (the same bits in every block).  Called by the whole first wave.
+__device__ __forceinline__ void big_sums_a(const SysDesc& D, int lane, double* sh,
+                                           const double (&v)[3], const double (&a)[3],
+                                           double m) {
+  const int nb = D.nb;
+  const double hh = 0.5 * D.h;
+  double t[6];
+  for (int c = 0; c < 3; ++c) {
+    t[c] = lane < nb ? m * v[c] : 0.0;
+    t[3 + c] = lane < nb ? m * (v[c] + hh * a[c]) : 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) t[c] = mxd::wave_sum_fixed(t[c]);
+  if (lane == 0)
+    for (int c = 0; c < 6; ++c) sh[c] = t[c];
+}
+
+// Ppre = P_pre / mu0 and Ppost = (h/2) P_post / mu0 from the sums in sh.
+__device__ __forceinline__ void big_frame_a(const SysDesc& D, const double* sh,
+                                            double (&Ppre)[3], double (&Ppost)[3]) {
+  const double hh = 0.5 * D.h;
+  for (int c = 0; c < 3; ++c) {
+    Ppre[c] = sh[c] / D.mu0;
+    Ppost[c] = hh * sh[3 + c] / D.mu0;
+  }
+}
+
+// Half kick, jump and drift of massive body k (identical arithmetic in every
+// block), kept in LDS: bst rows x0 (3) u0 (3) x1 (3) u1 (3), brc its changeover
+// radius rc.  `first` latches a failure once per system.
+__device__ __forceinline__ void big_advance_a(const SysDesc& D, bool first, int k,
+                                              double (*bst)[kSmallBig], double* brc,
+                                              double (&p)[3], double (&v)[3],
+                                              const double (&a)[3], double rc,
+                                              const double (&Ppre)[3], const double (&Ppost)[3]) {
+  const int nb = D.nb;
+  double q[3], w[3];
+  bool ok = advance_body(k, nb, D.mu0, D.h, D.dc, D.gas_on, 0.0, 0.0, Ppre, Ppost, p, v, a, q, w);
+  if (!ok && first) atomicOr(&D.dsc->err, MXE_NOCONV);
+  for (int c = 0; c < 3; ++c) {
+    bst[c][k] = p[c];
+    bst[3 + c][k] = v[c];
+    bst[6 + c][k] = q[c];
+    bst[9 + c][k] = w[c];
+  }
+  brc[k] = rc;
+}
+
+// Massive bodies of system D for a block: half kick, jump and drift of every
+// massive body (identical arithmetic in every block), kept in LDS.  Thread
+// tid < nb enters with massive body tid (p, v, a, mass m) already loaded from the
+// step-start snapshot.  Returns the momentum terms through Ppre and Ppost.
 template <int BLK>
 __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double* sh,
                                             double (*bst)[kSmallBig], double* brc,
@@ -67,39 +122,10 @@ __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double
                                             double m, double rc, double (&Ppre)[3],
                                             double (&Ppost)[3]) {
   const int tid = threadIdx.x;
-  const int nb = D.nb;
-  const double hh = 0.5 * D.h;
-  // momentum sums over the massive bodies, one per lane of the first wave, by
-  // the fixed lane reduction (the same bits in every block)
-  if (tid < 64) {
-    double t[6];
-    for (int c = 0; c < 3; ++c) {
-      t[c] = tid < nb ? m * v[c] : 0.0;
-      t[3 + c] = tid < nb ? m * (v[c] + hh * a[c]) : 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) t[c] = mxd::wave_sum_fixed(t[c]);
-    if (tid == 0)
-      for (int c = 0; c < 6; ++c) sh[c] = t[c];
-  }
+  if (tid < 64) big_sums_a(D, tid, sh, v, a, m);
   __syncthreads();
-  for (int c = 0; c < 3; ++c) {
-    Ppre[c] = sh[c] / D.mu0;
-    Ppost[c] = hh * sh[3 + c] / D.mu0;
-  }
-  if (tid < nb) {
-    double q[3], w[3];
-    bool ok = advance_body(tid, nb, D.mu0, D.h, D.dc, D.gas_on, 0.0, 0.0, Ppre, Ppost, p, v, a,
-                           q, w);
-    if (!ok && first) atomicOr(&D.dsc->err, MXE_NOCONV);
-    for (int c = 0; c < 3; ++c) {
-      bst[c][tid] = p[c];
-      bst[3 + c][tid] = v[c];
-      bst[6 + c][tid] = q[c];
-      bst[9 + c][tid] = w[c];
-    }
-    brc[tid] = rc;
-  }
+  big_frame_a(D, sh, Ppre, Ppost);
+  if (tid < D.nb) big_advance_a(D, first, tid, bst, brc, p, v, a, rc, Ppre, Ppost);
 }
 
 // Encounter test of body t (pre-drift p, v; post-drift q, w) against every
@@ -428,7 +454,9 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
 // is not stored.  Step n's massive bodies are read from bigmid buffer par (every
 // block reads them), step n + 1's are written to buffer par ^ 1, and its flagged
 // pairs are counted by the append counter of parity par ^ 1: no block overwrites
-// what another may still read.
+// what another may still read.  (A variant that gave the massive bodies a wave
+// of their own measured slower: at this kernel's register use a CU holds only
+// one five-wave block.)
 template <int BLK>
 __global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ desc,
                                                  const Tile* __restrict__ tiles, int n_tiles,
@@ -438,19 +466,23 @@ __global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ des
   __shared__ double bst[12][kSmallBig];
   __shared__ double brc[kSmallBig];
   const int tid = threadIdx.x;
+  const bool w0 = tid < 64;  // the first wave holds the massive bodies
   const int t_lo = blockIdx.x * tpb;
   const int t_hi = min(n_tiles, t_lo + tpb);
   int cur = -1;
   double J[3], vpre[3], Ppre[3], Ppost[3];
+  // the massive body of this lane of the first wave, carried from the closing to
+  // the opening phase of a fresh tile
+  double bpos[3], bvel[3], bacc[3], bm = 0.0, brc_t = 0.0;
   for (int ti = t_lo; ti < t_hi; ++ti) {
     const Tile tl = tiles[ti];
     const SysDesc& D = desc[tl.sys];
     const int n = D.n, nb = D.nb;
     const double h = D.h, hh = 0.5 * D.h, mu0 = D.mu0;
     const int t = tl.first + tid;
+    const bool mine = t < n;
     const bool fresh = tl.sys != cur;  // block-uniform
     // massive bodies after the encounter integrator, then the body's own state
-    double bpos[3], bvel[3], bacc[3], bm = 0.0, brc_t = 0.0;
     if (fresh && tid < nb) {
       const auto bigmid = gbl(D.bigmid) + (size_t)par * 6 * nb;
       for (int c = 0; c < 3; ++c) {
@@ -461,7 +493,7 @@ __global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ des
       brc_t = gbl(D.rcrit)[tid];
     }
     double p[3], v[3], a[3], q[3], w[3], rp = 0.0, rhop = 0.0;
-    if (t < n && t >= nb) {
+    if (mine && t >= nb) {
       for (int c = 0; c < 3; ++c) {
         p[c] = gbl(D.x)[c * n + t];
         v[c] = gbl(D.u)[c * n + t];
@@ -474,7 +506,7 @@ __global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ des
     if (fresh) {
       __syncthreads();  // the previous tile is done with the LDS copies
       // step n: momentum after the encounter integrator (as k_step_b)
-      if (tid < 64) {
+      if (w0) {
         double Q[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) Q[c] = mxd::wave_sum_fixed(tid < nb ? bm * bvel[c] : 0.0);
@@ -507,19 +539,33 @@ __global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ des
         D.dsc->step += 1;
         D.dsc->plan_ready = 0;
       }
-      // step n closed for the massive bodies, then step n + 1 opened for them
-      if (tid < nb) {
-        close_body(tid, nb, src, src[tid].rc, J, vpre, hh, D.dc, D.gas_on, 0.0, 0.0, true, bpos,
-                   bvel, bacc);
-        if (tl.first == 0 &&
-            !isfinite(bvel[0] + bvel[1] + bvel[2] + bpos[0] + bpos[1] + bpos[2]))
-          atomicOr(&D.dsc->err, MXE_NONFINITE);
+      // step n closed for the massive bodies; the momentum terms of step n + 1
+      if (w0) {
+        if (tid < nb) {
+          close_body(tid, nb, src, src[tid].rc, J, vpre, hh, D.dc, D.gas_on, 0.0, 0.0, true,
+                     bpos, bvel, bacc);
+          if (tl.first == 0 &&
+              !isfinite(bvel[0] + bvel[1] + bvel[2] + bpos[0] + bpos[1] + bpos[2]))
+            atomicOr(&D.dsc->err, MXE_NONFINITE);
+        }
+        big_sums_a(D, tid, sh, bvel, bacc, bm);
       }
-      big_phase_a<BLK>(D, tl.first == 0, sh, bst, brc, bpos, bvel, bacc, bm, brc_t, Ppre, Ppost);
       __syncthreads();
+      big_frame_a(D, sh, Ppre, Ppost);
       cur = tl.sys;
+      // step n + 1 opened for the massive bodies
+      if (tid < nb) big_advance_a(D, tl.first == 0, tid, bst, brc, bpos, bvel, bacc, brc_t, Ppre, Ppost);
     }
-    if (t < n) {
+    // step n closed and step n + 1 opened for the body
+    if (mine && t >= nb) {
+      close_body(t, nb, src, 0.0, J, vpre, hh, D.dc, D.gas_on, rp, rhop, true, p, v, a);
+      if (!isfinite(v[0] + v[1] + v[2] + p[0] + p[1] + p[2]))
+        atomicOr(&D.dsc->err, MXE_NONFINITE);
+      if (!advance_body(t, nb, mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v, a, q, w))
+        atomicOr(&D.dsc->err, MXE_NOCONV);
+    }
+    __syncthreads();  // the massive bodies of step n + 1 are in LDS
+    if (mine) {
       if (t < nb) {
         for (int c = 0; c < 3; ++c) {
           p[c] = bst[c][t];
@@ -533,12 +579,6 @@ __global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ des
           bigmid[c * nb + t] = q[c];
           bigmid[(3 + c) * nb + t] = w[c];
         }
-      } else {
-        close_body(t, nb, src, 0.0, J, vpre, hh, D.dc, D.gas_on, rp, rhop, true, p, v, a);
-        if (!isfinite(v[0] + v[1] + v[2] + p[0] + p[1] + p[2]))
-          atomicOr(&D.dsc->err, MXE_NONFINITE);
-        if (!advance_body(t, nb, mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v, a, q, w))
-          atomicOr(&D.dsc->err, MXE_NOCONV);
       }
       for (int c = 0; c < 3; ++c) {
         gbl(D.x)[c * n + t] = q[c];
@@ -571,7 +611,8 @@ hipError_t launch_step_ba_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc*
   if (n_tiles <= 0) return hipSuccess;
   const dim3 grid((n_tiles + tpb - 1) / tpb);
   switch (blk) {
-    case 64: return mxlaunch_on(st, tm, k_step_ba<64>, grid, dim3(64), desc, tiles, n_tiles, tpb, par);
+    case 64:
+      return mxlaunch_on(st, tm, k_step_ba<64>, grid, dim3(64), desc, tiles, n_tiles, tpb, par);
     case 128:
       return mxlaunch_on(st, tm, k_step_ba<128>, grid, dim3(128), desc, tiles, n_tiles, tpb, par);
     case 256:
