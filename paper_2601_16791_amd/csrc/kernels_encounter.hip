@@ -173,14 +173,17 @@ __device__ bool insert_sorted(int32_t* v, int& m, int cap, int b) {
 // ---- single-wave planner for short lists of massless encounters
 // Sort of np distinct keys in[0, np) into out by rank: the rank of a key is the
 // number of smaller keys, counted against every key read as a wave-uniform LDS
-// broadcast.  One wave; its LDS accesses complete in order.
+// broadcast, 32 reads in flight per round.  in[np, np rounded up to 32) must
+// hold key_max (never smaller than a key), so every round is whole; np <= 256.
+// One wave; its LDS accesses complete in order.
 __device__ __forceinline__ int64_t key_max(int64_t) { return INT64_MAX; }
 __device__ __forceinline__ uint32_t key_max(uint32_t) { return 0xffffffffu; }
 
 template <class K>
 __device__ __forceinline__ void wave_rank_sort(const K* in, K* out, int np) {
   const int lane = threadIdx.x & 63;
-  const int nr = (np + 63) >> 6;  // key slots in use per lane (np <= 256)
+  const int nr = (np + 63) >> 6;  // key slots in use per lane
+  const int np32 = (np + 31) & ~31;
   K key[4];
   int rank[4];
 #pragma unroll
@@ -189,32 +192,33 @@ __device__ __forceinline__ void wave_rank_sort(const K* in, K* out, int np) {
     key[r] = e < np ? in[e] : key_max(K());
     rank[r] = 0;
   }
-  // sixteen broadcast reads in flight per round
-  int f = 0;
-  for (; f + 16 <= np; f += 16) {
-    K kk[16];
+  for (int f = 0; f < np32; f += 32) {
+    K kk[32];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) kk[q] = in[f + q];
+    for (int q = 0; q < 32; ++q) kk[q] = in[f + q];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       if (r < nr) {
         int c = 0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) c += kk[q] < key[r];
+        for (int q = 0; q < 32; ++q) c += kk[q] < key[r];
         rank[r] += c;
       }
     }
-  }
-  for (; f < np; ++f) {
-    const K k0 = in[f];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) rank[r] += k0 < key[r];
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     if (64 * r + lane < np) out[rank[r]] = key[r];
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+}
+
+// key_max into in[np, np rounded up to 32): the padding wave_rank_sort reads
+template <class K>
+__device__ __forceinline__ void pad_keys(K* in, int np) {
+  const int lane = threadIdx.x & 63;
+  const int e = np + lane;
+  if (e < ((np + 31) & ~31)) in[e] = key_max(K());
 }
 
 constexpr int kPlanThreads = 256;
@@ -431,6 +435,7 @@ __device__ __forceinline__ void plan_block(int n, int nb, int32_t* __restrict__ 
         uint32_t* kb = ka + 256;
         for (int e = lane; e < np; e += 64)
           ka[e] = ((uint32_t)gpairs[2 * e + 1] << 6) | (uint32_t)gpairs[2 * e];
+        pad_keys(ka, np);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         wave_rank_sort(ka, kb, np);
@@ -440,6 +445,7 @@ __device__ __forceinline__ void plan_block(int n, int nb, int32_t* __restrict__ 
         }
       } else {
         for (int e = lane; e < np; e += 64) ls[e] = make_key(gpairs[2 * e], gpairs[2 * e + 1]);
+        pad_keys(ls, np);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         wave_rank_sort(ls, lk, np);  // (i, j) order
@@ -450,6 +456,7 @@ __device__ __forceinline__ void plan_block(int n, int nb, int32_t* __restrict__ 
         if (sort_only) return;
         // regroup by massless body j: keys (j, i)
         for (int e = lane; e < np; e += 64) lk[256 + e] = make_key(key_lo(lk[e]), key_hi(lk[e]));
+        pad_keys(lk + 256, np);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         wave_rank_sort(lk + 256, ls, np);
@@ -1078,12 +1085,23 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
     nsub = dsc->n_sub;
   } else {
     const bool b0 = blockIdx.x == 0;
+    const int cap_pairs = D.cap_pairs, cap_subs = D.cap_subs;
+    const bool ordered = D.bs_sched != nullptr;
+    const auto gpairs = gbl(D.pairs);
+    // the first 256 entries of the list are requested with its length (entries
+    // past the length are not used)
+    int32_t pre_i[4], pre_j[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = 64 * r + lane;
+      pre_i[r] = e < cap_pairs ? gpairs[2 * e] : 0;
+      pre_j[r] = e < cap_pairs ? gpairs[2 * e + 1] : 0;
+    }
     const int n_pairs = *pair_counter(dsc, par);
     // the other counter takes the next step's appends when steps are joined in
     // one launch; nothing reads or appends to it while this kernel runs
     if (b0 && lane == 0) *pair_counter(dsc, par ^ 1) = 0;
-    const int np = min(n_pairs, D.cap_pairs);
-    const auto gpairs = gbl(D.pairs);
+    const int np = min(n_pairs, cap_pairs);
     if (b0 && lane == 0) {
       dsc->n_pairs_last = n_pairs;
       dsc->pairs_flagged += (unsigned long long)n_pairs;
@@ -1093,17 +1111,32 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
       fast = np <= 256 && nb <= 64 && n < (1 << 26);
       if (fast) {
         bool bb = false;
-        for (int e = lane; e < np; e += 64) {
-          const int i = gpairs[2 * e], j = gpairs[2 * e + 1];
-          bb |= j < nb;
-          F.ka[e] = ((uint32_t)j << 6) | (uint32_t)i;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = 64 * r + lane;
+          if (e < np) {
+            bb |= pre_j[r] < nb;
+            F.ka[e] = ((uint32_t)pre_j[r] << 6) | (uint32_t)pre_i[r];
+          }
         }
         fast = __builtin_amdgcn_ballot_w64(bb) == 0;
       }
       if (fast) {
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        wave_rank_sort(F.ka, F.kb, np);
+        // The fused step appends each body's pairs as one run in increasing i, so
+        // the runs of equal j are the subsystems.  Their numbering only decides
+        // which block integrates which subsystem, except for the tape the adjoint
+        // records (bs_sched set): that needs the table in order of j, so the list
+        // is sorted first.
+        if (ordered) {
+          pad_keys(F.ka, np);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          wave_rank_sort(F.ka, F.kb, np);
+        } else {
+          for (int e = lane; e < np; e += 64) F.kb[e] = F.ka[e];
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+        }
         // group starts, numbered in list order
         int base = 0;
         for (int r = 0; r < (np + 63) / 64; ++r) {
@@ -1117,12 +1150,12 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
         if (lane == 0) F.gs[base] = np;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        nsub = min(base, D.cap_subs);
+        nsub = min(base, cap_subs);
         if (b0) {
           // the table for the readers after the step (same records as the
           // planning kernel writes)
           for (int g = lane; g < base; g += 64) {
-            if (g >= D.cap_subs) {
+            if (g >= cap_subs) {
               atomicOr(&dsc->err, MXE_SUBSYS);
               continue;
             }
@@ -1150,8 +1183,8 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
         }
       } else {
         if (b0) {
-          plan_general(nb, gpairs, np, D.keys, D.keys + D.cap_pairs, D.plan_idx,
-                       D.plan_idx + D.cap_pairs, D.uf, D.subs, D.cap_subs, dsc, 0, s_scan, &s_nbig);
+          plan_general(nb, gpairs, np, D.keys, D.keys + cap_pairs, D.plan_idx,
+                       D.plan_idx + cap_pairs, D.uf, D.subs, cap_subs, dsc, 0, s_scan, &s_nbig);
           __syncthreads();
           if (lane == 0) {
             s_nsub = dsc->n_sub;

@@ -162,7 +162,7 @@ __device__ __forceinline__ void flag_body(const SysDesc& D, int par, int t, int 
     double bound = rc + 1.7320508075688773 * fma(k427, nw, nd) * (1.0 + 1e-12);
     if (__builtin_expect(m0 <= bound * bound * (1.0 + 1e-12), 0)) cmask |= 1ull << i;
   }
-  bool hit = false;
+  uint64_t hmask = 0;
   while (cmask != 0) {
     const int i = __builtin_ctzll(cmask);
     cmask &= cmask - 1;
@@ -176,11 +176,16 @@ __device__ __forceinline__ void flag_body(const SysDesc& D, int par, int t, int 
     const double rc = fmax(brc[i], rct);
     double dmin = mxd::hermite_dmin2(r0[0], r0[1], r0[2], w0[0], w0[1], w0[2], r1[0], r1[1],
                                      r1[2], w1[0], w1[1], w1[2], h);
-    if (dmin <= rc * rc) {
-      hit = true;
-      int idx = atomicAdd(pair_counter(D.dsc, par), 1);
+    if (dmin <= rc * rc) hmask |= 1ull << i;
+  }
+  // the body's pairs are appended together, in increasing i: the list holds each
+  // body's partners as one ordered run
+  const bool hit = hmask != 0;
+  if (hit) {
+    int idx = atomicAdd(pair_counter(D.dsc, par), __popcll(hmask));
+    for (; hmask != 0; hmask &= hmask - 1, ++idx) {
       if (idx < D.cap_pairs) {
-        gbl(D.pairs)[2 * idx] = i;
+        gbl(D.pairs)[2 * idx] = __builtin_ctzll(hmask);
         gbl(D.pairs)[2 * idx + 1] = t;
       } else {
         atomicOr(&D.dsc->err, MXE_PAIRS);
