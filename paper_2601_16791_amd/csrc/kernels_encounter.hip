@@ -23,6 +23,7 @@
 
 #include "device_math.h"
 #include "mx_internal.h"
+#include "step_common.h"
 
 namespace {
 
@@ -1081,6 +1082,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
   const double tol2 = tol * tol;
   int nsub = 0;
   bool fast = false;
+  bool bigs_kept = true;  // false: no subsystem of this step changes a massive body
   if (!plan) {
     nsub = dsc->n_sub;
   } else {
@@ -1107,6 +1109,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
       dsc->pairs_flagged += (unsigned long long)n_pairs;
       if (np == 0) dsc->n_sub = 0;
     }
+    bigs_kept = np > 0;
     if (np > 0) {
       fast = np <= 256 && nb <= 64 && n < (1 << 26);
       if (fast) {
@@ -1122,6 +1125,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
         fast = __builtin_amdgcn_ballot_w64(bb) == 0;
       }
       if (fast) {
+        bigs_kept = false;  // massless subsystems keep only their massless member
         // The fused step appends each body's pairs as one run in increasing i, so
         // the runs of equal j are the subsystems.  Their numbering only decides
         // which block integrates which subsystem, except for the tape the adjoint
@@ -1206,6 +1210,47 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
         __syncthreads();
         nsub = s_nsub;
       }
+    }
+  }
+  // The system's last block, when it has no subsystem and the subsystems leave
+  // the massive bodies as they are, prepares the massive bodies of the joined
+  // step boundary that follows (the same arithmetic as the joined step kernel,
+  // which then copies them instead of computing them in every block).
+  if (plan && blockIdx.x == gridDim.x - 1) {
+    if (!bigs_kept && nsub < (int)gridDim.x) {
+      __shared__ double b_sh[8];
+      __shared__ KickSource b_src[kSmallBig];
+      __shared__ double b_bst[12][kSmallBig];
+      __shared__ double b_brc[kSmallBig];
+      double bpos[3], bvel[3], bm = 0.0, brc_t = 0.0, P[3], J[3], vpre[3], Ppre[3], Ppost[3];
+      if (lane < nb) {
+        for (int c = 0; c < 3; ++c) {
+          bpos[c] = bigmid[c * nb + lane];
+          bvel[c] = bigmid[(3 + c) * nb + lane];
+        }
+        bm = mu[lane];
+        brc_t = rcrit[lane];
+      }
+      mxs::big_boundary(D, true, b_sh, b_src, b_bst, b_brc, bpos, bvel, bm, brc_t, P, J, vpre,
+                        Ppre, Ppost);
+      __syncthreads();
+      BigNext* N = D.bignext + par;
+      if (lane == 0) {
+        for (int c = 0; c < 3; ++c) {
+          N->P[c] = P[c];
+          N->J[c] = J[c];
+          N->vpre[c] = vpre[c];
+          N->Ppre[c] = Ppre[c];
+          N->Ppost[c] = Ppost[c];
+        }
+      }
+      for (int i = lane; i < 8 * nb; i += 64)
+        reinterpret_cast<double*>(N->src)[i] = reinterpret_cast<const double*>(b_src)[i];
+      for (int i = lane; i < 12 * nb; i += 64) N->bst[i / nb][i % nb] = b_bst[i / nb][i % nb];
+      for (int i = lane; i < nb; i += 64) N->brc[i] = b_brc[i];
+      if (lane == 0) dsc->bn_valid[par] = 1;
+    } else if (lane == 0) {
+      dsc->bn_valid[par] = 0;
     }
   }
   for (int b = blockIdx.x; b < nsub; b += gridDim.x) {

@@ -25,91 +25,12 @@
 #include "device_math.h"
 #include "force_sum.h"
 #include "mx_internal.h"
+#include "step_common.h"
 
 namespace {
 
 using mxd::DragConst;
-
-// half kick (with drag for massless bodies, in the frame shifted by Ppre/mu0),
-// jump by Ppost/mu0, Kepler drift.  On entry (p, v, a) is the step-start state;
-// on exit (p, v) is the pre-drift state and (q, w) the post-drift state.
-__device__ __forceinline__ bool advance_body(int t, int nb, double mu0, double h,
-                                             const DragConst& dc, int gas_on, double rp,
-                                             double rhop, const double* vpre,
-                                             const double* jpost, double (&p)[3], double (&v)[3],
-                                             const double (&a)[3], double (&q)[3],
-                                             double (&w)[3]) {
-  // vpre = Ppre / mu0 (frame velocity of the drag), jpost = (h/2) Ppost / mu0 (jump);
-  // rp, rhop: radius and density of a massless body (unused for massive ones)
-  const double hh = 0.5 * h;
-  double ad[3] = {0.0, 0.0, 0.0};
-  if (t >= nb && gas_on)
-    mxd::gas_drag(dc, p[0], p[1], v[0] + vpre[0], v[1] + vpre[1], v[2] + vpre[2], rp, rhop,
-                  ad[0], ad[1], ad[2]);
-  for (int c = 0; c < 3; ++c) {
-    v[c] += hh * (a[c] + ad[c]);
-    p[c] += jpost[c];
-    q[c] = p[c];
-    w[c] = v[c];
-  }
-  return mxd::kepler_drift(mu0, h, q[0], q[1], q[2], w[0], w[1], w[2]);
-}
-
-// Massive bodies of system D for a block: half kick, jump and drift of every
-// massive body (identical arithmetic in every block), kept in LDS.  Thread
-// tid < nb enters with massive body tid (p, v, a, mass m) already loaded from the
-// step-start snapshot.  Returns the momentum terms through Ppre = P_pre / mu0 and
-// Ppost = (h/2) P_post / mu0.  `first` latches a failure once per system.
-// Momentum terms of the massive bodies for the opening half of a step: lane
-// k < nb of the first wave holds massive body k (velocity v, acceleration a,
-// mass m); the sums of m v and m (v + h/2 a) go to sh[0..5] by the fixed lane
-// reduction (the same bits in every block).  Called by the whole first wave.
-__device__ __forceinline__ void big_sums_a(const SysDesc& D, int lane, double* sh,
-                                           const double (&v)[3], const double (&a)[3],
-                                           double m) {
-  const int nb = D.nb;
-  const double hh = 0.5 * D.h;
-  double t[6];
-  for (int c = 0; c < 3; ++c) {
-    t[c] = lane < nb ? m * v[c] : 0.0;
-    t[3 + c] = lane < nb ? m * (v[c] + hh * a[c]) : 0.0;
-  }
-#pragma unroll
-  for (int c = 0; c < 6; ++c) t[c] = mxd::wave_sum_fixed(t[c]);
-  if (lane == 0)
-    for (int c = 0; c < 6; ++c) sh[c] = t[c];
-}
-
-// Ppre = P_pre / mu0 and Ppost = (h/2) P_post / mu0 from the sums in sh.
-__device__ __forceinline__ void big_frame_a(const SysDesc& D, const double* sh,
-                                            double (&Ppre)[3], double (&Ppost)[3]) {
-  const double hh = 0.5 * D.h;
-  for (int c = 0; c < 3; ++c) {
-    Ppre[c] = sh[c] / D.mu0;
-    Ppost[c] = hh * sh[3 + c] / D.mu0;
-  }
-}
-
-// Half kick, jump and drift of massive body k (identical arithmetic in every
-// block), kept in LDS: bst rows x0 (3) u0 (3) x1 (3) u1 (3), brc its changeover
-// radius rc.  `first` latches a failure once per system.
-__device__ __forceinline__ void big_advance_a(const SysDesc& D, bool first, int k,
-                                              double (*bst)[kSmallBig], double* brc,
-                                              double (&p)[3], double (&v)[3],
-                                              const double (&a)[3], double rc,
-                                              const double (&Ppre)[3], const double (&Ppost)[3]) {
-  const int nb = D.nb;
-  double q[3], w[3];
-  bool ok = advance_body(k, nb, D.mu0, D.h, D.dc, D.gas_on, 0.0, 0.0, Ppre, Ppost, p, v, a, q, w);
-  if (!ok && first) atomicOr(&D.dsc->err, MXE_NOCONV);
-  for (int c = 0; c < 3; ++c) {
-    bst[c][k] = p[c];
-    bst[3 + c][k] = v[c];
-    bst[6 + c][k] = q[c];
-    bst[9 + c][k] = w[c];
-  }
-  brc[k] = rc;
-}
+using namespace mxs;
 
 // Massive bodies of system D for a block: half kick, jump and drift of every
 // massive body (identical arithmetic in every block), kept in LDS.  Thread
@@ -282,49 +203,6 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
   }
 }
 
-// Closing part of a step for one body, from its state after the encounter
-// integrator: jump by J, changeover-weighted gravity of the massive bodies in
-// src (rct: the body's own changeover radius, 0 when massless) and, with kick,
-// the gas drag (massless bodies, frame velocity vpre) and the half kick.
-// pos: in before the jump, out after it; acc: out, the gravity.
-__device__ __forceinline__ void close_body(int t, int nb, const KickSource* src, double rct,
-                                           const double (&J)[3], const double (&vpre)[3],
-                                           double hh, const DragConst& dc, int gas_on, double rp,
-                                           double rhop, bool kick, double (&pos)[3],
-                                           double (&vel)[3], double (&acc)[3]) {
-  const double px = pos[0] + J[0], py = pos[1] + J[1], pz = pos[2] + J[2];
-  const double rc2t = rct * rct;
-  double k15, k1875;
-  mxd::vgpr_constants(k15, k1875);
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-#pragma unroll 4
-  for (int s = 0; s < nb; ++s) {
-    const KickSource S = src[s];
-    double dx = S.x - px, dy = S.y - py, dz = S.z - pz;
-    double s2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    double rc2 = fmax(S.rc2, rc2t);
-    double wgt = mxd::fast_weight(S.mu, s2, k15, k1875);
-    if (s2 < rc2) wgt = S.mu * mxd::changeover_weight_slow(s2, fmax(S.rc, rct), rc2);
-    a0 = fma(wgt, dx, a0);
-    a1 = fma(wgt, dy, a1);
-    a2 = fma(wgt, dz, a2);
-  }
-  pos[0] = px;
-  pos[1] = py;
-  pos[2] = pz;
-  acc[0] = a0;
-  acc[1] = a1;
-  acc[2] = a2;
-  if (!kick) return;
-  double adx = 0.0, ady = 0.0, adz = 0.0;
-  if (t >= nb && gas_on)
-    mxd::gas_drag(dc, px, py, vel[0] + vpre[0], vel[1] + vpre[1], vel[2] + vpre[2], rp, rhop,
-                  adx, ady, adz);
-  vel[0] += hh * (a0 + adx);
-  vel[1] += hh * (a1 + ady);
-  vel[2] += hh * (a2 + adz);
-}
-
 // Second half of the fused step over a tile table: jump by the massive-body
 // momentum after the encounter integrator, changeover-weighted gravity from the
 // massive bodies held in LDS, gas drag and (kick != 0) the closing half kick.
@@ -471,14 +349,12 @@ __global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ des
   __shared__ double bst[12][kSmallBig];
   __shared__ double brc[kSmallBig];
   const int tid = threadIdx.x;
-  const bool w0 = tid < 64;  // the first wave holds the massive bodies
   const int t_lo = blockIdx.x * tpb;
   const int t_hi = min(n_tiles, t_lo + tpb);
   int cur = -1;
   double J[3], vpre[3], Ppre[3], Ppost[3];
-  // the massive body of this lane of the first wave, carried from the closing to
-  // the opening phase of a fresh tile
-  double bpos[3], bvel[3], bacc[3], bm = 0.0, brc_t = 0.0;
+  // the massive body of this lane of the first wave (lane < nb) for a fresh tile
+  double bpos[3], bvel[3], bm = 0.0, brc_t = 0.0;
   for (int ti = t_lo; ti < t_hi; ++ti) {
     const Tile tl = tiles[ti];
     const SysDesc& D = desc[tl.sys];
@@ -509,34 +385,32 @@ __global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ des
       }
     }
     if (fresh) {
-      __syncthreads();  // the previous tile is done with the LDS copies
-      // step n: momentum after the encounter integrator (as k_step_b)
-      if (w0) {
-        double Q[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Q[c] = mxd::wave_sum_fixed(tid < nb ? bm * bvel[c] : 0.0);
-        if (tid == 0)
-          for (int c = 0; c < 3; ++c) sh[c] = Q[c];
-      }
-      __syncthreads();
       double P[3];
-      for (int c = 0; c < 3; ++c) {
-        P[c] = sh[c];
-        J[c] = hh * P[c] / mu0;
-        vpre[c] = P[c] / mu0;
+      // the encounter integrator of step n may have prepared the massive bodies
+      // of this boundary (when it left them unchanged): they are copied into LDS
+      // while the flag that says so is read, and computed here otherwise
+      const BigNext* N = D.bignext + par;
+      const int pre = nb > 0 ? D.dsc->bn_valid[par] : 0;
+      __syncthreads();  // the previous tile is done with the LDS copies
+      if (nb > 0) {
+        for (int i = tid; i < 8 * nb; i += BLK)
+          reinterpret_cast<double*>(src)[i] = reinterpret_cast<const double*>(N->src)[i];
+        for (int i = tid; i < 12 * nb; i += BLK) bst[i / nb][i % nb] = N->bst[i / nb][i % nb];
+        for (int i = tid; i < nb; i += BLK) brc[i] = N->brc[i];
       }
-      if (tid < nb) {
-        KickSource k;
-        k.x = bpos[0] + J[0];
-        k.y = bpos[1] + J[1];
-        k.z = bpos[2] + J[2];
-        k.mu = bm;
-        k.rc2 = fmax(brc_t * brc_t, 1e-300);
-        k.rc = brc_t;
-        k.pad0 = k.pad1 = 0.0;
-        src[tid] = k;
+      if (pre) {
+        for (int c = 0; c < 3; ++c) {
+          P[c] = N->P[c];
+          J[c] = N->J[c];
+          vpre[c] = N->vpre[c];
+          Ppre[c] = N->Ppre[c];
+          Ppost[c] = N->Ppost[c];
+        }
+        __syncthreads();
+      } else {
+        big_boundary(D, tl.first == 0, sh, src, bst, brc, bpos, bvel, bm, brc_t, P, J, vpre, Ppre,
+                     Ppost);
       }
-      __syncthreads();
       if (tl.first == 0 && tid == 0) {
         D.dsc->P[0] = P[0];
         D.dsc->P[1] = P[1];
@@ -544,22 +418,7 @@ __global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ des
         D.dsc->step += 1;
         D.dsc->plan_ready = 0;
       }
-      // step n closed for the massive bodies; the momentum terms of step n + 1
-      if (w0) {
-        if (tid < nb) {
-          close_body(tid, nb, src, src[tid].rc, J, vpre, hh, D.dc, D.gas_on, 0.0, 0.0, true,
-                     bpos, bvel, bacc);
-          if (tl.first == 0 &&
-              !isfinite(bvel[0] + bvel[1] + bvel[2] + bpos[0] + bpos[1] + bpos[2]))
-            atomicOr(&D.dsc->err, MXE_NONFINITE);
-        }
-        big_sums_a(D, tid, sh, bvel, bacc, bm);
-      }
-      __syncthreads();
-      big_frame_a(D, sh, Ppre, Ppost);
       cur = tl.sys;
-      // step n + 1 opened for the massive bodies
-      if (tid < nb) big_advance_a(D, tl.first == 0, tid, bst, brc, bpos, bvel, bacc, brc_t, Ppre, Ppost);
     }
     // step n closed and step n + 1 opened for the body
     if (mine && t >= nb) {

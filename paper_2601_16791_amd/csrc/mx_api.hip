@@ -81,6 +81,7 @@ SysDesc make_desc(const mx_system* s) {
   d.rho_p = s->rho_p;
   d.bigsnap = s->bigsnap;
   d.bigmid = s->bigmid;
+  d.bignext = s->bignext;
   d.pairs = s->pairs;
   d.keys = reinterpret_cast<int64_t*>(s->pairs_tmp);
   d.plan_idx = s->plan_idx;
@@ -110,7 +111,8 @@ void free_system(mx_system* s) {
   for (int32_t k = 0; k < s->tev_pool_n; ++k) (void)hipEventDestroy(s->tev_pool[k]);
   delete[] s->tev_pool;
   void* ptrs[] = {s->x, s->u, s->ag, s->x0, s->u0, s->mu, s->rcrit, s->mu_init, s->rcrit_init,
-                  s->growth, s->r_p, s->rho_p, s->bigsnap, s->bigmid, s->kpack, s->fpack, s->part,
+                  s->growth, s->r_p, s->rho_p, s->bigsnap, s->bigmid, s->bignext, s->kpack,
+                  s->fpack, s->part,
                   s->sympart,
                   s->pairs, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red,
                   s->desc, s->tiles};
@@ -265,7 +267,7 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   ALLOC(s->x, n3) ALLOC(s->u, n3) ALLOC(s->ag, n3) ALLOC(s->x0, n3) ALLOC(s->u0, n3)
   ALLOC(s->mu, nb) ALLOC(s->rcrit, nb) ALLOC(s->mu_init, nb) ALLOC(s->rcrit_init, nb)
   ALLOC(s->growth, 3 * (size_t)nb) ALLOC(s->r_p, s->ns) ALLOC(s->rho_p, s->ns)
-  ALLOC(s->bigsnap, 9 * (size_t)nb) ALLOC(s->bigmid, 12 * (size_t)nb)
+  ALLOC(s->bigsnap, 9 * (size_t)nb) ALLOC(s->bigmid, 12 * (size_t)nb) ALLOC(s->bignext, 2)
   ALLOC(s->kpack, mxk::kick_source_count(nb)) ALLOC(s->fpack, nb)
   ALLOC(s->part, s->use_sym && s->ns > 0 ? (size_t)s->split * n3 : 1)
   {

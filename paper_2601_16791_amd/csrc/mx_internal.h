@@ -57,7 +57,7 @@ struct DevScalars {
   unsigned long long pairs_flagged;  // cumulative flagged pairs
   int32_t plan_ready;    // set when the in-kernel general plan of this step is written
   int32_t n_pairs_alt;   // second append counter: steps joined in one launch alternate
-  int32_t pad0[2];
+  int32_t bn_valid[2];   // BigNext[parity] holds this step boundary's massive bodies
 };
 
 // Append counter of the flagged list for step parity w (0 outside joined launches).
@@ -94,6 +94,16 @@ inline DragConst make_drag_const(const mx_params& p) {
 }
 }  // namespace mxd
 
+// The massive bodies at a joined step boundary (closing step n, opening step
+// n + 1), precomputed by the encounter integrator of step n when it leaves them
+// unchanged; the joined step kernel then reads them instead of computing them.
+struct BigNext {
+  double P[3], J[3], vpre[3], Ppre[3], Ppost[3], pad;
+  KickSource src[kSmallBig];
+  double bst[12][kSmallBig];
+  double brc[kSmallBig];
+};
+
 // Device view of one system for the kernels that step one or many systems per
 // launch (fused small-B step, planner, encounter integrator).  All pointers are
 // device pointers into the system's own allocations; the state is SoA [3][n].
@@ -102,6 +112,7 @@ struct SysDesc {
   const double *mu, *rcrit;         // [nb]
   const double *r_p, *rho_p;        // [n - nb]
   double *bigsnap, *bigmid;         // [9][nb], [2][6][nb] (by step parity)
+  BigNext* bignext;                 // [2] (by step parity)
   int32_t* pairs;                   // [cap_pairs][2]
   int64_t* keys;                    // planner scratch [2 * cap_pairs]
   int32_t* plan_idx;                // planner scratch [2 * cap_pairs]
@@ -161,8 +172,10 @@ struct mx_system {
   // snapshots of the massive bodies, so that a kernel whose every block reads
   // them never sees them half-updated by the block that owns them:
   //   bigsnap [9][nb]: x, u, a at the step start (written at the end of a step)
-  //   bigmid  [6][nb]: x, u after drift and encounter integration (fused path)
+  //   bigmid  [2][6][nb]: x, u after drift and encounter integration (fused path,
+  //           by step parity)
   double *bigsnap, *bigmid;
+  BigNext* bignext;  // [2]: precomputed massive bodies of a joined step boundary
   // massless bodies
   double *r_p, *rho_p;  // rho_p in Msun/AU^3
   // packed sources
