@@ -126,12 +126,16 @@ enum {
 mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms);
 
 /* Runs n_steps steps with eager launches (no graph) and times one kernel group
- * (an MX_K_* value) with HIP events bound to its kernels' own start and end:
- * kernel_ms[q] (host, [n_steps]) is the time from the start of the group's
- * first kernel to the end of its last in step q, 0 where the group launched
- * nothing; *n_launched counts the steps where it launched.  Synchronises. */
-mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, float* kernel_ms,
-                        int32_t* n_launched);
+ * (an MX_K_* value) with HIP events bound to its kernels' own start and end, in
+ * every stride-th step (steps 0, stride, 2 stride, ...; stride >= 1, else
+ * MX_EINVAL): kernel_ms[q] (host, [n_steps]) is the time from the start of the
+ * group's first kernel to the end of its last in step q, 0 where step q was not
+ * timed or the group launched nothing; *n_launched counts the timed steps where
+ * it launched.  An event recorded between two kernels delays the second, so a
+ * stride above 1 keeps the other steps' launches as mx_step issues them.
+ * Synchronises. */
+mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, int32_t stride,
+                        float* kernel_ms, int32_t* n_launched);
 
 /* Cumulative work counters of the system since init: FP64 operations of the
  * encounter integrator (a model count per force evaluation and extrapolation

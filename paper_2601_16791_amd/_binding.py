@@ -68,8 +68,8 @@ def lib():
         L.mx_set_launch_mode.restype = st
         L.mx_set_launch_mode.argtypes = [_P, C.c_int32]
         L.mx_step_timed.restype = st
-        L.mx_step_timed.argtypes = [_P, C.c_int32, C.c_int32, C.POINTER(C.c_float),
-                                    C.POINTER(C.c_int32)]
+        L.mx_step_timed.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32,
+                                    C.POINTER(C.c_float), C.POINTER(C.c_int32)]
         L.mx_get_counters.restype = st
         L.mx_get_counters.argtypes = [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.mx_sync.restype = st
@@ -231,14 +231,14 @@ class System:
         """'eager' (default) or 'graph' (one captured HIP graph per step)."""
         _check(lib().mx_set_launch_mode(self._h, {"eager": 0, "graph": 1}[mode]))
 
-    def step_timed(self, n, group):
+    def step_timed(self, n, group, stride=1):
         """n eager steps; HIP events bound to the kernels of `group` (a name of
-        KERNELS).  Returns (per-step group milliseconds as a list, steps where the
-        group launched)."""
+        KERNELS) in every `stride`-th step.  Returns (per-step group milliseconds
+        as a list, 0 for untimed steps; timed steps where the group launched)."""
         g = self.KERNELS.index(group)
         ms = (C.c_float * max(int(n), 1))()
         nl = C.c_int32(0)
-        _check(lib().mx_step_timed(self._h, int(n), g, ms, C.byref(nl)))
+        _check(lib().mx_step_timed(self._h, int(n), g, int(stride), ms, C.byref(nl)))
         return list(ms[: int(n)]), nl.value
 
     def counters(self):

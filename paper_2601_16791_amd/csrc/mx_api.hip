@@ -403,19 +403,21 @@ mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms) {
   return read_err(s);
 }
 
-mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, float* kernel_ms,
-                        int32_t* n_launched) {
-  if (!s || n_steps < 0 || group < 0 || group >= MX_NUM_KERNELS || !kernel_ms || !n_launched)
+mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, int32_t stride,
+                        float* kernel_ms, int32_t* n_launched) {
+  if (!s || n_steps < 0 || group < 0 || group >= MX_NUM_KERNELS || stride < 1 || !kernel_ms ||
+      !n_launched)
     return fail(MX_EINVAL, "bad argument");
   *n_launched = 0;
   if (n_steps == 0) return MX_OK;
   if (n_steps > (1 << 24)) return fail(MX_EINVAL, "too many timed steps in one call");
   hipError_t e = hipSuccess;
-  if (s->tev_pool_n < 2 * n_steps) {  // grow the event pool (kept for later calls)
-    hipEvent_t* pool = new hipEvent_t[2 * (size_t)n_steps];
+  const int32_t n_timed = (n_steps - 1) / stride + 1;  // steps 0, stride, 2 stride, ...
+  if (s->tev_pool_n < 2 * n_timed) {  // grow the event pool (kept for later calls)
+    hipEvent_t* pool = new hipEvent_t[2 * (size_t)n_timed];
     int32_t k = 0;
     for (; k < s->tev_pool_n; ++k) pool[k] = s->tev_pool[k];
-    for (; k < 2 * n_steps && e == hipSuccess; ++k) e = hipEventCreate(&pool[k]);
+    for (; k < 2 * n_timed && e == hipSuccess; ++k) e = hipEventCreate(&pool[k]);
     if (e != hipSuccess) --k;  // pool[k] was not created
     delete[] s->tev_pool;
     s->tev_pool = pool;
@@ -430,14 +432,14 @@ mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, float* ker
   e = enqueue_steps(
       s, n_steps, join,
       [&](int k, int q) {
-        if (k == group) {
+        if (k == group && q % stride == 0) {
           s->tev.armed = true;
-          s->tev.start = ev[2 * q];
-          s->tev.stop = ev[2 * q + 1];
+          s->tev.start = ev[2 * (q / stride)];
+          s->tev.stop = ev[2 * (q / stride) + 1];
         }
       },
       [&](int k, int q) {
-        if (k == group) {
+        if (k == group && q % stride == 0) {
           used[q] = s->tev.start == nullptr;  // the start event went to a kernel
           s->tev.armed = false;
           s->tev.start = s->tev.stop = nullptr;
@@ -448,7 +450,7 @@ mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, float* ker
   for (int32_t q = 0; q < n_steps; ++q) {
     float ms = 0.f;
     if (e == hipSuccess && used[q]) {
-      e = hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]);
+      e = hipEventElapsedTime(&ms, ev[2 * (q / stride)], ev[2 * (q / stride) + 1]);
       ++nl;
     }
     kernel_ms[q] = ms;

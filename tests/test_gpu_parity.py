@@ -314,9 +314,11 @@ def test_launch_modes_give_identical_states(mx, name, kw, group):
     a.set_launch_mode("graph")
     a.step(12)
     c.step(12)
-    ms, nl = b.step_timed(8, group)
+    ms, nl = b.step_timed(5, group)
+    ms3, nl3 = b.step_timed(3, group, stride=2)
     prof = b.step_profiled(4)
-    assert nl == 8 and len(ms) == 8 and min(ms) > 0.0
+    assert nl == 5 and len(ms) == 5 and min(ms) > 0.0
+    assert nl3 == 2 and ms3[0] > 0.0 and ms3[1] == 0.0 and ms3[2] > 0.0
     assert set(prof) == set(mx.System.KERNELS)
     xa, ua = a.get_dh()
     xb, ub = b.get_dh()
