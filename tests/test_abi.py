@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libmx.so not built")
 def test_params_struct_layout_matches_header():
     import paper_2601_16791_amd as mx
-    # 5 doubles, 4 int32, 12 doubles
+    # 5 doubles, 4 int32, 10 doubles
     assert ctypes.sizeof(mx.Params) == 5 * 8 + 4 * 4 + 10 * 8
     text = open(HEADER).read()
     body = text[text.index("typedef struct {", text.index("mx_status;")):text.index("} mx_params;")]
