@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_force_kick(
 constexpr int kSymT = 64;     // bodies per tile
 constexpr int kSymC = 16;     // sources per pass-2 chunk
 constexpr int kSymS = 65;     // LDS row stride of the weights (odd: no bank conflicts)
-constexpr int kSymWaves = 4;  // independent waves per block
+constexpr int kSymWaves = 1;  // independent waves per block
 
 struct SymSrc {
   double x, y, z, mu;
