@@ -22,7 +22,8 @@ Extra objects:
                    sum of the same systems stepped one at a time
   adjoint       -- 1,000 differentiable steps of a 20,000-body embryo disk (checkpoints
                    every 50 steps) and the reverse pass, against plain steps
-  cpu_baseline  -- the CPU oracle (single thread) on a bounded sample of steps
+  cpu_baseline  -- the CPU oracle built for the host, serial and OpenMP over target
+                   bodies on all usable cores (bitwise equal), on a bounded sample
 """
 from __future__ import annotations
 
@@ -121,24 +122,69 @@ def recorded_traffic(kernel_group: str, workload_name: str):
         return None
 
 
+def host_cpu():
+    """CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
 def cpu_baseline(w, target_s: float):
+    """The CPU oracle built for this host (gcc -O3 -march=native, no FMA contraction),
+    serial and with OpenMP over target bodies, on a bounded sample: the serial build
+    runs consecutive steps from the initial state for about half of target_s, the
+    OpenMP build then runs the same number of steps, and both states must agree bit
+    for bit."""
+    import tempfile
+    import numpy as np
     import oracle
-    oracle.build_lib(force=False)
-    o = oracle.OracleSystem.from_workload(w)
+    model, ncpu, usable = host_cpu()
     n = w.params["n_big"] + w.params["n_small"]
     I = interactions_per_step(w.params["n_big"], n)
-    t0 = time.perf_counter()
-    steps = 0
-    while True:
-        o.step(1)
-        steps += 1
-        if time.perf_counter() - t0 >= target_s:
-            break
-    T = time.perf_counter() - t0
-    return {"value": I * steps / T, "unit": "interactions/s", "cores": 1, "kind": "oracle",
-            "steps_per_s": steps / T,
-            "sample": f"{steps} consecutive hybrid steps of the same workload from its initial state, "
-                      f"single-threaded C oracle (gcc -O2), {T:.1f} s"}
+    with tempfile.TemporaryDirectory() as d:
+        lib_s = oracle.load(oracle.build_variant(os.path.join(d, "or_serial.so"), openmp=False))
+        lib_p = oracle.load(oracle.build_variant(os.path.join(d, "or_omp.so"), openmp=True))
+        o = oracle.OracleSystem(w.params, w.x, w.v, w.m_big, w.r_p, w.rho_p, w.growth,
+                                library=lib_s)
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            o.step(1)
+            steps += 1
+            if time.perf_counter() - t0 >= 0.5 * target_s:
+                break
+        T_s = time.perf_counter() - t0
+        xs, us = o.get_dh()
+        o.close()
+        q = oracle.OracleSystem(w.params, w.x, w.v, w.m_big, w.r_p, w.rho_p, w.growth,
+                                library=lib_p)
+        threads = lib_p.or_threads()
+        t1 = time.perf_counter()
+        q.step(steps)
+        T_p = time.perf_counter() - t1
+        xp, up = q.get_dh()
+        q.close()
+        identical = bool(np.array_equal(xs, xp) and np.array_equal(us, up))
+    return {"value": I * steps / T_p, "unit": "interactions/s", "cores": threads,
+            "kind": "oracle", "steps_per_s": steps / T_p,
+            "serial": {"value": I * steps / T_s, "steps_per_s": steps / T_s, "cores": 1},
+            "openmp_equals_serial_bitwise": identical,
+            "host": {"cpu_model": model, "nproc": ncpu, "usable_cpus": usable,
+                     "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")},
+            "build": "gcc " + " ".join(oracle.CFLAGS_FAST) + " (+ -fopenmp for the parallel leg)",
+            "sample": f"{steps} consecutive hybrid steps of the same workload from its initial "
+                      f"state: serial {T_s:.1f} s, OpenMP over target bodies on {threads} threads "
+                      f"{T_p:.1f} s"}
 
 
 def kick_fp64(args):
@@ -228,7 +274,7 @@ def adjoint_leg(args):
     nb = w.params["n_big"]
     steps, every = args.adjoint_steps, 50
     spec = dict(params=w.params, x=w.x, v=w.v, r_p=w.r_p, rho_p=w.rho_p, n_steps=steps,
-                checkpoint_every=every)
+                checkpoint_every=every, m_big=w.m_big)
     dev = "cuda"
 
     def run(spec_run):
@@ -350,7 +396,10 @@ def main():
     pairs_last = len(s.encounters())
     pairs_avg = (p1 - p0) / args.steps
     dom_avg_s = sum(per_step_ms) / max(n_launch, 1) / 1e3
-    roof = roofline_for(dominant, dom_avg_s, w, pairs_avg, (f1 - f0) / max(n_launch, 1))
+    # the integrator's model flops are counted over every timed step; it launches
+    # once per step, so per launch they are divided by the steps, not by the
+    # event-timed launches
+    roof = roofline_for(dominant, dom_avg_s, w, pairs_avg, (f1 - f0) / args.steps)
     roof["avg_launch_us"] = dom_avg_s * 1e6
     roof["launches"] = n_launch
     roof["event_stride"] = args.event_stride

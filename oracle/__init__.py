@@ -16,7 +16,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
-CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-Wno-unknown-pragmas",
+          "-fPIC", "-shared"]
+# the CPU-baseline builds: the same source for the host it runs on, serial and with
+# OpenMP over target bodies (per-target sums in a fixed order: identical results)
+CFLAGS_FAST = ["-O3", "-march=native", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+               "-Wno-unknown-pragmas", "-fPIC", "-shared"]
 
 OR_OK, OR_EINVAL, OR_ENOMEM, OR_ENOCONV, OR_EBS = 0, -1, -2, -4, -5
 
@@ -54,9 +59,24 @@ def make_params(p: dict) -> _Params:
     return q
 
 
+def build_variant(path: str, openmp: bool) -> str:
+    """Compile oracle.c with CFLAGS_FAST (plus -fopenmp) into path; for timing the
+    oracle on the host that runs it."""
+    flags = CFLAGS_FAST + (["-fopenmp"] if openmp else [])
+    subprocess.check_call(["gcc", *flags, "-o", path, _SRC, "-lm"])
+    return path
+
+
 _lib = None
 _D = C.POINTER(C.c_double)
 _I32 = C.POINTER(C.c_int32)
+
+
+def load(path: str):
+    """Load an oracle library and declare its functions."""
+    L = C.CDLL(path)
+    _declare(L)
+    return L
 
 
 def lib():
@@ -64,37 +84,45 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build_lib()
-        L = C.CDLL(_LIB_PATH)
-        L.or_create.restype = C.c_void_p
-        L.or_create.argtypes = [C.POINTER(_Params), _D, _D, _D, _D, _D, _D, C.POINTER(C.c_int)]
-        L.or_destroy.argtypes = [C.c_void_p]
-        L.or_step.argtypes = [C.c_void_p, C.c_int]
-        L.or_energy.argtypes = [C.c_void_p, _D, _D]
-        L.or_encounters.argtypes = [C.c_void_p, _I32, C.c_int]
-        L.or_get_state.argtypes = [C.c_void_p, _D, _D]
-        L.or_get_dh.argtypes = [C.c_void_p, _D, _D]
-        L.or_set_dh.argtypes = [C.c_void_p, _D, _D, C.c_long]
-        L.or_get_accel.argtypes = [C.c_void_p, _D]
-        L.or_get_mu.argtypes = [C.c_void_p, _D, _D]
-        L.or_set_rcrit.argtypes = [C.c_void_p, _D]
-        L.or_step_index.restype = C.c_long
-        L.or_step_index.argtypes = [C.c_void_p]
-        L.or_changeover.restype = C.c_double
-        L.or_changeover.argtypes = [C.c_double, C.c_double]
-        L.or_gravity.argtypes = [C.c_int, C.c_int, _D, _D, _D, _D]
-        L.or_drag.argtypes = [C.POINTER(_Params), C.c_int, C.c_int, _D, _D, _D, _D, _D, _D]
-        L.or_drag_cd.restype = C.c_double
-        L.or_drag_cd.argtypes = [C.c_double, C.c_double, C.c_double]
-        L.or_drift.argtypes = [C.c_double, _D, _D, C.c_double, _D, _D]
-        L.or_pair_dmin2.restype = C.c_double
-        L.or_pair_dmin2.argtypes = [_D, _D, _D, _D, C.c_double]
-        L.or_flag.argtypes = [C.c_int, C.c_int, _D, _D, _D, _D, _D, C.c_double, _I32, C.c_int,
-                              C.POINTER(C.c_int)]
-        L.or_bs.argtypes = [C.c_int, _D, _D, C.c_int, _I32, C.c_double, C.c_double, C.c_double,
-                            _D, _D]
-        L.or_x2el.argtypes = [C.c_double, _D, _D, _D]
-        _lib = L
+        _lib = load(_LIB_PATH)
     return _lib
+
+
+def _declare(L):
+    L.or_create.restype = C.c_void_p
+    L.or_create.argtypes = [C.POINTER(_Params), _D, _D, _D, _D, _D, _D, C.POINTER(C.c_int)]
+    L.or_destroy.argtypes = [C.c_void_p]
+    L.or_step.argtypes = [C.c_void_p, C.c_int]
+    L.or_energy.argtypes = [C.c_void_p, _D, _D]
+    L.or_encounters.argtypes = [C.c_void_p, _I32, C.c_int]
+    L.or_get_state.argtypes = [C.c_void_p, _D, _D]
+    L.or_get_dh.argtypes = [C.c_void_p, _D, _D]
+    L.or_set_dh.argtypes = [C.c_void_p, _D, _D, C.c_long]
+    L.or_get_accel.argtypes = [C.c_void_p, _D]
+    L.or_get_mu.argtypes = [C.c_void_p, _D, _D]
+    L.or_set_rcrit.argtypes = [C.c_void_p, _D]
+    L.or_step_index.restype = C.c_long
+    L.or_step_index.argtypes = [C.c_void_p]
+    L.or_changeover.restype = C.c_double
+    L.or_changeover.argtypes = [C.c_double, C.c_double]
+    L.or_gravity.argtypes = [C.c_int, C.c_int, _D, _D, _D, _D]
+    L.or_drag.argtypes = [C.POINTER(_Params), C.c_int, C.c_int, _D, _D, _D, _D, _D, _D]
+    L.or_drag_cd.restype = C.c_double
+    L.or_drag_cd.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.or_drift.argtypes = [C.c_double, _D, _D, C.c_double, _D, _D]
+    L.or_pair_dmin2.restype = C.c_double
+    L.or_pair_dmin2.argtypes = [_D, _D, _D, _D, C.c_double]
+    L.or_flag.argtypes = [C.c_int, C.c_int, _D, _D, _D, _D, _D, C.c_double, _I32, C.c_int,
+                          C.POINTER(C.c_int)]
+    L.or_bs.argtypes = [C.c_int, _D, _D, C.c_int, _I32, C.c_double, C.c_double, C.c_double,
+                        _D, _D]
+    L.or_x2el.argtypes = [C.c_double, _D, _D, _D]
+    L.or_gas_sigma.restype = C.c_double
+    L.or_gas_sigma.argtypes = [C.POINTER(_Params), C.c_double]
+    L.or_last_pair_dmin2.restype = C.c_double
+    L.or_last_pair_dmin2.argtypes = [C.c_void_p, C.c_int, C.c_int, _D]
+    L.or_threads.restype = C.c_int
+    L.or_threads.argtypes = []
 
 
 def _d(a):
@@ -108,7 +136,9 @@ def _p(a):
 class OracleSystem:
     """Whole-system oracle: create / step / energy / encounters / state."""
 
-    def __init__(self, params: dict, x, v, m_big, r_p=None, rho_p=None, growth=None):
+    def __init__(self, params: dict, x, v, m_big, r_p=None, rho_p=None, growth=None,
+                 library=None):
+        self._L = library if library is not None else lib()
         self.params = dict(params)
         self.n = int(params["n_big"]) + int(params["n_small"])
         self.nb = int(params["n_big"])
@@ -119,7 +149,7 @@ class OracleSystem:
         gr = _d(growth) if growth is not None else None
         st = C.c_int(0)
         self._pp = make_params(params)
-        self._h = lib().or_create(C.byref(self._pp), _p(x), _p(v), _p(m), _p(rp), _p(rh), _p(gr),
+        self._h = self._L.or_create(C.byref(self._pp), _p(x), _p(v), _p(m), _p(rp), _p(rh), _p(gr),
                                   C.byref(st))
         if not self._h:
             raise ValueError(f"oracle create failed: {st.value}")
@@ -130,60 +160,66 @@ class OracleSystem:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().or_destroy(self._h)
+            self._L.or_destroy(self._h)
             self._h = None
 
     __del__ = close
 
     def step(self, n=1):
-        st = lib().or_step(self._h, int(n))
+        st = self._L.or_step(self._h, int(n))
         if st != OR_OK:
             raise RuntimeError(f"oracle step failed: {st}")
 
     def energy(self):
         E = C.c_double(0)
         L = np.zeros(3)
-        lib().or_energy(self._h, C.byref(E), _p(L))
+        self._L.or_energy(self._h, C.byref(E), _p(L))
         return E.value, L
 
     def encounters(self):
         cap = 1 << 20
         buf = np.zeros(2 * cap, dtype=np.int32)
-        k = lib().or_encounters(self._h, buf.ctypes.data_as(_I32), cap)
+        k = self._L.or_encounters(self._h, buf.ctypes.data_as(_I32), cap)
         return buf[: 2 * min(k, cap)].reshape(-1, 2).copy()
 
     def get_state(self):
         x = np.zeros((3, self.n)); v = np.zeros((3, self.n))
-        lib().or_get_state(self._h, _p(x), _p(v))
+        self._L.or_get_state(self._h, _p(x), _p(v))
         return x, v
 
     def get_dh(self):
         x = np.zeros((3, self.n)); u = np.zeros((3, self.n))
-        lib().or_get_dh(self._h, _p(x), _p(u))
+        self._L.or_get_dh(self._h, _p(x), _p(u))
         return x, u
 
     def set_dh(self, x, u, step_index=0):
         x, u = _d(x), _d(u)
-        lib().or_set_dh(self._h, _p(x), _p(u), int(step_index))
+        self._L.or_set_dh(self._h, _p(x), _p(u), int(step_index))
 
     def accel(self):
         a = np.zeros((3, self.n))
-        lib().or_get_accel(self._h, _p(a))
+        self._L.or_get_accel(self._h, _p(a))
         return a
 
     def mu(self):
         mu = np.zeros(max(self.nb, 1)); rc = np.zeros(max(self.nb, 1))
-        lib().or_get_mu(self._h, _p(mu), _p(rc))
+        self._L.or_get_mu(self._h, _p(mu), _p(rc))
         return mu[: self.nb], rc[: self.nb]
 
     def step_index(self):
-        return lib().or_step_index(self._h)
+        return self._L.or_step_index(self._h)
+
+    def last_pair_dmin2(self, i, j):
+        """(d_min^2, rc^2) of the last step's encounter test for the pair (i, j)."""
+        rc2 = C.c_double(0)
+        d = self._L.or_last_pair_dmin2(self._h, int(i), int(j), C.byref(rc2))
+        return d, rc2.value
 
     def set_rcrit(self, rcrit):
         """Hold the changeover radii at the given values (FSAL force refreshed)."""
         rc = _d(rcrit)
         assert rc.shape == (self.nb,)
-        lib().or_set_rcrit(self._h, _p(rc))
+        self._L.or_set_rcrit(self._h, _p(rc))
 
 
 # ------------------------------------------------------------ components
@@ -207,6 +243,12 @@ def drag(params, x, u, mu, r_p, rho_p_internal, nb):
     pp = make_params(params)
     lib().or_drag(C.byref(pp), n, nb, _p(x), _p(u), _p(mu), _p(rp), _p(rh), _p(a))
     return a
+
+
+def gas_sigma(params, R):
+    """Eq. 1 surface density in g cm^-2 at cylindrical radius R [AU]."""
+    pp = make_params(params)
+    return lib().or_gas_sigma(C.byref(pp), float(R))
 
 
 def drag_cd(re, ma, kexp=-2.0):

@@ -25,6 +25,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define PI 3.14159265358979323846
 
@@ -41,6 +44,7 @@ struct or_sys {
   int32_t* pairs;
   int npairs, cap_pairs;
   double *x0, *u0, *x1, *u1, *ad;   /* scratch [3][n] */
+  double *x1k, *u1k;                /* last step's post-drift state before BS [3][n] */
 };
 
 /* ------------------------------------------------------------------ */
@@ -80,6 +84,7 @@ static double pair_weight(double s2, double rc) {
  * rc = max(rcrit_s, rcrit_t), sources summed in ascending order.          */
 void or_gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,
                 double* a) {
+#pragma omp parallel for schedule(static)
   for (int t = 0; t < n; ++t) {
     double rct = t < nb ? rcrit[t] : 0.0;
     double ax = 0.0, ay = 0.0, az = 0.0;
@@ -111,6 +116,22 @@ double or_drag_cd(double re, double ma, double kexp) {
   return pow(inner, kexp) + 2.0 * (0.8 * k + ma) / (1.6 + ma);
 }
 
+/* Gas surface density of Eq. 1 (Sect. 3.1) in g cm^-2 at cylindrical radius R
+ * [AU]: Sigma0 (R/R_C)^-gamma exp[-(R/R_C)^(2-gamma)], with Sigma0 chosen so
+ * that Sigma(1 AU) = sigma1 (the configuration gives the density at 1 AU);
+ * without a taper radius (r_c = 0) the exponential is dropped.  Zero inward
+ * of the inner edge r_in.                                                  */
+double or_gas_sigma(const or_params* p, double R) {
+  if (!(R > 0.0) || R < p->r_in) return 0.0;
+  double sig = p->sigma1 * pow(R, -p->gamma);
+  if (p->r_c > 0.0) {
+    double at1 = pow(1.0 / p->r_c, 2.0 - p->gamma);
+    double atR = pow(R / p->r_c, 2.0 - p->gamma);
+    sig *= exp(at1 - atR);
+  }
+  return sig;
+}
+
 /* Gas drag on the massless bodies (Sect. 3.1, Eqs. 1, 3, 4, 5, 7), applied to
  * bodies nbig+1..nbod only.  Midplane density at every height; velocity
  * relative to the gas uses the heliocentric velocity u + P/mu0.            */
@@ -125,6 +146,7 @@ void or_drag(const or_params* p, int n, int nb, const double* x, const double* u
   }
   double sx = px / mu0, sy = py / mu0, sz = pz / mu0;
   double sigma_unit = p->rho_unit / p->au_cm; /* Msun/AU^2 per g/cm^2 */
+#pragma omp parallel for schedule(static)
   for (int t = 0; t < n; ++t) {
     a[t] = a[n + t] = a[2 * n + t] = 0.0;
     if (t < nb || !p->gas_on) continue;
@@ -136,10 +158,7 @@ void or_drag(const or_params* p, int n, int nb, const double* x, const double* u
     double om = vk / R;
     double hg = p->h_over_r * R;
     double cs = hg * om;
-    double taper = 1.0;
-    if (p->r_c > 0.0)
-      taper = exp(pow(1.0 / p->r_c, 2.0 - p->gamma) - pow(R / p->r_c, 2.0 - p->gamma));
-    double sig = p->sigma1 * sigma_unit * pow(R, -p->gamma) * taper;
+    double sig = or_gas_sigma(p, R) * sigma_unit;
     if (!(sig > 0.0)) continue;
     double rhog = sig / (sqrt(2.0 * PI) * hg);
     double vg = vk * sqrt(1.0 - 2.0 * p->eta);
@@ -358,80 +377,87 @@ int or_drift(double mu, const double x0[3], const double v0[3], double h, double
 }
 
 /* ------------------------------------------------------------------ */
-/* Minimum squared separation of a pair inside the step.  The relative
- * position r(tau), tau = t/h in [0,1], is the cubic Hermite interpolant of
- * (r0, h*w0) at tau = 0 and (r1, h*w1) at tau = 1.  Its squared length is
- * minimised over the end points and over every interior root of d|r|^2/dtau
- * at which the derivative changes from negative to non-negative on a fixed
- * 16-interval grid; each such root is refined by 40 bisection steps.  The
- * derivative (halved) is r . r', a quintic in tau whose coefficient of tau^m is
- * the sum of j c_i . c_j over i + j = m + 1 (c_0..c_3 the cubic's
- * coefficients); it is evaluated by Horner's rule.                            */
-static void herm_pos(const double c[4][3], double tau, double r[3]) {
-  for (int k = 0; k < 3; ++k)
-    r[k] = c[0][k] + tau * (c[1][k] + tau * (c[2][k] + tau * c[3][k]));
+/* Minimum squared separation of a pair inside the step (the encounter test of
+ * the mce_snif region, Sect. 2.1.2; the paper does not print how the minimum
+ * is found, so this is the reading the whole oracle uses).  Over the step,
+ * tau = t/h in [0,1], the relative position is the cubic Hermite interpolant
+ * that takes the value r0 and the slope h*w0 at tau = 0 and r1, h*w1 at tau = 1:
+ *   r(tau) = H00(tau) r0 + H10(tau) h w0 + H01(tau) r1 + H11(tau) h w1,
+ *   H00 = (1 + 2 tau)(1 - tau)^2,  H10 = tau (1 - tau)^2,
+ *   H01 = tau^2 (3 - 2 tau),       H11 = tau^2 (tau - 1).
+ * |r|^2 is minimised over the two end points and over the interior zeros of
+ * its derivative 2 r.r' at which the derivative passes from negative to
+ * non-negative between neighbouring points of a fixed grid of 16 intervals;
+ * such a zero is located by 40 halvings of its interval and |r|^2 taken at
+ * the final midpoint.                                                       */
+static void herm_at(const double r0[3], const double p0[3], const double r1[3],
+                    const double p1[3], double tau, double r[3], double dr[3]) {
+  double s = 1.0 - tau;
+  double h00 = (1.0 + 2.0 * tau) * s * s;
+  double h10 = tau * s * s;
+  double h01 = tau * tau * (3.0 - 2.0 * tau);
+  double h11 = tau * tau * (tau - 1.0);
+  double g00 = 6.0 * tau * (tau - 1.0); /* dH00/dtau; dH01/dtau = -g00 */
+  double g10 = s * (1.0 - 3.0 * tau);
+  double g11 = tau * (3.0 * tau - 2.0);
+  for (int k = 0; k < 3; ++k) {
+    r[k] = h00 * r0[k] + h10 * p0[k] + h01 * r1[k] + h11 * p1[k];
+    dr[k] = g00 * (r0[k] - r1[k]) + g10 * p0[k] + g11 * p1[k];
+  }
 }
 
-static double dot3(const double* a, const double* b) {
-  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-}
-
-static void herm_poly(const double c[4][3], double a[6]) {
-  a[0] = dot3(c[0], c[1]);
-  a[1] = dot3(c[1], c[1]) + 2.0 * dot3(c[0], c[2]);
-  a[2] = 3.0 * dot3(c[0], c[3]) + 3.0 * dot3(c[1], c[2]);
-  a[3] = 4.0 * dot3(c[1], c[3]) + 2.0 * dot3(c[2], c[2]);
-  a[4] = 5.0 * dot3(c[2], c[3]);
-  a[5] = 3.0 * dot3(c[3], c[3]);
-}
-
-static double herm_dd(const double a[6], double tau) {
-  return a[0] + tau * (a[1] + tau * (a[2] + tau * (a[3] + tau * (a[4] + tau * a[5]))));
+/* sign-deciding half derivative r . dr/dtau, and |r|^2 */
+static double herm_slope(const double r0[3], const double p0[3], const double r1[3],
+                         const double p1[3], double tau, double* d2) {
+  double r[3], dr[3];
+  herm_at(r0, p0, r1, p1, tau, r, dr);
+  if (d2) *d2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  return r[0] * dr[0] + r[1] * dr[1] + r[2] * dr[2];
 }
 
 double or_pair_dmin2(const double r0[3], const double w0[3], const double r1[3],
                      const double w1[3], double h) {
-  double c[4][3];
+  double p0[3], p1[3];
   for (int k = 0; k < 3; ++k) {
-    c[0][k] = r0[k];
-    c[1][k] = h * w0[k];
-    c[2][k] = 3.0 * (r1[k] - r0[k]) - h * (2.0 * w0[k] + w1[k]);
-    c[3][k] = 2.0 * (r0[k] - r1[k]) + h * (w0[k] + w1[k]);
+    p0[k] = h * w0[k];
+    p1[k] = h * w1[k];
   }
-  double a[6];
-  herm_poly(c, a);
   double d0 = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
   double d1 = r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2];
   double best = d0 < d1 ? d0 : d1;
   const int NG = 16;
-  double dprev = herm_dd(a, 0.0);
+  double s_lo = herm_slope(r0, p0, r1, p1, 0.0, NULL);
   for (int k = 0; k < NG; ++k) {
-    double t1 = (double)(k + 1) / NG;
-    double dnext = herm_dd(a, t1);
-    if (dprev < 0.0 && dnext >= 0.0) {
-      double lo = (double)k / NG, hi = t1;
-      for (int it = 0; it < 40; ++it) {
-        double mid = 0.5 * (lo + hi);
-        if (herm_dd(a, mid) < 0.0) lo = mid; else hi = mid;
-      }
-      double r[3];
-      herm_pos(c, 0.5 * (lo + hi), r);
-      double d = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-      if (d < best) best = d;
+    double lo = (double)k / NG, hi = (double)(k + 1) / NG;
+    double s_hi = herm_slope(r0, p0, r1, p1, hi, NULL);
+    int falls = s_lo < 0.0 && !(s_hi < 0.0);
+    s_lo = s_hi;
+    if (!falls) continue;
+    for (int it = 0; it < 40; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if (herm_slope(r0, p0, r1, p1, mid, NULL) < 0.0) lo = mid;
+      else hi = mid;
     }
-    dprev = dnext;
+    double d;
+    herm_slope(r0, p0, r1, p1, 0.5 * (lo + hi), &d);
+    if (d < best) best = d;
   }
   return best;
 }
 
 /* Encounter flagging (the mce_snif critical region): every unordered pair
  * {big i, body j > i} whose minimum separation over the step is <= rc,
- * rc = max(rcrit_i, rcrit_j), inclusive.  Pairs come out sorted by (i, j). */
+ * rc = max(rcrit_i, rcrit_j), inclusive.  Pairs come out sorted by (i, j):
+ * for each i the tests of all j are taken first (independently, so they may
+ * run in parallel) and the flagged j are then listed in increasing order.   */
 int or_flag(int n, int nb, const double* rcrit, const double* x0, const double* u0,
             const double* x1, const double* u1, double h, int32_t* pairs, int cap,
             int* n_pairs) {
   int np = 0;
+  unsigned char* hit = (unsigned char*)malloc(n > 0 ? (size_t)n : 1);
+  if (!hit) { *n_pairs = 0; return OR_ENOMEM; }
   for (int i = 0; i < nb; ++i) {
+#pragma omp parallel for schedule(static)
     for (int j = i + 1; j < n; ++j) {
       double rcj = j < nb ? rcrit[j] : 0.0;
       double rc = rcrit[i] > rcj ? rcrit[i] : rcj;
@@ -442,16 +468,18 @@ int or_flag(int n, int nb, const double* rcrit, const double* x0, const double* 
         w0[k] = u0[k * n + j] - u0[k * n + i];
         w1[k] = u1[k * n + j] - u1[k * n + i];
       }
-      double dmin = or_pair_dmin2(r0, w0, r1, w1, h);
-      if (dmin <= rc * rc) {
-        if (np < cap) {
-          pairs[2 * np] = i;
-          pairs[2 * np + 1] = j;
-        }
-        ++np;
+      hit[j] = or_pair_dmin2(r0, w0, r1, w1, h) <= rc * rc;
+    }
+    for (int j = i + 1; j < n; ++j) {
+      if (!hit[j]) continue;
+      if (np < cap) {
+        pairs[2 * np] = i;
+        pairs[2 * np + 1] = j;
       }
+      ++np;
     }
   }
+  free(hit);
   *n_pairs = np;
   return np <= cap ? OR_OK : OR_EINVAL;
 }
@@ -790,6 +818,7 @@ or_sys* or_create(const or_params* p, const double* x_h, const double* v_h, cons
   s->x = (double*)malloc(v3); s->u = (double*)malloc(v3); s->ag = (double*)malloc(v3);
   s->x0 = (double*)malloc(v3); s->u0 = (double*)malloc(v3);
   s->x1 = (double*)malloc(v3); s->u1 = (double*)malloc(v3); s->ad = (double*)malloc(v3);
+  s->x1k = (double*)calloc(1, v3); s->u1k = (double*)calloc(1, v3);
   size_t nbs = sizeof(double) * (s->nb > 0 ? s->nb : 1);
   s->mu = (double*)malloc(nbs); s->mu_init = (double*)malloc(nbs);
   s->rcrit = (double*)malloc(nbs); s->rcrit_init = (double*)malloc(nbs);
@@ -798,6 +827,7 @@ or_sys* or_create(const or_params* p, const double* x_h, const double* v_h, cons
   s->cap_pairs = 1 << 20;
   s->pairs = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)s->cap_pairs);
   if (!s->x || !s->u || !s->ag || !s->x0 || !s->u0 || !s->x1 || !s->u1 || !s->ad || !s->mu ||
+      !s->x1k || !s->u1k ||
       !s->mu_init || !s->rcrit || !s->rcrit_init || !s->r_p || !s->rho_p || !s->pairs) {
     or_destroy(s);
     return NULL;
@@ -848,7 +878,7 @@ or_sys* or_create(const or_params* p, const double* x_h, const double* v_h, cons
 void or_destroy(or_sys* s) {
   if (!s) return;
   free(s->x); free(s->u); free(s->ag); free(s->x0); free(s->u0); free(s->x1); free(s->u1);
-  free(s->ad); free(s->mu); free(s->mu_init); free(s->rcrit); free(s->rcrit_init);
+  free(s->ad); free(s->x1k); free(s->u1k); free(s->mu); free(s->mu_init); free(s->rcrit); free(s->rcrit_init);
   free(s->r_p); free(s->rho_p); free(s->growth); free(s->pairs);
   free(s);
 }
@@ -879,14 +909,19 @@ static int one_step(or_sys* s) {
   jump(s, hh);
   memcpy(s->x0, s->x, sizeof(double) * 3 * n);
   memcpy(s->u0, s->u, sizeof(double) * 3 * n);
+  int bad = OR_OK;
+#pragma omp parallel for schedule(static) reduction(min : bad)
   for (int t = 0; t < n; ++t) {
     double a[3] = {s->x0[t], s->x0[n + t], s->x0[2 * n + t]};
     double b[3] = {s->u0[t], s->u0[n + t], s->u0[2 * n + t]};
     double c[3], d[3];
     int st = or_drift(s->mu0, a, b, h, c, d);
-    if (st != OR_OK) return st;
+    if (st < bad) bad = st;
     for (int k = 0; k < 3; ++k) { s->x1[k * n + t] = c[k]; s->u1[k * n + t] = d[k]; }
   }
+  if (bad != OR_OK) return bad;
+  memcpy(s->x1k, s->x1, sizeof(double) * 3 * n);
+  memcpy(s->u1k, s->u1, sizeof(double) * 3 * n);
   int np = 0;
   or_flag(n, s->nb, s->rcrit, s->x0, s->u0, s->x1, s->u1, h, s->pairs, s->cap_pairs, &np);
   if (np > s->cap_pairs) return OR_EINVAL;
@@ -996,3 +1031,31 @@ void or_get_mu(const or_sys* s, double* mu, double* rcrit) {
 }
 
 long or_step_index(const or_sys* s) { return s->step; }
+
+/* Threads the loops over bodies run on (1 without OpenMP). */
+int or_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* The deciding quantity of the last step's encounter test for the pair (i, j):
+ * its minimum squared separation over the step (or_pair_dmin2) from the
+ * pre-drift state and the Kepler-drifted state before the encounter
+ * integrator, and the squared changeover radius it was compared with.      */
+double or_last_pair_dmin2(const or_sys* s, int i, int j, double* rc2) {
+  int n = s->n, nb = s->nb;
+  double r0[3], w0[3], r1[3], w1[3];
+  for (int k = 0; k < 3; ++k) {
+    r0[k] = s->x0[k * n + j] - s->x0[k * n + i];
+    w0[k] = s->u0[k * n + j] - s->u0[k * n + i];
+    r1[k] = s->x1k[k * n + j] - s->x1k[k * n + i];
+    w1[k] = s->u1k[k * n + j] - s->u1k[k * n + i];
+  }
+  double rci = i < nb ? s->rcrit[i] : 0.0, rcj = j < nb ? s->rcrit[j] : 0.0;
+  double rc = rci > rcj ? rci : rcj;
+  if (rc2) *rc2 = rc * rc;
+  return or_pair_dmin2(r0, w0, r1, w1, s->p.dt);
+}

@@ -46,6 +46,8 @@ void or_get_accel(const or_sys* s, double* a);  /* FSAL gravity (changeover-weig
 void or_get_mu(const or_sys* s, double* mu, double* rcrit);
 void or_set_rcrit(or_sys* s, const double* rcrit);
 long or_step_index(const or_sys* s);
+double or_last_pair_dmin2(const or_sys* s, int i, int j, double* rc2);
+int or_threads(void);
 
 /* --- component functions (pins and kernel-level parity) --------------- */
 double or_changeover(double s, double rc);
@@ -54,6 +56,7 @@ void or_gravity(int n, int n_big, const double* x, const double* mu, const doubl
 void or_drag(const or_params* p, int n, int n_big, const double* x, const double* u,
              const double* mu, const double* r_p, const double* rho_p, double* a);
 double or_drag_cd(double re, double ma, double kexp);
+double or_gas_sigma(const or_params* p, double R);
 int or_drift(double mu0, const double x0[3], const double v0[3], double h, double x1[3],
              double v1[3]);
 double or_pair_dmin2(const double r0[3], const double w0[3], const double r1[3],

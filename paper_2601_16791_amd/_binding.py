@@ -483,9 +483,21 @@ def _hybrid_function():
             v = torch.as_tensor(np.asarray(spec["v"], dtype=np.float64)).clone()
             x[:, :nb] = x_big.detach().cpu()
             v[:, :nb] = v_big.detach().cpu()
+            rcrit = spec.get("rcrit")
+            if rcrit is None:
+                # the changeover radii are constants of the differentiated map: taken
+                # from the undifferentiated base state, never from the inputs
+                if "m_big" not in spec:
+                    raise ValueError("spec needs 'rcrit' (changeover radii [n_big]) or "
+                                     "'m_big' (the base masses they are computed from with "
+                                     "the base state spec['x'], spec['v'])")
+                base = Adjoint(spec["params"], spec["x"], spec["v"], spec["m_big"],
+                               spec.get("r_p"), spec.get("rho_p"), 1, 1, device=m_big.device)
+                rcrit = base.rcrit()
+                base.close()
             adj = Adjoint(spec["params"], x, v, m_big.detach(), spec.get("r_p"),
                           spec.get("rho_p"), spec["n_steps"], spec.get("checkpoint_every", 50),
-                          spec.get("rcrit"), device=m_big.device)
+                          rcrit, device=m_big.device)
             xf, vf = adj.forward()
             ctx.adj = adj
             ctx.nb = nb
@@ -507,7 +519,9 @@ _HYBRID = None
 def hybrid_run(m_big, x_big, v_big, spec):
     """Differentiable run: m_big [n_big], x_big, v_big [3, n_big] torch tensors (float64,
     device); spec: dict(params, x, v (all bodies, heliocentric), r_p, rho_p, n_steps,
-    checkpoint_every, rcrit).  Returns the final heliocentric (x, v) [3, n]."""
+    checkpoint_every, and rcrit or m_big).  The changeover radii are held fixed: spec's
+    rcrit, else the Hill-rule radii of the base state (spec's x, v and m_big), never
+    radii of the differentiated inputs.  Returns the final heliocentric (x, v) [3, n]."""
     global _HYBRID
     if _HYBRID is None:
         _HYBRID = _hybrid_function()

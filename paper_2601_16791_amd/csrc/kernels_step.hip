@@ -235,8 +235,8 @@ __global__ __launch_bounds__(kBlock) void k_force_kick(
 // bodies of I from J) and [J][I]; the finish kernel adds the rows of each tile
 // in ascending source tile.  The record array is padded to whole tiles with
 // massless bodies far away from everything (see pad_kick_sources), so the loops
-// have no bounds.  Waves are independent (no block barrier): four per block,
-// about two per SIMD for the 4,004-body kick.
+// have no bounds.  Each workgroup is one independent wave (no block barrier);
+// the 4,004-body kick gives about two waves per SIMD.
 constexpr int kSymT = 64;     // bodies per tile
 constexpr int kSymC = 16;     // sources per pass-2 chunk
 constexpr int kSymS = 65;     // LDS row stride of the weights (odd: no bank conflicts)

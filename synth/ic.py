@@ -186,6 +186,33 @@ def self_gravitating(seed: int = 0, n_pl: int = 4, n_pls: int = 4000) -> Workloa
                     meta=dict(seed=seed, steps=5000))
 
 
+def crowded_annulus(seed: int = 0, n_big: int = 96, n_small: int = 2000,
+                    close_pairs: int = 3) -> Workload:
+    """Many massive bodies (0.02-0.2 M_earth, log-uniform) and massless bodies in one
+    narrow annulus a~U[1.0, 1.5] AU, e~Rayleigh(0.01), i~Rayleigh(0.005), so that
+    close encounters happen every step; the last close_pairs massive bodies are put
+    4e-3 AU from massive bodies 0, 1, ... (a few changeover radii apart at most) with
+    nearly the same velocity, so pairs of massive bodies meet as well."""
+    rng = np.random.default_rng(seed)
+    m0 = 1.0
+    m_big = M_EARTH * np.exp(rng.uniform(math.log(0.02), math.log(0.2), n_big))
+    a = rng.uniform(1.0, 1.5, n_big + n_small)
+    e = rayleigh(rng, 0.01, n_big + n_small)
+    i = rayleigh(rng, 0.005, n_big + n_small)
+    O, w, M = _angles(rng, n_big + n_small)
+    gm = np.concatenate([G * (m0 + m_big), np.full(n_small, G * m0)])
+    x, v = el2x(gm, a, e, i, O, w, M)
+    for q in range(close_pairs):
+        k = n_big - 1 - q
+        d = rng.normal(size=3)
+        d *= 4e-3 / np.linalg.norm(d)
+        x[:, k] = x[:, q] + d
+        v[:, k] = v[:, q] * (1 + rng.normal(0, 1e-4, 3))
+    dt = period(G * m0, 1.0) / 40.0
+    p = default_params(m0=m0, dt=dt, n_big=n_big, n_small=n_small, gas_on=0)
+    return Workload("crowded_annulus", p, x, v, m_big, meta=dict(seed=seed))
+
+
 def batch(seed: int = 0, n_sys: int = 256, n_small_range=(1_000, 50_000),
           n_pl_range=(2, 8)) -> list[Workload]:
     """Uneven ensemble: per-system seed = 1000*seed + index."""

@@ -154,3 +154,50 @@ def test_adjoint_checkpointing_does_not_change_the_gradient(mx):
         assert np.array_equal(xf, outs[0][0])
         for p, q in zip(g, outs[0][1]):
             assert np.array_equal(p, q)
+
+
+def test_hybrid_run_default_rcrit_is_a_constant_of_the_map(mx):
+    """Without spec['rcrit'] the changeover radii come from the base state (spec's x,
+    v and m_big), not from the differentiated inputs: the run and its gradient are
+    those of the explicit-radius path bit for bit, on a system with bodies inside a
+    changeover zone, and the mass gradient matches central differences of the GPU
+    forward run with those radii frozen."""
+    torch = pytest.importorskip("torch")
+    w = encounter_workload(seed=6, n_small=60, n_emb=3)
+    steps, every = 5, 2
+    nb = w.params["n_big"]
+    probe = mx.Adjoint(w.params, w.x, w.v, w.m_big, w.r_p, w.rho_p, 1, 1)
+    rcrit = probe.rcrit()
+    probe.close()
+    base = dict(params=w.params, x=w.x, v=w.v, r_p=w.r_p, rho_p=w.rho_p, n_steps=steps,
+                checkpoint_every=every)
+    grads, losses = [], []
+    for spec in (dict(base, m_big=w.m_big), dict(base, rcrit=rcrit)):
+        m = torch.tensor(w.m_big * 1.01, dtype=torch.float64, device="cuda", requires_grad=True)
+        xb = torch.tensor(w.x[:, :nb], dtype=torch.float64, device="cuda", requires_grad=True)
+        vb = torch.tensor(w.v[:, :nb], dtype=torch.float64, device="cuda", requires_grad=True)
+        xf, vf = mx.hybrid_run(m, xb, vb, spec)
+        h = torch.linalg.cross(xf.T, vf.T)
+        r = torch.linalg.norm(xf, dim=0)
+        e = torch.linalg.norm(torch.linalg.cross(vf.T, h) / ic.G - (xf / r).T, dim=1)[nb:]
+        loss = e.mean() + e.var(unbiased=False)
+        loss.backward()
+        losses.append(loss.item())
+        grads.append([t.grad.cpu().numpy() for t in (m, xb, vb)])
+    assert losses[0] == losses[1]
+    for p, q in zip(grads[0], grads[1]):
+        assert np.array_equal(p, q)
+    with pytest.raises(ValueError):
+        mx.hybrid_run(m, xb, vb, base)
+    mm0 = w.m_big * 1.01
+    for k in range(nb):
+        hs = 1e-4 * mm0[k]
+
+        def at(d):
+            mm = mm0.copy()
+            mm[k] += d
+            return gpu_loss(mx, w, mm, w.x[:, :nb], w.v[:, :nb], steps, every, rcrit)
+
+        fd = (-at(2 * hs) + 8 * at(hs) - 8 * at(-hs) + at(-2 * hs)) / (12 * hs)
+        noise = 20 * 2.2e-16 * abs(losses[0]) / hs
+        assert abs(grads[0][0][k] - fd) <= 1e-4 * abs(fd) + noise, (k, grads[0][0][k], fd)

@@ -224,6 +224,95 @@ def test_drag_magnitude_in_cgs(orc):
     assert np.allclose(a[:, 1], acc_au_d2, rtol=2e-6, atol=0)
 
 
+# ------------------------------------------------------------ Eq. 1, general disk
+def _disk(**kw):
+    return dict(ic.default_params(n_big=1, n_small=1, gas_on=1), **kw)
+
+
+def test_sigma_normalised_at_one_au(orc):
+    """The configuration gives the surface density at 1 AU: Sigma(1 AU) = sigma1
+    whatever the slope and the taper radius (Eq. 1 normalised there)."""
+    for gamma in (0.5, 0.8, 1.0, 1.3):
+        for r_c in (0.0, 3.0, 30.0):
+            p = _disk(gamma=gamma, r_c=r_c, r_in=0.0)
+            assert abs(orc.gas_sigma(p, 1.0) - p["sigma1"]) <= 1e-13 * p["sigma1"]
+
+
+def test_sigma_by_hand_three_points(orc):
+    """Eq. 1 evaluated by hand: Sigma = S0 (R/Rc)^-g exp[-(R/Rc)^(2-g)] with S0 fixed
+    by Sigma(1 AU) = 1700 g/cm^2, at (g, Rc, R) = (0.8, 6, 3), (1.2, 20, 7.5) and
+    (1, 0 [no taper], 4); the inner edge at 1.5 AU cuts R = 1.2 and keeps R = 1.6."""
+    # g = 0.8, Rc = 6: S0 = 1700 (1/6)^0.8 exp[(1/6)^1.2]
+    S0 = 1700.0 * (1 / 6.0) ** 0.8 * math.exp((1 / 6.0) ** 1.2)
+    ref = S0 * (3.0 / 6.0) ** -0.8 * math.exp(-(3.0 / 6.0) ** 1.2)
+    assert abs(orc.gas_sigma(_disk(gamma=0.8, r_c=6.0, r_in=0.0), 3.0) - ref) <= 1e-12 * ref
+    # by hand with five-digit logarithms: 1700 x 0.41524 x exp(0.11647 - 0.43528) = 513.2
+    assert abs(ref - 513.2) < 0.05
+    S0 = 1700.0 * (1 / 20.0) ** 1.2 * math.exp((1 / 20.0) ** 0.8)
+    ref = S0 * (7.5 / 20.0) ** -1.2 * math.exp(-(7.5 / 20.0) ** 0.8)
+    assert abs(orc.gas_sigma(_disk(gamma=1.2, r_c=20.0, r_in=0.0), 7.5) - ref) <= 1e-12 * ref
+    assert orc.gas_sigma(_disk(gamma=1.0, r_c=0.0, r_in=0.0), 4.0) == 425.0
+    p = _disk(gamma=0.8, r_c=6.0, r_in=1.5)
+    assert orc.gas_sigma(p, 1.2) == 0.0
+    assert orc.gas_sigma(p, 1.6) == orc.gas_sigma(dict(p, r_in=0.0), 1.6) > 0.0
+
+
+@pytest.mark.parametrize("gamma,r_c", [(0.8, 6.0), (1.0, 10.0), (1.5, 3.0)])
+def test_sigma_enclosed_mass_closed_form(orc, gamma, r_c):
+    """Mass inside R of the tapered profile (Lynden-Bell & Pringle similarity
+    solution): int_0^R 2 pi R' Sigma dR' = 2 pi S0 Rc^2/(2-g) [1 - exp(-(R/Rc)^(2-g))]
+    with S0 Rc^g = sigma1 exp[Rc^(g-2)] (R in AU).  Quadrature of the oracle's Sigma against
+    the closed form: a wrong exponent, sign or normalisation of the taper fails."""
+    from scipy.integrate import quad
+    p = _disk(gamma=gamma, r_c=r_c, r_in=0.0)
+    s1 = p["sigma1"]
+    for R in (0.5 * r_c, r_c, 3.0 * r_c):
+        num, _ = quad(lambda r: 2 * math.pi * r * orc.gas_sigma(p, r), 0.0, R, epsabs=0,
+                      epsrel=1e-13, limit=200)
+        S0_rcg = s1 * math.exp(r_c ** (gamma - 2))
+        ref = (2 * math.pi * S0_rcg * r_c ** (2 - gamma) / (2 - gamma)
+               * (1 - math.exp(-(R / r_c) ** (2 - gamma))))
+        assert abs(num - ref) <= 1e-10 * ref, (R, num, ref)
+
+
+def test_sigma_log_slope(orc):
+    """d ln Sigma / d ln R = -g - (2 - g)(R/Rc)^(2-g) (central differences)."""
+    for gamma, r_c in ((0.8, 6.0), (1.3, 15.0)):
+        p = _disk(gamma=gamma, r_c=r_c, r_in=0.0)
+        for R in (0.7, 2.0, 9.0):
+            e = 1e-5
+            d = (math.log(orc.gas_sigma(p, R * (1 + e))) - math.log(orc.gas_sigma(p, R * (1 - e)))) \
+                / (math.log1p(e) - math.log1p(-e))
+            ref = -gamma - (2 - gamma) * (R / r_c) ** (2 - gamma)
+            assert abs(d - ref) < 1e-8
+
+
+def test_drag_follows_sigma_of_the_general_disk(orc):
+    """At very large Re the drag coefficient no longer depends on the gas density,
+    so |a_drag| scales with Sigma alone: the drag of a tapered, gamma != 1 disk over
+    that of the plain disk at the same point and relative velocity is the ratio of
+    the two Sigma (the scale height is the same).  Inside the inner edge the drag
+    vanishes."""
+    base = ic.default_params(n_big=1, n_small=3, gas_on=1)
+    gen = dict(base, gamma=0.7, r_c=8.0, r_in=1.5)
+    n = 4
+    x = np.zeros((3, n)); u = np.zeros((3, n))
+    x[:, 0] = [30.0, 0, 0]
+    mu = np.array([1e-14])
+    for t, R in zip((1, 2, 3), (1.2, 2.5, 11.0)):
+        x[:, t] = [R, 0.0, 0.0]
+        u[:, t] = [2e-4, math.sqrt(MU0 / R), 0.0]
+    r_p = np.full(3, 5000.0 * ic.KM_AU)               # Re >> 1e5
+    rho = np.full(3, 1.5 * ic.RHO_UNIT)
+    a0 = orc.drag(base, x, u, mu, r_p, rho, 1)
+    a1 = orc.drag(gen, x, u, mu, r_p, rho, 1)
+    assert np.all(a1[:, 1] == 0.0) and np.any(a0[:, 1] != 0.0)
+    for t, R in ((2, 2.5), (3, 11.0)):
+        ratio = np.linalg.norm(a1[:, t]) / np.linalg.norm(a0[:, t])
+        ref = orc.gas_sigma(gen, R) / orc.gas_sigma(base, R)
+        assert abs(ratio - ref) <= 1e-9 * ref, (R, ratio, ref)
+
+
 # ------------------------------------------------------------ Kepler drift
 def _two_body_ode(mu, x0, v0, h):
     def f(t, y):
@@ -335,6 +424,27 @@ def test_dmin_constant_acceleration_matches_dense_search(orc):
         got = orc.pair_dmin2(r0, w0, r1, w1, h)
         assert got <= ref * (1 + 1e-9) + 1e-300
         assert got >= ref - 1e-9 * (r0 @ r0)
+
+
+def test_dmin_general_cubic_matches_dense_search(orc):
+    """A genuinely cubic relative motion (end slopes that no quadratic joins): the
+    interpolant written in monomial form, sampled densely, against the oracle."""
+    rng = np.random.default_rng(9)
+    for _ in range(40):
+        r0 = rng.uniform(-1, 1, 3)
+        r1 = rng.uniform(-1, 1, 3)
+        h = rng.uniform(0.5, 3.0)
+        w0 = rng.uniform(-1, 1, 3) / h
+        w1 = rng.uniform(-1, 1, 3) / h
+        c0, c1 = r0, h * w0
+        c2 = 3 * (r1 - r0) - h * (2 * w0 + w1)
+        c3 = 2 * (r0 - r1) + h * (w0 + w1)
+        tau = np.linspace(0.0, 1.0, 400001)[:, None]
+        pts = c0 + tau * (c1 + tau * (c2 + tau * c3))
+        ref = (pts ** 2).sum(axis=1).min()
+        got = orc.pair_dmin2(r0, w0, r1, w1, h)
+        assert got <= ref * (1 + 1e-9) + 1e-300
+        assert got >= ref - 1e-10 * max(r0 @ r0, r1 @ r1)
 
 
 def test_flag_brute_force_kepler_sampling(orc):
