@@ -301,6 +301,19 @@ mx_status mx_flag_pairs(int32_t n, int32_t n_big, const double* rcrit, const dou
                         const double* u0, const double* x1, const double* u1, double h,
                         int32_t* pairs, int32_t cap, int32_t* n_out, void* hip_stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): mx_flag_pairs with the same arguments, results
+ * and errors, whose scratch (counters, packed records of the massive bodies, sort
+ * keys) is a fixed device array of about 1.5 MiB that the library holds on each
+ * device it runs on until the process ends; it calls no hipMalloc, hipFree or
+ * allocating library routine.  Limits: n_big <= 4096 and cap <= 65536, else
+ * MX_ECAPACITY.  The array keeps the last call's contents and is cleared where
+ * needed at each call; calls that overlap on one device (other streams or
+ * threads) share it and race.  Synchronises hip_stream. */
+mx_status mx_flag_pairs_noalloc(int32_t n, int32_t n_big, const double* rcrit, const double* x0,
+                                const double* u0, const double* x1, const double* u1, double h,
+                                int32_t* pairs, int32_t cap, int32_t* n_out, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -133,6 +133,9 @@ def lib():
         L.mx_flag_pairs.restype = st
         L.mx_flag_pairs.argtypes = [C.c_int32, C.c_int32, _D, _D, _D, _D, _D, C.c_double, _D,
                                     C.c_int32, C.POINTER(C.c_int32), _P]
+        L.mx_flag_pairs_noalloc.restype = st
+        L.mx_flag_pairs_noalloc.argtypes = [C.c_int32, C.c_int32, _D, _D, _D, _D, _D, C.c_double,
+                                            _D, C.c_int32, C.POINTER(C.c_int32), _P]
         _lib = L
     return _lib
 
@@ -573,14 +576,17 @@ def kepler_drift(mu0, x0, u0, h):
     return x1, u1
 
 
-def flag_pairs(nb, rcrit, x0, u0, x1, u1, h, cap=1 << 16):
+def flag_pairs(nb, rcrit, x0, u0, x1, u1, h, cap=1 << 16, noalloc=False):
+    """Encounter flagging of the pairs (i < nb, j > i); noalloc selects the entry point
+    that takes its scratch from the library's fixed device array."""
     torch = _torch()
     tx0, tu0, tx1, tu1 = _dev(x0), _dev(u0), _dev(x1), _dev(u1)
     n = tx0.shape[1]
     trc = _dev(rcrit) if nb > 0 else torch.zeros(1, dtype=torch.float64, device="cuda")
     pairs = torch.empty(2 * cap, dtype=torch.int32, device="cuda")
     nout = C.c_int32(0)
-    _check(lib().mx_flag_pairs(n, nb, _ptr(trc), _ptr(tx0), _ptr(tu0), _ptr(tx1), _ptr(tu1),
-                               float(h), _ptr(pairs), cap, C.byref(nout), C.c_void_p(_stream())))
+    fn = lib().mx_flag_pairs_noalloc if noalloc else lib().mx_flag_pairs
+    _check(fn(n, nb, _ptr(trc), _ptr(tx0), _ptr(tu0), _ptr(tx1), _ptr(tu1), float(h),
+              _ptr(pairs), cap, C.byref(nout), C.c_void_p(_stream())))
     k = min(nout.value, cap)
     return pairs[: 2 * k].view(-1, 2).cpu().numpy()

@@ -1472,13 +1472,15 @@ __global__ void k_fpack_plain(int n, int nb, const double* __restrict__ rcrit,
   fp[t] = f;
 }
 
-hipError_t flag_pairs(int n, int nb, const double* rcrit, const double* x0, const double* u0,
-                      const double* x1, const double* u1, double h, int32_t* pairs,
-                      int32_t* pairs_tmp, int32_t cap, DevScalars* dsc, hipStream_t st) {
+// Queues the stateless encounter test on caller buffers: source packing into fp
+// ([nb] records), flagging into pairs, and the (i, j) sort of the list with
+// pairs_tmp (2 cap int64) as keys; dsc must start zeroed.  No allocation, no
+// synchronisation.
+hipError_t flag_pairs_enqueue(int n, int nb, const double* rcrit, const double* x0,
+                              const double* u0, const double* x1, const double* u1, double h,
+                              int32_t* pairs, int32_t* pairs_tmp, int32_t cap, DevScalars* dsc,
+                              FlagSource* fp, hipStream_t st) {
   if (nb == 0) return hipSuccess;
-  FlagSource* fp = nullptr;
-  hipError_t e = hipMalloc((void**)&fp, sizeof(FlagSource) * nb);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fpack_plain, dim3((nb + 255) / 256), dim3(256), 0, st, n, nb, rcrit, x0, u0,
                      x1, u1, fp);
   int tiles = (n + kBlock - 1) / kBlock;
@@ -1487,7 +1489,17 @@ hipError_t flag_pairs(int n, int nb, const double* rcrit, const double* x0, cons
                      u1, fp, pairs, cap, &dsc->n_pairs, &dsc->err);
   hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, st, nb, pairs, cap,
                      (int64_t*)pairs_tmp, nullptr, nullptr, nullptr, 0, dsc, 1);
-  e = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t flag_pairs(int n, int nb, const double* rcrit, const double* x0, const double* u0,
+                      const double* x1, const double* u1, double h, int32_t* pairs,
+                      int32_t* pairs_tmp, int32_t cap, DevScalars* dsc, hipStream_t st) {
+  if (nb == 0) return hipSuccess;
+  FlagSource* fp = nullptr;
+  hipError_t e = hipMalloc((void**)&fp, sizeof(FlagSource) * nb);
+  if (e != hipSuccess) return e;
+  e = flag_pairs_enqueue(n, nb, rcrit, x0, u0, x1, u1, h, pairs, pairs_tmp, cap, dsc, fp, st);
   hipError_t e2 = hipStreamSynchronize(st);
   (void)hipFree(fp);
   return e != hipSuccess ? e : e2;

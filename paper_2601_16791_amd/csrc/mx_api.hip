@@ -15,6 +15,7 @@
 #include <string>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "mx_internal.h"
@@ -668,6 +669,88 @@ mx_status mx_flag_pairs(int32_t n, int32_t n_big, const double* rcrit, const dou
   HIPCHK(hipStreamSynchronize(st), "sync");
   (void)hipFree(dsc);
   (void)hipFree(tmp);
+  *n_out = hd.n_pairs_last;
+  if (hd.err) return fail(MX_ECAPACITY, "more flagged pairs than cap");
+  return MX_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------- allocation-free encounter test
+// A file-scope device array serves as the scratch of mx_flag_pairs_noalloc: the
+// DevScalars block (counters, cleared by a kernel at every call), the packed
+// source records of up to kNoAllocMaxBig massive bodies and the sort keys of up
+// to kNoAllocMaxPairs pairs.  Every device holds its own copy, at its own
+// address, which is looked up once per device; host code never passes the
+// array's name itself to a kernel.
+namespace {
+constexpr int32_t kNoAllocMaxBig = 4096;
+constexpr int32_t kNoAllocMaxPairs = 1 << 16;
+constexpr size_t kScrDsc = 256;
+constexpr size_t kScrFp = sizeof(FlagSource) * (size_t)kNoAllocMaxBig;
+constexpr size_t kScrKeys = 2 * sizeof(int64_t) * (size_t)kNoAllocMaxPairs;
+constexpr size_t kScrBytes = kScrDsc + kScrFp + kScrKeys;  // 1.5 MiB
+static_assert(sizeof(DevScalars) <= kScrDsc, "scratch header too small");
+static_assert(sizeof(DevScalars) % 4 == 0 && sizeof(DevScalars) / 4 <= 64,
+              "the header is cleared by one 64-lane wave, a word per lane");
+static_assert(kScrDsc % alignof(FlagSource) == 0, "record alignment");
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScrBytes];
+
+namespace {
+std::mutex g_scr_mu;
+void* g_scr_ptr[kMaxDevices];
+
+// Device address of this device's scratch array (the current device).
+hipError_t scratch_address(unsigned char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scr_mu);
+  if (!g_scr_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scr_ptr[dev] = p;
+  }
+  *out = (unsigned char*)g_scr_ptr[dev];
+  return hipSuccess;
+}
+
+__global__ void k_zero_words(uint32_t* __restrict__ p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+}  // namespace
+
+extern "C" {
+
+mx_status mx_flag_pairs_noalloc(int32_t n, int32_t n_big, const double* rcrit, const double* x0,
+                                const double* u0, const double* x1, const double* u1, double h,
+                                int32_t* pairs, int32_t cap, int32_t* n_out, void* hip_stream) {
+  if (n <= 0 || n_big < 0 || n_big > n || !x0 || !u0 || !x1 || !u1 || !n_out || cap <= 0 ||
+      !pairs || (n_big > 0 && !rcrit) || (cap & (cap - 1)) != 0)
+    return fail(MX_EINVAL, "bad argument (cap must be a power of two)");
+  if (n_big > kNoAllocMaxBig || cap > kNoAllocMaxPairs)
+    return fail(MX_ECAPACITY, "mx_flag_pairs_noalloc: n_big above 4096 or cap above 65536");
+  hipStream_t st = (hipStream_t)hip_stream;
+  unsigned char* scr = nullptr;
+  HIPCHK(scratch_address(&scr), "scratch address");
+  DevScalars* dsc = (DevScalars*)scr;
+  FlagSource* fp = (FlagSource*)(scr + kScrDsc);
+  int32_t* keys = (int32_t*)(scr + kScrDsc + kScrFp);
+  const int words = (int)(sizeof(DevScalars) / sizeof(uint32_t));
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, (uint32_t*)dsc, words);
+  HIPCHK(hipGetLastError(), "clear");
+  HIPCHK(mxk::flag_pairs_enqueue(n, n_big, rcrit, x0, u0, x1, u1, h, pairs, keys, cap, dsc, fp,
+                                 st),
+         "flag");
+  DevScalars hd;
+  HIPCHK(hipMemcpyAsync(&hd, dsc, sizeof(hd), hipMemcpyDeviceToHost, st), "copy");
+  HIPCHK(hipStreamSynchronize(st), "sync");
   *n_out = hd.n_pairs_last;
   if (hd.err) return fail(MX_ECAPACITY, "more flagged pairs than cap");
   return MX_OK;

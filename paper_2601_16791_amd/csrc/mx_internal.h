@@ -278,4 +278,8 @@ hipError_t kepler(int n, double mu0, double h, const double* x0, const double* u
 hipError_t flag_pairs(int n, int nb, const double* rcrit, const double* x0, const double* u0,
                       const double* x1, const double* u1, double h, int32_t* pairs,
                       int32_t* pairs_tmp, int32_t cap, DevScalars* dsc, hipStream_t st);
+hipError_t flag_pairs_enqueue(int n, int nb, const double* rcrit, const double* x0,
+                              const double* u0, const double* x1, const double* u1, double h,
+                              int32_t* pairs, int32_t* pairs_tmp, int32_t cap, DevScalars* dsc,
+                              FlagSource* fp, hipStream_t st);
 }  // namespace mxk
