@@ -47,7 +47,9 @@ class _Params(C.Structure):
                 ("sigma1", C.c_double), ("gamma", C.c_double), ("r_c", C.c_double),
                 ("r_in", C.c_double), ("h_over_r", C.c_double), ("eta", C.c_double),
                 ("kdrag_exp", C.c_double), ("rho_unit", C.c_double), ("au_cm", C.c_double),
-                ("mfp_coef", C.c_double)]
+                ("mfp_coef", C.c_double),
+                ("temp_1au", C.c_double), ("temp_beta", C.c_double), ("cs2_per_k", C.c_double),
+                ("eta_mode", C.c_int32), ("dg_mode", C.c_int32)]
 
 
 def make_params(p: dict) -> _Params:
@@ -55,7 +57,7 @@ def make_params(p: dict) -> _Params:
     for name, _ in _Params._fields_:
         if name == "pad":
             continue
-        setattr(q, name, p[name])
+        setattr(q, name, p.get(name, 0))
     return q
 
 
@@ -117,6 +119,10 @@ def _declare(L):
     L.or_bs.argtypes = [C.c_int, _D, _D, C.c_int, _I32, C.c_double, C.c_double, C.c_double,
                         _D, _D]
     L.or_x2el.argtypes = [C.c_double, _D, _D, _D]
+    L.or_dg_series.restype = C.c_double
+    L.or_dg_series.argtypes = [C.c_double]
+    L.or_disk_gravity.restype = C.c_double
+    L.or_disk_gravity.argtypes = [C.POINTER(_Params), C.c_double]
     L.or_gas_sigma.restype = C.c_double
     L.or_gas_sigma.argtypes = [C.POINTER(_Params), C.c_double]
     L.or_last_pair_dmin2.restype = C.c_double
@@ -249,6 +255,17 @@ def gas_sigma(params, R):
     """Eq. 1 surface density in g cm^-2 at cylindrical radius R [AU]."""
     pp = make_params(params)
     return lib().or_gas_sigma(C.byref(pp), float(R))
+
+
+def dg_series(gamma):
+    """S(gamma) of the disk-gravity series (Eq. 10)."""
+    return lib().or_dg_series(float(gamma))
+
+
+def disk_gravity(params, R):
+    """Signed radial disk-gravity acceleration at R (positive away from the star)."""
+    pp = make_params(params)
+    return lib().or_disk_gravity(C.byref(pp), float(R))
 
 
 def drag_cd(re, ma, kexp=-2.0):

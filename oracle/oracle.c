@@ -132,9 +132,59 @@ double or_gas_sigma(const or_params* p, double R) {
   return sig;
 }
 
-/* Gas drag on the massless bodies (Sect. 3.1, Eqs. 1, 3, 4, 5, 7), applied to
- * bodies nbig+1..nbod only.  Midplane density at every height; velocity
- * relative to the gas uses the heliocentric velocity u + P/mu0.            */
+/* Disk gravity, leading term of the axisymmetric thin-disk treatment (Sect. 3.1,
+ * Eqs. 10-12).  For gamma != 1 the radial force is 2 pi G Sigma(R) S(gamma) with
+ *   S(gamma) = sum_{n>=0} A_n (1-gamma)(4n+1) / ((2n+2-gamma)(2n-1+gamma)),
+ *   A_n = [(2n)! / (2^{2n} (n!)^2)]^2   (Eq. 10);
+ * for gamma = 1 the leading term of the inner-edge series, 2 pi G Sigma(R) R_in/R
+ * (Eqs. 11-12).  The series is summed term by term for n < 2^20 (A_n from
+ * A_{n-1} by the factor ((2n-1)/(2n))^2) and the rest is added from the large-n
+ * form of its terms, (1-gamma)/(pi n^2) (1 - 1/(2n) + O(n^-2)), whose sum from N
+ * on is (1-gamma)/pi (1/N + 1/(4N^2)) + O(N^-3).                            */
+double or_dg_series(double gamma) {
+  const long N = 1L << 20;
+  double A = 1.0, sum = 0.0;
+  for (long n = 0; n < N; ++n) {
+    if (n > 0) {
+      double r = (2.0 * n - 1.0) / (2.0 * n);
+      A *= r * r;
+    }
+    double t = A * (1.0 - gamma) * (4.0 * n + 1.0) /
+               ((2.0 * n + 2.0 - gamma) * (2.0 * n - 1.0 + gamma));
+    sum += t;
+  }
+  double Nd = (double)N;
+  return sum + (1.0 - gamma) / PI * (1.0 / Nd + 1.0 / (4.0 * Nd * Nd));
+}
+
+/* The printed F_DG read as the signed cylindrical-radial acceleration, positive
+ * away from the star, in AU day^-2 for Sigma of Eq. 1 (zero inside r_in): the
+ * gamma -> 1 limit of the Eq. 10 series is -1, the inward pull 2 pi G Sigma of
+ * an infinite disk with Sigma ~ 1/R, which fixes the sign.                  */
+static double dg_cached_gamma = -1e300, dg_cached_S = 0.0;
+
+static double dg_series_cached(double gamma) {
+  if (gamma != dg_cached_gamma) {
+    dg_cached_S = or_dg_series(gamma);
+    dg_cached_gamma = gamma;
+  }
+  return dg_cached_S;
+}
+
+double or_disk_gravity(const or_params* p, double R) {
+  double sig = or_gas_sigma(p, R) * (p->rho_unit / p->au_cm); /* Msun/AU^2 */
+  if (!(sig > 0.0)) return 0.0;
+  double f = 2.0 * PI * p->G * sig;
+  if (p->gamma == 1.0) return f * p->r_in / R;
+  return f * dg_series_cached(p->gamma);
+}
+
+/* Gas acceleration of the massless bodies (Sect. 3.1, Eqs. 1-7 and 10-12),
+ * applied to bodies nbig+1..nbod only: the drag of Eq. 3, plus the disk gravity
+ * when dg_mode is set.  Midplane density at every height; the velocity relative
+ * to the gas uses the heliocentric velocity u + P/mu0.  The sound speed is
+ * h_over_r v_K, or with a temperature profile sqrt(cs2_per_k T(R)) (Eq. 2); the
+ * scale height is c_s/Omega; eta is fixed or from Eq. 6 with gamma_C = 7/5.    */
 void or_drag(const or_params* p, int n, int nb, const double* x, const double* u,
              const double* mu, const double* r_p, const double* rho_p, double* a) {
   double mu0 = p->G * p->m0;
@@ -146,6 +196,7 @@ void or_drag(const or_params* p, int n, int nb, const double* x, const double* u
   }
   double sx = px / mu0, sy = py / mu0, sz = pz / mu0;
   double sigma_unit = p->rho_unit / p->au_cm; /* Msun/AU^2 per g/cm^2 */
+  if (p->dg_mode && p->gas_on && p->gamma != 1.0) dg_series_cached(p->gamma);
 #pragma omp parallel for schedule(static)
   for (int t = 0; t < n; ++t) {
     a[t] = a[n + t] = a[2 * n + t] = 0.0;
@@ -154,14 +205,26 @@ void or_drag(const or_params* p, int n, int nb, const double* x, const double* u
     double X = x[t], Y = x[n + t];
     double R = sqrt(X * X + Y * Y);
     if (!(R > 0.0) || R < p->r_in) continue;
-    double vk = sqrt(mu0 / R);
-    double om = vk / R;
-    double hg = p->h_over_r * R;
-    double cs = hg * om;
     double sig = or_gas_sigma(p, R) * sigma_unit;
     if (!(sig > 0.0)) continue;
+    if (p->dg_mode) {
+      double g = or_disk_gravity(p, R);
+      a[t] += g * X / R;
+      a[n + t] += g * Y / R;
+    }
+    double vk = sqrt(mu0 / R);
+    double om = vk / R;
+    double cs;
+    if (p->temp_1au > 0.0)
+      cs = sqrt(p->cs2_per_k * p->temp_1au * pow(R, -p->temp_beta));
+    else
+      cs = p->h_over_r * vk;
+    double hg = cs / om;
+    double eta = p->eta;
+    if (p->eta_mode)
+      eta = (p->gamma + 0.5 * p->temp_beta + 1.5) / (2.0 * 1.4) * (cs / vk) * (cs / vk);
     double rhog = sig / (sqrt(2.0 * PI) * hg);
-    double vg = vk * sqrt(1.0 - 2.0 * p->eta);
+    double vg = vk * sqrt(1.0 - 2.0 * eta);
     double gx = -vg * Y / R, gy = vg * X / R;
     double dvx = u[t] + sx - gx;
     double dvy = u[n + t] + sy - gy;
@@ -174,9 +237,9 @@ void or_drag(const or_params* p, int n, int nb, const double* x, const double* u
     double re = 2.0 * r_p[j] * dv / nu;
     double cd = or_drag_cd(re, ma, p->kdrag_exp);
     double f = -(3.0 / 8.0) * (cd / r_p[j]) * (rhog / rho_p[j]) * dv;
-    a[t] = f * dvx;
-    a[n + t] = f * dvy;
-    a[2 * n + t] = f * dvz;
+    a[t] += f * dvx;
+    a[n + t] += f * dvy;
+    a[2 * n + t] += f * dvz;
   }
 }
 

@@ -25,6 +25,12 @@ typedef struct {
   int32_t n_big, n_small, gas_on, pad;
   double sigma1, gamma, r_c, r_in, h_over_r, eta;
   double kdrag_exp, rho_unit, au_cm, mfp_coef;
+  /* Sect. 3.1 extensions: midplane temperature T = temp_1au (R/1 AU)^-temp_beta
+   * (Eq. 2; temp_1au = 0 keeps c_s = h_over_r v_k), isothermal c_s^2 = cs2_per_k T;
+   * eta_mode 1: eta(R) of Eq. 6 instead of the fixed eta; dg_mode 1: disk gravity
+   * (Eqs. 10-12) on the massless bodies.                                      */
+  double temp_1au, temp_beta, cs2_per_k;
+  int32_t eta_mode, dg_mode;
 } or_params;
 
 typedef struct or_sys or_sys;
@@ -57,6 +63,8 @@ void or_drag(const or_params* p, int n, int n_big, const double* x, const double
              const double* mu, const double* r_p, const double* rho_p, double* a);
 double or_drag_cd(double re, double ma, double kexp);
 double or_gas_sigma(const or_params* p, double R);
+double or_dg_series(double gamma);
+double or_disk_gravity(const or_params* p, double R);
 int or_drift(double mu0, const double x0[3], const double v0[3], double h, double x1[3],
              double v1[3]);
 double or_pair_dmin2(const double r0[3], const double w0[3], const double r1[3],

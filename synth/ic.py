@@ -43,6 +43,9 @@ MU_MOL = 2.34
 M_H_G = 1.6735575e-24                 # g
 SIGMA_H2_CM2 = 2.0e-15                # cm^2
 MFP_COEF = MU_MOL * M_H_G * RHO_UNIT / (SIGMA_H2_CM2 * AU_CM)
+# isothermal sound speed squared per kelvin, k_B / (mu_mol m_H), in AU^2 day^-2 K^-1
+K_BOLTZ = 1.380649e-16                # erg/K
+CS2_PER_K = K_BOLTZ / (MU_MOL * M_H_G) * (86400.0 / AU_CM) ** 2
 
 
 @dataclass
@@ -67,7 +70,8 @@ def default_params(**kw) -> dict:
     p = dict(G=G, m0=1.0, dt=1.0, rcrit_hill=3.0, bs_tol=1e-12,
              n_big=0, n_small=0, gas_on=0,
              sigma1=1700.0, gamma=1.0, r_c=0.0, r_in=0.0, h_over_r=0.05, eta=0.002,
-             kdrag_exp=-2.0, rho_unit=RHO_UNIT, au_cm=AU_CM, mfp_coef=MFP_COEF)
+             kdrag_exp=-2.0, rho_unit=RHO_UNIT, au_cm=AU_CM, mfp_coef=MFP_COEF,
+             temp_1au=0.0, temp_beta=0.5, cs2_per_k=CS2_PER_K, eta_mode=0, dg_mode=0)
     p.update(kw)
     return p
 

@@ -313,6 +313,102 @@ def test_drag_follows_sigma_of_the_general_disk(orc):
         assert abs(ratio - ref) <= 1e-9 * ref, (R, ratio, ref)
 
 
+# ------------------------------------------------- Eqs. 2, 6, 10-12 (disk model)
+@pytest.mark.parametrize("gamma", [0.3, 0.5, 0.8, 0.95, 1.05, 1.2, 1.5, 1.8])
+def test_dg_series_closed_form(orc, gamma):
+    """The series of Eq. 10 has the closed form of the razor-thin power-law disk,
+    S(g) = -Gamma((1+g)/2) Gamma(1-g/2) / (Gamma(g/2) Gamma((3-g)/2)) (the radial
+    force of Sigma ~ R^-g over 2 pi G Sigma; -1 for the Mestel disk g = 1)."""
+    from scipy.special import gamma as G_
+    ref = -G_((1 + gamma) / 2) * G_(1 - gamma / 2) / (G_(gamma / 2) * G_((3 - gamma) / 2))
+    assert abs(orc.dg_series(gamma) - ref) <= 1e-12 * abs(ref), (orc.dg_series(gamma), ref)
+
+
+def test_disk_gravity_edge_term_and_direction(orc):
+    """gamma = 1: 2 pi G Sigma(R) R_in / R (Eq. 12), radial in the midplane, away from
+    the star; gamma != 1: 2 pi G Sigma S(gamma).  Added on top of the drag."""
+    p = dict(ic.default_params(n_big=1, n_small=2, gas_on=1), r_in=0.8)
+    x = np.zeros((3, 3)); u = np.zeros((3, 3))
+    x[:, 0] = [25.0, 0, 0]
+    mu = np.array([1e-14])
+    x[:, 1] = [1.2, 1.6, 0.03]           # R = 2
+    x[:, 2] = [-3.0, 0.0, -0.02]          # R = 3
+    for t in (1, 2):
+        R = np.hypot(x[0, t], x[1, t])
+        u[:, t] = [-x[1, t] / R * math.sqrt(MU0 / R), x[0, t] / R * math.sqrt(MU0 / R), 1e-4]
+    r_p = np.full(2, 20 * ic.KM_AU); rho = np.full(2, 1.5 * ic.RHO_UNIT)
+    base = orc.drag(p, x, u, mu, r_p, rho, 1)
+    for gamma, r_c in ((1.0, 0.0), (0.8, 12.0)):
+        q = dict(p, gamma=gamma, r_c=r_c)
+        a0 = orc.drag(q, x, u, mu, r_p, rho, 1)
+        a1 = orc.drag(dict(q, dg_mode=1), x, u, mu, r_p, rho, 1)
+        for t in (1, 2):
+            R = np.hypot(x[0, t], x[1, t])
+            sig = orc.gas_sigma(q, R) * ic.RHO_UNIT / ic.AU_CM
+            mag = 2 * math.pi * ic.G * sig * (0.8 / R if gamma == 1.0 else orc.dg_series(gamma))
+            ref = mag * np.array([x[0, t] / R, x[1, t] / R, 0.0])
+            assert np.allclose(a1[:, t] - a0[:, t], ref, rtol=1e-12, atol=1e-14 * abs(mag))
+            assert abs(orc.disk_gravity(q, R) - mag) <= 1e-14 * abs(mag)
+    assert np.array_equal(orc.drag(p, x, u, mu, r_p, rho, 1), base)
+    assert orc.disk_gravity(dict(p, r_in=0.0), 2.0) == 0.0     # gamma = 1, no inner edge
+
+
+def _cs_equivalent_temperature(h_over_r):
+    """T0 of a beta = 1 profile whose sound speed is h_over_r v_K at every R:
+    cs2_per_k T0 R^-1 = h_over_r^2 mu0 / R."""
+    return h_over_r ** 2 * MU0 / ic.CS2_PER_K
+
+
+def test_temperature_profile_with_beta_one_is_the_constant_aspect_ratio_disk(orc):
+    """T = T0 (R / 1 AU)^-1 (Eq. 2) gives c_s / v_K = const: with T0 chosen so that
+    c_s = 0.05 v_K the drag equals that of the H/r = 0.05 disk everywhere."""
+    p = ic.default_params(n_big=1, n_small=6, gas_on=1)
+    x, u, mu, r_p, rho = _drag_setup(p, ns=6)
+    rng = np.random.default_rng(4)
+    for t in range(1, 7):
+        R = rng.uniform(0.7, 9.0)
+        ph = rng.uniform(0, 2 * math.pi)
+        x[:, t] = [R * math.cos(ph), R * math.sin(ph), 0.01]
+        u[:, t] = [-math.sin(ph), math.cos(ph), 0.0] * np.array(math.sqrt(MU0 / R)) + rng.normal(0, 3e-5, 3)
+    a0 = orc.drag(p, x, u, mu, r_p, rho, 1)
+    q = dict(p, temp_1au=_cs_equivalent_temperature(0.05), temp_beta=1.0, h_over_r=0.3)
+    a1 = orc.drag(q, x, u, mu, r_p, rho, 1)
+    assert np.allclose(a1, a0, rtol=1e-12, atol=0)
+    assert q["temp_1au"] > 100 and q["temp_1au"] < 1000   # a plausible disk temperature
+
+
+def test_eta_of_eq6(orc):
+    """Eq. 6 with c_s / v_K = 0.05 (gamma = 1, beta = 1): eta = (1 + 1/2 + 3/2) / (2 x 7/5)
+    x 0.05^2 = 0.00267857...; the eta_mode drag equals the fixed-eta drag with that
+    value, and vanishes for a body moving with that gas."""
+    p = ic.default_params(n_big=1, n_small=3, gas_on=1)
+    x, u, mu, r_p, rho = _drag_setup(p)
+    q = dict(p, temp_1au=_cs_equivalent_temperature(0.05), temp_beta=1.0, eta_mode=1)
+    eta = 3.0 / 2.8 * 0.0025
+    assert abs(eta - 0.0026785714285714286) < 1e-18
+    u[:, 0] = 0.0
+    for j, (R, ph) in enumerate([(1.1, 0.2), (4.0, 2.5), (8.5, -1.0)]):
+        t = 1 + j
+        x[:, t] = [R * math.cos(ph), R * math.sin(ph), 0.0]
+        vg = math.sqrt(MU0 / R) * math.sqrt(1 - 2 * eta)
+        u[:, t] = [-vg * math.sin(ph), vg * math.cos(ph), 0.0]
+    # on the gas velocity only rounding of dv is left (dv ~ 1e-16 v_K against 1e-3 v_K
+    # below); with the Stokes exponent -1 the drag is linear in dv at low Re
+    stokes = dict(q, kdrag_exp=-1.0)
+    a_zero = orc.drag(stokes, x, u, mu, r_p, rho, 1)
+    u[:, 1:] *= 1.001
+    a_lin = orc.drag(stokes, x, u, mu, r_p, rho, 1)
+    assert np.all(np.abs(a_zero[:, 1:]) <= 1e-10 * np.abs(a_lin[:, 1:]).max())
+    a_mode = orc.drag(q, x, u, mu, r_p, rho, 1)
+    a_fix = orc.drag(dict(q, eta_mode=0, eta=eta), x, u, mu, r_p, rho, 1)
+    assert np.allclose(a_mode, a_fix, rtol=1e-12, atol=0)
+    # another slope: (gamma + beta/2 + 3/2) scales eta
+    q2 = dict(q, gamma=0.5, temp_beta=1.0)
+    a2 = orc.drag(q2, x, u, mu, r_p, rho, 1)
+    a2f = orc.drag(dict(q2, eta_mode=0, eta=2.5 / 2.8 * 0.0025), x, u, mu, r_p, rho, 1)
+    assert np.allclose(a2, a2f, rtol=1e-12, atol=0)
+
+
 # ------------------------------------------------------------ Kepler drift
 def _two_body_ode(mu, x0, v0, h):
     def f(t, y):
