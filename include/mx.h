@@ -75,6 +75,15 @@ typedef struct {
   double rho_unit;    /* Msun AU^-3 per g cm^-3 */
   double au_cm;       /* cm per AU */
   double mfp_coef;    /* mean free path lambda[AU] = mfp_coef / rho_gas[Msun AU^-3] */
+  /* Further disk physics of Sect. 3.1 (all off when zero): */
+  double temp_1au;    /* midplane temperature at 1 AU, K (Eq. 2); 0 = c_s = h_over_r v_K */
+  double temp_beta;   /* slope beta of T = temp_1au (R / 1 AU)^-beta */
+  double cs2_per_k;   /* isothermal c_s^2 per kelvin, AU^2 day^-2 K^-1 (k_B / mu m_H) */
+  int32_t eta_mode;   /* 1: eta(R) of Eq. 6 (gamma_C = 7/5) instead of the fixed eta */
+  int32_t dg_mode;    /* 1: disk gravity of Eqs. 10-12 on the massless bodies, as the
+                         signed radial acceleration (positive away from the star):
+                         2 pi G Sigma S(gamma) for gamma != 1 (0 < gamma < 2), and
+                         2 pi G Sigma r_in / R for gamma = 1 */
 } mx_params;
 
 /* ---------------------------------------------------------------- system */
@@ -281,7 +290,8 @@ void mx_destroy_adjoint(mx_adjoint* a);
 mx_status mx_gravity(int32_t n, int32_t n_big, const double* x, const double* mu,
                      const double* rcrit, double* a, void* hip_stream);
 
-/* Gas drag (Sect. 3.1, Eqs. 1-7) on bodies t >= n_big; a[t] = 0 for big bodies.
+/* Gas acceleration (Sect. 3.1: drag of Eqs. 1-7, and with dg_mode the disk gravity of
+ * Eqs. 10-12) on bodies t >= n_big; a[t] = 0 for big bodies.
  * u: barycentric velocities; mu: device [n_big] (for the heliocentric shift);
  * r_p: AU; rho_p: Msun AU^-3.  All device pointers. */
 mx_status mx_gas_drag(const mx_params* p, int32_t n, int32_t n_big, const double* x,

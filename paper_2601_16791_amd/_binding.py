@@ -29,14 +29,20 @@ class Params(C.Structure):
                 ("sigma1", C.c_double), ("gamma", C.c_double), ("r_c", C.c_double),
                 ("r_in", C.c_double), ("h_over_r", C.c_double), ("eta", C.c_double),
                 ("kdrag_exp", C.c_double), ("rho_unit", C.c_double), ("au_cm", C.c_double),
-                ("mfp_coef", C.c_double)]
+                ("mfp_coef", C.c_double),
+                ("temp_1au", C.c_double), ("temp_beta", C.c_double), ("cs2_per_k", C.c_double),
+                ("eta_mode", C.c_int32), ("dg_mode", C.c_int32)]
+
+
+# fields a parameter dict may leave out (the disk physics beyond the plain drag is off)
+_OPTIONAL = {"temp_1au": 0.0, "temp_beta": 0.0, "cs2_per_k": 0.0, "eta_mode": 0, "dg_mode": 0}
 
 
 def make_params(p: dict) -> Params:
     q = Params()
     for name, _ in Params._fields_:
         if name != "pad":
-            setattr(q, name, p[name])
+            setattr(q, name, p[name] if name in p else _OPTIONAL[name])
     return q
 
 

@@ -63,6 +63,31 @@ __device__ __forceinline__ double pow_kexp(double b, double kexp) {
   return pow(b, kexp);
 }
 
+// Sound speed, midplane density and gas speed of the general disk (c.ext): c_s
+// from T(R) = T0 (R/1AU)^-beta (Eq. 2) or h_over_r v_K; scale height c_s/Omega;
+// eta fixed or eta(R) of Eq. 6; and the disk gravity of Eqs. 10-12 (signed radial,
+// positive away from the star) into (gx, gy).
+__device__ __noinline__ void gas_general(const DragConst& c, double X, double Y, double R,
+                                         double inv_R, double vk, double sig, double& cs,
+                                         double& rhog, double& vg, double& gx, double& gy) {
+  if (c.cs2_1au > 0.0) cs = sqrt(c.cs2_1au * pow(R, -c.beta));
+  else cs = c.h_over_r * vk;
+  // rho_g = Sigma / (sqrt(2 pi) c_s / Omega) = Sigma v_K / (sqrt(2 pi) c_s R)
+  rhog = sig * vk * inv_R / (kSqrt2Pi * cs);
+  double eta = c.eta;
+  if (c.eta6_fac != 0.0) {
+    const double m = cs / vk;
+    eta = c.eta6_fac * m * m;
+  }
+  vg = vk * sqrt(1.0 - 2.0 * eta);
+  gx = gy = 0.0;
+  if (c.dg_fac != 0.0) {
+    const double g = c.dg_edge ? c.dg_fac * sig * inv_R : c.dg_fac * sig;
+    gx = g * X * inv_R;
+    gy = g * Y * inv_R;
+  }
+}
+
 __device__ __forceinline__ void gas_drag(const DragConst& c, double X, double Y, double vx,
                                          double vy, double vz, double r_p, double rho_p,
                                          double& ax, double& ay, double& az) {
@@ -76,14 +101,21 @@ __device__ __forceinline__ void gas_drag(const DragConst& c, double X, double Y,
   if (!(R > 0.0) || R < c.r_in) return;
   double inv_R = 1.0 / R;
   double vk = sqrt(c.mu0 * inv_R);
-  double cs = c.h_over_r * vk;
   double sig;
   if (c.gamma == 1.0) sig = c.sigma1_unit * inv_R;
   else sig = c.sigma1_unit * pow(R, -c.gamma);
   if (c.r_c > 0.0) sig *= exp(c.rc_norm - pow(R * c.inv_rc, 2.0 - c.gamma));
   if (!(sig > 0.0)) return;
-  double rhog = sig * inv_R * c.rho_fac;
-  double vg = vk * c.vg_fac;
+  double cs, rhog, vg, gx = 0.0, gy = 0.0;
+  if (__builtin_expect(c.ext != 0, 0)) {
+    gas_general(c, X, Y, R, inv_R, vk, sig, cs, rhog, vg, gx, gy);
+    ax = gx;
+    ay = gy;
+  } else {
+    cs = c.h_over_r * vk;
+    rhog = sig * inv_R * c.rho_fac;
+    vg = vk * c.vg_fac;
+  }
   double dvx = vx + vg * Y * inv_R;
   double dvy = vy - vg * X * inv_R;
   double dvz = vz;
@@ -96,8 +128,8 @@ __device__ __forceinline__ void gas_drag(const DragConst& c, double X, double Y,
   double inner = re * (10.0 + re) / fma(64.0, re, 240.0) + 0.23 * ma;
   double cd = pow_kexp(inner, c.kexp) + 2.0 * (0.8 * k + ma) / (1.6 + ma);
   double f = -0.375 * cd * rhog * dv / (r_p * rho_p);
-  ax = f * dvx;
-  ay = f * dvy;
+  ax = fma(f, dvx, gx);
+  ay = fma(f, dvy, gy);
   az = f * dvz;
 }
 

@@ -221,6 +221,11 @@ mx_status check_params(const mx_params* p) {
   if (p->gas_on && !(p->h_over_r > 0.0 && p->rho_unit > 0.0 && p->au_cm > 0.0 &&
                      p->mfp_coef > 0.0 && p->eta < 0.5))
     return fail(MX_EINVAL, "gas parameters out of range");
+  if (!(p->temp_1au >= 0.0) || (p->temp_1au > 0.0 && !(p->cs2_per_k > 0.0)) ||
+      (p->eta_mode != 0 && p->eta_mode != 1) || (p->dg_mode != 0 && p->dg_mode != 1) ||
+      (p->dg_mode && p->gamma != 1.0 && !(p->gamma > 0.0 && p->gamma < 2.0)))
+    return fail(MX_EINVAL, "disk parameters out of range (temp_1au >= 0 with cs2_per_k > 0, "
+                           "eta_mode and dg_mode 0 or 1, disk gravity needs 0 < gamma < 2)");
   return MX_OK;
 }
 
@@ -1260,6 +1265,9 @@ mx_status mx_adjoint_create(const mx_params* p, const double* x_h, const double*
   if (!p || n_steps < 1 || checkpoint_every < 1)
     return fail(MX_EINVAL, "need params, n_steps >= 1 and checkpoint_every >= 1");
   if (p->n_big > kSmallBig) return fail(MX_EINVAL, "the adjoint needs n_big <= 64");
+  if (p->temp_1au > 0.0 || p->eta_mode || p->dg_mode)
+    return fail(MX_EINVAL, "the adjoint supports the constant aspect-ratio disk with fixed "
+                           "eta and no disk gravity");
   if (hip_stream == nullptr) return fail(MX_EINVAL, "the adjoint needs a non-default stream");
   mx_adjoint* a = new mx_adjoint();
   std::memset((void*)a, 0, sizeof(mx_adjoint));

@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 #include <hip/hip_ext.h>
 #include <math.h>
 #include <stdint.h>
@@ -72,11 +74,36 @@ struct DragConst {
   double rc_norm;  // (1/r_c)^(2-gamma), the normalisation of the taper at 1 AU
   double rho_fac;  // 1 / (sqrt(2 pi) H/r): midplane density = Sigma / R * rho_fac
   double re_fac;   // 6 / (sqrt(8/pi) mfp_coef): Re = re_fac r_p dv rho_g / c_s
+  // disk model beyond the constant aspect ratio (ext != 0)
+  double cs2_1au;   // c_s^2 at 1 AU from the temperature (0: c_s = h_over_r v_K)
+  double beta;      // temperature slope
+  double eta;       // fixed eta
+  double eta6_fac;  // (gamma + beta/2 + 3/2) / (2 gamma_C), or 0 for the fixed eta
+  double dg_fac;    // disk gravity per unit Sigma: 2 pi G S(gamma), or 2 pi G r_in / R
+                    // per unit Sigma / R for gamma = 1; 0 = off
+  int ext, dg_edge;
 };
+
+// S(gamma) of the disk-gravity series of Eq. 10 through its closed form for a
+// power-law disk, -Gamma((1+g)/2) Gamma(1-g/2) / (Gamma(g/2) Gamma((3-g)/2)),
+// valid for 0 < g < 2.
+inline double dg_series_closed(double g) {
+  return -std::tgamma(0.5 * (1.0 + g)) * std::tgamma(1.0 - 0.5 * g) /
+         (std::tgamma(0.5 * g) * std::tgamma(0.5 * (3.0 - g)));
+}
 
 // Drag constants of a parameter set (host side).
 inline DragConst make_drag_const(const mx_params& p) {
   DragConst c;
+  const double kTwoPi = 6.283185307179586;
+  c.cs2_1au = p.temp_1au > 0.0 ? p.cs2_per_k * p.temp_1au : 0.0;
+  c.beta = p.temp_beta;
+  c.eta = p.eta;
+  c.eta6_fac = p.eta_mode ? (p.gamma + 0.5 * p.temp_beta + 1.5) / (2.0 * 1.4) : 0.0;
+  c.dg_edge = p.dg_mode && p.gamma == 1.0;
+  c.dg_fac = !p.dg_mode ? 0.0 : (c.dg_edge ? kTwoPi * p.G * p.r_in
+                                          : kTwoPi * p.G * dg_series_closed(p.gamma));
+  c.ext = (c.cs2_1au > 0.0 || p.eta_mode || p.dg_mode) ? 1 : 0;
   c.mu0 = p.G * p.m0;
   c.sigma1_unit = p.sigma1 * (p.rho_unit / p.au_cm);
   c.gamma = p.gamma;

@@ -31,10 +31,22 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libmx.so not built")
-def test_params_struct_layout_matches_header():
+def test_params_struct_layout_matches_header(tmp_path):
+    """The binding's mx_params has the header's fields, sizes and offsets (the header
+    compiled with the host C compiler)."""
+    import subprocess
     import paper_2601_16791_amd as mx
-    # 5 doubles, 4 int32, 10 doubles
-    assert ctypes.sizeof(mx.Params) == 5 * 8 + 4 * 4 + 10 * 8
+    names = [f for f, _ in mx.Params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mx.h"\nint main(void){\n'
+                   'printf("%zu\\n", sizeof(mx_params));\n' +
+                   "".join(f'printf("%zu\\n", offsetof(mx_params, {f}));\n' for f in names) +
+                   "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert got[0] == ctypes.sizeof(mx.Params)
+    assert got[1:] == [getattr(mx.Params, f).offset for f in names]
     text = open(HEADER).read()
     body = text[text.index("typedef struct {", text.index("mx_status;")):text.index("} mx_params;")]
     fields = re.findall(r"\b(?:double|int32_t)\s+([A-Za-z0-9_]+)\s*;", body)

@@ -583,3 +583,56 @@ def test_step_parity_crowded_annulus(mx, orc, nb, ns, close):
         bigbig += int(np.sum(po[:, 1] < nb)) if len(po) else 0
         pairs += check_step(g, o, nb, sx, su, label=f"crowded nb={nb} ns={ns} step {k}")[0]
     assert pairs > 20 and bigbig > 0
+
+
+# ----------------------------------------------- disk model of Sect. 3.1 (Eqs. 2, 6, 10-12)
+DISK_MODES = {
+    "temperature": dict(temp_1au=280.0, temp_beta=0.5),
+    "eta_eq6": dict(temp_1au=200.0, temp_beta=0.75, eta_mode=1),
+    "gravity_edge": dict(dg_mode=1, r_in=1.3),
+    "gravity_series": dict(dg_mode=1, gamma=0.8, r_c=15.0, r_in=0.6),
+    "all": dict(temp_1au=250.0, temp_beta=0.6, eta_mode=1, dg_mode=1, gamma=1.2, r_c=20.0,
+                r_in=0.9),
+}
+
+
+@pytest.mark.parametrize("mode", sorted(DISK_MODES))
+def test_gas_kernel_disk_model_matches_oracle(mx, orc, mode):
+    """Drag plus disk gravity of the general disk on the massless bodies, every body
+    against the oracle."""
+    w = ic.embryo_disk(seed=21, n_small=4000, n_emb=5)
+    p = dict(w.params, **DISK_MODES[mode])
+    o = orc.OracleSystem(p, w.x, w.v, w.m_big, w.r_p, w.rho_p)
+    x, u = o.get_dh()
+    mu, _ = o.mu()
+    rho = w.rho_p * ic.RHO_UNIT
+    a_o = orc.drag(p, x, u, mu, w.r_p, rho, p["n_big"])
+    a_g = mx.gas_drag(p, x, u, mu, w.r_p, rho, p["n_big"]).cpu().numpy()
+    nb = p["n_big"]
+    assert np.all(a_g[:, :nb] == 0)
+    assert np.any(a_o[:, nb:] != 0)
+    assert relerr_rows(a_g[:, nb:], a_o[:, nb:]) < 1e-12
+
+
+def test_step_parity_disk_model(mx, orc):
+    """Whole steps with the temperature profile, eta(R), a tapered gamma != 1 disk with
+    an inner edge and disk gravity; each step from the same state on both sides."""
+    w = ic.embryo_disk(seed=22, n_small=3000, n_emb=6)
+    w.params = dict(w.params, **DISK_MODES["all"])
+    g = mx.System.from_workload(w)
+    o = orc.OracleSystem.from_workload(w)
+    nb = w.params["n_big"]
+    x, u = g.get_dh()
+    o.set_dh(x, u, 0)
+    g.set_dh(x, u, 0)
+    pairs = 0
+    for k in range(5):
+        x, u = g.get_dh()
+        g.step(1)
+        g.sync()
+        xo, uo, sx, su = oracle_sensitivity(o, x, u, k)
+        pairs += check_step(g, o, nb, sx, su, label=f"disk model step {k}")[0]
+    assert pairs > 0
+    with pytest.raises(mx.MxError) as e:
+        mx.Adjoint(w.params, w.x, w.v, w.m_big, w.r_p, w.rho_p, 2, 1)
+    assert e.value.code == -1
