@@ -52,6 +52,21 @@ class _Params(C.Structure):
                 ("eta_mode", C.c_int32), ("dg_mode", C.c_int32)]
 
 
+class Planet(C.Structure):
+    """Time-dependent physics of one massive body (or_planet)."""
+    _fields_ = [(f, C.c_double) for f in
+                ("M0", "Mc", "tau_c", "Mf", "tau_g", "R_I", "da1", "tau1", "da2", "tau2", "gap_C")]
+
+
+def make_planets(rows):
+    """rows: sequence of dicts with the Planet fields (missing ones 0)."""
+    arr = (Planet * len(rows))()
+    for k, r in enumerate(rows):
+        for f, _ in Planet._fields_:
+            setattr(arr[k], f, float(r.get(f, 0.0)))
+    return arr
+
+
 def make_params(p: dict) -> _Params:
     q = _Params()
     for name, _ in _Params._fields_:
@@ -127,6 +142,16 @@ def _declare(L):
     L.or_gas_sigma.argtypes = [C.POINTER(_Params), C.c_double]
     L.or_last_pair_dmin2.restype = C.c_double
     L.or_last_pair_dmin2.argtypes = [C.c_void_p, C.c_int, C.c_int, _D]
+    L.or_set_physics.argtypes = [C.c_void_p, C.POINTER(Planet), C.c_double, C.c_double]
+    L.or_get_radii.argtypes = [C.c_void_p, _D]
+    L.or_time.restype = C.c_double
+    L.or_time.argtypes = [C.c_void_p]
+    L.or_step_size.restype = C.c_double
+    L.or_step_size.argtypes = [C.c_void_p]
+    L.or_set_xu.argtypes = [C.c_void_p, _D, _D]
+    L.or_get_gaps.argtypes = [C.c_void_p, _D]
+    L.or_drag_gaps.argtypes = [C.POINTER(_Params), C.c_int, C.c_int, _D, _D, _D, _D, _D, _D,
+                               C.POINTER(C.c_int), _D]
     L.or_threads.restype = C.c_int
     L.or_threads.argtypes = []
 
@@ -221,6 +246,36 @@ class OracleSystem:
         d = self._L.or_last_pair_dmin2(self._h, int(i), int(j), C.byref(rc2))
         return d, rc2.value
 
+    def set_physics(self, planets, a_switch=0.0, a_min=0.0):
+        """Growth, radius, migration and gap of every massive body (list of dicts
+        with the Planet fields) and the step switch."""
+        self._planets = make_planets(planets)
+        st = self._L.or_set_physics(self._h, self._planets, float(a_switch), float(a_min))
+        if st != OR_OK:
+            raise ValueError(f"oracle set_physics failed: {st}")
+
+    def radii(self):
+        r = np.zeros(max(self.nb, 1))
+        self._L.or_get_radii(self._h, _p(r))
+        return r[: self.nb]
+
+    def time(self):
+        return self._L.or_time(self._h)
+
+    def step_size(self):
+        return self._L.or_step_size(self._h)
+
+    def gaps(self):
+        """[nb, 4]: centre R, half width, density factor, open (1/0) of each gap."""
+        g = np.zeros(4 * max(self.nb, 1))
+        self._L.or_get_gaps(self._h, _p(g))
+        return g[: 4 * self.nb].reshape(-1, 4)
+
+    def set_xu(self, x, u):
+        """Replace positions and velocities only (time and physics state kept)."""
+        x, u = _d(x), _d(u)
+        self._L.or_set_xu(self._h, _p(x), _p(u))
+
     def set_rcrit(self, rcrit):
         """Hold the changeover radii at the given values (FSAL force refreshed)."""
         rc = _d(rcrit)
@@ -266,6 +321,19 @@ def disk_gravity(params, R):
     """Signed radial disk-gravity acceleration at R (positive away from the star)."""
     pp = make_params(params)
     return lib().or_disk_gravity(C.byref(pp), float(R))
+
+
+def drag_gaps(params, x, u, mu, r_p, rho_p_internal, nb, gaps, gap_on):
+    """Gas acceleration with the density factors of open gaps (gaps [nb, 3]: centre R,
+    half width, factor; gap_on [nb])."""
+    x = _d(x); u = _d(u); mu = _d(mu); rp = _d(r_p); rh = _d(rho_p_internal)
+    g = _d(gaps); on = np.ascontiguousarray(gap_on, dtype=np.int32)
+    n = x.shape[1]
+    a = np.zeros((3, n))
+    pp = make_params(params)
+    lib().or_drag_gaps(C.byref(pp), n, nb, _p(x), _p(u), _p(mu), _p(rp), _p(rh), _p(g),
+                       on.ctypes.data_as(C.POINTER(C.c_int)), _p(a))
+    return a
 
 
 def drag_cd(re, ma, kexp=-2.0):

@@ -45,6 +45,14 @@ struct or_sys {
   int npairs, cap_pairs;
   double *x0, *u0, *x1, *u1, *ad;   /* scratch [3][n] */
   double *x1k, *u1k;                /* last step's post-drift state before BS [3][n] */
+  /* time-dependent physics (or_set_physics) */
+  or_planet* phys;                  /* [nb] or NULL */
+  double *radius, *rad_c;           /* [nb] planet radius; radius at the start of the runaway */
+  double* gaps;                     /* [nb][3] gap centre R, half width, density factor; */
+  int* gap_on;                      /* [nb] 1 while the gap is open */
+  double time, h;                   /* time at the start of the next step; current step */
+  double a_switch, a_min;           /* step switch (a_switch <= 0: none) */
+  int switched;
 };
 
 /* ------------------------------------------------------------------ */
@@ -185,8 +193,20 @@ double or_disk_gravity(const or_params* p, double R) {
  * to the gas uses the heliocentric velocity u + P/mu0.  The sound speed is
  * h_over_r v_K, or with a temperature profile sqrt(cs2_per_k T(R)) (Eq. 2); the
  * scale height is c_s/Omega; eta is fixed or from Eq. 6 with gamma_C = 7/5.    */
+
 void or_drag(const or_params* p, int n, int nb, const double* x, const double* u,
              const double* mu, const double* r_p, const double* rho_p, double* a) {
+  or_drag_gaps(p, n, nb, x, u, mu, r_p, rho_p, NULL, NULL, a);
+}
+
+/* gaps, gap_on: the open gaps of the massive bodies (or NULL).  A massless body
+ * at cylindrical R strictly inside (R_gap - w, R_gap + w) of an open gap sees the
+ * gas density times that gap's factor, the gap of the highest index winning (the
+ * dens_factor loop of Sect. 3.1.1); the factor multiplies the midplane density of
+ * the drag only.                                                               */
+void or_drag_gaps(const or_params* p, int n, int nb, const double* x, const double* u,
+                  const double* mu, const double* r_p, const double* rho_p, const double* gaps,
+                  const int* gap_on, double* a) {
   double mu0 = p->G * p->m0;
   double px = 0, py = 0, pz = 0;
   for (int k = 0; k < nb; ++k) {
@@ -224,6 +244,11 @@ void or_drag(const or_params* p, int n, int nb, const double* x, const double* u
     if (p->eta_mode)
       eta = (p->gamma + 0.5 * p->temp_beta + 1.5) / (2.0 * 1.4) * (cs / vk) * (cs / vk);
     double rhog = sig / (sqrt(2.0 * PI) * hg);
+    if (gaps) {
+      for (int i = 0; i < nb; ++i)
+        if (gap_on[i] && R < gaps[3 * i] + gaps[3 * i + 1] && R > gaps[3 * i] - gaps[3 * i + 1])
+          rhog = sig / (sqrt(2.0 * PI) * hg) * gaps[3 * i + 2];
+    }
     double vg = vk * sqrt(1.0 - 2.0 * eta);
     double gx = -vg * Y / R, gy = vg * X / R;
     double dvx = u[t] + sx - gx;
@@ -849,6 +874,118 @@ static void apply_growth(or_sys* s, double t) {
   }
 }
 
+static void momentum(const or_sys* s, const double* u, double P[3]);
+
+/* Sound speed of the disk at cylindrical radius R (as in the drag). */
+static double disk_cs(const or_params* p, double mu0, double R) {
+  if (p->temp_1au > 0.0) return sqrt(p->cs2_per_k * p->temp_1au * pow(R, -p->temp_beta));
+  return p->h_over_r * sqrt(mu0 / R);
+}
+
+/* Planet radius during the solid/atmosphere phase, Eq. 14 (Sect. 3.2):
+ * R_p = G M / (c_s^2 / k1 + G M / (k2 R_H)), k1 = 1, k2 = 1/4.              */
+static double radius_core(double gm, double cs, double rhill) {
+  return gm / (cs * cs / 1.0 + gm / (0.25 * rhill));
+}
+
+/* The time-dependent physics of the massive bodies at the start of a step (time
+ * t = s->time), held through the step:
+ *  - mass: Eq. 13 for t < tau_c; for t >= tau_c, Eq. 15 (runaway gas accretion)
+ *    when tau_g > 0, else M_c; the changeover radius follows the Hill radius,
+ *    rcrit = rcrit_init (M / M_init)^(1/3);
+ *  - radius: Eq. 14 before tau_c with the disk's c_s at the planet's cylindrical
+ *    distance and its Hill radius r (M / 3 m0)^(1/3) at its distance r from the
+ *    star; from tau_c on (with tau_g > 0), Eq. 16 with R_c the Eq. 14 radius at the
+ *    first step of the runaway and Delta R = R_c - R_I;
+ *  - migration: a velocity change along the planet's heliocentric velocity of
+ *    Eq. 17 for t < tau1 and of Eq. 18 for t >= tau1, with a_p the osculating
+ *    semi-major axis (gm = G(m0 + m)) and v_k = sqrt(G (m0 + m) / a_p);
+ *  - gap: open after tau_c (tau_g > 0, gap_C > 0), centred on the planet's
+ *    cylindrical distance, half width gap_C R_H (Eq. 8), density factor
+ *    exp(-(t - tau_c)/tau_g) (Eq. 9);
+ *  - step switch (Sect. 3.6): once a migrating planet's a_p <= a_switch, the step
+ *    becomes 1/25 of the orbital period at a_min, from this step on.          */
+static void apply_physics(or_sys* s) {
+  const double E = 2.718281828459045235;
+  int n = s->n, nb = s->nb;
+  double t = s->time, G = s->p.G, mu0 = s->mu0;
+  for (int k = 0; k < nb; ++k) {
+    const or_planet* q = &s->phys[k];
+    if (!(q->tau_c > 0.0)) continue;
+    double m;
+    if (t < q->tau_c)
+      m = q->M0 + (E / (E - 1.0)) * (q->Mc - q->M0) * (1.0 - exp(-t / q->tau_c));
+    else if (q->tau_g > 0.0)
+      m = q->Mc + (q->Mf - q->Mc) * (1.0 - exp(-(t - q->tau_c) / q->tau_g));
+    else
+      m = q->Mc;
+    s->mu[k] = G * m;
+    s->rcrit[k] = s->rcrit_init[k] * cbrt(s->mu[k] / s->mu_init[k]);
+  }
+  /* heliocentric states and osculating semi-major axes at the step start */
+  double P[3];
+  momentum(s, s->u, P);
+  double* ap = (double*)malloc(sizeof(double) * 5 * (size_t)nb);
+  if (!ap) return;
+  double* rr = ap + nb;      /* distance from the star */
+  double* Rc = ap + 2 * nb;  /* cylindrical distance */
+  double* vn = ap + 3 * nb;  /* |v| heliocentric */
+  double* rh = ap + 4 * nb;  /* Hill radius */
+  int inside = 0;
+  for (int k = 0; k < nb; ++k) {
+    const or_planet* q = &s->phys[k];
+    double x[3] = {s->x[k], s->x[n + k], s->x[2 * n + k]};
+    double v[3];
+    for (int c = 0; c < 3; ++c) v[c] = s->u[c * n + k] + P[c] / mu0;
+    double el[6];
+    or_x2el(mu0 + s->mu[k], x, v, el);
+    ap[k] = el[0];
+    rr[k] = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    Rc[k] = sqrt(x[0] * x[0] + x[1] * x[1]);
+    vn[k] = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    rh[k] = rr[k] * cbrt(s->mu[k] / (3.0 * mu0));
+    if ((q->tau1 > 0.0 || q->tau2 > 0.0) && s->a_switch > 0.0 && ap[k] > 0.0 &&
+        ap[k] <= s->a_switch)
+      inside = 1;
+  }
+  if (inside && !s->switched) {
+    s->h = 2.0 * PI * sqrt(s->a_min * s->a_min * s->a_min / mu0) / 25.0;
+    s->switched = 1;
+  }
+  for (int k = 0; k < nb; ++k) {
+    const or_planet* q = &s->phys[k];
+    /* radius */
+    double cs = disk_cs(&s->p, mu0, Rc[k]);
+    if (q->tau_c > 0.0 && q->tau_g > 0.0 && t >= q->tau_c) {
+      if (s->rad_c[k] == 0.0) s->rad_c[k] = radius_core(s->mu[k], cs, rh[k]);
+      double R0 = s->rad_c[k];
+      s->radius[k] = R0 - (R0 - q->R_I) * (1.0 - exp(-(t - q->tau_c) / q->tau_g));
+    } else {
+      s->radius[k] = radius_core(s->mu[k], cs, rh[k]);
+    }
+    /* gap */
+    s->gap_on[k] = q->gap_C > 0.0 && q->tau_c > 0.0 && q->tau_g > 0.0 && t > q->tau_c;
+    s->gaps[3 * k] = Rc[k];
+    s->gaps[3 * k + 1] = q->gap_C * rh[k];
+    s->gaps[3 * k + 2] = s->gap_on[k] ? exp(-(t - q->tau_c) / q->tau_g) : 1.0;
+    /* migration: velocity change along the heliocentric velocity */
+    if ((q->tau1 > 0.0 || q->tau2 > 0.0) && ap[k] > 0.0) {
+      double vk = sqrt((mu0 + s->mu[k]) / ap[k]);
+      double t1 = q->tau1 > 0.0 ? q->tau1 : 0.0;
+      double dv = 0.0;
+      if (q->tau1 > 0.0 && t < q->tau1)
+        dv = 0.5 * (q->da1 / ap[k]) * (s->h / q->tau1) * vk;
+      else if (q->tau2 > 0.0)
+        dv = 0.5 * (q->da2 / ap[k]) * (s->h / q->tau2) * exp(-(t - t1) / q->tau2) * vk;
+      for (int c = 0; c < 3; ++c) {
+        double vc = s->u[c * n + k] + P[c] / mu0;
+        s->u[c * n + k] += dv * vc / vn[k];
+      }
+    }
+  }
+  free(ap);
+}
+
 static void momentum(const or_sys* s, const double* u, double P[3]) {
   int n = s->n;
   P[0] = P[1] = P[2] = 0.0;
@@ -933,6 +1070,8 @@ or_sys* or_create(const or_params* p, const double* x_h, const double* v_h, cons
     if (rho_p) s->rho_p[j] = rho_p[j] * p->rho_unit;
   }
   s->step = 0;
+  s->time = 0.0;
+  s->h = p->dt;
   refresh_fsal(s);
   *status = OR_OK;
   return s;
@@ -941,14 +1080,16 @@ or_sys* or_create(const or_params* p, const double* x_h, const double* v_h, cons
 void or_destroy(or_sys* s) {
   if (!s) return;
   free(s->x); free(s->u); free(s->ag); free(s->x0); free(s->u0); free(s->x1); free(s->u1);
-  free(s->ad); free(s->x1k); free(s->u1k); free(s->mu); free(s->mu_init); free(s->rcrit); free(s->rcrit_init);
+  free(s->ad); free(s->x1k); free(s->u1k); free(s->mu);
+  free(s->phys); free(s->radius); free(s->rad_c); free(s->gaps); free(s->gap_on); free(s->mu_init); free(s->rcrit); free(s->rcrit_init);
   free(s->r_p); free(s->rho_p); free(s->growth); free(s->pairs);
   free(s);
 }
 
 static void half_kick(or_sys* s, double hh) {
   int n = s->n;
-  or_drag(&s->p, n, s->nb, s->x, s->u, s->mu, s->r_p, s->rho_p, s->ad);
+  or_drag_gaps(&s->p, n, s->nb, s->x, s->u, s->mu, s->r_p, s->rho_p,
+               s->phys ? s->gaps : NULL, s->gap_on, s->ad);
   for (int i = 0; i < 3 * n; ++i) s->u[i] += hh * (s->ag[i] + s->ad[i]);
 }
 
@@ -966,8 +1107,9 @@ static void jump(or_sys* s, double hh) {
 /* One hybrid step (Sect. 2; the kick listing of Sect. 2.1.2 with angf = 0). */
 static int one_step(or_sys* s) {
   int n = s->n;
-  double h = s->p.dt, hh = 0.5 * h;
-  apply_growth(s, s->step * h);
+  if (s->phys) apply_physics(s);
+  else apply_growth(s, s->step * s->p.dt);
+  double h = s->h, hh = 0.5 * h;
   half_kick(s, hh);
   jump(s, hh);
   memcpy(s->x0, s->x, sizeof(double) * 3 * n);
@@ -997,6 +1139,7 @@ static int one_step(or_sys* s) {
   refresh_fsal(s);
   half_kick(s, hh);
   s->step += 1;
+  s->time += h;
   return OR_OK;
 }
 
@@ -1065,7 +1208,26 @@ void or_set_dh(or_sys* s, const double* x, const double* u, long step_index) {
   memcpy(s->x, x, sizeof(double) * 3 * s->n);
   memcpy(s->u, u, sizeof(double) * 3 * s->n);
   s->step = step_index;
-  if (s->growth) {
+  s->time = (double)step_index * s->p.dt;
+  s->h = s->p.dt;
+  s->switched = 0;
+  if (s->phys) {
+    for (int k = 0; k < s->nb; ++k) s->rad_c[k] = 0.0;
+    if (step_index > 0) {
+      /* masses of the step before (the end-of-step force of a continuous run) */
+      double keep_t = s->time;
+      double* ukeep = (double*)malloc(sizeof(double) * 3 * (size_t)s->n);
+      if (ukeep) memcpy(ukeep, s->u, sizeof(double) * 3 * (size_t)s->n);
+      s->time = (double)(step_index - 1) * s->p.dt;
+      apply_physics(s);
+      if (ukeep) { memcpy(s->u, ukeep, sizeof(double) * 3 * (size_t)s->n); free(ukeep); }
+      s->time = keep_t;
+      s->h = s->p.dt;
+      s->switched = 0;
+    } else {
+      for (int k = 0; k < s->nb; ++k) { s->mu[k] = s->mu_init[k]; s->rcrit[k] = s->rcrit_init[k]; }
+    }
+  } else if (s->growth) {
     if (step_index > 0) {
       apply_growth(s, (step_index - 1) * s->p.dt);
     } else {
@@ -1121,4 +1283,55 @@ double or_last_pair_dmin2(const or_sys* s, int i, int j, double* rc2) {
   double rc = rci > rcj ? rci : rcj;
   if (rc2) *rc2 = rc * rc;
   return or_pair_dmin2(r0, w0, r1, w1, s->p.dt);
+}
+
+
+/* Install the time-dependent physics of the massive bodies (replaces a growth
+ * schedule given at creation).  pl: [nb]; a_switch > 0 enables the step switch to
+ * 1/25 of the period at a_min.                                               */
+int or_set_physics(or_sys* s, const or_planet* pl, double a_switch, double a_min) {
+  int nb = s->nb;
+  if (nb <= 0 || !pl || (a_switch > 0.0 && !(a_min > 0.0))) return OR_EINVAL;
+  free(s->phys); free(s->radius); free(s->rad_c); free(s->gaps); free(s->gap_on);
+  s->phys = (or_planet*)malloc(sizeof(or_planet) * (size_t)nb);
+  s->radius = (double*)calloc((size_t)nb, sizeof(double));
+  s->rad_c = (double*)calloc((size_t)nb, sizeof(double));
+  s->gaps = (double*)calloc(3 * (size_t)nb, sizeof(double));
+  s->gap_on = (int*)calloc((size_t)nb, sizeof(int));
+  if (!s->phys || !s->radius || !s->rad_c || !s->gaps || !s->gap_on) return OR_ENOMEM;
+  memcpy(s->phys, pl, sizeof(or_planet) * (size_t)nb);
+  /* the masses given at creation are the ones in force before the first step
+   * (M0 for a growing body) */
+  s->a_switch = a_switch;
+  s->a_min = a_min;
+  s->switched = 0;
+  s->h = s->p.dt;
+  refresh_fsal(s);
+  return OR_OK;
+}
+
+void or_get_radii(const or_sys* s, double* radius) {
+  for (int k = 0; k < s->nb; ++k) radius[k] = s->radius ? s->radius[k] : 0.0;
+}
+
+double or_time(const or_sys* s) { return s->time; }
+double or_step_size(const or_sys* s) { return s->h; }
+
+/* The gaps of the current step: [nb][4] = centre R, half width, density factor,
+ * open (1) or not (0). */
+void or_get_gaps(const or_sys* s, double* g) {
+  for (int k = 0; k < s->nb; ++k) {
+    g[4 * k] = s->gaps ? s->gaps[3 * k] : 0.0;
+    g[4 * k + 1] = s->gaps ? s->gaps[3 * k + 1] : 0.0;
+    g[4 * k + 2] = s->gaps ? s->gaps[3 * k + 2] : 1.0;
+    g[4 * k + 3] = s->gap_on ? (double)s->gap_on[k] : 0.0;
+  }
+}
+
+/* Replace positions and velocities only (time, step size, masses and the physics
+ * state are kept) and refresh the stored end-of-step force.                   */
+void or_set_xu(or_sys* s, const double* x, const double* u) {
+  memcpy(s->x, x, sizeof(double) * 3 * (size_t)s->n);
+  memcpy(s->u, u, sizeof(double) * 3 * (size_t)s->n);
+  refresh_fsal(s);
 }

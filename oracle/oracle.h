@@ -35,6 +35,17 @@ typedef struct {
 
 typedef struct or_sys or_sys;
 
+/* Time-dependent physics of one massive body (Sects. 3.1-3.3): growth, radius,
+ * migration and its gap.  Masses in Msun, times in days, lengths in AU. */
+typedef struct {
+  double M0, Mc, tau_c; /* core growth, Eq. 13 (tau_c <= 0: fixed mass, no later phase) */
+  double Mf, tau_g;     /* runaway gas accretion after tau_c, Eq. 15 (tau_g <= 0: held at Mc) */
+  double R_I;           /* radius reached by the collapse of Eq. 16 */
+  double da1, tau1;     /* first migration phase, Eq. 17 (tau1 <= 0: none) */
+  double da2, tau2;     /* second migration phase, Eq. 18 (tau2 <= 0: none) */
+  double gap_C;         /* gap width in Hill radii, Eq. 8 (0: no gap) */
+} or_planet;
+
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2, OR_ENOCONV = -4, OR_EBS = -5 };
 
 /* --- whole-system API -------------------------------------------------- */
@@ -54,6 +65,12 @@ void or_set_rcrit(or_sys* s, const double* rcrit);
 long or_step_index(const or_sys* s);
 double or_last_pair_dmin2(const or_sys* s, int i, int j, double* rc2);
 int or_threads(void);
+int or_set_physics(or_sys* s, const or_planet* pl, double a_switch, double a_min);
+void or_get_radii(const or_sys* s, double* radius);
+double or_time(const or_sys* s);
+double or_step_size(const or_sys* s);
+void or_set_xu(or_sys* s, const double* x, const double* u);
+void or_get_gaps(const or_sys* s, double* g);
 
 /* --- component functions (pins and kernel-level parity) --------------- */
 double or_changeover(double s, double rc);
@@ -62,6 +79,10 @@ void or_gravity(int n, int n_big, const double* x, const double* mu, const doubl
 void or_drag(const or_params* p, int n, int n_big, const double* x, const double* u,
              const double* mu, const double* r_p, const double* rho_p, double* a);
 double or_drag_cd(double re, double ma, double kexp);
+void or_drag_gaps(const or_params* p, int n, int n_big, const double* x, const double* u,
+                  const double* mu, const double* r_p, const double* rho_p,
+                  const double* gaps /* [n_big][3] R, half width, factor, or NULL */,
+                  const int* gap_on /* [n_big] */, double* a);
 double or_gas_sigma(const or_params* p, double R);
 double or_dg_series(double gamma);
 double or_disk_gravity(const or_params* p, double R);

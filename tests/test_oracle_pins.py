@@ -796,3 +796,170 @@ def test_step_close_encounter_hands_off_to_bs(orc, layout):
     err_bs = np.linalg.norm(rel - rel_ref)
     err_kep = np.linalg.norm((xk - xo[:, 0]) - rel_ref)
     assert err_kep > 3e-4 * np.linalg.norm(rel_ref) and err_kep > 100 * err_bs
+
+
+# --------------------------------------- time-dependent physics (Sects. 3.1-3.3, 3.6)
+def _one_planet(a=5.0, m=1e-5, n_small=0, gas=False, seed=0):
+    """A single massive body on a circular orbit (plus optional massless bodies on
+    circular orbits in its neighbourhood)."""
+    rng = np.random.default_rng(seed)
+    x = [[a, 0.0, 0.0]]
+    v = [[0.0, math.sqrt(G * (1 + m) / a), 0.0]]
+    for _ in range(n_small):
+        r = a * rng.uniform(0.8, 1.2)
+        ph = rng.uniform(0, 2 * math.pi)
+        x.append([r * math.cos(ph), r * math.sin(ph), 0.0])
+        vk = math.sqrt(MU0 / r)
+        v.append([-vk * math.sin(ph), vk * math.cos(ph), 0.0])
+    p = ic.default_params(n_big=1, n_small=n_small, gas_on=int(gas), dt=ic.period(MU0, a) / 40)
+    rp = np.full(n_small, 1000 * ic.KM_AU) if gas else None
+    rho = np.full(n_small, 1.5) if gas else None
+    return p, np.array(x).T, np.array(v).T, np.array([m]), rp, rho
+
+
+def test_growth_two_phases(orc):
+    """Eq. 13 from M0 to Mc over tau_c (exactly Mc at tau_c), then Eq. 15 towards Mf
+    with e-folding tau_g; the changeover radius follows m^(1/3)."""
+    p, x, v, m, _, _ = _one_planet(m=1e-6)
+    dt = p["dt"]
+    tc, tg = 10 * dt, 8 * dt
+    o = orc.OracleSystem(p, x, v, m)
+    rc0 = o.mu()[1][0]
+    o.set_physics([dict(M0=1e-6, Mc=5e-6, tau_c=tc, Mf=4e-5, tau_g=tg)])
+    e = math.e
+    for k in range(30):
+        o.step(1)
+        t = k * dt                                   # the step's start
+        if t < tc:
+            ref = 1e-6 + e / (e - 1) * 4e-6 * (1 - math.exp(-t / tc))
+        else:
+            ref = 5e-6 + 3.5e-5 * (1 - math.exp(-(t - tc) / tg))
+        mu, rc = o.mu()
+        assert abs(mu[0] / G - ref) <= 1e-13 * ref, (k, mu[0] / G, ref)
+        assert abs(rc[0] - rc0 * (ref / 1e-6) ** (1 / 3)) <= 1e-12 * rc[0]
+    # at t = tau_c exactly the core law gives Mc
+    assert abs(1e-6 + e / (e - 1) * 4e-6 * (1 - math.exp(-1.0)) - 5e-6) < 1e-20
+
+
+def test_radius_laws(orc):
+    """Eq. 14 by hand in the disk with H/r = 0.05 (k1 = 1, k2 = 1/4), then Eq. 16
+    from R_c at the onset of the runaway to R_I."""
+    p, x, v, m, _, _ = _one_planet(a=5.0, m=1e-5)
+    dt = p["dt"]
+    tc, tg = 4 * dt, 3 * dt
+    o = orc.OracleSystem(p, x, v, m)
+    o.set_physics([dict(M0=1e-5, Mc=1e-5, tau_c=tc, Mf=1e-5, tau_g=tg, R_I=2e-4)])
+    o.step(1)
+    gm = G * 1e-5
+    cs = 0.05 * math.sqrt(MU0 / 5.0)
+    rh = 5.0 * (1e-5 / 3.0) ** (1 / 3)
+    ref = gm / (cs * cs + gm / (0.25 * rh))
+    assert abs(o.radii()[0] - ref) <= 1e-12 * ref
+    radii = {}
+    for k in range(1, 40):                  # the step starting at t = k dt
+        o.step(1)
+        radii[k] = o.radii()[0]
+    # the step starting at tau_c = 4 dt opens the runaway: R = R_c there, then
+    # R_c - (R_c - R_I)(1 - exp(-(t - tau_c)/tau_g))
+    Rc = radii[4]
+    assert abs(Rc - radii[3]) < 1e-3 * Rc      # the same law just before, the planet moved a bit
+    for k in range(4, 40):
+        want = Rc - (Rc - 2e-4) * (1 - math.exp(-(k * dt - tc) / tg))
+        assert abs(radii[k] - want) <= 1e-12 * Rc, k
+    assert abs(radii[39] - 2e-4) < 1e-4 * Rc
+
+
+@pytest.mark.parametrize("phase", [1, 2])
+def test_migration_moves_the_semi_major_axis(orc, phase):
+    """The velocity changes of Eq. 17 (1/2 (da1/a)(dt/tau1) v_k per step along the
+    orbit) move a circular orbit by da1 over tau1 (da/a = 2 dv/v), to first order;
+    Eq. 18 gives da2 (1 - exp(-T/tau2)) after a time T."""
+    p, x, v, m, _, _ = _one_planet(a=5.0, m=1e-6)
+    dt = p["dt"]
+    o = orc.OracleSystem(p, x, v, m)
+    if phase == 1:
+        o.set_physics([dict(da1=-0.25, tau1=400 * dt)])
+        steps, want = 400, -0.25
+    else:
+        o.set_physics([dict(da2=-0.25, tau2=200 * dt)])
+        steps, want = 400, -0.25 * (1 - math.exp(-2.0))
+    o.step(steps)
+    xh, vh = o.get_state()
+    a = orc.x2el(G * (1 + 1e-6), xh[:, 0], vh[:, 0])[0]
+    assert abs((a - 5.0) - want) <= 0.02 * abs(want), (a - 5.0, want)
+
+
+def test_gap_density_factor(orc):
+    """dens_factor of the gaps (Sect. 3.1.1): a massless body strictly inside
+    (R_gap - w, R_gap + w) of an open gap sees the gas density times the gap's factor,
+    the gap of the highest index winning where gaps overlap; at very large Re the
+    drag scales with the density, so the drag is multiplied by exactly that factor;
+    closed gaps and bodies outside change nothing."""
+    p = ic.default_params(n_big=2, n_small=5, gas_on=1)
+    n = 7
+    x = np.zeros((3, n)); u = np.zeros((3, n))
+    x[:, 0] = [30.0, 0, 0]; x[:, 1] = [0, -40.0, 0]
+    mu = np.array([1e-14, 1e-14])
+    Rs = [3.0, 3.15, 3.32, 3.6, 2.5]          # in gap 0 only, in both, in gap 1 only, out, edge
+    for t, R in enumerate(Rs):
+        x[:, 2 + t] = [R, 0.0, 0.0]
+        u[:, 2 + t] = [1e-4, math.sqrt(MU0 / R), 0.0]
+    r_p = np.full(5, 1e5 * ic.KM_AU); rho = np.full(5, 1.5 * ic.RHO_UNIT)
+    gaps = np.array([[3.0, 0.2, 0.5], [3.3, 0.2, 0.25]])
+    a0 = orc.drag(p, x, u, mu, r_p, rho, 2)
+    a1 = orc.drag_gaps(p, x, u, mu, r_p, rho, 2, gaps, [1, 1])
+    want = [0.5, 0.25, 0.25, 1.0, 1.0]        # R = 2.5 is outside (2.8, 3.2)... and (3.1, 3.5)
+    for t, f in enumerate(want):
+        r = np.linalg.norm(a1[:, 2 + t]) / np.linalg.norm(a0[:, 2 + t])
+        assert abs(r - f) <= 1e-9 * f, (Rs[t], r, f)
+    assert np.array_equal(orc.drag_gaps(p, x, u, mu, r_p, rho, 2, gaps, [0, 0]), a0)
+    edge = dict(p)
+    x[:, 6] = [3.2, 0.0, 0.0]                  # exactly on the edge of gap 0: outside (strict)
+    a2 = orc.drag_gaps(edge, x, u, mu, r_p, rho, 2, gaps, [1, 0])
+    a3 = orc.drag(edge, x, u, mu, r_p, rho, 2)
+    assert np.array_equal(a2[:, 6], a3[:, 6])
+
+
+def test_gap_records_follow_eqs_8_9(orc):
+    """The gap of a body after tau_c: centred on its cylindrical distance, half width
+    gap_C R_H with R_H = r (m / 3 m0)^(1/3) (Eq. 8), factor exp(-(t - tau_c)/tau_g)
+    (Eq. 9); closed before tau_c."""
+    p, x, v, m, rp, rho = _one_planet(a=5.0, m=3e-5, n_small=3, gas=True)
+    dt = p["dt"]
+    tc, tg = 2.5 * dt, 3 * dt
+    o = orc.OracleSystem(p, x, v, m, rp, rho)
+    o.set_physics([dict(M0=3e-5, Mc=3e-5, tau_c=tc, Mf=3e-5, tau_g=tg, gap_C=4.0)])
+    for k in range(6):
+        xs, _ = o.get_dh()
+        o.step(1)
+        g = o.gaps()[0]
+        t = k * dt
+        r = np.linalg.norm(xs[:, 0])
+        assert abs(g[0] - np.hypot(xs[0, 0], xs[1, 0])) <= 1e-15 * r
+        assert abs(g[1] - 4.0 * r * (3e-5 / 3) ** (1 / 3)) <= 1e-14 * r
+        if t > tc:
+            assert g[3] == 1.0 and abs(g[2] - math.exp(-(t - tc) / tg)) <= 1e-15
+        else:
+            assert g[3] == 0.0
+
+
+def test_step_switch(orc):
+    """Once the migrating planet's semi-major axis is inside a_switch the step becomes
+    1/25 of the orbital period at a_min (Sect. 3.6), and stays so."""
+    p, x, v, m, _, _ = _one_planet(a=1.0, m=1e-6)
+    dt = p["dt"]
+    o = orc.OracleSystem(p, x, v, m)
+    o.set_physics([dict(da1=-0.3, tau1=100 * dt)], a_switch=0.9, a_min=0.5)
+    small = ic.period(MU0, 0.5) / 25
+    seen = False
+    t = 0.0
+    for k in range(120):
+        h = o.step_size()
+        o.step(1)
+        t += o.step_size() if seen else 0.0
+        xh, vh = o.get_state()
+        if o.step_size() != dt:
+            assert abs(o.step_size() - small) <= 1e-15 * small
+            seen = True
+    assert seen
+    assert o.time() > 0
