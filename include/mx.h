@@ -184,6 +184,46 @@ mx_status mx_get_masses(mx_system* s, double* mu, double* rcrit);
 /* Steps taken so far (the step counter). */
 mx_status mx_get_step_index(mx_system* s, int64_t* step_index);
 
+/* Time-dependent physics of one massive body (Sects. 3.2-3.3, 3.1 gaps): masses
+ * in Msun, times in days, lengths in AU. */
+typedef struct {
+  double M0, Mc, tau_c; /* core growth, Eq. 13 (tau_c <= 0: fixed mass, no later phase) */
+  double Mf, tau_g;     /* runaway gas accretion for t >= tau_c, Eq. 15 (tau_g <= 0: Mc) */
+  double R_I;           /* radius after the collapse, Eq. 16 (Delta R = R_c - R_I) */
+  double da1, tau1;     /* linear migration, Eq. 17 (tau1 <= 0: none) */
+  double da2, tau2;     /* second migration phase, Eq. 18 (tau2 <= 0: none) */
+  double gap_C;         /* gap half width in Hill radii, Eq. 8 (the paper's C = 4; 0: no gap) */
+} mx_planet;
+
+/* Install the time-dependent physics of the massive bodies (n_big <= 64, a single
+ * system; replaces a growth schedule given at init).  planets: host [n_big].  At the
+ * start of each step, at its time t, held through the step:
+ *  - mass of Eq. 13 for t < tau_c, then of Eq. 15 (or Mc), and rcrit scaled by the
+ *    cube root of the mass (Hill radius);
+ *  - radius of Eq. 14 (k1 = 1, k2 = 1/4, c_s of the disk at the body's cylindrical
+ *    distance, R_H = r (m / 3 m0)^(1/3) at its distance r), from tau_c on Eq. 16
+ *    with R_c the Eq. 14 radius at the first step of the runaway;
+ *  - migration: a change of the velocity along the heliocentric velocity by
+ *    Eq. 17 for t < tau1 and by Eq. 18 after (a_p the osculating semi-major axis,
+ *    v_k = sqrt(G (m0 + m) / a_p), Delta t the step);
+ *  - gap (after tau_c, with tau_g > 0 and gap_C > 0): massless bodies strictly
+ *    within gap_C R_H of the body's cylindrical distance see the drag density times
+ *    exp(-(t - tau_c)/tau_g) (Eqs. 8-9; the highest-index gap wins);
+ *  - step switch (Sect. 3.6; a_switch > 0): once a migrating body's a_p <= a_switch
+ *    the step becomes 1/25 of the orbital period at a_min, from that step on.
+ * The time advances by the step actually taken.  mx_set_state / mx_set_state_dh
+ * restart the clock at step_index * dt with the initial step and forget R_c.
+ * MX_EINVAL for n_big > 64, n_big = 0 or a_switch > 0 without a_min > 0.
+ * Synchronises. */
+mx_status mx_set_planet_physics(mx_system* s, const mx_planet* planets, double a_switch,
+                                double a_min);
+
+/* Radii of the massive bodies from the last step (0 before any step with physics),
+ * host [n_big]; the time at the start of the next step and the current step size,
+ * host scalars.  Synchronise. */
+mx_status mx_get_planet_radii(mx_system* s, double* radius);
+mx_status mx_get_time(mx_system* s, double* t, double* h);
+
 void mx_destroy(mx_system* s);
 const char* mx_last_error(void);
 

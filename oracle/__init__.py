@@ -150,6 +150,8 @@ def _declare(L):
     L.or_step_size.argtypes = [C.c_void_p]
     L.or_set_xu.argtypes = [C.c_void_p, _D, _D]
     L.or_get_gaps.argtypes = [C.c_void_p, _D]
+    L.or_clone.restype = C.c_void_p
+    L.or_clone.argtypes = [C.c_void_p]
     L.or_drag_gaps.argtypes = [C.POINTER(_Params), C.c_int, C.c_int, _D, _D, _D, _D, _D, _D,
                                C.POINTER(C.c_int), _D]
     L.or_threads.restype = C.c_int
@@ -264,6 +266,17 @@ class OracleSystem:
 
     def step_size(self):
         return self._L.or_step_size(self._h)
+
+    def clone(self):
+        """A deep copy (state, masses, clock, physics state)."""
+        c = OracleSystem.__new__(OracleSystem)
+        c._L, c.params, c.n, c.nb = self._L, dict(self.params), self.n, self.nb
+        c._pp = self._pp
+        c._planets = getattr(self, "_planets", None)
+        c._h = self._L.or_clone(self._h)
+        if not c._h:
+            raise MemoryError("oracle clone failed")
+        return c
 
     def gaps(self):
         """[nb, 4]: centre R, half width, density factor, open (1/0) of each gap."""

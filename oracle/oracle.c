@@ -1224,6 +1224,7 @@ void or_set_dh(or_sys* s, const double* x, const double* u, long step_index) {
       s->time = keep_t;
       s->h = s->p.dt;
       s->switched = 0;
+      for (int k = 0; k < s->nb; ++k) s->rad_c[k] = 0.0;  /* re-latched after a restart */
     } else {
       for (int k = 0; k < s->nb; ++k) { s->mu[k] = s->mu_init[k]; s->rcrit[k] = s->rcrit_init[k]; }
     }
@@ -1334,4 +1335,36 @@ void or_set_xu(or_sys* s, const double* x, const double* u) {
   memcpy(s->x, x, sizeof(double) * 3 * (size_t)s->n);
   memcpy(s->u, u, sizeof(double) * 3 * (size_t)s->n);
   refresh_fsal(s);
+}
+
+static void* dup_bytes(const void* src, size_t bytes) {
+  if (!src) return NULL;
+  void* d = malloc(bytes ? bytes : 1);
+  if (d) memcpy(d, src, bytes);
+  return d;
+}
+
+/* A deep copy of a system (state, masses, clock and physics state), for re-running a
+ * step from the same point. */
+or_sys* or_clone(const or_sys* s) {
+  or_sys* c = (or_sys*)malloc(sizeof(or_sys));
+  if (!c) return NULL;
+  *c = *s;
+  size_t v3 = sizeof(double) * 3 * (size_t)s->n;
+  size_t nbs = sizeof(double) * (s->nb > 0 ? s->nb : 1);
+  size_t nss = sizeof(double) * (s->ns > 0 ? s->ns : 1);
+  c->x = dup_bytes(s->x, v3); c->u = dup_bytes(s->u, v3); c->ag = dup_bytes(s->ag, v3);
+  c->x0 = dup_bytes(s->x0, v3); c->u0 = dup_bytes(s->u0, v3); c->x1 = dup_bytes(s->x1, v3);
+  c->u1 = dup_bytes(s->u1, v3); c->ad = dup_bytes(s->ad, v3);
+  c->x1k = dup_bytes(s->x1k, v3); c->u1k = dup_bytes(s->u1k, v3);
+  c->mu = dup_bytes(s->mu, nbs); c->mu_init = dup_bytes(s->mu_init, nbs);
+  c->rcrit = dup_bytes(s->rcrit, nbs); c->rcrit_init = dup_bytes(s->rcrit_init, nbs);
+  c->r_p = dup_bytes(s->r_p, nss); c->rho_p = dup_bytes(s->rho_p, nss);
+  c->growth = dup_bytes(s->growth, 3 * nbs);
+  c->pairs = dup_bytes(s->pairs, sizeof(int32_t) * 2 * (size_t)s->cap_pairs);
+  c->phys = dup_bytes(s->phys, sizeof(or_planet) * (size_t)(s->nb > 0 ? s->nb : 1));
+  c->radius = dup_bytes(s->radius, nbs); c->rad_c = dup_bytes(s->rad_c, nbs);
+  c->gaps = dup_bytes(s->gaps, 3 * nbs);
+  c->gap_on = dup_bytes(s->gap_on, sizeof(int) * (size_t)(s->nb > 0 ? s->nb : 1));
+  return c;
 }

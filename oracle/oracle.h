@@ -71,6 +71,7 @@ double or_time(const or_sys* s);
 double or_step_size(const or_sys* s);
 void or_set_xu(or_sys* s, const double* x, const double* u);
 void or_get_gaps(const or_sys* s, double* g);
+or_sys* or_clone(const or_sys* s);
 
 /* --- component functions (pins and kernel-level parity) --------------- */
 double or_changeover(double s, double rc);

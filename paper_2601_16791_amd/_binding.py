@@ -34,6 +34,12 @@ class Params(C.Structure):
                 ("eta_mode", C.c_int32), ("dg_mode", C.c_int32)]
 
 
+class Planet(C.Structure):
+    """mx_planet: time-dependent physics of one massive body."""
+    _fields_ = [(f, C.c_double) for f in
+                ("M0", "Mc", "tau_c", "Mf", "tau_g", "R_I", "da1", "tau1", "da2", "tau2", "gap_C")]
+
+
 # fields a parameter dict may leave out (the disk physics beyond the plain drag is off)
 _OPTIONAL = {"temp_1au": 0.0, "temp_beta": 0.0, "cs2_per_k": 0.0, "eta_mode": 0, "dg_mode": 0}
 
@@ -136,6 +142,12 @@ def lib():
         L.mx_adjoint_system.restype = st
         L.mx_adjoint_system.argtypes = [_P, C.POINTER(C.c_void_p)]
         L.mx_destroy_adjoint.argtypes = [_P]
+        L.mx_set_planet_physics.restype = st
+        L.mx_set_planet_physics.argtypes = [_P, C.POINTER(Planet), C.c_double, C.c_double]
+        L.mx_get_planet_radii.restype = st
+        L.mx_get_planet_radii.argtypes = [_P, _D]
+        L.mx_get_time.restype = st
+        L.mx_get_time.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.mx_flag_pairs.restype = st
         L.mx_flag_pairs.argtypes = [C.c_int32, C.c_int32, _D, _D, _D, _D, _D, C.c_double, _D,
                                     C.c_int32, C.POINTER(C.c_int32), _P]
@@ -312,6 +324,26 @@ class System:
         rc = (C.c_double * k)()
         _check(lib().mx_get_masses(self._h, mu, rc))
         return np.array(mu[: self.nb]), np.array(rc[: self.nb])
+
+    def set_planet_physics(self, planets, a_switch=0.0, a_min=0.0):
+        """planets: one dict per massive body with the Planet fields (missing = 0)."""
+        arr = (Planet * len(planets))()
+        for k, r in enumerate(planets):
+            for f, _ in Planet._fields_:
+                setattr(arr[k], f, float(r.get(f, 0.0)))
+        _check(lib().mx_set_planet_physics(self._h, arr, float(a_switch), float(a_min)))
+
+    def radii(self):
+        k = max(self.nb, 1)
+        r = (C.c_double * k)()
+        _check(lib().mx_get_planet_radii(self._h, r))
+        return np.array(r[: self.nb])
+
+    def time(self):
+        """(time at the start of the next step, current step size)."""
+        t, h = C.c_double(0), C.c_double(0)
+        _check(lib().mx_get_time(self._h, C.byref(t), C.byref(h)))
+        return t.value, h.value
 
     def step_index(self):
         v = C.c_int64(0)

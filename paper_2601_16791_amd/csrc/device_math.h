@@ -65,8 +65,9 @@ __device__ __forceinline__ double pow_kexp(double b, double kexp) {
 
 // Sound speed, midplane density and gas speed of the general disk (c.ext): c_s
 // from T(R) = T0 (R/1AU)^-beta (Eq. 2) or h_over_r v_K; scale height c_s/Omega;
-// eta fixed or eta(R) of Eq. 6; and the disk gravity of Eqs. 10-12 (signed radial,
-// positive away from the star) into (gx, gy).
+// the density factor of the gaps (Eqs. 8-9); eta fixed or eta(R) of Eq. 6; and the
+// disk gravity of Eqs. 10-12 (signed radial, positive away from the star) into
+// (gx, gy).
 __device__ __noinline__ void gas_general(const DragConst& c, double X, double Y, double R,
                                          double inv_R, double vk, double sig, double& cs,
                                          double& rhog, double& vg, double& gx, double& gy) {
@@ -74,6 +75,12 @@ __device__ __noinline__ void gas_general(const DragConst& c, double X, double Y,
   else cs = c.h_over_r * vk;
   // rho_g = Sigma / (sqrt(2 pi) c_s / Omega) = Sigma v_K / (sqrt(2 pi) c_s R)
   rhog = sig * vk * inv_R / (kSqrt2Pi * cs);
+  // the gaps of the massive bodies (dens_factor of Sect. 3.1.1): the open gap of
+  // the highest index with R strictly inside it scales the density
+  for (int i = 0; i < c.gap_n; ++i) {
+    const double* g = c.gaps + 4 * i;
+    if (g[3] != 0.0 && R < g[0] + g[1] && R > g[0] - g[1]) rhog = sig * vk * inv_R / (kSqrt2Pi * cs) * g[2];
+  }
   double eta = c.eta;
   if (c.eta6_fac != 0.0) {
     const double m = cs / vk;

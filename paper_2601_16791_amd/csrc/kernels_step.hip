@@ -43,6 +43,140 @@ __global__ void k_growth(int nb, double dt, const double* __restrict__ growth,
   rcrit[k] = rcrit_init[k] * cbrt(m / mu_init[k]);
 }
 
+// ------------------------------------------------- time-dependent physics
+// Sect. 3.2 (Eqs. 13-16), Sect. 3.3 (Eqs. 17-18), the gaps of Sect. 3.1 (Eqs. 8-9)
+// and the step switch of Sect. 3.6, at the start of a step (one wave; n_big <= 64,
+// lane k = massive body k).  masses_only: only the masses and changeover radii at
+// time t_fix (restarts).  Otherwise at t = the step's start time: masses; the
+// massive-body momentum P (summed in index order) for the heliocentric velocities;
+// osculating semi-major axes; the step switch; radii; gap records; the migration
+// velocity changes (written to u and to the step-start snapshot); the clock
+// advanced by the step taken.
+__device__ __forceinline__ double planet_radius_core(double gm, double cs, double rhill) {
+  return gm / (cs * cs + gm / (0.25 * rhill));  // k1 = 1, k2 = 1/4
+}
+
+__global__ __launch_bounds__(64) void k_physics(
+    int n, int nb, double G, double mu0, DragConst dc, const PlanetPhys* __restrict__ ph,
+    const double* __restrict__ mu_init, const double* __restrict__ rcrit_init,
+    double* __restrict__ mu, double* __restrict__ rcrit, const double* __restrict__ x,
+    double* __restrict__ u, double* __restrict__ bigsnap, double* __restrict__ radius,
+    double* __restrict__ rad_c, double* __restrict__ gaps, DevScalars* __restrict__ dsc,
+    SysDesc* __restrict__ desc, double a_switch, double a_min, int masses_only, double t_fix) {
+  __shared__ double smu[64 * 3];
+  __shared__ double sP[3];
+  const int k = threadIdx.x;
+  const double t = masses_only ? t_fix : dsc->time;
+  PlanetPhys q{};
+  if (k < nb) q = ph[k];
+  double m_k = 0.0;
+  if (k < nb) {
+    m_k = mu[k];
+    if (q.tau_c > 0.0) {
+      const double E = 2.718281828459045235;
+      double m;
+      if (t < q.tau_c) m = q.M0 + (E / (E - 1.0)) * (q.Mc - q.M0) * (1.0 - exp(-t / q.tau_c));
+      else if (q.tau_g > 0.0) m = q.Mc + (q.Mf - q.Mc) * (1.0 - exp(-(t - q.tau_c) / q.tau_g));
+      else m = q.Mc;
+      m_k = G * m;
+      mu[k] = m_k;
+      rcrit[k] = rcrit_init[k] * cbrt(m_k / mu_init[k]);
+    }
+  }
+  if (masses_only) return;
+  double v[3] = {0.0, 0.0, 0.0}, p[3] = {0.0, 0.0, 0.0};
+  if (k < nb) {
+    for (int c = 0; c < 3; ++c) {
+      p[c] = x[c * n + k];
+      v[c] = u[c * n + k];
+      smu[3 * k + c] = m_k * v[c];
+    }
+  }
+  __syncthreads();
+  if (k == 0) {
+    double P0 = 0.0, P1 = 0.0, P2 = 0.0;
+    for (int j = 0; j < nb; ++j) {
+      P0 += smu[3 * j];
+      P1 += smu[3 * j + 1];
+      P2 += smu[3 * j + 2];
+    }
+    sP[0] = P0;
+    sP[1] = P1;
+    sP[2] = P2;
+  }
+  __syncthreads();
+  double vh[3], ap = 0.0, r = 0.0, Rc = 0.0, vn = 0.0, rh = 0.0;
+  bool inside = false;
+  const bool migrates = k < nb && (q.tau1 > 0.0 || q.tau2 > 0.0);
+  if (k < nb) {
+    for (int c = 0; c < 3; ++c) vh[c] = v[c] + sP[c] / mu0;
+    r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    Rc = sqrt(p[0] * p[0] + p[1] * p[1]);
+    const double vv = vh[0] * vh[0] + vh[1] * vh[1] + vh[2] * vh[2];
+    vn = sqrt(vv);
+    const double gm = mu0 + m_k;
+    ap = gm / (2.0 * gm / r - vv);  // osculating semi-major axis (negative if unbound)
+    rh = r * cbrt(m_k / (3.0 * mu0));
+    inside = migrates && a_switch > 0.0 && ap > 0.0 && ap <= a_switch;
+  }
+  const bool any_inside = __builtin_amdgcn_ballot_w64(inside) != 0;
+  double h = desc->h;
+  if (any_inside && !dsc->switched) {
+    h = 2.0 * mxd::kPi * sqrt(a_min * a_min * a_min / mu0) / 25.0;
+    if (k == 0) {
+      desc->h = h;
+      dsc->switched = 1;
+    }
+  }
+  if (k < nb) {
+    // radius: Eq. 14 with the disk's sound speed at the cylindrical distance
+    const double cs = dc.cs2_1au > 0.0 ? sqrt(dc.cs2_1au * pow(Rc, -dc.beta))
+                                       : dc.h_over_r * sqrt(mu0 / Rc);
+    if (q.tau_c > 0.0 && q.tau_g > 0.0 && t >= q.tau_c) {
+      double R0 = rad_c[k];
+      if (R0 == 0.0) {
+        R0 = planet_radius_core(m_k, cs, rh);
+        rad_c[k] = R0;
+      }
+      radius[k] = R0 - (R0 - q.R_I) * (1.0 - exp(-(t - q.tau_c) / q.tau_g));
+    } else {
+      radius[k] = planet_radius_core(m_k, cs, rh);
+    }
+    // gap (Eqs. 8-9)
+    const bool open = q.gap_C > 0.0 && q.tau_c > 0.0 && q.tau_g > 0.0 && t > q.tau_c;
+    gaps[4 * k] = Rc;
+    gaps[4 * k + 1] = q.gap_C * rh;
+    gaps[4 * k + 2] = open ? exp(-(t - q.tau_c) / q.tau_g) : 1.0;
+    gaps[4 * k + 3] = open ? 1.0 : 0.0;
+    // migration (Eqs. 17-18) along the heliocentric velocity
+    if (migrates && ap > 0.0) {
+      const double vk = sqrt((mu0 + m_k) / ap);
+      const double t1 = q.tau1 > 0.0 ? q.tau1 : 0.0;
+      double dv = 0.0;
+      if (q.tau1 > 0.0 && t < q.tau1) dv = 0.5 * (q.da1 / ap) * (h / q.tau1) * vk;
+      else if (q.tau2 > 0.0) dv = 0.5 * (q.da2 / ap) * (h / q.tau2) * exp(-(t - t1) / q.tau2) * vk;
+      for (int c = 0; c < 3; ++c) {
+        const double w = v[c] + dv * vh[c] / vn;
+        u[c * n + k] = w;
+        bigsnap[(3 + c) * nb + k] = w;
+      }
+    }
+  }
+  if (k == 0) dsc->time = t + h;
+}
+
+// clock restart: time t, the initial step, the step switch undone, R_c forgotten
+__global__ void k_physics_reset(int nb, double t, double dt, double* __restrict__ rad_c,
+                                DevScalars* __restrict__ dsc, SysDesc* __restrict__ desc) {
+  const int k = threadIdx.x;
+  if (k < nb) rad_c[k] = 0.0;
+  if (k == 0) {
+    dsc->time = t;
+    dsc->switched = 0;
+    desc->h = dt;
+  }
+}
+
 // ------------------------------------------------- kick + jump + drift
 __global__ __launch_bounds__(kBlock) void k_kick_jump_drift(
     int n, int nb, double mu0, double h, DragConst dc, int gas_on, double* __restrict__ x,
@@ -572,6 +706,20 @@ hipError_t launch_growth(mx_system* s) {
   if (!s->has_growth || s->nb == 0) return hipSuccess;
   return mxlaunch(s, k_growth, dim3((s->nb + 255) / 256), dim3(256), s->nb, s->p.dt,
                   s->growth, s->mu_init, s->rcrit_init, s->mu, s->rcrit, s->dsc);
+}
+
+hipError_t launch_physics_reset(mx_system* s, double t) {
+  if (!s->has_phys) return hipSuccess;
+  return mxlaunch(s, k_physics_reset, dim3(1), dim3(64), s->nb, t, s->p.dt, s->rad_c, s->dsc,
+                  s->desc);
+}
+
+hipError_t launch_physics(mx_system* s, int masses_only, double t) {
+  if (!s->has_phys) return hipSuccess;
+  return mxlaunch(s, k_physics, dim3(1), dim3(64), s->n, s->nb, s->p.G, s->mu0,
+                  make_drag_const(s->p), s->phys, s->mu_init, s->rcrit_init, s->mu, s->rcrit, s->x,
+                  s->u, s->bigsnap, s->radius, s->rad_c, s->gaps, s->dsc, s->desc, s->a_switch,
+                  s->a_min, masses_only, t);
 }
 
 hipError_t launch_kick_jump_drift(mx_system* s) {

@@ -90,6 +90,11 @@ SysDesc make_desc(const mx_system* s) {
   d.subs = s->subs;
   d.dsc = s->dsc;
   d.dc = mxd::make_drag_const(s->p);
+  if (s->has_phys && s->any_gap) {
+    d.dc.gaps = s->gaps;
+    d.dc.gap_n = s->nb;
+    d.dc.ext = 1;
+  }
   d.mu0 = s->mu0;
   d.h = s->p.dt;
   d.bs_tol = s->p.bs_tol;
@@ -116,7 +121,7 @@ void free_system(mx_system* s) {
                   s->fpack, s->part,
                   s->sympart,
                   s->pairs, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red,
-                  s->desc, s->tiles};
+                  s->desc, s->tiles, s->phys, s->radius, s->rad_c, s->gaps};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -128,7 +133,7 @@ void free_system(mx_system* s) {
 hipError_t launch_group(mx_system* s, int k, int par = 0) {
   const bool small = s->nb <= kSmallBig;
   switch (k) {
-    case MX_K_GROWTH: return mxk::launch_growth(s);
+    case MX_K_GROWTH: return s->has_phys ? mxk::launch_physics(s, 0, 0.0) : mxk::launch_growth(s);
     case MX_K_KICK_JUMP_DRIFT:
       return small ? mxk::launch_step_a_tiles(s->stream, &s->tev, s->desc, s->tiles, s->n_tiles,
                                               kTileBlk, 1, par)
@@ -163,7 +168,7 @@ hipError_t enqueue_step(mx_system* s) {
 // first step) and after(k, q) right after it.
 template <class Visit, class After>
 hipError_t enqueue_steps(mx_system* s, int32_t n, bool join, Visit visit, After after) {
-  join = join && n >= 2 && s->nb <= kSmallBig && !s->has_growth;
+  join = join && n >= 2 && s->nb <= kSmallBig && !s->has_growth && !s->has_phys;
   for (int32_t q = 0; q < n; ++q) {
     const int par = join ? (q & 1) : 0;  // step parity (buffers alternate between joined steps)
     for (int k = 0; k < MX_NUM_KERNELS; ++k) {
@@ -539,7 +544,18 @@ mx_status mx_get_state(mx_system* s, double* x_h, double* v_h, int is_device_ptr
 }
 
 static mx_status set_common(mx_system* s, int64_t step_index) {
-  if (s->has_growth) {
+  if (s->has_phys) {
+    // restart: the clock at step_index * dt with the initial step, R_c forgotten,
+    // the masses of the step before in force
+    HIPCHK(mxk::launch_reset_scalars(s, step_index), "reset");
+    HIPCHK(mxk::launch_physics_reset(s, (double)step_index * s->p.dt), "physics reset");
+    if (step_index > 0)
+      HIPCHK(mxk::launch_physics(s, 1, (double)(step_index - 1) * s->p.dt), "masses");
+    else {
+      HIPCHK(hipMemcpyAsync(s->mu, s->mu_init, sizeof(double) * s->nb, hipMemcpyDeviceToDevice, s->stream), "mu");
+      HIPCHK(hipMemcpyAsync(s->rcrit, s->rcrit_init, sizeof(double) * s->nb, hipMemcpyDeviceToDevice, s->stream), "rcrit");
+    }
+  } else if (s->has_growth) {
     // the masses of the step before step_index were the ones in force
     int64_t prev = step_index > 0 ? step_index - 1 : 0;
     HIPCHK(mxk::launch_reset_scalars(s, prev), "reset");
@@ -612,6 +628,67 @@ mx_status mx_get_step_index(mx_system* s, int64_t* step_index) {
   DevScalars d;
   HIPCHK(hipMemcpy(&d, s->dsc, sizeof(DevScalars), hipMemcpyDeviceToHost), "read scalars");
   *step_index = d.step;
+  return MX_OK;
+}
+
+mx_status mx_set_planet_physics(mx_system* s, const mx_planet* planets, double a_switch,
+                                double a_min) {
+  if (!s || !planets) return fail(MX_EINVAL, "NULL argument");
+  if (s->owned) return fail(MX_EINVAL, "planet physics is for a system of its own");
+  if (s->nb <= 0 || s->nb > kSmallBig)
+    return fail(MX_EINVAL, "planet physics needs 1 <= n_big <= 64");
+  if (a_switch > 0.0 && !(a_min > 0.0)) return fail(MX_EINVAL, "the step switch needs a_min > 0");
+  static_assert(sizeof(mx_planet) == sizeof(PlanetPhys), "planet record layout");
+  const int nb = s->nb;
+  HIPCHK(hipStreamSynchronize(s->stream), "sync");
+  if (!s->phys) {
+    HIPCHK(dalloc(&s->phys, nb), "alloc");
+    HIPCHK(dalloc(&s->radius, nb), "alloc");
+    HIPCHK(dalloc(&s->rad_c, nb), "alloc");
+    HIPCHK(dalloc(&s->gaps, 4 * (size_t)nb), "alloc");
+  }
+  s->any_gap = 0;
+  for (int k = 0; k < nb; ++k) s->any_gap |= planets[k].gap_C > 0.0 && planets[k].tau_g > 0.0;
+  HIPCHK(hipMemcpy(s->phys, planets, sizeof(PlanetPhys) * nb, hipMemcpyHostToDevice), "copy");
+  HIPCHK(hipMemset(s->radius, 0, sizeof(double) * nb), "clear");
+  HIPCHK(hipMemset(s->gaps, 0, sizeof(double) * 4 * nb), "clear");
+  s->has_phys = 1;
+  s->has_growth = 0;
+  s->a_switch = a_switch;
+  s->a_min = a_min;
+  SysDesc d = make_desc(s);
+  HIPCHK(hipMemcpy(s->desc, &d, sizeof(SysDesc), hipMemcpyHostToDevice), "descriptor");
+  DevScalars hd;
+  HIPCHK(hipMemcpy(&hd, s->dsc, sizeof(hd), hipMemcpyDeviceToHost), "read scalars");
+  HIPCHK(mxk::launch_physics_reset(s, (double)hd.step * s->p.dt), "physics reset");
+  HIPCHK(hipStreamSynchronize(s->stream), "sync");
+  if (s->graph_ok) {
+    (void)hipGraphExecDestroy(s->graph);
+    s->graph_ok = false;
+  }
+  return MX_OK;
+}
+
+mx_status mx_get_planet_radii(mx_system* s, double* radius) {
+  if (!s || !radius) return fail(MX_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(s->stream), "sync");
+  if (!s->has_phys || s->nb == 0) {
+    for (int k = 0; k < s->nb; ++k) radius[k] = 0.0;
+    return MX_OK;
+  }
+  HIPCHK(hipMemcpy(radius, s->radius, sizeof(double) * s->nb, hipMemcpyDeviceToHost), "copy");
+  return MX_OK;
+}
+
+mx_status mx_get_time(mx_system* s, double* t, double* h) {
+  if (!s || !t || !h) return fail(MX_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(s->stream), "sync");
+  DevScalars hd;
+  HIPCHK(hipMemcpy(&hd, s->dsc, sizeof(hd), hipMemcpyDeviceToHost), "read scalars");
+  SysDesc d;
+  HIPCHK(hipMemcpy(&d, s->desc, sizeof(d), hipMemcpyDeviceToHost), "read descriptor");
+  *t = s->has_phys ? hd.time : (double)hd.step * s->p.dt;
+  *h = d.h;
   return MX_OK;
 }
 

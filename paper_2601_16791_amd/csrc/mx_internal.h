@@ -60,6 +60,9 @@ struct DevScalars {
   int32_t plan_ready;    // set when the in-kernel general plan of this step is written
   int32_t n_pairs_alt;   // second append counter: steps joined in one launch alternate
   int32_t bn_valid[2];   // BigNext[parity] holds this step boundary's massive bodies
+  double time;           // time at the start of the next step (time-dependent physics)
+  int32_t switched;      // the step switch has happened
+  int32_t pad_phys;
 };
 
 // Append counter of the flagged list for step parity w (0 outside joined launches).
@@ -81,6 +84,8 @@ struct DragConst {
   double eta6_fac;  // (gamma + beta/2 + 3/2) / (2 gamma_C), or 0 for the fixed eta
   double dg_fac;    // disk gravity per unit Sigma: 2 pi G S(gamma), or 2 pi G r_in / R
                     // per unit Sigma / R for gamma = 1; 0 = off
+  const double* gaps;  // [gap_n][4] centre R, half width, density factor, open (device)
+  int gap_n;
   int ext, dg_edge;
 };
 
@@ -104,6 +109,8 @@ inline DragConst make_drag_const(const mx_params& p) {
   c.dg_fac = !p.dg_mode ? 0.0 : (c.dg_edge ? kTwoPi * p.G * p.r_in
                                           : kTwoPi * p.G * dg_series_closed(p.gamma));
   c.ext = (c.cs2_1au > 0.0 || p.eta_mode || p.dg_mode) ? 1 : 0;
+  c.gaps = nullptr;
+  c.gap_n = 0;
   c.mu0 = p.G * p.m0;
   c.sigma1_unit = p.sigma1 * (p.rho_unit / p.au_cm);
   c.gamma = p.gamma;
@@ -185,6 +192,11 @@ struct LaunchTiming {
   hipEvent_t start, stop;
 };
 
+// Time-dependent physics of one massive body (the mx_planet fields).
+struct PlanetPhys {
+  double M0, Mc, tau_c, Mf, tau_g, R_I, da1, tau1, da2, tau2, gap_C;
+};
+
 struct mx_system {
   mx_params p;
   int n, nb, ns;
@@ -196,6 +208,12 @@ struct mx_system {
   // massive bodies
   double *mu, *rcrit, *mu_init, *rcrit_init, *growth;  // growth: [nb][3] (G*M0, G*Mc, tau)
   int has_growth;
+  // time-dependent physics (mx_set_planet_physics): per-body parameters, radius,
+  // radius at the onset of the runaway, gap records [nb][4]
+  PlanetPhys* phys;
+  double *radius, *rad_c, *gaps;
+  int has_phys, any_gap;
+  double a_switch, a_min;
   // snapshots of the massive bodies, so that a kernel whose every block reads
   // them never sees them half-updated by the block that owns them:
   //   bigsnap [9][nb]: x, u, a at the step start (written at the end of a step)
@@ -275,6 +293,8 @@ hipError_t launch_h2dh(mx_system* s, const double* v_h);
 hipError_t launch_dh2h(mx_system* s, double* v_h);
 hipError_t launch_init_bodies(mx_system* s, const double* x_h, const double* v_h);
 hipError_t launch_reset_scalars(mx_system* s, int64_t step);
+hipError_t launch_physics(mx_system* s, int masses_only, double t);
+hipError_t launch_physics_reset(mx_system* s, double t);
 // fused small-B kernels over a tile table (n_big <= kSmallBig in every system);
 // blk bodies per tile (64, 128, 256 or 512), tpb consecutive tiles per block
 hipError_t launch_step_a_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,

@@ -636,3 +636,88 @@ def test_step_parity_disk_model(mx, orc):
     with pytest.raises(mx.MxError) as e:
         mx.Adjoint(w.params, w.x, w.v, w.m_big, w.r_p, w.rho_p, 2, 1)
     assert e.value.code == -1
+
+
+# --------------------------------- time-dependent physics (Sects. 3.1-3.3, 3.6)
+def _physics_workload():
+    """Embryo disk in a gas disk where embryo 0 grows through both phases, opens a
+    gap and migrates inward through both phases, fast enough that every law acts
+    within a dozen steps, with the step switch armed just inside its orbit."""
+    w = ic.embryo_disk(seed=31, n_small=3000, n_emb=4)
+    dt = w.params["dt"]
+    import oracle as _o
+    o = _o.OracleSystem.from_workload(w)
+    xh, vh = o.get_state()
+    a0 = _o.x2el(ic.G * (1 + w.m_big[0]), xh[:, 0], vh[:, 0])[0]
+    o.close()
+    m0 = w.m_big[0]
+    planets = [dict(M0=m0, Mc=4 * m0, tau_c=3 * dt, Mf=60 * m0, tau_g=5 * dt, R_I=2e-5,
+                    da1=-0.04 * a0, tau1=4 * dt, da2=-0.03 * a0, tau2=6 * dt, gap_C=4.0),
+               {}, dict(M0=w.m_big[2], Mc=2 * w.m_big[2], tau_c=6 * dt), {}]
+    return w, planets, dict(a_switch=a0 * 0.975, a_min=0.6 * a0)
+
+
+def test_step_parity_time_dependent_physics(mx, orc):
+    """Growth (both phases), radii, gap, migration (both phases) and the step switch:
+    each step from the same state on both sides (positions and velocities handed
+    over, the time and the physics state kept by each side), every body, the
+    masses, radii, time and step size against the oracle."""
+    w, planets, sw = _physics_workload()
+    g = mx.System.from_workload(w)
+    o = orc.OracleSystem.from_workload(w)
+    g.set_planet_physics(planets, **sw)
+    o.set_physics(planets, **sw)
+    nb = w.params["n_big"]
+    x, u = g.get_dh()
+    o.set_xu(x, u)
+    switched_at = None
+    rng = np.random.default_rng(0)
+    for k in range(14):
+        g.step(1)
+        g.sync()
+        # the oracle's own one-ulp sensitivity from copies of its whole state
+        xs, us = o.get_dh()
+        sx = np.zeros(w.n); su = np.zeros(w.n)
+        ref = o.clone()
+        ref.step(1)
+        xr, ur = ref.get_dh()
+        for _ in range(2):
+            c = o.clone()
+            c.set_xu(xs * (1 + rng.uniform(-2.2e-16, 2.2e-16, xs.shape)),
+                     us * (1 + rng.uniform(-2.2e-16, 2.2e-16, us.shape)))
+            c.step(1)
+            xq, uq = c.get_dh()
+            sx = np.maximum(sx, relerr_per_body(xq, xr))
+            su = np.maximum(su, relerr_per_body(uq, ur))
+            c.close()
+        ref.close()
+        o.step(1)
+        check_step(g, o, nb, sx, su, label=f"physics step {k}")
+        mu_g, rc_g = g.masses()
+        mu_o, rc_o = o.mu()
+        assert np.allclose(mu_g, mu_o, rtol=1e-14, atol=0), k
+        assert np.allclose(rc_g, rc_o, rtol=1e-13, atol=0), k
+        assert np.allclose(g.radii(), o.radii(), rtol=1e-12, atol=0), k
+        tg, hg = g.time()
+        assert abs(tg - o.time()) <= 1e-12 * abs(o.time()) and hg == o.step_size(), k
+        if switched_at is None and hg != w.params["dt"]:
+            switched_at = k
+        xg, ug = g.get_dh()
+        o.set_xu(xg, ug)
+    assert mu_g[0] > 10 * w.m_big[0] * ic.G          # into the runaway phase
+    assert switched_at is not None                    # the step switch happened
+    # a restart puts the clock at step_index dt with the initial step
+    x, u = g.get_dh()
+    g.set_dh(x, u, 14)
+    assert g.time() == (14 * w.params["dt"], w.params["dt"])
+
+
+def test_physics_rejected_where_unsupported(mx):
+    w = ic.crowded_annulus(seed=1, n_big=96, n_small=100, close_pairs=0)
+    g = mx.System.from_workload(w)
+    with pytest.raises(mx.MxError) as e:
+        g.set_planet_physics([{}] * 96)
+    assert e.value.code == -1
+    b = mx.Batch.from_workloads([ic.embryo_disk(seed=2, n_small=100, n_emb=3)])
+    with pytest.raises(mx.MxError):
+        b.system(0).set_planet_physics([{}] * 3)
