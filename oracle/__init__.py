@@ -150,6 +150,13 @@ def _declare(L):
     L.or_step_size.argtypes = [C.c_void_p]
     L.or_set_xu.argtypes = [C.c_void_p, _D, _D]
     L.or_get_gaps.argtypes = [C.c_void_p, _D]
+    L.or_check_removal.restype = C.c_int
+    L.or_check_removal.argtypes = [C.c_void_p, C.c_double]
+    L.or_compact.restype = C.c_int
+    L.or_compact.argtypes = [C.c_void_p, _I32]
+    L.or_get_status.argtypes = [C.c_void_p, _I32]
+    L.or_n_bodies.restype = C.c_int
+    L.or_n_bodies.argtypes = [C.c_void_p]
     L.or_clone.restype = C.c_void_p
     L.or_clone.argtypes = [C.c_void_p]
     L.or_drag_gaps.argtypes = [C.POINTER(_Params), C.c_int, C.c_int, _D, _D, _D, _D, _D, _D,
@@ -266,6 +273,26 @@ class OracleSystem:
 
     def step_size(self):
         return self._L.or_step_size(self._h)
+
+    def check_removal(self, r_cen=0.0):
+        """Ejection (e >= 1) and central-body encounter flags; returns ejcount."""
+        k = self._L.or_check_removal(self._h, float(r_cen))
+        if k < 0:
+            raise RuntimeError(f"oracle check_removal failed: {k}")
+        return k
+
+    def status(self):
+        st = np.zeros(self.n, dtype=np.int32)
+        self._L.or_get_status(self._h, st.ctypes.data_as(_I32))
+        return st
+
+    def compact(self):
+        """Remove the flagged massless bodies; returns (number removed, index map)."""
+        mp = np.zeros(self.n, dtype=np.int32)
+        k = self._L.or_compact(self._h, mp.ctypes.data_as(_I32))
+        self.n = self._L.or_n_bodies(self._h)
+        self.params["n_small"] = self.n - self.nb
+        return k, mp
 
     def clone(self):
         """A deep copy (state, masses, clock, physics state)."""

@@ -53,6 +53,10 @@ struct or_sys {
   double time, h;                   /* time at the start of the next step; current step */
   double a_switch, a_min;           /* step switch (a_switch <= 0: none) */
   int switched;
+  /* body removal: status (0 alive, -2 central-body encounter, -3 ejected), radial
+   * direction at the previous check (-1 inward, +1 outward, 0 none yet) */
+  int32_t* stat;
+  int8_t* rsign;
 };
 
 /* ------------------------------------------------------------------ */
@@ -1081,7 +1085,8 @@ void or_destroy(or_sys* s) {
   if (!s) return;
   free(s->x); free(s->u); free(s->ag); free(s->x0); free(s->u0); free(s->x1); free(s->u1);
   free(s->ad); free(s->x1k); free(s->u1k); free(s->mu);
-  free(s->phys); free(s->radius); free(s->rad_c); free(s->gaps); free(s->gap_on); free(s->mu_init); free(s->rcrit); free(s->rcrit_init);
+  free(s->phys); free(s->radius); free(s->rad_c); free(s->gaps); free(s->gap_on);
+  free(s->stat); free(s->rsign); free(s->mu_init); free(s->rcrit); free(s->rcrit_init);
   free(s->r_p); free(s->rho_p); free(s->growth); free(s->pairs);
   free(s);
 }
@@ -1294,6 +1299,7 @@ int or_set_physics(or_sys* s, const or_planet* pl, double a_switch, double a_min
   int nb = s->nb;
   if (nb <= 0 || !pl || (a_switch > 0.0 && !(a_min > 0.0))) return OR_EINVAL;
   free(s->phys); free(s->radius); free(s->rad_c); free(s->gaps); free(s->gap_on);
+  free(s->stat); free(s->rsign);
   s->phys = (or_planet*)malloc(sizeof(or_planet) * (size_t)nb);
   s->radius = (double*)calloc((size_t)nb, sizeof(double));
   s->rad_c = (double*)calloc((size_t)nb, sizeof(double));
@@ -1366,5 +1372,109 @@ or_sys* or_clone(const or_sys* s) {
   c->radius = dup_bytes(s->radius, nbs); c->rad_c = dup_bytes(s->rad_c, nbs);
   c->gaps = dup_bytes(s->gaps, 3 * nbs);
   c->gap_on = dup_bytes(s->gap_on, sizeof(int) * (size_t)(s->nb > 0 ? s->nb : 1));
+  c->stat = dup_bytes(s->stat, sizeof(int32_t) * (size_t)s->n);
+  c->rsign = dup_bytes(s->rsign, (size_t)s->n);
   return c;
+}
+
+/* Body removal.  The ejection criterion of Sect. 3.5: a body whose osculating
+ * orbit about the star is unbound, e >= 1 (gm = G(m0 + m) for massive bodies,
+ * G m0 for massless ones; heliocentric position and velocity), is flagged
+ * stat = -3 and its mass set to zero.  Central-body encounters (the mce_cent
+ * routine, whose test the paper does not print): with r_cen > 0 a body is flagged
+ * stat = -2 when its distance from the star is <= r_cen, or when it passed
+ * pericentre since the previous check (radial velocity inward then, outward or
+ * zero now) on an orbit of perihelion distance q = |h|^2 / (gm (1 + e)) <= r_cen.
+ * A flagged massive body keeps its place with zero mass, zero changeover radius
+ * and its growth, migration and gap switched off; or_compact removes flagged
+ * massless bodies.  Returns ejcount, the number of bodies with stat < 0 (the
+ * workshare count of Sect. 2.1.2).                                            */
+static int ensure_status(or_sys* s) {
+  if (s->stat) return OR_OK;
+  s->stat = (int32_t*)calloc((size_t)s->n, sizeof(int32_t));
+  s->rsign = (int8_t*)calloc((size_t)s->n, 1);
+  return s->stat && s->rsign ? OR_OK : OR_ENOMEM;
+}
+
+int or_check_removal(or_sys* s, double r_cen) {
+  if (ensure_status(s) != OR_OK) return OR_ENOMEM;
+  int n = s->n, nb = s->nb;
+  double P[3];
+  momentum(s, s->u, P);
+  int count = 0;
+  for (int t = 0; t < n; ++t) {
+    if (s->stat[t] < 0) { ++count; continue; }
+    double x[3] = {s->x[t], s->x[n + t], s->x[2 * n + t]};
+    double v[3];
+    for (int c = 0; c < 3; ++c) v[c] = s->u[c * n + t] + P[c] / s->mu0;
+    double gm = s->mu0 + (t < nb ? s->mu[t] : 0.0);
+    double el[6];
+    or_x2el(gm, x, v, el);
+    double e = el[1], q = el[3];
+    double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    double rdot = x[0] * v[0] + x[1] * v[1] + x[2] * v[2];
+    int st = 0;
+    if (e >= 1.0) st = -3;
+    else if (r_cen > 0.0 && (r <= r_cen || (s->rsign[t] < 0 && rdot >= 0.0 && q <= r_cen)))
+      st = -2;
+    s->rsign[t] = rdot < 0.0 ? -1 : 1;
+    if (st < 0) {
+      s->stat[t] = st;
+      ++count;
+      if (t < nb) {
+        s->mu[t] = 0.0;
+        s->rcrit[t] = 0.0;
+        if (s->growth) s->growth[3 * t + 2] = 0.0;
+        if (s->phys) memset(&s->phys[t], 0, sizeof(or_planet));
+      }
+    }
+  }
+  return count;
+}
+
+void or_get_status(const or_sys* s, int32_t* stat) {
+  for (int t = 0; t < s->n; ++t) stat[t] = s->stat ? s->stat[t] : 0;
+}
+
+int or_n_bodies(const or_sys* s) { return s->n; }
+
+/* Remove the flagged massless bodies, keeping the order of the others (massive
+ * bodies keep their places).  index_map (or NULL): [n before] new index of each
+ * body, -1 if removed.  Returns the number removed; the end-of-step force is kept
+ * (the survivors' entries).                                                   */
+int or_compact(or_sys* s, int32_t* index_map) {
+  if (!s->stat) {
+    if (index_map)
+      for (int t = 0; t < s->n; ++t) index_map[t] = t;
+    return 0;
+  }
+  int n = s->n, nb = s->nb, m = 0;
+  int32_t* map = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!map) return OR_ENOMEM;
+  for (int t = 0; t < n; ++t) map[t] = (t < nb || s->stat[t] >= 0) ? m++ : -1;
+  int removed = n - m;
+  double* arrs[] = {s->x, s->u, s->ag};
+  for (int a = 0; a < 3; ++a) {
+    double* A = arrs[a];
+    for (int c = 0; c < 3; ++c)
+      for (int t = 0; t < n; ++t)
+        if (map[t] >= 0) A[c * m + map[t]] = A[c * n + t];
+  }
+  for (int t = nb; t < n; ++t)
+    if (map[t] >= 0) {
+      s->r_p[map[t] - nb] = s->r_p[t - nb];
+      s->rho_p[map[t] - nb] = s->rho_p[t - nb];
+    }
+  for (int t = 0; t < n; ++t)
+    if (map[t] >= 0) {
+      s->stat[map[t]] = s->stat[t];
+      s->rsign[map[t]] = s->rsign[t];
+    }
+  if (index_map) memcpy(index_map, map, sizeof(int32_t) * (size_t)n);
+  free(map);
+  s->n = m;
+  s->ns = m - nb;
+  s->p.n_small = s->ns;
+  s->npairs = 0;
+  return removed;
 }

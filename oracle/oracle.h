@@ -72,6 +72,10 @@ double or_step_size(const or_sys* s);
 void or_set_xu(or_sys* s, const double* x, const double* u);
 void or_get_gaps(const or_sys* s, double* g);
 or_sys* or_clone(const or_sys* s);
+int or_check_removal(or_sys* s, double r_cen);
+int or_compact(or_sys* s, int32_t* index_map);
+void or_get_status(const or_sys* s, int32_t* stat);
+int or_n_bodies(const or_sys* s);
 
 /* --- component functions (pins and kernel-level parity) --------------- */
 double or_changeover(double s, double rc);

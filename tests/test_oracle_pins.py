@@ -963,3 +963,89 @@ def test_step_switch(orc):
             seen = True
     assert seen
     assert o.time() > 0
+
+
+# ------------------------------------------------- body removal (Sect. 3.5, mce_cent)
+def _removal_system():
+    """A planet on a circular orbit at 5 AU and massless bodies: 1 bound, 2 unbound
+    (heliocentric e = 1.02 and e = 3), 3 at r = 0.004 AU (inside r_cen = 0.005),
+    4 on an eccentric orbit (q = 0.003 AU) half a step before pericentre, 5 on an
+    eccentric orbit with q = 0.02 AU half a step before pericentre."""
+    m = 1e-7
+    xs, vs = [], []
+    a_p = 5.0
+    xs.append([a_p, 0, 0]); vs.append([0, math.sqrt(G * (1 + m) / a_p), 0])
+    xs.append([2.0, 0, 0]); vs.append([0, math.sqrt(MU0 / 2.0), 0])
+    # e = 1.02 and e = 3 at pericentre distance 1 AU: v^2 = mu (1 + e) / q
+    xs.append([0, 1.0, 0]); vs.append([-math.sqrt(MU0 * 2.02), 0, 0])
+    xs.append([0, -1.5, 0]); vs.append([math.sqrt(MU0 * 4.0 / 1.5), 0, 0])
+    xs.append([0.004, 0, 0]); vs.append([0, math.sqrt(MU0 / 0.004), 0])
+    dt = 0.05
+    for q in (0.003, 0.02):
+        # near-parabolic orbit of perihelion q, placed at the position reached a half
+        # step before pericentre (a sample of the drift from pericentre backwards)
+        import oracle as _o
+        x1, v1 = _o.drift(MU0, np.array([q, 0, 0]), np.array([0, math.sqrt(MU0 * 1.9 / q), 0]),
+                          -0.5 * dt)
+        xs.append(list(x1)); vs.append(list(v1))
+    x, v = np.array(xs).T, np.array(vs).T
+    p = ic.default_params(n_big=1, n_small=x.shape[1] - 1, dt=dt, rcrit_hill=0.0)
+    return p, x, v, np.array([m])
+
+
+def test_ejection_criterion(orc):
+    p, x, v, m = _removal_system()
+    o = orc.OracleSystem(p, x, v, m)
+    assert o.check_removal(0.0) == 2
+    st = o.status()
+    assert list(st[:4]) == [0, 0, -3, -3]
+    # the bound body right at the edge: e = 1 - 1e-9 stays, e = 1 + 1e-9 goes
+    for e, want in ((1 - 1e-9, 0), (1 + 1e-9, -3)):
+        xx, vv = x[:, :2].copy(), v[:, :2].copy()
+        vv[:, 1] = [0, math.sqrt(MU0 * (1 + e) / 2.0), 0]
+        q = orc.OracleSystem(dict(p, n_small=1), xx, vv, m)
+        q.check_removal(0.0)
+        assert q.status()[1] == want, e
+
+
+def test_central_body_encounters(orc):
+    """r <= r_cen at the check, or a pericentre passage since the previous check with
+    q <= r_cen; q slightly above r_cen is kept."""
+    p, x, v, m = _removal_system()
+    o = orc.OracleSystem(p, x, v, m)
+    r_cen = 0.005
+    assert o.check_removal(r_cen) == 3            # the two unbound and the one inside r_cen
+    assert list(o.status()) == [0, 0, -3, -3, -2, 0, 0]
+    o.step(1)                                     # both eccentric bodies pass pericentre
+    assert o.check_removal(r_cen) == 4
+    assert list(o.status()) == [0, 0, -3, -3, -2, -2, 0]
+
+
+def test_massive_body_removed_keeps_place_with_zero_mass(orc):
+    p, x, v, m = _removal_system()
+    v[:, 0] *= 1.5                                 # the planet unbound: e = 1.25
+    o = orc.OracleSystem(p, x, v, m)
+    o.check_removal(0.0)
+    mu, rc = o.mu()
+    assert o.status()[0] == -3 and mu[0] == 0.0 and rc[0] == 0.0
+
+
+def test_compaction_keeps_survivors_and_order(orc):
+    p, x, v, m = _removal_system()
+    o = orc.OracleSystem(p, x, v, m)
+    o.check_removal(0.005)
+    xd, ud = o.get_dh()
+    a0 = o.accel()
+    k, mp = o.compact()
+    assert k == 3 and list(mp) == [0, 1, -1, -1, -1, 2, 3]
+    xn, un = o.get_dh()
+    keep = [0, 1, 5, 6]
+    assert np.array_equal(xn, xd[:, keep]) and np.array_equal(un, ud[:, keep])
+    assert np.array_equal(o.accel(), a0[:, keep])
+    assert list(o.status()) == [0, 0, 0, 0]
+    o.step(2)                                      # the smaller system steps on
+    # a fresh system built from the survivors steps identically
+    q = orc.OracleSystem(dict(p, n_small=3), x[:, keep], v[:, keep], m)
+    q.set_dh(xn, un, 0)
+    q.step(2)
+    assert np.array_equal(q.get_dh()[0], o.get_dh()[0])
