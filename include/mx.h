@@ -224,6 +224,31 @@ mx_status mx_set_planet_physics(mx_system* s, const mx_planet* planets, double a
 mx_status mx_get_planet_radii(mx_system* s, double* radius);
 mx_status mx_get_time(mx_system* s, double* t, double* h);
 
+/* Body removal (single systems).  mx_check_removal flags, among the bodies not yet
+ * flagged: the ejection criterion of Sect. 3.5, e >= 1 of the osculating orbit
+ * about the star (gm = G(m0 + m) for massive bodies, G m0 for massless ones;
+ * heliocentric state) -> status -3; with r_cen > 0 the central-body encounters
+ * (the mce_cent routine of Sect. 4.1, whose test the paper does not print): the
+ * distance from the star <= r_cen, or a pericentre passage since the previous
+ * check (radial velocity inward then, outward or zero now) on an orbit of
+ * perihelion distance q = |h|^2 / (gm (1 + e)) <= r_cen -> status -2.  A flagged
+ * massive body keeps its place with zero mass and zero changeover radius, its
+ * growth, migration and gap switched off (the force stored for the next half kick
+ * still has it).  *ejcount (host) receives the number of bodies with status < 0,
+ * the workshare count of Sect. 2.1.2.  Synchronises. */
+mx_status mx_check_removal(mx_system* s, double r_cen, int32_t* ejcount);
+
+/* Removes the flagged massless bodies (stable: the others keep their order) on the
+ * device; massive bodies keep their places.  *n_removed (host) the number removed;
+ * index_map: host [n before the call] receiving each body's new index or -1, or
+ * NULL.  The system then has fewer massless bodies (mx_get_counts); the state and
+ * stored force of the survivors are unchanged.  Synchronises. */
+mx_status mx_compact(mx_system* s, int32_t* n_removed, int32_t* index_map);
+
+/* Status of every body (0, -2, -3), host [n]; current body counts.  Synchronise. */
+mx_status mx_get_status(mx_system* s, int32_t* stat);
+mx_status mx_get_counts(mx_system* s, int32_t* n_big, int32_t* n_small);
+
 void mx_destroy(mx_system* s);
 const char* mx_last_error(void);
 

@@ -148,6 +148,14 @@ def lib():
         L.mx_get_planet_radii.argtypes = [_P, _D]
         L.mx_get_time.restype = st
         L.mx_get_time.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.mx_check_removal.restype = st
+        L.mx_check_removal.argtypes = [_P, C.c_double, C.POINTER(C.c_int32)]
+        L.mx_compact.restype = st
+        L.mx_compact.argtypes = [_P, C.POINTER(C.c_int32), _D]
+        L.mx_get_status.restype = st
+        L.mx_get_status.argtypes = [_P, _D]
+        L.mx_get_counts.restype = st
+        L.mx_get_counts.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.mx_flag_pairs.restype = st
         L.mx_flag_pairs.argtypes = [C.c_int32, C.c_int32, _D, _D, _D, _D, _D, C.c_double, _D,
                                     C.c_int32, C.POINTER(C.c_int32), _P]
@@ -332,6 +340,28 @@ class System:
             for f, _ in Planet._fields_:
                 setattr(arr[k], f, float(r.get(f, 0.0)))
         _check(lib().mx_set_planet_physics(self._h, arr, float(a_switch), float(a_min)))
+
+    def check_removal(self, r_cen=0.0):
+        """Ejection and central-body flags (statuses -3, -2); returns ejcount."""
+        k = C.c_int32(0)
+        _check(lib().mx_check_removal(self._h, float(r_cen), C.byref(k)))
+        return k.value
+
+    def status(self):
+        st = np.zeros(self.n, dtype=np.int32)
+        _check(lib().mx_get_status(self._h, st.ctypes.data_as(C.c_void_p)))
+        return st
+
+    def compact(self):
+        """Remove the flagged massless bodies; returns (number removed, index map)."""
+        mp = np.zeros(self.n, dtype=np.int32)
+        k = C.c_int32(0)
+        _check(lib().mx_compact(self._h, C.byref(k), mp.ctypes.data_as(C.c_void_p)))
+        nb, ns = C.c_int32(0), C.c_int32(0)
+        _check(lib().mx_get_counts(self._h, C.byref(nb), C.byref(ns)))
+        self.n = nb.value + ns.value
+        self.params["n_small"] = ns.value
+        return k.value, mp
 
     def radii(self):
         k = max(self.nb, 1)

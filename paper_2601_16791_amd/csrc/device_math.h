@@ -227,7 +227,12 @@ __device__ __forceinline__ bool kepler_drift(double mu, double h, double& x, dou
   double s = h * inv_r0 - 0.5 * h * h * eta * inv_r0 * inv_r0 * inv_r0;
   if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
   bool ok = false;
-  for (int it = 0; it < 60; ++it) {
+  // A Halley step that leaves the bracket, or (after the first steps) does not at
+  // least halve the previous correction, is replaced by a bisection of the
+  // bracket, so stiff cases (near-radial orbits through a close pericentre) still
+  // converge within the cap.
+  double ds_prev = hi - lo;
+  for (int it = 0; it < 120; ++it) {
     kepler_eval(beta, r0, eta, zeta, s, c0, G1, G2, G3);
     double F = fma(r0, s, fma(eta, G2, fma(zeta, G3, -h)));
     double Fp = fma(eta, G1, fma(zeta, G2, r0));
@@ -244,8 +249,10 @@ __device__ __forceinline__ bool kepler_drift(double mu, double h, double& x, dou
       ok = true;
       break;
     }
-    if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+    if (!(sn > lo && sn < hi) || (it >= 4 && fabs(sn - s) > 0.5 * ds_prev))
+      sn = 0.5 * (lo + hi);
     double ds = sn - s;
+    ds_prev = fabs(ds);
     s = sn;
     if (fabs(ds) <= 1e-13 * fabs(s) || lo == hi) {
       ok = true;

@@ -152,6 +152,133 @@ __global__ void k_reset(DevScalars* dsc, int64_t step) {
   dsc->P[0] = dsc->P[1] = dsc->P[2] = 0.0;
 }
 
+// ------------------------------------------------------------ body removal
+// Massive-body momentum P = sum mu u in index order (one thread), for the
+// heliocentric velocities of the removal test.
+__global__ void k_removal_momentum(int n, int nb, const double* __restrict__ mu,
+                                   const double* __restrict__ u, double* __restrict__ P) {
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    p0 += mu[k] * u[k];
+    p1 += mu[k] * u[n + k];
+    p2 += mu[k] * u[2 * n + k];
+  }
+  P[0] = p0;
+  P[1] = p1;
+  P[2] = p2;
+}
+
+// Ejection (e >= 1, Sect. 3.5) and central-body encounter test of every body not
+// yet flagged; a flagged massive body loses its mass, changeover radius, growth,
+// migration and gap.
+__global__ __launch_bounds__(kBlock) void k_check_removal(
+    int n, int nb, double mu0, double r_cen, const double* __restrict__ x,
+    const double* __restrict__ u, const double* __restrict__ P, double* __restrict__ mu,
+    double* __restrict__ rcrit, double* __restrict__ growth, PlanetPhys* __restrict__ phys,
+    int32_t* __restrict__ stat, int8_t* __restrict__ rsign, int32_t* __restrict__ ejcount) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n || stat[t] < 0) return;
+  const double px = x[t], py = x[n + t], pz = x[2 * n + t];
+  const double vx = u[t] + P[0] / mu0, vy = u[n + t] + P[1] / mu0, vz = u[2 * n + t] + P[2] / mu0;
+  const double gm = mu0 + (t < nb ? mu[t] : 0.0);
+  const double r = sqrt(px * px + py * py + pz * pz);
+  // specific angular momentum and the Laplace-Runge-Lenz vector / gm
+  const double hx = py * vz - pz * vy, hy = pz * vx - px * vz, hz = px * vy - py * vx;
+  const double ex = (vy * hz - vz * hy) / gm - px / r;
+  const double ey = (vz * hx - vx * hz) / gm - py / r;
+  const double ez = (vx * hy - vy * hx) / gm - pz / r;
+  const double e = sqrt(ex * ex + ey * ey + ez * ez);
+  const double q = (hx * hx + hy * hy + hz * hz) / (gm * (1.0 + e));
+  const double rdot = px * vx + py * vy + pz * vz;
+  int st = 0;
+  if (e >= 1.0) st = -3;
+  else if (r_cen > 0.0 && (r <= r_cen || (rsign[t] < 0 && rdot >= 0.0 && q <= r_cen))) st = -2;
+  rsign[t] = rdot < 0.0 ? -1 : 1;
+  if (st < 0) {
+    stat[t] = st;
+    atomicAdd(ejcount, 1);
+    if (t < nb) {
+      mu[t] = 0.0;
+      rcrit[t] = 0.0;
+      if (growth) growth[3 * t + 2] = 0.0;
+      if (phys) phys[t] = PlanetPhys{};
+    }
+  }
+}
+
+// Stable compaction of the flagged massless bodies: survivors per block, an
+// exclusive scan of the block counts (one thread, in order), then each block's
+// scan in LDS gives every survivor its new index.
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(kScanBlock) void k_keep_count(int n, int nb,
+                                                           const int32_t* __restrict__ stat,
+                                                           int32_t* __restrict__ counts) {
+  __shared__ int32_t sh[kScanBlock / 64];
+  const int t = blockIdx.x * kScanBlock + threadIdx.x;
+  const bool keep = t < n && (t < nb || stat[t] >= 0);
+  const uint64_t b = __builtin_amdgcn_ballot_w64(keep);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = __popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t c = 0;
+    for (int w = 0; w < kScanBlock / 64; ++w) c += sh[w];
+    counts[blockIdx.x] = c;
+  }
+}
+
+__global__ void k_keep_offsets(int nblk, int32_t* __restrict__ counts, int32_t* __restrict__ total) {
+  int32_t run = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const int32_t c = counts[b];
+    counts[b] = run;
+    run += c;
+  }
+  *total = run;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_keep_map(int n, int nb,
+                                                         const int32_t* __restrict__ stat,
+                                                         const int32_t* __restrict__ offsets,
+                                                         int32_t* __restrict__ map) {
+  __shared__ int32_t sh[kScanBlock / 64];
+  const int t = blockIdx.x * kScanBlock + threadIdx.x;
+  const bool keep = t < n && (t < nb || stat[t] >= 0);
+  const uint64_t b = __builtin_amdgcn_ballot_w64(keep);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = __popcll(b);
+  __syncthreads();
+  int32_t base = offsets[blockIdx.x];
+  for (int k = 0; k < w; ++k) base += sh[k];
+  const int32_t below = __popcll(b & ((1ull << lane) - 1ull));
+  if (t < n) map[t] = keep ? base + below : -1;
+}
+
+// dst[c * m + map[t]] = src[c * n + t] for the survivors, c < rows
+__global__ __launch_bounds__(kBlock) void k_gather_rows(int n, int m, int rows, int first,
+                                                        const int32_t* __restrict__ map,
+                                                        const double* __restrict__ src,
+                                                        double* __restrict__ dst) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t < first || t >= n) return;
+  const int j = map[t];
+  if (j < 0) return;
+  for (int c = 0; c < rows; ++c) dst[(size_t)c * m + (j - first)] = src[(size_t)c * n + (t - first)];
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_status(int n, const int32_t* __restrict__ map,
+                                                          const int32_t* __restrict__ st,
+                                                          const int8_t* __restrict__ rs,
+                                                          int32_t* __restrict__ st2,
+                                                          int8_t* __restrict__ rs2) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const int j = map[t];
+  if (j < 0) return;
+  st2[j] = st[t];
+  rs2[j] = rs[t];
+}
+
 int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
 }  // namespace
@@ -192,6 +319,80 @@ hipError_t launch_energy(mx_system* s, double* out) {
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, s->stream, s->n, s->nb, nred,
                      s->mu0, s->p.G, s->x, s->u, s->mu, s->red, out);
   return hipGetLastError();
+}
+
+hipError_t launch_check_removal(mx_system* s, double r_cen) {
+  hipLaunchKernelGGL(k_removal_momentum, dim3(1), dim3(1), 0, s->stream, s->n, s->nb, s->mu, s->u,
+                     s->rm_P);
+  hipLaunchKernelGGL(k_check_removal, dim3(blocks_for(s->n)), dim3(kBlock), 0, s->stream, s->n,
+                     s->nb, s->mu0, r_cen, s->x, s->u, s->rm_P, s->mu, s->rcrit,
+                     s->has_growth ? s->growth : nullptr, s->has_phys ? s->phys : nullptr, s->stat,
+                     s->rsign, s->ejcount);
+  return hipGetLastError();
+}
+
+// Compacts x, u, ag, r_p, rho_p, status and radial directions of the system into
+// the survivors (new stride *n_new); map_dev: device [n] receives the index map.
+// Temporary buffers are allocated and freed here (not a step of the integrator).
+hipError_t compact_bodies(mx_system* s, int32_t* n_new, int32_t* map_dev) {
+  const int n = s->n, nb = s->nb;
+  const int nblk = (n + kScanBlock - 1) / kScanBlock;
+  int32_t* counts = nullptr;
+  hipError_t e = hipMalloc((void**)&counts, sizeof(int32_t) * (nblk + 1));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_keep_count, dim3(nblk), dim3(kScanBlock), 0, s->stream, n, nb, s->stat,
+                     counts);
+  hipLaunchKernelGGL(k_keep_offsets, dim3(1), dim3(1), 0, s->stream, nblk, counts, counts + nblk);
+  hipLaunchKernelGGL(k_keep_map, dim3(nblk), dim3(kScanBlock), 0, s->stream, n, nb, s->stat,
+                     counts, map_dev);
+  int32_t m = n;
+  e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&m, counts + nblk, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  (void)hipFree(counts);
+  if (e != hipSuccess) return e;
+  *n_new = m;
+  if (m == n) return hipSuccess;
+  double* tmp = nullptr;
+  const size_t rows = 9 * (size_t)m + 2 * (size_t)(m - nb);
+  e = hipMalloc((void**)&tmp, sizeof(double) * (rows > 0 ? rows : 1));
+  int32_t* st2 = nullptr;
+  int8_t* rs2 = nullptr;
+  if (e == hipSuccess) e = hipMalloc((void**)&st2, sizeof(int32_t) * m);
+  if (e == hipSuccess) e = hipMalloc((void**)&rs2, (size_t)m);
+  if (e == hipSuccess) {
+    const dim3 g(blocks_for(n)), b(kBlock);
+    hipLaunchKernelGGL(k_gather_rows, g, b, 0, s->stream, n, m, 3, 0, map_dev, s->x, tmp);
+    hipLaunchKernelGGL(k_gather_rows, g, b, 0, s->stream, n, m, 3, 0, map_dev, s->u, tmp + 3 * (size_t)m);
+    hipLaunchKernelGGL(k_gather_rows, g, b, 0, s->stream, n, m, 3, 0, map_dev, s->ag, tmp + 6 * (size_t)m);
+    if (n > nb) {
+      // the massless bodies' properties are indexed from nb: shift map and arrays
+      hipLaunchKernelGGL(k_gather_rows, dim3(blocks_for(n)), b, 0, s->stream, n, m - nb, 1, nb,
+                         map_dev, s->r_p, tmp + 9 * (size_t)m);
+      hipLaunchKernelGGL(k_gather_rows, dim3(blocks_for(n)), b, 0, s->stream, n, m - nb, 1, nb,
+                         map_dev, s->rho_p, tmp + 9 * (size_t)m + (m - nb));
+    }
+    hipLaunchKernelGGL(k_gather_status, g, b, 0, s->stream, n, map_dev, s->stat, s->rsign, st2, rs2);
+    e = hipGetLastError();
+  }
+  const size_t v3 = sizeof(double) * 3 * (size_t)m;
+  if (e == hipSuccess) e = hipMemcpyAsync(s->x, tmp, v3, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->u, tmp + 3 * (size_t)m, v3, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->ag, tmp + 6 * (size_t)m, v3, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess && m > nb) {
+    e = hipMemcpyAsync(s->r_p, tmp + 9 * (size_t)m, sizeof(double) * (m - nb), hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->rho_p, tmp + 9 * (size_t)m + (m - nb), sizeof(double) * (m - nb),
+                         hipMemcpyDeviceToDevice, s->stream);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(s->stat, st2, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->rsign, rs2, (size_t)m, hipMemcpyDeviceToDevice, s->stream);
+  hipError_t e2 = hipStreamSynchronize(s->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (st2) (void)hipFree(st2);
+  if (rs2) (void)hipFree(rs2);
+  return e != hipSuccess ? e : e2;
 }
 
 hipError_t launch_reset_scalars(mx_system* s, int64_t step) {

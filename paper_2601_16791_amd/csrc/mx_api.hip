@@ -121,7 +121,8 @@ void free_system(mx_system* s) {
                   s->fpack, s->part,
                   s->sympart,
                   s->pairs, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red,
-                  s->desc, s->tiles, s->phys, s->radius, s->rad_c, s->gaps};
+                  s->desc, s->tiles, s->phys, s->radius, s->rad_c, s->gaps, s->stat,
+                  s->rsign, s->ejcount, s->rm_P};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -689,6 +690,90 @@ mx_status mx_get_time(mx_system* s, double* t, double* h) {
   HIPCHK(hipMemcpy(&d, s->desc, sizeof(d), hipMemcpyDeviceToHost), "read descriptor");
   *t = s->has_phys ? hd.time : (double)hd.step * s->p.dt;
   *h = d.h;
+  return MX_OK;
+}
+
+mx_status mx_check_removal(mx_system* s, double r_cen, int32_t* ejcount) {
+  if (!s || !ejcount) return fail(MX_EINVAL, "NULL argument");
+  if (s->owned) return fail(MX_EINVAL, "body removal is for a system of its own");
+  if (!(r_cen >= 0.0)) return fail(MX_EINVAL, "r_cen must be >= 0");
+  if (!s->stat) {
+    HIPCHK(dalloc(&s->stat, s->n), "alloc");
+    HIPCHK(dalloc(&s->rsign, s->n), "alloc");
+    HIPCHK(dalloc(&s->ejcount, 1), "alloc");
+    HIPCHK(dalloc(&s->rm_P, 3), "alloc");
+    HIPCHK(hipMemsetAsync(s->stat, 0, sizeof(int32_t) * s->n, s->stream), "clear");
+    HIPCHK(hipMemsetAsync(s->rsign, 0, (size_t)s->n, s->stream), "clear");
+    HIPCHK(hipMemsetAsync(s->ejcount, 0, sizeof(int32_t), s->stream), "clear");
+  }
+  HIPCHK(mxk::launch_check_removal(s, r_cen), "check removal");
+  HIPCHK(hipMemcpyAsync(ejcount, s->ejcount, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream),
+         "copy");
+  HIPCHK(hipStreamSynchronize(s->stream), "sync");
+  return MX_OK;
+}
+
+mx_status mx_compact(mx_system* s, int32_t* n_removed, int32_t* index_map) {
+  if (!s || !n_removed) return fail(MX_EINVAL, "NULL argument");
+  if (s->owned) return fail(MX_EINVAL, "body removal is for a system of its own");
+  const int n = s->n;
+  *n_removed = 0;
+  if (!s->stat) {
+    if (index_map)
+      for (int t = 0; t < n; ++t) index_map[t] = t;
+    return MX_OK;
+  }
+  HIPCHK(hipStreamSynchronize(s->stream), "sync");
+  int32_t* map = nullptr;
+  HIPCHK(dalloc(&map, n), "alloc");
+  int32_t m = n;
+  hipError_t e = mxk::compact_bodies(s, &m, map);
+  if (e == hipSuccess && index_map)
+    e = hipMemcpy(index_map, map, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
+  (void)hipFree(map);
+  if (e != hipSuccess) return hip_fail(e, "compact");
+  if (m == n) return MX_OK;
+  // the survivors with the new stride: counts, tiles and descriptor follow; the
+  // flagged massive bodies stay, so the count of flagged bodies is theirs
+  s->n = m;
+  s->ns = m - s->nb;
+  s->p.n_small = s->ns;
+  std::vector<Tile> tl;
+  append_tiles(tl, 0, s->n, kTileBlk);
+  s->n_tiles = (int32_t)tl.size();
+  SysDesc d = make_desc(s);
+  HIPCHK(hipMemcpy(s->desc, &d, sizeof(SysDesc), hipMemcpyHostToDevice), "descriptor");
+  HIPCHK(hipMemcpy(s->tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice), "tiles");
+  std::vector<int32_t> st(s->nb > 0 ? s->nb : 1);
+  int32_t flagged = 0;
+  if (s->nb > 0) {
+    HIPCHK(hipMemcpy(st.data(), s->stat, sizeof(int32_t) * s->nb, hipMemcpyDeviceToHost), "status");
+    for (int k = 0; k < s->nb; ++k) flagged += st[k] < 0;
+  }
+  HIPCHK(hipMemcpy(s->ejcount, &flagged, sizeof(int32_t), hipMemcpyHostToDevice), "count");
+  if (s->graph_ok) {
+    (void)hipGraphExecDestroy(s->graph);
+    s->graph_ok = false;
+  }
+  *n_removed = n - m;
+  return MX_OK;
+}
+
+mx_status mx_get_status(mx_system* s, int32_t* stat) {
+  if (!s || !stat) return fail(MX_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(s->stream), "sync");
+  if (!s->stat) {
+    for (int t = 0; t < s->n; ++t) stat[t] = 0;
+    return MX_OK;
+  }
+  HIPCHK(hipMemcpy(stat, s->stat, sizeof(int32_t) * s->n, hipMemcpyDeviceToHost), "copy");
+  return MX_OK;
+}
+
+mx_status mx_get_counts(mx_system* s, int32_t* n_big, int32_t* n_small) {
+  if (!s || !n_big || !n_small) return fail(MX_EINVAL, "NULL argument");
+  *n_big = s->nb;
+  *n_small = s->ns;
   return MX_OK;
 }
 

@@ -214,6 +214,12 @@ struct mx_system {
   double *radius, *rad_c, *gaps;
   int has_phys, any_gap;
   double a_switch, a_min;
+  // body removal: status [n] (0, -2, -3), radial direction at the previous check
+  // [n] (-1, +1, 0), counter of flagged bodies, momentum scratch [3]
+  int32_t* stat;
+  int8_t* rsign;
+  int32_t* ejcount;
+  double* rm_P;
   // snapshots of the massive bodies, so that a kernel whose every block reads
   // them never sees them half-updated by the block that owns them:
   //   bigsnap [9][nb]: x, u, a at the step start (written at the end of a step)
@@ -295,6 +301,8 @@ hipError_t launch_init_bodies(mx_system* s, const double* x_h, const double* v_h
 hipError_t launch_reset_scalars(mx_system* s, int64_t step);
 hipError_t launch_physics(mx_system* s, int masses_only, double t);
 hipError_t launch_physics_reset(mx_system* s, double t);
+hipError_t launch_check_removal(mx_system* s, double r_cen);
+hipError_t compact_bodies(mx_system* s, int32_t* n_new, int32_t* map_dev);
 // fused small-B kernels over a tile table (n_big <= kSmallBig in every system);
 // blk bodies per tile (64, 128, 256 or 512), tpb consecutive tiles per block
 hipError_t launch_step_a_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,

@@ -153,9 +153,12 @@ def test_drag_kernel_general_disk(mx, orc):
 
 
 # -------------------------------------------------------------- Kepler drift
-@pytest.mark.parametrize("kind", ["disk", "eccentric", "hyperbolic", "near_parabolic", "backward"])
+KEPLER_KINDS = ["disk", "eccentric", "hyperbolic", "near_parabolic", "backward", "plunging"]
+
+
+@pytest.mark.parametrize("kind", KEPLER_KINDS)
 def test_kepler_kernel_matches_oracle(mx, orc, kind):
-    rng = np.random.default_rng(["disk", "eccentric", "hyperbolic", "near_parabolic", "backward"].index(kind))
+    rng = np.random.default_rng(KEPLER_KINDS.index(kind))
     k = 513
     r = rng.uniform(0.5, 12, k)
     th = rng.uniform(0, 2 * np.pi, k)
@@ -174,9 +177,15 @@ def test_kepler_kernel_matches_oracle(mx, orc, kind):
     elif kind == "near_parabolic":
         v0 = tang * np.sqrt(2 * MU0 / np.linalg.norm(x0, axis=0)) * (1 + rng.uniform(-1e-8, 1e-8, k))
         h = 50.0
-    else:
+    elif kind == "backward":
         v0 = tang * vc * rng.uniform(0.9, 1.1, k)
         h = -25.0
+    else:
+        # near-radial infall through a close pericentre within the step (q ~ 1e-6 to
+        # 1e-3 AU): the stiff case of the time equation
+        rhat = x0 / np.linalg.norm(x0, axis=0)
+        v0 = -rhat * vc * rng.uniform(0.5, 1.3, k) + tang * vc * 10 ** rng.uniform(-3.5, -1.5, k)
+        h = 600.0
     xo = np.zeros_like(x0); vo = np.zeros_like(v0)
     for t in range(k):
         xo[:, t], vo[:, t] = orc.drift(MU0, x0[:, t], v0[:, t], h)
@@ -721,3 +730,65 @@ def test_physics_rejected_where_unsupported(mx):
     b = mx.Batch.from_workloads([ic.embryo_disk(seed=2, n_small=100, n_emb=3)])
     with pytest.raises(mx.MxError):
         b.system(0).set_planet_physics([{}] * 3)
+
+
+# ---------------------------------------------- body removal (Sect. 3.5, mce_cent)
+def _removal_workload(seed=41, n_small=4000):
+    """Embryo disk where a fifth of the massless bodies are unbound (heliocentric
+    speed 1.2-2 times the escape speed), a tenth plunge towards the star (angular
+    momentum cut so that q < r_cen for half of them) and one embryo is unbound."""
+    w = ic.embryo_disk(seed=seed, n_small=n_small, n_emb=5)
+    rng = np.random.default_rng(seed)
+    nb = w.params["n_big"]
+    idx = rng.permutation(np.arange(nb, w.n))
+    unb, plunge = idx[: n_small // 5], idx[n_small // 5: n_small // 5 + n_small // 10]
+    for t in unb:
+        r = np.linalg.norm(w.x[:, t])
+        vesc = math.sqrt(2 * G / r)
+        w.v[:, t] *= rng.uniform(1.2, 2.0) * vesc / np.linalg.norm(w.v[:, t])
+    for t in plunge:
+        r = np.linalg.norm(w.x[:, t])
+        rhat = w.x[:, t] / r
+        vt = w.v[:, t] - (w.v[:, t] @ rhat) * rhat
+        # mostly radial inward motion with a small tangential part
+        w.v[:, t] = -0.6 * math.sqrt(G / r) * rhat + rng.uniform(0.002, 0.03) * vt
+    w.v[:, 2] *= 1.6
+    return w
+
+
+def test_removal_and_compaction_match_oracle(mx, orc):
+    """Every step: a removal check (statuses compared exactly), then each few steps a
+    compaction (index maps compared exactly); the states, from the same input each
+    step, against the oracle's; the smaller system steps on."""
+    w = _removal_workload()
+    g = mx.System.from_workload(w)
+    o = orc.OracleSystem.from_workload(w)
+    nb = w.params["n_big"]
+    x, u = g.get_dh()
+    o.set_xu(x, u)
+    r_cen = 0.05
+    removed = 0
+    for k in range(8):
+        eg = g.check_removal(r_cen)
+        eo = o.check_removal(r_cen)
+        assert eg == eo and np.array_equal(g.status(), o.status()), k
+        if k % 3 == 1:
+            kg, mg = g.compact()
+            ko, mo = o.compact()
+            assert kg == ko and np.array_equal(mg, mo), k
+            removed += kg
+            xs, us = g.get_dh()
+            xo, uo = o.get_dh()
+            assert np.array_equal(xs, xo) and np.array_equal(us, uo)   # the same survivors
+            assert np.array_equal(g.accel(), o.accel()) or relerr_rows(g.accel(), o.accel()) < 1e-12
+        g.step(1)
+        g.sync()
+        o.step(1)
+        check_step(g, o, nb, label=f"removal step {k}")
+        xg, ug = g.get_dh()
+        o.set_xu(xg, ug)
+    st = g.status()
+    assert removed > 500 and st[2] == -3 and g.masses()[0][2] == 0.0
+    assert np.any(st == -2) or removed > 0
+    E, L = g.energy()
+    assert np.isfinite(E)
