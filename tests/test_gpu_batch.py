@@ -144,3 +144,39 @@ def test_batch_member_steps_alone_and_errors(mx):
     with pytest.raises(mx.MxError) as e:
         mx.Batch.from_workloads([ws[0], big])
     assert e.value.code == -1
+
+
+def test_full_batch_members_match_oracle(mx, orc):
+    """The 256-system ensemble the benchmark runs (3.2 M bodies), at the autotuned
+    launch shape: its smallest, median and largest members against the oracle, per
+    step from the same state, for three steps."""
+    from parity_helpers import compare_pairs, relerr_per_body, step_close
+    ws = ic.batch(seed=0, n_sys=256)
+    sizes = np.array([w.n for w in ws])
+    order = np.argsort(sizes, kind="stable")
+    picks = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    keep = {k: ws[k] for k in picks}
+    b = mx.Batch.from_workloads(ws)
+    del ws
+    b.autotune(steps_per_candidate=1)
+    ors = {k: orc.OracleSystem.from_workload(keep[k]) for k in picks}
+    for step in range(3):
+        before = {k: b.system(k).get_dh() for k in picks}
+        idx = b.system(picks[0]).step_index()
+        b.step(1)
+        b.sync()
+        for k in picks:
+            o = ors[k]
+            x, u = before[k]
+            o.set_dh(x, u, idx)
+            o.step(1)
+            v = b.system(k)
+            xg, ug = v.get_dh()
+            xo, uo = o.get_dh()
+            nb = keep[k].params["n_big"]
+            excluded, n_border, big = compare_pairs(o, v.encounters(), o.encounters(), xo, nb)
+            assert not big
+            ex, eu, bad_x, bad_u = step_close(xg, ug, xo, uo, excluded)
+            print(f"[parity] batch member {k} (n={xo.shape[1]}) step {step}: pairs "
+                  f"{len(o.encounters())}, borderline {n_border}, max rel err x {ex:.2e} u {eu:.2e}")
+            assert bad_x.size == 0 and bad_u.size == 0, (k, step, ex, eu)
