@@ -44,6 +44,8 @@ COPY_BYTES = 256 << 20     # calibration copy: bytes read (and bytes written)
 # read x,u,a (72) + r_p,rho_p (16, massless only); write x0,u0,x,u (96)
 BYTES_KJD_SMALL = 184
 BYTES_KJD_BIG = 168
+# the joined closing/opening launch: read x, u, r_p, rho_p (64), write x, u (48)
+BYTES_JOINED_SMALL = 112
 
 
 def interactions_per_step(nb: int, n: int) -> int:
@@ -97,12 +99,12 @@ def roofline_for(name: str, avg_s: float, w, n_pairs_avg: float, bs_flop_per_lau
             "model": "24 B per flagged pair (list read, sorted list and plan written)"}
 
 
-def recorded_traffic(kernel_group: str, workload_name: str):
-    """HBM bytes per launch of a kernel group from the committed counter summary
-    (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or
-    None when there is none or the kernel sources changed since it was taken."""
+def recorded(summary: str):
+    """Fields ("- key: value" lines) of the committed rocprofv3 summary
+    profiles/<summary>.md, or None when there is none or the kernel sources it
+    names changed since it was taken (their SHA-256 is recorded with it)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_group}_{workload_name}.md")
+    path = os.path.join(ROOT, "profiles", f"{summary}.md")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -114,12 +116,58 @@ def recorded_traffic(kernel_group: str, workload_name: str):
         h = hashlib.sha256()
         for f in rec["source"].split(","):
             h.update(open(os.path.join(ROOT, f.strip()), "rb").read())
-        digest = h.hexdigest()[:16]
-        if digest != rec["source_sha256_16"]:
+        if h.hexdigest()[:16] != rec["source_sha256_16"]:
             return None
-        return float(rec["bytes_per_launch"]), os.path.relpath(path, ROOT)
-    except (KeyError, OSError, ValueError):
+    except (KeyError, OSError):
         return None
+    rec["path"] = os.path.relpath(path, ROOT)
+    return rec
+
+
+def recorded_sum(rec, prefix: str, kernels):
+    """Sum of rec[prefix.kernel] over kernels (None if any is missing)."""
+    if rec is None:
+        return None
+    try:
+        return sum(float(rec[f"{prefix}.{k}"]) for k in kernels)
+    except (KeyError, ValueError):
+        return None
+
+
+# kernels of each timed group, per workload shape (n_big <= 64: fused small-B path)
+GROUP_KERNELS = {
+    ("bs", True): ["k_bs"], ("bs", False): ["k_bs"],
+    ("kick_jump_drift", True): ["k_step_a"], ("kick_jump_drift", False): ["k_kick_jump_drift"],
+    ("force_kick", True): ["k_step_b"], ("force_kick", False): ["k_force_sym", "k_force_finish_sym"],
+    ("step_joined", True): ["k_step_ba"],
+    ("flag", False): ["k_flag"], ("jump_pack", False): ["k_jump_pack"], ("growth", False): ["k_growth"],
+}
+
+
+def counter_rate(w, group: str, avg_s: float):
+    """Counter-based FP64 rate of a kernel group from the committed counter summary:
+    (ADD + MUL + TRANS + 2 FMA)_F64 instructions per launch times the active lanes per
+    VALU instruction, over the measured average launch."""
+    small = w.params["n_big"] <= 64
+    ks = GROUP_KERNELS.get((group, small))
+    rec = recorded(f"fp64_{w.name}")
+    ops = recorded_sum(rec, "fp64_ops_per_launch", ks) if ks else None
+    if ops is None or avg_s <= 0:
+        return None
+    a = ops / avg_s
+    return {"kernels": ks, "fp64_ops_per_launch": ops, "achieved": a / 1e12,
+            "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": a / PEAK_FP64,
+            "lanes": rec.get("lanes"), "source": rec["path"]}
+
+
+def recorded_traffic(w, group: str):
+    """HBM bytes per launch of a kernel group (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled
+    by a plain copy of known size) from the committed summary, or None."""
+    small = w.params["n_big"] <= 64
+    ks = GROUP_KERNELS.get((group, small))
+    rec = recorded(f"traffic_{w.name}")
+    b = recorded_sum(rec, "bytes_per_launch", ks) if ks else None
+    return None if b is None else (b, rec["path"])
 
 
 def host_cpu():
@@ -206,7 +254,10 @@ def kick_fp64(args):
     I = interactions_per_step(nb, n)
     a = FLOP_PER_INTERACTION * I / avg
     s.close()
+    tr = recorded_traffic(w, "force_kick")
     return {"workload": "self_gravitating", "n_big": nb, "interactions_per_kick": I,
+            "counter_fp64": counter_rate(w, "force_kick", avg),
+            "traffic": tr[0] if tr else None, "traffic_source": tr[1] if tr else None,
             "kernels": "k_force_sym + k_force_finish_sym (start of the first to end of the "
                        "second): massive pairs once each by tiles, Newton's third law",
             "avg_kick_us": avg * 1e6, "launches": n_launch, "achieved": a / 1e12,
@@ -338,6 +389,9 @@ def main():
     ap.add_argument("--event-stride", type=int, default=8,
                     help="HIP events around the dominant kernel group in every k-th timed "
                          "step (an event between two launches delays the second)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the graph-launched pass after the timed region (counter runs: "
+                         "the profiler serialises every replayed kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device-to-device once (reference reading for "
                          "HBM byte counters)")
@@ -405,17 +459,38 @@ def main():
     roof["event_stride"] = args.event_stride
     roof["traffic_unit"] = "bytes per launch"
     roof["traffic_source"] = None
-    tr = recorded_traffic(dominant, w.name)
+    tr = recorded_traffic(w, dominant)
     if tr is not None:
         roof["traffic"], roof["traffic_source"] = tr
+    roof["counter_fp64"] = counter_rate(w, dominant, dom_avg_s)
+    # the launch that closes one step and opens the next (fused small-B path),
+    # timed over further steps of the same run (outside the timed region)
+    step_kernel = None
+    if nb <= 64:
+        ms, nl = s.step_timed(args.profile_steps, "step_joined", args.event_stride)
+        if nl > 0:
+            sk_s = sum(ms) / nl / 1e3
+            b = BYTES_JOINED_SMALL * ns + BYTES_KJD_BIG * nb
+            step_kernel = {"kernel": "k_step_ba", "avg_launch_us": sk_s * 1e6, "launches": nl,
+                           "bound": "hbm", "achieved": b / sk_s / 1e9, "peak": PEAK_HBM / 1e9,
+                           "unit": "GB/s", "frac": b / sk_s / PEAK_HBM,
+                           "model": f"{BYTES_JOINED_SMALL} B per massless body (x, u, r_p, "
+                                    "rho_p read; x, u written)",
+                           "traffic": None, "traffic_source": None,
+                           "counter_fp64": counter_rate(w, "step_joined", sk_s)}
+            tr = recorded_traffic(w, "step_joined")
+            if tr is not None:
+                step_kernel["traffic"], step_kernel["traffic_source"] = tr
     # the same number of steps launched as one captured HIP graph per step (context)
-    s.set_launch_mode("graph")
-    s.step(1)
-    s.sync()
-    t1 = time.perf_counter()
-    s.step(args.steps)
-    s.sync()
-    T_graph = time.perf_counter() - t1
+    T_graph = None
+    if not args.no_graph:
+        s.set_launch_mode("graph")
+        s.step(1)
+        s.sync()
+        t1 = time.perf_counter()
+        s.step(args.steps)
+        s.sync()
+        T_graph = time.perf_counter() - t1
     E, L = s.energy()
     s.close()
     out = {
@@ -437,10 +512,11 @@ def main():
         "steps_per_s": args.steps / T,
         "kernel_us_per_step_events": {k: v * 1e6 for k, v in avg.items()},
         "kernel_us_per_step_bound_events": {k: v * 1e3 for k, v in per_step.items()},
-        "steps_per_s_graph_launch": args.steps / T_graph,
+        "steps_per_s_graph_launch": args.steps / T_graph if T_graph else None,
         "encounter_pairs_last_step": pairs_last,
         "encounter_pairs_per_step": pairs_avg,
         "roofline": roof,
+        "step_kernel": step_kernel,
     }
     if not args.no_kick:
         out["kick_fp64"] = kick_fp64(args)

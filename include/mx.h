@@ -121,12 +121,16 @@ enum {
   MX_K_KICK_JUMP_DRIFT = 1, /* half kick + gas drag + jump + Kepler drift (with n_big <= 64
                                also the close-encounter flagging) */
   MX_K_FLAG = 2,            /* close-encounter flagging (empty with n_big <= 64) */
-  MX_K_PLAN = 3,            /* sort of the encounter list and subsystem plan */
-  MX_K_BS = 4,              /* Bulirsch-Stoer integration of the subsystems */
+  MX_K_PLAN = 3,            /* empty: the encounter integrator sorts the list and plans its
+                               subsystems itself */
+  MX_K_BS = 4,              /* subsystem plan + Bulirsch-Stoer integration of the subsystems */
   MX_K_JUMP_PACK = 5,       /* second jump, source packing (empty with n_big <= 64: the jump
                                is done by the force kernel) */
   MX_K_FORCE_KICK = 6,      /* changeover-weighted gravity + gas drag + half kick */
-  MX_NUM_KERNELS = 7
+  MX_NUM_KERNELS = 7,
+  MX_K_STEP_JOINED = 7      /* mx_step_timed only: the single launch that closes one step and
+                               opens the next between the steps of a call (n_big <= 64 without
+                               time-dependent masses); never launched in the last step */
 };
 
 /* Same as mx_step, launched without the graph and with a HIP event around each
@@ -135,7 +139,8 @@ enum {
 mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms);
 
 /* Runs n_steps steps with eager launches (no graph) and times one kernel group
- * (an MX_K_* value) with HIP events bound to its kernels' own start and end, in
+ * (an MX_K_* value, or MX_K_STEP_JOINED) with HIP events bound to its kernels' own
+ * start and end, in
  * every stride-th step (steps 0, stride, 2 stride, ...; stride >= 1, else
  * MX_EINVAL): kernel_ms[q] (host, [n_steps]) is the time from the start of the
  * group's first kernel to the end of its last in step q, 0 where step q was not

@@ -262,9 +262,10 @@ class System:
 
     def step_timed(self, n, group, stride=1):
         """n eager steps; HIP events bound to the kernels of `group` (a name of
-        KERNELS) in every `stride`-th step.  Returns (per-step group milliseconds
+        KERNELS, or "step_joined": the launch joining two steps) in every
+        `stride`-th step.  Returns (per-step group milliseconds
         as a list, 0 for untimed steps; timed steps where the group launched)."""
-        g = self.KERNELS.index(group)
+        g = len(self.KERNELS) if group == "step_joined" else self.KERNELS.index(group)
         ms = (C.c_float * max(int(n), 1))()
         nl = C.c_int32(0)
         _check(lib().mx_step_timed(self._h, int(n), g, int(stride), ms, C.byref(nl)))

@@ -386,6 +386,255 @@ __device__ void plan_general(int nb, gmem<int32_t> gpairs, int np, int64_t* K, i
   if (tid == 0) dsc->n_sub = min(nbig_sub + ng, cap_subs);
 }
 
+// ---- single-wave general planner for short lists (np <= kPlanShort, any pairs)
+// The same table as plan_general, with every list held in lanes: the sorted
+// pairs (one per lane), the big-big pairs, the union-find over the bodies they
+// name (node k in lane k, root = smallest body index as in plan_general), the
+// members and pair list of the subsystem being built (lane k = entry k).  The
+// sequential parts run as wave-uniform loops over register data, so no step
+// waits on a memory round trip; each record is stored with one write per lane.
+constexpr int kPlanShort = 32;
+
+struct ShortPlanLds {
+  int64_t a[64], b[64];  // sort input (padded to whole rounds) and output
+};
+
+__device__ __forceinline__ int lane_of(uint64_t m) { return m ? __builtin_ctzll(m) : -1; }
+
+// members held one per lane (lane < m), ascending; insert b unless present
+__device__ __forceinline__ bool wave_insert_sorted(int& memv, int& m, int cap, int b) {
+  const int lane = threadIdx.x & 63;
+  const bool in = lane < m;
+  if (__builtin_amdgcn_ballot_w64(in && memv == b) != 0) return true;
+  if (m >= cap) return false;
+  const int pos = __popcll(__builtin_amdgcn_ballot_w64(in && memv < b));
+  const int up = __shfl_up(memv, 1);
+  if (lane == pos) memv = b;
+  else if (lane > pos && lane <= m) memv = up;
+  ++m;
+  return true;
+}
+
+__device__ void plan_short(int nb, gmem<int32_t> gpairs, int np, gmem<Subsystem> subs,
+                           int32_t cap_subs, DevScalars* __restrict__ dsc, int sort_only,
+                           ShortPlanLds& L) {
+  const int lane = threadIdx.x & 63;
+  // 1. sort by (i, j)
+  const int64_t key_in = lane < np ? make_key(gpairs[2 * lane], gpairs[2 * lane + 1]) : INT64_MAX;
+  L.a[lane] = key_in;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  wave_rank_sort(L.a, L.b, np);
+  const int64_t K = lane < np ? L.b[lane] : INT64_MAX;
+  const int ki = key_hi(K), kj = key_lo(K);
+  if (lane < np) {
+    gpairs[2 * lane] = ki;
+    gpairs[2 * lane + 1] = kj;
+  }
+  if (sort_only) return;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  // 2. big-big pairs in (i, j) order (lane b = pair b); massless pairs keyed (j, i)
+  const bool isbb = lane < np && kj < nb;
+  const uint64_t bbm = __builtin_amdgcn_ballot_w64(isbb);
+  const int nbb = __popcll(bbm);
+  const bool isms = lane < np && !isbb;
+  const uint64_t msm = __builtin_amdgcn_ballot_w64(isms);
+  const int ns = __popcll(msm);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (isbb) L.a[__popcll(bbm & lt)] = K;
+  if (isms) L.b[__popcll(msm & lt)] = make_key(kj, ki);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int bi = lane < nbb ? key_hi(L.a[lane]) : -1;
+  const int bj = lane < nbb ? key_lo(L.a[lane]) : -1;
+  // massless pairs sorted by (j, i)
+  const int64_t skey = lane < ns ? L.b[lane] : INT64_MAX;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  L.a[lane] = skey;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  wave_rank_sort(L.a, L.b, ns);
+  const int64_t sk = lane < ns ? L.b[lane] : INT64_MAX;
+  const int sj = key_hi(sk), si = key_lo(sk);
+  // 3. union-find over the bodies of the big-big pairs (node k = lane k)
+  int nodeb = -1, nodep = lane;
+  int nn = 0;
+  for (int b = 0; b < nbb; ++b) {
+    const int e[2] = {__builtin_amdgcn_readlane(bi, b), __builtin_amdgcn_readlane(bj, b)};
+    int r[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      int k = lane_of(__builtin_amdgcn_ballot_w64(lane < nn && nodeb == e[t]));
+      if (k < 0) {
+        k = nn++;
+        if (lane == k) nodeb = e[t];
+      }
+      int x = k;
+      for (;;) {
+        const int px = __builtin_amdgcn_readlane(nodep, x);
+        if (px == x) break;
+        x = px;
+      }
+      r[t] = x;
+    }
+    if (r[0] != r[1]) {
+      const int b0 = __builtin_amdgcn_readlane(nodeb, r[0]);
+      const int b1 = __builtin_amdgcn_readlane(nodeb, r[1]);
+      if (b0 < b1) {
+        if (lane == r[1]) nodep = r[0];
+      } else {
+        if (lane == r[0]) nodep = r[1];
+      }
+    }
+  }
+  // root node of every big-big pair and of every node (lane-parallel finds)
+  int ncomp = lane;
+  for (;;) {
+    const int p = __shfl(nodep, ncomp);
+    if (__builtin_amdgcn_ballot_w64(p != ncomp) == 0) break;
+    ncomp = p;
+  }
+  int broot = -1;  // root node of big-big pair `lane`
+  for (int k = 0; k < nn; ++k) {
+    const int nbk = __builtin_amdgcn_readlane(nodeb, k), nck = __builtin_amdgcn_readlane(ncomp, k);
+    if (lane < nbb && bi == nbk) broot = nck;
+  }
+  // 4. one subsystem per component, in order of its first pair
+  int nsub = 0;
+  uint64_t emitted = 0;
+  for (int b = 0; b < nbb; ++b) {
+    const int r = __builtin_amdgcn_readlane(broot, b);
+    if ((emitted >> r) & 1ull) continue;
+    emitted |= 1ull << r;
+    if (nsub >= cap_subs) {
+      if (lane == 0) atomicOr(&dsc->err, MXE_SUBSYS);
+      continue;
+    }
+    const bool inc = lane < nbb && broot == r;
+    const uint64_t incm = __builtin_amdgcn_ballot_w64(inc);
+    int memv = 0, m = 0;
+    bool ok = true;
+    for (uint64_t q = incm; q != 0 && ok; q &= q - 1) {
+      const int c = __builtin_ctzll(q);
+      ok = wave_insert_sorted(memv, m, kBsMaxMembers, __builtin_amdgcn_readlane(bi, c)) &&
+           wave_insert_sorted(memv, m, kBsMaxMembers, __builtin_amdgcn_readlane(bj, c));
+    }
+    const int npl = __popcll(incm);
+    if (ok && npl > kBsMaxPairs) ok = false;
+    if (!ok) {
+      if (lane == 0) atomicOr(&dsc->err, MXE_SUBSYS);
+      continue;
+    }
+    const auto R = subs + nsub;
+    if (lane == 0) {
+      R->m = m;
+      R->keep_from = 0;
+      R->np = npl;
+      R->pad = 0;
+    }
+    if (lane < m) R->mem[lane] = memv;
+    // member indices of each pair's ends (uniform loop over the members)
+    int la = -1, lb = -1;
+    for (int k = 0; k < m; ++k) {
+      const int mk = __builtin_amdgcn_readlane(memv, k);
+      if (bi == mk) la = k;
+      if (bj == mk) lb = k;
+    }
+    if (inc) {
+      const int slot = __popcll(incm & lt);
+      R->pl[slot][0] = la;
+      R->pl[slot][1] = lb;
+    }
+    ++nsub;
+  }
+  const int nbig_sub = nsub;
+  // 5. one subsystem per flagged massless body, groups of equal j in order of j
+  const int sjp = __shfl_up(sj, 1);
+  const bool gstart = lane < ns && (lane == 0 || sjp != sj);
+  const uint64_t gsm = __builtin_amdgcn_ballot_w64(gstart);
+  const int ng = __popcll(gsm);
+  int g = 0;
+  for (uint64_t q = gsm; q != 0; q &= q - 1, ++g) {
+    const int q0 = __builtin_ctzll(q);
+    const uint64_t rest = q & (q - 1);
+    const int q1 = rest ? __builtin_ctzll(rest) : ns;
+    const int j = __builtin_amdgcn_readlane(sj, q0);
+    const int slot = nbig_sub + g;
+    if (slot >= cap_subs) {
+      if (lane == 0) atomicOr(&dsc->err, MXE_SUBSYS);
+      continue;
+    }
+    int memv = 0, m = 0;
+    bool ok = true;
+    for (int e = q0; e < q1 && ok; ++e) {
+      const int i = __builtin_amdgcn_readlane(si, e);
+      const int k = lane_of(__builtin_amdgcn_ballot_w64(lane < nn && nodeb == i));
+      if (k >= 0) {
+        const int r = __builtin_amdgcn_readlane(ncomp, k);
+        const uint64_t incm = __builtin_amdgcn_ballot_w64(lane < nbb && broot == r);
+        for (uint64_t c2 = incm; c2 != 0 && ok; c2 &= c2 - 1) {
+          const int c = __builtin_ctzll(c2);
+          ok = wave_insert_sorted(memv, m, kBsMaxMembers - 1, __builtin_amdgcn_readlane(bi, c)) &&
+               wave_insert_sorted(memv, m, kBsMaxMembers - 1, __builtin_amdgcn_readlane(bj, c));
+        }
+      } else {
+        ok = wave_insert_sorted(memv, m, kBsMaxMembers - 1, i);
+      }
+    }
+    const auto R = subs + slot;
+    int npl = 0;
+    if (ok) {
+      const int nbm = m;
+      if (lane == nbm) memv = j;
+      m = nbm + 1;
+      // big-big pairs among the members, then the pairs naming j, both in (i, j) order
+      int la = -1, lb = -1;
+      for (int k = 0; k < nbm; ++k) {
+        const int mk = __builtin_amdgcn_readlane(memv, k);
+        if (bi == mk) la = k;
+        if (bj == mk) lb = k;
+      }
+      const bool inbb = lane < nbb && la >= 0 && lb >= 0;
+      const uint64_t inbbm = __builtin_amdgcn_ballot_w64(inbb);
+      const int nbbp = __popcll(inbbm);
+      npl = nbbp + (q1 - q0);
+      if (npl > kBsMaxPairs) {
+        ok = false;
+      } else {
+        if (inbb) {
+          const int sl = __popcll(inbbm & lt);
+          R->pl[sl][0] = la;
+          R->pl[sl][1] = lb;
+        }
+        int li = -1;
+        for (int k = 0; k < nbm; ++k)
+          if (__builtin_amdgcn_readlane(memv, k) == si) li = k;
+        if (lane >= q0 && lane < q1) {
+          R->pl[nbbp + lane - q0][0] = li;
+          R->pl[nbbp + lane - q0][1] = nbm;
+        }
+        if (lane < m) R->mem[lane] = memv;
+        if (lane == 0) {
+          R->m = m;
+          R->keep_from = nbm;
+          R->np = npl;
+          R->pad = 0;
+        }
+      }
+    }
+    if (!ok && lane == 0) {
+      atomicOr(&dsc->err, MXE_SUBSYS);
+      R->m = 0;  // an empty subsystem keeps the table dense; the integrator skips it
+      R->np = 0;
+      R->keep_from = 0;
+      R->pad = 0;
+    }
+  }
+  if (lane == 0) dsc->n_sub = min(nbig_sub + ng, cap_subs);
+}
+
 // Sort of the flagged list by (i, j) and the subsystem plan, in one block.
 //   - big-big pairs join big bodies (union-find, root = smallest index); every
 //     component of two or more bodies is one subsystem (all members kept);
@@ -508,6 +757,12 @@ __device__ __forceinline__ void plan_block(int n, int nb, int32_t* __restrict__ 
       return;
     }
   }
+  if (np <= kPlanShort) {
+    if (threadIdx.x >= 64) return;
+    plan_short(nb, gpairs, np, gsubs, cap_subs, dsc, sort_only,
+               *reinterpret_cast<ShortPlanLds*>(lk));
+    return;
+  }
   const bool small_list = np <= kPlanLds;
   int64_t* K = small_list ? lk : gkeys;
   int64_t* S = small_list ? ls : gkeys + cap;
@@ -521,13 +776,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(
     int32_t* __restrict__ gidx, int32_t* __restrict__ uf, Subsystem* __restrict__ subs,
     int32_t cap_subs, DevScalars* __restrict__ dsc, int sort_only) {
   plan_block(0, nb, pairs, cap, gkeys, gidx, uf, subs, cap_subs, dsc, sort_only);
-}
-
-// one block per system of the descriptor table
-__global__ __launch_bounds__(kPlanThreads) void k_plan_sys(const SysDesc* __restrict__ desc) {
-  const SysDesc& D = desc[blockIdx.x];
-  if (D.nb == 0) return;
-  plan_block(D.n, D.nb, D.pairs, D.cap_pairs, D.keys, D.plan_idx, D.uf, D.subs, D.cap_subs, D.dsc, 0);
 }
 
 // ------------------------------------------------------------------ BS
@@ -1041,16 +1289,18 @@ __device__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, 
 // each): most steps are accepted in the first round, and the table rows do not
 // depend on later rows, so the accepted column is the one a sequential
 // integrator would stop at.
-// In-kernel plan (plan != 0, systems of at most 64 massive bodies): the blocks
-// of a system plan their subsystems themselves, so the step needs no planning
-// launch.  A list of at most 256 pairs none of which joins two massive bodies
-// (the common case) is planned by every block at once: one wave rank-sorts the
-// 32-bit keys (j, i) in LDS and numbers the groups of equal j, which is the
-// table the planning kernel builds (one subsystem per flagged massless body in
-// order of j, its partners in order of i).  Block 0 also writes that table and
-// the list counters for the readers after the step.  Any other list takes the
-// general plan in block 0 while the other blocks of the system wait for its
-// flag; the wait is bounded, and an expired wait latches an error.
+// In-kernel plan (plan != 0): the blocks of a system plan their subsystems
+// themselves, so the step needs no planning launch.  In systems of at most 64
+// massive bodies a list of at most 256 pairs none of which joins two massive
+// bodies (the common case) is planned by every block at once: one wave
+// rank-sorts the 32-bit keys (j, i) in LDS and numbers the groups of equal j,
+// which is the table the planning kernel builds (one subsystem per flagged
+// massless body in order of j, its partners in order of i).  Block 0 also
+// writes that table and the list counters for the readers after the step.  Any
+// other list (and every list of a system with more massive bodies) takes the
+// general plan in block 0 -- the single-wave planner for short lists -- while
+// the other blocks of the system wait for its flag; the wait is bounded, and an
+// expired wait latches an error.  The step's closing kernel clears the flag.
 struct FastPlan {
   uint32_t ka[256], kb[256];  // keys (j << 6) | i in append order, then sorted
   int32_t gs[257];            // first sorted entry of each group, then the list length
@@ -1187,16 +1437,23 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
         }
       } else {
         if (b0) {
-          plan_general(nb, gpairs, np, D.keys, D.keys + cap_pairs, D.plan_idx,
-                       D.plan_idx + cap_pairs, D.uf, D.subs, cap_subs, dsc, 0, s_scan, &s_nbig);
+          static_assert(sizeof(FastPlan) >= sizeof(ShortPlanLds), "short plan scratch");
+          if (np <= kPlanShort)
+            plan_short(nb, gpairs, np, subs, cap_subs, dsc, 0,
+                       *reinterpret_cast<ShortPlanLds*>(&F));
+          else
+            plan_general(nb, gpairs, np, D.keys, D.keys + cap_pairs, D.plan_idx,
+                         D.plan_idx + cap_pairs, D.uf, D.subs, cap_subs, dsc, 0, s_scan, &s_nbig);
           __syncthreads();
           if (lane == 0) {
             s_nsub = dsc->n_sub;
             __hip_atomic_store(&dsc->plan_ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
           }
         } else if (lane == 0) {
+          // relaxed polls (an acquiring load would invalidate this CU's caches on
+          // every poll), then one acquire fence once the flag is seen
           int it = 0;
-          while (__hip_atomic_load(&dsc->plan_ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+          while (__hip_atomic_load(&dsc->plan_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
             __builtin_amdgcn_s_sleep(8);
             if (++it >= kPlanWaitMax) break;
           }
@@ -1204,6 +1461,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
             atomicOr(&dsc->err, MXE_PLANWAIT);
             s_nsub = 0;
           } else {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_nsub = __hip_atomic_load(&dsc->n_sub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
@@ -1217,7 +1475,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
   // step boundary that follows (the same arithmetic as the joined step kernel,
   // which then copies them instead of computing them in every block).
   if (plan && blockIdx.x == gridDim.x - 1) {
-    if (!bigs_kept && nsub < (int)gridDim.x) {
+    if (!bigs_kept && nsub < (int)gridDim.x && nb <= kSmallBig) {
       __shared__ double b_sh[8];
       __shared__ KickSource b_src[kSmallBig];
       __shared__ double b_bst[12][kSmallBig];
@@ -1442,11 +1700,6 @@ hipError_t launch_flag(mx_system* s) {
   return mxlaunch(s, k_flag, dim3(tiles * split), dim3(kBlock), s->n, s->nb, split, s->p.dt,
                   s->x0, s->u0, s->x, s->u, s->fpack, s->pairs, s->cap_pairs, &s->dsc->n_pairs,
                   &s->dsc->err);
-}
-
-hipError_t launch_plan_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys) {
-  if (n_sys <= 0) return hipSuccess;
-  return mxlaunch_on(st, tm, k_plan_sys, dim3(n_sys), dim3(kPlanThreads), desc);
 }
 
 hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys,

@@ -140,11 +140,10 @@ hipError_t launch_group(mx_system* s, int k, int par = 0) {
                                               kTileBlk, 1, par)
                    : mxk::launch_kick_jump_drift(s);
     case MX_K_FLAG: return small ? hipSuccess : mxk::launch_flag(s);
-    case MX_K_PLAN:  // the fused path plans inside the encounter integrator
-      return s->nb > 0 && !small ? mxk::launch_plan_sys(s->stream, &s->tev, s->desc, 1)
-                                 : hipSuccess;
+    case MX_K_PLAN:  // the encounter integrator plans its subsystems itself
+      return hipSuccess;
     case MX_K_BS:
-      return s->nb > 0 ? mxk::launch_bs_sys(s->stream, &s->tev, s->desc, 1, kBsBlocks, small, par)
+      return s->nb > 0 ? mxk::launch_bs_sys(s->stream, &s->tev, s->desc, 1, kBsBlocks, 1, par)
                        : hipSuccess;
     case MX_K_JUMP_PACK: return small ? hipSuccess : mxk::launch_jump_pack(s);
     default:
@@ -167,9 +166,14 @@ hipError_t enqueue_step(mx_system* s) {
 // (k_step_ba), the same operations per body.  visit(k, q) runs before the launch
 // of group k of step q (the joined launch is visited as the closing group of its
 // first step) and after(k, q) right after it.
+// whether a call of n steps joins the closing and opening kernels of its steps
+bool joinable(const mx_system* s, int32_t n) {
+  return n >= 2 && s->nb <= kSmallBig && !s->has_growth && !s->has_phys;
+}
+
 template <class Visit, class After>
 hipError_t enqueue_steps(mx_system* s, int32_t n, bool join, Visit visit, After after) {
-  join = join && n >= 2 && s->nb <= kSmallBig && !s->has_growth && !s->has_phys;
+  join = join && joinable(s, n);
   for (int32_t q = 0; q < n; ++q) {
     const int par = join ? (q & 1) : 0;  // step parity (buffers alternate between joined steps)
     for (int k = 0; k < MX_NUM_KERNELS; ++k) {
@@ -417,7 +421,7 @@ mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms) {
 
 mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, int32_t stride,
                         float* kernel_ms, int32_t* n_launched) {
-  if (!s || n_steps < 0 || group < 0 || group >= MX_NUM_KERNELS || stride < 1 || !kernel_ms ||
+  if (!s || n_steps < 0 || group < 0 || group > MX_K_STEP_JOINED || stride < 1 || !kernel_ms ||
       !n_launched)
     return fail(MX_EINVAL, "bad argument");
   *n_launched = 0;
@@ -441,17 +445,25 @@ mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, int32_t st
   // the joined launch spans two steps: it is used unless the timed group is one
   // of the two kernels it joins
   const bool join = group != MX_K_KICK_JUMP_DRIFT && group != MX_K_FORCE_KICK;
+  const bool joins = joinable(s, n_steps);
+  // the group launched as kernel k of step q (the joined launch stands at the
+  // closing group of every step but the last)
+  auto timed = [&](int k, int q) {
+    if (q % stride != 0) return false;
+    if (group == MX_K_STEP_JOINED) return joins && k == MX_K_FORCE_KICK && q < n_steps - 1;
+    return k == group;
+  };
   e = enqueue_steps(
       s, n_steps, join,
       [&](int k, int q) {
-        if (k == group && q % stride == 0) {
+        if (timed(k, q)) {
           s->tev.armed = true;
           s->tev.start = ev[2 * (q / stride)];
           s->tev.stop = ev[2 * (q / stride) + 1];
         }
       },
       [&](int k, int q) {
-        if (k == group && q % stride == 0) {
+        if (timed(k, q)) {
           used[q] = s->tev.start == nullptr;  // the start event went to a kernel
           s->tev.armed = false;
           s->tev.start = s->tev.stop = nullptr;

@@ -318,7 +318,6 @@ hipError_t launch_step_ba_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc*
                                 const Tile* tiles, int n_tiles, int blk, int tpb, int par);
 // planner (one block per system) and encounter integrator (bps blocks per system;
 // plan != 0: the integrator plans its subsystems itself, systems of n_big <= 64)
-hipError_t launch_plan_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys);
 hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys,
                          int bps, int plan, int par);
 
