@@ -13,10 +13,14 @@ Extra objects:
                    one is timed over K further steps of the same run with HIP events
                    bound to its kernels' own start and end in every 8th step (eager
                    launches; --event-stride); its
-                   HBM traffic comes from the committed counter summary while the
-                   kernel source is unchanged
+                   HBM traffic and counter-based FP64 rate (counter_fp64) come from
+                   the committed counter summaries while the kernel sources are
+                   unchanged
+  step_kernel   -- the launch that closes one step and opens the next (n_big <= 64),
+                   timed over further steps, against HBM, with its counter FP64 rate
   kick_fp64     -- the force kernel of the fully self-gravitating 4,004-body case
-                   (16.0 M interactions per kick) against FP64 peak
+                   (16.0 M interactions per kick) against FP64 peak, by the 20-flop
+                   model and by counters
   batch         -- 256 independent embryo disks of uneven size stepped together
                    (autotuned launch shape; eager and graph launches), against the
                    sum of the same systems stepped one at a time
