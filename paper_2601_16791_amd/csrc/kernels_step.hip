@@ -25,20 +25,24 @@ using mxd::make_drag_const;
 
 
 // ------------------------------------------------------------------ growth
-// M(t) = M0 + e/(e-1) (Mc - M0) (1 - exp(-t/tau_c)) for t < tau_c, Mc after;
-// rcrit scales with the cube root of the mass (Hill radius).
+// M(t) = M0 + e/(e-1) (Mc - M0) (1 - exp(-t/tau_c)) for t < tau_c, Mc after
+// (body k grows when its tau_c = growth[3 k + 2] > 0); rcrit scales with the
+// cube root of the mass (Hill radius).
+__device__ __forceinline__ double grown_mass(const double* __restrict__ growth, int k, double t) {
+  const double E = 2.718281828459045235;
+  const double tau = growth[3 * k + 2];
+  const double m0 = growth[3 * k], mc = growth[3 * k + 1];
+  return t >= tau ? mc : m0 + (E / (E - 1.0)) * (mc - m0) * (1.0 - exp(-t / tau));
+}
+
 __global__ void k_growth(int nb, double dt, const double* __restrict__ growth,
                          const double* __restrict__ mu_init,
                          const double* __restrict__ rcrit_init, double* __restrict__ mu,
                          double* __restrict__ rcrit, const DevScalars* __restrict__ dsc) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nb) return;
-  double tau = growth[3 * k + 2];
-  if (!(tau > 0.0)) return;
-  const double E = 2.718281828459045235;
-  double t = (double)dsc->step * dt;
-  double m0 = growth[3 * k], mc = growth[3 * k + 1];
-  double m = t >= tau ? mc : m0 + (E / (E - 1.0)) * (mc - m0) * (1.0 - exp(-t / tau));
+  if (!(growth[3 * k + 2] > 0.0)) return;
+  const double m = grown_mass(growth, k, (double)dsc->step * dt);
   mu[k] = m;
   rcrit[k] = rcrit_init[k] * cbrt(m / mu_init[k]);
 }
@@ -178,22 +182,30 @@ __global__ void k_physics_reset(int nb, double t, double dt, double* __restrict_
 }
 
 // ------------------------------------------------- kick + jump + drift
+// Growing bodies (k < gpre with growth[3 k + 2] > 0) take their mass at the
+// step start here, with k_growth's arithmetic: every block evaluates it for its
+// momentum sum, and the owner of the body stores the mass and changeover radius
+// (no block reads mu of a growing body, so the store races with nothing).
 __global__ __launch_bounds__(kBlock) void k_kick_jump_drift(
     int n, int nb, double mu0, double h, DragConst dc, int gas_on, double* __restrict__ x,
     double* __restrict__ u, const double* __restrict__ ag, double* __restrict__ x0s,
-    double* __restrict__ u0s, const double* __restrict__ mu, const double* __restrict__ rcrit,
+    double* __restrict__ u0s, double* __restrict__ mu, double* __restrict__ rcrit,
     const double* __restrict__ r_p, const double* __restrict__ rho_p,
     FlagSource* __restrict__ fpack, DevScalars* __restrict__ dsc,
-    const double* __restrict__ bigsnap) {
+    const double* __restrict__ bigsnap, int gpre, const double* __restrict__ growth,
+    const double* __restrict__ mu_init, const double* __restrict__ rcrit_init) {
   __shared__ double sh[6 * kBlock];
   const double hh = 0.5 * h;
+  const double tg = gpre > 0 ? (double)dsc->step * h : 0.0;
   // massive-body momentum before (drag frame) and after the half kick (jump);
   // big bodies feel no drag, so their kicked velocity is u + hh * ag.
   // (from the step-start snapshot: the blocks that own massive bodies overwrite
   // u while other blocks are still reading)
   double v[6] = {0, 0, 0, 0, 0, 0};
   for (int k = threadIdx.x; k < nb; k += kBlock) {
-    double m = mu[k];
+    double m;
+    if (k < gpre && growth[3 * k + 2] > 0.0) m = grown_mass(growth, k, tg);
+    else m = mu[k];
     double ux = bigsnap[3 * nb + k], uy = bigsnap[4 * nb + k], uz = bigsnap[5 * nb + k];
     v[0] += m * ux;
     v[1] += m * uy;
@@ -226,11 +238,20 @@ __global__ __launch_bounds__(kBlock) void k_kick_jump_drift(
   x[t] = qx; x[n + t] = qy; x[2 * n + t] = qz;
   u[t] = wx; u[n + t] = wy; u[2 * n + t] = wz;
   if (t < nb) {
+    double rc;
+    if (t < gpre && growth[3 * t + 2] > 0.0) {
+      const double m = grown_mass(growth, t, tg);
+      rc = rcrit_init[t] * cbrt(m / mu_init[t]);
+      mu[t] = m;
+      rcrit[t] = rc;
+    } else {
+      rc = rcrit[t];
+    }
     FlagSource f;
     f.x0 = px; f.y0 = py; f.z0 = pz; f.u0x = vx; f.u0y = vy; f.u0z = vz;
     f.dx = qx - px; f.dy = qy - py; f.dz = qz - pz;  // displacement over the drift
     f.u1x = wx; f.u1y = wy; f.u1z = wz;
-    f.rc = rcrit[t];
+    f.rc = rc;
     f.pad0 = f.pad1 = f.pad2 = 0.0;
     fpack[t] = f;
   }
@@ -732,7 +753,8 @@ hipError_t launch_kick_jump_drift(mx_system* s) {
   DragConst dc = make_drag_const(s->p);
   return mxlaunch(s, k_kick_jump_drift, dim3(blocks_for(s->n)), dim3(kBlock), s->n,
                   s->nb, s->mu0, s->p.dt, dc, s->p.gas_on, s->x, s->u, s->ag, s->x0, s->u0,
-                  s->mu, s->rcrit, s->r_p, s->rho_p, s->fpack, s->dsc, s->bigsnap);
+                  s->mu, s->rcrit, s->r_p, s->rho_p, s->fpack, s->dsc, s->bigsnap,
+                  s->has_growth ? s->growth_prefix : 0, s->growth, s->mu_init, s->rcrit_init);
 }
 
 hipError_t launch_jump_pack(mx_system* s) {

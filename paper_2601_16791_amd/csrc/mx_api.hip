@@ -134,7 +134,9 @@ void free_system(mx_system* s) {
 hipError_t launch_group(mx_system* s, int k, int par = 0) {
   const bool small = s->nb <= kSmallBig;
   switch (k) {
-    case MX_K_GROWTH: return s->has_phys ? mxk::launch_physics(s, 0, 0.0) : mxk::launch_growth(s);
+    case MX_K_GROWTH:  // n_big > 64: the masses grow inside the next group's kernel
+      return s->has_phys ? mxk::launch_physics(s, 0, 0.0)
+                         : small ? mxk::launch_growth(s) : hipSuccess;
     case MX_K_KICK_JUMP_DRIFT:
       return small ? mxk::launch_step_a_tiles(s->stream, &s->tev, s->desc, s->tiles, s->n_tiles,
                                               kTileBlk, 1, par)
@@ -336,6 +338,13 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   STEP(hipStreamSynchronize(sm), "sync");
   (void)hipFree(vh_tmp);
   vh_tmp = nullptr;
+  if (s->has_growth) {  // bodies [0, growth_prefix) hold every growing body
+    std::vector<double> gh(3 * (size_t)nb);
+    STEP(hipMemcpy(gh.data(), s->growth, sizeof(double) * gh.size(), hipMemcpyDeviceToHost),
+         "read growth");
+    for (int k = 0; k < nb; ++k)
+      if (gh[3 * k + 2] > 0.0) s->growth_prefix = k + 1;
+  }
 #undef STEP
   if (is_device_ptr && nb > 0) {
     // validate the masses now that they are on the device

@@ -208,6 +208,7 @@ struct mx_system {
   // massive bodies
   double *mu, *rcrit, *mu_init, *rcrit_init, *growth;  // growth: [nb][3] (G*M0, G*Mc, tau)
   int has_growth;
+  int growth_prefix;  // 1 + the largest index of a growing body (0: none)
   // time-dependent physics (mx_set_planet_physics): per-body parameters, radius,
   // radius at the onset of the runaway, gap records [nb][4]
   PlanetPhys* phys;
