@@ -374,6 +374,31 @@ def test_launch_modes_give_identical_states(mx, name, kw, group):
     assert f >= 0 and npairs >= 0
 
 
+@pytest.mark.parametrize("name,kw,joined", [
+    ("embryo_disk", dict(seed=2, n_small=3000, n_emb=8), True),
+    ("self_gravitating", dict(seed=1, n_pl=4, n_pls=600), False),
+])
+def test_joined_launch_timing(mx, name, kw, joined):
+    """The joined-launch timing group: every timed step but the last of the call
+    carries one joined launch on the fused path, none where steps are not joined
+    (more than 64 massive bodies); the states equal plain eager steps."""
+    w = getattr(ic, name)(**kw)
+    a = mx.System.from_workload(w)
+    b = mx.System.from_workload(w)
+    a.step(7)
+    ms, nl = b.step_timed(7, "step_joined", stride=2)  # steps 0, 2, 4, 6 timed
+    assert len(ms) == 7
+    if joined:
+        assert nl == 3 and min(ms[0], ms[2], ms[4]) > 0.0
+        assert ms[1] == ms[3] == ms[5] == ms[6] == 0.0
+    else:
+        assert nl == 0 and max(ms) == 0.0
+    xa, ua = a.get_dh()
+    xb, ub = b.get_dh()
+    assert np.array_equal(xa, xb) and np.array_equal(ua, ub)
+    assert a.step_index() == b.step_index() == 7
+
+
 def test_heliocentric_roundtrip(mx, orc):
     w = ic.two_giants(seed=3, n_small=100)
     g = mx.System.from_workload(w)
