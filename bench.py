@@ -280,7 +280,7 @@ def batch_leg(args):
     bodies = sum(w.n for w in ws)
     b = mx.Batch.from_workloads(ws)
     del ws
-    taken, cfg, best_ms = b.autotune(steps_per_candidate=3)
+    taken, cfg, best_ms = b.autotune(steps_per_candidate=5)
     b.step(args.warmup)
     b.sync()
     t0 = time.perf_counter()

@@ -293,8 +293,9 @@ mx_status mx_batch_set_config(mx_batch* b, int32_t blk, int32_t tiles_per_block,
 mx_status mx_batch_get_config(mx_batch* b, int32_t* cfg);
 
 /* Autotuner: times real steps of the batch (steps_per_candidate per candidate;
- * every candidate gives the same results) over the tile shapes and then the
- * encounter-integrator width, and keeps the fastest.  *steps_taken (host) is the
+ * every candidate gives the same results) over the tile shapes, then over the
+ * encounter-integrator widths 8..64 (each tried twice, in mirrored order, and
+ * judged by the sum), and keeps the fastest.  *steps_taken (host) is the
  * number of steps it advanced; cfg_out (host [3]) the chosen triple; *best_ms the
  * best time per step.  Synchronises and reports device failures. */
 mx_status mx_batch_autotune(mx_batch* b, int32_t steps_per_candidate, int32_t* steps_taken,

@@ -1359,6 +1359,10 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
       dsc->pairs_flagged += (unsigned long long)n_pairs;
       if (np == 0) dsc->n_sub = 0;
     }
+    // a system never has more subsystems than flagged pairs: blocks past the
+    // pair count have nothing to integrate (the last block may still prepare
+    // the next step boundary's massive bodies)
+    if ((int)blockIdx.x >= np && blockIdx.x != gridDim.x - 1) return;
     bigs_kept = np > 0;
     if (np > 0) {
       fast = np <= 256 && nb <= 64 && n < (1 << 26);
