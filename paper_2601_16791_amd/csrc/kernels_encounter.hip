@@ -88,6 +88,149 @@ __global__ __launch_bounds__(kBlock) void k_flag(
   }
 }
 
+// ------------------------------------------------------- flag, culled form
+// Systems of massive bodies only (n_big > 64, no massless body): the bodies are
+// taken in an order of increasing heliocentric distance fixed at init (`perm`)
+// and cut into 64-body chunks.  k_chunk_bounds gives every chunk the range of its
+// bodies' distances at the step start, the largest reach
+// R = |Delta|_inf + (4/27) h (|u0|_inf + |u1|_inf) and the largest changeover
+// radius (ChunkBound; a separate launch: taking the bodies in this order in the
+// drift kernel scatters its accesses and costs more than the launch).  A wave takes a pair of chunks (S <= T;
+// every unordered pair of bodies once): every pair's separation at the step
+// start is at least the radial gap
+// of the chunks (| |a| - |b| | <= |a - b|), and every pair's cheap bound is at
+// most rc_max + sqrt(3) (R_T + R_S), because the relative displacement and
+// velocities are differences of the bodies' own.  A unit whose gap exceeds that
+// (with a margin for rounding) has no candidate and stops.  The order is only a
+// heuristic: a stale order makes the bound weaker, never wrong.  A chunk pair
+// that is not rejected is tested by four waves, each with a quarter of chunk S
+// (so the surviving work spreads over the chip).  The cheap bound
+// and the Hermite minimum are symmetric in the two bodies (the relative
+// quantities only change sign), so each pair is tested with the chunk roles as
+// they come and appended as (smaller index, larger index).
+__device__ __forceinline__ double wave_min_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_chunk_bounds(int nb, double h,
+                                                     const int32_t* __restrict__ perm,
+                                                     const FlagSource* __restrict__ fp,
+                                                     ChunkBound* __restrict__ cb) {
+  const int lane = threadIdx.x, p = blockIdx.x * 64 + lane;
+  const bool v = p < nb;
+  const FlagSource& F = fp[v ? perm[p] : perm[0]];
+  const double k427 = (4.0 / 27.0) * fabs(h);
+  const double r = sqrt(fma(F.z0, F.z0, fma(F.y0, F.y0, F.x0 * F.x0)));
+  const double reach = fmax(fmax(fabs(F.dx), fabs(F.dy)), fabs(F.dz)) +
+                       k427 * (fmax(fmax(fabs(F.u0x), fabs(F.u0y)), fabs(F.u0z)) +
+                               fmax(fmax(fabs(F.u1x), fabs(F.u1y)), fabs(F.u1z)));
+  const double inf = __builtin_inf();
+  const double rmin = wave_min_d(v ? r : inf), rmax = wave_max_d(v ? r : -inf);
+  const double R = wave_max_d(v ? reach : 0.0), rc = wave_max_d(v ? F.rc : 0.0);
+  if (lane == 0) cb[blockIdx.x] = ChunkBound{rmin, rmax, R, rc};
+}
+
+constexpr int kCullPart = 16;  // sources of chunk S per wave: four waves per chunk pair
+
+struct FlagRec {  // the fields of a source record the cheap bound uses
+  double x0, y0, z0, u0x, u0y, u0z, dx, dy, dz, u1x, u1y, u1z, rc;
+};
+__device__ __forceinline__ FlagRec flag_rec(const FlagSource& f) {
+  return FlagRec{f.x0, f.y0, f.z0, f.u0x, f.u0y, f.u0z, f.dx, f.dy, f.dz, f.u1x, f.u1y, f.u1z, f.rc};
+}
+
+__global__ __launch_bounds__(64) void k_flag_cull(
+    int nb, double h, const int32_t* __restrict__ perm, const ChunkBound* __restrict__ cb,
+    const double* __restrict__ x0s, const double* __restrict__ u0s,
+    const double* __restrict__ x1s, const double* __restrict__ u1s,
+    const FlagSource* __restrict__ fp, int32_t* __restrict__ pairs, int32_t cap,
+    int32_t* __restrict__ counter, int32_t* __restrict__ err) {
+  __shared__ FlagSource ls[kCullPart];
+  const int lane = threadIdx.x;
+  const int u = blockIdx.x / (64 / kCullPart);            // chunk pair
+  const int q0 = (blockIdx.x % (64 / kCullPart)) * kCullPart;  // first source of this part
+  // unit u -> chunks (T, S), S <= T, units in order of T
+  int T = (int)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+  while (T * (T + 1) / 2 > u) --T;
+  while ((T + 1) * (T + 2) / 2 <= u) ++T;
+  const int S = u - T * (T + 1) / 2;
+  const ChunkBound bT = cb[T], bS = cb[S];
+  const double gap = fmax(0.0, fmax(bS.rmin - bT.rmax, bT.rmin - bS.rmax));
+  const double B = fmax(bT.rc, bS.rc) + 1.7320508075688773 * (bT.reach + bS.reach) * (1.0 + 1e-12);
+  if (gap > B * (1.0 + 1e-9)) return;  // no pair of the unit is a candidate
+  const int n = nb;  // the arrays' stride: no massless body
+  const double k427 = (4.0 / 27.0) * fabs(h);
+  // this part's source records into LDS (one round trip), this lane's target of chunk T
+  const int q1 = min(q0 + kCullPart, nb - S * 64);
+  if (q0 >= q1) return;
+  {
+    constexpr int kW = sizeof(FlagSource) / sizeof(double);
+    double* dst = reinterpret_cast<double*>(ls);
+    for (int e = lane; e < (q1 - q0) * kW; e += 64)
+      dst[e] = reinterpret_cast<const double*>(fp + perm[S * 64 + q0 + e / kW])[e % kW];
+  }
+  const int pt = T * 64 + lane;
+  const bool tv = pt < nb;
+  const int jb = tv ? perm[pt] : perm[0];
+  const double ax0 = x0s[jb], ay0 = x0s[n + jb], az0 = x0s[2 * n + jb];
+  const double bx0 = u0s[jb], by0 = u0s[n + jb], bz0 = u0s[2 * n + jb];
+  const double bx1 = u1s[jb], by1 = u1s[n + jb], bz1 = u1s[2 * n + jb];
+  const double djx = x1s[jb] - ax0, djy = x1s[n + jb] - ay0, djz = x1s[2 * n + jb] - az0;
+  const double rcj = fp[jb].rc;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint64_t mask = 0;  // bit q - q0: source q of chunk S is a candidate
+  FlagRec Sr = flag_rec(ls[0]);
+  for (int q = q0; q < q1; ++q) {
+    const FlagRec N = flag_rec(ls[(q + 1 < q1 ? q + 1 : q) - q0]);  // read while this one is tested
+    const double r0x = ax0 - Sr.x0, r0y = ay0 - Sr.y0, r0z = az0 - Sr.z0;
+    const double w0x = bx0 - Sr.u0x, w0y = by0 - Sr.u0y, w0z = bz0 - Sr.u0z;
+    const double w1x = bx1 - Sr.u1x, w1y = by1 - Sr.u1y, w1z = bz1 - Sr.u1z;
+    const double ddx = djx - Sr.dx, ddy = djy - Sr.dy, ddz = djz - Sr.dz;
+    const double m0 = fma(r0z, r0z, fma(r0y, r0y, r0x * r0x));
+    const double nd = fmax(fmax(fabs(ddx), fabs(ddy)), fabs(ddz));
+    const double nw = fmax(fmax(fabs(w0x), fabs(w0y)), fabs(w0z)) +
+                      fmax(fmax(fabs(w1x), fabs(w1y)), fabs(w1z));
+    const double rc = fmax(Sr.rc, rcj);
+    // |r(tau) - r0| <= |Delta| + (4/27) h (|w0| + |w1|) for the cubic Hermite on [0,1]
+    const double bound = rc + 1.7320508075688773 * fma(k427, nw, nd) * (1.0 + 1e-12);
+    // each unordered pair once: the whole square off the diagonal, below it on it
+    const bool own = tv & ((T > S) | (q < lane));
+    const bool cand = own & (m0 <= bound * bound * (1.0 + 1e-12));
+    mask |= (uint64_t)cand << (q - q0);
+    Sr = N;
+  }
+  while (mask != 0) {
+    const int q = q0 + __builtin_ctzll(mask);
+    mask &= mask - 1;
+    const int i = perm[S * 64 + q];
+    const FlagSource& Si = fp[i];
+    const double w0x = bx0 - Si.u0x, w0y = by0 - Si.u0y, w0z = bz0 - Si.u0z;
+    const double w1x = bx1 - Si.u1x, w1y = by1 - Si.u1y, w1z = bz1 - Si.u1z;
+    const double r1x = x1s[jb] - x1s[i], r1y = x1s[n + jb] - x1s[n + i],
+                 r1z = x1s[2 * n + jb] - x1s[2 * n + i];
+    const double q0x = ax0 - x0s[i], q0y = ay0 - x0s[n + i], q0z = az0 - x0s[2 * n + i];
+    const double dmin = mxd::hermite_dmin2(q0x, q0y, q0z, w0x, w0y, w0z, r1x, r1y, r1z, w1x, w1y,
+                                           w1z, h);
+    const double rc = fmax(Si.rc, rcj);
+    if (dmin <= rc * rc) {
+      const int idx = atomicAdd(counter, 1);
+      if (idx < cap) {
+        pairs[2 * idx] = min(i, jb);
+        pairs[2 * idx + 1] = max(i, jb);
+      } else {
+        atomicOr(err, MXE_PAIRS);
+      }
+    }
+  }
+}
+
 // Bitonic sort of p2 (a power of two) 64-bit keys with one block; `key` may
 // point to LDS or to global memory.
 __device__ void block_bitonic(int64_t* key, int p2) {
@@ -1698,6 +1841,15 @@ int flag_split(int n, int nb) {
 }
 
 hipError_t launch_flag(mx_system* s) {
+  if (s->flag_perm && s->nb > 0) {
+    const int nC = (s->nb + 63) / 64;
+    hipError_t e = mxlaunch(s, k_chunk_bounds, dim3(nC), dim3(64), s->nb, s->p.dt,
+                            s->flag_perm, s->fpack, s->flag_bounds);
+    if (e != hipSuccess) return e;
+    return mxlaunch(s, k_flag_cull, dim3(nC * (nC + 1) / 2 * (64 / kCullPart)), dim3(64), s->nb,
+                    s->p.dt, s->flag_perm, s->flag_bounds, s->x0, s->u0, s->x, s->u, s->fpack,
+                    s->pairs, s->cap_pairs, &s->dsc->n_pairs, &s->dsc->err);
+  }
   int tiles = (s->n + kBlock - 1) / kBlock;
   int split = flag_split(s->n, s->nb);
   if (s->nb == 0) return hipSuccess;

@@ -118,7 +118,7 @@ void free_system(mx_system* s) {
   delete[] s->tev_pool;
   void* ptrs[] = {s->x, s->u, s->ag, s->x0, s->u0, s->mu, s->rcrit, s->mu_init, s->rcrit_init,
                   s->growth, s->r_p, s->rho_p, s->bigsnap, s->bigmid, s->bignext, s->kpack,
-                  s->fpack, s->part,
+                  s->fpack, s->flag_perm, s->flag_bounds, s->part,
                   s->sympart,
                   s->pairs, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red,
                   s->desc, s->tiles, s->phys, s->radius, s->rad_c, s->gaps, s->stat,
@@ -338,6 +338,21 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   STEP(hipStreamSynchronize(sm), "sync");
   (void)hipFree(vh_tmp);
   vh_tmp = nullptr;
+  if (s->nb > kSmallBig && s->ns == 0) {
+    // order of the culled encounter test: increasing heliocentric distance at init
+    std::vector<double> xh(n3);
+    STEP(hipMemcpy(xh.data(), s->x, sizeof(double) * n3, hipMemcpyDeviceToHost), "read x");
+    std::vector<double> r(nb);
+    for (int k = 0; k < nb; ++k)
+      r[k] = xh[k] * xh[k] + xh[s->n + k] * xh[s->n + k] + xh[2 * s->n + k] * xh[2 * s->n + k];
+    std::vector<int32_t> perm(nb);
+    for (int k = 0; k < nb; ++k) perm[k] = k;
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return r[a] < r[b]; });
+    STEP(dalloc(&s->flag_perm, nb), "alloc order");
+    STEP(dalloc(&s->flag_bounds, (nb + 63) / 64), "alloc chunk bounds");
+    STEP(hipMemcpy(s->flag_perm, perm.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice),
+         "copy order");
+  }
   if (s->has_growth) {  // bodies [0, growth_prefix) hold every growing body
     std::vector<double> gh(3 * (size_t)nb);
     STEP(hipMemcpy(gh.data(), s->growth, sizeof(double) * gh.size(), hipMemcpyDeviceToHost),

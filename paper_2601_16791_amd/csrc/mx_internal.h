@@ -41,6 +41,14 @@ struct __align__(128) FlagSource {  // one massive body over a drift
   double rc, pad0, pad1, pad2;
 };
 
+// Per 64-body chunk of the culled encounter test (massive-only systems, bodies in
+// the order flag_perm): range of the bodies' distances from the star at the step
+// start, the largest reach |Delta|_inf + (4/27) h (|u0|_inf + |u1|_inf) over the
+// drift, the largest changeover radius.
+struct ChunkBound {
+  double rmin, rmax, reach, rc;
+};
+
 struct Subsystem {                  // one Bulirsch-Stoer subsystem
   int32_t m, keep_from, np, pad;
   int32_t mem[kBsMaxMembers];
@@ -233,6 +241,8 @@ struct mx_system {
   // packed sources
   KickSource* kpack;
   FlagSource* fpack;
+  int32_t* flag_perm;     // [nb] body order of the culled encounter test (massive-only systems), or null
+  ChunkBound* flag_bounds;  // [ceil(nb / 64)] per-chunk bounds of the culled encounter test
   // force partials: split sums of the massless targets, symmetric tile-pair rows
   // of the massive-massive block (n_big >= 128)
   double* part;
