@@ -138,14 +138,29 @@ def recorded_sum(rec, prefix: str, kernels):
         return None
 
 
-# kernels of each timed group, per workload shape (n_big <= 64: fused small-B path)
+# kernels of each timed group, per workload shape (n_big <= 64: fused small-B path);
+# where a group runs different kernels in different systems, the alternatives are
+# listed and the first one the summary holds is used
 GROUP_KERNELS = {
     ("bs", True): ["k_bs"], ("bs", False): ["k_bs"],
     ("kick_jump_drift", True): ["k_step_a"], ("kick_jump_drift", False): ["k_kick_jump_drift"],
     ("force_kick", True): ["k_step_b"], ("force_kick", False): ["k_force_sym", "k_force_finish_sym"],
     ("step_joined", True): ["k_step_ba"],
-    ("flag", False): ["k_flag"], ("jump_pack", False): ["k_jump_pack"], ("growth", False): ["k_growth"],
+    ("flag", False): [["k_chunk_bounds", "k_flag_cull"], ["k_flag"]],
+    ("jump_pack", False): ["k_jump_pack"], ("growth", False): ["k_growth"],
 }
+
+
+def group_sum(rec, prefix: str, group_kernels):
+    """recorded_sum over a group's kernels (the first alternative the summary holds)."""
+    if not group_kernels:
+        return None, None
+    alts = group_kernels if isinstance(group_kernels[0], list) else [group_kernels]
+    for ks in alts:
+        v = recorded_sum(rec, prefix, ks)
+        if v is not None:
+            return v, ks
+    return None, None
 
 
 def counter_rate(w, group: str, avg_s: float):
@@ -153,9 +168,8 @@ def counter_rate(w, group: str, avg_s: float):
     (ADD + MUL + TRANS + 2 FMA)_F64 instructions per launch times the active lanes per
     VALU instruction, over the measured average launch."""
     small = w.params["n_big"] <= 64
-    ks = GROUP_KERNELS.get((group, small))
     rec = recorded(f"fp64_{w.name}")
-    ops = recorded_sum(rec, "fp64_ops_per_launch", ks) if ks else None
+    ops, ks = group_sum(rec, "fp64_ops_per_launch", GROUP_KERNELS.get((group, small)))
     if ops is None or avg_s <= 0:
         return None
     a = ops / avg_s
@@ -168,9 +182,8 @@ def recorded_traffic(w, group: str):
     """HBM bytes per launch of a kernel group (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled
     by a plain copy of known size) from the committed summary, or None."""
     small = w.params["n_big"] <= 64
-    ks = GROUP_KERNELS.get((group, small))
     rec = recorded(f"traffic_{w.name}")
-    b = recorded_sum(rec, "bytes_per_launch", ks) if ks else None
+    b, _ = group_sum(rec, "bytes_per_launch", GROUP_KERNELS.get((group, small)))
     return None if b is None else (b, rec["path"])
 
 
