@@ -551,6 +551,38 @@ def test_full_size_embryo_disk_step(mx, orc):
     assert n_pairs > 0
 
 
+def test_culled_flagging_wide_disk_with_planted_pairs(mx, orc):
+    """The all-massive encounter test that rejects whole chunk pairs by distance
+    (bodies over 0.5-4 AU, so most chunk pairs are rejected), with close pairs of
+    massive bodies planted at several distances: every pair the oracle flags is
+    found, and each step matches the oracle from the same state."""
+    w = ic.self_gravitating(seed=5, n_pl=4, n_pls=1500)
+    nb = w.params["n_big"]
+    g0 = mx.System.from_workload(w)
+    _, rc = g0.masses()
+    g0.close()
+    rng = np.random.default_rng(5)
+    order = np.argsort(np.linalg.norm(w.x[:, :nb], axis=0))
+    for k in order[[40, 400, 800, 1200, 1480]]:   # partners at different distances
+        j = int(rng.integers(4, nb))
+        d = rng.normal(size=3)
+        w.x[:, j] = w.x[:, k] + 0.4 * rc[k] * d / np.linalg.norm(d)
+        w.v[:, j] = w.v[:, k] * (1.0 + 1e-4)
+    g = mx.System.from_workload(w)
+    o = orc.OracleSystem.from_workload(w)
+    x, u = g.get_dh()
+    o.set_dh(x, u, 0)
+    g.set_dh(x, u, 0)
+    pairs = 0
+    for k in range(3):
+        x, u = g.get_dh()
+        g.step(1)
+        g.sync()
+        xo, uo, sx, su = oracle_sensitivity(o, x, u, k)
+        pairs += check_step(g, o, nb, sx, su, label=f"culled flagging step {k}")[0]
+    assert pairs >= 10
+
+
 def test_deep_encounters_with_step_halvings(mx, orc):
     """Massless bodies aimed at an embryo with impact parameters of 0.3-3% of its
     changeover radius and slow approach: the encounter integrator has to halve its
