@@ -392,7 +392,7 @@ def main():
     ap.add_argument("--workload", default="embryo_disk")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--profile-steps", type=int, default=100)
-    ap.add_argument("--kick-reps", type=int, default=50)
+    ap.add_argument("--kick-reps", type=int, default=300)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kick", action="store_true")
