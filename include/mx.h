@@ -128,9 +128,14 @@ enum {
                                is done by the force kernel) */
   MX_K_FORCE_KICK = 6,      /* changeover-weighted gravity + gas drag + half kick */
   MX_NUM_KERNELS = 7,
-  MX_K_STEP_JOINED = 7      /* mx_step_timed only: the single launch that closes one step and
+  MX_K_STEP_JOINED = 7,     /* mx_step_timed only: the single launch that closes one step and
                                opens the next between the steps of a call (n_big <= 64 without
                                time-dependent masses); never launched in the last step */
+  MX_K_STEP_JOINT = 8       /* mx_step_timed only: the launch that integrates the encounters of
+                               one step beside the closing of that step and the opening of the
+                               next, between the steps of a call (single systems with
+                               0 < n_big <= 64 without time-dependent masses: what mx_step
+                               launches there); never launched in the last step */
 };
 
 /* Same as mx_step, launched without the graph and with a HIP event around each
@@ -139,7 +144,8 @@ enum {
 mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms);
 
 /* Runs n_steps steps with eager launches (no graph) and times one kernel group
- * (an MX_K_* value, or MX_K_STEP_JOINED) with HIP events bound to its kernels' own
+ * (an MX_K_* value, MX_K_STEP_JOINED or MX_K_STEP_JOINT) with HIP events bound to its
+ * kernels' own
  * start and end, in
  * every stride-th step (steps 0, stride, 2 stride, ...; stride >= 1, else
  * MX_EINVAL): kernel_ms[q] (host, [n_steps]) is the time from the start of the

@@ -262,10 +262,13 @@ class System:
 
     def step_timed(self, n, group, stride=1):
         """n eager steps; HIP events bound to the kernels of `group` (a name of
-        KERNELS, or "step_joined": the launch joining two steps) in every
-        `stride`-th step.  Returns (per-step group milliseconds
-        as a list, 0 for untimed steps; timed steps where the group launched)."""
-        g = len(self.KERNELS) if group == "step_joined" else self.KERNELS.index(group)
+        KERNELS, "step_joined": the launch joining two steps, or "step_joint":
+        the launch integrating one step's encounters beside the closing of that
+        step and the opening of the next) in every `stride`-th step.  Returns
+        (per-step group milliseconds as a list, 0 for untimed steps; timed steps
+        where the group launched)."""
+        extra = {"step_joined": len(self.KERNELS), "step_joint": len(self.KERNELS) + 1}
+        g = extra[group] if group in extra else self.KERNELS.index(group)
         ms = (C.c_float * max(int(n), 1))()
         nl = C.c_int32(0)
         _check(lib().mx_step_timed(self._h, int(n), g, int(stride), ms, C.byref(nl)))

@@ -145,10 +145,12 @@ __global__ __launch_bounds__(kBlock) void k_energy_final(int n, int nb, int nred
 
 __global__ void k_reset(DevScalars* dsc, int64_t step) {
   dsc->step = step;
-  dsc->n_pairs = 0;
-  dsc->n_pairs_alt = 0;
+  for (int r = 0; r < 3; ++r) {
+    dsc->n_pairs[r] = 0;
+    dsc->plan_ready[r] = 0;
+    dsc->bs_done[r] = 0;
+  }
   dsc->n_sub = 0;
-  dsc->plan_ready = 0;
   dsc->P[0] = dsc->P[1] = dsc->P[2] = 0.0;
 }
 

@@ -231,12 +231,12 @@ __global__ __launch_bounds__(64) void k_flag_cull(
   }
 }
 
-// Bitonic sort of p2 (a power of two) 64-bit keys with one block; `key` may
-// point to LDS or to global memory.
-__device__ void block_bitonic(int64_t* key, int p2) {
+// Bitonic sort of p2 (a power of two) 64-bit keys with the first T threads of a
+// block; `key` may point to LDS or to global memory.
+__device__ void block_bitonic(int64_t* key, int p2, int T) {
   for (int k = 2; k <= p2; k <<= 1) {
     for (int jx = k >> 1; jx > 0; jx >>= 1) {
-      for (int i = threadIdx.x; i < p2; i += blockDim.x) {
+      for (int i = threadIdx.x; i < p2; i += T) {
         int ixj = i ^ jx;
         if (ixj > i) {
           bool up = (i & k) == 0;
@@ -260,10 +260,11 @@ __device__ int next_pow2(int v) {
 
 // Ordered compaction over q in [0, m): emit(position, q) for every q with pred(q),
 // positions in increasing q.  Each thread scans a contiguous chunk; chunk counts
-// are prefix-summed in LDS (Hillis-Steele).  Returns the total (block-uniform).
+// are prefix-summed in LDS (Hillis-Steele) over the first T threads of the block.
+// Returns the total (the same in every thread).
 template <class Pred, class Emit>
-__device__ int block_compact(int m, Pred pred, Emit emit, int* scan) {
-  const int T = blockDim.x, tid = threadIdx.x;
+__device__ int block_compact(int m, Pred pred, Emit emit, int* scan, int T) {
+  const int tid = threadIdx.x;
   const int per = (m + T - 1) / T;
   const int b = min(m, tid * per), e = min(m, b + per);
   int c = 0;
@@ -371,38 +372,42 @@ constexpr int kPlanLds = 2048;   // pairs handled in LDS; larger lists use globa
 // General plan (any list): sort by (i, j), big-big components by union-find,
 // one subsystem per flagged massless body.  K, S: 64-bit key arrays of at least
 // next_pow2(np) entries; BB, GS: index arrays of np entries (LDS or global
-// scratch); scan: blockDim.x ints of LDS.
+// scratch); scan: T ints of LDS.  Run by the first T threads of the block (the
+// block's other threads, if any, have exited).  write_back: the list itself is
+// left sorted (else only the subsystem table is written).
 __device__ void plan_general(int nb, gmem<int32_t> gpairs, int np, int64_t* K, int64_t* S,
                              int32_t* BB, int32_t* GS, int32_t* __restrict__ uf,
                              Subsystem* __restrict__ subs, int32_t cap_subs,
                              DevScalars* __restrict__ dsc, int sort_only, int* scan,
-                             int* s_nbig_sub) {
-  const int tid = threadIdx.x, T = blockDim.x;
+                             int* s_nbig_sub, int T, bool write_back) {
+  const int tid = threadIdx.x;
   // 1. sort by (i, j)
   int p2 = next_pow2(np);
   for (int q = tid; q < p2; q += T)
     K[q] = q < np ? make_key(gpairs[2 * q], gpairs[2 * q + 1]) : INT64_MAX;
   __syncthreads();
-  if (np > 1) block_bitonic(K, p2);
-  for (int q = tid; q < np; q += T) {
-    gpairs[2 * q] = key_hi(K[q]);
-    gpairs[2 * q + 1] = key_lo(K[q]);
+  if (np > 1) block_bitonic(K, p2, T);
+  if (write_back) {
+    for (int q = tid; q < np; q += T) {
+      gpairs[2 * q] = key_hi(K[q]);
+      gpairs[2 * q + 1] = key_lo(K[q]);
+    }
   }
   if (sort_only) return;
   // 2. big-big pairs (in (i, j) order) and massless pairs keyed (j, i)
   const int nbb = block_compact(
-      np, [&](int q) { return key_lo(K[q]) < nb; }, [&](int pos, int q) { BB[pos] = q; }, scan);
+      np, [&](int q) { return key_lo(K[q]) < nb; }, [&](int pos, int q) { BB[pos] = q; }, scan, T);
   const int ns = block_compact(
       np, [&](int q) { return key_lo(K[q]) >= nb; },
-      [&](int pos, int q) { S[pos] = make_key(key_lo(K[q]), key_hi(K[q])); }, scan);
+      [&](int pos, int q) { S[pos] = make_key(key_lo(K[q]), key_hi(K[q])); }, scan, T);
   int p2s = next_pow2(ns > 0 ? ns : 1);
   for (int q = ns + tid; q < p2s; q += T) S[q] = INT64_MAX;
   __syncthreads();
-  if (ns > 1) block_bitonic(S, p2s);
+  if (ns > 1) block_bitonic(S, p2s, T);
   // 3. one group per flagged massless body
   const int ng = block_compact(
       ns, [&](int q) { return q == 0 || key_hi(S[q]) != key_hi(S[q - 1]); },
-      [&](int pos, int q) { GS[pos] = q; }, scan);
+      [&](int pos, int q) { GS[pos] = q; }, scan, T);
   int32_t* par = uf;
   int32_t* inbig = uf + nb;
   // 4. components of the big-big graph and their subsystems (one thread; the
@@ -433,7 +438,7 @@ __device__ void plan_general(int nb, gmem<int32_t> gpairs, int np, int64_t* K, i
       sub.m = 0;
       sub.keep_from = 0;
       sub.np = 0;
-      sub.pad = 0;
+      sub.jm = 0;
       bool ok = true;
       for (int c = 0; c < nbb && ok; ++c) {
         int64_t k = K[BB[c]];
@@ -473,7 +478,7 @@ __device__ void plan_general(int nb, gmem<int32_t> gpairs, int np, int64_t* K, i
     Subsystem& sub = subs[slot];  // built in place (no private copy)
     sub.m = 0;
     sub.np = 0;
-    sub.pad = 0;
+    sub.jm = j;
     bool ok = true;
     for (int q = q0; q < q1 && ok; ++q) {
       int i = key_lo(S[q]);
@@ -675,7 +680,7 @@ __device__ void plan_short(int nb, gmem<int32_t> gpairs, int np, gmem<Subsystem>
       R->m = m;
       R->keep_from = 0;
       R->np = npl;
-      R->pad = 0;
+      R->jm = 0;
     }
     if (lane < m) R->mem[lane] = memv;
     // member indices of each pair's ends (uniform loop over the members)
@@ -763,7 +768,7 @@ __device__ void plan_short(int nb, gmem<int32_t> gpairs, int np, gmem<Subsystem>
           R->m = m;
           R->keep_from = nbm;
           R->np = npl;
-          R->pad = 0;
+          R->jm = 0;
         }
       }
     }
@@ -772,7 +777,7 @@ __device__ void plan_short(int nb, gmem<int32_t> gpairs, int np, gmem<Subsystem>
       R->m = 0;  // an empty subsystem keeps the table dense; the integrator skips it
       R->np = 0;
       R->keep_from = 0;
-      R->pad = 0;
+      R->jm = 0;
     }
   }
   if (lane == 0) dsc->n_sub = min(nbig_sub + ng, cap_subs);
@@ -798,10 +803,10 @@ __device__ __forceinline__ void plan_block(int n, int nb, int32_t* __restrict__ 
   __shared__ int32_t lgs[kPlanLds];
   __shared__ int scan[kPlanThreads];
   __shared__ int s_nbig_sub;
-  const int np = min(dsc->n_pairs, cap);
+  const int np = min(dsc->n_pairs[0], cap);
   if (threadIdx.x == 0) {
-    dsc->n_pairs_last = dsc->n_pairs;
-    if (!sort_only) dsc->pairs_flagged += (unsigned long long)dsc->n_pairs;
+    dsc->n_pairs_last = dsc->n_pairs[0];
+    if (!sort_only) dsc->pairs_flagged += (unsigned long long)dsc->n_pairs[0];
   }
   if (np == 0) {
     if (threadIdx.x == 0 && !sort_only) dsc->n_sub = 0;
@@ -882,13 +887,13 @@ __device__ __forceinline__ void plan_block(int n, int nb, int32_t* __restrict__ 
           S->m = 0;  // an empty subsystem keeps the table dense; the integrator skips it
           S->np = 0;
           S->keep_from = 0;
-          S->pad = 0;
+          S->jm = 0;
           continue;
         }
         S->m = k + 1;
         S->keep_from = k;
         S->np = k;
-        S->pad = 0;
+        S->jm = 0;
         for (int q = 0; q < k; ++q) {
           S->mem[q] = li[e + q];
           S->pl[q][0] = q;
@@ -911,7 +916,8 @@ __device__ __forceinline__ void plan_block(int n, int nb, int32_t* __restrict__ 
   int64_t* S = small_list ? ls : gkeys + cap;
   int32_t* BB = small_list ? lbb : gidx;
   int32_t* GS = small_list ? lgs : gidx + cap;
-  plan_general(nb, gpairs, np, K, S, BB, GS, uf, subs, cap_subs, dsc, sort_only, scan, &s_nbig_sub);
+  plan_general(nb, gpairs, np, K, S, BB, GS, uf, subs, cap_subs, dsc, sort_only, scan, &s_nbig_sub,
+               blockDim.x, true);
 }
 
 __global__ __launch_bounds__(kPlanThreads) void k_plan(
@@ -1263,7 +1269,7 @@ __device__ __forceinline__ int first_ok(const double (&lerr)[kC], double tol2) {
 // sequences are not finished.  Returns the number of accepted steps, or -1
 // when more than 30 consecutive failures occurred.
 template <int M, bool LM>
-__device__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, int np,
+__device__ __forceinline__ int bs_small(int lane, int b, double h, double tol2, uint32_t pmask, int np,
                         const double* mum, const double* rcm, double mu0, double* xs,
                         double* vs, double* scal, double (*resS)[kC][6 * 4],
                         const SysDesc& D, DevScalars* __restrict__ dsc) {
@@ -1450,8 +1456,59 @@ struct FastPlan {
 };
 constexpr int kPlanWaitMax = 1 << 22;  // polls of the plan flag (each after a short sleep)
 
-__global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int plan, int par) {
-  const SysDesc& D = desc[blockIdx.y];
+// Joint launches: step q closed and step q + 1 opened for massless body j (the
+// joined step kernel's operations, by lane 0 of the integrator's wave) with the
+// boundary prepared for phase par (jsrc, jbst, jbrc in LDS), from its state after
+// the integrator (xj, vj in LDS) or, when its subsystem was not integrated, after
+// the drift (null: read from x, u).  Step q + 1's pairs go to phase nx.
+__device__ __forceinline__ void joint_member(const SysDesc& D, int j, const double* xj,
+                                          const double* vj, int par, int nx,
+                                          const KickSource* jsrc,
+                                          const double (*jbst)[kSmallBig], const double* jbrc) {
+  const int n = D.n, nb = D.nb;
+  if (threadIdx.x != 0 || j < nb || j >= n) return;
+  const double h = D.h, mu0 = D.mu0;
+  double p[3], v[3], a[3], q[3], w[3], J[3], vpre[3], Ppre[3], Ppost[3];
+  for (int c = 0; c < 3; ++c) {
+    p[c] = xj ? xj[c] : gbl(D.x)[(size_t)c * n + j];
+    v[c] = vj ? vj[c] : gbl(D.u)[(size_t)c * n + j];
+  }
+  const double rp = D.gas_on ? gbl(D.r_p)[j - nb] : 0.0;
+  const double rhop = D.gas_on ? gbl(D.rho_p)[j - nb] : 0.0;
+  const BigNext* N = D.bignext + par;
+  for (int c = 0; c < 3; ++c) {
+    J[c] = N->J[c];
+    vpre[c] = N->vpre[c];
+    Ppre[c] = N->Ppre[c];
+    Ppost[c] = N->Ppost[c];
+  }
+  mxs::close_body(j, nb, jsrc, 0.0, J, vpre, 0.5 * h, D.dc, D.gas_on, rp, rhop, true, p, v, a);
+  if (!isfinite(v[0] + v[1] + v[2] + p[0] + p[1] + p[2])) atomicOr(&D.dsc->err, MXE_NONFINITE);
+  if (!mxs::advance_body(j, nb, mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v, a, q, w))
+    atomicOr(&D.dsc->err, MXE_NOCONV);
+  for (int c = 0; c < 3; ++c) {
+    gbl(D.x)[(size_t)c * n + j] = q[c];
+    gbl(D.u)[(size_t)c * n + j] = w[c];
+  }
+  mxs::flag_body(D, nx, nx, j, n, nb, h, jbst, jbrc, p, v, q, w);
+}
+
+// One block (one wave) of a system's encounter integrator: block bx of nbx.
+// par: the step phase (append counter, plan flag, bigmid and BigNext copies),
+// lst: the flagged list read, clr: the append counter cleared for the next step
+// (-1: none).  kJoint: the integrator runs inside a joint launch beside the
+// closing of step q and the opening of step q + 1 (phase nx); the massive
+// members start from bigpre[par], and with jfast (the boundary of step q was
+// prepared: no flagged pair joins two massive bodies, so every subsystem is one
+// massless body and the massive bodies it met, the massless body last) the wave
+// closes and opens its massless member itself with the prepared boundary (jsrc,
+// jbst, jbrc: LDS of the launch).  The list is then left in append order (the
+// tile blocks of the launch read it).
+template <bool kJoint>
+__device__ __forceinline__ void bs_body(const SysDesc& D, const int bx, const int nbx, int plan,
+                                        int par, int nx, int lst, int clr, bool jfast,
+                                        KickSource* jsrc, double (*jbst)[kSmallBig],
+                                        double* jbrc) {
   const int n = D.n, nb = D.nb;
   const double mu0 = D.mu0, h = D.h, tol = D.bs_tol;
   const auto x0s = gbl(D.x0);
@@ -1479,10 +1536,10 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
   if (!plan) {
     nsub = dsc->n_sub;
   } else {
-    const bool b0 = blockIdx.x == 0;
+    const bool b0 = bx == 0;
     const int cap_pairs = D.cap_pairs, cap_subs = D.cap_subs;
     const bool ordered = D.bs_sched != nullptr;
-    const auto gpairs = gbl(D.pairs);
+    const auto gpairs = gbl(D.pairs) + (size_t)lst * 2 * cap_pairs;
     // the first 256 entries of the list are requested with its length (entries
     // past the length are not used)
     int32_t pre_i[4], pre_j[4];
@@ -1493,9 +1550,9 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
       pre_j[r] = e < cap_pairs ? gpairs[2 * e + 1] : 0;
     }
     const int n_pairs = *pair_counter(dsc, par);
-    // the other counter takes the next step's appends when steps are joined in
-    // one launch; nothing reads or appends to it while this kernel runs
-    if (b0 && lane == 0) *pair_counter(dsc, par ^ 1) = 0;
+    // the next step's append counter when the closing and opening kernels of
+    // two steps are joined; nothing reads or appends to it while this kernel runs
+    if (clr >= 0 && b0 && lane == 0) *pair_counter(dsc, clr) = 0;
     const int np = min(n_pairs, cap_pairs);
     if (b0 && lane == 0) {
       dsc->n_pairs_last = n_pairs;
@@ -1505,7 +1562,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
     // a system never has more subsystems than flagged pairs: blocks past the
     // pair count have nothing to integrate (the last block may still prepare
     // the next step boundary's massive bodies)
-    if ((int)blockIdx.x >= np && blockIdx.x != gridDim.x - 1) return;
+    if (bx >= np && (kJoint || bx != nbx - 1)) return;
     bigs_kept = np > 0;
     if (np > 0) {
       fast = np <= 256 && nb <= 64 && n < (1 << 26);
@@ -1562,7 +1619,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
             }
             const int e0 = F.gs[g], k = F.gs[g + 1] - e0;
             const auto R = subs + g;
-            R->pad = 0;
+            R->jm = 0;
             if (k + 1 > kBsMaxMembers || k > kBsMaxPairs) {
               atomicOr(&dsc->err, MXE_SUBSYS);
               R->m = 0;
@@ -1590,17 +1647,18 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
                        *reinterpret_cast<ShortPlanLds*>(&F));
           else
             plan_general(nb, gpairs, np, D.keys, D.keys + cap_pairs, D.plan_idx,
-                         D.plan_idx + cap_pairs, D.uf, D.subs, cap_subs, dsc, 0, s_scan, &s_nbig);
+                         D.plan_idx + cap_pairs, D.uf, D.subs, cap_subs, dsc, 0, s_scan, &s_nbig,
+                         64, !kJoint);
           __syncthreads();
           if (lane == 0) {
             s_nsub = dsc->n_sub;
-            __hip_atomic_store(&dsc->plan_ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&dsc->plan_ready[par], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
           }
         } else if (lane == 0) {
           // relaxed polls (an acquiring load would invalidate this CU's caches on
           // every poll), then one acquire fence once the flag is seen
           int it = 0;
-          while (__hip_atomic_load(&dsc->plan_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+          while (__hip_atomic_load(&dsc->plan_ready[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
             __builtin_amdgcn_s_sleep(8);
             if (++it >= kPlanWaitMax) break;
           }
@@ -1621,8 +1679,9 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
   // the massive bodies as they are, prepares the massive bodies of the joined
   // step boundary that follows (the same arithmetic as the joined step kernel,
   // which then copies them instead of computing them in every block).
-  if (plan && blockIdx.x == gridDim.x - 1) {
-    if (!bigs_kept && nsub < (int)gridDim.x && nb <= kSmallBig) {
+  if constexpr (!kJoint) {
+  if (plan && bx == nbx - 1) {
+    if (!bigs_kept && nsub < nbx && nb <= kSmallBig) {
       __shared__ double b_sh[8];
       __shared__ KickSource b_src[kSmallBig];
       __shared__ double b_bst[12][kSmallBig];
@@ -1658,7 +1717,18 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
       dsc->bn_valid[par] = 0;
     }
   }
-  for (int b = blockIdx.x; b < nsub; b += gridDim.x) {
+  }
+  if constexpr (kJoint) {
+    if (jfast) {
+      // the prepared boundary: the massless members are closed and opened with it
+      const BigNext* N = D.bignext + par;
+      for (int i = lane; i < 8 * nb; i += 64)
+        reinterpret_cast<double*>(jsrc)[i] = reinterpret_cast<const double*>(N->src)[i];
+      for (int i = lane; i < 12 * nb; i += 64) jbst[i / nb][i % nb] = N->bst[i / nb][i % nb];
+      for (int i = lane; i < nb; i += 64) jbrc[i] = N->brc[i];
+    }
+  }
+  for (int b = bx; b < nsub; b += nbx) {
     __syncthreads();
     if (fast) {
       // subsystem b from the sorted keys in LDS
@@ -1668,7 +1738,7 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
         S.m = fits ? k + 1 : 0;
         S.keep_from = fits ? k : 0;
         S.np = fits ? k : 0;
-        S.pad = 0;
+        S.jm = 0;
         if (fits) S.mem[k] = (int32_t)(F.kb[e0] >> 6);
       }
       if (fits && lane < k) {
@@ -1684,12 +1754,23 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
     __syncthreads();
     const int m = S.m, np = S.np;
     const int nn = 3 * m;
-    if (m == 0) continue;  // a subsystem dropped for capacity (error already latched)
+    if (m == 0) {  // a subsystem dropped for capacity (error already latched)
+      if (kJoint && jfast)
+        joint_member(D, fast ? (int)(F.kb[F.gs[b]] >> 6) : S.jm, nullptr, nullptr, par, nx, jsrc,
+                     jbst, jbrc);
+      continue;
+    }
     for (int e = lane; e < nn; e += 64) {
       int k = e / 3, c = e - 3 * (e / 3);
       int body = S.mem[k];
-      xs[e] = x0s[(size_t)c * n + body];
-      vs[e] = u0s[(size_t)c * n + body];
+      if (kJoint && body < nb) {
+        const auto bigpre = gbl(D.bigpre) + (size_t)par * 6 * nb;
+        xs[e] = bigpre[c * nb + body];
+        vs[e] = bigpre[(3 + c) * nb + body];
+      } else {
+        xs[e] = x0s[(size_t)c * n + body];
+        vs[e] = u0s[(size_t)c * n + body];
+      }
     }
     for (int k = lane; k < m; k += 64) {
       int body = S.mem[k];
@@ -1808,6 +1889,13 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
     if (D.bs_sched && lane == 0) D.bs_nsched[b] = failed ? 0 : nsched;
     if (failed) {
       if (lane == 0) atomicOr(&dsc->err, MXE_BS);
+      if (kJoint && jfast) joint_member(D, S.mem[m - 1], nullptr, nullptr, par, nx, jsrc, jbst,
+                                        jbrc);
+      continue;
+    }
+    if (kJoint && jfast) {  // the member's closing and opening replace the write-back
+      joint_member(D, S.mem[m - 1], xs + 3 * (m - 1), vs + 3 * (m - 1), par, nx, jsrc, jbst,
+                   jbrc);
       continue;
     }
     for (int e = lane; e < nn; e += 64) {
@@ -1821,6 +1909,173 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
         bigmid[(size_t)(3 + c) * nb + body] = vs[e];
       }
     }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int plan, int par,
+                                           int lst, int clr) {
+  bs_body<false>(desc[blockIdx.y], blockIdx.x, gridDim.x, plan, par, 0, lst, clr, false, nullptr,
+                 nullptr, nullptr);
+}
+
+// One launch per step of a joint sequence (a single system with n_big <= 64 and
+// no core growth): blocks 0 .. nbs - 1 run the encounter integrator of step q
+// (phase ph) on their first wave, the following blocks (one 256-body tile each)
+// close step q and open step q + 1 (phase nx) for their bodies with exactly the
+// joined step kernel's operations.  The two parts depend on each other only
+// through the bodies the integrator moves, and the launch that opened step q
+// prepared what the closing needs when no flagged pair of step q joins two
+// massive bodies (prepare_boundary: the massive bodies are then left as they
+// are; jfast, read by every block from the same final value): the tile blocks
+// then skip the flagged bodies, whose closing and opening the integrator's wave
+// does after their subsystem, and nothing waits.
+// Otherwise the tile blocks wait for every integrator block (a count released
+// at agent scope; the integrator's blocks have the lower indices, so they are
+// dispatched first and the wait ends) and then close every body as the joined
+// kernel does, from the massive bodies the integrator left.  What step q + 1
+// appends goes to the copies of phase nx, which nothing in this launch reads, the
+// massive members start from bigpre (the tile of the massive bodies rewrites
+// x0, u0), and the tile of the massive bodies clears the copies of step q - 1 and
+// prepares the next boundary.
+__global__ __launch_bounds__(256) void k_step_joint(const SysDesc* __restrict__ desc,
+                                                    const Tile* __restrict__ tiles, int nbs,
+                                                    int ph) {
+  using namespace mxs;
+  constexpr int BLK = 256;
+  const SysDesc& D = desc[0];
+  __shared__ double sh[8];
+  __shared__ KickSource src[kSmallBig];
+  __shared__ double bst[12][kSmallBig];
+  __shared__ double brc[kSmallBig];
+  __shared__ uint32_t fl[BLK / 32];  // the tile's bodies the integrator closes
+  const int nx = ph == 2 ? 0 : ph + 1;
+  const int tid = threadIdx.x;
+  const int n = D.n, nb = D.nb;
+  const double h = D.h, hh = 0.5 * D.h, mu0 = D.mu0;
+  DevScalars* __restrict__ dsc = D.dsc;
+  const int npq = min(*pair_counter(dsc, ph), D.cap_pairs);
+  const bool jfast = dsc->bn_valid[ph] != 0;
+  if ((int)blockIdx.x < nbs) {
+    if (tid >= 64) return;  // one wave per integrator block
+    bs_body<true>(D, blockIdx.x, nbs, 1, ph, nx, ph, -1, jfast, src, bst, brc);
+    if (!jfast) {
+      __syncthreads();  // the wave's stores precede the release
+      if (tid == 0)
+        __hip_atomic_fetch_add(&dsc->bs_done[ph], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  const Tile tl = tiles[blockIdx.x - nbs];
+  const int t = tl.first + tid;
+  const bool owner = tl.first == 0;  // block-uniform: the tile of the massive bodies
+  if (!jfast) {
+    if (tid == 0) {
+      int it = 0;
+      while (__hip_atomic_load(&dsc->bs_done[ph], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+             nbs) {
+        __builtin_amdgcn_s_sleep(8);
+        if (++it >= kPlanWaitMax) break;
+      }
+      if (it >= kPlanWaitMax) atomicOr(&dsc->err, MXE_PLANWAIT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+  }
+  double bpos[3], bvel[3], bm = 0.0, brc_t = 0.0;
+  if (tid < nb) {
+    bm = gbl(D.mu)[tid];
+    brc_t = gbl(D.rcrit)[tid];
+    if (!jfast) {
+      const auto bigmid = gbl(D.bigmid) + (size_t)ph * 6 * nb;
+      for (int c = 0; c < 3; ++c) {
+        bpos[c] = bigmid[c * nb + tid];
+        bvel[c] = bigmid[(3 + c) * nb + tid];
+      }
+    }
+  }
+  double p[3], v[3], a[3], q[3], w[3], rp = 0.0, rhop = 0.0;
+  if (t < n && t >= nb) {
+    for (int c = 0; c < 3; ++c) {
+      p[c] = gbl(D.x)[c * n + t];
+      v[c] = gbl(D.u)[c * n + t];
+    }
+    if (D.gas_on) {
+      rp = gbl(D.r_p)[t - nb];
+      rhop = gbl(D.rho_p)[t - nb];
+    }
+  }
+  double P[3], J[3], vpre[3], Ppre[3], Ppost[3];
+  if (jfast) {
+    const BigNext* N = D.bignext + ph;
+    if (tid < BLK / 32) fl[tid] = 0u;
+    for (int i = tid; i < 8 * nb; i += BLK)
+      reinterpret_cast<double*>(src)[i] = reinterpret_cast<const double*>(N->src)[i];
+    for (int i = tid; i < 12 * nb; i += BLK) bst[i / nb][i % nb] = N->bst[i / nb][i % nb];
+    for (int i = tid; i < nb; i += BLK) brc[i] = N->brc[i];
+    for (int c = 0; c < 3; ++c) {
+      P[c] = N->P[c];
+      J[c] = N->J[c];
+      vpre[c] = N->vpre[c];
+      Ppre[c] = N->Ppre[c];
+      Ppost[c] = N->Ppost[c];
+    }
+    __syncthreads();
+    const auto list = gbl(D.pairs) + (size_t)ph * 2 * D.cap_pairs;
+    for (int e = tid; e < npq; e += BLK) {
+      const int j = list[2 * e + 1] - tl.first;
+      if (j >= 0 && j < BLK) atomicOr(&fl[j >> 5], 1u << (j & 31));
+    }
+    __syncthreads();
+  } else {
+    big_boundary(D, owner, sh, src, bst, brc, bpos, bvel, bm, brc_t, P, J, vpre, Ppre, Ppost);
+  }
+  if (owner && tid == 0) {
+    dsc->P[0] = P[0];
+    dsc->P[1] = P[1];
+    dsc->P[2] = P[2];
+    dsc->step += 1;
+    const int r = nx == 2 ? 0 : nx + 1;  // step q - 1: nothing in this launch reads its copies
+    dsc->n_pairs[r] = 0;
+    dsc->plan_ready[r] = 0;
+    dsc->bs_done[r] = 0;
+  }
+  const bool skip = jfast && ((fl[tid >> 5] >> (tid & 31)) & 1u);
+  const bool mine = t < n && !skip;
+  // step q closed and step q + 1 opened for the body
+  if (mine && t >= nb) {
+    close_body(t, nb, src, 0.0, J, vpre, hh, D.dc, D.gas_on, rp, rhop, true, p, v, a);
+    if (!isfinite(v[0] + v[1] + v[2] + p[0] + p[1] + p[2])) atomicOr(&dsc->err, MXE_NONFINITE);
+    if (!advance_body(t, nb, mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v, a, q, w))
+      atomicOr(&dsc->err, MXE_NOCONV);
+  }
+  __syncthreads();  // the massive bodies of step q + 1 are in LDS
+  bool hit = false;
+  if (mine) {
+    if (t < nb) {
+      for (int c = 0; c < 3; ++c) {
+        p[c] = bst[c][t];
+        v[c] = bst[3 + c][t];
+        q[c] = bst[6 + c][t];
+        w[c] = bst[9 + c][t];
+      }
+      const auto bigmid = gbl(D.bigmid) + (size_t)nx * 6 * nb;
+      const auto bigpre = gbl(D.bigpre) + (size_t)nx * 6 * nb;
+      for (int c = 0; c < 3; ++c) {
+        bigmid[c * nb + t] = q[c];
+        bigmid[(3 + c) * nb + t] = w[c];
+        bigpre[c * nb + t] = p[c];
+        bigpre[(3 + c) * nb + t] = v[c];
+      }
+    }
+    for (int c = 0; c < 3; ++c) {
+      gbl(D.x)[c * n + t] = q[c];
+      gbl(D.u)[c * n + t] = w[c];
+    }
+    hit = flag_body(D, nx, nx, t, n, nb, h, bst, brc, p, v, q, w);
+  }
+  if (owner) {
+    const bool any_bb = __syncthreads_or(t < nb && hit);
+    prepare_boundary(D, nx, any_bb, sh, src, bst, brc, q, w, bm, brc_t);
   }
 }
 
@@ -1848,20 +2103,26 @@ hipError_t launch_flag(mx_system* s) {
     if (e != hipSuccess) return e;
     return mxlaunch(s, k_flag_cull, dim3(nC * (nC + 1) / 2 * (64 / kCullPart)), dim3(64), s->nb,
                     s->p.dt, s->flag_perm, s->flag_bounds, s->x0, s->u0, s->x, s->u, s->fpack,
-                    s->pairs, s->cap_pairs, &s->dsc->n_pairs, &s->dsc->err);
+                    s->pairs, s->cap_pairs, &s->dsc->n_pairs[0], &s->dsc->err);
   }
   int tiles = (s->n + kBlock - 1) / kBlock;
   int split = flag_split(s->n, s->nb);
   if (s->nb == 0) return hipSuccess;
   return mxlaunch(s, k_flag, dim3(tiles * split), dim3(kBlock), s->n, s->nb, split, s->p.dt,
-                  s->x0, s->u0, s->x, s->u, s->fpack, s->pairs, s->cap_pairs, &s->dsc->n_pairs,
+                  s->x0, s->u0, s->x, s->u, s->fpack, s->pairs, s->cap_pairs, &s->dsc->n_pairs[0],
                   &s->dsc->err);
 }
 
 hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys,
-                         int bps, int plan, int par) {
+                         int bps, int plan, int par, int lst, int clr) {
   if (n_sys <= 0 || bps <= 0) return hipSuccess;
-  return mxlaunch_on(st, tm, k_bs, dim3(bps, n_sys), dim3(64), desc, plan, par);
+  return mxlaunch_on(st, tm, k_bs, dim3(bps, n_sys), dim3(64), desc, plan, par, lst, clr);
+}
+
+hipError_t launch_step_joint(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
+                             const Tile* tiles, int n_tiles, int nbs, int ph) {
+  if (n_tiles <= 0 || nbs <= 0 || ph < 0 || ph > 2) return hipErrorInvalidValue;
+  return mxlaunch_on(st, tm, k_step_joint, dim3(nbs + n_tiles), dim3(256), desc, tiles, nbs, ph);
 }
 
 // flag + sort for the stateless entry; fpack built from the given states
@@ -1895,7 +2156,7 @@ hipError_t flag_pairs_enqueue(int n, int nb, const double* rcrit, const double* 
   int tiles = (n + kBlock - 1) / kBlock;
   int split = flag_split(n, nb);
   hipLaunchKernelGGL(k_flag, dim3(tiles * split), dim3(kBlock), 0, st, n, nb, split, h, x0, u0, x1,
-                     u1, fp, pairs, cap, &dsc->n_pairs, &dsc->err);
+                     u1, fp, pairs, cap, &dsc->n_pairs[0], &dsc->err);
   hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, st, nb, pairs, cap,
                      (int64_t*)pairs_tmp, nullptr, nullptr, nullptr, 0, dsc, 1);
   return hipGetLastError();

@@ -49,90 +49,21 @@ __device__ __forceinline__ void big_phase_a(const SysDesc& D, bool first, double
   if (tid < D.nb) big_advance_a(D, first, tid, bst, brc, p, v, a, rc, Ppre, Ppost);
 }
 
-// Encounter test of body t (pre-drift p, v; post-drift q, w) against every
-// massive body i < t held in LDS (same bound and exact Hermite test as the
-// general flag kernel): the bound marks candidates in a bit mask (nb <= 64), then
-// the lanes of the wave take their candidates one at a time together, so a wave
-// with candidates against different massive bodies runs the Hermite test once
-// per round rather than once per body.  Flagged pairs are appended to the list
-// (append counter of step parity par);
-// the pre-drift state is stored where the encounter integrator starts from it.
-__device__ __forceinline__ void flag_body(const SysDesc& D, int par, int t, int n, int nb,
-                                          double h, const double (*bst)[kSmallBig],
-                                          const double* brc, const double (&p)[3],
-                                          const double (&v)[3], const double (&q)[3],
-                                          const double (&w)[3]) {
-  const double rct = t < nb ? brc[t] : 0.0;
-  const int imax = t < nb ? t : nb;
-  const double k427 = (4.0 / 27.0) * fabs(h);
-  uint64_t cmask = 0;
-#pragma unroll 4
-  for (int i = 0; i < imax; ++i) {
-    double r0[3], w0[3], w1[3], dd[3];
-    for (int c = 0; c < 3; ++c) {
-      r0[c] = p[c] - bst[c][i];
-      w0[c] = v[c] - bst[3 + c][i];
-      w1[c] = w[c] - bst[9 + c][i];
-      dd[c] = (q[c] - p[c]) - (bst[6 + c][i] - bst[c][i]);
-    }
-    double m0 = fma(r0[2], r0[2], fma(r0[1], r0[1], r0[0] * r0[0]));
-    double nd = fmax(fmax(fabs(dd[0]), fabs(dd[1])), fabs(dd[2]));
-    double nw = fmax(fmax(fabs(w0[0]), fabs(w0[1])), fabs(w0[2])) +
-                fmax(fmax(fabs(w1[0]), fabs(w1[1])), fabs(w1[2]));
-    double rc = fmax(brc[i], rct);
-    double bound = rc + 1.7320508075688773 * fma(k427, nw, nd) * (1.0 + 1e-12);
-    if (__builtin_expect(m0 <= bound * bound * (1.0 + 1e-12), 0)) cmask |= 1ull << i;
-  }
-  uint64_t hmask = 0;
-  while (cmask != 0) {
-    const int i = __builtin_ctzll(cmask);
-    cmask &= cmask - 1;
-    double r0[3], w0[3], w1[3], r1[3];
-    for (int c = 0; c < 3; ++c) {
-      r0[c] = p[c] - bst[c][i];
-      w0[c] = v[c] - bst[3 + c][i];
-      w1[c] = w[c] - bst[9 + c][i];
-      r1[c] = q[c] - bst[6 + c][i];
-    }
-    const double rc = fmax(brc[i], rct);
-    double dmin = mxd::hermite_dmin2(r0[0], r0[1], r0[2], w0[0], w0[1], w0[2], r1[0], r1[1],
-                                     r1[2], w1[0], w1[1], w1[2], h);
-    if (dmin <= rc * rc) hmask |= 1ull << i;
-  }
-  // the body's pairs are appended together, in increasing i: the list holds each
-  // body's partners as one ordered run
-  const bool hit = hmask != 0;
-  if (hit) {
-    int idx = atomicAdd(pair_counter(D.dsc, par), __popcll(hmask));
-    for (; hmask != 0; hmask &= hmask - 1, ++idx) {
-      if (idx < D.cap_pairs) {
-        gbl(D.pairs)[2 * idx] = __builtin_ctzll(hmask);
-        gbl(D.pairs)[2 * idx + 1] = t;
-      } else {
-        atomicOr(&D.dsc->err, MXE_PAIRS);
-      }
-    }
-  }
-  // pre-drift state: the encounter integrator starts its subsystems from it
-  if (hit || t < nb || D.keep_x0) {
-    for (int c = 0; c < 3; ++c) {
-      gbl(D.x0)[c * n + t] = p[c];
-      gbl(D.u0)[c * n + t] = v[c];
-    }
-  }
-}
-
 // First half of the fused step over a tile table: per tile, drag + half kick +
 // jump + Kepler drift of its bodies and the encounter test against the massive
 // bodies.  A block takes `tpb` consecutive tiles and redoes the massive-body
 // phase only when the system changes.
-template <int BLK>
+// kJoint: the first launch of a joint sequence (single system): the massive
+// bodies' pre-drift state also goes to bigpre[par], and the block of the massive
+// bodies prepares the boundary that closes this step (prepare_boundary).
+template <int BLK, bool kJoint>
 __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc,
                                                 const Tile* __restrict__ tiles, int n_tiles,
                                                 int tpb, int par) {
   __shared__ double sh[8];
   __shared__ double bst[12][kSmallBig];  // x0 (3) u0 (3) x1 (3) u1 (3) of the big bodies
   __shared__ double brc[kSmallBig];
+  __shared__ KickSource jsrc[kJoint ? kSmallBig : 1];
   const int tid = threadIdx.x;
   const int t_lo = blockIdx.x * tpb;
   const int t_hi = min(n_tiles, t_lo + tpb);
@@ -178,28 +109,41 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
       __syncthreads();
       cur = tl.sys;
     }
-    if (t >= n) continue;
-    if (t < nb) {
-      for (int c = 0; c < 3; ++c) {
-        p[c] = bst[c][t];
-        v[c] = bst[3 + c][t];
-        q[c] = bst[6 + c][t];
-        w[c] = bst[9 + c][t];
+    bool hit = false;
+    if (t < n) {
+      if (t < nb) {
+        for (int c = 0; c < 3; ++c) {
+          p[c] = bst[c][t];
+          v[c] = bst[3 + c][t];
+          q[c] = bst[6 + c][t];
+          w[c] = bst[9 + c][t];
+        }
+        const auto bigmid = gbl(D.bigmid) + (size_t)par * 6 * nb;
+        for (int c = 0; c < 3; ++c) {
+          bigmid[c * nb + t] = q[c];
+          bigmid[(3 + c) * nb + t] = w[c];
+        }
+        if (kJoint) {
+          const auto bigpre = gbl(D.bigpre) + (size_t)par * 6 * nb;
+          for (int c = 0; c < 3; ++c) {
+            bigpre[c * nb + t] = p[c];
+            bigpre[(3 + c) * nb + t] = v[c];
+          }
+        }
+      } else {
+        if (!advance_body(t, nb, D.mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v, a, q, w))
+          atomicOr(&D.dsc->err, MXE_NOCONV);
       }
-      const auto bigmid = gbl(D.bigmid) + (size_t)par * 6 * nb;
       for (int c = 0; c < 3; ++c) {
-        bigmid[c * nb + t] = q[c];
-        bigmid[(3 + c) * nb + t] = w[c];
+        gbl(D.x)[c * n + t] = q[c];
+        gbl(D.u)[c * n + t] = w[c];
       }
-    } else {
-      if (!advance_body(t, nb, D.mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v, a, q, w))
-        atomicOr(&D.dsc->err, MXE_NOCONV);
+      hit = flag_body(D, par, kJoint ? par : 0, t, n, nb, h, bst, brc, p, v, q, w);
     }
-    for (int c = 0; c < 3; ++c) {
-      gbl(D.x)[c * n + t] = q[c];
-      gbl(D.u)[c * n + t] = w[c];
+    if (kJoint && tl.first == 0) {  // block-uniform: the block of the massive bodies
+      const bool any_bb = __syncthreads_or(t < nb && hit);
+      prepare_boundary(D, par, any_bb, sh, jsrc, bst, brc, q, w, bm, brc_t);
     }
-    flag_body(D, par, t, n, nb, h, bst, brc, p, v, q, w);
   }
 }
 
@@ -292,9 +236,11 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
       D.dsc->P[2] = P[2];
       if (kick) {
         D.dsc->step += 1;
-        D.dsc->n_pairs = 0;  // the encounter list of this step has been planned
-        D.dsc->n_pairs_alt = 0;
-        D.dsc->plan_ready = 0;
+        for (int r = 0; r < 3; ++r) {  // the encounter lists of the call have been planned
+          D.dsc->n_pairs[r] = 0;
+          D.dsc->plan_ready[r] = 0;
+          D.dsc->bs_done[r] = 0;
+        }
       }
     }
     if (t >= n) continue;
@@ -416,7 +362,7 @@ __global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ des
         D.dsc->P[1] = P[1];
         D.dsc->P[2] = P[2];
         D.dsc->step += 1;
-        D.dsc->plan_ready = 0;
+        D.dsc->plan_ready[par] = 0;
       }
       cur = tl.sys;
     }
@@ -448,7 +394,7 @@ __global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ des
         gbl(D.x)[c * n + t] = q[c];
         gbl(D.u)[c * n + t] = w[c];
       }
-      flag_body(D, par ^ 1, t, n, nb, h, bst, brc, p, v, q, w);
+      flag_body(D, par ^ 1, 0, t, n, nb, h, bst, brc, p, v, q, w);
     }
   }
 }
@@ -458,14 +404,19 @@ __global__ __launch_bounds__(BLK) void k_step_ba(const SysDesc* __restrict__ des
 namespace mxk {
 
 hipError_t launch_step_a_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
-                               const Tile* tiles, int n_tiles, int blk, int tpb, int par) {
+                               const Tile* tiles, int n_tiles, int blk, int tpb, int par,
+                               int joint) {
   if (n_tiles <= 0) return hipSuccess;
   const dim3 grid((n_tiles + tpb - 1) / tpb);
+  if (joint)
+    return blk == 256 ? mxlaunch_on(st, tm, k_step_a<256, true>, grid, dim3(256), desc, tiles,
+                                    n_tiles, tpb, par)
+                      : hipErrorInvalidValue;
   switch (blk) {
-    case 64: return mxlaunch_on(st, tm, k_step_a<64>, grid, dim3(64), desc, tiles, n_tiles, tpb, par);
-    case 128: return mxlaunch_on(st, tm, k_step_a<128>, grid, dim3(128), desc, tiles, n_tiles, tpb, par);
-    case 256: return mxlaunch_on(st, tm, k_step_a<256>, grid, dim3(256), desc, tiles, n_tiles, tpb, par);
-    case 512: return mxlaunch_on(st, tm, k_step_a<512>, grid, dim3(512), desc, tiles, n_tiles, tpb, par);
+    case 64: return mxlaunch_on(st, tm, k_step_a<64, false>, grid, dim3(64), desc, tiles, n_tiles, tpb, par);
+    case 128: return mxlaunch_on(st, tm, k_step_a<128, false>, grid, dim3(128), desc, tiles, n_tiles, tpb, par);
+    case 256: return mxlaunch_on(st, tm, k_step_a<256, false>, grid, dim3(256), desc, tiles, n_tiles, tpb, par);
+    case 512: return mxlaunch_on(st, tm, k_step_a<512, false>, grid, dim3(512), desc, tiles, n_tiles, tpb, par);
     default: return hipErrorInvalidValue;
   }
 }

@@ -362,9 +362,9 @@ __global__ __launch_bounds__(kBlock) void k_force_kick(
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (kick) {
       dsc->step += 1;
-      dsc->n_pairs = 0;  // the encounter list of this step has been planned
+      dsc->n_pairs[0] = 0;  // the encounter list of this step has been planned
     }
-    dsc->plan_ready = 0;  // the in-kernel plan of the next step starts unpublished
+    dsc->plan_ready[0] = 0;  // the in-kernel plan of the next step starts unpublished
   }
   const double xt = x[tt], yt = x[n + tt], zt = x[2 * n + tt];
   double rct = 0.0, rc2t = 0.0;
@@ -571,9 +571,9 @@ __global__ __launch_bounds__(64 * kFinSlices) void k_force_finish_sym(
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (kick) {
       dsc->step += 1;
-      dsc->n_pairs = 0;  // the encounter list of this step has been planned
+      dsc->n_pairs[0] = 0;  // the encounter list of this step has been planned
     }
-    dsc->plan_ready = 0;  // the in-kernel plan of the next step starts unpublished
+    dsc->plan_ready[0] = 0;  // the in-kernel plan of the next step starts unpublished
   }
   double P[3] = {dsc->P[0], dsc->P[1], dsc->P[2]};
   if ((int)blockIdx.x < nT) {

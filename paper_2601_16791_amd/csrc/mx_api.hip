@@ -67,6 +67,7 @@ hipError_t copy_out(void* dst, const void* src, size_t bytes, int is_dev, hipStr
 
 constexpr int kTileBlk = 256;   // bodies per tile of a single system's fused kernels
 constexpr int kBsBlocks = 512;  // encounter-integrator blocks of a single system
+constexpr int kJointBs = 128;   // integrator blocks of a single system's joint launch
 
 SysDesc make_desc(const mx_system* s) {
   SysDesc d;
@@ -82,6 +83,7 @@ SysDesc make_desc(const mx_system* s) {
   d.rho_p = s->rho_p;
   d.bigsnap = s->bigsnap;
   d.bigmid = s->bigmid;
+  d.bigpre = s->bigpre;
   d.bignext = s->bignext;
   d.pairs = s->pairs;
   d.keys = reinterpret_cast<int64_t*>(s->pairs_tmp);
@@ -117,7 +119,7 @@ void free_system(mx_system* s) {
   for (int32_t k = 0; k < s->tev_pool_n; ++k) (void)hipEventDestroy(s->tev_pool[k]);
   delete[] s->tev_pool;
   void* ptrs[] = {s->x, s->u, s->ag, s->x0, s->u0, s->mu, s->rcrit, s->mu_init, s->rcrit_init,
-                  s->growth, s->r_p, s->rho_p, s->bigsnap, s->bigmid, s->bignext, s->kpack,
+                  s->growth, s->r_p, s->rho_p, s->bigsnap, s->bigmid, s->bigpre, s->bignext, s->kpack,
                   s->fpack, s->flag_perm, s->flag_bounds, s->part,
                   s->sympart,
                   s->pairs, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red,
@@ -145,7 +147,8 @@ hipError_t launch_group(mx_system* s, int k, int par = 0) {
     case MX_K_PLAN:  // the encounter integrator plans its subsystems itself
       return hipSuccess;
     case MX_K_BS:
-      return s->nb > 0 ? mxk::launch_bs_sys(s->stream, &s->tev, s->desc, 1, kBsBlocks, 1, par)
+      return s->nb > 0 ? mxk::launch_bs_sys(s->stream, &s->tev, s->desc, 1, kBsBlocks, 1, par, 0,
+                                            par ^ 1)
                        : hipSuccess;
     case MX_K_JUMP_PACK: return small ? hipSuccess : mxk::launch_jump_pack(s);
     default:
@@ -173,9 +176,48 @@ bool joinable(const mx_system* s, int32_t n) {
   return n >= 2 && s->nb <= kSmallBig && !s->has_growth && !s->has_phys;
 }
 
+// whether a call of n steps runs as a joint sequence: the first step opened by
+// k_step_a, then one launch per step that integrates its encounters beside the
+// closing of that step and the opening of the next (k_step_joint), the last
+// step's encounters and closing as usual
+bool joint_ok(const mx_system* s, int32_t n) {
+  return joinable(s, n) && s->nb > 0 && s->n < (1 << 26) && !s->no_joint;
+}
+
+// n >= 2 steps as a joint sequence; visit/after as for enqueue_steps, the joint
+// launch visited as MX_K_STEP_JOINT of the step whose encounters it integrates
+template <class Visit, class After>
+hipError_t enqueue_joint(mx_system* s, int32_t n, Visit visit, After after) {
+  hipError_t e;
+  visit(MX_K_KICK_JUMP_DRIFT, 0);
+  e = mxk::launch_step_a_tiles(s->stream, &s->tev, s->desc, s->tiles, s->n_tiles, kTileBlk, 1, 0,
+                               1);
+  after(MX_K_KICK_JUMP_DRIFT, 0);
+  if (e != hipSuccess) return e;
+  for (int32_t q = 0; q < n - 1; ++q) {
+    visit(MX_K_STEP_JOINT, q);
+    e = mxk::launch_step_joint(s->stream, &s->tev, s->desc, s->tiles, s->n_tiles, kJointBs,
+                               q % 3);
+    after(MX_K_STEP_JOINT, q);
+    if (e != hipSuccess) return e;
+  }
+  const int pf = (n - 1) % 3;  // phase of the last step
+  visit(MX_K_BS, n - 1);
+  e = mxk::launch_bs_sys(s->stream, &s->tev, s->desc, 1, kBsBlocks, 1, pf, pf, -1);
+  after(MX_K_BS, n - 1);
+  if (e != hipSuccess) return e;
+  visit(MX_K_FORCE_KICK, n - 1);
+  e = mxk::launch_step_b_tiles(s->stream, &s->tev, s->desc, s->tiles, s->n_tiles, kTileBlk, 1, 1,
+                               pf);
+  after(MX_K_FORCE_KICK, n - 1);
+  s->last_list = pf;
+  return e;
+}
+
 template <class Visit, class After>
 hipError_t enqueue_steps(mx_system* s, int32_t n, bool join, Visit visit, After after) {
   join = join && joinable(s, n);
+  s->last_list = 0;
   for (int32_t q = 0; q < n; ++q) {
     const int par = join ? (q & 1) : 0;  // step parity (buffers alternate between joined steps)
     for (int k = 0; k < MX_NUM_KERNELS; ++k) {
@@ -285,14 +327,15 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   ALLOC(s->x, n3) ALLOC(s->u, n3) ALLOC(s->ag, n3) ALLOC(s->x0, n3) ALLOC(s->u0, n3)
   ALLOC(s->mu, nb) ALLOC(s->rcrit, nb) ALLOC(s->mu_init, nb) ALLOC(s->rcrit_init, nb)
   ALLOC(s->growth, 3 * (size_t)nb) ALLOC(s->r_p, s->ns) ALLOC(s->rho_p, s->ns)
-  ALLOC(s->bigsnap, 9 * (size_t)nb) ALLOC(s->bigmid, 12 * (size_t)nb) ALLOC(s->bignext, 2)
+  ALLOC(s->bigsnap, 9 * (size_t)nb) ALLOC(s->bigmid, 18 * (size_t)nb)
+  ALLOC(s->bigpre, 18 * (size_t)nb) ALLOC(s->bignext, 3)
   ALLOC(s->kpack, mxk::kick_source_count(nb)) ALLOC(s->fpack, nb)
   ALLOC(s->part, s->use_sym && s->ns > 0 ? (size_t)s->split * n3 : 1)
   {
     const size_t nT = (size_t)(nb + 63) / 64;
     ALLOC(s->sympart, s->use_sym ? nT * nT * 3 * 64 : 1)
   }
-  ALLOC(s->pairs, 2 * (size_t)s->cap_pairs) ALLOC(s->pairs_tmp, 4 * (size_t)s->cap_pairs)
+  ALLOC(s->pairs, 6 * (size_t)s->cap_pairs) ALLOC(s->pairs_tmp, 4 * (size_t)s->cap_pairs)
   ALLOC(s->plan_idx, 2 * (size_t)s->cap_pairs)
   ALLOC(s->subs, s->cap_subs) ALLOC(s->uf, 2 * (size_t)nb) ALLOC(s->dsc, 1) ALLOC(s->red, s->red_blocks)
   s->n_tiles = (s->n + kTileBlk - 1) / kTileBlk;
@@ -401,6 +444,8 @@ mx_status mx_step(mx_system* s, int32_t n_steps) {
   if (use_graph) {
     for (int32_t k = 0; k < n_steps; ++k)
       HIPCHK(hipGraphLaunch(s->graph, s->stream), "graph launch");
+  } else if (joint_ok(s, n_steps)) {
+    HIPCHK(enqueue_joint(s, n_steps, [](int, int) {}, [](int, int) {}), "step launch");
   } else {
     HIPCHK(enqueue_steps(s, n_steps, true, [](int, int) {}, [](int, int) {}), "step launch");
   }
@@ -445,7 +490,7 @@ mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms) {
 
 mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, int32_t stride,
                         float* kernel_ms, int32_t* n_launched) {
-  if (!s || n_steps < 0 || group < 0 || group > MX_K_STEP_JOINED || stride < 1 || !kernel_ms ||
+  if (!s || n_steps < 0 || group < 0 || group > MX_K_STEP_JOINT || stride < 1 || !kernel_ms ||
       !n_launched)
     return fail(MX_EINVAL, "bad argument");
   *n_launched = 0;
@@ -477,22 +522,26 @@ mx_status mx_step_timed(mx_system* s, int32_t n_steps, int32_t group, int32_t st
     if (group == MX_K_STEP_JOINED) return joins && k == MX_K_FORCE_KICK && q < n_steps - 1;
     return k == group;
   };
-  e = enqueue_steps(
-      s, n_steps, join,
-      [&](int k, int q) {
-        if (timed(k, q)) {
-          s->tev.armed = true;
-          s->tev.start = ev[2 * (q / stride)];
-          s->tev.stop = ev[2 * (q / stride) + 1];
-        }
-      },
-      [&](int k, int q) {
-        if (timed(k, q)) {
-          used[q] = s->tev.start == nullptr;  // the start event went to a kernel
-          s->tev.armed = false;
-          s->tev.start = s->tev.stop = nullptr;
-        }
-      });
+  auto visit = [&](int k, int q) {
+    if (timed(k, q)) {
+      s->tev.armed = true;
+      s->tev.start = ev[2 * (q / stride)];
+      s->tev.stop = ev[2 * (q / stride) + 1];
+    }
+  };
+  auto after = [&](int k, int q) {
+    if (timed(k, q)) {
+      used[q] = s->tev.start == nullptr;  // the start event went to a kernel
+      s->tev.armed = false;
+      s->tev.start = s->tev.stop = nullptr;
+    }
+  };
+  // the joint launch is timed in the joint sequence mx_step runs; every other
+  // group in the sequence of separate (or two-step joined) launches
+  if (group == MX_K_STEP_JOINT && joint_ok(s, n_steps))
+    e = enqueue_joint(s, n_steps, visit, after);
+  else
+    e = enqueue_steps(s, n_steps, join, visit, after);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   int32_t nl = 0;
   for (int32_t q = 0; q < n_steps; ++q) {
@@ -552,7 +601,8 @@ mx_status mx_encounters(mx_system* s, int32_t* pairs, int32_t cap, int32_t* n_ou
   const int m = all < cap ? all : cap;
   if (m > 0) {
     std::vector<int32_t> buf(2 * (size_t)all);
-    HIPCHK(hipMemcpy(buf.data(), s->pairs, sizeof(int32_t) * 2 * all, hipMemcpyDeviceToHost),
+    HIPCHK(hipMemcpy(buf.data(), s->pairs + (size_t)s->last_list * 2 * s->cap_pairs,
+                     sizeof(int32_t) * 2 * all, hipMemcpyDeviceToHost),
            "copy pairs");
     std::vector<int64_t> key(all);
     for (int q = 0; q < all; ++q)
@@ -1003,7 +1053,7 @@ hipError_t enqueue_batch_steps(mx_batch* b, int32_t n) {
       e = mxk::launch_step_a_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles, b->blk,
                                    b->tpb, 0);
     if (e == hipSuccess)
-      e = mxk::launch_bs_sys(b->stream, &b->tev, b->desc, b->n_sys, b->bps, 1, par);
+      e = mxk::launch_bs_sys(b->stream, &b->tev, b->desc, b->n_sys, b->bps, 1, par, 0, par ^ 1);
     if (e != hipSuccess) break;
     if (q < n - 1)
       e = mxk::launch_step_ba_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles, b->blk,
@@ -1487,6 +1537,7 @@ mx_status mx_adjoint_create(const mx_params* p, const double* x_h, const double*
   }
   mx_system* s = a->s;
   s->owned = true;
+  s->no_joint = true;
   const int n = s->n, nb = s->nb;
   const size_t n3 = 3 * (size_t)n;
   a->n_steps = n_steps;

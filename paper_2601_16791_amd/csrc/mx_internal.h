@@ -50,33 +50,39 @@ struct ChunkBound {
 };
 
 struct Subsystem {                  // one Bulirsch-Stoer subsystem
-  int32_t m, keep_from, np, pad;
+  int32_t m, keep_from, np;
+  int32_t jm;  // general plan: the massless body a subsystem was built for (else 0)
   int32_t mem[kBsMaxMembers];
   int32_t pl[kBsMaxPairs][2];
 };
 
 // Device scalars of a system (one allocation).
+// Per-step flags and counters come in three copies indexed by the step phase:
+// consecutive steps of a joined sequence use alternating (two-step joins) or
+// rotating (joint launches, which run the encounter integrator of step q beside
+// the opening of step q + 1) copies, so that no launch clears or appends to a
+// copy that another part of the same launch still reads.  Outside joined
+// launches the phase is 0.
 struct DevScalars {
   int64_t step;          // step counter (t = step * dt)
-  int32_t n_pairs;       // pairs flagged so far in the current step (append counter)
+  int32_t n_pairs[3];    // pairs flagged so far in the step of each phase (append counters)
   int32_t n_sub;         // subsystems of the current step
   int32_t err;           // latched failure bits
   int32_t n_pairs_last;  // flagged pairs of the last completed step
   double P[3];           // massive-body momentum sum mu*u after the last jump
   unsigned long long bs_flop;        // cumulative model FP64 ops of the encounter integrator
   unsigned long long pairs_flagged;  // cumulative flagged pairs
-  int32_t plan_ready;    // set when the in-kernel general plan of this step is written
-  int32_t n_pairs_alt;   // second append counter: steps joined in one launch alternate
-  int32_t bn_valid[2];   // BigNext[parity] holds this step boundary's massive bodies
+  int32_t plan_ready[3];  // set when the in-kernel general plan of the step is written
+  int32_t bn_valid[3];    // BigNext[phase] holds the step boundary's massive bodies
+  int32_t bs_done[3];     // joint launches: encounter-integrator blocks finished
+  int32_t pad_ph;
   double time;           // time at the start of the next step (time-dependent physics)
   int32_t switched;      // the step switch has happened
   int32_t pad_phys;
 };
 
-// Append counter of the flagged list for step parity w (0 outside joined launches).
-__host__ __device__ inline int32_t* pair_counter(DevScalars* d, int w) {
-  return w ? &d->n_pairs_alt : &d->n_pairs;
-}
+// Append counter of the flagged list for step phase w (0 outside joined launches).
+__host__ __device__ inline int32_t* pair_counter(DevScalars* d, int w) { return &d->n_pairs[w]; }
 
 namespace mxd {
 // Gas-disk constants of a parameter set in the units of the drag formula.
@@ -137,8 +143,9 @@ inline DragConst make_drag_const(const mx_params& p) {
 }  // namespace mxd
 
 // The massive bodies at a joined step boundary (closing step n, opening step
-// n + 1), precomputed by the encounter integrator of step n when it leaves them
-// unchanged; the joined step kernel then reads them instead of computing them.
+// n + 1), precomputed when the encounter integrator of step n leaves them
+// unchanged (by that integrator, or by the launch that opened step n); the
+// kernel that closes step n then reads them instead of computing them.
 struct BigNext {
   double P[3], J[3], vpre[3], Ppre[3], Ppost[3], pad;
   KickSource src[kSmallBig];
@@ -153,9 +160,10 @@ struct SysDesc {
   double *x, *u, *ag, *x0, *u0;
   const double *mu, *rcrit;         // [nb]
   const double *r_p, *rho_p;        // [n - nb]
-  double *bigsnap, *bigmid;         // [9][nb], [2][6][nb] (by step parity)
-  BigNext* bignext;                 // [2] (by step parity)
-  int32_t* pairs;                   // [cap_pairs][2]
+  double *bigsnap, *bigmid;         // [9][nb], [3][6][nb] (by step phase)
+  double* bigpre;                   // [3][6][nb]: pre-drift x, u of the massive bodies (by phase)
+  BigNext* bignext;                 // [3] (by step phase)
+  int32_t* pairs;                   // [lists][cap_pairs][2]: flagged list (joint launches: by phase)
   int64_t* keys;                    // planner scratch [2 * cap_pairs]
   int32_t* plan_idx;                // planner scratch [2 * cap_pairs]
   int32_t* uf;                      // [2 * nb] union-find scratch
@@ -232,10 +240,11 @@ struct mx_system {
   // snapshots of the massive bodies, so that a kernel whose every block reads
   // them never sees them half-updated by the block that owns them:
   //   bigsnap [9][nb]: x, u, a at the step start (written at the end of a step)
-  //   bigmid  [2][6][nb]: x, u after drift and encounter integration (fused path,
-  //           by step parity)
-  double *bigsnap, *bigmid;
-  BigNext* bignext;  // [2]: precomputed massive bodies of a joined step boundary
+  //   bigmid  [3][6][nb]: x, u after drift and encounter integration (fused path,
+  //           by step phase)
+  //   bigpre  [3][6][nb]: x, u before the drift (joint launches, by step phase)
+  double *bigsnap, *bigmid, *bigpre;
+  BigNext* bignext;  // [3]: precomputed massive bodies of a joined step boundary
   // massless bodies
   double *r_p, *rho_p;  // rho_p in Msun/AU^3
   // packed sources
@@ -250,7 +259,8 @@ struct mx_system {
   int split;
   int use_sym;
   // encounters
-  int32_t* pairs;      // [cap][2]
+  int32_t* pairs;      // [3][cap][2] (lists by step phase in joint launches)
+  int32_t last_list;   // phase of the list of the last completed step
   int32_t* pairs_tmp;  // [4*cap] int32 = [2*cap] int64 sort keys of the planner
   int32_t* plan_idx;   // [2*cap] index lists of the planner
   int32_t cap_pairs;
@@ -264,6 +274,7 @@ struct mx_system {
   // graph of one step
   hipGraphExec_t graph;
   bool graph_ok;
+  bool no_joint;  // steps of a call are never joint (the adjoint records per-step tapes)
   int launch_mode;  // MX_LAUNCH_EAGER or MX_LAUNCH_GRAPH
   LaunchTiming tev;
   hipEvent_t* tev_pool;  // events of mx_step_timed, kept between calls
@@ -316,8 +327,10 @@ hipError_t launch_check_removal(mx_system* s, double r_cen);
 hipError_t compact_bodies(mx_system* s, int32_t* n_new, int32_t* map_dev);
 // fused small-B kernels over a tile table (n_big <= kSmallBig in every system);
 // blk bodies per tile (64, 128, 256 or 512), tpb consecutive tiles per block
+// joint != 0: the first launch of a joint sequence (single system, blk 256)
 hipError_t launch_step_a_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
-                               const Tile* tiles, int n_tiles, int blk, int tpb, int par);
+                               const Tile* tiles, int n_tiles, int blk, int tpb, int par,
+                               int joint = 0);
 hipError_t launch_step_b_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
                                const Tile* tiles, int n_tiles, int blk, int tpb, int kick,
                                int par);
@@ -330,7 +343,11 @@ hipError_t launch_step_ba_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc*
 // planner (one block per system) and encounter integrator (bps blocks per system;
 // plan != 0: the integrator plans its subsystems itself, systems of n_big <= 64)
 hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys,
-                         int bps, int plan, int par);
+                         int bps, int plan, int par, int lst, int clr);
+// encounter integrator of step q (phase ph, nbs one-wave blocks) beside the
+// closing of step q and the opening of step q + 1 for a single system's tiles
+hipError_t launch_step_joint(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
+                             const Tile* tiles, int n_tiles, int nbs, int ph);
 
 // stateless single-kernel launchers
 hipError_t gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,

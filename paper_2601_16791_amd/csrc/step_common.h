@@ -194,4 +194,119 @@ __device__ __forceinline__ void big_boundary(const SysDesc& D, bool latch, doubl
   if (tid < nb) big_advance_a(D, latch, tid, bst, brc, bpos, bvel, bacc, brc_t, Ppre, Ppost);
 }
 
+// Encounter test of body t (pre-drift p, v; post-drift q, w) against every
+// massive body i < t held in LDS (same bound and exact Hermite test as the
+// general flag kernel): the bound marks candidates in a bit mask (nb <= 64), then
+// the lanes of the wave take their candidates one at a time together, so a wave
+// with candidates against different massive bodies runs the Hermite test once
+// per round rather than once per body.  Flagged pairs are appended to list lst
+// with the append counter of step phase par; the pre-drift state is stored
+// where the encounter integrator starts from it.  Returns whether the body
+// flagged a pair.
+__device__ __forceinline__ bool flag_body(const SysDesc& D, int par, int lst, int t, int n, int nb,
+                                          double h, const double (*bst)[kSmallBig],
+                                          const double* brc, const double (&p)[3],
+                                          const double (&v)[3], const double (&q)[3],
+                                          const double (&w)[3]) {
+  const double rct = t < nb ? brc[t] : 0.0;
+  const int imax = t < nb ? t : nb;
+  const double k427 = (4.0 / 27.0) * fabs(h);
+  uint64_t cmask = 0;
+#pragma unroll 4
+  for (int i = 0; i < imax; ++i) {
+    double r0[3], w0[3], w1[3], dd[3];
+    for (int c = 0; c < 3; ++c) {
+      r0[c] = p[c] - bst[c][i];
+      w0[c] = v[c] - bst[3 + c][i];
+      w1[c] = w[c] - bst[9 + c][i];
+      dd[c] = (q[c] - p[c]) - (bst[6 + c][i] - bst[c][i]);
+    }
+    double m0 = fma(r0[2], r0[2], fma(r0[1], r0[1], r0[0] * r0[0]));
+    double nd = fmax(fmax(fabs(dd[0]), fabs(dd[1])), fabs(dd[2]));
+    double nw = fmax(fmax(fabs(w0[0]), fabs(w0[1])), fabs(w0[2])) +
+                fmax(fmax(fabs(w1[0]), fabs(w1[1])), fabs(w1[2]));
+    double rc = fmax(brc[i], rct);
+    double bound = rc + 1.7320508075688773 * fma(k427, nw, nd) * (1.0 + 1e-12);
+    if (__builtin_expect(m0 <= bound * bound * (1.0 + 1e-12), 0)) cmask |= 1ull << i;
+  }
+  uint64_t hmask = 0;
+  while (cmask != 0) {
+    const int i = __builtin_ctzll(cmask);
+    cmask &= cmask - 1;
+    double r0[3], w0[3], w1[3], r1[3];
+    for (int c = 0; c < 3; ++c) {
+      r0[c] = p[c] - bst[c][i];
+      w0[c] = v[c] - bst[3 + c][i];
+      w1[c] = w[c] - bst[9 + c][i];
+      r1[c] = q[c] - bst[6 + c][i];
+    }
+    const double rc = fmax(brc[i], rct);
+    double dmin = mxd::hermite_dmin2(r0[0], r0[1], r0[2], w0[0], w0[1], w0[2], r1[0], r1[1],
+                                     r1[2], w1[0], w1[1], w1[2], h);
+    if (dmin <= rc * rc) hmask |= 1ull << i;
+  }
+  // the body's pairs are appended together, in increasing i: the list holds each
+  // body's partners as one ordered run
+  const bool hit = hmask != 0;
+  if (hit) {
+    const auto list = gbl(D.pairs) + (size_t)lst * 2 * D.cap_pairs;
+    int idx = atomicAdd(pair_counter(D.dsc, par), __popcll(hmask));
+    for (; hmask != 0; hmask &= hmask - 1, ++idx) {
+      if (idx < D.cap_pairs) {
+        list[2 * idx] = __builtin_ctzll(hmask);
+        list[2 * idx + 1] = t;
+      } else {
+        atomicOr(&D.dsc->err, MXE_PAIRS);
+      }
+    }
+  }
+  // pre-drift state: the encounter integrator starts its subsystems from it
+  if (hit || t < nb || D.keep_x0) {
+    for (int c = 0; c < 3; ++c) {
+      gbl(D.x0)[c * n + t] = p[c];
+      gbl(D.u0)[c * n + t] = v[c];
+    }
+  }
+  return hit;
+}
+
+// Launches that open step q in a joint sequence (the next launch integrates the
+// encounters of step q beside opening step q + 1): the block of the massive
+// bodies (bodies 0 .. nb - 1, lane k of the first wave holding massive body k
+// with its state q, w after the drift, its mass bm and changeover radius brc_t)
+// prepares the boundary that closes step q, when no flagged pair of step q joins
+// two massive bodies (the encounter integrator then leaves them as they are),
+// with big_boundary's arithmetic: BigNext[ph] and bn_valid[ph] = 1, or
+// bn_valid[ph] = 0 when such a pair exists.  Every thread of the block calls it.
+__device__ __forceinline__ void prepare_boundary(const SysDesc& D, int ph, bool any_bb,
+                                                 double* sh, KickSource* src,
+                                                 double (*bst)[kSmallBig], double* brc,
+                                                 const double (&q)[3], const double (&w)[3],
+                                                 double bm, double brc_t) {
+  const int tid = threadIdx.x, nb = D.nb;
+  if (any_bb) {
+    if (tid == 0) D.dsc->bn_valid[ph] = 0;
+    return;
+  }
+  double bpos[3] = {q[0], q[1], q[2]}, bvel[3] = {w[0], w[1], w[2]};
+  double P[3], J[3], vpre[3], Ppre[3], Ppost[3];
+  big_boundary(D, true, sh, src, bst, brc, bpos, bvel, bm, brc_t, P, J, vpre, Ppre, Ppost);
+  __syncthreads();
+  BigNext* N = D.bignext + ph;
+  if (tid == 0) {
+    for (int c = 0; c < 3; ++c) {
+      N->P[c] = P[c];
+      N->J[c] = J[c];
+      N->vpre[c] = vpre[c];
+      N->Ppre[c] = Ppre[c];
+      N->Ppost[c] = Ppost[c];
+    }
+  }
+  for (int i = tid; i < 8 * nb; i += blockDim.x)
+    reinterpret_cast<double*>(N->src)[i] = reinterpret_cast<const double*>(src)[i];
+  for (int i = tid; i < 12 * nb; i += blockDim.x) N->bst[i / nb][i % nb] = bst[i / nb][i % nb];
+  for (int i = tid; i < nb; i += blockDim.x) N->brc[i] = brc[i];
+  if (tid == 0) D.dsc->bn_valid[ph] = 1;
+}
+
 }  // namespace mxs

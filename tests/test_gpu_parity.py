@@ -399,6 +399,76 @@ def test_joined_launch_timing(mx, name, kw, joined):
     assert a.step_index() == b.step_index() == 7
 
 
+def _joint_cases():
+    return {
+        "embryo_disk": lambda: ic.embryo_disk(seed=11, n_small=4000, n_emb=10),
+        "close_planets": _close_planets_workload,
+        "long_list": lambda: _planets_with_cloud(n_far=50, k=320, close_pair=False),
+        "disk_model": _joint_disk_model,
+    }
+
+
+def _joint_disk_model():
+    w = ic.embryo_disk(seed=4, n_small=2000, n_emb=6)
+    w.params = dict(w.params, **DISK_MODES["all"])
+    return w
+
+
+@pytest.mark.parametrize("case", ["embryo_disk", "close_planets", "long_list", "disk_model"])
+def test_joint_launches_equal_single_steps(mx, case):
+    """A call of several steps on a single system with at most 64 massive bodies
+    runs each step's encounter integrator in one launch with the closing of that
+    step and the opening of the next.  Without a pair of massive bodies in an
+    encounter the boundary is prepared and the integrator closes and opens its
+    massless members itself (with more than 256 pairs, long_list, after the
+    general plan); with such a pair (close_planets) the tile blocks wait for the
+    integrator.  States, the last list, the step count and the counters must
+    equal those of one-step calls bit for bit, over enough steps to cycle the
+    three phases."""
+    w = _joint_cases()[case]()
+    a = mx.System.from_workload(w)
+    b = mx.System.from_workload(w)
+    n = 8
+    a.step(n)
+    for _ in range(n):
+        b.step(1)
+    xa, ua = a.get_dh()
+    xb, ub = b.get_dh()
+    print(f"[joint] {case}: {len(a.encounters())} pairs in the last step, "
+          f"{a.counters()[1]} flagged in {n} steps", flush=True)
+    assert np.array_equal(xa, xb) and np.array_equal(ua, ub)
+    assert np.array_equal(a.encounters(), b.encounters())
+    assert a.step_index() == b.step_index() == n
+    assert a.counters() == b.counters()
+    assert a.energy()[0] == b.energy()[0]
+    if case == "close_planets":
+        saw = False
+        c = mx.System.from_workload(w)
+        for _ in range(n):
+            c.step(1)
+            e = c.encounters()
+            saw |= bool(len(e)) and bool(np.any(e[:, 1] < w.params["n_big"]))
+        assert saw
+    if case == "long_list":
+        assert a.counters()[1] > 256 * n // 2
+
+
+def test_joint_launch_timing(mx):
+    """The joint-launch timing group times the launches of the sequence mx_step
+    runs (one per step but the last); the states equal plain eager steps."""
+    w = ic.embryo_disk(seed=2, n_small=3000, n_emb=8)
+    a = mx.System.from_workload(w)
+    b = mx.System.from_workload(w)
+    a.step(7)
+    ms, nl = b.step_timed(7, "step_joint", stride=2)  # steps 0, 2, 4, 6 timed
+    assert nl == 3 and min(ms[0], ms[2], ms[4]) > 0.0
+    assert ms[1] == ms[3] == ms[5] == ms[6] == 0.0
+    xa, ua = a.get_dh()
+    xb, ub = b.get_dh()
+    assert np.array_equal(xa, xb) and np.array_equal(ua, ub)
+    assert a.step_index() == b.step_index() == 7
+
+
 def test_heliocentric_roundtrip(mx, orc):
     w = ic.two_giants(seed=3, n_small=100)
     g = mx.System.from_workload(w)
