@@ -1457,40 +1457,133 @@ struct FastPlan {
 constexpr int kPlanWaitMax = 1 << 22;  // polls of the plan flag (each after a short sleep)
 
 // Joint launches: step q closed and step q + 1 opened for massless body j (the
-// joined step kernel's operations, by lane 0 of the integrator's wave) with the
-// boundary prepared for phase par (jsrc, jbst, jbrc in LDS), from its state after
-// the integrator (xj, vj in LDS) or, when its subsystem was not integrated, after
-// the drift (null: read from x, u).  Step q + 1's pairs go to phase nx.
+// joined step kernel's operations) by the integrator's whole wave, with the
+// boundary prepared for phase par (jsrc, jbst, jbrc, and jsc = J, vpre, Ppre,
+// Ppost, in LDS), from its state after the integrator (xj, vj in LDS) or, when
+// its subsystem was not integrated, after the drift (null: read from x, u); jr:
+// its radius and density (LDS), or null (read here).  Lane s takes the gravity
+// terms and the encounter test of massive body s; the terms are added in order
+// of s and everything else runs on the same values in every lane, so each
+// quantity is the per-body code's (close_body, advance_body, flag_body), bit
+// for bit, with a shorter chain.  Step q + 1's pairs go to phase nx.
 __device__ __forceinline__ void joint_member(const SysDesc& D, int j, const double* xj,
-                                          const double* vj, int par, int nx,
-                                          const KickSource* jsrc,
-                                          const double (*jbst)[kSmallBig], const double* jbrc) {
+                                             const double* vj, int par, int nx,
+                                             const KickSource* jsrc,
+                                             const double (*jbst)[kSmallBig], const double* jbrc,
+                                             const double* jsc, const double* jr) {
   const int n = D.n, nb = D.nb;
-  if (threadIdx.x != 0 || j < nb || j >= n) return;
-  const double h = D.h, mu0 = D.mu0;
+  if (j < nb || j >= n) return;  // wave-uniform
+  const int lane = threadIdx.x & 63;
+  const double h = D.h, hh = 0.5 * D.h, mu0 = D.mu0;
+  const double rct = 0.0;  // a massless body has no changeover radius of its own
   double p[3], v[3], a[3], q[3], w[3], J[3], vpre[3], Ppre[3], Ppost[3];
   for (int c = 0; c < 3; ++c) {
     p[c] = xj ? xj[c] : gbl(D.x)[(size_t)c * n + j];
     v[c] = vj ? vj[c] : gbl(D.u)[(size_t)c * n + j];
+    J[c] = jsc[c];
+    vpre[c] = jsc[3 + c];
+    Ppre[c] = jsc[6 + c];
+    Ppost[c] = jsc[9 + c];
   }
-  const double rp = D.gas_on ? gbl(D.r_p)[j - nb] : 0.0;
-  const double rhop = D.gas_on ? gbl(D.rho_p)[j - nb] : 0.0;
-  const BigNext* N = D.bignext + par;
-  for (int c = 0; c < 3; ++c) {
-    J[c] = N->J[c];
-    vpre[c] = N->vpre[c];
-    Ppre[c] = N->Ppre[c];
-    Ppost[c] = N->Ppost[c];
+  const double rp = !D.gas_on ? 0.0 : jr ? jr[0] : gbl(D.r_p)[j - nb];
+  const double rhop = !D.gas_on ? 0.0 : jr ? jr[1] : gbl(D.rho_p)[j - nb];
+  // step q closed: jump, gravity, drag, half kick
+  const double px = p[0] + J[0], py = p[1] + J[1], pz = p[2] + J[2];
+  {
+    const double rc2t = rct * rct;
+    double k15, k1875;
+    mxd::vgpr_constants(k15, k1875);
+    double wgt = 0.0, dx = 0.0, dy = 0.0, dz = 0.0;
+    if (lane < nb) {
+      const KickSource S = jsrc[lane];
+      dx = S.x - px;
+      dy = S.y - py;
+      dz = S.z - pz;
+      double s2 = fma(dz, dz, fma(dy, dy, dx * dx));
+      double rc2 = fmax(S.rc2, rc2t);
+      wgt = mxd::fast_weight(S.mu, s2, k15, k1875);
+      if (s2 < rc2) wgt = S.mu * mxd::changeover_weight_slow(s2, fmax(S.rc, rct), rc2);
+    }
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int s = 0; s < nb; ++s) {
+      const double ws = __shfl(wgt, s);
+      a0 = fma(ws, __shfl(dx, s), a0);
+      a1 = fma(ws, __shfl(dy, s), a1);
+      a2 = fma(ws, __shfl(dz, s), a2);
+    }
+    double adx = 0.0, ady = 0.0, adz = 0.0;
+    if (D.gas_on)
+      mxd::gas_drag(D.dc, px, py, v[0] + vpre[0], v[1] + vpre[1], v[2] + vpre[2], rp, rhop, adx,
+                    ady, adz);
+    v[0] += hh * (a0 + adx);
+    v[1] += hh * (a1 + ady);
+    v[2] += hh * (a2 + adz);
+    p[0] = px;
+    p[1] = py;
+    p[2] = pz;
+    a[0] = a0;
+    a[1] = a1;
+    a[2] = a2;
   }
-  mxs::close_body(j, nb, jsrc, 0.0, J, vpre, 0.5 * h, D.dc, D.gas_on, rp, rhop, true, p, v, a);
-  if (!isfinite(v[0] + v[1] + v[2] + p[0] + p[1] + p[2])) atomicOr(&D.dsc->err, MXE_NONFINITE);
-  if (!mxs::advance_body(j, nb, mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v, a, q, w))
-    atomicOr(&D.dsc->err, MXE_NOCONV);
-  for (int c = 0; c < 3; ++c) {
-    gbl(D.x)[(size_t)c * n + j] = q[c];
-    gbl(D.u)[(size_t)c * n + j] = w[c];
+  const bool fin = isfinite(v[0] + v[1] + v[2] + p[0] + p[1] + p[2]);
+  // step q + 1 opened: drag, half kick, jump, drift
+  const bool conv = mxs::advance_body(j, nb, mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v,
+                                      a, q, w);
+  // encounter test of step q + 1 against massive body `lane`
+  bool hit = false;
+  if (lane < nb) {
+    const int i = lane;
+    const double k427 = (4.0 / 27.0) * fabs(h);
+    double r0[3], w0[3], w1[3], dd[3];
+    for (int c = 0; c < 3; ++c) {
+      r0[c] = p[c] - jbst[c][i];
+      w0[c] = v[c] - jbst[3 + c][i];
+      w1[c] = w[c] - jbst[9 + c][i];
+      dd[c] = (q[c] - p[c]) - (jbst[6 + c][i] - jbst[c][i]);
+    }
+    double m0 = fma(r0[2], r0[2], fma(r0[1], r0[1], r0[0] * r0[0]));
+    double nd = fmax(fmax(fabs(dd[0]), fabs(dd[1])), fabs(dd[2]));
+    double nw = fmax(fmax(fabs(w0[0]), fabs(w0[1])), fabs(w0[2])) +
+                fmax(fmax(fabs(w1[0]), fabs(w1[1])), fabs(w1[2]));
+    double rc = fmax(jbrc[i], rct);
+    double bound = rc + 1.7320508075688773 * fma(k427, nw, nd) * (1.0 + 1e-12);
+    if (m0 <= bound * bound * (1.0 + 1e-12)) {
+      double r1[3];
+      for (int c = 0; c < 3; ++c) r1[c] = q[c] - jbst[6 + c][i];
+      double dmin = mxd::hermite_dmin2(r0[0], r0[1], r0[2], w0[0], w0[1], w0[2], r1[0], r1[1],
+                                       r1[2], w1[0], w1[1], w1[2], h);
+      hit = dmin <= rc * rc;
+    }
   }
-  mxs::flag_body(D, nx, nx, j, n, nb, h, jbst, jbrc, p, v, q, w);
+  const uint64_t hits = __ballot(hit);
+  if (lane == 0) {
+    if (!fin) atomicOr(&D.dsc->err, MXE_NONFINITE);
+    if (!conv) atomicOr(&D.dsc->err, MXE_NOCONV);
+    for (int c = 0; c < 3; ++c) {
+      gbl(D.x)[(size_t)c * n + j] = q[c];
+      gbl(D.u)[(size_t)c * n + j] = w[c];
+    }
+    // the body's pairs appended together, in increasing i (as flag_body)
+    uint64_t hmask = hits;
+    if (hmask != 0) {
+      const auto list = gbl(D.pairs) + (size_t)nx * 2 * D.cap_pairs;
+      int idx = atomicAdd(pair_counter(D.dsc, nx), __popcll(hmask));
+      for (; hmask != 0; hmask &= hmask - 1, ++idx) {
+        if (idx < D.cap_pairs) {
+          list[2 * idx] = __builtin_ctzll(hmask);
+          list[2 * idx + 1] = j;
+        } else {
+          atomicOr(&D.dsc->err, MXE_PAIRS);
+        }
+      }
+    }
+    if (hits != 0 || D.keep_x0) {
+      for (int c = 0; c < 3; ++c) {
+        gbl(D.x0)[(size_t)c * n + j] = p[c];
+        gbl(D.u0)[(size_t)c * n + j] = v[c];
+      }
+    }
+  }
 }
 
 // One block (one wave) of a system's encounter integrator: block bx of nbx.
@@ -1498,17 +1591,18 @@ __device__ __forceinline__ void joint_member(const SysDesc& D, int j, const doub
 // lst: the flagged list read, clr: the append counter cleared for the next step
 // (-1: none).  kJoint: the integrator runs inside a joint launch beside the
 // closing of step q and the opening of step q + 1 (phase nx); the massive
-// members start from bigpre[par], and with jfast (the boundary of step q was
-// prepared: no flagged pair joins two massive bodies, so every subsystem is one
+// members start from bigpre[par], and with jfast (bn_valid[par]: the boundary of
+// step q was prepared, no flagged pair joins two massive bodies, so every subsystem is one
 // massless body and the massive bodies it met, the massless body last) the wave
 // closes and opens its massless member itself with the prepared boundary (jsrc,
-// jbst, jbrc: LDS of the launch).  The list is then left in append order (the
-// tile blocks of the launch read it).
+// jbst, jbrc, jsc: LDS of the launch; jr: LDS for the member's radius and
+// density, read with the subsystem's state).  The list is then left in append
+// order (the tile blocks of the launch read it).  Returns jfast.
 template <bool kJoint>
-__device__ __forceinline__ void bs_body(const SysDesc& D, const int bx, const int nbx, int plan,
-                                        int par, int nx, int lst, int clr, bool jfast,
-                                        KickSource* jsrc, double (*jbst)[kSmallBig],
-                                        double* jbrc) {
+__device__ __forceinline__ bool bs_body(const SysDesc& D, const int bx, const int nbx, int plan,
+                                        int par, int nx, int lst, int clr, KickSource* jsrc,
+                                        double (*jbst)[kSmallBig], double* jbrc, double* jsc,
+                                        double* jr) {
   const int n = D.n, nb = D.nb;
   const double mu0 = D.mu0, h = D.h, tol = D.bs_tol;
   const auto x0s = gbl(D.x0);
@@ -1520,12 +1614,24 @@ __device__ __forceinline__ void bs_body(const SysDesc& D, const int bx, const in
   const auto subs = gbl(D.subs);
   DevScalars* __restrict__ dsc = D.dsc;
   const auto bigmid = gbl(D.bigmid) + (size_t)par * 6 * nb;
-  if (nb == 0) return;
+  if (nb == 0) return false;
+  // joint launches: whether the boundary was prepared (requested with the list)
+  const bool jfast = kJoint && dsc->bn_valid[par] != 0;
   __shared__ Subsystem S;
   __shared__ double xs[3 * kM], vs[3 * kM], mum[kM], rcm[kM], scal[2 * kM];
-  __shared__ double res[kC][6 * kM];
-  __shared__ double wk[kC][3][3 * kM];
-  __shared__ double resS[8][kC][6 * 4];  // speculative rounds of subsystems of <= 4 members
+  // the tables of larger subsystems and the speculative rounds of subsystems of
+  // at most four members (never both for one subsystem) share their LDS
+  union BsTables {
+    struct {
+      double res[kC][6 * kM];
+      double wk[kC][3][3 * kM];
+    } big;
+    double resS[8][kC][6 * 4];
+  };
+  __shared__ BsTables U;
+  auto& res = U.big.res;
+  auto& wk = U.big.wk;
+  auto& resS = U.resS;
   __shared__ FastPlan F;
   __shared__ int s_scan[64], s_nbig, s_nsub;
   const int lane = threadIdx.x;
@@ -1562,7 +1668,7 @@ __device__ __forceinline__ void bs_body(const SysDesc& D, const int bx, const in
     // a system never has more subsystems than flagged pairs: blocks past the
     // pair count have nothing to integrate (the last block may still prepare
     // the next step boundary's massive bodies)
-    if (bx >= np && (kJoint || bx != nbx - 1)) return;
+    if (bx >= np && (kJoint || bx != nbx - 1)) return jfast;
     bigs_kept = np > 0;
     if (np > 0) {
       fast = np <= 256 && nb <= 64 && n < (1 << 26);
@@ -1726,6 +1832,11 @@ __device__ __forceinline__ void bs_body(const SysDesc& D, const int bx, const in
         reinterpret_cast<double*>(jsrc)[i] = reinterpret_cast<const double*>(N->src)[i];
       for (int i = lane; i < 12 * nb; i += 64) jbst[i / nb][i % nb] = N->bst[i / nb][i % nb];
       for (int i = lane; i < nb; i += 64) jbrc[i] = N->brc[i];
+      if (lane < 12)
+        jsc[lane] = lane < 3 ? N->J[lane]
+                    : lane < 6 ? N->vpre[lane - 3]
+                    : lane < 9 ? N->Ppre[lane - 6]
+                               : N->Ppost[lane - 9];
     }
   }
   for (int b = bx; b < nsub; b += nbx) {
@@ -1757,8 +1868,17 @@ __device__ __forceinline__ void bs_body(const SysDesc& D, const int bx, const in
     if (m == 0) {  // a subsystem dropped for capacity (error already latched)
       if (kJoint && jfast)
         joint_member(D, fast ? (int)(F.kb[F.gs[b]] >> 6) : S.jm, nullptr, nullptr, par, nx, jsrc,
-                     jbst, jbrc);
+                     jbst, jbrc, jsc, nullptr);
       continue;
+    }
+    if (kJoint && jfast && lane == 63 && D.gas_on) {
+      // the massless member's radius and density, for its closing after the
+      // integration (requested with the members' state)
+      const int jj = S.mem[m - 1];
+      if (jj >= nb && jj < n) {
+        jr[0] = gbl(D.r_p)[jj - nb];
+        jr[1] = gbl(D.rho_p)[jj - nb];
+      }
     }
     for (int e = lane; e < nn; e += 64) {
       int k = e / 3, c = e - 3 * (e / 3);
@@ -1890,12 +2010,12 @@ __device__ __forceinline__ void bs_body(const SysDesc& D, const int bx, const in
     if (failed) {
       if (lane == 0) atomicOr(&dsc->err, MXE_BS);
       if (kJoint && jfast) joint_member(D, S.mem[m - 1], nullptr, nullptr, par, nx, jsrc, jbst,
-                                        jbrc);
+                                        jbrc, jsc, jr);
       continue;
     }
     if (kJoint && jfast) {  // the member's closing and opening replace the write-back
       joint_member(D, S.mem[m - 1], xs + 3 * (m - 1), vs + 3 * (m - 1), par, nx, jsrc, jbst,
-                   jbrc);
+                   jbrc, jsc, jr);
       continue;
     }
     for (int e = lane; e < nn; e += 64) {
@@ -1910,19 +2030,22 @@ __device__ __forceinline__ void bs_body(const SysDesc& D, const int bx, const in
       }
     }
   }
+  return jfast;
 }
 
 __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int plan, int par,
                                            int lst, int clr) {
-  bs_body<false>(desc[blockIdx.y], blockIdx.x, gridDim.x, plan, par, 0, lst, clr, false, nullptr,
-                 nullptr, nullptr);
+  bs_body<false>(desc[blockIdx.y], blockIdx.x, gridDim.x, plan, par, 0, lst, clr, nullptr,
+                 nullptr, nullptr, nullptr, nullptr);
 }
 
 // One launch per step of a joint sequence (a single system with n_big <= 64 and
 // no core growth): blocks 0 .. nbs - 1 run the encounter integrator of step q
-// (phase ph) on their first wave, the following blocks (one 256-body tile each)
+// (phase ph) on their first wave, the following blocks (one BLK-body tile each)
 // close step q and open step q + 1 (phase nx) for their bodies with exactly the
-// joined step kernel's operations.  The two parts depend on each other only
+// joined step kernel's operations.  The integrator's registers set the launch
+// to one wave per SIMD; with one-wave blocks an integrator block holds one SIMD
+// of a CU, not the whole CU, while it runs.  The two parts depend on each other only
 // through the bodies the integrator moves, and the launch that opened step q
 // prepared what the closing needs when no flagged pair of step q joins two
 // massive bodies (prepare_boundary: the massive bodies are then left as they
@@ -1937,27 +2060,25 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
 // massive members start from bigpre (the tile of the massive bodies rewrites
 // x0, u0), and the tile of the massive bodies clears the copies of step q - 1 and
 // prepares the next boundary.
-__global__ __launch_bounds__(256) void k_step_joint(const SysDesc* __restrict__ desc,
-                                                    const Tile* __restrict__ tiles, int nbs,
+template <int BLK>
+__global__ __launch_bounds__(BLK) void k_step_joint(const SysDesc* __restrict__ desc, int nbs,
                                                     int ph) {
   using namespace mxs;
-  constexpr int BLK = 256;
   const SysDesc& D = desc[0];
   __shared__ double sh[8];
   __shared__ KickSource src[kSmallBig];
   __shared__ double bst[12][kSmallBig];
   __shared__ double brc[kSmallBig];
   __shared__ uint32_t fl[BLK / 32];  // the tile's bodies the integrator closes
+  __shared__ double jsc[12], jr[2];  // integrator blocks: J, vpre, Ppre, Ppost; rp, rho_p
   const int nx = ph == 2 ? 0 : ph + 1;
   const int tid = threadIdx.x;
   const int n = D.n, nb = D.nb;
   const double h = D.h, hh = 0.5 * D.h, mu0 = D.mu0;
   DevScalars* __restrict__ dsc = D.dsc;
-  const int npq = min(*pair_counter(dsc, ph), D.cap_pairs);
-  const bool jfast = dsc->bn_valid[ph] != 0;
   if ((int)blockIdx.x < nbs) {
     if (tid >= 64) return;  // one wave per integrator block
-    bs_body<true>(D, blockIdx.x, nbs, 1, ph, nx, ph, -1, jfast, src, bst, brc);
+    const bool jfast = bs_body<true>(D, blockIdx.x, nbs, 1, ph, nx, ph, -1, src, bst, brc, jsc, jr);
     if (!jfast) {
       __syncthreads();  // the wave's stores precede the release
       if (tid == 0)
@@ -1965,7 +2086,9 @@ __global__ __launch_bounds__(256) void k_step_joint(const SysDesc* __restrict__ 
     }
     return;
   }
-  const Tile tl = tiles[blockIdx.x - nbs];
+  const int npq = min(*pair_counter(dsc, ph), D.cap_pairs);
+  const bool jfast = dsc->bn_valid[ph] != 0;
+  const Tile tl = {0, ((int)blockIdx.x - nbs) * BLK};
   const int t = tl.first + tid;
   const bool owner = tl.first == 0;  // block-uniform: the tile of the massive bodies
   if (!jfast) {
@@ -2119,10 +2242,12 @@ hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, 
   return mxlaunch_on(st, tm, k_bs, dim3(bps, n_sys), dim3(64), desc, plan, par, lst, clr);
 }
 
-hipError_t launch_step_joint(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
-                             const Tile* tiles, int n_tiles, int nbs, int ph) {
-  if (n_tiles <= 0 || nbs <= 0 || ph < 0 || ph > 2) return hipErrorInvalidValue;
-  return mxlaunch_on(st, tm, k_step_joint, dim3(nbs + n_tiles), dim3(256), desc, tiles, nbs, ph);
+hipError_t launch_step_joint(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n,
+                             int nbs, int ph) {
+  constexpr int kBlk = 64;  // bodies per tile block
+  if (n <= 0 || nbs <= 0 || ph < 0 || ph > 2) return hipErrorInvalidValue;
+  const int n_tiles = (n + kBlk - 1) / kBlk;
+  return mxlaunch_on(st, tm, k_step_joint<kBlk>, dim3(nbs + n_tiles), dim3(kBlk), desc, nbs, ph);
 }
 
 // flag + sort for the stateless entry; fpack built from the given states

@@ -196,8 +196,7 @@ hipError_t enqueue_joint(mx_system* s, int32_t n, Visit visit, After after) {
   if (e != hipSuccess) return e;
   for (int32_t q = 0; q < n - 1; ++q) {
     visit(MX_K_STEP_JOINT, q);
-    e = mxk::launch_step_joint(s->stream, &s->tev, s->desc, s->tiles, s->n_tiles, kJointBs,
-                               q % 3);
+    e = mxk::launch_step_joint(s->stream, &s->tev, s->desc, s->n, kJointBs, q % 3);
     after(MX_K_STEP_JOINT, q);
     if (e != hipSuccess) return e;
   }

@@ -345,9 +345,9 @@ hipError_t launch_step_ba_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc*
 hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys,
                          int bps, int plan, int par, int lst, int clr);
 // encounter integrator of step q (phase ph, nbs one-wave blocks) beside the
-// closing of step q and the opening of step q + 1 for a single system's tiles
-hipError_t launch_step_joint(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
-                             const Tile* tiles, int n_tiles, int nbs, int ph);
+// closing of step q and the opening of step q + 1 for a single system of n bodies
+hipError_t launch_step_joint(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n,
+                             int nbs, int ph);
 
 // stateless single-kernel launchers
 hipError_t gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,
