@@ -8,16 +8,19 @@ one JSON line.  `value` is changeover-weighted kick interactions per second over
 whole steps (I = n_big * (n - 1) per step, ordered pairs, n = non-star bodies).
 
 Extra objects:
-  roofline      -- the dominant kernel group of the step against its bound: groups
-                   are ranked with HIP events around each group, then the dominant
-                   one is timed over K further steps of the same run with HIP events
-                   bound to its kernels' own start and end in every 8th step (eager
-                   launches; --event-stride); its
-                   HBM traffic and counter-based FP64 rate (counter_fp64) come from
-                   the committed counter summaries while the kernel sources are
-                   unchanged
-  step_kernel   -- the launch that closes one step and opens the next (n_big <= 64),
-                   timed over further steps, against HBM, with its counter FP64 rate
+  roofline      -- the dominant kernel group of the step against its bound.  With
+                   n_big <= 64 every step but the last of a call is one joint launch
+                   (the encounter integrator of the step beside the closing of that
+                   step and the opening of the next), which is then the dominant
+                   group; otherwise groups are ranked with HIP events around each
+                   group.  The dominant group is timed over the K timed steps with
+                   HIP events bound to its kernels' own start and end in every 8th
+                   step (eager launches; --event-stride); its HBM traffic and
+                   counter-based FP64 rate (counter_fp64) come from the committed
+                   counter summaries while the kernel sources are unchanged
+  step_kernel   -- the launch that closes one step and opens the next without the
+                   integrator (n_big <= 64; the batched ensemble's launch), timed over
+                   further steps, against HBM, with its counter FP64 rate
   kick_fp64     -- the force kernel of the fully self-gravitating 4,004-body case
                    (16.0 M interactions per kick) against FP64 peak, by the 20-flop
                    model and by counters
@@ -88,6 +91,15 @@ def roofline_for(name: str, avg_s: float, w, n_pairs_avg: float, bs_flop_per_lau
         return {"kernel": name, "bound": "hbm", "achieved": a / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s", "frac": a / PEAK_HBM, "traffic": None,
                 "model": "96 B per body (x0,u0,x1,u1) + 128 B per massive source record"}
+    if name == "step_joint":
+        b = BYTES_JOINED_SMALL * ns + BYTES_KJD_BIG * nb
+        a = b / avg_s
+        return {"kernel": name, "bound": "hbm", "achieved": a / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "frac": a / PEAK_HBM, "traffic": None,
+                "model": f"{BYTES_JOINED_SMALL} B per massless body (x, u, r_p, rho_p read; "
+                         f"x, u written), {BYTES_KJD_BIG} B per massive body; the encounter "
+                         "integrator in the same launch adds no HBM traffic of note",
+                "bs_model_flop_per_launch": bs_flop_per_launch}
     if name == "bs":
         # model FP64 operations counted by the library while the kernel ran
         a = bs_flop_per_launch / avg_s
@@ -145,7 +157,7 @@ GROUP_KERNELS = {
     ("bs", True): ["k_bs"], ("bs", False): ["k_bs"],
     ("kick_jump_drift", True): ["k_step_a"], ("kick_jump_drift", False): ["k_kick_jump_drift"],
     ("force_kick", True): ["k_step_b"], ("force_kick", False): ["k_force_sym", "k_force_finish_sym"],
-    ("step_joined", True): ["k_step_ba"],
+    ("step_joined", True): ["k_step_ba"], ("step_joint", True): ["k_step_joint"],
     ("flag", False): [["k_chunk_bounds", "k_flag_cull"], ["k_flag"]],
     ("jump_pack", False): ["k_jump_pack"], ("growth", False): ["k_growth"],
 }
@@ -449,6 +461,11 @@ def main():
         n_timed = (args.profile_steps - 1) // args.event_stride + 1
         per_step[g] = sum(ms) / n_timed
     dominant = max(per_step, key=per_step.get)
+    # the joint launch, where mx_step uses it: one per step but the last of a call
+    ms, nl = s.step_timed(args.profile_steps, "step_joint", args.event_stride)
+    if nl > 0:
+        per_step["step_joint"] = sum(ms) / nl
+        dominant = "step_joint"
     # also creates the timing events outside the timed region
     s.step_timed(args.steps, dominant, args.event_stride)
     s.sync()
@@ -467,9 +484,9 @@ def main():
     pairs_last = len(s.encounters())
     pairs_avg = (p1 - p0) / args.steps
     dom_avg_s = sum(per_step_ms) / max(n_launch, 1) / 1e3
-    # the integrator's model flops are counted over every timed step; it launches
-    # once per step, so per launch they are divided by the steps, not by the
-    # event-timed launches
+    # the integrator's model flops are counted over every timed step; it runs once
+    # per step, so per launch they are divided by the steps, not by the event-timed
+    # launches
     roof = roofline_for(dominant, dom_avg_s, w, pairs_avg, (f1 - f0) / args.steps)
     roof["avg_launch_us"] = dom_avg_s * 1e6
     roof["launches"] = n_launch
