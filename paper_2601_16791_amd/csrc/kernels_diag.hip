@@ -149,6 +149,7 @@ __global__ void k_reset(DevScalars* dsc, int64_t step) {
     dsc->n_pairs[r] = 0;
     dsc->plan_ready[r] = 0;
     dsc->bs_done[r] = 0;
+    dsc->n_jsub[r] = 0;
   }
   dsc->n_sub = 0;
   dsc->P[0] = dsc->P[1] = dsc->P[2] = 0.0;

@@ -1563,11 +1563,27 @@ __device__ __forceinline__ void joint_member(const SysDesc& D, int j, const doub
       gbl(D.x)[(size_t)c * n + j] = q[c];
       gbl(D.u)[(size_t)c * n + j] = w[c];
     }
-    // the body's pairs appended together, in increasing i (as flag_body)
+    // the body's pairs appended together, in increasing i (as flag_body), and
+    // its subsystem record; both slots are taken before either is written
     uint64_t hmask = hits;
     if (hmask != 0) {
       const auto list = gbl(D.pairs) + (size_t)nx * 2 * D.cap_pairs;
       int idx = atomicAdd(pair_counter(D.dsc, nx), __popcll(hmask));
+      const int ridx = atomicAdd(&D.dsc->n_jsub[nx], 1);
+      if (ridx < D.cap_subs) {
+        JointSub* R = D.jsub + (size_t)nx * D.cap_subs + ridx;
+        R->mask = hits;
+        R->j = j;
+        R->pad = 0;
+        for (int c = 0; c < 3; ++c) {
+          R->x[c] = p[c];
+          R->v[c] = v[c];
+        }
+        R->rp = rp;
+        R->rhop = rhop;
+      } else {
+        atomicOr(&D.dsc->err, MXE_SUBSYS);
+      }
       for (; hmask != 0; hmask &= hmask - 1, ++idx) {
         if (idx < D.cap_pairs) {
           list[2 * idx] = __builtin_ctzll(hmask);
@@ -1592,12 +1608,14 @@ __device__ __forceinline__ void joint_member(const SysDesc& D, int j, const doub
 // (-1: none).  kJoint: the integrator runs inside a joint launch beside the
 // closing of step q and the opening of step q + 1 (phase nx); the massive
 // members start from bigpre[par], and with jfast (bn_valid[par]: the boundary of
-// step q was prepared, no flagged pair joins two massive bodies, so every subsystem is one
-// massless body and the massive bodies it met, the massless body last) the wave
-// closes and opens its massless member itself with the prepared boundary (jsrc,
-// jbst, jbrc, jsc: LDS of the launch; jr: LDS for the member's radius and
-// density, read with the subsystem's state).  The list is then left in append
-// order (the tile blocks of the launch read it).  Returns jfast.
+// step q was prepared, no flagged pair joins two massive bodies, so every
+// subsystem is one massless body and the massive bodies it met, the massless
+// body last) the subsystems are the records the flagging launch appended (one
+// per flagged massless body, with its pre-drift state), and the wave closes and
+// opens its massless member itself with the prepared boundary (jsrc, jbst, jbrc,
+// jsc: LDS of the launch; jr: LDS for the member's radius and density, read with
+// the subsystem's state).  Without jfast the list is planned as in k_bs and left
+// in append order.  Returns jfast.
 template <bool kJoint>
 __device__ __forceinline__ bool bs_body(const SysDesc& D, const int bx, const int nbx, int plan,
                                         int par, int nx, int lst, int clr, KickSource* jsrc,
@@ -1634,13 +1652,84 @@ __device__ __forceinline__ bool bs_body(const SysDesc& D, const int bx, const in
   auto& resS = U.resS;
   __shared__ FastPlan F;
   __shared__ int s_scan[64], s_nbig, s_nsub;
+  // joint launches: the massive bodies' pre-drift state [6][nb], masses [nb] and
+  // changeover radii [nb]
+  __shared__ double jstage[kJoint ? 8 * kSmallBig : 1];
   const int lane = threadIdx.x;
   const double tol2 = tol * tol;
   int nsub = 0;
   bool fast = false;
   bool bigs_kept = true;  // false: no subsystem of this step changes a massive body
+  // the block's first record (joint launches)
+  uint64_t r0mask = 0;
+  int r0j = 0;
+  double r0x[3] = {0.0, 0.0, 0.0}, r0v[3] = {0.0, 0.0, 0.0}, r0rp = 0.0, r0rh = 0.0;
   if (!plan) {
     nsub = dsc->n_sub;
+  } else if (kJoint && jfast) {
+    // one subsystem per record appended by the launch that flagged the step's
+    // pairs (the massless body, its massive partners, its pre-drift state); the
+    // subsystem table is not written (only the adjoint reads it, and it never
+    // runs joint launches).  Requested at once: the counts, the block's first
+    // record (read before its count is known; used only if it exists), the
+    // massive bodies' state, masses and radii, and the prepared boundary.
+    const BigNext* N = D.bignext + par;
+    const auto bpre = gbl(D.bigpre) + (size_t)par * 6 * nb;
+    const JointSub* R0 = D.jsub + (size_t)par * D.cap_subs + bx;
+    const int nrec = dsc->n_jsub[par];
+    const int n_pairs = *pair_counter(dsc, par);
+    r0mask = R0->mask;
+    r0j = R0->j;
+    for (int c = 0; c < 3; ++c) {
+      r0x[c] = R0->x[c];
+      r0v[c] = R0->v[c];
+    }
+    r0rp = R0->rp;
+    r0rh = R0->rhop;
+    double sv[6], bsrc[8], bbst[12];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      const int e = lane + 64 * r;
+      sv[r] = e < 6 * nb ? bpre[e] : 0.0;
+    }
+    const double muv = lane < nb ? mu[lane] : 0.0, rcv = lane < nb ? rcrit[lane] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = lane + 64 * r;
+      bsrc[r] = e < 8 * nb ? reinterpret_cast<const double*>(N->src)[e] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 12; ++r) bbst[r] = lane < nb ? N->bst[r][lane] : 0.0;
+    const double bbrc = lane < nb ? N->brc[lane] : 0.0;
+    const double bsc = lane < 12 ? reinterpret_cast<const double*>(N)[3 + lane] : 0.0;
+    nsub = min(nrec, D.cap_subs);
+    if (bx == 0 && lane == 0) {
+      dsc->n_pairs_last = n_pairs;
+      dsc->pairs_flagged += (unsigned long long)n_pairs;
+      dsc->n_sub = nsub;
+    }
+    if (bx >= nsub) return jfast;
+    bigs_kept = false;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      const int e = lane + 64 * r;
+      if (e < 6 * nb) jstage[e] = sv[r];
+    }
+    if (lane < nb) {
+      jstage[6 * nb + lane] = muv;
+      jstage[7 * nb + lane] = rcv;
+    }
+    // the prepared boundary: the massless members are closed and opened with it
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = lane + 64 * r;
+      if (e < 8 * nb) reinterpret_cast<double*>(jsrc)[e] = bsrc[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 12; ++r)
+      if (lane < nb) jbst[r][lane] = bbst[r];
+    if (lane < nb) jbrc[lane] = bbrc;
+    if (lane < 12) jsc[lane] = bsc;
   } else {
     const bool b0 = bx == 0;
     const int cap_pairs = D.cap_pairs, cap_subs = D.cap_subs;
@@ -1824,24 +1913,49 @@ __device__ __forceinline__ bool bs_body(const SysDesc& D, const int bx, const in
     }
   }
   }
-  if constexpr (kJoint) {
-    if (jfast) {
-      // the prepared boundary: the massless members are closed and opened with it
-      const BigNext* N = D.bignext + par;
-      for (int i = lane; i < 8 * nb; i += 64)
-        reinterpret_cast<double*>(jsrc)[i] = reinterpret_cast<const double*>(N->src)[i];
-      for (int i = lane; i < 12 * nb; i += 64) jbst[i / nb][i % nb] = N->bst[i / nb][i % nb];
-      for (int i = lane; i < nb; i += 64) jbrc[i] = N->brc[i];
-      if (lane < 12)
-        jsc[lane] = lane < 3 ? N->J[lane]
-                    : lane < 6 ? N->vpre[lane - 3]
-                    : lane < 9 ? N->Ppre[lane - 6]
-                               : N->Ppost[lane - 9];
-    }
-  }
   for (int b = bx; b < nsub; b += nbx) {
     __syncthreads();
-    if (fast) {
+    if (kJoint && jfast) {
+      // subsystem b from its record: the massive partners in increasing index,
+      // then the massless body, with its state, radius and density (the other
+      // members' state from bigpre)
+      uint64_t mask = r0mask;
+      int jj = r0j;
+      double rx[3] = {r0x[0], r0x[1], r0x[2]}, rv[3] = {r0v[0], r0v[1], r0v[2]};
+      double rrp = r0rp, rrh = r0rh;
+      if (b != bx) {
+        const JointSub* R = D.jsub + (size_t)par * D.cap_subs + b;
+        mask = R->mask;
+        jj = R->j;
+        for (int c = 0; c < 3; ++c) {
+          rx[c] = R->x[c];
+          rv[c] = R->v[c];
+        }
+        rrp = R->rp;
+        rrh = R->rhop;
+      }
+      const int k = __popcll(mask);
+      const bool fits = k + 1 <= kBsMaxMembers && k <= kBsMaxPairs;
+      if (lane == 0) {
+        S.m = fits ? k + 1 : 0;
+        S.keep_from = fits ? k : 0;
+        S.np = fits ? k : 0;
+        S.jm = jj;
+        if (fits) S.mem[k] = jj;
+      }
+      if (fits && ((mask >> lane) & 1ull)) {
+        const int pos = __popcll(mask & ((1ull << lane) - 1ull));
+        S.mem[pos] = lane;
+        S.pl[pos][0] = pos;
+        S.pl[pos][1] = k;
+      }
+      if (fits && lane < 6) {
+        if (lane < 3) xs[3 * k + lane] = rx[lane];
+        else vs[3 * k + lane - 3] = rv[lane - 3];
+      }
+      if (lane == 6) jr[0] = rrp;
+      if (lane == 7) jr[1] = rrh;
+    } else if (fast) {
       // subsystem b from the sorted keys in LDS
       const int e0 = F.gs[b], k = F.gs[b + 1] - e0;
       const bool fits = k + 1 <= kBsMaxMembers && k <= kBsMaxPairs;
@@ -1867,22 +1981,19 @@ __device__ __forceinline__ bool bs_body(const SysDesc& D, const int bx, const in
     const int nn = 3 * m;
     if (m == 0) {  // a subsystem dropped for capacity (error already latched)
       if (kJoint && jfast)
-        joint_member(D, fast ? (int)(F.kb[F.gs[b]] >> 6) : S.jm, nullptr, nullptr, par, nx, jsrc,
-                     jbst, jbrc, jsc, nullptr);
+        joint_member(D, S.jm, nullptr, nullptr, par, nx, jsrc, jbst, jbrc, jsc, nullptr);
       continue;
-    }
-    if (kJoint && jfast && lane == 63 && D.gas_on) {
-      // the massless member's radius and density, for its closing after the
-      // integration (requested with the members' state)
-      const int jj = S.mem[m - 1];
-      if (jj >= nb && jj < n) {
-        jr[0] = gbl(D.r_p)[jj - nb];
-        jr[1] = gbl(D.rho_p)[jj - nb];
-      }
     }
     for (int e = lane; e < nn; e += 64) {
       int k = e / 3, c = e - 3 * (e / 3);
       int body = S.mem[k];
+      if (kJoint && jfast) {  // massive members staged in LDS, the massless one from its record
+        if (body < nb) {
+          xs[e] = jstage[c * nb + body];
+          vs[e] = jstage[(3 + c) * nb + body];
+        }
+        continue;
+      }
       if (kJoint && body < nb) {
         const auto bigpre = gbl(D.bigpre) + (size_t)par * 6 * nb;
         xs[e] = bigpre[c * nb + body];
@@ -1894,8 +2005,13 @@ __device__ __forceinline__ bool bs_body(const SysDesc& D, const int bx, const in
     }
     for (int k = lane; k < m; k += 64) {
       int body = S.mem[k];
-      mum[k] = body < nb ? mu[body] : 0.0;
-      rcm[k] = body < nb ? rcrit[body] : 0.0;
+      if (kJoint && jfast) {
+        mum[k] = body < nb ? jstage[6 * nb + body] : 0.0;
+        rcm[k] = body < nb ? jstage[7 * nb + body] : 0.0;
+      } else {
+        mum[k] = body < nb ? mu[body] : 0.0;
+        rcm[k] = body < nb ? rcrit[body] : 0.0;
+      }
     }
     uint32_t pmask = 0;
     if (m <= 4)
@@ -2086,7 +2202,6 @@ __global__ __launch_bounds__(BLK) void k_step_joint(const SysDesc* __restrict__ 
     }
     return;
   }
-  const int npq = min(*pair_counter(dsc, ph), D.cap_pairs);
   const bool jfast = dsc->bn_valid[ph] != 0;
   const Tile tl = {0, ((int)blockIdx.x - nbs) * BLK};
   const int t = tl.first + tid;
@@ -2143,9 +2258,11 @@ __global__ __launch_bounds__(BLK) void k_step_joint(const SysDesc* __restrict__ 
       Ppost[c] = N->Ppost[c];
     }
     __syncthreads();
-    const auto list = gbl(D.pairs) + (size_t)ph * 2 * D.cap_pairs;
-    for (int e = tid; e < npq; e += BLK) {
-      const int j = list[2 * e + 1] - tl.first;
+    // the bodies with a subsystem record: the integrator closes and opens them
+    const int nrec = min(dsc->n_jsub[ph], D.cap_subs);
+    const JointSub* recs = D.jsub + (size_t)ph * D.cap_subs;
+    for (int e = tid; e < nrec; e += BLK) {
+      const int j = recs[e].j - tl.first;
       if (j >= 0 && j < BLK) atomicOr(&fl[j >> 5], 1u << (j & 31));
     }
     __syncthreads();
@@ -2161,6 +2278,7 @@ __global__ __launch_bounds__(BLK) void k_step_joint(const SysDesc* __restrict__ 
     dsc->n_pairs[r] = 0;
     dsc->plan_ready[r] = 0;
     dsc->bs_done[r] = 0;
+    dsc->n_jsub[r] = 0;
   }
   const bool skip = jfast && ((fl[tid >> 5] >> (tid & 31)) & 1u);
   const bool mine = t < n && !skip;
@@ -2194,7 +2312,7 @@ __global__ __launch_bounds__(BLK) void k_step_joint(const SysDesc* __restrict__ 
       gbl(D.x)[c * n + t] = q[c];
       gbl(D.u)[c * n + t] = w[c];
     }
-    hit = flag_body(D, nx, nx, t, n, nb, h, bst, brc, p, v, q, w);
+    hit = flag_body(D, nx, nx, t, n, nb, h, bst, brc, p, v, q, w, true, rp, rhop);
   }
   if (owner) {
     const bool any_bb = __syncthreads_or(t < nb && hit);

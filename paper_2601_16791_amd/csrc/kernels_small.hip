@@ -138,7 +138,8 @@ __global__ __launch_bounds__(BLK) void k_step_a(const SysDesc* __restrict__ desc
         gbl(D.x)[c * n + t] = q[c];
         gbl(D.u)[c * n + t] = w[c];
       }
-      hit = flag_body(D, par, kJoint ? par : 0, t, n, nb, h, bst, brc, p, v, q, w);
+      hit = flag_body(D, par, kJoint ? par : 0, t, n, nb, h, bst, brc, p, v, q, w, kJoint, rp,
+                      rhop);
     }
     if (kJoint && tl.first == 0) {  // block-uniform: the block of the massive bodies
       const bool any_bb = __syncthreads_or(t < nb && hit);
@@ -240,6 +241,7 @@ __global__ __launch_bounds__(BLK) void k_step_b(const SysDesc* __restrict__ desc
           D.dsc->n_pairs[r] = 0;
           D.dsc->plan_ready[r] = 0;
           D.dsc->bs_done[r] = 0;
+          D.dsc->n_jsub[r] = 0;
         }
       }
     }

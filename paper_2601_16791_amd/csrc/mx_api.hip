@@ -86,6 +86,7 @@ SysDesc make_desc(const mx_system* s) {
   d.bigpre = s->bigpre;
   d.bignext = s->bignext;
   d.pairs = s->pairs;
+  d.jsub = s->jsub;
   d.keys = reinterpret_cast<int64_t*>(s->pairs_tmp);
   d.plan_idx = s->plan_idx;
   d.uf = s->uf;
@@ -122,7 +123,7 @@ void free_system(mx_system* s) {
                   s->growth, s->r_p, s->rho_p, s->bigsnap, s->bigmid, s->bigpre, s->bignext, s->kpack,
                   s->fpack, s->flag_perm, s->flag_bounds, s->part,
                   s->sympart,
-                  s->pairs, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red,
+                  s->pairs, s->jsub, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red,
                   s->desc, s->tiles, s->phys, s->radius, s->rad_c, s->gaps, s->stat,
                   s->rsign, s->ejcount, s->rm_P};
   for (void* p : ptrs)
@@ -337,6 +338,7 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   ALLOC(s->pairs, 6 * (size_t)s->cap_pairs) ALLOC(s->pairs_tmp, 4 * (size_t)s->cap_pairs)
   ALLOC(s->plan_idx, 2 * (size_t)s->cap_pairs)
   ALLOC(s->subs, s->cap_subs) ALLOC(s->uf, 2 * (size_t)nb) ALLOC(s->dsc, 1) ALLOC(s->red, s->red_blocks)
+  ALLOC(s->jsub, nb > 0 && nb <= kSmallBig ? 3 * (size_t)s->cap_subs : 1)
   s->n_tiles = (s->n + kTileBlk - 1) / kTileBlk;
   ALLOC(s->desc, 1) ALLOC(s->tiles, s->n_tiles)
 #undef ALLOC

@@ -75,7 +75,7 @@ struct DevScalars {
   int32_t plan_ready[3];  // set when the in-kernel general plan of the step is written
   int32_t bn_valid[3];    // BigNext[phase] holds the step boundary's massive bodies
   int32_t bs_done[3];     // joint launches: encounter-integrator blocks finished
-  int32_t pad_ph;
+  int32_t n_jsub[3];      // joint launches: subsystem records appended for the step
   double time;           // time at the start of the next step (time-dependent physics)
   int32_t switched;      // the step switch has happened
   int32_t pad_phys;
@@ -153,6 +153,16 @@ struct BigNext {
   double brc[kSmallBig];
 };
 
+// Joint launches: the subsystem of one flagged massless body j, recorded by the
+// launch that flags it (its massive partners as a bit mask, its pre-drift state),
+// so that the encounter integrator of the next launch starts from one record.
+struct JointSub {
+  uint64_t mask;  // massive partners, bit i for massive body i
+  int32_t j, pad;
+  double x[3], v[3];
+  double rp, rhop;  // radius and density of the body (gas drag)
+};
+
 // Device view of one system for the kernels that step one or many systems per
 // launch (fused small-B step, planner, encounter integrator).  All pointers are
 // device pointers into the system's own allocations; the state is SoA [3][n].
@@ -164,6 +174,7 @@ struct SysDesc {
   double* bigpre;                   // [3][6][nb]: pre-drift x, u of the massive bodies (by phase)
   BigNext* bignext;                 // [3] (by step phase)
   int32_t* pairs;                   // [lists][cap_pairs][2]: flagged list (joint launches: by phase)
+  JointSub* jsub;                   // [3][cap_subs] (by step phase), single systems with n_big <= 64
   int64_t* keys;                    // planner scratch [2 * cap_pairs]
   int32_t* plan_idx;                // planner scratch [2 * cap_pairs]
   int32_t* uf;                      // [2 * nb] union-find scratch
@@ -260,6 +271,7 @@ struct mx_system {
   int use_sym;
   // encounters
   int32_t* pairs;      // [3][cap][2] (lists by step phase in joint launches)
+  JointSub* jsub;      // [3][cap_subs] subsystem records of joint launches (0 < n_big <= 64)
   int32_t last_list;   // phase of the list of the last completed step
   int32_t* pairs_tmp;  // [4*cap] int32 = [2*cap] int64 sort keys of the planner
   int32_t* plan_idx;   // [2*cap] index lists of the planner

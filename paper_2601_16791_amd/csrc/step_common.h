@@ -201,13 +201,35 @@ __device__ __forceinline__ void big_boundary(const SysDesc& D, bool latch, doubl
 // with candidates against different massive bodies runs the Hermite test once
 // per round rather than once per body.  Flagged pairs are appended to list lst
 // with the append counter of step phase par; the pre-drift state is stored
-// where the encounter integrator starts from it.  Returns whether the body
-// flagged a pair.
+// where the encounter integrator starts from it.  rec: a flagged massless body
+// also appends its subsystem record for the joint launch (phase par; rp, rhop its
+// radius and density).  Returns whether the body flagged a pair.
+__device__ __forceinline__ void joint_record(const SysDesc& D, int par, int t, uint64_t mask,
+                                             const double (&p)[3], const double (&v)[3], double rp,
+                                             double rhop) {
+  const int idx = atomicAdd(&D.dsc->n_jsub[par], 1);
+  if (idx >= D.cap_subs) {
+    atomicOr(&D.dsc->err, MXE_SUBSYS);
+    return;
+  }
+  JointSub* R = D.jsub + (size_t)par * D.cap_subs + idx;
+  R->mask = mask;
+  R->j = t;
+  R->pad = 0;
+  for (int c = 0; c < 3; ++c) {
+    R->x[c] = p[c];
+    R->v[c] = v[c];
+  }
+  R->rp = rp;
+  R->rhop = rhop;
+}
+
 __device__ __forceinline__ bool flag_body(const SysDesc& D, int par, int lst, int t, int n, int nb,
                                           double h, const double (*bst)[kSmallBig],
                                           const double* brc, const double (&p)[3],
                                           const double (&v)[3], const double (&q)[3],
-                                          const double (&w)[3]) {
+                                          const double (&w)[3], bool rec = false, double rp = 0.0,
+                                          double rhop = 0.0) {
   const double rct = t < nb ? brc[t] : 0.0;
   const int imax = t < nb ? t : nb;
   const double k427 = (4.0 / 27.0) * fabs(h);
@@ -248,6 +270,7 @@ __device__ __forceinline__ bool flag_body(const SysDesc& D, int par, int lst, in
   // the body's pairs are appended together, in increasing i: the list holds each
   // body's partners as one ordered run
   const bool hit = hmask != 0;
+  if (rec && hit && t >= nb) joint_record(D, par, t, hmask, p, v, rp, rhop);
   if (hit) {
     const auto list = gbl(D.pairs) + (size_t)lst * 2 * D.cap_pairs;
     int idx = atomicAdd(pair_counter(D.dsc, par), __popcll(hmask));
