@@ -95,49 +95,85 @@ __device__ __noinline__ void gas_general(const DragConst& c, double X, double Y,
   }
 }
 
-__device__ __forceinline__ void gas_drag(const DragConst& c, double X, double Y, double vx,
-                                         double vy, double vz, double r_p, double rho_p,
-                                         double& ax, double& ay, double& az) {
-  // Written with few divisions (each is a long dependent chain in FP64):
-  // c_s = (H/r) v_k; rho_g = Sigma / (sqrt(2 pi) (H/r) R); Re = 2 r_p dv / nu with
-  // nu = sqrt(8/pi) c_s (mfp / rho_g) / 3, i.e. Re = re_fac r_p dv rho_g / c_s;
-  // 1 / (24/Re + 40/(10 + Re)) = Re (10 + Re) / (240 + 64 Re).
-  ax = ay = az = 0.0;
+// The part of the drag that depends only on the position (X, Y): the disk's
+// surface density, sound speed, gas density and velocity and the disk gravity
+// at R.  A body closed and opened at the same position (the closing kick of one
+// step and the opening kick of the next) can evaluate it once.  on = 0: no gas
+// there (R = 0, inside the inner edge, or Sigma = 0): no drag, no disk gravity.
+// Written with few divisions (each is a long dependent chain in FP64):
+// c_s = (H/r) v_k; rho_g = Sigma / (sqrt(2 pi) (H/r) R).
+struct GasSite {
+  double X, Y, inv_R, cs, rhog, vg, gx, gy;
+  int on;
+};
+
+__device__ __forceinline__ GasSite gas_site(const DragConst& c, double X, double Y) {
+  GasSite g;
+  g.on = 0;
+  g.X = X;
+  g.Y = Y;
+  g.gx = g.gy = 0.0;
   double R2 = X * X + Y * Y;
   double R = sqrt(R2);
-  if (!(R > 0.0) || R < c.r_in) return;
+  if (!(R > 0.0) || R < c.r_in) return g;
   double inv_R = 1.0 / R;
   double vk = sqrt(c.mu0 * inv_R);
   double sig;
   if (c.gamma == 1.0) sig = c.sigma1_unit * inv_R;
   else sig = c.sigma1_unit * pow(R, -c.gamma);
   if (c.r_c > 0.0) sig *= exp(c.rc_norm - pow(R * c.inv_rc, 2.0 - c.gamma));
-  if (!(sig > 0.0)) return;
+  if (!(sig > 0.0)) return g;
   double cs, rhog, vg, gx = 0.0, gy = 0.0;
   if (__builtin_expect(c.ext != 0, 0)) {
     gas_general(c, X, Y, R, inv_R, vk, sig, cs, rhog, vg, gx, gy);
-    ax = gx;
-    ay = gy;
   } else {
     cs = c.h_over_r * vk;
     rhog = sig * inv_R * c.rho_fac;
     vg = vk * c.vg_fac;
   }
-  double dvx = vx + vg * Y * inv_R;
-  double dvy = vy - vg * X * inv_R;
+  g.inv_R = inv_R;
+  g.cs = cs;
+  g.rhog = rhog;
+  g.vg = vg;
+  g.gx = gx;
+  g.gy = gy;
+  g.on = 1;
+  return g;
+}
+
+// Drag (and disk gravity) at site g on a body of radius r_p and density rho_p
+// moving at (vx, vy, vz): Re = 2 r_p dv / nu with nu = sqrt(8/pi) c_s (mfp /
+// rho_g) / 3, i.e. Re = re_fac r_p dv rho_g / c_s;
+// 1 / (24/Re + 40/(10 + Re)) = Re (10 + Re) / (240 + 64 Re).
+__device__ __forceinline__ void gas_drag_at(const DragConst& c, const GasSite& g, double vx,
+                                            double vy, double vz, double r_p, double rho_p,
+                                            double& ax, double& ay, double& az) {
+  ax = ay = az = 0.0;
+  if (!g.on) return;
+  ax = g.gx;
+  ay = g.gy;
+  double dvx = vx + g.vg * g.Y * g.inv_R;
+  double dvy = vy - g.vg * g.X * g.inv_R;
   double dvz = vz;
   double dv = sqrt(dvx * dvx + dvy * dvy + dvz * dvz);
   if (!(dv > 0.0)) return;
-  double inv_cs = 1.0 / cs;
+  double inv_cs = 1.0 / g.cs;
   double ma = dv * inv_cs;
-  double re = c.re_fac * r_p * dv * rhog * inv_cs;
+  double re = c.re_fac * r_p * dv * g.rhog * inv_cs;
   double k = re < 1.0e5 ? 0.4 : 0.2;
   double inner = re * (10.0 + re) / fma(64.0, re, 240.0) + 0.23 * ma;
   double cd = pow_kexp(inner, c.kexp) + 2.0 * (0.8 * k + ma) / (1.6 + ma);
-  double f = -0.375 * cd * rhog * dv / (r_p * rho_p);
-  ax = fma(f, dvx, gx);
-  ay = fma(f, dvy, gy);
+  double f = -0.375 * cd * g.rhog * dv / (r_p * rho_p);
+  ax = fma(f, dvx, g.gx);
+  ay = fma(f, dvy, g.gy);
   az = f * dvz;
+}
+
+__device__ __forceinline__ void gas_drag(const DragConst& c, double X, double Y, double vx,
+                                         double vy, double vz, double r_p, double rho_p,
+                                         double& ax, double& ay, double& az) {
+  const GasSite g = gas_site(c, X, Y);
+  gas_drag_at(c, g, vx, vy, vz, r_p, rho_p, ax, ay, az);
 }
 
 // ------------------------------------------------------------ Kepler drift

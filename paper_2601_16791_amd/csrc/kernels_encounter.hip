@@ -1487,8 +1487,10 @@ __device__ __forceinline__ void joint_member(const SysDesc& D, int j, const doub
   }
   const double rp = !D.gas_on ? 0.0 : jr ? jr[0] : gbl(D.r_p)[j - nb];
   const double rhop = !D.gas_on ? 0.0 : jr ? jr[1] : gbl(D.rho_p)[j - nb];
-  // step q closed: jump, gravity, drag, half kick
+  // step q closed: jump, gravity, drag, half kick (the gas where the body is
+  // closed is also where it is opened)
   const double px = p[0] + J[0], py = p[1] + J[1], pz = p[2] + J[2];
+  mxd::GasSite site;
   {
     const double rc2t = rct * rct;
     double k15, k1875;
@@ -1512,9 +1514,11 @@ __device__ __forceinline__ void joint_member(const SysDesc& D, int j, const doub
       a2 = fma(ws, __shfl(dz, s), a2);
     }
     double adx = 0.0, ady = 0.0, adz = 0.0;
-    if (D.gas_on)
-      mxd::gas_drag(D.dc, px, py, v[0] + vpre[0], v[1] + vpre[1], v[2] + vpre[2], rp, rhop, adx,
-                    ady, adz);
+    if (D.gas_on) {
+      site = mxd::gas_site(D.dc, px, py);
+      mxd::gas_drag_at(D.dc, site, v[0] + vpre[0], v[1] + vpre[1], v[2] + vpre[2], rp, rhop, adx,
+                       ady, adz);
+    }
     v[0] += hh * (a0 + adx);
     v[1] += hh * (a1 + ady);
     v[2] += hh * (a2 + adz);
@@ -1528,7 +1532,7 @@ __device__ __forceinline__ void joint_member(const SysDesc& D, int j, const doub
   const bool fin = isfinite(v[0] + v[1] + v[2] + p[0] + p[1] + p[2]);
   // step q + 1 opened: drag, half kick, jump, drift
   const bool conv = mxs::advance_body(j, nb, mu0, h, D.dc, D.gas_on, rp, rhop, Ppre, Ppost, p, v,
-                                      a, q, w);
+                                      a, q, w, &site);
   // encounter test of step q + 1 against massive body `lane`
   bool hit = false;
   if (lane < nb) {
@@ -1633,7 +1637,7 @@ __device__ __forceinline__ bool bs_body(const SysDesc& D, const int bx, const in
   DevScalars* __restrict__ dsc = D.dsc;
   const auto bigmid = gbl(D.bigmid) + (size_t)par * 6 * nb;
   if (nb == 0) return false;
-  // joint launches: whether the boundary was prepared (requested with the list)
+  // joint launches: whether the boundary was prepared
   const bool jfast = kJoint && dsc->bn_valid[par] != 0;
   __shared__ Subsystem S;
   __shared__ double xs[3 * kM], vs[3 * kM], mum[kM], rcm[kM], scal[2 * kM];
@@ -1664,20 +1668,19 @@ __device__ __forceinline__ bool bs_body(const SysDesc& D, const int bx, const in
   uint64_t r0mask = 0;
   int r0j = 0;
   double r0x[3] = {0.0, 0.0, 0.0}, r0v[3] = {0.0, 0.0, 0.0}, r0rp = 0.0, r0rh = 0.0;
-  if (!plan) {
-    nsub = dsc->n_sub;
-  } else if (kJoint && jfast) {
-    // one subsystem per record appended by the launch that flagged the step's
-    // pairs (the massless body, its massive partners, its pre-drift state); the
-    // subsystem table is not written (only the adjoint reads it, and it never
-    // runs joint launches).  Requested at once: the counts, the block's first
-    // record (read before its count is known; used only if it exists), the
-    // massive bodies' state, masses and radii, and the prepared boundary.
+  // joint launches: requested at once, before the mode is known (every address is
+  // valid either way): the counts, the block's first record (used only if it
+  // exists), the massive bodies' state, masses and radii, and the prepared
+  // boundary
+  int nrec = 0, n_pairs = 0;
+  double sv[kJoint ? 6 : 1], bsrc[kJoint ? 8 : 1], bbst[kJoint ? 12 : 1];
+  double muv = 0.0, rcv = 0.0, bbrc = 0.0, bsc = 0.0;
+  if constexpr (kJoint) {
     const BigNext* N = D.bignext + par;
     const auto bpre = gbl(D.bigpre) + (size_t)par * 6 * nb;
     const JointSub* R0 = D.jsub + (size_t)par * D.cap_subs + bx;
-    const int nrec = dsc->n_jsub[par];
-    const int n_pairs = *pair_counter(dsc, par);
+    nrec = dsc->n_jsub[par];
+    n_pairs = *pair_counter(dsc, par);
     r0mask = R0->mask;
     r0j = R0->j;
     for (int c = 0; c < 3; ++c) {
@@ -1686,13 +1689,13 @@ __device__ __forceinline__ bool bs_body(const SysDesc& D, const int bx, const in
     }
     r0rp = R0->rp;
     r0rh = R0->rhop;
-    double sv[6], bsrc[8], bbst[12];
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
       const int e = lane + 64 * r;
       sv[r] = e < 6 * nb ? bpre[e] : 0.0;
     }
-    const double muv = lane < nb ? mu[lane] : 0.0, rcv = lane < nb ? rcrit[lane] : 0.0;
+    muv = lane < nb ? mu[lane] : 0.0;
+    rcv = lane < nb ? rcrit[lane] : 0.0;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const int e = lane + 64 * r;
@@ -1700,8 +1703,16 @@ __device__ __forceinline__ bool bs_body(const SysDesc& D, const int bx, const in
     }
 #pragma unroll
     for (int r = 0; r < 12; ++r) bbst[r] = lane < nb ? N->bst[r][lane] : 0.0;
-    const double bbrc = lane < nb ? N->brc[lane] : 0.0;
-    const double bsc = lane < 12 ? reinterpret_cast<const double*>(N)[3 + lane] : 0.0;
+    bbrc = lane < nb ? N->brc[lane] : 0.0;
+    bsc = lane < 12 ? reinterpret_cast<const double*>(N)[3 + lane] : 0.0;
+  }
+  if (!plan) {
+    nsub = dsc->n_sub;
+  } else if (kJoint && jfast) {
+    // one subsystem per record appended by the launch that flagged the step's
+    // pairs (the massless body, its massive partners, its pre-drift state); the
+    // subsystem table is not written (only the adjoint reads it, and it never
+    // runs joint launches)
     nsub = min(nrec, D.cap_subs);
     if (bx == 0 && lane == 0) {
       dsc->n_pairs_last = n_pairs;

@@ -15,20 +15,27 @@ using mxd::DragConst;
 
 // half kick (with drag for massless bodies, in the frame shifted by Ppre/mu0),
 // jump by Ppost/mu0, Kepler drift.  On entry (p, v, a) is the step-start state;
-// on exit (p, v) is the pre-drift state and (q, w) the post-drift state.
+// on exit (p, v) is the pre-drift state and (q, w) the post-drift state.  site:
+// the gas at p when already evaluated, else null.
 __device__ __forceinline__ bool advance_body(int t, int nb, double mu0, double h,
                                              const DragConst& dc, int gas_on, double rp,
                                              double rhop, const double* vpre,
                                              const double* jpost, double (&p)[3], double (&v)[3],
                                              const double (&a)[3], double (&q)[3],
-                                             double (&w)[3]) {
+                                             double (&w)[3],
+                                             const mxd::GasSite* site = nullptr) {
   // vpre = Ppre / mu0 (frame velocity of the drag), jpost = (h/2) Ppost / mu0 (jump);
   // rp, rhop: radius and density of a massless body (unused for massive ones)
   const double hh = 0.5 * h;
   double ad[3] = {0.0, 0.0, 0.0};
-  if (t >= nb && gas_on)
-    mxd::gas_drag(dc, p[0], p[1], v[0] + vpre[0], v[1] + vpre[1], v[2] + vpre[2], rp, rhop,
-                  ad[0], ad[1], ad[2]);
+  if (t >= nb && gas_on) {
+    if (site)
+      mxd::gas_drag_at(dc, *site, v[0] + vpre[0], v[1] + vpre[1], v[2] + vpre[2], rp, rhop,
+                       ad[0], ad[1], ad[2]);
+    else
+      mxd::gas_drag(dc, p[0], p[1], v[0] + vpre[0], v[1] + vpre[1], v[2] + vpre[2], rp, rhop,
+                    ad[0], ad[1], ad[2]);
+  }
   for (int c = 0; c < 3; ++c) {
     v[c] += hh * (a[c] + ad[c]);
     p[c] += jpost[c];
