@@ -2285,6 +2285,8 @@ __global__ __launch_bounds__(BLK) void k_step_joint(const SysDesc* __restrict__ 
     dsc->P[1] = P[1];
     dsc->P[2] = P[2];
     dsc->step += 1;
+    dsc->joint_runs += 1;
+    if (!jfast) dsc->joint_slow += 1;
     const int r = nx == 2 ? 0 : nx + 1;  // step q - 1: nothing in this launch reads its copies
     dsc->n_pairs[r] = 0;
     dsc->plan_ready[r] = 0;

@@ -182,7 +182,8 @@ bool joinable(const mx_system* s, int32_t n) {
 // closing of that step and the opening of the next (k_step_joint), the last
 // step's encounters and closing as usual
 bool joint_ok(const mx_system* s, int32_t n) {
-  return joinable(s, n) && s->nb > 0 && s->n < (1 << 26) && !s->no_joint;
+  return joinable(s, n) && s->nb > 0 && s->n < (1 << 26) && !s->no_joint &&
+         (!s->joint_off || s->host_step >= s->joint_retry_at);
 }
 
 // n >= 2 steps as a joint sequence; visit/after as for enqueue_steps, the joint
@@ -243,10 +244,29 @@ hipError_t refresh_accel(mx_system* s) {
   return mxk::launch_force_kick(s, 0);
 }
 
+// Joint launches whose tiles had to wait for the integrator (a pair of massive
+// bodies in an encounter) take longer than two launches; when more than a fifth
+// of the last 32 or more did, joint launches stop for the next 4,096 steps (both
+// forms compute the same bits).
+constexpr int kJointWindow = 32;
+constexpr int64_t kJointPause = 4096;
+
 mx_status read_err(mx_system* s) {
-  int32_t err = 0;
   HIPCHK(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-  HIPCHK(hipMemcpy(&err, &s->dsc->err, sizeof(int32_t), hipMemcpyDeviceToHost), "read err");
+  DevScalars d;
+  HIPCHK(hipMemcpy(&d, s->dsc, sizeof(DevScalars), hipMemcpyDeviceToHost), "read scalars");
+  const int32_t err = d.err;
+  if (d.joint_runs >= kJointWindow) {
+    if (d.joint_slow * 5 > d.joint_runs) {
+      s->joint_off = true;
+      s->joint_retry_at = s->host_step + kJointPause;
+    } else {
+      s->joint_off = false;
+    }
+    int32_t zero2[2] = {0, 0};
+    HIPCHK(hipMemcpy(&s->dsc->joint_runs, zero2, sizeof(zero2), hipMemcpyHostToDevice),
+           "clear joint counts");
+  }
   if (err) {
     int32_t zero = 0;
     HIPCHK(hipMemcpy(&s->dsc->err, &zero, sizeof(int32_t), hipMemcpyHostToDevice), "clear err");

@@ -79,6 +79,8 @@ struct DevScalars {
   double time;           // time at the start of the next step (time-dependent physics)
   int32_t switched;      // the step switch has happened
   int32_t pad_phys;
+  int32_t joint_runs;    // joint launches since the host last looked
+  int32_t joint_slow;    // of which the tiles waited for the integrator
 };
 
 // Append counter of the flagged list for step phase w (0 outside joined launches).
@@ -287,6 +289,11 @@ struct mx_system {
   hipGraphExec_t graph;
   bool graph_ok;
   bool no_joint;  // steps of a call are never joint (the adjoint records per-step tapes)
+  // joint launches switched off for a while: in a system whose massive bodies
+  // meet often, the tiles wait for the integrator in most steps and two launches
+  // per step are faster
+  bool joint_off;
+  int64_t joint_retry_at;  // host step from which joint launches are tried again
   int launch_mode;  // MX_LAUNCH_EAGER or MX_LAUNCH_GRAPH
   LaunchTiming tev;
   hipEvent_t* tev_pool;  // events of mx_step_timed, kept between calls

@@ -453,6 +453,47 @@ def test_joint_launches_equal_single_steps(mx, case):
         assert a.counters()[1] > 256 * n // 2
 
 
+def _bound_pair_disk(n_small=3000):
+    """An embryo disk whose first two embryos form a bound pair well inside each
+    other's changeover radius: an encounter between massive bodies in every step."""
+    w = ic.embryo_disk(seed=3, n_small=n_small, n_emb=6)
+    m = w.m_big
+    x = w.x.copy()
+    v = w.v.copy()
+    rH = np.linalg.norm(x[:, 0]) * (m[0] / 3) ** (1 / 3)
+    d = 0.3 * rH
+    x[:, 1] = x[:, 0] + np.array([d, 0.0, 0.0])
+    v[:, 1] = v[:, 0] + np.array([0.0, math.sqrt(G * (m[0] + m[1]) / d), 0.0])
+    w.x, w.v = x, v
+    return w
+
+
+def test_joint_launches_pause_with_frequent_massive_pairs(mx):
+    """Where massive bodies meet in most steps the joint launch waits for its
+    integrator and is slower than two launches: after a synchronisation that sees
+    more than a fifth of 32 or more joint launches wait, calls step with separate
+    launches (same bits).  A fresh system starts with joint launches."""
+    w = _bound_pair_disk()
+    a = mx.System.from_workload(w)
+    b = mx.System.from_workload(w)
+    c = mx.System.from_workload(w)
+    ms, nl = c.step_timed(6, "step_joint")
+    assert nl == 5
+    a.step(40)
+    a.sync()
+    ms, nl = a.step_timed(6, "step_joint")
+    assert nl == 0
+    a.step(10)
+    for _ in range(56):
+        b.step(1)
+    e = b.encounters()
+    assert len(e) and np.any(e[:, 1] < w.params["n_big"])
+    xa, ua = a.get_dh()
+    xb, ub = b.get_dh()
+    assert np.array_equal(xa, xb) and np.array_equal(ua, ub)
+    assert a.step_index() == b.step_index() == 56
+
+
 def test_joint_launch_timing(mx):
     """The joint-launch timing group times the launches of the sequence mx_step
     runs (one per step but the last); the states equal plain eager steps."""
