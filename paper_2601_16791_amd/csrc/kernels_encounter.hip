@@ -2166,11 +2166,12 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
                  nullptr, nullptr, nullptr, nullptr);
 }
 
-// One launch per step of a joint sequence (a single system with n_big <= 64 and
-// no core growth): blocks 0 .. nbs - 1 run the encounter integrator of step q
-// (phase ph) on their first wave, the following blocks (one BLK-body tile each)
-// close step q and open step q + 1 (phase nx) for their bodies with exactly the
-// joined step kernel's operations.  The integrator's registers set the launch
+// One launch per step of a joint sequence (systems with 0 < n_big <= 64 and no
+// core growth: a single system, or every member of a batch): blocks 0 ..
+// nbs * n_sys - 1 run the encounter integrator of step q (phase ph; nbs one-wave
+// blocks per system, system-major), the following blocks (one BLK-body tile of
+// the tile table each) close step q and open step q + 1 (phase nx) for their
+// bodies with exactly the joined step kernel's operations.  The integrator's registers set the launch
 // to one wave per SIMD; with one-wave blocks an integrator block holds one SIMD
 // of a CU, not the whole CU, while it runs.  The two parts depend on each other only
 // through the bodies the integrator moves, and the launch that opened step q
@@ -2188,10 +2189,14 @@ __global__ __launch_bounds__(64) void k_bs(const SysDesc* __restrict__ desc, int
 // x0, u0), and the tile of the massive bodies clears the copies of step q - 1 and
 // prepares the next boundary.
 template <int BLK>
-__global__ __launch_bounds__(BLK) void k_step_joint(const SysDesc* __restrict__ desc, int nbs,
-                                                    int ph) {
+__global__ __launch_bounds__(BLK) void k_step_joint(const SysDesc* __restrict__ desc,
+                                                    const Tile* __restrict__ tiles, int nbs,
+                                                    int n_sys, int ph) {
   using namespace mxs;
-  const SysDesc& D = desc[0];
+  const int nbs_all = nbs * n_sys;
+  const Tile tl = (int)blockIdx.x < nbs_all ? Tile{(int)blockIdx.x / nbs, 0}
+                                            : tiles[blockIdx.x - nbs_all];
+  const SysDesc& D = desc[tl.sys];
   __shared__ double sh[8];
   __shared__ KickSource src[kSmallBig];
   __shared__ double bst[12][kSmallBig];
@@ -2203,9 +2208,10 @@ __global__ __launch_bounds__(BLK) void k_step_joint(const SysDesc* __restrict__ 
   const int n = D.n, nb = D.nb;
   const double h = D.h, hh = 0.5 * D.h, mu0 = D.mu0;
   DevScalars* __restrict__ dsc = D.dsc;
-  if ((int)blockIdx.x < nbs) {
+  if ((int)blockIdx.x < nbs_all) {
     if (tid >= 64) return;  // one wave per integrator block
-    const bool jfast = bs_body<true>(D, blockIdx.x, nbs, 1, ph, nx, ph, -1, src, bst, brc, jsc, jr);
+    const bool jfast =
+        bs_body<true>(D, (int)blockIdx.x % nbs, nbs, 1, ph, nx, ph, -1, src, bst, brc, jsc, jr);
     if (!jfast) {
       __syncthreads();  // the wave's stores precede the release
       if (tid == 0)
@@ -2214,7 +2220,6 @@ __global__ __launch_bounds__(BLK) void k_step_joint(const SysDesc* __restrict__ 
     return;
   }
   const bool jfast = dsc->bn_valid[ph] != 0;
-  const Tile tl = {0, ((int)blockIdx.x - nbs) * BLK};
   const int t = tl.first + tid;
   const bool owner = tl.first == 0;  // block-uniform: the tile of the massive bodies
   if (!jfast) {
@@ -2373,12 +2378,11 @@ hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, 
   return mxlaunch_on(st, tm, k_bs, dim3(bps, n_sys), dim3(64), desc, plan, par, lst, clr);
 }
 
-hipError_t launch_step_joint(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n,
-                             int nbs, int ph) {
-  constexpr int kBlk = 64;  // bodies per tile block
-  if (n <= 0 || nbs <= 0 || ph < 0 || ph > 2) return hipErrorInvalidValue;
-  const int n_tiles = (n + kBlk - 1) / kBlk;
-  return mxlaunch_on(st, tm, k_step_joint<kBlk>, dim3(nbs + n_tiles), dim3(kBlk), desc, nbs, ph);
+hipError_t launch_step_joint(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
+                             const Tile* tiles64, int n_tiles64, int nbs, int n_sys, int ph) {
+  if (n_tiles64 <= 0 || nbs <= 0 || n_sys <= 0 || ph < 0 || ph > 2) return hipErrorInvalidValue;
+  return mxlaunch_on(st, tm, k_step_joint<64>, dim3(nbs * n_sys + n_tiles64), dim3(64), desc,
+                     tiles64, nbs, n_sys, ph);
 }
 
 // flag + sort for the stateless entry; fpack built from the given states

@@ -123,7 +123,7 @@ void free_system(mx_system* s) {
                   s->growth, s->r_p, s->rho_p, s->bigsnap, s->bigmid, s->bigpre, s->bignext, s->kpack,
                   s->fpack, s->flag_perm, s->flag_bounds, s->part,
                   s->sympart,
-                  s->pairs, s->jsub, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red,
+                  s->pairs, s->jsub, s->tiles64, s->pairs_tmp, s->plan_idx, s->subs, s->uf, s->dsc, s->red,
                   s->desc, s->tiles, s->phys, s->radius, s->rad_c, s->gaps, s->stat,
                   s->rsign, s->ejcount, s->rm_P};
   for (void* p : ptrs)
@@ -160,6 +160,7 @@ hipError_t launch_group(mx_system* s, int k, int par = 0) {
 }
 
 hipError_t enqueue_step(mx_system* s) {
+  s->last_list = 0;
   for (int k = 0; k < MX_NUM_KERNELS; ++k) {
     hipError_t e = launch_group(s, k);
     if (e != hipSuccess) return e;
@@ -198,7 +199,8 @@ hipError_t enqueue_joint(mx_system* s, int32_t n, Visit visit, After after) {
   if (e != hipSuccess) return e;
   for (int32_t q = 0; q < n - 1; ++q) {
     visit(MX_K_STEP_JOINT, q);
-    e = mxk::launch_step_joint(s->stream, &s->tev, s->desc, s->n, kJointBs, q % 3);
+    e = mxk::launch_step_joint(s->stream, &s->tev, s->desc, s->tiles64, s->n_tiles64, kJointBs, 1,
+                               q % 3);
     after(MX_K_STEP_JOINT, q);
     if (e != hipSuccess) return e;
   }
@@ -360,7 +362,9 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
   ALLOC(s->subs, s->cap_subs) ALLOC(s->uf, 2 * (size_t)nb) ALLOC(s->dsc, 1) ALLOC(s->red, s->red_blocks)
   ALLOC(s->jsub, nb > 0 && nb <= kSmallBig ? 3 * (size_t)s->cap_subs : 1)
   s->n_tiles = (s->n + kTileBlk - 1) / kTileBlk;
+  s->n_tiles64 = (s->n + 63) / 64;
   ALLOC(s->desc, 1) ALLOC(s->tiles, s->n_tiles)
+  ALLOC(s->tiles64, nb > 0 && nb <= kSmallBig ? s->n_tiles64 : 1)
 #undef ALLOC
   if (e != hipSuccess) {
     free_system(s);
@@ -385,6 +389,12 @@ mx_status mx_init_system(const mx_params* p, const double* x_h, const double* v_
     STEP(hipMemcpy(s->desc, &d, sizeof(SysDesc), hipMemcpyHostToDevice), "copy descriptor");
     STEP(hipMemcpy(s->tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice),
          "copy tiles");
+    if (nb > 0 && nb <= kSmallBig) {
+      std::vector<Tile> t64;
+      append_tiles(t64, 0, s->n, 64);
+      STEP(hipMemcpy(s->tiles64, t64.data(), sizeof(Tile) * t64.size(), hipMemcpyHostToDevice),
+           "copy tiles");
+    }
   }
   STEP(dalloc(&vh_tmp, n3), "alloc v_h");
   STEP(hipMemsetAsync(s->dsc, 0, sizeof(DevScalars), sm), "memset");
@@ -463,6 +473,7 @@ mx_status mx_step(mx_system* s, int32_t n_steps) {
     s->graph_ok = true;
   }
   if (use_graph) {
+    s->last_list = 0;  // one step per graph
     for (int32_t k = 0; k < n_steps; ++k)
       HIPCHK(hipGraphLaunch(s->graph, s->stream), "graph launch");
   } else if (joint_ok(s, n_steps)) {
@@ -490,6 +501,7 @@ mx_status mx_step_profiled(mx_system* s, int32_t n_steps, double* kernel_ms) {
   for (int k = 0; k <= K; ++k) HIPCHK(hipEventCreate(&ev[k]), "event create");
   for (int k = 0; k < K; ++k) kernel_ms[k] = 0.0;
   hipError_t e = hipSuccess;
+  s->last_list = 0;
   for (int32_t q = 0; q < n_steps && e == hipSuccess; ++q) {
     e = hipEventRecord(ev[0], s->stream);
     for (int k = 0; k < K && e == hipSuccess; ++k) {
@@ -851,6 +863,13 @@ mx_status mx_compact(mx_system* s, int32_t* n_removed, int32_t* index_map) {
   SysDesc d = make_desc(s);
   HIPCHK(hipMemcpy(s->desc, &d, sizeof(SysDesc), hipMemcpyHostToDevice), "descriptor");
   HIPCHK(hipMemcpy(s->tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice), "tiles");
+  if (s->nb > 0 && s->nb <= kSmallBig) {
+    std::vector<Tile> t64;
+    append_tiles(t64, 0, s->n, 64);
+    s->n_tiles64 = (int32_t)t64.size();
+    HIPCHK(hipMemcpy(s->tiles64, t64.data(), sizeof(Tile) * t64.size(), hipMemcpyHostToDevice),
+           "tiles");
+  }
   std::vector<int32_t> st(s->nb > 0 ? s->nb : 1);
   int32_t flagged = 0;
   if (s->nb > 0) {
@@ -1068,6 +1087,10 @@ hipError_t upload_tiles(mx_batch* b) {
 // (k_step_ba), the same operations per body
 hipError_t enqueue_batch_steps(mx_batch* b, int32_t n) {
   hipError_t e = hipSuccess;
+  // (joint launches, the integrator beside the tiles, measured slower here: the
+  // integrator's registers and LDS hold the ensemble's many tiles to one wave per
+  // SIMD)
+  for (int k = 0; k < b->n_sys; ++k) b->sys[k]->last_list = 0;
   for (int32_t q = 0; q < n && e == hipSuccess; ++q) {
     const int par = q & 1;  // step parity (buffers alternate between joined steps)
     if (q == 0)
@@ -1215,6 +1238,7 @@ mx_status mx_init_batch(int32_t n_sys, const mx_params* params, const int64_t* o
     e = hipMemcpy(b->desc, d.data(), sizeof(SysDesc) * n_sys, hipMemcpyHostToDevice);
   b->tiles_cap = (int32_t)max_tiles;
   if (e == hipSuccess) e = upload_tiles(b);
+
   if (e != hipSuccess) {
     free_batch(b);
     return hip_fail(e, "batch tables");
@@ -1277,6 +1301,7 @@ mx_status mx_step_batch(mx_batch* b, int32_t n_steps) {
     }
     for (; done + b->graph_steps <= n_steps; done += b->graph_steps)
       HIPCHK(hipGraphLaunch(b->graph, b->stream), "graph launch");
+    for (int k = 0; k < b->n_sys; ++k) b->sys[k]->last_list = 0;
   }
   if (done < n_steps) HIPCHK(enqueue_batch_steps(b, n_steps - done), "batch step launch");
   advance_host_steps(b, n_steps);

@@ -273,6 +273,8 @@ struct mx_system {
   int use_sym;
   // encounters
   int32_t* pairs;      // [3][cap][2] (lists by step phase in joint launches)
+  Tile* tiles64;       // 64-body tiles of the joint launch
+  int32_t n_tiles64;
   JointSub* jsub;      // [3][cap_subs] subsystem records of joint launches (0 < n_big <= 64)
   int32_t last_list;   // phase of the list of the last completed step
   int32_t* pairs_tmp;  // [4*cap] int32 = [2*cap] int64 sort keys of the planner
@@ -363,10 +365,10 @@ hipError_t launch_step_ba_tiles(hipStream_t st, LaunchTiming* tm, const SysDesc*
 // plan != 0: the integrator plans its subsystems itself, systems of n_big <= 64)
 hipError_t launch_bs_sys(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n_sys,
                          int bps, int plan, int par, int lst, int clr);
-// encounter integrator of step q (phase ph, nbs one-wave blocks) beside the
-// closing of step q and the opening of step q + 1 for a single system of n bodies
-hipError_t launch_step_joint(hipStream_t st, LaunchTiming* tm, const SysDesc* desc, int n,
-                             int nbs, int ph);
+// encounter integrator of step q (phase ph, nbs one-wave blocks per system) beside
+// the closing of step q and the opening of step q + 1 over a table of 64-body tiles
+hipError_t launch_step_joint(hipStream_t st, LaunchTiming* tm, const SysDesc* desc,
+                             const Tile* tiles64, int n_tiles64, int nbs, int n_sys, int ph);
 
 // stateless single-kernel launchers
 hipError_t gravity(int n, int nb, const double* x, const double* mu, const double* rcrit,
