@@ -305,7 +305,11 @@ def batch_leg(args):
     bodies = sum(w.n for w in ws)
     b = mx.Batch.from_workloads(ws)
     del ws
-    taken, cfg, best_ms = b.autotune(steps_per_candidate=5)
+    # the encounters of the first steps from the initial state are not yet those of
+    # the run: the autotuner runs after 200 steps
+    b.step(200)
+    b.sync()
+    taken, cfg, best_ms = b.autotune(steps_per_candidate=10)
     b.step(args.warmup)
     b.sync()
     t0 = time.perf_counter()

@@ -298,12 +298,14 @@ mx_status mx_batch_set_config(mx_batch* b, int32_t blk, int32_t tiles_per_block,
                               int32_t bs_blocks);
 mx_status mx_batch_get_config(mx_batch* b, int32_t* cfg);
 
-/* Autotuner: times real steps of the batch (steps_per_candidate per candidate;
- * every candidate gives the same results) over the tile shapes, then over the
- * encounter-integrator widths 8..64 (each tried twice, in mirrored order, and
- * judged by the sum), and keeps the fastest.  *steps_taken (host) is the
- * number of steps it advanced; cfg_out (host [3]) the chosen triple; *best_ms the
- * best time per step.  Synchronises and reports device failures. */
+/* Autotuner: runs real steps of the batch (steps_per_candidate per candidate;
+ * every candidate gives the same results) with HIP events around each step's
+ * kernels: the tile shapes are judged by the time of the body kernels, then the
+ * encounter-integrator widths 8..64 by the integrator's time (each width tried
+ * twice, in mirrored order, and judged by the sum), and the fastest of each is
+ * kept.  *steps_taken (host) is the number of steps it advanced; cfg_out (host
+ * [3]) the chosen triple; *best_ms the kernel time per step of the choice.
+ * Synchronises and reports device failures. */
 mx_status mx_batch_autotune(mx_batch* b, int32_t steps_per_candidate, int32_t* steps_taken,
                             int32_t* cfg_out, float* best_ms);
 

@@ -1642,20 +1642,30 @@ __device__ __forceinline__ bool bs_body(const SysDesc& D, const int bx, const in
   __shared__ Subsystem S;
   __shared__ double xs[3 * kM], vs[3 * kM], mum[kM], rcm[kM], scal[2 * kM];
   // the tables of larger subsystems and the speculative rounds of subsystems of
-  // at most four members (never both for one subsystem) share their LDS
+  // at most four members (never both for one subsystem), the general planner's
+  // scan (before any integration) and the boundary a block without subsystems
+  // prepares share their LDS
   union BsTables {
     struct {
       double res[kC][6 * kM];
       double wk[kC][3][3 * kM];
     } big;
     double resS[8][kC][6 * 4];
+    int scan[64];
+    struct {
+      double sh[8];
+      KickSource src[kSmallBig];
+      double bst[12][kSmallBig];
+      double brc[kSmallBig];
+    } prep;
   };
   __shared__ BsTables U;
   auto& res = U.big.res;
   auto& wk = U.big.wk;
   auto& resS = U.resS;
   __shared__ FastPlan F;
-  __shared__ int s_scan[64], s_nbig, s_nsub;
+  __shared__ int s_nbig, s_nsub;
+  int* s_scan = U.scan;
   // joint launches: the massive bodies' pre-drift state [6][nb], masses [nb] and
   // changeover radii [nb]
   __shared__ double jstage[kJoint ? 8 * kSmallBig : 1];
@@ -1888,10 +1898,10 @@ __device__ __forceinline__ bool bs_body(const SysDesc& D, const int bx, const in
   if constexpr (!kJoint) {
   if (plan && bx == nbx - 1) {
     if (!bigs_kept && nsub < nbx && nb <= kSmallBig) {
-      __shared__ double b_sh[8];
-      __shared__ KickSource b_src[kSmallBig];
-      __shared__ double b_bst[12][kSmallBig];
-      __shared__ double b_brc[kSmallBig];
+      double* b_sh = U.prep.sh;
+      KickSource* b_src = U.prep.src;
+      auto& b_bst = U.prep.bst;
+      double* b_brc = U.prep.brc;
       double bpos[3], bvel[3], bm = 0.0, brc_t = 0.0, P[3], J[3], vpre[3], Ppre[3], Ppost[3];
       if (lane < nb) {
         for (int c = 0; c < 3; ++c) {

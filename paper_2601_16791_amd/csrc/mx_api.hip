@@ -1313,43 +1313,74 @@ mx_status mx_batch_autotune(mx_batch* b, int32_t steps_per_candidate, int32_t* s
   if (!b || steps_per_candidate < 1 || !steps_taken || !cfg_out || !best_ms)
     return fail(MX_EINVAL, "bad argument");
   *steps_taken = 0;
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0), "event");
-  HIPCHK(hipEventCreate(&e1), "event");
+  hipEvent_t ev[4];
+  for (int k = 0; k < 4; ++k) HIPCHK(hipEventCreate(&ev[k]), "event");
   const int saved_mode = b->launch_mode;
   b->launch_mode = MX_LAUNCH_EAGER;
   int32_t taken = 0;
-  // time `steps_per_candidate` real steps of the batch under one configuration
-  auto trial = [&](int blk, int tpb, int bps, float* ms) -> mx_status {
+  // `steps_per_candidate` real steps of the batch under one configuration, with
+  // events around the body kernels (the tile shape's) and around the encounter
+  // integrator (its width's) of every step: each knob is judged by the kernels
+  // it shapes, so the encounters of the moment, which set the integrator's time,
+  // do not decide the tile shape
+  auto trial = [&](int blk, int tpb, int bps, float* body_ms, float* bs_ms) -> mx_status {
     mx_status st = mx_batch_set_config(b, blk, tpb, bps);
     if (st != MX_OK) return st;
-    HIPCHK(hipEventRecord(e0, b->stream), "record");
-    HIPCHK(enqueue_batch_steps(b, steps_per_candidate), "trial step");
-    HIPCHK(hipEventRecord(e1, b->stream), "record");
-    HIPCHK(hipEventSynchronize(e1), "sync");
-    HIPCHK(hipEventElapsedTime(ms, e0, e1), "elapsed");
-    advance_host_steps(b, steps_per_candidate);
-    taken += steps_per_candidate;
+    float tb = 0.f, ts = 0.f;
+    const int n = steps_per_candidate;
+    for (int q = 0; q < n; ++q) {
+      const int par = q & 1;
+      float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+      HIPCHK(hipEventRecord(ev[0], b->stream), "record");
+      if (q == 0)
+        HIPCHK(mxk::launch_step_a_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles,
+                                        b->blk, b->tpb, 0),
+               "trial step");
+      HIPCHK(hipEventRecord(ev[1], b->stream), "record");
+      HIPCHK(mxk::launch_bs_sys(b->stream, &b->tev, b->desc, b->n_sys, b->bps, 1, par, 0, par ^ 1),
+             "trial step");
+      HIPCHK(hipEventRecord(ev[2], b->stream), "record");
+      if (q < n - 1)
+        HIPCHK(mxk::launch_step_ba_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles,
+                                         b->blk, b->tpb, par),
+               "trial step");
+      else
+        HIPCHK(mxk::launch_step_b_tiles(b->stream, &b->tev, b->desc, b->tiles, b->n_tiles,
+                                        b->blk, b->tpb, 1, par),
+               "trial step");
+      HIPCHK(hipEventRecord(ev[3], b->stream), "record");
+      HIPCHK(hipEventSynchronize(ev[3]), "sync");
+      HIPCHK(hipEventElapsedTime(&m0, ev[0], ev[1]), "elapsed");
+      HIPCHK(hipEventElapsedTime(&m1, ev[1], ev[2]), "elapsed");
+      HIPCHK(hipEventElapsedTime(&m2, ev[2], ev[3]), "elapsed");
+      tb += m0 + m2;
+      ts += m1;
+    }
+    for (int k = 0; k < b->n_sys; ++k) b->sys[k]->last_list = 0;
+    advance_host_steps(b, n);
+    taken += n;
+    *body_ms = tb;
+    *bs_ms = ts;
     return MX_OK;
   };
   mx_status st = MX_OK;
-  float best = 3.0e38f;
+  float best_body = 3.0e38f;
   int bb = b->blk, bt = b->tpb, bs = b->bps;
   // tile shape of the body kernels first, then the encounter-integrator width
   const int blks[] = {64, 128, 256, 512};
   const int tpbs[] = {1, 2, 4, 8};
-  // widths of the encounter integrator, tried twice in mirrored order (the step
-  // time varies with the encounters of the moment; the sums compare like with like)
+  // widths of the encounter integrator, tried twice in mirrored order (its time
+  // varies with the encounters of the moment; the sums compare like with like)
   const int bpss[] = {8, 16, 32, 64};
   constexpr int nbps = sizeof(bpss) / sizeof(bpss[0]);
-  float ms = 0.f;
-  if (st == MX_OK) st = trial(bb, bt, bs, &ms);  // warm-up of the current configuration
+  float tb = 0.f, ts = 0.f;
+  if (st == MX_OK) st = trial(bb, bt, bs, &tb, &ts);  // warm-up of the current configuration
   for (int blk : blks)
     for (int tpb : tpbs) {
       if (st != MX_OK) break;
-      st = trial(blk, tpb, bs, &ms);
-      if (st == MX_OK && ms < best) {
-        best = ms;
+      st = trial(blk, tpb, bs, &tb, &ts);
+      if (st == MX_OK && tb < best_body) {
+        best_body = tb;
         bb = blk;
         bt = tpb;
       }
@@ -1359,18 +1390,18 @@ mx_status mx_batch_autotune(mx_batch* b, int32_t steps_per_candidate, int32_t* s
     for (int q = 0; q < nbps; ++q) {
       if (st != MX_OK) break;
       const int k = pass == 0 ? q : nbps - 1 - q;
-      st = trial(bb, bt, bpss[k], &ms);
-      sum[k] += ms;
+      st = trial(bb, bt, bpss[k], &tb, &ts);
+      sum[k] += ts;
     }
+  float best = 0.f;
   if (st == MX_OK) {
     int kb = 0;
     for (int k = 1; k < nbps; ++k)
       if (sum[k] < sum[kb]) kb = k;
     bs = bpss[kb];
-    best = 0.5f * sum[kb];
+    best = best_body + 0.5f * sum[kb];
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  for (int k = 0; k < 4; ++k) (void)hipEventDestroy(ev[k]);
   b->launch_mode = saved_mode;
   *steps_taken = taken;
   if (st != MX_OK) return st;
