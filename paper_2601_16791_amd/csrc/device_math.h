@@ -437,4 +437,32 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* sh) {
   __syncthreads();
 }
 
+// Fixed-order sum over a block of BS threads (a multiple of 64, at most 1024):
+// each wave sums its lanes by the fixed DPP reduction, then every thread adds
+// the waves' sums from LDS as a pairwise tree (one barrier instead of one per
+// level).  Every block that runs it on the same data gets the same bits.
+template <int BS, int K>
+__device__ __forceinline__ void block_sum_waves(double (&v)[K], double* sh) {
+  constexpr int W = BS / 64;
+  static_assert(W >= 1 && (W & (W - 1)) == 0 && W <= 16, "waves per block");
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum_fixed(v[k]);
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < K; ++k) sh[k * W + w] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) t[i] = sh[k * W + i];
+#pragma unroll
+    for (int span = 1; span < W; span <<= 1)
+#pragma unroll
+      for (int i = 0; i + span < W; i += 2 * span) t[i] = t[i] + t[i + span];
+    v[k] = t[0];
+  }
+  __syncthreads();
+}
+
 }  // namespace mxd

@@ -202,6 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_jump_drift(
   // (from the step-start snapshot: the blocks that own massive bodies overwrite
   // u while other blocks are still reading)
   double v[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 4
   for (int k = threadIdx.x; k < nb; k += kBlock) {
     double m;
     if (k < gpre && growth[3 * k + 2] > 0.0) m = grown_mass(growth, k, tg);
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_jump_drift(
     v[4] += m * (uy + hh * (bigsnap[7 * nb + k] + 0.0));
     v[5] += m * (uz + hh * (bigsnap[8 * nb + k] + 0.0));
   }
-  mxd::block_sum<kBlock, 6>(v, sh);
+  mxd::block_sum_waves<kBlock, 6>(v, sh);
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= n) return;
   double px = x[t], py = x[n + t], pz = x[2 * n + t];
@@ -271,13 +272,14 @@ __global__ __launch_bounds__(kBlock) void k_jump_pack(int n, int nb, double mu0,
                                                       DevScalars* __restrict__ dsc, int jump) {
   __shared__ double sh[3 * kBlock];
   double v[3] = {0, 0, 0};
+#pragma unroll 4
   for (int k = threadIdx.x; k < nb; k += kBlock) {
     double m = mu[k];
     v[0] += m * u[k];
     v[1] += m * u[n + k];
     v[2] += m * u[2 * n + k];
   }
-  mxd::block_sum<kBlock, 3>(v, sh);
+  mxd::block_sum_waves<kBlock, 3>(v, sh);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     dsc->P[0] = v[0];
     dsc->P[1] = v[1];
