@@ -21,9 +21,9 @@
 //                     whose tangent comes from the solved time equation
 //   k_adj_bs        : tangents of the Bulirsch-Stoer map of a subsystem along
 //                     the accepted step sizes and columns of the forward run, one
-//                     input direction per lane, contracted with the adjoint of
-//                     the kept members
-//   k_adj_bs_apply  : those contributions added in subsystem order
+//                     input direction and column per thread, contracted with the
+//                     adjoint of the kept members
+//   k_adj_bs_apply  : those contributions added in a fixed order
 //   k_adj_sum3 / k_adj_momentum : sum of an adjoint over all bodies and the
 //                     resulting momentum term (jumps, DH <-> heliocentric)
 //   k_adj_copy, k_adj_copy_tape : the per-step record (state, subsystem table,
@@ -575,15 +575,6 @@ __global__ __launch_bounds__(64) void k_adj_momentum(int n, int nb, const double
 }
 
 // ------------------------------------------------------------------ drift
-__global__ void k_adj_mark(const Subsystem* __restrict__ subs, const int32_t* __restrict__ n_sub,
-                           int32_t* __restrict__ kept, int32_t val) {
-  const int nsub = *n_sub;
-  for (int b = blockIdx.x; b < nsub; b += gridDim.x) {
-    const Subsystem& S = subs[b];
-    for (int k = S.keep_from + threadIdx.x; k < S.m; k += blockDim.x) kept[S.mem[k]] = val;
-  }
-}
-
 // (lx, lu) <- J_Kepler^T (lx, lu) at the pre-drift state for bodies that drifted;
 // zero for the kept members of encounter subsystems (their part comes from the
 // Bulirsch-Stoer tangents)
@@ -667,7 +658,7 @@ __device__ __forceinline__ void tforce(uint32_t pmask, const D1 (&mu)[M], const 
 }
 
 template <int M>
-__device__ void tstoermer(int ns, double H, uint32_t pmask, const D1 (&mu)[M],
+__device__ __forceinline__ void tstoermer(int ns, double H, uint32_t pmask, const D1 (&mu)[M],
                           const double (&rc)[M], double mu0, const D1 (&xs)[3 * M],
                           const D1 (&vs)[3 * M], D1 (&xo)[3 * M], D1 (&vo)[3 * M]) {
   constexpr int NN = 3 * M;
@@ -694,32 +685,43 @@ __device__ void tstoermer(int ns, double H, uint32_t pmask, const D1 (&mu)[M],
   for (int i = 0; i < NN; ++i) vo[i] = d[i] / dt + (0.5 * dt) * acc[i];
 }
 
-// Lane i carries the derivative along input i of the subsystem: member
-// positions (3M), velocities (3M), then masses (M).  The state is advanced along
-// the accepted steps of the forward run; each accepted step is the polynomial
-// extrapolation to zero step of the Stoermer columns 0..a, written as the
-// Lagrange combination sum_k w_k T_k with w_k = prod_{j != k} n_k^2/(n_k^2-n_j^2).
+// One block per subsystem: thread t carries input direction t % 32 (member
+// positions 3M, velocities 3M, masses M; directions >= 7M idle along) and
+// Stoermer column t / 32.  The state is advanced along the accepted steps of the
+// forward run; the columns 0..a of one accepted step run side by side, their
+// results meet in LDS, and the step's result is their polynomial extrapolation to
+// zero step, the Lagrange combination sum_k w_k T_k with
+// w_k = prod_{j != k} n_k^2/(n_k^2-n_j^2), summed in column order.
+constexpr int kAdjBsDirs = 32;
+constexpr int kAdjBsThreads = kAdjBsDirs * kBsColumns;
+
+struct AdjBsShared {
+  double cv[kBsColumns][24];              // each column's result, primal (x then v)
+  double cd[kBsColumns][24][kAdjBsDirs];  // and its tangent per direction
+  double sv[24];                          // state after the accepted step, primal
+  double sd[24][kAdjBsDirs];              // and tangent per direction
+  double xs[12], vs[12], mum[4], rcm[4], lxo[12], luo[12];
+};
+
 template <int M>
-__device__ void bs_tangent_lane(int lane, const Subsystem& S, int nsched,
-                                const double* __restrict__ sched, const double* xs0,
-                                const double* vs0, const double* mum, const double* rcm,
-                                double mu0, const double* lxo, const double* luo, double* out) {
-  constexpr int NN = 3 * M;
-  const int nin = 7 * M;
+__device__ void bs_tangent_block(AdjBsShared& sh, const Subsystem& S, int nsched,
+                                 const double* __restrict__ sched, double mu0, double* out) {
+  constexpr int NN = 3 * M, NC = 6 * M;
+  const int dir = threadIdx.x % kAdjBsDirs, col = threadIdx.x / kAdjBsDirs;
   D1 xs[NN], vs[NN], mu[M];
   double rc[M];
 #pragma unroll
   for (int i = 0; i < NN; ++i) {
-    xs[i] = dconst<1>(xs0[i]);
-    vs[i] = dconst<1>(vs0[i]);
-    if (lane == i) xs[i].d[0] = 1.0;
-    if (lane == NN + i) vs[i].d[0] = 1.0;
+    xs[i] = dconst<1>(sh.xs[i]);
+    vs[i] = dconst<1>(sh.vs[i]);
+    if (dir == i) xs[i].d[0] = 1.0;
+    if (dir == NN + i) vs[i].d[0] = 1.0;
   }
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    mu[k] = dconst<1>(mum[k]);
-    if (lane == 2 * NN + k) mu[k].d[0] = 1.0;
-    rc[k] = rcm[k];
+    mu[k] = dconst<1>(sh.mum[k]);
+    if (dir == 2 * NN + k) mu[k].d[0] = 1.0;
+    rc[k] = sh.rcm[k];
   }
   uint32_t pmask = 0;
   for (int q = 0; q < S.np; ++q) {
@@ -728,79 +730,106 @@ __device__ void bs_tangent_lane(int lane, const Subsystem& S, int nsched,
   }
   for (int j = 0; j < nsched; ++j) {
     const double H = sched[2 * j];
-    const int acc = (int)sched[2 * j + 1];
-    D1 nx[NN], nv[NN];
-#pragma unroll
-    for (int i = 0; i < NN; ++i) nx[i] = nv[i] = dconst<1>(0.0);
-    for (int k = 0; k <= acc; ++k) {
-      const double nk = 2.0 * (k + 1);
-      double w = 1.0;
-      for (int jj = 0; jj <= acc; ++jj) {
-        if (jj == k) continue;
-        const double nj = 2.0 * (jj + 1);
-        w *= nk * nk / (nk * nk - nj * nj);
-      }
+    const int acc = min((int)sched[2 * j + 1], kBsColumns - 1);  // columns the LDS holds
+    if (col <= acc) {
       D1 xo[NN], vo[NN];
-      tstoermer<M>(2 * (k + 1), H, pmask, mu, rc, mu0, xs, vs, xo, vo);
+      tstoermer<M>(2 * (col + 1), H, pmask, mu, rc, mu0, xs, vs, xo, vo);
 #pragma unroll
       for (int i = 0; i < NN; ++i) {
-        nx[i] = nx[i] + w * xo[i];
-        nv[i] = nv[i] + w * vo[i];
+        sh.cd[col][i][dir] = xo[i].d[0];
+        sh.cd[col][NN + i][dir] = vo[i].d[0];
+      }
+      if (dir == 0) {
+#pragma unroll
+        for (int i = 0; i < NN; ++i) {
+          sh.cv[col][i] = xo[i].v;
+          sh.cv[col][NN + i] = vo[i].v;
+        }
       }
     }
+    __syncthreads();
+    for (int c = col; c < NC; c += kBsColumns) {
+      D1 sum = dconst<1>(0.0);
+      for (int k = 0; k <= acc; ++k) {
+        const double nk = 2.0 * (k + 1);
+        double w = 1.0;
+        for (int jj = 0; jj <= acc; ++jj) {
+          if (jj == k) continue;
+          const double nj = 2.0 * (jj + 1);
+          w *= nk * nk / (nk * nk - nj * nj);
+        }
+        D1 t;
+        t.v = sh.cv[k][c];
+        t.d[0] = sh.cd[k][c][dir];
+        sum = sum + w * t;
+      }
+      sh.sd[c][dir] = sum.d[0];
+      if (dir == 0) sh.sv[c] = sum.v;
+    }
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < NN; ++i) {
-      xs[i] = nx[i];
-      vs[i] = nv[i];
+      xs[i].v = sh.sv[i];
+      xs[i].d[0] = sh.sd[i][dir];
+      vs[i].v = sh.sv[NN + i];
+      vs[i].d[0] = sh.sd[NN + i][dir];
     }
   }
-  if (lane >= nin) return;
+  if (col != 0 || dir >= 7 * M) return;
   double acc = 0.0;
-  for (int k = S.keep_from; k < M; ++k)
+  const int keep_from = S.keep_from;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {  // static indices keep the state in registers
+    if (k < keep_from) continue;
+#pragma unroll
     for (int c = 0; c < 3; ++c)
-      acc += xs[3 * k + c].d[0] * lxo[3 * k + c] + vs[3 * k + c].d[0] * luo[3 * k + c];
-  out[lane] = acc;
+      acc += xs[3 * k + c].d[0] * sh.lxo[3 * k + c] + vs[3 * k + c].d[0] * sh.luo[3 * k + c];
+  }
+  out[dir] = acc;
 }
 
-// One wave per subsystem: contributions contrib[b][i] = d(kept outputs)/d(input
-// i) . adjoint of the kept outputs, i over positions, velocities, masses.
-__global__ __launch_bounds__(64) void k_adj_bs(int n, int nb, double mu0,
-                                               const double* __restrict__ x0s,
-                                               const double* __restrict__ u0s,
-                                               const double* __restrict__ mu,
-                                               const double* __restrict__ rcrit,
-                                               const Subsystem* __restrict__ subs,
-                                               const int32_t* __restrict__ n_sub,
-                                               const double* __restrict__ sched,
-                                               const int32_t* __restrict__ nsched,
-                                               const double* __restrict__ lx,
-                                               const double* __restrict__ lu,
-                                               double* __restrict__ contrib,
-                                               int32_t* __restrict__ err) {
-  __shared__ double xs[12], vs[12], mum[4], rcm[4], lxo[12], luo[12];
-  const int lane = threadIdx.x;
+// One block per subsystem: contributions contrib[b][i] = d(kept outputs)/d(input
+// i) . adjoint of the kept outputs, i over positions, velocities, masses; the
+// kept members are marked in kept[] for the drift kernel that follows.
+__global__ __launch_bounds__(kAdjBsThreads) void k_adj_bs(int n, int nb, double mu0,
+                                                          const double* __restrict__ x0s,
+                                                          const double* __restrict__ u0s,
+                                                          const double* __restrict__ mu,
+                                                          const double* __restrict__ rcrit,
+                                                          const Subsystem* __restrict__ subs,
+                                                          const int32_t* __restrict__ n_sub,
+                                                          const double* __restrict__ sched,
+                                                          const int32_t* __restrict__ nsched,
+                                                          const double* __restrict__ lx,
+                                                          const double* __restrict__ lu,
+                                                          double* __restrict__ contrib,
+                                                          int32_t* __restrict__ kept,
+                                                          int32_t* __restrict__ err) {
+  __shared__ AdjBsShared sh;
+  const int t = threadIdx.x;
   const int nsub = *n_sub;
   for (int b = blockIdx.x; b < nsub; b += gridDim.x) {
     const Subsystem& S = subs[b];
     const int m = S.m;
+    if (t >= S.keep_from && t < m) kept[S.mem[t]] = 1;  // read by k_adj_drift
     if (m == 0) continue;
     if (m > 4 || nsched[b] > kBsMaxSched) {
-      if (lane == 0) atomicOr(err, MXE_ADJOINT);
+      if (t == 0) atomicOr(err, MXE_ADJOINT);
       continue;
     }
     __syncthreads();
-    if (lane < 3 * m) {
-      const int k = lane / 3, c = lane - 3 * (lane / 3);
+    if (t < 3 * m) {
+      const int k = t / 3, c = t - 3 * (t / 3);
       const int body = S.mem[k];
-      xs[lane] = x0s[(size_t)c * n + body];
-      vs[lane] = u0s[(size_t)c * n + body];
-      lxo[lane] = lx[(size_t)c * n + body];
-      luo[lane] = lu[(size_t)c * n + body];
+      sh.xs[t] = x0s[(size_t)c * n + body];
+      sh.vs[t] = u0s[(size_t)c * n + body];
+      sh.lxo[t] = lx[(size_t)c * n + body];
+      sh.luo[t] = lu[(size_t)c * n + body];
     }
-    if (lane < m) {
-      const int body = S.mem[lane];
-      mum[lane] = body < nb ? mu[body] : 0.0;
-      rcm[lane] = body < nb ? rcrit[body] : 0.0;
+    if (t < m) {
+      const int body = S.mem[t];
+      sh.mum[t] = body < nb ? mu[body] : 0.0;
+      sh.rcm[t] = body < nb ? rcrit[body] : 0.0;
     }
     __syncthreads();
     double* out = contrib + (size_t)b * 28;
@@ -808,49 +837,69 @@ __global__ __launch_bounds__(64) void k_adj_bs(int n, int nb, double mu0,
     const int ns = nsched[b];
     switch (m) {
       case 1:
-        if (lane < 7) out[lane] = 0.0;  // cannot occur: subsystems have two or more members
+        if (t < 7) out[t] = 0.0;  // cannot occur: subsystems have two or more members
         break;
-      case 2: bs_tangent_lane<2>(lane, S, ns, sc, xs, vs, mum, rcm, mu0, lxo, luo, out); break;
-      case 3: bs_tangent_lane<3>(lane, S, ns, sc, xs, vs, mum, rcm, mu0, lxo, luo, out); break;
-      default: bs_tangent_lane<4>(lane, S, ns, sc, xs, vs, mum, rcm, mu0, lxo, luo, out); break;
+      case 2: bs_tangent_block<2>(sh, S, ns, sc, mu0, out); break;
+      case 3: bs_tangent_block<3>(sh, S, ns, sc, mu0, out); break;
+      default: bs_tangent_block<4>(sh, S, ns, sc, mu0, out); break;
     }
   }
 }
 
-// Adds the subsystem contributions in subsystem order: thread k < nb walks all
-// subsystems for massive body k; massless members belong to one subsystem only.
-__global__ void k_adj_bs_apply(int n, int nb, const Subsystem* __restrict__ subs,
-                               const int32_t* __restrict__ n_sub,
-                               const double* __restrict__ contrib, double* __restrict__ lx,
-                               double* __restrict__ lu, double* __restrict__ lmu) {
+// Adds the subsystem contributions.  Massive body k < nb gets wave k: lane l
+// sums subsystems l, l + 64, ... in order and the 64 partials meet in a fixed
+// tree, so the sum is the same on every run.  The remaining threads take the
+// massless members, each of which belongs to one subsystem only, and clear the
+// marks k_adj_bs set.
+constexpr int kAdjApplyMassless = 1024;  // threads beyond the massive bodies' waves
+
+__global__ __launch_bounds__(256) void k_adj_bs_apply(int n, int nb,
+                                                      const Subsystem* __restrict__ subs,
+                                                      const int32_t* __restrict__ n_sub,
+                                                      const double* __restrict__ contrib,
+                                                      double* __restrict__ lx,
+                                                      double* __restrict__ lu,
+                                                      double* __restrict__ lmu,
+                                                      int32_t* __restrict__ kept) {
   const int nsub = *n_sub;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid < nb) {
-    double ax[3] = {0.0, 0.0, 0.0}, av[3] = {0.0, 0.0, 0.0}, am = 0.0;
-    for (int b = 0; b < nsub; ++b) {
+  const int wave = tid / 64, lane = tid % 64;
+  if (wave < nb) {
+    double a[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = lane; b < nsub; b += 64) {
       const Subsystem& S = subs[b];
       const int m = S.m;
       if (m < 2 || m > 4) continue;
       const double* c = contrib + (size_t)b * 28;
       for (int k = 0; k < m; ++k) {
-        if (S.mem[k] != tid) continue;
+        if (S.mem[k] != wave) continue;
+#pragma unroll
         for (int q = 0; q < 3; ++q) {
-          ax[q] += c[3 * k + q];
-          av[q] += c[3 * m + 3 * k + q];
+          a[q] += c[3 * k + q];
+          a[3 + q] += c[3 * m + 3 * k + q];
         }
-        am += c[6 * m + k];
+        a[6] += c[6 * m + k];
       }
     }
-    for (int q = 0; q < 3; ++q) {
-      lx[q * n + tid] += ax[q];
-      lu[q * n + tid] += av[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int i = 0; i < 7; ++i) a[i] += __shfl_down(a[i], off);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        lx[q * n + wave] += a[q];
+        lu[q * n + wave] += a[3 + q];
+      }
+      lmu[wave] += a[6];
     }
-    lmu[tid] += am;
     return;
   }
-  for (int b = tid - nb; b < nsub; b += gridDim.x * blockDim.x) {
+  const int stride = gridDim.x * blockDim.x - 64 * nb;
+  for (int b = tid - 64 * nb; b < nsub; b += stride) {
     const Subsystem& S = subs[b];
     const int m = S.m;
+    for (int k = S.keep_from; k < m; ++k) kept[S.mem[k]] = 0;
     if (m < 2 || m > 4) continue;
     const double* c = contrib + (size_t)b * 28;
     for (int k = 0; k < m; ++k) {
@@ -987,14 +1036,13 @@ hipError_t adj_drift(hipStream_t st, int n, int nb, double mu0, double h, const 
                      const Subsystem* subs, const int32_t* n_sub, const double* sched,
                      const int32_t* nsched, int32_t* kept, double* contrib, double* lx,
                      double* lu, double* lmu, int32_t* err) {
-  hipLaunchKernelGGL(k_adj_mark, dim3(256), dim3(64), 0, st, subs, n_sub, kept, 1);
-  hipLaunchKernelGGL(k_adj_bs, dim3(256), dim3(64), 0, st, n, nb, mu0, x0, u0, mu, rcrit, subs,
-                     n_sub, sched, nsched, lx, lu, contrib, err);
+  hipLaunchKernelGGL(k_adj_bs, dim3(256), dim3(kAdjBsThreads), 0, st, n, nb, mu0, x0, u0, mu,
+                     rcrit, subs, n_sub, sched, nsched, lx, lu, contrib, kept, err);
   hipLaunchKernelGGL(k_adj_drift, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, mu0, h, x0, u0,
                      kept, lx, lu, err);
-  hipLaunchKernelGGL(k_adj_bs_apply, dim3(4), dim3(256), 0, st, n, nb, subs, n_sub, contrib, lx,
-                     lu, lmu);
-  hipLaunchKernelGGL(k_adj_mark, dim3(256), dim3(64), 0, st, subs, n_sub, kept, 0);
+  const int apply_blocks = (64 * nb + kAdjApplyMassless + 255) / 256;
+  hipLaunchKernelGGL(k_adj_bs_apply, dim3(apply_blocks), dim3(256), 0, st, n, nb, subs, n_sub,
+                     contrib, lx, lu, lmu, kept);
   return hipGetLastError();
 }
 
