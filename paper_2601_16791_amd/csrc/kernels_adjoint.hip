@@ -13,9 +13,10 @@
 //                     f = K(r)/r^3, Jacobian f I + f'(r)/r d d^T), its mass term,
 //                     and the drag Jacobian (forward-mode over the drag formula,
 //                     drag regime fixed); source-side sums reduced per wave
-//   k_adj_reduce /  : fixed-order sums of the per-wave partials, applied to the
-//   k_adj_kick_apply  massive bodies, with the momentum terms of the jump and of
-//                     the heliocentric velocity that the drag sees
+//   k_adj_reduce_apply : fixed-order sums of the per-wave partials, applied to
+//                     the massive bodies by the block that ends last, with the
+//                     momentum terms of the jump and of the heliocentric
+//                     velocity that the drag sees
 //   k_adj_drift     : transposed Jacobian of the Kepler map per body, by
 //                     forward-mode evaluation at the solved universal variable,
 //                     whose tangent comes from the solved time equation
@@ -24,8 +25,9 @@
 //                     input direction and column per thread, contracted with the
 //                     adjoint of the kept members
 //   k_adj_bs_apply  : those contributions added in a fixed order
-//   k_adj_sum3 / k_adj_momentum : sum of an adjoint over all bodies and the
-//                     resulting momentum term (jumps, DH <-> heliocentric)
+//   k_adj_sum3      : per-wave sums of an adjoint over all bodies, whose
+//                     momentum term (jumps, DH <-> heliocentric) the reduction
+//                     above applies
 //   k_adj_copy, k_adj_copy_tape : the per-step record (state, subsystem table,
 //                     accepted Bulirsch-Stoer steps) kept for the reverse pass
 #include <hip/hip_runtime.h>
@@ -379,11 +381,8 @@ __device__ bool kepler_vjp(double mu, double h, const double (&x0)[3], const dou
 }
 
 // ------------------------------------------------------------------ helpers
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
+// Fixed-order sum over the 64 lanes of a wave by DPP row moves (all lanes active).
+__device__ __forceinline__ double wave_sum(double v) { return mxd::wave_sum_fixed(v); }
 
 // f(r) = K(r)/r^3 and F1 = f'(r)/r of the changeover-weighted pair force
 __device__ __forceinline__ void pair_f(double s2, double rc, double& f, double& F1) {
@@ -409,6 +408,18 @@ __device__ __forceinline__ void pair_f(double s2, double rc, double& f, double& 
 }
 
 // ------------------------------------------------------------------ kick
+// Arguments of the massive-body step that follows a reduction: uref is the
+// velocity the momentum is taken of, lx is touched by the kick only.
+struct AdjApply {
+  int n, nb;
+  double coef;
+  const double* mu;
+  const double* uref;
+  double* lx;
+  double* lu;
+  double* lmu;
+};
+
 // Partials per wave: [4 nb] source terms (3 position, 1 mass), [3] sum of the
 // updated lx over the wave's bodies, [3] momentum term of the drag.
 __host__ __device__ __forceinline__ int part_stride(int nb) { return 4 * nb + 6; }
@@ -421,16 +432,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_kick(
     const double* __restrict__ rcrit, const double* __restrict__ r_p,
     const double* __restrict__ rho_p, double* __restrict__ lx, double* __restrict__ lu,
     double* __restrict__ part) {
-  __shared__ double sh[3 * kBlock];
   __shared__ double bx[3][kSmallBig], bmu[kSmallBig], brc[kSmallBig];
   const int tid = threadIdx.x;
-  double P[3] = {0.0, 0.0, 0.0};
-  for (int k = tid; k < nb; k += kBlock) {
-    P[0] += mu[k] * up[k];
-    P[1] += mu[k] * up[n + k];
-    P[2] += mu[k] * up[2 * n + k];
+  double P[3] = {0.0, 0.0, 0.0};  // massive momentum: every wave sums it the same way
+  if ((tid & 63) < nb) {
+    const int k = tid & 63;
+    P[0] = mu[k] * up[k];
+    P[1] = mu[k] * up[n + k];
+    P[2] = mu[k] * up[2 * n + k];
   }
-  mxd::block_sum<kBlock, 3>(P, sh);
+  for (int c = 0; c < 3; ++c) P[c] = wave_sum(P[c]);
   if (tid < nb) {
     for (int c = 0; c < 3; ++c) bx[c][tid] = x[c * n + tid];
     bmu[tid] = mu[tid];
@@ -514,37 +525,72 @@ __global__ __launch_bounds__(64) void k_adj_reduce(const double* __restrict__ pa
   a = wave_sum(a);
   if (threadIdx.x == 0) tot[v] = a;
 }
-
-// Kick totals applied: source terms to the massive bodies (lx, lmu); the
-// momentum adjoint lP = jump_coef * (sum of the updated lx over all bodies) +
-// (drag term) feeds lu and lmu of the massive bodies through P = sum mu_k up_k.
-__global__ __launch_bounds__(64) void k_adj_kick_apply(int n, int nb,
-                                                       const double* __restrict__ tot,
-                                                       double jump_coef,
-                                                       const double* __restrict__ mu,
-                                                       const double* __restrict__ up,
-                                                       double* __restrict__ lx,
-                                                       double* __restrict__ lu,
-                                                       double* __restrict__ lmu) {
-  const int tid = threadIdx.x;
-  if (tid >= nb) return;
+// The massive bodies' part of a kick taken back (tid < nb): the source terms
+// tot[4 k + {0,1,2,3}], and the momentum of the jump before the kick (coef =
+// hh / mu0, else 0) and of the drag, from the summed lx tot[4 nb + c] and drag
+// term tot[4 nb + 3 + c].
+__device__ __forceinline__ void kick_apply(int tid, const AdjApply& ap, const double* tot) {
+  const int n = ap.n, nb = ap.nb;
   double lP[3];
   for (int c = 0; c < 3; ++c) {
     double sx = tot[4 * nb + c];
     for (int s = 0; s < nb; ++s) sx += tot[4 * s + c];
-    lP[c] = jump_coef * sx + tot[4 * nb + 3 + c];
+    lP[c] = ap.coef * sx + tot[4 * nb + 3 + c];
   }
   double dm = tot[4 * tid + 3];
   for (int c = 0; c < 3; ++c) {
-    lx[c * n + tid] += tot[4 * tid + c];
-    lu[c * n + tid] += mu[tid] * lP[c];
-    dm += up[c * n + tid] * lP[c];
+    ap.lx[c * n + tid] += tot[4 * tid + c];
+    ap.lu[c * n + tid] += ap.mu[tid] * lP[c];
+    dm += ap.uref[c * n + tid] * lP[c];
   }
-  lmu[tid] += dm;
+  ap.lmu[tid] += dm;
 }
 
-// ------------------------------------------------------------------ sums
-// per-wave sums of a [3][n] array
+// lP = coef * sum_t a_t (tot[c]); lu_k += mu_k lP; lmu_k += uref_k . lP
+__device__ __forceinline__ void momentum_apply(int tid, const AdjApply& ap, const double* tot) {
+  const int n = ap.n;
+  double dm = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double lP = ap.coef * tot[c];
+    ap.lu[c * n + tid] += ap.mu[tid] * lP;
+    dm += ap.uref[c * n + tid] * lP;
+  }
+  ap.lmu[tid] += dm;
+}
+
+// Block v sums column v of the per-wave partials into tot[v]; the block that
+// finishes last (counted in *ctr, which it sets back to zero) applies the sums
+// to the massive bodies.  Release and acquire fences at device scope order the
+// sums before the count and the count before their reads.
+template <bool kKick>
+__global__ __launch_bounds__(64) void k_adj_reduce_apply(const double* __restrict__ part, int nw,
+                                                         int S, double* __restrict__ tot,
+                                                         unsigned* __restrict__ ctr, AdjApply ap) {
+  __shared__ int last;
+  __shared__ double sums[4 * kSmallBig + 6];
+  const int v = blockIdx.x, tid = threadIdx.x;
+  double a = 0.0;
+  for (int w = tid; w < nw; w += 64) a += part[(size_t)w * S + v];
+  a = wave_sum(a);
+  if (tid == 0) {
+    tot[v] = a;
+    __threadfence();
+    last = atomicAdd(ctr, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (tid == 0) *ctr = 0;
+  for (int i = tid; i < S; i += 64) sums[i] = tot[i];  // all loads in flight at once
+  __syncthreads();
+  if (tid >= ap.nb) return;
+  if (kKick) kick_apply(tid, ap, sums);
+  else momentum_apply(tid, ap, sums);
+}
+
+// Kick totals applied: source terms to the massive bodies (lx, lmu); the
+// momentum adjoint lP = jump_coef * (sum of the updated lx over all bodies) +
+// (drag term) feeds lu and lmu of the massive bodies through P = sum mu_k up_k.
 __global__ __launch_bounds__(kBlock) void k_adj_sum3(int n, const double* __restrict__ a,
                                                      double* __restrict__ part) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -558,21 +604,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_sum3(int n, const double* __rest
 }
 
 // lP = coef * tot[0..2]; lu_k += mu_k lP, lmu_k += uref_k . lP
-__global__ __launch_bounds__(64) void k_adj_momentum(int n, int nb, const double* __restrict__ tot,
-                                                     double coef, const double* __restrict__ mu,
-                                                     const double* __restrict__ uref,
-                                                     double* __restrict__ lu,
-                                                     double* __restrict__ lmu) {
-  const int tid = threadIdx.x;
-  if (tid >= nb) return;
-  double dm = 0.0;
-  for (int c = 0; c < 3; ++c) {
-    const double lP = coef * tot[c];
-    lu[c * n + tid] += mu[tid] * lP;
-    dm += uref[c * n + tid] * lP;
-  }
-  lmu[tid] += dm;
-}
 
 // ------------------------------------------------------------------ drift
 // (lx, lu) <- J_Kepler^T (lx, lu) at the pre-drift state for bodies that drifted;
@@ -701,11 +732,14 @@ struct AdjBsShared {
   double sv[24];                          // state after the accepted step, primal
   double sd[24][kAdjBsDirs];              // and tangent per direction
   double xs[12], vs[12], mum[4], rcm[4], lxo[12], luo[12];
+  double w[kBsColumns][kBsColumns];  // w[a][k]: weight of column k when column a is accepted
+  double sched[2 * kBsMaxSched];     // the subsystem's accepted steps (H, a)
+  uint32_t pmask;                    // pairs of members that interact
 };
 
 template <int M>
-__device__ void bs_tangent_block(AdjBsShared& sh, const Subsystem& S, int nsched,
-                                 const double* __restrict__ sched, double mu0, double* out) {
+__device__ void bs_tangent_block(AdjBsShared& sh, const Subsystem& S, int nsched, double mu0,
+                                 double* out) {
   constexpr int NN = 3 * M, NC = 6 * M;
   const int dir = threadIdx.x % kAdjBsDirs, col = threadIdx.x / kAdjBsDirs;
   D1 xs[NN], vs[NN], mu[M];
@@ -723,14 +757,10 @@ __device__ void bs_tangent_block(AdjBsShared& sh, const Subsystem& S, int nsched
     if (dir == 2 * NN + k) mu[k].d[0] = 1.0;
     rc[k] = sh.rcm[k];
   }
-  uint32_t pmask = 0;
-  for (int q = 0; q < S.np; ++q) {
-    const int a = S.pl[q][0], b = S.pl[q][1];
-    pmask |= 1u << (a * (2 * M - a - 1) / 2 + (b - a - 1));
-  }
+  const uint32_t pmask = sh.pmask;
   for (int j = 0; j < nsched; ++j) {
-    const double H = sched[2 * j];
-    const int acc = min((int)sched[2 * j + 1], kBsColumns - 1);  // columns the LDS holds
+    const double H = sh.sched[2 * j];
+    const int acc = min((int)sh.sched[2 * j + 1], kBsColumns - 1);  // columns the LDS holds
     if (col <= acc) {
       D1 xo[NN], vo[NN];
       tstoermer<M>(2 * (col + 1), H, pmask, mu, rc, mu0, xs, vs, xo, vo);
@@ -751,17 +781,10 @@ __device__ void bs_tangent_block(AdjBsShared& sh, const Subsystem& S, int nsched
     for (int c = col; c < NC; c += kBsColumns) {
       D1 sum = dconst<1>(0.0);
       for (int k = 0; k <= acc; ++k) {
-        const double nk = 2.0 * (k + 1);
-        double w = 1.0;
-        for (int jj = 0; jj <= acc; ++jj) {
-          if (jj == k) continue;
-          const double nj = 2.0 * (jj + 1);
-          w *= nk * nk / (nk * nk - nj * nj);
-        }
         D1 t;
         t.v = sh.cv[k][c];
         t.d[0] = sh.cd[k][c][dir];
-        sum = sum + w * t;
+        sum = sum + sh.w[acc][k] * t;
       }
       sh.sd[c][dir] = sum.d[0];
       if (dir == 0) sh.sv[c] = sum.v;
@@ -808,6 +831,17 @@ __global__ __launch_bounds__(kAdjBsThreads) void k_adj_bs(int n, int nb, double 
   __shared__ AdjBsShared sh;
   const int t = threadIdx.x;
   const int nsub = *n_sub;
+  if (t < kBsColumns * kBsColumns) {  // Lagrange weights of column k among columns 0..a
+    const int a = t / kBsColumns, k = t % kBsColumns;
+    const double nk = 2.0 * (k + 1);
+    double w = 1.0;
+    for (int jj = 0; jj <= a; ++jj) {
+      if (jj == k) continue;
+      const double nj = 2.0 * (jj + 1);
+      w *= nk * nk / (nk * nk - nj * nj);
+    }
+    sh.w[a][k] = w;
+  }
   for (int b = blockIdx.x; b < nsub; b += gridDim.x) {
     const Subsystem& S = subs[b];
     const int m = S.m;
@@ -831,17 +865,23 @@ __global__ __launch_bounds__(kAdjBsThreads) void k_adj_bs(int n, int nb, double 
       sh.mum[t] = body < nb ? mu[body] : 0.0;
       sh.rcm[t] = body < nb ? rcrit[body] : 0.0;
     }
+    const int ns = nsched[b];
+    if (t < 2 * ns) sh.sched[t] = sched[(size_t)b * kBsMaxSched * 2 + t];
+    if (t == 0) sh.pmask = 0;
+    __syncthreads();
+    if (t < S.np) {  // bit of pair (a, b), a < b, in row-major order of the upper triangle
+      const int a = S.pl[t][0], c = S.pl[t][1];
+      atomicOr(&sh.pmask, 1u << (a * (2 * m - a - 1) / 2 + (c - a - 1)));
+    }
     __syncthreads();
     double* out = contrib + (size_t)b * 28;
-    const double* sc = sched + (size_t)b * kBsMaxSched * 2;
-    const int ns = nsched[b];
     switch (m) {
       case 1:
         if (t < 7) out[t] = 0.0;  // cannot occur: subsystems have two or more members
         break;
-      case 2: bs_tangent_block<2>(sh, S, ns, sc, mu0, out); break;
-      case 3: bs_tangent_block<3>(sh, S, ns, sc, mu0, out); break;
-      default: bs_tangent_block<4>(sh, S, ns, sc, mu0, out); break;
+      case 2: bs_tangent_block<2>(sh, S, ns, mu0, out); break;
+      case 3: bs_tangent_block<3>(sh, S, ns, mu0, out); break;
+      default: bs_tangent_block<4>(sh, S, ns, mu0, out); break;
     }
   }
 }
@@ -995,6 +1035,12 @@ int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
 namespace mxk {
 
+// tot holds the part_stride(kSmallBig) sums, then one word that counts the
+// blocks of a reduction (zero between launches)
+unsigned* tot_counter(double* tot) {
+  return reinterpret_cast<unsigned*>(tot + part_stride(kSmallBig));
+}
+
 hipError_t adj_reduce(hipStream_t st, const double* part, int nw, int S, double* tot) {
   hipLaunchKernelGGL(k_adj_reduce, dim3(S), dim3(64), 0, st, part, nw, S, tot);
   return hipGetLastError();
@@ -1010,10 +1056,9 @@ hipError_t adj_kick(hipStream_t st, int n, int nb, double mu0, double hh,
   if (nb > kSmallBig) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_adj_kick, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, nb, mu0, hh, dc,
                      gas_on, x, up, mu, rcrit, r_p, rho_p, lx, lu, part);
-  hipError_t e = adj_reduce(st, part, (n + 63) / 64, part_stride(nb), tot);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_kick_apply, dim3(1), dim3(64), 0, st, n, nb, tot, jump_coef, mu, up,
-                     lx, lu, lmu);
+  const AdjApply ap{n, nb, jump_coef, mu, up, lx, lu, lmu};
+  hipLaunchKernelGGL(k_adj_reduce_apply<true>, dim3(part_stride(nb)), dim3(64), 0, st, part,
+                     (n + 63) / 64, part_stride(nb), tot, tot_counter(tot), ap);
   return hipGetLastError();
 }
 
@@ -1022,10 +1067,9 @@ hipError_t adj_momentum(hipStream_t st, int n, int nb, const double* a, double c
                         const double* mu, const double* uref, double* lu, double* lmu,
                         double* part, double* tot) {
   hipLaunchKernelGGL(k_adj_sum3, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, a, part);
-  hipError_t e = adj_reduce(st, part, (n + 63) / 64, 3, tot);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_momentum, dim3(1), dim3(64), 0, st, n, nb, tot, coef, mu, uref, lu,
-                     lmu);
+  const AdjApply ap{n, nb, coef, mu, uref, nullptr, lu, lmu};
+  hipLaunchKernelGGL(k_adj_reduce_apply<false>, dim3(3), dim3(64), 0, st, part, (n + 63) / 64, 3,
+                     tot, tot_counter(tot), ap);
   return hipGetLastError();
 }
 

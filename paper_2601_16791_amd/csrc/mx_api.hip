@@ -1488,7 +1488,7 @@ struct mx_adjoint {
   int32_t* tnsched;  // [every][cap_subs]
   double *lx, *lu, *lmu;  // adjoints of x, u [3][n] and of mu [n_big]
   double* part;      // wave partials
-  double* tot;       // reduced partials
+  double* tot;       // reduced partials, then the reductions' block counter
   double* sched;     // [cap_subs][kBsMaxSched][2] written by the forward integrator
   int32_t* nsched;   // [cap_subs]
   double* contrib;   // [cap_subs][28]
@@ -1630,12 +1630,15 @@ mx_status mx_adjoint_create(const mx_params* p, const double* x_h, const double*
   ALLOC(a->tape, a->every * 4 * n3) ALLOC(a->tsubs, a->every * cs) ALLOC(a->tnsub, a->every)
   ALLOC(a->tsched, a->every * cs * kBsMaxSched * 2) ALLOC(a->tnsched, a->every * cs)
   ALLOC(a->lx, n3) ALLOC(a->lu, n3) ALLOC(a->lmu, nb)
-  ALLOC(a->part, nwaves * (4 * (size_t)kSmallBig + 6)) ALLOC(a->tot, 4 * (size_t)kSmallBig + 6)
+  ALLOC(a->part, nwaves * (4 * (size_t)kSmallBig + 6)) ALLOC(a->tot, 4 * (size_t)kSmallBig + 7)
   ALLOC(a->sched, (size_t)s->cap_subs * kBsMaxSched * 2) ALLOC(a->nsched, s->cap_subs)
   ALLOC(a->contrib, (size_t)s->cap_subs * 28) ALLOC(a->kept, n) ALLOC(a->m_big, nb)
   ALLOC(a->v_h0, n3) ALLOC(a->gm, nb) ALLOC(a->gv, n3)
 #undef ALLOC
   if (e == hipSuccess) e = hipMemsetAsync(a->kept, 0, sizeof(int32_t) * n, s->stream);
+  // the sums, then the block counter of the reductions (left at zero by each)
+  if (e == hipSuccess)
+    e = hipMemsetAsync(a->tot, 0, sizeof(double) * (4 * kSmallBig + 7), s->stream);
   if (e == hipSuccess && nb > 0)
     e = copy_in(a->m_big, m_big, sizeof(double) * nb, is_device_ptr, s->stream);
   if (e == hipSuccess) e = copy_in(a->v_h0, v_h, sizeof(double) * n3, is_device_ptr, s->stream);
