@@ -2220,6 +2220,9 @@ __global__ __launch_bounds__(BLK) void k_step_joint(const SysDesc* __restrict__ 
   DevScalars* __restrict__ dsc = D.dsc;
   if ((int)blockIdx.x < nbs_all) {
     if (tid >= 64) return;  // one wave per integrator block
+    // the integrator's chain sets the launch time: its wave takes the issue
+    // slots first when a tile wave shares its SIMD
+    __builtin_amdgcn_s_setprio(3);
     const bool jfast =
         bs_body<true>(D, (int)blockIdx.x % nbs, nbs, 1, ph, nx, ph, -1, src, bst, brc, jsc, jr);
     if (!jfast) {
