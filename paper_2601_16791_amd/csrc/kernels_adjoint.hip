@@ -387,8 +387,7 @@ __device__ __forceinline__ double wave_sum(double v) { return mxd::wave_sum_fixe
 // f(r) = K(r)/r^3 and F1 = f'(r)/r of the changeover-weighted pair force
 __device__ __forceinline__ void pair_f(double s2, double rc, double& f, double& F1) {
   const double rc2 = rc * rc;
-  const double r = sqrt(s2);
-  const double ir = 1.0 / r, ir2 = ir * ir, ir3 = ir2 * ir;
+  const double ir = mxd::rsqrt_full(s2), r = s2 * ir, ir2 = ir * ir, ir3 = ir2 * ir;
   if (s2 >= rc2) {
     f = ir3;
     F1 = -3.0 * ir3 * ir2;

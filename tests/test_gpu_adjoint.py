@@ -156,6 +156,30 @@ def test_adjoint_checkpointing_does_not_change_the_gradient(mx):
             assert np.array_equal(p, q)
 
 
+def test_adjoint_backward_repeats_bitwise(mx):
+    """Two reverse passes of one adjoint, and one of a second adjoint built the same
+    way, give the same bits: the reductions leave their block counter at zero and
+    the encounter subsystems' member marks are cleared after every step."""
+    w = encounter_workload(seed=8, n_small=80, n_emb=3)
+    steps, every = 8, 3
+    rng = np.random.default_rng(4)
+    gx, gv = rng.normal(size=(3, w.n)), rng.normal(size=(3, w.n)) * 10.0
+    runs = []
+    a = mx.Adjoint(w.params, w.x, w.v, w.m_big, w.r_p, w.rho_p, steps, every)
+    a.forward()
+    for _ in range(2):
+        runs.append([t.cpu().numpy() for t in a.backward(gx, gv)])
+    a.close()
+    b = mx.Adjoint(w.params, w.x, w.v, w.m_big, w.r_p, w.rho_p, steps, every)
+    b.forward()
+    runs.append([t.cpu().numpy() for t in b.backward(gx, gv)])
+    b.close()
+    for g in runs[1:]:
+        for p, q in zip(g, runs[0]):
+            assert np.array_equal(p, q)
+    assert all(np.isfinite(p).all() for p in runs[0])
+
+
 def test_hybrid_run_default_rcrit_is_a_constant_of_the_map(mx):
     """Without spec['rcrit'] the changeover radii come from the base state (spec's x,
     v and m_big), not from the differentiated inputs: the run and its gradient are
