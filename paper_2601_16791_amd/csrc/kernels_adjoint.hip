@@ -646,12 +646,16 @@ typedef Dn<1> D1;
 template <int M>
 __device__ __forceinline__ void tforce(uint32_t pmask, const D1 (&mu)[M], const double (&rc)[M],
                                        double mu0, const D1 (&pos)[3 * M], D1 (&acc)[3 * M]) {
+  // r^-3 and its derivative from y = 1/sqrt(r^2) (the corrected hardware
+  // estimate): d(r^-3)/d(r^2) = -1.5 y^5, no division on the dual chain
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     const D1 r2 = pos[3 * k] * pos[3 * k] + pos[3 * k + 1] * pos[3 * k + 1] +
                   pos[3 * k + 2] * pos[3 * k + 2];
-    const D1 r = dsqrt(r2);
-    const D1 f = (-mu0) / (r2 * r);
+    const double y = mxd::rsqrt_full(r2.v), y2 = y * y, y3 = y2 * y;
+    D1 f;
+    f.v = -mu0 * y3;
+    f.d[0] = (1.5 * mu0) * (y3 * y2) * r2.d[0];
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[3 * k + c] = f * pos[3 * k + c];
   }
@@ -669,10 +673,14 @@ __device__ __forceinline__ void tforce(uint32_t pmask, const D1 (&mu)[M], const 
       const double rc2 = rcp * rcp;
       D1 w = dconst<1>(0.0);
       if (s2.v < rc2 && s2.v > 0.0) {
-        const D1 s = dsqrt(s2);
-        w = 1.0 / (s2 * s);
+        const double y = mxd::rsqrt_full(s2.v), y2 = y * y, y3 = y2 * y;
+        w.v = y3;  // 1/s^3
+        w.d[0] = -1.5 * (y3 * y2) * s2.d[0];
         if (s2.v > 0.01 * rc2) {
-          const D1 q = (s - 0.1 * rcp) / (0.9 * rcp);
+          D1 sd;  // s = s2 y, ds/ds2 = y/2
+          sd.v = s2.v * y;
+          sd.d[0] = 0.5 * y * s2.d[0];
+          const D1 q = (sd - 0.1 * rcp) * (1.0 / (0.9 * rcp));
           const D1 K = q * q * q * (10.0 + q * (-15.0 + 6.0 * q));
           w = w * (1.0 - K);
         }
