@@ -28,8 +28,9 @@
 //   k_adj_sum3      : per-wave sums of an adjoint over all bodies, whose
 //                     momentum term (jumps, DH <-> heliocentric) the reduction
 //                     above applies
-//   k_adj_copy, k_adj_copy_tape : the per-step record (state, subsystem table,
-//                     accepted Bulirsch-Stoer steps) kept for the reverse pass
+//   k_adj_copy, k_adj_record : saved states, and the per-step record (state,
+//                     subsystem table, accepted Bulirsch-Stoer steps) kept for
+//                     the reverse pass
 #include <hip/hip_runtime.h>
 
 #include "device_math.h"
@@ -1016,20 +1017,34 @@ __global__ __launch_bounds__(kBlock) void k_adj_copy(CopyList l, double* __restr
   }
 }
 
-// the subsystem table of a step (its n_sub entries), n_sub, and the accepted
-// Bulirsch-Stoer steps of those subsystems
-__global__ void k_adj_copy_tape(const Subsystem* __restrict__ subs,
-                                const DevScalars* __restrict__ dsc,
-                                const double* __restrict__ sched,
-                                const int32_t* __restrict__ nsched, Subsystem* __restrict__ dsubs,
-                                int32_t* __restrict__ n_sub_out, double* __restrict__ dsched,
-                                int32_t* __restrict__ dnsched) {
+// One step's record in one launch.  Blocks below ncopy pack the arrays of l
+// (the pre-drift state and the velocities after the drift) into `packed`; the
+// other blocks copy the subsystem table of the step (its n_sub entries), n_sub,
+// and the accepted Bulirsch-Stoer steps of those subsystems.
+constexpr int kTapeBlocks = 64;
+
+__global__ __launch_bounds__(kBlock) void k_adj_record(
+    CopyList l, double* __restrict__ packed, int ncopy, const Subsystem* __restrict__ subs,
+    const DevScalars* __restrict__ dsc, const double* __restrict__ sched,
+    const int32_t* __restrict__ nsched, Subsystem* __restrict__ dsubs,
+    int32_t* __restrict__ n_sub_out, double* __restrict__ dsched, int32_t* __restrict__ dnsched) {
+  if ((int)blockIdx.x < ncopy) {
+    int64_t off = 0;
+    for (int a = 0; a < 4; ++a) {
+      const int64_t m = l.len[a];
+      for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+           i += (int64_t)ncopy * kBlock)
+        packed[off + i] = l.ptr[a][i];
+      off += m;
+    }
+    return;
+  }
   const int nsub = dsc->n_sub;
   const int words = (int)(sizeof(Subsystem) / 4);
   const int32_t* src = reinterpret_cast<const int32_t*>(subs);
   int32_t* out = reinterpret_cast<int32_t*>(dsubs);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)(gridDim.x - ncopy) * kBlock;
+  const int64_t i0 = (int64_t)(blockIdx.x - ncopy) * kBlock + threadIdx.x;
   for (int64_t i = i0; i < (int64_t)nsub * words; i += stride) out[i] = src[i];
   for (int64_t i = i0; i < (int64_t)nsub * kBsMaxSched * 2; i += stride) dsched[i] = sched[i];
   for (int64_t i = i0; i < nsub; i += stride) dnsched[i] = nsched[i];
@@ -1129,11 +1144,23 @@ hipError_t adj_copy(hipStream_t st, double* const* ptr, const int64_t* len, int 
   return hipGetLastError();
 }
 
-hipError_t adj_copy_tape(hipStream_t st, const Subsystem* subs, const DevScalars* dsc,
-                         const double* sched, const int32_t* nsched, Subsystem* dsubs,
-                         int32_t* n_sub_out, double* dsched, int32_t* dnsched) {
-  hipLaunchKernelGGL(k_adj_copy_tape, dim3(64), dim3(256), 0, st, subs, dsc, sched, nsched, dsubs,
-                     n_sub_out, dsched, dnsched);
+hipError_t adj_record(hipStream_t st, double* const* ptr, const int64_t* len, int count,
+                      double* packed, const Subsystem* subs, const DevScalars* dsc,
+                      const double* sched, const int32_t* nsched, Subsystem* dsubs,
+                      int32_t* n_sub_out, double* dsched, int32_t* dnsched) {
+  CopyList l;
+  int64_t tot = 0;
+  for (int a = 0; a < 4; ++a) {
+    l.ptr[a] = a < count ? ptr[a] : nullptr;
+    l.len[a] = a < count ? len[a] : 0;
+    tot += l.len[a];
+  }
+  int64_t ncopy = (tot / 4 + kBlock - 1) / kBlock;
+  if (ncopy < 1) ncopy = 1;
+  if (ncopy > 4096) ncopy = 4096;
+  hipLaunchKernelGGL(k_adj_record, dim3((unsigned)ncopy + kTapeBlocks), dim3(kBlock), 0, st, l,
+                     packed, (int)ncopy, subs, dsc, sched, nsched, dsubs, n_sub_out, dsched,
+                     dnsched);
   return hipGetLastError();
 }
 

@@ -1465,15 +1465,16 @@ hipError_t adj_h2dh(hipStream_t st, int n, int nb, double G, double m0, const do
                     double* gv, double* part, double* tot);
 hipError_t adj_copy(hipStream_t st, double* const* ptr, const int64_t* len, int count,
                     double* packed, int unpack);
-hipError_t adj_copy_tape(hipStream_t st, const Subsystem* subs, const DevScalars* dsc,
-                         const double* sched, const int32_t* nsched, Subsystem* dsubs,
-                         int32_t* n_sub_out, double* dsched, int32_t* dnsched);
+hipError_t adj_record(hipStream_t st, double* const* ptr, const int64_t* len, int count,
+                      double* packed, const Subsystem* subs, const DevScalars* dsc,
+                      const double* sched, const int32_t* nsched, Subsystem* dsubs,
+                      int32_t* n_sub_out, double* dsched, int32_t* dnsched);
 }  // namespace mxk
 
 // A differentiable run.  Per step of the segment being reversed, the record
 // ("tape") keeps the pre-drift state x0, u0, the velocities after drift and
-// encounters, the positions after the step, the subsystem table, its size and
-// the accepted Bulirsch-Stoer steps.
+// encounters, the subsystem table, its size and the accepted Bulirsch-Stoer
+// steps; the positions after the step are those of the next saved state.
 struct mx_adjoint {
   mx_system* s;
   int32_t n_steps, every, n_ckpt;
@@ -1481,7 +1482,7 @@ struct mx_adjoint {
   double* ckpt;      // [n_ckpt][blk]: states at steps 0, every, 2 every, ...
   double* seg;       // [every][blk]: step-start states of the segment being reversed
   double* fin;       // [blk]: state after the last step
-  double* tape;      // [every][12 n]: x0, u0, u after drift/encounters, x after the step
+  double* tape;      // [every][9 n]: x0, u0, u after drift/encounters
   Subsystem* tsubs;  // [every][cap_subs]
   int32_t* tnsub;    // [every]
   double* tsched;    // [every][cap_subs][kBsMaxSched][2]
@@ -1533,39 +1534,33 @@ hipError_t restore_state(mx_adjoint* a, const double* src, int64_t step) {
 hipError_t recorded_step(mx_adjoint* a, int q) {
   mx_system* s = a->s;
   const int64_t n3 = 3 * (int64_t)s->n;
-  double* tp = a->tape + (size_t)q * 4 * n3;
+  double* tp = a->tape + (size_t)q * 3 * n3;
   hipError_t e = hipSuccess;
   for (int k = 0; k < MX_NUM_KERNELS && e == hipSuccess; ++k) {
     if (k == MX_K_JUMP_PACK) {
-      // after drift and encounters: x0, u0 (pre-drift) and u
+      // after drift and encounters: x0, u0 (pre-drift), u, and the subsystems
       double* ptr[3] = {s->x0, s->u0, s->u};
       int64_t len[3] = {n3, n3, n3};
-      e = mxk::adj_copy(s->stream, ptr, len, 3, tp, 0);
-      if (e == hipSuccess)
-        e = mxk::adj_copy_tape(s->stream, s->subs, s->dsc, a->sched, a->nsched,
-                               a->tsubs + (size_t)q * s->cap_subs, a->tnsub + q,
-                               a->tsched + (size_t)q * s->cap_subs * kBsMaxSched * 2,
-                               a->tnsched + (size_t)q * s->cap_subs);
+      e = mxk::adj_record(s->stream, ptr, len, 3, tp, s->subs, s->dsc, a->sched, a->nsched,
+                          a->tsubs + (size_t)q * s->cap_subs, a->tnsub + q,
+                          a->tsched + (size_t)q * s->cap_subs * kBsMaxSched * 2,
+                          a->tnsched + (size_t)q * s->cap_subs);
     }
     if (e == hipSuccess) e = launch_group(s, k);
-  }
-  if (e == hipSuccess) {
-    double* ptr[1] = {s->x};
-    int64_t len[1] = {n3};
-    e = mxk::adj_copy(s->stream, ptr, len, 1, tp + 3 * n3, 0);
   }
   return e;
 }
 
-// adjoint of the step recorded in slot q, whose start state is `start`
-hipError_t reverse_step(mx_adjoint* a, int q, const double* start) {
+// adjoint of the step recorded in slot q, whose start state is `start` and end
+// state `end` (saved states: the positions come first)
+hipError_t reverse_step(mx_adjoint* a, int q, const double* start, const double* end) {
   mx_system* s = a->s;
   const int n = s->n, nb = s->nb;
   const double h = s->p.dt, hh = 0.5 * h, mu0 = s->mu0;
   const mxd::DragConst dc = mxd::make_drag_const(s->p);
   const size_t n3 = 3 * (size_t)n;
-  const double* tp = a->tape + (size_t)q * 4 * n3;
-  const double *x0 = tp, *u0 = tp + n3, *ud = tp + 2 * n3, *xe = tp + 3 * n3;
+  const double* tp = a->tape + (size_t)q * 3 * n3;
+  const double *x0 = tp, *u0 = tp + n3, *ud = tp + 2 * n3, *xe = end;
   hipError_t e;
   // closing half kick at the final positions, with the jump before it
   e = mxk::adj_kick(s->stream, n, nb, mu0, hh, dc, s->p.gas_on, xe, ud, s->mu, s->rcrit, s->r_p,
@@ -1627,7 +1622,7 @@ mx_status mx_adjoint_create(const mx_params* p, const double* x_h, const double*
   if (e == hipSuccess) e = dalloc(&(ptr), (size_t)(cnt));
   const size_t cs = (size_t)s->cap_subs;
   ALLOC(a->ckpt, a->n_ckpt * a->blk) ALLOC(a->seg, a->every * a->blk) ALLOC(a->fin, a->blk)
-  ALLOC(a->tape, a->every * 4 * n3) ALLOC(a->tsubs, a->every * cs) ALLOC(a->tnsub, a->every)
+  ALLOC(a->tape, a->every * 3 * n3) ALLOC(a->tsubs, a->every * cs) ALLOC(a->tnsub, a->every)
   ALLOC(a->tsched, a->every * cs * kBsMaxSched * 2) ALLOC(a->tnsched, a->every * cs)
   ALLOC(a->lx, n3) ALLOC(a->lu, n3) ALLOC(a->lmu, nb)
   ALLOC(a->part, nwaves * (4 * (size_t)kSmallBig + 6)) ALLOC(a->tot, 4 * (size_t)kSmallBig + 7)
@@ -1715,9 +1710,13 @@ mx_status mx_adjoint_backward(mx_adjoint* a, const double* gx, const double* gv,
       HIPCHK(state_copy(a, a->seg + (size_t)(j - j0) * a->blk, 0), "segment state");
       HIPCHK(recorded_step(a, j - j0), "recorded step");
     }
-    // and back
-    for (int32_t j = j1 - 1; j >= j0; --j)
-      HIPCHK(reverse_step(a, j - j0, a->seg + (size_t)(j - j0) * a->blk), "adjoint step");
+    // and back; the state after the segment's last step is the next checkpoint (the
+    // recording reproduces the forward run bit for bit) or the final state
+    const double* after = c + 1 < a->n_ckpt ? a->ckpt + (size_t)(c + 1) * a->blk : a->fin;
+    for (int32_t j = j1 - 1; j >= j0; --j) {
+      const double* end = j + 1 < j1 ? a->seg + (size_t)(j + 1 - j0) * a->blk : after;
+      HIPCHK(reverse_step(a, j - j0, a->seg + (size_t)(j - j0) * a->blk, end), "adjoint step");
+    }
   }
   hipError_t e = mxk::adj_h2dh(st, n, nb, s->p.G, s->p.m0, a->m_big, a->v_h0, a->lu, a->lmu,
                                a->gm, a->gv, a->part, a->tot);
