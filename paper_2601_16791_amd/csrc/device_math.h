@@ -123,13 +123,17 @@ __device__ __forceinline__ GasSite gas_site(const DragConst& c, double X, double
   else sig = c.sigma1_unit * pow(R, -c.gamma);
   if (c.r_c > 0.0) sig *= exp(c.rc_norm - pow(R * c.inv_rc, 2.0 - c.gamma));
   if (!(sig > 0.0)) return g;
-  double cs, rhog, vg, gx = 0.0, gy = 0.0;
+  double cs, rhog, vg, gx, gy;
   if (__builtin_expect(c.ext != 0, 0)) {
+    // the outputs start at zero only on this branch: the call takes their
+    // addresses, so the plain disk stores nothing to private memory
+    gx = gy = 0.0;
     gas_general(c, X, Y, R, inv_R, vk, sig, cs, rhog, vg, gx, gy);
   } else {
     cs = c.h_over_r * vk;
     rhog = sig * inv_R * c.rho_fac;
     vg = vk * c.vg_fac;
+    gx = gy = 0.0;
   }
   g.inv_R = inv_R;
   g.cs = cs;
